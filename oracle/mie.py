@@ -1,0 +1,29 @@
+"""Mie series for plane-wave scattering by one rigid sphere (oracle; analytic pin).
+
+Incident p_inc = e^{ik d.x}, time convention e^{-i w t} (Sec. 2.1).  Expanding
+p_inc = sum_n i^n (2n+1) j_n(kr) P_n(cos t) and imposing dp/dr = 0 at r = a gives
+the total surface pressure
+
+    p(a, t) = sum_n i^n (2n+1) [j_n(ka) - j_n'(ka) h_n(ka) / h_n'(ka)] P_n(cos t)
+            = sum_n i^{n+1} (2n+1) P_n(cos t) / ((ka)^2 h_n'(ka)),
+
+the second form by the Wronskian j_n y_n' - j_n' y_n = 1/x^2.
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy import special
+
+from .specfun import sph_hd
+
+
+def rigid_sphere_surface_pressure(points, radius, k, direction=(1.0, 0.0, 0.0), n_terms=None):
+    pts = np.asarray(points, dtype=np.float64)
+    d = np.asarray(direction, dtype=np.float64)
+    ct = (pts @ d) / np.linalg.norm(pts, axis=1)
+    ka = k * radius
+    N = int(ka + 30) if n_terms is None else n_terms
+    out = np.zeros(pts.shape[0], dtype=np.complex128)
+    for n in range(N + 1):
+        out += (1j ** ((n + 1) % 4)) * (2 * n + 1) * special.eval_legendre(n, ct) / (ka * ka * sph_hd(n, ka))
+    return out
