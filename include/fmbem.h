@@ -1,0 +1,180 @@
+/*
+ * fmbem.h - C ABI of the MI355X (gfx950) fast multipole periodic BEM library.
+ *
+ * The library applies and solves the single-level fast multipole periodic
+ * boundary element operator of Jelich, Zhao, Chen & Marburg (arXiv 2201.12050):
+ * a unit-cell surface mesh of flat constant triangles is replicated on an
+ * M1 x M2 x M3 axis-aligned lattice, each cell is one FMM box, and the rigid-body
+ * Burton-Miller (or CBIE) collocation operator is approximated by
+ *
+ *     A  ~  S + U K V          (Sec. 3.1, eq. (SingleLevelFMM); Sec. 3.2, eq. (2dPeriodicFMM))
+ *
+ * with S the banded multilevel block-Toeplitz near field, U = diag(U0) and
+ * V = diag(V0) the per-cell L2P and P2M operators and K the multilevel
+ * block-Toeplitz M2L operator, applied through its circulant embedding as
+ * U F^-1 Lambda F V (Sec. 2.4, eq. (diagonalized); Sec. 3.5, eq. (FMPBEMsystem)).
+ *
+ * Conventions for every entry point:
+ *  - No C++ exception crosses the ABI; every call returns fmbem_status.
+ *  - Argument errors are detected before any device work is enqueued; on an
+ *    error nothing is written.
+ *  - Complex numbers are interleaved (re, im) pairs: complex128 (two doubles)
+ *    or complex64 (two floats), matching torch.complex128 / torch.complex64.
+ *  - Vector layout [n_rhs][n_cells][n_dof_cell]: cell c = i1 + M1*(i2 + M2*i3),
+ *    DOF within a cell = triangle index of the unit-cell mesh.
+ *  - "device" pointers are HIP device memory on the device that was current
+ *    when the plan was created; "host" pointers are ordinary host memory.
+ *  - hip_stream is a hipStream_t passed as void* (NULL = the null stream).
+ *    Stream-ordered calls return before the work completes.
+ */
+#ifndef FMBEM_H
+#define FMBEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FMBEM_OK = 0,
+  FMBEM_ERR_INVALID_ARG = 1,   /* bad pointer, size, mesh or descriptor field */
+  FMBEM_ERR_UNSUPPORTED = 2,   /* valid request the library does not implement */
+  FMBEM_ERR_OUT_OF_MEMORY = 3, /* a device allocation failed; nothing leaked */
+  FMBEM_ERR_DEVICE = 4,        /* a HIP call failed (no device, launch failure) */
+  FMBEM_ERR_NOT_CONVERGED = 5, /* solve stopped at its iteration limit; x = last iterate */
+  FMBEM_ERR_WORKSPACE = 6      /* caller workspace smaller than fmbem_plan_info says */
+} fmbem_status;
+
+typedef enum { FMBEM_FP64 = 0, FMBEM_FP32 = 1 } fmbem_precision;
+typedef enum { FMBEM_BURTON_MILLER = 0, FMBEM_CBIE = 1 } fmbem_formulation;
+
+typedef struct fmbem_plan_s* fmbem_plan;
+
+/* Unit-cell mesh in cell-local coordinates: the cell centre (= expansion centre
+ * of its FMM box, Sec. 3.2) is the origin.  Copied during fmbem_plan_create. */
+typedef struct {
+  int32_t n_vertices;
+  const double* vertices;     /* host [n_vertices][3], metres */
+  int32_t n_triangles;
+  const int32_t* triangles;   /* host [n_triangles][3], 0-based; (v1-v0)x(v2-v0) points
+                                 out of the fluid, into the scatterer (Sec. 2.1) */
+} fmbem_cell_mesh;
+
+typedef struct {
+  int32_t grid[3];            /* M1, M2, M3 >= 1 */
+  double pitch[3];            /* lattice spacing per axis (m), > 0 */
+  double k;                   /* wavenumber k = 2 pi f / c > 0 (1/m), Sec. 2.1 */
+  int32_t order;              /* truncation number n_t in [0, 20]; p = (n_t+1)^2 (Sec. 3.1) */
+  int32_t formulation;        /* fmbem_formulation */
+  double alpha_re, alpha_im;  /* Burton-Miller coupling; both NaN => -i/k (Sec. 2.1) */
+  int32_t near_radius[3];     /* near field: |d_a| <= near_radius_a cells (0 => 1) */
+  int32_t fft_shape[3];       /* 0 => smallest 2^a3^b5^c7^d >= 2 M_a - 1; else >= 2 M_a - 1 */
+  uint32_t precisions;        /* bitmask (1<<FMBEM_FP64) | (1<<FMBEM_FP32) of resident copies;
+                                 0 => FP64 only */
+} fmbem_plan_desc;
+
+typedef struct {
+  int32_t n_dof_cell;         /* n (triangles per cell) */
+  int32_t n_cells;            /* C = M1 M2 M3 */
+  int64_t n_dof;              /* N = C n */
+  int32_t p;                  /* (n_t+1)^2 */
+  int32_t fft_shape[3];       /* N1, N2, N3 */
+  int32_t n_near;             /* number of near-field offsets (unique blocks S_d) */
+  int32_t n_far;              /* number of far offsets in the Toeplitz structure */
+  uint32_t precisions;        /* resident operator copies */
+  size_t resident_bytes;      /* device memory owned by the plan */
+  size_t workspace_bytes_per_rhs[2]; /* matvec workspace per right-hand side, [FP64, FP32] */
+  double scale;               /* s of the diagonal scaling s^n applied to V0, U0, Lambda */
+} fmbem_plan_info;
+
+/* Build the plan: near blocks S_d (Sec. 3.2), P2M V0 and L2P U0 (Appendix A,
+ * eqs. (p2m), (l2p)), and Lambda = DFT over the cell grid of the first block
+ * column of the circulant embedding of K (Sec. 2.4, eq. (blockDiagonal);
+ * Sec. 3.5), all computed on the device in FP64.  Blocks until the plan is
+ * ready.  The mesh must be a set of non-degenerate triangles; the returned
+ * plan is owned by the caller and released with fmbem_plan_destroy. */
+fmbem_status fmbem_plan_create(const fmbem_cell_mesh* mesh, const fmbem_plan_desc* desc,
+                               void* hip_stream, fmbem_plan* out);
+fmbem_status fmbem_plan_query(fmbem_plan plan, fmbem_plan_info* out);
+fmbem_status fmbem_plan_destroy(fmbem_plan plan);
+
+/* Operator data for inspection (host copies; complex128 unless stated):
+ *   what = 0: S_d          [n_near][n][n] row-major, offsets in fmbem_plan_offsets order
+ *   what = 1: V0           [p][n]   (unscaled)
+ *   what = 2: U0           [n][p]   (unscaled)
+ *   what = 3: Lambda       [B][p][p] row-major, unscaled and without the 1/B factor
+ *   what = 4: near offsets int32 [n_near][3]
+ * host_bytes must be at least the size of the requested array. Blocks. */
+fmbem_status fmbem_plan_export(fmbem_plan plan, int32_t what, void* host, size_t host_bytes);
+
+/* y = A x (Sec. 3.5, eq. (FMPBEMsystem)): near-field block-Toeplitz product,
+ * S2M, pruned grid FFT, per-bin M2L product, inverse FFT with cropping, L2T.
+ * x, y: device [n_rhs][n_cells][n_dof_cell], complex128 for FMBEM_FP64 and
+ * complex64 for FMBEM_FP32; x and y must not overlap.  workspace: device,
+ * at least n_rhs * workspace_bytes_per_rhs[precision] bytes, 256-byte aligned.
+ * The operator copy of that precision must be resident.  Stream-ordered. */
+fmbem_status fmbem_matvec(fmbem_plan plan, int32_t precision, int32_t n_rhs,
+                          const void* x, void* y, void* workspace, size_t workspace_bytes,
+                          void* hip_stream);
+
+typedef struct {
+  double tol;                 /* stop when ||b - A x||_2 / ||b||_2 <= tol (FP64 true residual) */
+  int32_t restart;            /* GMRES restart length m (default 30 when 0), at most 200 */
+  int32_t max_iters;          /* total inner iterations (default 1000 when 0) */
+  int32_t max_refinements;    /* outer refinement steps for FP32 inner solves (default 20 when 0) */
+  int32_t inner_precision;    /* FMBEM_FP64: plain FP64 GMRES; FMBEM_FP32: FP32 operator inside
+                                 GMRES, FP64 Arnoldi, FP64 residual and refinement */
+  double inner_tol;           /* relative tolerance of each FP32 inner solve (default 1e-5 when 0) */
+} fmbem_solve_opts;
+
+typedef struct {
+  int32_t iterations;         /* inner GMRES iterations (operator applications) */
+  int32_t refinements;        /* outer refinement steps (FP32 inner mode) */
+  double rel_residual;        /* final FP64 ||b - A x|| / ||b|| */
+} fmbem_solve_info;
+
+/* Solve A x = b by restarted GMRES (Sec. 2.4, Sec. 3.5; GMRES as in Sec. 4)
+ * with classical Gram-Schmidt applied twice, Givens rotations, and (for
+ * inner_precision = FMBEM_FP32) FP64 iterative refinement around FP32 inner
+ * solves.  b, x: device complex128 [n_rhs][n_cells][n_dof_cell]; x holds the
+ * initial guess on entry and the solution on return.  All right-hand sides
+ * are iterated together.  Allocates its Krylov basis on the device for the
+ * duration of the call.  Blocks until done; info (host, [n_rhs]) may be NULL.
+ * Returns FMBEM_ERR_NOT_CONVERGED (x = last iterate, info filled) when some
+ * right-hand side misses tol within the limits. */
+fmbem_status fmbem_solve(fmbem_plan plan, const fmbem_solve_opts* opts, int32_t n_rhs,
+                         const void* b, void* x, fmbem_solve_info* info, void* hip_stream);
+
+/* Right-hand sides b = p_inc + alpha dp_inc/dn at the collocation points
+ * (Sec. 2.1, eq. (bm)), device complex128 [n_rhs][n_cells][n_dof_cell].
+ * Plane wave p_inc = A e^{ik d.x} (Sec. 4.1, eq. (planewave)); dirs host [n_rhs][3]
+ * unit vectors.  Point source p_inc = A e^{ikR}/R, R = |x - s| (Sec. 4.2);
+ * src host [n_rhs][3] absolute positions (m), cell (0,0,0) centred at the origin.
+ * Stream-ordered. */
+fmbem_status fmbem_incident_plane_wave(fmbem_plan plan, int32_t n_rhs, const double* dirs,
+                                       double amplitude, void* b, void* hip_stream);
+fmbem_status fmbem_incident_point_source(fmbem_plan plan, int32_t n_rhs, const double* src,
+                                         double amplitude, void* b, void* hip_stream);
+
+/* Per-stage device time of the operator applications made with this plan
+ * (fmbem_matvec and the ones inside fmbem_solve), measured with HIP events
+ * recorded on the call's stream around each stage.  enable = 1 clears the
+ * counters and starts recording, 0 stops.  Not for concurrent use of the same
+ * plan from several host threads while enabled.
+ * Stages: 0 near field, 1 S2M, 2 forward DFT, 3 M2L, 4 inverse DFT, 5 L2T in FP64;
+ * 6..11 the same stages in FP32. */
+#define FMBEM_N_STAGES 12
+fmbem_status fmbem_plan_profile(fmbem_plan plan, int32_t enable);
+/* Synchronizes with the recorded events and returns the accumulated time (ms)
+ * and the number of launches of each stage (host arrays [FMBEM_N_STAGES]). */
+fmbem_status fmbem_plan_profile_read(fmbem_plan plan, double* ms, int64_t* count);
+
+const char* fmbem_status_string(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMBEM_H */

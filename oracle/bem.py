@@ -87,23 +87,25 @@ def hypersingular_self(a, b, c, x, k, q: int = 16):
     return (fp_inv_r3(a, b, c, x) + reg) / FOUR_PI
 
 
-def block(geom, k, alpha, target_shift, source_shift, self_block: bool, chunk: int = 1 << 15):
+def block(geom, k, alpha, target_shift, source_shift, self_block: bool, chunk: int = 1 << 15, rows=None):
     """Matrix block for collocation points of one cell (shifted by ``target_shift``)
     against the elements of one cell (shifted by ``source_shift``).  ``self_block``
-    marks the block of a cell with itself (diagonal = self terms)."""
-    x = geom["centroid"] + np.asarray(target_shift)
-    nx = geom["normal"]
+    marks the block of a cell with itself (diagonal = self terms).  ``rows``
+    restricts the targets to a subset of the cell's collocation points."""
+    rows = np.arange(geom["centroid"].shape[0]) if rows is None else np.asarray(rows)
+    x = geom["centroid"][rows] + np.asarray(target_shift)
+    nx = geom["normal"][rows]
     sa = geom["a"] + np.asarray(source_shift)
     sb = geom["b"] + np.asarray(source_shift)
     sc = geom["c"] + np.asarray(source_shift)
     ny = geom["normal"]
     scen = geom["centroid"] + np.asarray(source_shift)
-    n = x.shape[0]
+    n = scen.shape[0]
     dist = np.linalg.norm(x[:, None, :] - scen[None, :, :], axis=-1)
     order = rule_order(dist, geom["longest"][None, :])
-    out = np.zeros((n, n), dtype=np.complex128)
+    out = np.zeros((rows.size, n), dtype=np.complex128)
     if self_block:
-        order[np.arange(n), np.arange(n)] = 0
+        order[np.arange(rows.size), rows] = 0
     for q in (4, 8, 16):
         ia, jb = np.nonzero(order == q)
         for s in range(0, ia.size, chunk):
@@ -113,9 +115,9 @@ def block(geom, k, alpha, target_shift, source_shift, self_block: bool, chunk: i
             vals = kernels.bm_kernel(x[i_][:, None, :], pts, nx[i_][:, None, :], ny[j_][:, None, :], k, alpha)
             out[i_, j_] = (vals * w).sum(-1)
     if self_block:
-        for i in range(n):
-            hs = hypersingular_self(sa[i], sb[i], sc[i], x[i], k) if alpha != 0 else 0.0
-            out[i, i] = 0.5 + alpha * hs
+        for r, i in enumerate(rows):
+            hs = hypersingular_self(sa[i], sb[i], sc[i], x[r], k) if alpha != 0 else 0.0
+            out[r, i] = 0.5 + alpha * hs
     return out
 
 

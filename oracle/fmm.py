@@ -97,10 +97,14 @@ def p2m(vertices, triangles, k, order, q: int = 8):
     a, b, c = v[t[:, 0]], v[t[:, 1]], v[t[:, 2]]
     nrm = np.cross(b - a, c - a)
     nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
-    pts, w = duffy_points(a, b, c, q)                       # [n, q*q, 3], [n, q*q]
-    g = grad_conj_regular(pts, k, order)                     # [n, q*q, p, 3]
-    dn = (g * nrm[:, None, None, :]).sum(-1)                 # [n, q*q, p]
-    return (dn * w[..., None]).sum(1).T.copy()               # [p, n]
+    out = np.zeros((n_coeffs(order), a.shape[0]), dtype=np.complex128)
+    for s in range(0, a.shape[0], 64):
+        e = slice(s, s + 64)
+        pts, w = duffy_points(a[e], b[e], c[e], q)           # [ne, q*q, 3], [ne, q*q]
+        g = grad_conj_regular(pts, k, order)                 # [ne, q*q, p, 3]
+        dn = (g * nrm[e][:, None, None, :]).sum(-1)          # [ne, q*q, p]
+        out[:, e] = (dn * w[..., None]).sum(1).T
+    return out                                               # [p, n]
 
 
 def l2p(vertices, triangles, k, order, alpha):

@@ -125,3 +125,91 @@ class FMPBEM:
             d = tuple(int(v) for v in (g[i] - g[j]))
             out[j * n:(j + 1) * n] = self.S[d][a] if d in self.S else (ua @ self.K[d]) @ self.V0
         return out
+
+
+def sampled_apply(vertices, triangles, lattice, k, order, alpha, x, dofs, near_radius=(1, 1, 1)):
+    """(A x)[:, dof] of the O2 operator for the listed DOFs only, each computed from
+    its own row of near blocks (integrated for that collocation point alone) and
+    the far chain U0[a] sum_j K_{i-j} V0 x_j.  For lattices too large to
+    materialise S_d.  x: [R, C, n]; returns [R, len(dofs)]."""
+    x = np.asarray(x, dtype=np.complex128)
+    grid = tuple(lattice.grid)
+    n = int(np.asarray(triangles).shape[0])
+    geom = bem.element_geometry(vertices, triangles)
+    pitch = np.asarray(lattice.pitch)
+    V0 = fmm.p2m(vertices, triangles, k, order)
+    U0 = fmm.l2p(vertices, triangles, k, order, alpha)
+    m = x @ V0.T                                            # [R, C, p]
+    near = bem.near_offsets(grid, near_radius)
+    far = far_offsets(grid, near)
+    K = fmm.m2l(np.asarray(far, dtype=np.float64) * pitch[None, :], k, order) if far else None
+    g = grid_coords(grid)
+    gsz = np.asarray(grid)
+    out = np.zeros((x.shape[0], len(dofs)), dtype=np.complex128)
+    loc_cache = {}
+    for s, dof in enumerate(dofs):
+        i, a = divmod(int(dof), n)
+        val = np.zeros(x.shape[0], dtype=np.complex128)
+        for d in near:
+            src = g[i] - np.asarray(d)
+            if np.all((src >= 0) & (src < gsz)):
+                j = int(src[0] + grid[0] * (src[1] + grid[1] * src[2]))
+                row = bem.block(geom, k, alpha, np.zeros(3), -np.asarray(d) * pitch, d == (0, 0, 0), rows=[a])[0]
+                val += x[:, j, :] @ row
+        if far:
+            if i not in loc_cache:
+                loc = np.zeros((x.shape[0], V0.shape[0]), dtype=np.complex128)
+                for t, d in enumerate(far):
+                    src = g[i] - np.asarray(d)
+                    if np.all((src >= 0) & (src < gsz)):
+                        j = int(src[0] + grid[0] * (src[1] + grid[1] * src[2]))
+                        loc += m[:, j, :] @ K[t].T
+                loc_cache[i] = loc
+            val += loc_cache[i] @ U0[a]
+        out[:, s] = val
+    return out
+
+
+class RowSample:
+    """The O2 apply on a bounded sample of one lattice, for timing the oracle:
+    near field for a subset of collocation rows of every cell (rows of every S_d
+    integrated once), far field (S2M for every cell, M2L chain and L2T) for a
+    subset of target cells.  Scaling the two parts by n/len(rows) and
+    C/len(cells) estimates the time of a full block-by-block apply."""
+
+    def __init__(self, vertices, triangles, lattice, k, order, alpha, rows, cells, near_radius=(1, 1, 1)):
+        self.grid = tuple(lattice.grid)
+        self.n = int(np.asarray(triangles).shape[0])
+        self.rows = np.asarray(rows)
+        self.cells = np.asarray(cells)
+        geom = bem.element_geometry(vertices, triangles)
+        pitch = np.asarray(lattice.pitch)
+        self.near = bem.near_offsets(self.grid, near_radius)
+        self.S = {d: bem.block(geom, k, alpha, np.zeros(3), -np.asarray(d) * pitch, d == (0, 0, 0), rows=self.rows)
+                  for d in self.near}
+        self.V0 = fmm.p2m(vertices, triangles, k, order)
+        self.U0 = fmm.l2p(vertices, triangles, k, order, alpha)
+        self.far = far_offsets(self.grid, self.near)
+        Ks = fmm.m2l(np.asarray(self.far, dtype=np.float64) * pitch[None, :], k, order) if self.far else []
+        self.K = {d: Ks[i] for i, d in enumerate(self.far)}
+        self._pairs = {d: pairs(self.grid, d) for d in self.near + self.far}
+
+    def near_rows(self, x):
+        """[R, C, len(rows)] = sampled rows of sum_d S_d x_{i-d} for every cell."""
+        y = np.zeros((x.shape[0], x.shape[1], self.rows.size), dtype=np.complex128)
+        for d in self.near:
+            t, s = self._pairs[d]
+            y[:, t, :] += x[:, s, :] @ self.S[d].T
+        return y
+
+    def far_cells(self, x):
+        """[R, len(cells), n] = U0 sum_j K_{i-j} V0 x_j at the sampled target cells."""
+        m = x @ self.V0.T
+        want = set(int(c) for c in self.cells)
+        loc = np.zeros((x.shape[0], x.shape[1], m.shape[2]), dtype=np.complex128)
+        for d in self.far:
+            t, s = self._pairs[d]
+            keep = np.array([ti in want for ti in t], dtype=bool)
+            if keep.any():
+                loc[:, t[keep], :] += m[:, s[keep], :] @ self.K[d].T
+        return loc[:, self.cells, :] @ self.U0.T

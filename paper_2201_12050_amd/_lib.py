@@ -1,0 +1,249 @@
+"""ctypes binding of libfmbem.so (the C ABI declared in include/fmbem.h).
+
+Argument marshalling only: every step of the operator and the solve runs in
+the HIP library.  PyTorch tensors provide device memory and streams.  There is
+no fallback: if the library is missing or a call fails, an exception is raised.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfmbem.so")
+
+FP64, FP32 = 0, 1
+BURTON_MILLER, CBIE = 0, 1
+STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "out of device memory", 4: "device error",
+          5: "not converged", 6: "workspace too small"}
+
+
+class FmbemError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)} (status {status})")
+        self.status = status
+
+
+class CellMesh(ct.Structure):
+    _fields_ = [("n_vertices", ct.c_int32), ("vertices", ct.POINTER(ct.c_double)),
+                ("n_triangles", ct.c_int32), ("triangles", ct.POINTER(ct.c_int32))]
+
+
+class PlanDesc(ct.Structure):
+    _fields_ = [("grid", ct.c_int32 * 3), ("pitch", ct.c_double * 3), ("k", ct.c_double),
+                ("order", ct.c_int32), ("formulation", ct.c_int32), ("alpha_re", ct.c_double),
+                ("alpha_im", ct.c_double), ("near_radius", ct.c_int32 * 3), ("fft_shape", ct.c_int32 * 3),
+                ("precisions", ct.c_uint32)]
+
+
+class PlanInfo(ct.Structure):
+    _fields_ = [("n_dof_cell", ct.c_int32), ("n_cells", ct.c_int32), ("n_dof", ct.c_int64), ("p", ct.c_int32),
+                ("fft_shape", ct.c_int32 * 3), ("n_near", ct.c_int32), ("n_far", ct.c_int32),
+                ("precisions", ct.c_uint32), ("resident_bytes", ct.c_size_t),
+                ("workspace_bytes_per_rhs", ct.c_size_t * 2), ("scale", ct.c_double)]
+
+
+class SolveOpts(ct.Structure):
+    _fields_ = [("tol", ct.c_double), ("restart", ct.c_int32), ("max_iters", ct.c_int32),
+                ("max_refinements", ct.c_int32), ("inner_precision", ct.c_int32), ("inner_tol", ct.c_double)]
+
+
+class SolveInfo(ct.Structure):
+    _fields_ = [("iterations", ct.c_int32), ("refinements", ct.c_int32), ("rel_residual", ct.c_double)]
+
+
+EXPORTS = ["fmbem_plan_create", "fmbem_plan_query", "fmbem_plan_destroy", "fmbem_plan_export", "fmbem_matvec",
+           "fmbem_solve", "fmbem_incident_plane_wave", "fmbem_incident_point_source", "fmbem_plan_profile",
+           "fmbem_plan_profile_read", "fmbem_status_string"]
+STAGES = tuple(f"{s}_{p}" for p in ("fp64", "fp32") for s in ("near", "s2m", "fft", "m2l", "ifft", "l2t"))
+
+_lib = None
+
+
+def load():
+    """Load libfmbem.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2201_12050_amd.build`")
+    lib = ct.CDLL(LIB_PATH)
+    vp = ct.c_void_p
+    lib.fmbem_plan_create.argtypes = [ct.POINTER(CellMesh), ct.POINTER(PlanDesc), vp, ct.POINTER(vp)]
+    lib.fmbem_plan_query.argtypes = [vp, ct.POINTER(PlanInfo)]
+    lib.fmbem_plan_destroy.argtypes = [vp]
+    lib.fmbem_plan_export.argtypes = [vp, ct.c_int32, vp, ct.c_size_t]
+    lib.fmbem_matvec.argtypes = [vp, ct.c_int32, ct.c_int32, vp, vp, vp, ct.c_size_t, vp]
+    lib.fmbem_solve.argtypes = [vp, ct.POINTER(SolveOpts), ct.c_int32, vp, vp, ct.POINTER(SolveInfo), vp]
+    lib.fmbem_incident_plane_wave.argtypes = [vp, ct.c_int32, ct.POINTER(ct.c_double), ct.c_double, vp, vp]
+    lib.fmbem_incident_point_source.argtypes = [vp, ct.c_int32, ct.POINTER(ct.c_double), ct.c_double, vp, vp]
+    lib.fmbem_plan_profile.argtypes = [vp, ct.c_int32]
+    lib.fmbem_plan_profile_read.argtypes = [vp, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)]
+    lib.fmbem_status_string.argtypes = [ct.c_int32]
+    lib.fmbem_status_string.restype = ct.c_char_p
+    for f in EXPORTS[:-1]:
+        getattr(lib, f).restype = ct.c_int32
+    _lib = lib
+    return lib
+
+
+def check(status: int, where: str):
+    if status != 0:
+        raise FmbemError(status, where)
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ct.c_void_p(s.cuda_stream)
+
+
+def _precision(p) -> int:
+    if p in (FP64, "fp64", "f64", "complex128"):
+        return FP64
+    if p in (FP32, "fp32", "f32", "complex64"):
+        return FP32
+    raise ValueError(p)
+
+
+class Plan:
+    """A device-resident FMPBEM operator (fmbem_plan_create)."""
+
+    def __init__(self, vertices, triangles, grid, pitch, k, order, formulation="bm", alpha=None,
+                 near_radius=(1, 1, 1), fft_shape=(0, 0, 0), precisions=("fp64", "fp32"), stream=None):
+        lib = load()
+        self._lib = lib
+        v = np.ascontiguousarray(vertices, dtype=np.float64)
+        t = np.ascontiguousarray(triangles, dtype=np.int32)
+        mesh = CellMesh(v.shape[0], v.ctypes.data_as(ct.POINTER(ct.c_double)), t.shape[0],
+                        t.ctypes.data_as(ct.POINTER(ct.c_int32)))
+        d = PlanDesc()
+        for a in range(3):
+            d.grid[a] = int(grid[a])
+            d.pitch[a] = float(pitch[a])
+            d.near_radius[a] = int(near_radius[a])
+            d.fft_shape[a] = int(fft_shape[a])
+        d.k = float(k)
+        d.order = int(order)
+        d.formulation = {"bm": BURTON_MILLER, "cbie": CBIE}[formulation]
+        if alpha is None:
+            d.alpha_re = d.alpha_im = math.nan
+        else:
+            d.alpha_re, d.alpha_im = float(np.real(alpha)), float(np.imag(alpha))
+        d.precisions = sum(1 << _precision(p) for p in precisions)
+        h = ct.c_void_p()
+        check(lib.fmbem_plan_create(ct.byref(mesh), ct.byref(d), _stream_ptr(stream), ct.byref(h)),
+              "fmbem_plan_create")
+        self._h = h
+        info = PlanInfo()
+        check(lib.fmbem_plan_query(h, ct.byref(info)), "fmbem_plan_query")
+        self.info = {f: getattr(info, f) for f, _ in PlanInfo._fields_}
+        self.info["fft_shape"] = tuple(info.fft_shape)
+        self.info["workspace_bytes_per_rhs"] = tuple(info.workspace_bytes_per_rhs)
+        self.n = info.n_dof_cell
+        self.n_cells = info.n_cells
+        self.n_dof = info.n_dof
+        self.p = info.p
+
+    @classmethod
+    def from_workload(cls, w, precisions=("fp64", "fp32"), stream=None, **kw):
+        return cls(w.vertices, w.triangles, w.lattice.grid, w.lattice.pitch, w.k, w.order, w.formulation,
+                   near_radius=w.near_radius, precisions=precisions, stream=stream, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.fmbem_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- inspection
+    def export(self, what: str) -> np.ndarray:
+        n, p = self.n, self.p
+        B = int(np.prod(self.info["fft_shape"]))
+        shapes = {"S": (0, (self.info["n_near"], n, n), np.complex128), "V0": (1, (p, n), np.complex128),
+                  "U0": (2, (n, p), np.complex128), "Lambda": (3, (B, p, p), np.complex128),
+                  "near_offsets": (4, (self.info["n_near"], 3), np.int32)}
+        code, shape, dt = shapes[what]
+        out = np.zeros(shape, dtype=dt)
+        check(self._lib.fmbem_plan_export(self._h, code, out.ctypes.data_as(ct.c_void_p), out.nbytes),
+              "fmbem_plan_export")
+        return out
+
+    # ---------------------------------------------------------------- profiling
+    def profile(self, enable: bool = True):
+        check(self._lib.fmbem_plan_profile(self._h, 1 if enable else 0), "fmbem_plan_profile")
+
+    def profile_read(self):
+        """{stage: (total ms, launches)} of the operator applications since profile(True)."""
+        ms = (ct.c_double * len(STAGES))()
+        cnt = (ct.c_int64 * len(STAGES))()
+        check(self._lib.fmbem_plan_profile_read(self._h, ms, cnt), "fmbem_plan_profile_read")
+        return {s: (ms[i], cnt[i]) for i, s in enumerate(STAGES)}
+
+    # ---------------------------------------------------------------- operator
+    def workspace(self, n_rhs: int, precision="fp64"):
+        import torch
+        nb = n_rhs * self.info["workspace_bytes_per_rhs"][_precision(precision)]
+        return torch.empty(max(nb, 256), dtype=torch.uint8, device="cuda")
+
+    def matvec(self, x, y=None, precision="fp64", workspace=None, stream=None):
+        """y = A x for x of shape [R, n_cells, n_dof_cell] (or [R, N]) on the device."""
+        import torch
+        pr = _precision(precision)
+        dt = torch.complex128 if pr == FP64 else torch.complex64
+        if x.dtype != dt or not x.is_cuda or not x.is_contiguous():
+            raise ValueError(f"x must be a contiguous {dt} CUDA tensor")
+        R = x.numel() // self.n_dof
+        if R * self.n_dof != x.numel():
+            raise ValueError("x size is not a multiple of the DOF count")
+        if y is None:
+            y = torch.empty_like(x)
+        if workspace is None:
+            workspace = self.workspace(R, pr)
+        check(self._lib.fmbem_matvec(self._h, pr, R, ct.c_void_p(x.data_ptr()), ct.c_void_p(y.data_ptr()),
+                                     ct.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_ptr(stream)),
+              "fmbem_matvec")
+        return y
+
+    def solve(self, b, x=None, tol=1e-8, restart=30, max_iters=1000, max_refinements=20, inner="fp64",
+              inner_tol=1e-5, stream=None, raise_on_not_converged=True):
+        import torch
+        if b.dtype != torch.complex128 or not b.is_cuda or not b.is_contiguous():
+            raise ValueError("b must be a contiguous complex128 CUDA tensor")
+        R = b.numel() // self.n_dof
+        if x is None:
+            x = torch.zeros_like(b)
+        o = SolveOpts(tol, restart, max_iters, max_refinements, _precision(inner), inner_tol)
+        info = (SolveInfo * R)()
+        st = self._lib.fmbem_solve(self._h, ct.byref(o), R, ct.c_void_p(b.data_ptr()), ct.c_void_p(x.data_ptr()),
+                                   info, _stream_ptr(stream))
+        if st != 0 and (st != 5 or raise_on_not_converged):
+            check(st, "fmbem_solve")
+        return x, [dict(iterations=i.iterations, refinements=i.refinements, rel_residual=i.rel_residual)
+                   for i in info]
+
+    def incident_plane_wave(self, directions, amplitude=1.0, stream=None):
+        import torch
+        d = np.ascontiguousarray(np.atleast_2d(directions), dtype=np.float64)
+        out = torch.empty((d.shape[0], self.n_cells, self.n), dtype=torch.complex128, device="cuda")
+        check(self._lib.fmbem_incident_plane_wave(self._h, d.shape[0], d.ctypes.data_as(ct.POINTER(ct.c_double)),
+                                                  float(amplitude), ct.c_void_p(out.data_ptr()),
+                                                  _stream_ptr(stream)), "fmbem_incident_plane_wave")
+        return out
+
+    def incident_point_source(self, sources, amplitude=1.0, stream=None):
+        import torch
+        s = np.ascontiguousarray(np.atleast_2d(sources), dtype=np.float64)
+        out = torch.empty((s.shape[0], self.n_cells, self.n), dtype=torch.complex128, device="cuda")
+        check(self._lib.fmbem_incident_point_source(self._h, s.shape[0], s.ctypes.data_as(ct.POINTER(ct.c_double)),
+                                                    float(amplitude), ct.c_void_p(out.data_ptr()),
+                                                    _stream_ptr(stream)), "fmbem_incident_point_source")
+        return out

@@ -1,0 +1,136 @@
+// Internal declarations of the fmbem HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fmbem.h"
+
+namespace fmbem {
+
+// ---------------------------------------------------------------------------
+// complex helpers: interleaved (re, im) as HIP vector types
+// ---------------------------------------------------------------------------
+template <typename T> struct cplx_t;
+template <> struct cplx_t<double> { using type = double2; };
+template <> struct cplx_t<float> { using type = float2; };
+template <typename T> using cplx = typename cplx_t<T>::type;
+
+template <typename T>
+__host__ __device__ inline cplx<T> mk(T re, T im) { cplx<T> c; c.x = re; c.y = im; return c; }
+template <typename T>
+__host__ __device__ inline cplx<T> cadd(cplx<T> a, cplx<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+template <typename T>
+__host__ __device__ inline cplx<T> csub(cplx<T> a, cplx<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+template <typename T>
+__host__ __device__ inline cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T>
+__host__ __device__ inline cplx<T> cconj(cplx<T> a) { return mk<T>(a.x, -a.y); }
+template <typename T>
+__host__ __device__ inline cplx<T> cscale(cplx<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
+// a += b * c
+template <typename T>
+__host__ __device__ inline void cfma(cplx<T>& a, cplx<T> b, cplx<T> c) {
+  a.x += b.x * c.x - b.y * c.y;
+  a.y += b.x * c.y + b.y * c.x;
+}
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+constexpr int kMaxNear = 343;   // (2*3+1)^3 near offsets at near radius 3
+
+struct Plan {
+  int device = 0;
+  int n = 0;                 // triangles (DOFs) per cell
+  int grid[3] = {1, 1, 1};
+  int C = 1;
+  double pitch[3] = {1, 1, 1};
+  double k = 1.0;
+  int order = 0, p = 1, p2 = 1;  // p = (nt+1)^2, p2 = (2nt+1)^2
+  int formulation = 0;
+  double alpha_re = 0, alpha_im = 0;
+  int near_radius[3] = {1, 1, 1};
+  int fft[3] = {1, 1, 1};
+  int B = 1;
+  uint32_t precisions = 1;
+  double scale = 1.0;        // diagonal scaling s: V0 rows / s^n, U0 cols / s^n, Lambda * s^(n+n')
+  int n_near = 0, n_far = 0;
+  std::vector<int> near_off; // [n_near][3]
+  // device arrays (owned)
+  double* geom = nullptr;    // [n][18]: a(3) b(3) c(3) centroid(3) normal(3) longest, area, pad
+  int* d_near = nullptr;     // [n_near][3]
+  void* S[2] = {nullptr, nullptr};    // [n_near][n][n] complex, row-major
+  void* V0[2] = {nullptr, nullptr};   // [p][n] complex, row-major, scaled
+  void* U0[2] = {nullptr, nullptr};   // [n][p] complex, row-major, scaled
+  void* Lam[2] = {nullptr, nullptr};  // [B][p(col)][p(row)] complex: per-bin column-major, scaled, /B
+  size_t resident = 0;
+  std::vector<void*> allocations;
+  // stage profiling (HIP events on the caller's stream)
+  struct Prof {
+    bool on = false;
+    std::vector<hipEvent_t> pool;                     // free events
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;  // (stage, start, stop)
+    double ms[FMBEM_N_STAGES] = {0};
+    long long count[FMBEM_N_STAGES] = {0};
+  };
+  mutable Prof prof;
+};
+
+// record the start / end of a stage when profiling is on (returns the start event)
+hipEvent_t prof_begin(const Plan& P, hipStream_t s);
+void prof_end(const Plan& P, int stage, hipEvent_t start, hipStream_t s);
+
+size_t matvec_workspace_bytes_per_rhs(const Plan& P, int precision);
+
+// stream-ordered operator application (all arguments validated by the caller)
+hipError_t matvec_launch(const Plan& P, int precision, int R, const void* x, void* y, void* ws,
+                         hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// kernels shared between translation units
+// ---------------------------------------------------------------------------
+// column address maps of the complex GEMM
+enum ColMap : int {
+  COL_LINEAR = 0,      // column j at base + j*ld
+  COL_CELL_SHIFT = 1,  // column j = (r, c): source cell c - d (zero column if outside the grid)
+  COL_CELL_TO_BIN = 2  // column j = (r, c): padded grid bin of c, layout [bin][R][ld]
+};
+
+struct GemmCols {
+  int kind;
+  int ld;          // complex elements between consecutive columns (LINEAR) or per column
+  int R, C;        // right-hand sides, cells
+  int g0, g1, g2;  // grid M1, M2, M3
+  int f0, f1;      // FFT shape N1, N2 (for COL_CELL_TO_BIN)
+};
+
+struct GemmSeg {
+  const void* A;   // complex [M][K] row-major
+  int d0, d1, d2;  // cell offset for COL_CELL_SHIFT
+};
+
+constexpr int kMaxSeg = 32;
+struct GemmSegs {
+  int count;
+  GemmSeg seg[kMaxSeg];
+};
+
+template <typename T>
+hipError_t gemm_launch(int M, int K, int N, const GemmSegs& segs, const void* B, GemmCols bmap,
+                       void* Cm, GemmCols cmap, bool accumulate, hipStream_t s);
+
+template <typename T>
+hipError_t grid_dft_launch(void* buf, int channels, const int M[3], const int N[3], bool inverse,
+                           bool pruned, hipStream_t s);
+
+template <typename T>
+hipError_t m2l_launch(const void* Lam, void* buf, int B, int R, int p, hipStream_t s);
+
+}  // namespace fmbem

@@ -1,0 +1,118 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every
+symbol that include/fmbem.h declares, rejects invalid arguments before any
+device work, and the Python layer fails loudly when the library is missing."""
+import ctypes as ct
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2201_12050_amd as fm
+from paper_2201_12050_amd import _lib
+from workloads import icosphere
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "fmbem.h")).read()
+    return set(re.findall(r"\b(fmbem_[a-z_0-9]+)\s*\(", text))
+
+
+def test_exports_every_declared_symbol():
+    declared = _declared()
+    assert declared == set(_lib.EXPORTS)
+    lib = ct.CDLL(_lib.LIB_PATH)
+    for name in sorted(declared):
+        assert hasattr(lib, name), name
+
+
+def _desc(**kw):
+    d = _lib.PlanDesc()
+    for a in range(3):
+        d.grid[a] = (3, 3, 1)[a]
+        d.pitch[a] = 0.3
+        d.near_radius[a] = 1
+        d.fft_shape[a] = 0
+    d.k = 10.0
+    d.order = 4
+    d.formulation = 0
+    d.alpha_re = d.alpha_im = math.nan
+    d.precisions = 3
+    for key, v in kw.items():
+        if key in ("grid", "pitch", "fft_shape", "near_radius"):
+            for a in range(3):
+                getattr(d, key)[a] = v[a]
+        else:
+            setattr(d, key, v)
+    return d
+
+
+def _mesh(v, t):
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    t = np.ascontiguousarray(t, dtype=np.int32)
+    return _lib.CellMesh(v.shape[0], v.ctypes.data_as(ct.POINTER(ct.c_double)), t.shape[0],
+                         t.ctypes.data_as(ct.POINTER(ct.c_int32))), (v, t)
+
+
+@pytest.mark.parametrize("case", ["null", "bad_index", "degenerate", "order", "fft", "k", "grid", "formulation",
+                                  "nan_vertex", "radius"])
+def test_plan_create_rejects_invalid_arguments(case):
+    lib = fm.load()
+    v, t = icosphere(1, 0.1)
+    out = ct.c_void_p()
+    if case == "null":
+        assert lib.fmbem_plan_create(None, None, None, ct.byref(out)) == 1
+        return
+    desc = _desc()
+    if case == "bad_index":
+        t = t.copy(); t[3, 1] = v.shape[0]
+    elif case == "degenerate":
+        t = t.copy(); t[5, 2] = t[5, 1]
+    elif case == "nan_vertex":
+        v = v.copy(); v[0, 0] = np.nan
+    elif case == "order":
+        desc = _desc(order=21)
+    elif case == "fft":
+        desc = _desc(fft_shape=(4, 0, 0))   # needs >= 2*3-1 = 5
+    elif case == "k":
+        desc = _desc(k=0.0)
+    elif case == "grid":
+        desc = _desc(grid=(0, 3, 1))
+    elif case == "formulation":
+        desc = _desc(formulation=7)
+    elif case == "radius":
+        desc = _desc(near_radius=(4, 1, 1))
+    mesh, keep = _mesh(v, t)
+    assert lib.fmbem_plan_create(ct.byref(mesh), ct.byref(desc), None, ct.byref(out)) == 1
+    assert out.value is None
+
+
+def test_other_entry_points_reject_null_plan():
+    lib = fm.load()
+    assert lib.fmbem_matvec(None, 0, 1, None, None, None, 0, None) == 1
+    assert lib.fmbem_plan_query(None, None) == 1
+    assert lib.fmbem_plan_destroy(None) == 1
+    assert lib.fmbem_plan_export(None, 0, None, 0) == 1
+    assert lib.fmbem_solve(None, None, 1, None, None, None, None) == 1
+    assert lib.fmbem_incident_plane_wave(None, 1, None, 1.0, None, None) == 1
+    assert lib.fmbem_status_string(5) == b"not converged"
+    assert lib.fmbem_status_string(99) == b"unknown status"
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "nope.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(ImportError):
+        _lib.load()
+
+
+def test_product_path_does_not_import_oracle():
+    pkg = os.path.join(ROOT, "paper_2201_12050_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f

@@ -1,0 +1,180 @@
+"""GPU parity of the HIP library against the FP64 oracle, through the C ABI.
+
+Tolerances (relative l2 norms): FP64 operator 1e-12, FP32 operator 1e-5,
+solution after refinement 1e-6; operator data (S_d, V0, U0, Lambda) 1e-12.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import bem, operator as op, solve
+from workloads import icosphere, tube_segment, Lattice, config_tiny, config_grid16
+from workloads.rng import random_complex, unit_directions
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _plan(fm_mod, v, t, grid, pitch, k, nt, formulation="bm"):
+    return fm_mod.Plan(v, t, grid, pitch, k, nt, formulation)
+
+
+CASES = {
+    # name: (icosphere level or 'tube', grid, frequency, n_t)
+    "sphere80_3x3": (1, (3, 3, 1), 800.0, 6),
+    "sphere80_5x3_ragged": (1, (5, 3, 1), 800.0, 4),
+    "sphere80_line7": (1, (7, 1, 1), 1200.0, 8),
+    "tube192_3x2x3": ("tube", (3, 2, 3), 600.0, 6),
+}
+
+
+def _geometry(kind):
+    if kind == "tube":
+        v, t = tube_segment(0.08, 0.25, 32, 3)
+        return v, t, (0.2, 0.2, 0.25)
+    v, t = icosphere(kind, 0.1)
+    return v, t, (0.3, 0.3, 0.3)
+
+
+@pytest.fixture(scope="module")
+def cases():
+    import paper_2201_12050_amd as fm
+    out = {}
+    for name, (kind, grid, f, nt) in CASES.items():
+        v, t, pitch = _geometry(kind)
+        lat = Lattice(grid, pitch)
+        k = 2 * np.pi * f / 343.0
+        F = op.FMPBEM(v, t, lat, k, nt, -1j / k)
+        P = fm.Plan(v, t, grid, pitch, k, nt)
+        out[name] = (F, P, lat)
+    return out
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_operator_data_matches_oracle(cases, name):
+    F, P, lat = cases[name]
+    S = P.export("S")
+    offs = P.export("near_offsets")
+    assert len(offs) == len(F.near)
+    for i, d in enumerate(offs):
+        assert rel(S[i], F.S[tuple(int(c) for c in d)]) < 1e-12
+    assert rel(P.export("V0"), F.V0) < 1e-12
+    assert rel(P.export("U0"), F.U0) < 1e-12
+    # Lambda = DFT over the grid of the first block column of the circulant embedding of K
+    N = P.info["fft_shape"]
+    col = np.zeros((N[2], N[1], N[0], F.p, F.p), dtype=np.complex128)
+    for d in F.far:
+        col[(d[2] % N[2], d[1] % N[1], d[0] % N[0])] = F.K[d]
+    ref = np.fft.fftn(col, axes=(0, 1, 2)).reshape(-1, F.p, F.p)
+    assert rel(P.export("Lambda"), ref) < 1e-12
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("R", [1, 3])
+def test_matvec_matches_oracle(cases, name, R):
+    F, P, lat = cases[name]
+    x = random_complex((R, lat.n_cells, F.n), 100 + R)
+    ref = F.matvec(x)
+    xd = torch.from_numpy(x).cuda()
+    y64 = P.matvec(xd, precision="fp64").cpu().numpy()
+    assert rel(y64, ref) < 1e-12
+    y32 = P.matvec(xd.to(torch.complex64), precision="fp32").cpu().numpy()
+    assert rel(y32, ref) < 1e-5
+    # every right-hand side on its own
+    for r in range(R):
+        assert rel(y64[r], ref[r]) < 1e-12
+
+
+def test_matvec_batched_equals_alone(cases):
+    F, P, lat = cases["sphere80_5x3_ragged"]
+    x = torch.from_numpy(random_complex((5, lat.n_cells, F.n), 7)).cuda().to(torch.complex64)
+    yb = P.matvec(x, precision="fp32")
+    for r in range(5):
+        ya = P.matvec(x[r:r + 1].contiguous(), precision="fp32")
+        assert torch.equal(yb[r:r + 1], ya)
+
+
+def test_incident_fields_match_oracle(cases):
+    F, P, lat = cases["sphere80_3x3"]
+    v, t, _ = _geometry(1)
+    dirs = unit_directions(3, 11)
+    ref = bem.rhs_plane_wave(v, t, lat, F.k, F.alpha, dirs)
+    got = P.incident_plane_wave(dirs).cpu().numpy().reshape(3, -1)
+    assert rel(got, ref) < 1e-13
+    src = np.array([[0.3, -2.0, 0.1], [1.0, 1.5, -0.7]])
+    ref = bem.rhs_point_source(v, t, lat, F.k, F.alpha, src, amplitude=2.0)
+    got = P.incident_point_source(src, amplitude=2.0).cpu().numpy().reshape(2, -1)
+    assert rel(got, ref) < 1e-13
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    import paper_2201_12050_amd as fm
+    out = {}
+    for form in ("bm", "cbie"):
+        w = config_tiny(form)
+        F = op.FMPBEM.from_workload(w)
+        P = fm.Plan.from_workload(w)
+        out[form] = (w, F, P)
+    return out
+
+
+@pytest.mark.parametrize("form", ["bm", "cbie"])
+def test_tiny_config_matvec_and_solve(tiny, form):
+    # 4x1 line of 320-triangle spheres, 500 Hz, n_t = 10 (N = 1280)
+    w, F, P = tiny[form]
+    a = bem.default_alpha(w.k, form)
+    x = random_complex((1, w.lattice.n_cells, w.n_dof_cell), 3)
+    xd = torch.from_numpy(x).cuda()
+    assert rel(P.matvec(xd).cpu().numpy(), F.matvec(x)) < 1e-12
+    b = bem.rhs_plane_wave(w.vertices, w.triangles, w.lattice, w.k, a, w.plane_waves)
+    bd = P.incident_plane_wave(w.plane_waves)
+    assert rel(bd.cpu().numpy().reshape(1, -1), b) < 1e-13
+    x_lu = solve.lu_solve(F.dense(), b[0])
+    xs, info = P.solve(bd, tol=1e-10, inner="fp64")
+    assert info[0]["rel_residual"] <= 1e-10
+    assert rel(xs.cpu().numpy().ravel(), x_lu) < 1e-8
+    xr, info = P.solve(bd, tol=1e-9, inner="fp32")
+    assert info[0]["rel_residual"] <= 1e-9
+    assert rel(xr.cpu().numpy().ravel(), x_lu) < 1e-6
+
+
+def test_solve_not_converged_reports_status(tiny):
+    w, F, P = tiny["bm"]
+    bd = P.incident_plane_wave(w.plane_waves)
+    import paper_2201_12050_amd as fm
+    with pytest.raises(fm.FmbemError) as e:
+        P.solve(bd, tol=1e-14, max_iters=2, inner="fp64")
+    assert e.value.status == 5
+    xs, info = P.solve(bd, tol=1e-14, max_iters=2, inner="fp64", raise_on_not_converged=False)
+    assert info[0]["iterations"] == 2 and np.isfinite(info[0]["rel_residual"])
+
+
+@pytest.mark.slow
+def test_grid16_full_size_sampled_rows():
+    # 16x16 lattice of 1280-triangle spheres, 1 kHz, n_t = 10 (N = 327,680), in the launch
+    # configuration the benchmark times; sampled output rows computed one by one by the oracle
+    import paper_2201_12050_amd as fm
+    w = config_grid16()
+    P = fm.Plan.from_workload(w)
+    x = random_complex((1, w.lattice.n_cells, w.n_dof_cell), 2201)
+    xd = torch.from_numpy(x).cuda()
+    y64 = P.matvec(xd).cpu().numpy().reshape(1, -1)
+    y32 = P.matvec(xd.to(torch.complex64), precision="fp32").cpu().numpy().reshape(1, -1)
+    rng = np.random.default_rng(5)
+    n = w.n_dof_cell
+    cells = [0, 15, 17 * 8, 255] + list(rng.integers(0, 256, 4))
+    dofs = [c * n + int(rng.integers(0, n)) for c in cells]
+    ref = op.sampled_apply(w.vertices, w.triangles, w.lattice, w.k, w.order, -1j / w.k, x, dofs)
+    assert rel(y64[:, dofs], ref) < 1e-12
+    assert rel(y32[:, dofs], ref) < 1e-5

@@ -75,3 +75,14 @@ def test_all_near_is_pbem(small):
     A1 = bem.dense_exact(v, t, lat, k, a)
     x = random_complex(lat.n_cells * t.shape[0], 3)
     assert np.linalg.norm(F.matvec(x) - A1 @ x) <= 1e-13 * np.linalg.norm(A1 @ x)
+
+
+def test_sampled_apply_matches_blocks(small):
+    # the row-by-row sampler used at full lattice sizes agrees with the block-by-block apply
+    v, t, lat, k, a = small
+    F = op.FMPBEM(v, t, lat, k, 4, a)
+    x = random_complex((2, lat.n_cells, t.shape[0]), 9)
+    y = F.matvec(x).reshape(2, -1)
+    dofs = [0, 17, 80 * 4 + 5, 80 * 8 + 79]
+    ys = op.sampled_apply(v, t, lat, k, 4, a, x, dofs)
+    assert np.abs(ys - y[:, dofs]).max() <= 1e-13 * np.abs(y).max()
