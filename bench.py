@@ -89,7 +89,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--tol", type=float, default=1e-8, help="FP64 true relative residual of a solve")
+    # residual target calibrated so that the solution error stays below 1e-6 (checked every step)
+    ap.add_argument("--tol", type=float, default=1e-7, help="FP64 true relative residual of a solve")
     ap.add_argument("--matvec-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--grid", type=int, nargs=2, default=(16, 16))
@@ -130,19 +131,21 @@ def main():
         torch.cuda.synchronize()
         if profile:
             P.profile(True)
-        lat, infos, errs = [], [], []
+        lat, infos, xs = [], [], []
+        torch.cuda.synchronize()
         t_start = time.perf_counter()
         for _ in range(steps):
             t1 = time.perf_counter()
             x, info = P.solve(b, tol=args.tol, inner=inner)
             lat.append(time.perf_counter() - t1)
             infos.append(info[0])
-            errs.append(solution_error(x))
+            xs.append(x)
         torch.cuda.synchronize()
         total = time.perf_counter() - t_start
         prof = P.profile_read() if profile else None
         if profile:
             P.profile(False)
+        errs = [solution_error(x) for x in xs]   # every solution checked, outside the timed region
         return total, lat, infos, errs, prof
 
     tot32, lat32, inf32, err32, prof = timed_solves("fp32", args.steps, args.warmup, True)
@@ -173,7 +176,8 @@ def main():
     # roofline of the dominant kernel: the FP32 near-field grouped GEMM, timed with HIP events
     # recorded inside the library on the solve's stream over the timed region
     n = w.n_dof_cell
-    flops_near = 8.0 * n * n * near_pairs(w.lattice.grid)          # one RHS per launch
+    # one grouped launch: near-field block products plus the S2M product, one RHS
+    flops_near = 8.0 * n * n * near_pairs(w.lattice.grid) + 8.0 * P.p * n * w.lattice.n_cells
     ms_near, cnt_near = prof["near_fp32"]
     avg_near = ms_near / cnt_near / 1e3
     achieved = flops_near / avg_near
@@ -204,11 +208,12 @@ def main():
                        "fp64": {"p50": percentile(lat64, 50) * 1e3, "p99": percentile(lat64, 99) * 1e3}},
         "matvecs_per_s": mv,
         "solution_error_vs_fp64": {"fp32_refined": max(err32), "fp64": max(err64)},
+        "accuracy_ok": bool(max(err32) <= 1e-6 and max(err64) <= 1e-6),
         "iterations": {"fp32_refined": inf32[-1], "fp64": inf64[-1]},
         "plan_build_s": plan_s,
         "stages_fp32_refined": stages,
         "m2l_fp32_GBps": m2l_bytes / m2l_avg / 1e9 if m2l_avg > 0 else None,
-        "roofline": {"bound": "mfma", "kernel": "near-field grouped GEMM (FP32, real-split 2x2 MFMA)",
+        "roofline": {"bound": "mfma", "kernel": "near field + S2M grouped GEMM (FP32, real-split 2x2 MFMA)",
                      "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_MFMA, "traffic": None,
                      "avg_launch_us": avg_near * 1e6, "algorithmic_flops_per_launch": flops_near},

@@ -163,7 +163,8 @@ fmbem_status fmbem_incident_point_source(fmbem_plan plan, int32_t n_rhs, const d
  * recorded on the call's stream around each stage.  enable = 1 clears the
  * counters and starts recording, 0 stops.  Not for concurrent use of the same
  * plan from several host threads while enabled.
- * Stages: 0 near field, 1 S2M, 2 forward DFT, 3 M2L, 4 inverse DFT, 5 L2T in FP64;
+ * Stages: 0 near field + S2M (one grouped launch), 1 sum of the near-field partial
+ * products, 2 forward DFT, 3 M2L, 4 inverse DFT, 5 L2T, in FP64;
  * 6..11 the same stages in FP32. */
 #define FMBEM_N_STAGES 12
 fmbem_status fmbem_plan_profile(fmbem_plan plan, int32_t enable);

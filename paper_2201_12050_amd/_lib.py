@@ -58,7 +58,7 @@ class SolveInfo(ct.Structure):
 EXPORTS = ["fmbem_plan_create", "fmbem_plan_query", "fmbem_plan_destroy", "fmbem_plan_export", "fmbem_matvec",
            "fmbem_solve", "fmbem_incident_plane_wave", "fmbem_incident_point_source", "fmbem_plan_profile",
            "fmbem_plan_profile_read", "fmbem_status_string"]
-STAGES = tuple(f"{s}_{p}" for p in ("fp64", "fp32") for s in ("near", "s2m", "fft", "m2l", "ifft", "l2t"))
+STAGES = tuple(f"{s}_{p}" for p in ("fp64", "fp32") for s in ("near", "reduce", "fft", "m2l", "ifft", "l2t"))
 
 _lib = None
 

@@ -69,7 +69,7 @@ struct Plan {
   void* S[2] = {nullptr, nullptr};    // [n_near][n][n] complex, row-major
   void* V0[2] = {nullptr, nullptr};   // [p][n] complex, row-major, scaled
   void* U0[2] = {nullptr, nullptr};   // [n][p] complex, row-major, scaled
-  void* Lam[2] = {nullptr, nullptr};  // [B][p(col)][p(row)] complex: per-bin column-major, scaled, /B
+  void* Lam[2] = {nullptr, nullptr};  // [B][p(col)][ldp] complex: per-bin column-major, scaled, /B
   size_t resident = 0;
   std::vector<void*> allocations;
   // stage profiling (HIP events on the caller's stream)
@@ -81,6 +81,8 @@ struct Plan {
     long long count[FMBEM_N_STAGES] = {0};
   };
   mutable Prof prof;
+  // autotuned near-field tile shape per (precision, columns = n_rhs * cells)
+  mutable std::vector<std::pair<long long, int>> near_shape;
 };
 
 // record the start / end of a stage when profiling is on (returns the start event)
@@ -126,10 +128,36 @@ template <typename T>
 hipError_t gemm_launch(int M, int K, int N, const GemmSegs& segs, const void* B, GemmCols bmap,
                        void* Cm, GemmCols cmap, bool accumulate, hipStream_t s);
 
+// grouped near-field / S2M launch (near.hip)
+struct NearJob {
+  const void* A;   // complex [M][n] row-major
+  void* out;       // dest 0: [N][M] column-major slice; dest 1: padded grid [bin][R][M]
+  int M;
+  int d0, d1, d2;  // cell offset of the B columns
+  int dest;
+  int tile0;       // first workgroup of this job (set by near_launch)
+};
+struct NearJobs {
+  int count;
+  NearJob job[kMaxSeg + 1];
+};
+struct NearGrid {
+  int C, R, M0, M1, M2, N0, N1;
+};
+
+// shape < 0: default tile shape for this problem; else one of near_num_shapes() shapes
+template <typename T>
+hipError_t near_launch(int n, int N, NearJobs jobs, const void* x, const NearGrid& g, hipStream_t s, int shape = -1);
+int near_num_shapes();
+template <typename T>
+hipError_t near_reduce_launch(const void* part, int ns, size_t len, void* y, hipStream_t s);
+
 template <typename T>
 hipError_t grid_dft_launch(void* buf, int channels, const int M[3], const int N[3], bool inverse,
                            bool pruned, hipStream_t s);
 
+// column stride (complex elements) of the per-bin column-major Lambda blocks
+int lambda_ld(int p);
 template <typename T>
 hipError_t m2l_launch(const void* Lam, void* buf, int B, int R, int p, hipStream_t s);
 

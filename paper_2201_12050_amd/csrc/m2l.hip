@@ -1,23 +1,96 @@
 // Per-bin M2L product of the diagonalised far field (Sec. 2.4, eq. (diagonalized);
 // Sec. 3.5, eq. (FMPBEMsystem)):  lhat_b = Lambda_b mhat_b  for every FFT bin b.
 //
-// Lambda_b (p x p, complex) is stored column-major per bin, so that the
-// threads of a workgroup, one per output row, read consecutive addresses for
-// every column j.  The product is in place in the [bin][R][p] spectrum buffer:
-// each workgroup owns one bin, stages a group of up to kRhs right-hand-side
-// vectors in LDS, and writes the results over them.
+// HBM-bound for one right-hand side: Lambda (B p^2 complex) is streamed once.
+// Lambda_b is stored column-major with an even column stride ldp, so that two
+// consecutive rows form one aligned 16-byte (FP32) / 32-byte (FP64) load.  A
+// workgroup owns one bin: 4 wave groups split the columns j, each thread of a
+// group accumulates two rows for up to kRhs right-hand sides, and the groups are
+// summed in LDS.  The product is in place in the [bin][R][p] spectrum buffer.
 #include "common.hpp"
 
 namespace fmbem {
 
 constexpr int kRhs = 4;
+constexpr int kGroups = 4;
+
+template <typename T> struct Pair;
+template <> struct Pair<float> { using type = float4; };
+template <> struct Pair<double> { using type = double4; };
 
 template <typename T>
-__global__ void m2l_gemv_kernel(const cplx<T>* __restrict__ Lam, cplx<T>* __restrict__ buf, int R, int p) {
+__global__ __launch_bounds__(256) void m2l_gemv_kernel(const cplx<T>* __restrict__ Lam, cplx<T>* __restrict__ buf,
+                                                       int R, int p, int ldp) {
+  extern __shared__ unsigned char smem_raw[];
+  cplx<T>* xs = reinterpret_cast<cplx<T>*>(smem_raw);        // [kRhs][p]
+  cplx<T>* red = xs + kRhs * p;                               // [kGroups][64][kRhs][2]
+  using P2 = typename Pair<T>::type;
+  const int bin = blockIdx.x;
+  const cplx<T>* Lb = Lam + (size_t)bin * p * ldp;
+  cplx<T>* vb = buf + (size_t)bin * R * p;
+  const int g = threadIdx.x / 64;
+  const int rp = threadIdx.x % 64;                 // row pair (rows 2rp, 2rp+1); p <= 128
+  const int jc = (p + kGroups - 1) / kGroups;
+  const int j0 = g * jc, j1 = min(p, j0 + jc);
+  const bool active = 2 * rp < p;
+  for (int r0 = 0; r0 < R; r0 += kRhs) {
+    const int nr = min(kRhs, R - r0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < nr * p; t += blockDim.x) xs[t] = vb[(size_t)r0 * p + t];
+    __syncthreads();
+    cplx<T> a0[kRhs], a1[kRhs];
+#pragma unroll
+    for (int r = 0; r < kRhs; ++r) {
+      a0[r] = mk<T>(0, 0);
+      a1[r] = mk<T>(0, 0);
+    }
+    if (active) {
+      const P2* col = reinterpret_cast<const P2*>(Lb + 2 * rp);
+      const int step = ldp / 2;
+#pragma unroll 4
+      for (int j = j0; j < j1; ++j) {
+        const P2 v = col[(size_t)j * step];
+        const cplx<T> l0 = mk<T>(v.x, v.y), l1 = mk<T>(v.z, v.w);
+#pragma unroll
+        for (int r = 0; r < kRhs; ++r) {
+          if (r < nr) {
+            const cplx<T> m = xs[r * p + j];
+            cfma<T>(a0[r], l0, m);
+            cfma<T>(a1[r], l1, m);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kRhs; ++r) {
+      red[((g * 64 + rp) * kRhs + r) * 2] = a0[r];
+      red[((g * 64 + rp) * kRhs + r) * 2 + 1] = a1[r];
+    }
+    __syncthreads();
+    if (g == 0 && active) {
+#pragma unroll
+      for (int r = 0; r < kRhs; ++r) {
+        if (r < nr) {
+          cplx<T> s0 = red[(rp * kRhs + r) * 2], s1 = red[(rp * kRhs + r) * 2 + 1];
+          for (int q = 1; q < kGroups; ++q) {
+            s0 = cadd<T>(s0, red[((q * 64 + rp) * kRhs + r) * 2]);
+            s1 = cadd<T>(s1, red[((q * 64 + rp) * kRhs + r) * 2 + 1]);
+          }
+          vb[(size_t)(r0 + r) * p + 2 * rp] = s0;
+          if (2 * rp + 1 < p) vb[(size_t)(r0 + r) * p + 2 * rp + 1] = s1;
+        }
+      }
+    }
+  }
+}
+
+// generic fallback for p > 128: one thread per row
+template <typename T>
+__global__ void m2l_rows_kernel(const cplx<T>* __restrict__ Lam, cplx<T>* __restrict__ buf, int R, int p, int ldp) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* xs = reinterpret_cast<cplx<T>*>(smem_raw);  // [kRhs][p]
   const int bin = blockIdx.x;
-  const cplx<T>* Lb = Lam + (size_t)bin * p * p;
+  const cplx<T>* Lb = Lam + (size_t)bin * p * ldp;
   cplx<T>* vb = buf + (size_t)bin * R * p;
   for (int r0 = 0; r0 < R; r0 += kRhs) {
     const int nr = min(kRhs, R - r0);
@@ -29,7 +102,7 @@ __global__ void m2l_gemv_kernel(const cplx<T>* __restrict__ Lam, cplx<T>* __rest
 #pragma unroll
       for (int r = 0; r < kRhs; ++r) acc[r] = mk<T>(0, 0);
       for (int j = 0; j < p; ++j) {
-        const cplx<T> a = Lb[(size_t)j * p + i];
+        const cplx<T> a = Lb[(size_t)j * ldp + i];
 #pragma unroll
         for (int r = 0; r < kRhs; ++r)
           if (r < nr) cfma<T>(acc[r], a, xs[r * p + j]);
@@ -41,11 +114,20 @@ __global__ void m2l_gemv_kernel(const cplx<T>* __restrict__ Lam, cplx<T>* __rest
   }
 }
 
+int lambda_ld(int p) { return p + (p & 1); }
+
 template <typename T>
 hipError_t m2l_launch(const void* Lam, void* buf, int B, int R, int p, hipStream_t s) {
-  const int threads = min(512, ((p + 63) / 64) * 64);
-  hipLaunchKernelGGL(m2l_gemv_kernel<T>, dim3(B), dim3(threads), kRhs * p * sizeof(cplx<T>), s,
-                     reinterpret_cast<const cplx<T>*>(Lam), reinterpret_cast<cplx<T>*>(buf), R, p);
+  const int ldp = lambda_ld(p);
+  if (p <= 128) {
+    const size_t lds = (size_t)(kRhs * p + kGroups * 64 * kRhs * 2) * sizeof(cplx<T>);
+    hipLaunchKernelGGL(m2l_gemv_kernel<T>, dim3(B), dim3(256), lds, s, reinterpret_cast<const cplx<T>*>(Lam),
+                       reinterpret_cast<cplx<T>*>(buf), R, p, ldp);
+  } else {
+    const int threads = min(512, ((p + 63) / 64) * 64);
+    hipLaunchKernelGGL(m2l_rows_kernel<T>, dim3(B), dim3(threads), kRhs * p * sizeof(cplx<T>), s,
+                       reinterpret_cast<const cplx<T>*>(Lam), reinterpret_cast<cplx<T>*>(buf), R, p, ldp);
+  }
   return hipGetLastError();
 }
 

@@ -1,22 +1,26 @@
 // Operator application y = (S + U F^-1 Lambda F V) x  (Sec. 3.5, eq. (FMPBEMsystem)).
 //
-// Stream-ordered sequence on the caller's stream:
-//   1. near field   y = sum_d S_d x_{c-d}                  (grouped GEMM, one segment per offset)
-//   2. S2M          mhat[bin(c)][r] = V0 x_c               (GEMM into the padded grid)
-//   3. forward DFT  over the cell grid, pruned inputs      (incomplete Fourier matrices, Sec. 2.4)
-//   4. M2L          lhat_b = Lambda_b mhat_b               (per-bin product)
-//   5. inverse DFT  cropped to the first M_a outputs per axis
-//   6. L2T          y += U0 l_c                            (GEMM reading the padded grid)
+// Stream-ordered sequence on the caller's stream (profiling stage in brackets):
+//   [0] near field + S2M, one grouped launch:
+//         part_d = S_d x_{c-d} for every near offset d, mhat[bin(c)][r] = V0 x_c
+//   [1] y = sum_d part_d  (fixed order)
+//   [2] forward DFT  over the cell grid, pruned inputs      (incomplete Fourier matrices, Sec. 2.4)
+//   [3] M2L          lhat_b = Lambda_b mhat_b               (per-bin product)
+//   [4] inverse DFT  cropped to the first M_a outputs per axis
+//   [5] L2T          y += U0 l_c                            (GEMM reading the padded grid)
+// Workspace: [padded grid B x R x p][near partials n_near x R x C x n], 256-byte aligned.
+#include <algorithm>
 #include <cmath>
 
 #include "common.hpp"
 
 namespace fmbem {
 
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
 size_t matvec_workspace_bytes_per_rhs(const Plan& P, int precision) {
   const size_t el = precision == FMBEM_FP64 ? 16 : 8;
-  const size_t b = (size_t)P.B * P.p * el;
-  return (b + 255) / 256 * 256;
+  return align256((size_t)P.B * P.p * el) + align256((size_t)P.n_near * P.C * P.n * el);
 }
 
 hipEvent_t prof_begin(const Plan& P, hipStream_t s) {
@@ -39,43 +43,90 @@ void prof_end(const Plan& P, int stage, hipEvent_t start, hipStream_t s) {
   P.prof.marks.push_back({stage, {start, e}});
 }
 
+// Autotuner of the near-field tile shape: on the first application with a given
+// precision and column count, every shape is launched once to warm up and twice
+// timed with HIP events on the caller's stream (the launches compute the real
+// partial products, which the launch that follows overwrites); the fastest is
+// cached in the plan.  Blocks the host once per (precision, columns).
+template <typename T>
+static int near_tuned_shape(const Plan& P, int n, int N, const NearJobs& jobs, const void* x, const NearGrid& g,
+                            hipStream_t s) {
+  const long long key = (long long)N * 2 + (sizeof(T) == 8 ? 0 : 1);
+  for (const auto& kv : P.near_shape)
+    if (kv.first == key) return kv.second;
+  int best = -1;
+  float best_ms = 0.f;
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
+    for (int v = 0; v < near_num_shapes(); ++v) {
+      if (near_launch<T>(n, N, jobs, x, g, s, v) != hipSuccess) continue;
+      hipEventRecord(a, s);
+      near_launch<T>(n, N, jobs, x, g, s, v);
+      near_launch<T>(n, N, jobs, x, g, s, v);
+      hipEventRecord(b, s);
+      float ms = 0.f;
+      if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) continue;
+      if (best < 0 || ms < best_ms) {
+        best = v;
+        best_ms = ms;
+      }
+    }
+  }
+  if (a) hipEventDestroy(a);
+  if (b) hipEventDestroy(b);
+  P.near_shape.push_back({key, best});
+  return best;
+}
+
 template <typename T>
 static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* ws, hipStream_t s) {
   const int prec = sizeof(T) == 8 ? 0 : 1;
   const int n = P.n, C = P.C, p = P.p;
   const int N = R * C;
-  hipEvent_t ev = prof_begin(P, s);
-  // 1. near field
+  const size_t el = sizeof(cplx<T>);
+  char* grid_buf = reinterpret_cast<char*>(ws);
+  char* part = grid_buf + align256((size_t)P.B * R * p * el);
+  const size_t slice = (size_t)N * n;  // complex elements per near partial
+  // [0] near field and S2M
+  hipEvent_t ev = nullptr;
   {
-    GemmSegs segs;
-    segs.count = P.n_near;
-    const size_t blk = (size_t)n * n * sizeof(cplx<T>);
+    NearJobs jobs;
+    jobs.count = 0;
+    const size_t blk = (size_t)n * n * el;
     for (int d = 0; d < P.n_near; ++d) {
-      segs.seg[d].A = reinterpret_cast<const char*>(P.S[prec]) + d * blk;
-      segs.seg[d].d0 = P.near_off[3 * d];
-      segs.seg[d].d1 = P.near_off[3 * d + 1];
-      segs.seg[d].d2 = P.near_off[3 * d + 2];
+      NearJob& j = jobs.job[jobs.count++];
+      j.A = reinterpret_cast<const char*>(P.S[prec]) + d * blk;
+      j.out = part + d * slice * el;
+      j.M = n;
+      j.d0 = P.near_off[3 * d];
+      j.d1 = P.near_off[3 * d + 1];
+      j.d2 = P.near_off[3 * d + 2];
+      j.dest = 0;
     }
-    GemmCols bm{COL_CELL_SHIFT, n, R, C, P.grid[0], P.grid[1], P.grid[2], P.fft[0], P.fft[1]};
-    GemmCols cm{COL_LINEAR, n, R, C, P.grid[0], P.grid[1], P.grid[2], P.fft[0], P.fft[1]};
-    hipError_t e = gemm_launch<T>(n, n, N, segs, x, bm, y, cm, false, s);
+    if (P.n_far > 0) {
+      NearJob& j = jobs.job[jobs.count++];
+      j.A = P.V0[prec];
+      j.out = grid_buf;
+      j.M = p;
+      j.d0 = j.d1 = j.d2 = 0;
+      j.dest = 1;
+    }
+    NearGrid g{C, R, P.grid[0], P.grid[1], P.grid[2], P.fft[0], P.fft[1]};
+    const int shape = near_tuned_shape<T>(P, n, N, jobs, x, g, s);
+    ev = prof_begin(P, s);
+    hipError_t e = near_launch<T>(n, N, jobs, x, g, s, shape);
     if (e != hipSuccess) return e;
   }
   prof_end(P, 0 + 6 * prec, ev, s);
-  if (P.n_far == 0) return hipSuccess;
+  // [1] sum of the near partials
   ev = prof_begin(P, s);
-  // 2. S2M into the padded grid
   {
-    GemmSegs segs;
-    segs.count = 1;
-    segs.seg[0] = GemmSeg{P.V0[prec], 0, 0, 0};
-    GemmCols bm{COL_LINEAR, n, R, C, P.grid[0], P.grid[1], P.grid[2], P.fft[0], P.fft[1]};
-    GemmCols cm{COL_CELL_TO_BIN, p, R, C, P.grid[0], P.grid[1], P.grid[2], P.fft[0], P.fft[1]};
-    hipError_t e = gemm_launch<T>(p, n, N, segs, x, bm, ws, cm, false, s);
+    hipError_t e = near_reduce_launch<T>(part, P.n_near, slice, y, s);
     if (e != hipSuccess) return e;
   }
   prof_end(P, 1 + 6 * prec, ev, s);
-  // 3-5. DFT, M2L, inverse DFT
+  if (P.n_far == 0) return hipSuccess;
+  // [2]-[4] DFT, M2L, inverse DFT
   ev = prof_begin(P, s);
   hipError_t e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, false, true, s);
   if (e != hipSuccess) return e;
@@ -88,7 +139,7 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
   e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, true, true, s);
   if (e != hipSuccess) return e;
   prof_end(P, 4 + 6 * prec, ev, s);
-  // 6. L2T accumulate
+  // [5] L2T accumulate
   ev = prof_begin(P, s);
   {
     GemmSegs segs;

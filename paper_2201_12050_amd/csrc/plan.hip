@@ -196,7 +196,7 @@ __device__ double2 hyper_self(const Geo& e, double k, const QuadTab& Q) {
 }
 
 // one entry S_d[i][j] per thread; entries ordered (d, i, j) with j fastest
-__global__ void near_kernel(const double* __restrict__ geom, int n, const int* __restrict__ offs, int n_near,
+__global__ void assemble_near_kernel(const double* __restrict__ geom, int n, const int* __restrict__ offs, int n_near,
                             double p0, double p1, double p2, double k, double2 alpha, int hyper, QuadTab Q,
                             double2* __restrict__ S64, float2* __restrict__ S32) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -435,7 +435,7 @@ __global__ void ogrid_kernel(int B, int N0, int N1, int N2, int M0, int M1, int 
 __global__ void lambda_kernel(const double2* __restrict__ Oh, int P2, int p, int B, const int* __restrict__ ptr,
                               const double2* __restrict__ coef, const int* __restrict__ oidx,
                               const double* __restrict__ sig, const int* __restrict__ nof, double invB,
-                              double2* __restrict__ L64, float2* __restrict__ L32) {
+                              int ldp, double2* __restrict__ L64, float2* __restrict__ L32) {
   extern __shared__ double2 so[];
   const int bin = blockIdx.y;
   for (int t = threadIdx.x; t < P2; t += blockDim.x) so[t] = Oh[(size_t)bin * P2 + t];
@@ -454,8 +454,13 @@ __global__ void lambda_kernel(const double2* __restrict__ Oh, int P2, int p, int
     }
     const double f = sig[nof[i]] * sig[nof[j]] * invB;
     const double2 v = make_double2(re * f, im * f);
-    L64[(size_t)bin * pp + e] = v;
-    if (L32) L32[(size_t)bin * pp + e] = make_float2((float)v.x, (float)v.y);
+    const size_t o = ((size_t)bin * p + j) * ldp + i;
+    L64[o] = v;
+    if (L32) L32[o] = make_float2((float)v.x, (float)v.y);
+    if (i == p - 1 && ldp > p) {  // zero the padding row of the column
+      L64[o + 1] = make_double2(0, 0);
+      if (L32) L32[o + 1] = make_float2(0.f, 0.f);
+    }
   }
 }
 
@@ -635,7 +640,7 @@ static hipError_t plan_build(Plan& P, const std::vector<double>& geo, hipStream_
   if (want32) FM_CHECK(plan_alloc(P, &P.S[1], ns * sizeof(float2)));
   {
     const size_t blocks = (ns + 255) / 256;
-    hipLaunchKernelGGL(near_kernel, dim3((unsigned)blocks), dim3(256), 0, s, P.geom, n, P.d_near, P.n_near,
+    hipLaunchKernelGGL(assemble_near_kernel, dim3((unsigned)blocks), dim3(256), 0, s, P.geom, n, P.d_near, P.n_near,
                        P.pitch[0], P.pitch[1], P.pitch[2], P.k, alpha, hyper, Q, (double2*)P.S[0],
                        (float2*)P.S[1]);
     FM_CHECK(hipGetLastError());
@@ -710,13 +715,14 @@ static hipError_t plan_build(Plan& P, const std::vector<double>& geo, hipStream_
     hipMemcpyAsync(d_oidx, T.oidx.data(), T.oidx.size() * sizeof(int), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(d_coef, T.coef.data(), T.coef.size() * sizeof(double2), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(d_nof, nof.data(), p * sizeof(int), hipMemcpyHostToDevice, s);
-    const size_t nl = (size_t)P.B * p * p;
+    const int ldp = lambda_ld(p);
+    const size_t nl = (size_t)P.B * p * ldp;
     if ((err = plan_alloc(P, &P.Lam[0], nl * sizeof(double2))) != hipSuccess) break;
     if (want32 && (err = plan_alloc(P, &P.Lam[1], nl * sizeof(float2))) != hipSuccess) break;
     {
       const int bx = (int)std::min<size_t>(((size_t)p * p + 255) / 256, 64);
       hipLaunchKernelGGL(lambda_kernel, dim3(bx, P.B), dim3(256), P2 * sizeof(double2), s, Og, P2, p, P.B, d_ptr,
-                         d_coef, d_oidx, d_sig, d_nof, 1.0 / P.B, (double2*)P.Lam[0], (float2*)P.Lam[1]);
+                         d_coef, d_oidx, d_sig, d_nof, 1.0 / P.B, ldp, (double2*)P.Lam[0], (float2*)P.Lam[1]);
       if ((err = hipGetLastError()) != hipSuccess) break;
     }
     // host vectors (T) must outlive the async copies
@@ -914,8 +920,9 @@ extern "C" fmbem_status fmbem_plan_export(fmbem_plan plan, int32_t what, void* h
         std::memset(host, 0, cnt * sizeof(double2));
         break;
       }
-      tmp.resize(cnt);
-      st = to_status(hipMemcpy(tmp.data(), P.Lam[0], cnt * sizeof(double2), hipMemcpyDeviceToHost));
+      const size_t ldp = (size_t)lambda_ld(p);
+      tmp.resize((size_t)P.B * p * ldp);
+      st = to_status(hipMemcpy(tmp.data(), P.Lam[0], tmp.size() * sizeof(double2), hipMemcpyDeviceToHost));
       if (st != FMBEM_OK) break;
       double2* h = reinterpret_cast<double2*>(host);
       std::vector<int> nof(p);
@@ -925,7 +932,7 @@ extern "C" fmbem_status fmbem_plan_export(fmbem_plan plan, int32_t what, void* h
         for (int j = 0; j < p; ++j)
           for (int i = 0; i < p; ++i) {
             const double f = P.B / (std::pow(P.scale, nof[i]) * std::pow(P.scale, nof[j]));
-            const double2 v = tmp[(size_t)b * pp + (size_t)j * p + i];
+            const double2 v = tmp[((size_t)b * p + j) * ldp + i];
             h[(size_t)b * pp + (size_t)i * p + j] = make_double2(v.x * f, v.y * f);
           }
       break;
