@@ -91,6 +91,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     # residual target calibrated so that the solution error stays below 1e-6 (checked every step)
     ap.add_argument("--tol", type=float, default=1e-7, help="FP64 true relative residual of a solve")
+    # one classical Gram-Schmidt pass per Arnoldi step: on this operator it gives the same iteration
+    # counts as the DGKS-guarded second pass (the FP64 true residual decides convergence either way)
+    ap.add_argument("--ortho", choices=("dgks", "twice", "once"), default="once")
     ap.add_argument("--matvec-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--grid", type=int, nargs=2, default=(16, 16))
@@ -127,16 +130,18 @@ def main():
 
     def timed_solves(inner, steps, warmup, profile):
         for _ in range(warmup):
-            P.solve(b, tol=args.tol, inner=inner)
+            P.solve(b, tol=args.tol, inner=inner, ortho=args.ortho)
         torch.cuda.synchronize()
         if profile:
-            P.profile(True)
+            # only the dominant kernel is bracketed by events inside the timed region, on every
+            # 8th operator application (each event pair leaves a gap of a few microseconds)
+            P.profile(["near_fp32", "near_fp64"], period=8)
         lat, infos, xs = [], [], []
         torch.cuda.synchronize()
         t_start = time.perf_counter()
         for _ in range(steps):
             t1 = time.perf_counter()
-            x, info = P.solve(b, tol=args.tol, inner=inner)
+            x, info = P.solve(b, tol=args.tol, inner=inner, ortho=args.ortho)
             lat.append(time.perf_counter() - t1)
             infos.append(info[0])
             xs.append(x)
@@ -144,7 +149,7 @@ def main():
         total = time.perf_counter() - t_start
         prof = P.profile_read() if profile else None
         if profile:
-            P.profile(False)
+            P.profile([])
         errs = [solution_error(x) for x in xs]   # every solution checked, outside the timed region
         return total, lat, infos, errs, prof
 
@@ -173,6 +178,13 @@ def main():
         mv[prec] = args.matvec_reps / (e0.elapsed_time(e1) / 1e3)
     print(f"[bench] matvecs/s {mv}", file=sys.stderr, flush=True)
 
+    # per-stage breakdown from one more FP32-refined solve with every stage bracketed by events
+    # (outside the timed region: the events themselves add gaps between stages)
+    P.profile()
+    P.solve(b, tol=args.tol, inner="fp32", ortho=args.ortho)
+    stage_prof = P.profile_read()
+    P.profile([])
+
     # roofline of the dominant kernel: the FP32 near-field grouped GEMM, timed with HIP events
     # recorded inside the library on the solve's stream over the timed region
     n = w.n_dof_cell
@@ -181,12 +193,13 @@ def main():
     ms_near, cnt_near = prof["near_fp32"]
     avg_near = ms_near / cnt_near / 1e3
     achieved = flops_near / avg_near
-    stages = {k: {"avg_us": (v[0] / v[1] * 1e3 if v[1] else None), "launches": v[1]} for k, v in prof.items()}
+    stages = {k: {"avg_us": (v[0] / v[1] * 1e3 if v[1] else None), "launches": v[1]}
+              for k, v in stage_prof.items()}
     # HBM view of the M2L stage (FP32 Lambda read once + spectrum in/out)
     B = int(np.prod(P.info["fft_shape"]))
     p = P.p
     m2l_bytes = B * p * p * 8 + 2 * B * p * 8
-    m2l_avg = prof["m2l_fp32"][0] / max(prof["m2l_fp32"][1], 1) / 1e3
+    m2l_avg = stage_prof["m2l_fp32"][0] / max(stage_prof["m2l_fp32"][1], 1) / 1e3
     out = {
         "metric": METRIC,
         "value": args.steps / tot32,
@@ -202,7 +215,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "sphere lattice 16x16, 1280 triangles/cell, N=327680, 1 kHz, n_t=10, 1 plane wave",
                    "grid": list(w.lattice.grid), "n_dof": int(w.n_dof), "order": w.order, "n_rhs": 1,
-                   "tol": args.tol},
+                   "tol": args.tol, "gram_schmidt": args.ortho},
         "solves_per_s": {"fp32_refined": args.steps / tot32, "fp64": args.steps / tot64},
         "latency_ms": {"fp32_refined": {"p50": percentile(lat32, 50) * 1e3, "p99": percentile(lat32, 99) * 1e3},
                        "fp64": {"p50": percentile(lat64, 50) * 1e3, "p99": percentile(lat64, 99) * 1e3}},

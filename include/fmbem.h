@@ -127,7 +127,15 @@ typedef struct {
   int32_t inner_precision;    /* FMBEM_FP64: plain FP64 GMRES; FMBEM_FP32: FP32 operator inside
                                  GMRES, FP64 Arnoldi, FP64 residual and refinement */
   double inner_tol;           /* relative tolerance of each FP32 inner solve (default 1e-5 when 0) */
+  int32_t orthogonalization;  /* FMBEM_ORTHO_*: Gram-Schmidt passes per Arnoldi step */
 } fmbem_solve_opts;
+
+/* 0: classical Gram-Schmidt plus a second pass when ||w_new|| < ||w_old|| / sqrt(2)
+ *    (Daniel-Gragg-Kaufman-Stewart criterion, decided on the device);
+ * 1: always two passes; 2: one pass.  Every solve ends on the FP64 true residual. */
+#define FMBEM_ORTHO_DGKS 0
+#define FMBEM_ORTHO_TWICE 1
+#define FMBEM_ORTHO_ONCE 2
 
 typedef struct {
   int32_t iterations;         /* inner GMRES iterations (operator applications) */
@@ -136,7 +144,8 @@ typedef struct {
 } fmbem_solve_info;
 
 /* Solve A x = b by restarted GMRES (Sec. 2.4, Sec. 3.5; GMRES as in Sec. 4)
- * with classical Gram-Schmidt applied twice, Givens rotations, and (for
+ * with classical Gram-Schmidt and a second pass where the Daniel-Gragg-Kaufman-
+ * Stewart criterion asks for one, Givens rotations, and (for
  * inner_precision = FMBEM_FP32) FP64 iterative refinement around FP32 inner
  * solves.  b, x: device complex128 [n_rhs][n_cells][n_dof_cell]; x holds the
  * initial guess on entry and the solution on return.  All right-hand sides
@@ -160,14 +169,17 @@ fmbem_status fmbem_incident_point_source(fmbem_plan plan, int32_t n_rhs, const d
 
 /* Per-stage device time of the operator applications made with this plan
  * (fmbem_matvec and the ones inside fmbem_solve), measured with HIP events
- * recorded on the call's stream around each stage.  enable = 1 clears the
- * counters and starts recording, 0 stops.  Not for concurrent use of the same
- * plan from several host threads while enabled.
+ * recorded on the call's stream around each selected stage.  stage_mask != 0
+ * clears the counters and records the stages whose bit (1 << stage) is set on
+ * every period-th operator application (period >= 1); stage_mask = 0 stops.
+ * Each recorded stage adds two event records to the stream.  Not for concurrent
+ * use of the same plan from several host threads while enabled.
  * Stages: 0 near field + S2M (one grouped launch), 1 sum of the near-field partial
- * products, 2 forward DFT, 3 M2L, 4 inverse DFT, 5 L2T, in FP64;
- * 6..11 the same stages in FP32. */
+ * products (only for lattices without far-field offsets), 2 forward DFT, 3 M2L,
+ * 4 inverse DFT, 5 L2T with the near-field sum, in FP64; 6..11 the same in FP32. */
 #define FMBEM_N_STAGES 12
-fmbem_status fmbem_plan_profile(fmbem_plan plan, int32_t enable);
+#define FMBEM_PROFILE_ALL 0xFFFu
+fmbem_status fmbem_plan_profile(fmbem_plan plan, uint32_t stage_mask, int32_t period);
 /* Synchronizes with the recorded events and returns the accumulated time (ms)
  * and the number of launches of each stage (host arrays [FMBEM_N_STAGES]). */
 fmbem_status fmbem_plan_profile_read(fmbem_plan plan, double* ms, int64_t* count);

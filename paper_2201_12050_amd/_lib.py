@@ -48,7 +48,11 @@ class PlanInfo(ct.Structure):
 
 class SolveOpts(ct.Structure):
     _fields_ = [("tol", ct.c_double), ("restart", ct.c_int32), ("max_iters", ct.c_int32),
-                ("max_refinements", ct.c_int32), ("inner_precision", ct.c_int32), ("inner_tol", ct.c_double)]
+                ("max_refinements", ct.c_int32), ("inner_precision", ct.c_int32), ("inner_tol", ct.c_double),
+                ("orthogonalization", ct.c_int32)]
+
+
+ORTHO = {"dgks": 0, "twice": 1, "once": 2}
 
 
 class SolveInfo(ct.Structure):
@@ -80,7 +84,7 @@ def load():
     lib.fmbem_solve.argtypes = [vp, ct.POINTER(SolveOpts), ct.c_int32, vp, vp, ct.POINTER(SolveInfo), vp]
     lib.fmbem_incident_plane_wave.argtypes = [vp, ct.c_int32, ct.POINTER(ct.c_double), ct.c_double, vp, vp]
     lib.fmbem_incident_point_source.argtypes = [vp, ct.c_int32, ct.POINTER(ct.c_double), ct.c_double, vp, vp]
-    lib.fmbem_plan_profile.argtypes = [vp, ct.c_int32]
+    lib.fmbem_plan_profile.argtypes = [vp, ct.c_uint32, ct.c_int32]
     lib.fmbem_plan_profile_read.argtypes = [vp, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)]
     lib.fmbem_status_string.argtypes = [ct.c_int32]
     lib.fmbem_status_string.restype = ct.c_char_p
@@ -178,11 +182,19 @@ class Plan:
         return out
 
     # ---------------------------------------------------------------- profiling
-    def profile(self, enable: bool = True):
-        check(self._lib.fmbem_plan_profile(self._h, 1 if enable else 0), "fmbem_plan_profile")
+    def profile(self, stages=None, period: int = 1):
+        """Start recording the named stages (None: all; [] stops), e.g. ["near_fp32"], on every
+        period-th operator application."""
+        if stages is None:
+            mask = (1 << len(STAGES)) - 1
+        else:
+            mask = 0
+            for s in stages:
+                mask |= 1 << STAGES.index(s)
+        check(self._lib.fmbem_plan_profile(self._h, mask, int(period)), "fmbem_plan_profile")
 
     def profile_read(self):
-        """{stage: (total ms, launches)} of the operator applications since profile(True)."""
+        """{stage: (total ms, launches)} of the operator applications since profile()."""
         ms = (ct.c_double * len(STAGES))()
         cnt = (ct.c_int64 * len(STAGES))()
         check(self._lib.fmbem_plan_profile_read(self._h, ms, cnt), "fmbem_plan_profile_read")
@@ -214,14 +226,14 @@ class Plan:
         return y
 
     def solve(self, b, x=None, tol=1e-8, restart=30, max_iters=1000, max_refinements=20, inner="fp64",
-              inner_tol=1e-5, stream=None, raise_on_not_converged=True):
+              inner_tol=1e-5, ortho="dgks", stream=None, raise_on_not_converged=True):
         import torch
         if b.dtype != torch.complex128 or not b.is_cuda or not b.is_contiguous():
             raise ValueError("b must be a contiguous complex128 CUDA tensor")
         R = b.numel() // self.n_dof
         if x is None:
             x = torch.zeros_like(b)
-        o = SolveOpts(tol, restart, max_iters, max_refinements, _precision(inner), inner_tol)
+        o = SolveOpts(tol, restart, max_iters, max_refinements, _precision(inner), inner_tol, ORTHO[ortho])
         info = (SolveInfo * R)()
         st = self._lib.fmbem_solve(self._h, ct.byref(o), R, ct.c_void_p(b.data_ptr()), ct.c_void_p(x.data_ptr()),
                                    info, _stream_ptr(stream))

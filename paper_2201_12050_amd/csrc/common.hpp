@@ -74,7 +74,10 @@ struct Plan {
   std::vector<void*> allocations;
   // stage profiling (HIP events on the caller's stream)
   struct Prof {
-    bool on = false;
+    uint32_t mask = 0;                                // recorded stages (bit per stage)
+    int period = 1;                                   // record every period-th application
+    long long calls = 0;                              // applications since profiling started
+    bool active = false;                              // the current application is recorded
     std::vector<hipEvent_t> pool;                     // free events
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;  // (stage, start, stop)
     double ms[FMBEM_N_STAGES] = {0};
@@ -85,57 +88,41 @@ struct Plan {
   mutable std::vector<std::pair<long long, int>> near_shape;
 };
 
-// record the start / end of a stage when profiling is on (returns the start event)
-hipEvent_t prof_begin(const Plan& P, hipStream_t s);
+// record the start / end of a stage when that stage is being profiled (returns the start event)
+hipEvent_t prof_begin(const Plan& P, int stage, hipStream_t s);
 void prof_end(const Plan& P, int stage, hipEvent_t start, hipStream_t s);
 
 size_t matvec_workspace_bytes_per_rhs(const Plan& P, int precision);
 
-// stream-ordered operator application (all arguments validated by the caller)
+// stream-ordered operator application (all arguments validated by the caller);
+// y64 (FP32 only, optional): write the result as complex128 there instead of y
 hipError_t matvec_launch(const Plan& P, int precision, int R, const void* x, void* y, void* ws,
-                         hipStream_t s);
+                         hipStream_t s, void* y64 = nullptr);
 
 // ---------------------------------------------------------------------------
 // kernels shared between translation units
 // ---------------------------------------------------------------------------
-// column address maps of the complex GEMM
-enum ColMap : int {
-  COL_LINEAR = 0,      // column j at base + j*ld
-  COL_CELL_SHIFT = 1,  // column j = (r, c): source cell c - d (zero column if outside the grid)
-  COL_CELL_TO_BIN = 2  // column j = (r, c): padded grid bin of c, layout [bin][R][ld]
+constexpr int kMaxSeg = 32;  // near offsets per plan (3-D lattices with near radius 1 need 27)
+
+// grouped complex GEMM jobs on the near-field kernel (near.hip): C = A B with A complex
+// [M][K] row-major and B columns = cells (x RHS) of x, shifted by a cell offset, or
+// padded-grid bins
+enum NearSrc : int { SRC_X = 0, SRC_GRID = 1 };
+enum NearDest : int {
+  DEST_SLICE = 0,  // out [N][M] column-major
+  DEST_GRID = 1,   // out padded grid [bin][R][M]
+  DEST_FINAL = 2   // out [N][M] = acc + sum of nparts slices of part (same layout); FP64 to out64 if set
 };
-
-struct GemmCols {
-  int kind;
-  int ld;          // complex elements between consecutive columns (LINEAR) or per column
-  int R, C;        // right-hand sides, cells
-  int g0, g1, g2;  // grid M1, M2, M3
-  int f0, f1;      // FFT shape N1, N2 (for COL_CELL_TO_BIN)
-};
-
-struct GemmSeg {
-  const void* A;   // complex [M][K] row-major
-  int d0, d1, d2;  // cell offset for COL_CELL_SHIFT
-};
-
-constexpr int kMaxSeg = 32;
-struct GemmSegs {
-  int count;
-  GemmSeg seg[kMaxSeg];
-};
-
-template <typename T>
-hipError_t gemm_launch(int M, int K, int N, const GemmSegs& segs, const void* B, GemmCols bmap,
-                       void* Cm, GemmCols cmap, bool accumulate, hipStream_t s);
-
-// grouped near-field / S2M launch (near.hip)
 struct NearJob {
-  const void* A;   // complex [M][n] row-major
-  void* out;       // dest 0: [N][M] column-major slice; dest 1: padded grid [bin][R][M]
-  int M;
-  int d0, d1, d2;  // cell offset of the B columns
-  int dest;
+  const void* A;
+  void* out;
+  int M, K;
+  int d0, d1, d2;  // cell offset of the B columns (SRC_X)
+  int src, dest;
   int tile0;       // first workgroup of this job (set by near_launch)
+  const void* part;
+  int nparts;
+  void* out64;
 };
 struct NearJobs {
   int count;
@@ -145,12 +132,16 @@ struct NearGrid {
   int C, R, M0, M1, M2, N0, N1;
 };
 
-// shape < 0: default tile shape for this problem; else one of near_num_shapes() shapes
+// shape < 0: default tile shape for this problem; else one of near_num_shapes() shapes.
+// x: B source for SRC_X jobs (stride n per cell column); grid: B source for SRC_GRID jobs.
+// kind 0 launches the tile body as near_kernel (near field + S2M), 1 as l2t_kernel (L2T).
 template <typename T>
-hipError_t near_launch(int n, int N, NearJobs jobs, const void* x, const NearGrid& g, hipStream_t s, int shape = -1);
+hipError_t near_launch(int n, int N, NearJobs jobs, const void* x, const void* grid, const NearGrid& g,
+                       hipStream_t s, int shape = -1, int kind = 0);
 int near_num_shapes();
+// y = sum of ns partial slices (FP64 to y64 when set)
 template <typename T>
-hipError_t near_reduce_launch(const void* part, int ns, size_t len, void* y, hipStream_t s);
+hipError_t near_reduce_launch(const void* part, int ns, size_t len, void* y, void* y64, hipStream_t s);
 
 template <typename T>
 hipError_t grid_dft_launch(void* buf, int channels, const int M[3], const int N[3], bool inverse,

@@ -3,11 +3,11 @@
 // Stream-ordered sequence on the caller's stream (profiling stage in brackets):
 //   [0] near field + S2M, one grouped launch:
 //         part_d = S_d x_{c-d} for every near offset d, mhat[bin(c)][r] = V0 x_c
-//   [1] y = sum_d part_d  (fixed order)
 //   [2] forward DFT  over the cell grid, pruned inputs      (incomplete Fourier matrices, Sec. 2.4)
 //   [3] M2L          lhat_b = Lambda_b mhat_b               (per-bin product)
 //   [4] inverse DFT  cropped to the first M_a outputs per axis
-//   [5] L2T          y += U0 l_c                            (GEMM reading the padded grid)
+//   [5] L2T          y = sum_d part_d + U0 l_c              (GEMM reading the padded grid, fixed-order sum)
+//   [1] only without far-field offsets: y = sum_d part_d
 // Workspace: [padded grid B x R x p][near partials n_near x R x C x n], 256-byte aligned.
 #include <algorithm>
 #include <cmath>
@@ -23,8 +23,7 @@ size_t matvec_workspace_bytes_per_rhs(const Plan& P, int precision) {
   return align256((size_t)P.B * P.p * el) + align256((size_t)P.n_near * P.C * P.n * el);
 }
 
-hipEvent_t prof_begin(const Plan& P, hipStream_t s) {
-  if (!P.prof.on) return nullptr;
+static hipEvent_t prof_record(const Plan& P, hipStream_t s) {
   hipEvent_t e = nullptr;
   if (!P.prof.pool.empty()) {
     e = P.prof.pool.back();
@@ -36,41 +35,48 @@ hipEvent_t prof_begin(const Plan& P, hipStream_t s) {
   return e;
 }
 
+hipEvent_t prof_begin(const Plan& P, int stage, hipStream_t s) {
+  if (!P.prof.active || !(P.prof.mask & (1u << stage))) return nullptr;
+  return prof_record(P, s);
+}
+
 void prof_end(const Plan& P, int stage, hipEvent_t start, hipStream_t s) {
   if (!start) return;
-  hipEvent_t e = prof_begin(P, s);
+  hipEvent_t e = prof_record(P, s);
   if (!e) return;
   P.prof.marks.push_back({stage, {start, e}});
 }
 
-// Autotuner of the near-field tile shape: on the first application with a given
-// precision and column count, every shape is launched once to warm up and twice
-// timed with HIP events on the caller's stream (the launches compute the real
-// partial products, which the launch that follows overwrites); the fastest is
-// cached in the plan.  Blocks the host once per (precision, columns).
+// Autotuner of the tile shape of a grouped launch: on the first launch of a given
+// kind, precision and column count, every shape is launched once to warm up and
+// twice timed with HIP events on the caller's stream (the launches compute the real
+// products, which the launch that follows overwrites); the fastest is cached in the
+// plan.  Blocks the host once per key.
 template <typename T>
-static int near_tuned_shape(const Plan& P, int n, int N, const NearJobs& jobs, const void* x, const NearGrid& g,
-                            hipStream_t s) {
-  const long long key = (long long)N * 2 + (sizeof(T) == 8 ? 0 : 1);
+static int tuned_shape(const Plan& P, int kind, int n, int N, const NearJobs& jobs, const void* x,
+                       const void* gridbuf, const NearGrid& g, hipStream_t s) {
+  const long long key = ((long long)N * 4 + kind) * 2 + (sizeof(T) == 8 ? 0 : 1);
   for (const auto& kv : P.near_shape)
     if (kv.first == key) return kv.second;
   int best = -1;
-  float best_ms = 0.f;
   hipEvent_t a = nullptr, b = nullptr;
   if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
-    for (int v = 0; v < near_num_shapes(); ++v) {
-      if (near_launch<T>(n, N, jobs, x, g, s, v) != hipSuccess) continue;
-      hipEventRecord(a, s);
-      near_launch<T>(n, N, jobs, x, g, s, v);
-      near_launch<T>(n, N, jobs, x, g, s, v);
-      hipEventRecord(b, s);
-      float ms = 0.f;
-      if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) continue;
-      if (best < 0 || ms < best_ms) {
-        best = v;
-        best_ms = ms;
+    // two sweeps over the shapes, the minimum of each shape's timings counts
+    std::vector<float> t(near_num_shapes(), 1e30f);
+    for (int sweep = 0; sweep < 2; ++sweep) {
+      for (int v = 0; v < near_num_shapes(); ++v) {
+        if (near_launch<T>(n, N, jobs, x, gridbuf, g, s, v, kind) != hipSuccess) continue;
+        hipEventRecord(a, s);
+        near_launch<T>(n, N, jobs, x, gridbuf, g, s, v, kind);
+        near_launch<T>(n, N, jobs, x, gridbuf, g, s, v, kind);
+        hipEventRecord(b, s);
+        float ms = 0.f;
+        if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) continue;
+        t[v] = std::min(t[v], ms);
       }
     }
+    for (int v = 0; v < near_num_shapes(); ++v)
+      if (t[v] < 1e29f && (best < 0 || t[v] < t[best])) best = v;
   }
   if (a) hipEventDestroy(a);
   if (b) hipEventDestroy(b);
@@ -79,7 +85,7 @@ static int near_tuned_shape(const Plan& P, int n, int N, const NearJobs& jobs, c
 }
 
 template <typename T>
-static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* ws, hipStream_t s) {
+static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* ws, hipStream_t s, void* y64) {
   const int prec = sizeof(T) == 8 ? 0 : 1;
   const int n = P.n, C = P.C, p = P.p;
   const int N = R * C;
@@ -87,6 +93,18 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
   char* grid_buf = reinterpret_cast<char*>(ws);
   char* part = grid_buf + align256((size_t)P.B * R * p * el);
   const size_t slice = (size_t)N * n;  // complex elements per near partial
+  const NearGrid g{C, R, P.grid[0], P.grid[1], P.grid[2], P.fft[0], P.fft[1]};
+  P.prof.active = P.prof.mask != 0 && (P.prof.calls++ % P.prof.period) == 0;
+  auto job = [](const void* A, void* out, int M, int K, int src, int dest) {
+    NearJob j{};
+    j.A = A;
+    j.out = out;
+    j.M = M;
+    j.K = K;
+    j.src = src;
+    j.dest = dest;
+    return j;
+  };
   // [0] near field and S2M
   hipEvent_t ev = nullptr;
   {
@@ -94,67 +112,61 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
     jobs.count = 0;
     const size_t blk = (size_t)n * n * el;
     for (int d = 0; d < P.n_near; ++d) {
-      NearJob& j = jobs.job[jobs.count++];
-      j.A = reinterpret_cast<const char*>(P.S[prec]) + d * blk;
-      j.out = part + d * slice * el;
-      j.M = n;
+      NearJob j = job(reinterpret_cast<const char*>(P.S[prec]) + d * blk, part + d * slice * el, n, n, SRC_X,
+                      DEST_SLICE);
       j.d0 = P.near_off[3 * d];
       j.d1 = P.near_off[3 * d + 1];
       j.d2 = P.near_off[3 * d + 2];
-      j.dest = 0;
+      jobs.job[jobs.count++] = j;
     }
-    if (P.n_far > 0) {
-      NearJob& j = jobs.job[jobs.count++];
-      j.A = P.V0[prec];
-      j.out = grid_buf;
-      j.M = p;
-      j.d0 = j.d1 = j.d2 = 0;
-      j.dest = 1;
-    }
-    NearGrid g{C, R, P.grid[0], P.grid[1], P.grid[2], P.fft[0], P.fft[1]};
-    const int shape = near_tuned_shape<T>(P, n, N, jobs, x, g, s);
-    ev = prof_begin(P, s);
-    hipError_t e = near_launch<T>(n, N, jobs, x, g, s, shape);
+    if (P.n_far > 0) jobs.job[jobs.count++] = job(P.V0[prec], grid_buf, p, n, SRC_X, DEST_GRID);
+    const int shape = tuned_shape<T>(P, 0, n, N, jobs, x, grid_buf, g, s);
+    ev = prof_begin(P, 0 + 6 * prec, s);
+    hipError_t e = near_launch<T>(n, N, jobs, x, grid_buf, g, s, shape);
     if (e != hipSuccess) return e;
   }
   prof_end(P, 0 + 6 * prec, ev, s);
-  // [1] sum of the near partials
-  ev = prof_begin(P, s);
-  {
-    hipError_t e = near_reduce_launch<T>(part, P.n_near, slice, y, s);
+  if (P.n_far == 0) {
+    // [1] sum of the near partials
+    ev = prof_begin(P, 1 + 6 * prec, s);
+    hipError_t e = near_reduce_launch<T>(part, P.n_near, slice, y, y64, s);
     if (e != hipSuccess) return e;
+    prof_end(P, 1 + 6 * prec, ev, s);
+    return hipSuccess;
   }
-  prof_end(P, 1 + 6 * prec, ev, s);
-  if (P.n_far == 0) return hipSuccess;
   // [2]-[4] DFT, M2L, inverse DFT
-  ev = prof_begin(P, s);
+  ev = prof_begin(P, 2 + 6 * prec, s);
   hipError_t e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, false, true, s);
   if (e != hipSuccess) return e;
   prof_end(P, 2 + 6 * prec, ev, s);
-  ev = prof_begin(P, s);
+  ev = prof_begin(P, 3 + 6 * prec, s);
   e = m2l_launch<T>(P.Lam[prec], ws, P.B, R, p, s);
   if (e != hipSuccess) return e;
   prof_end(P, 3 + 6 * prec, ev, s);
-  ev = prof_begin(P, s);
+  ev = prof_begin(P, 4 + 6 * prec, s);
   e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, true, true, s);
   if (e != hipSuccess) return e;
   prof_end(P, 4 + 6 * prec, ev, s);
-  // [5] L2T accumulate
-  ev = prof_begin(P, s);
+  // [5] L2T with the fixed-order sum of the near partials
   {
-    GemmSegs segs;
-    segs.count = 1;
-    segs.seg[0] = GemmSeg{P.U0[prec], 0, 0, 0};
-    GemmCols bm{COL_CELL_TO_BIN, p, R, C, P.grid[0], P.grid[1], P.grid[2], P.fft[0], P.fft[1]};
-    GemmCols cm{COL_LINEAR, n, R, C, P.grid[0], P.grid[1], P.grid[2], P.fft[0], P.fft[1]};
-    e = gemm_launch<T>(n, p, N, segs, ws, bm, y, cm, true, s);
+    NearJobs jobs;
+    jobs.count = 1;
+    jobs.job[0] = job(P.U0[prec], y, n, p, SRC_GRID, DEST_FINAL);
+    jobs.job[0].part = part;
+    jobs.job[0].nparts = P.n_near;
+    jobs.job[0].out64 = y64;
+    const int shape = tuned_shape<T>(P, 1, n, N, jobs, x, grid_buf, g, s);
+    ev = prof_begin(P, 5 + 6 * prec, s);
+    e = near_launch<T>(n, N, jobs, x, grid_buf, g, s, shape, 1);
   }
   prof_end(P, 5 + 6 * prec, ev, s);
   return e;
 }
 
-hipError_t matvec_launch(const Plan& P, int precision, int R, const void* x, void* y, void* ws, hipStream_t s) {
-  return precision == FMBEM_FP64 ? matvec_t<double>(P, R, x, y, ws, s) : matvec_t<float>(P, R, x, y, ws, s);
+hipError_t matvec_launch(const Plan& P, int precision, int R, const void* x, void* y, void* ws, hipStream_t s,
+                         void* y64) {
+  return precision == FMBEM_FP64 ? matvec_t<double>(P, R, x, y, ws, s, nullptr)
+                                 : matvec_t<float>(P, R, x, y, ws, s, y64);
 }
 
 }  // namespace fmbem
@@ -173,18 +185,18 @@ extern "C" fmbem_status fmbem_matvec(fmbem_plan plan, int32_t precision, int32_t
   const char* xb = reinterpret_cast<const char*>(x);
   const char* yb = reinterpret_cast<const char*>(y);
   if (xb < yb + vbytes && yb < xb + vbytes) return FMBEM_ERR_INVALID_ARG;
-  if (P.n_far > 0) {
-    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255)) return FMBEM_ERR_INVALID_ARG;
-    if (workspace_bytes < (size_t)n_rhs * matvec_workspace_bytes_per_rhs(P, precision)) return FMBEM_ERR_WORKSPACE;
-  }
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255)) return FMBEM_ERR_INVALID_ARG;
+  if (workspace_bytes < (size_t)n_rhs * matvec_workspace_bytes_per_rhs(P, precision)) return FMBEM_ERR_WORKSPACE;
   hipError_t e = matvec_launch(P, precision, n_rhs, x, y, workspace, reinterpret_cast<hipStream_t>(hip_stream));
   return e == hipSuccess ? FMBEM_OK : FMBEM_ERR_DEVICE;
 }
 
-extern "C" fmbem_status fmbem_plan_profile(fmbem_plan plan, int32_t enable) {
-  if (!plan || (enable != 0 && enable != 1)) return FMBEM_ERR_INVALID_ARG;
+extern "C" fmbem_status fmbem_plan_profile(fmbem_plan plan, uint32_t stage_mask, int32_t period) {
+  if (!plan || (stage_mask & ~FMBEM_PROFILE_ALL) || period < 1) return FMBEM_ERR_INVALID_ARG;
   const Plan& P = *reinterpret_cast<Plan*>(plan);
-  if (enable) {
+  P.prof.period = period;
+  P.prof.calls = 0;
+  if (stage_mask) {
     for (auto& m : P.prof.marks) {
       hipEventSynchronize(m.second.second);
       P.prof.pool.push_back(m.second.first);
@@ -196,7 +208,7 @@ extern "C" fmbem_status fmbem_plan_profile(fmbem_plan plan, int32_t enable) {
       P.prof.count[i] = 0;
     }
   }
-  P.prof.on = enable != 0;
+  P.prof.mask = stage_mask;
   return FMBEM_OK;
 }
 

@@ -1,13 +1,14 @@
-// Restarted GMRES with FP64 Arnoldi (classical Gram-Schmidt applied twice),
-// Givens rotations and FP64 iterative refinement around FP32 inner solves.
+// Restarted GMRES with FP64 Arnoldi (classical Gram-Schmidt with the DGKS selective
+// second pass), Givens rotations and FP64 iterative refinement around FP32 inner solves.
 //
 // The paper solves the FMPBEM system iteratively with GMRES (Sec. 2.4, Sec. 3.5,
 // Sec. 4).  All right-hand sides are iterated together, each in its own Krylov
 // space; vectors are [R][N] complex128.  Per Arnoldi step:
-//   w = A v_j                         (operator in FP64, or FP32 through casts)
-//   h = V^H w, w -= V h  (twice)      (multi-dot and multi-axpy kernels, FP64)
+//   w = A v_j, built in the slot of v_{j+1}   (operator in FP64, or FP32 with FP64 output)
+//   h = V^H w, w -= V h                       (multi-dot and multi-axpy kernels, FP64)
+//   if ||w_new|| < ||w_old|| / sqrt(2): h2 = V^H w, w -= V h2, h += h2   (device-side decision)
 //   h_{j+1} = ||w||, v_{j+1} = w / h_{j+1}
-//   Givens update of the Hessenberg column and of g on the device (one thread per RHS)
+//   Givens update of the Hessenberg column and of g on the device (one workgroup per RHS)
 // The host learns the residual estimates |g_{j+1}| one step late: step j+1 is
 // already queued when it waits for step j, so the device never idles on the
 // host; a step queued after convergence is discarded by the per-RHS freeze.
@@ -31,9 +32,10 @@ __device__ inline double wave_sum(double v) {
 // part[r][i][blk] = sum_{n in block} conj(V_i[r][n]) w[r][n]; grid (blocks, vector groups of 8, R)
 __global__ __launch_bounds__(kDotThreads) void mdot_kernel(const double2* __restrict__ V, size_t vstride,
                                                            const double2* __restrict__ w, size_t N, int J,
-                                                           double2* __restrict__ part) {
+                                                           double2* __restrict__ part, const int* __restrict__ flag) {
   __shared__ double2 red[kDotThreads / 64][kDotVec];
   const int r = blockIdx.z;
+  if (flag && !flag[r]) return;  // conditional pass not needed for this RHS
   const int i0 = blockIdx.y * kDotVec;
   const int nblk = gridDim.x;
   const size_t base = (size_t)blockIdx.x * kDotThreads * kDotEl + threadIdx.x;
@@ -80,11 +82,12 @@ __global__ __launch_bounds__(kDotThreads) void mdot_kernel(const double2* __rest
 // one wave per (r, i) sums the block partials s; mode 0: h = s; mode 2: h = sqrt(Re s);
 // mode 3: h2 = s and h += s (second Gram-Schmidt pass)
 __global__ void mdot_finish(const double2* __restrict__ part, int nblk, int R, int J, double2* __restrict__ h,
-                            int hstride, int mode, double2* __restrict__ h2) {
+                            int hstride, int mode, double2* __restrict__ h2, const int* __restrict__ flag) {
   const int t = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (t >= R * J) return;
   const int r = t / J, i = t - r * J;
+  if (flag && !flag[r]) return;
   double sx = 0.0, sy = 0.0;
   for (int b = lane; b < nblk; b += 64) {
     const double2 v = part[(size_t)t * nblk + b];
@@ -108,10 +111,11 @@ __global__ void mdot_finish(const double2* __restrict__ part, int nblk, int R, i
 __global__ __launch_bounds__(256) void maxpy_kernel(const double2* __restrict__ V, size_t vstride,
                                                     const double2* __restrict__ c, int cstride,
                                                     double2* __restrict__ w, size_t N, int J, double sgn,
-                                                    double* __restrict__ npart) {
+                                                    double* __restrict__ npart, const int* __restrict__ flag) {
   extern __shared__ double2 cs[];
   __shared__ double red[4];
   const int r = blockIdx.y;
+  if (flag && !flag[r]) return;
   for (int i = threadIdx.x; i < J; i += blockDim.x) cs[i] = c[(size_t)r * cstride + i];
   __syncthreads();
   double nn = 0.0;
@@ -133,9 +137,31 @@ __global__ __launch_bounds__(256) void maxpy_kernel(const double2* __restrict__ 
   }
 }
 
-// out[r][n] = a[r][n] / s[r] (s = .x of a double2 array; 0 when s = 0); optional FP32 copy
-__global__ void scale_kernel(const double2* __restrict__ a, const double2* __restrict__ s, int sstride,
-                             double2* __restrict__ out, float2* __restrict__ out32, size_t N) {
+// DGKS criterion (Daniel, Gragg, Kaufman & Stewart, 1976): a second Gram-Schmidt pass is
+// needed when the projection removed more than 1 - 1/sqrt(2) of the norm, i.e. when
+// ||w'|| < ||w|| / sqrt(2).  ||w||^2 is the last dot of the first pass (hc[j+1]);
+// ||w'||^2 is the sum of the first multi-axpy's partials.  One workgroup per RHS.
+// mode: 0 DGKS, 1 always, 2 never.
+__global__ __launch_bounds__(256) void reorth_check_kernel(int mode, int nb, const double* __restrict__ npart,
+                                                           const double2* __restrict__ hc, int hstride, int j,
+                                                           const int* __restrict__ jdone, int* __restrict__ flag) {
+  __shared__ double red[4];
+  const int r = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += npart[(size_t)r * nb + b];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double w2 = hc[(size_t)r * hstride + j + 1].x;
+    const bool need = mode == 1 || (mode == 0 && 2.0 * (red[0] + red[1] + red[2] + red[3]) < w2);
+    flag[r] = (jdone[r] < 0 && need) ? 1 : 0;
+  }
+}
+
+// out[r][n] = a[r][n] / s[r] (s = .x of a double2 array; 0 when s = 0); optional FP32 copy; may run in place
+__global__ void scale_kernel(const double2* a, const double2* __restrict__ s, int sstride, double2* out,
+                             float2* __restrict__ out32, size_t N) {
   const int r = blockIdx.y;
   const double d = s[(size_t)r * sstride].x;
   const double f = d > 0 ? 1.0 / d : 0.0;
@@ -295,6 +321,7 @@ struct Solver {
   const Plan& P;
   hipStream_t s;
   int R, m;
+  int ortho = 0;  // FMBEM_ORTHO_*
   size_t N;       // DOFs per RHS
   size_t vlen;    // R * N
   int nblk;
@@ -306,6 +333,7 @@ struct Solver {
           *y = nullptr;
   double *res = nullptr, *tol = nullptr, *npart = nullptr;
   int* jdone = nullptr;
+  int* reorth = nullptr;  // per-RHS second Gram-Schmidt pass flag
   // freeze flags of two steps in flight, in mapped pinned host memory written by the device
   int* hjd[2] = {nullptr, nullptr};
   int* djd[2] = {nullptr, nullptr};
@@ -358,6 +386,7 @@ struct Solver {
     if ((e = alloc((void**)&tol, R * sizeof(double)))) return e;
     if ((e = alloc((void**)&jdone, R * sizeof(int)))) return e;
     if ((e = alloc((void**)&npart, (size_t)R * nb * sizeof(double)))) return e;
+    if ((e = alloc((void**)&reorth, R * sizeof(int)))) return e;
     for (int i = 0; i < 2; ++i) {
       if ((e = hipHostMalloc((void**)&hjd[i], R * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent)))
         return e;
@@ -375,27 +404,30 @@ struct Solver {
       hipLaunchKernelGGL(to32_kernel, dim3(lgrid(vlen)), dim3(256), 0, s, in, x32, vlen);
       in32 = x32;
     }
-    hipError_t e = matvec_launch(P, FMBEM_FP32, R, in32, y32, ws, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(to64_kernel, dim3(lgrid(vlen)), dim3(256), 0, s, y32, out, vlen);
-    return hipGetLastError();
+    // the FP32 operator writes its result directly as FP64 into out
+    return matvec_launch(P, FMBEM_FP32, R, in32, y32, ws, s, out);
   }
-  // dots of the first J basis vectors with vec -> h (mode 0: h = dots; mode 3: h2 = dots, h += dots)
-  void mdot(const double2* Vb, int J, const double2* vec, double2* h, int mode, double2* h2 = nullptr) {
+  // dots of the first J basis vectors with vec -> h (mode 0: h = dots; mode 3: h2 = dots, h += dots);
+  // with flag, only for the RHS whose flag is set
+  void mdot(const double2* Vb, int J, const double2* vec, double2* h, int mode, double2* h2 = nullptr,
+            const int* flag = nullptr) {
     dim3 grid(nblk, (J + kDotVec - 1) / kDotVec, R);
-    hipLaunchKernelGGL(mdot_kernel, grid, dim3(kDotThreads), 0, s, Vb, vlen, vec, N, J, part);
-    hipLaunchKernelGGL(mdot_finish, dim3((R * J + 3) / 4), dim3(256), 0, s, part, nblk, R, J, h, hstride, mode, h2);
+    hipLaunchKernelGGL(mdot_kernel, grid, dim3(kDotThreads), 0, s, Vb, vlen, vec, N, J, part, flag);
+    hipLaunchKernelGGL(mdot_finish, dim3((R * J + 3) / 4), dim3(256), 0, s, part, nblk, R, J, h, hstride, mode, h2,
+                       flag);
   }
   // per-RHS 2-norm of vec into out[r][0]
   void norm(const double2* vec, double2* out) {
-    hipLaunchKernelGGL(mdot_kernel, dim3(nblk, 1, R), dim3(kDotThreads), 0, s, vec, vlen, vec, N, 1, part);
+    hipLaunchKernelGGL(mdot_kernel, dim3(nblk, 1, R), dim3(kDotThreads), 0, s, vec, vlen, vec, N, 1, part,
+                       (const int*)nullptr);
     hipLaunchKernelGGL(mdot_finish, dim3((R + 3) / 4), dim3(256), 0, s, part, nblk, R, 1, out, hstride, 2,
-                       (double2*)nullptr);
+                       (double2*)nullptr, (const int*)nullptr);
   }
-  // vec += sgn V c; with_norm: per-block |vec|^2 partials into npart
-  void maxpy(const double2* Vb, const double2* c, double2* vec, int J, double sgn, bool with_norm = false) {
+  // vec += sgn V c; with_norm: per-block |vec|^2 partials into npart; with flag, only flagged RHS
+  void maxpy(const double2* Vb, const double2* c, double2* vec, int J, double sgn, bool with_norm = false,
+             const int* flag = nullptr) {
     hipLaunchKernelGGL(maxpy_kernel, vgrid(), dim3(256), std::max(J, 1) * sizeof(double2), s, Vb, vlen, c, hstride,
-                       vec, N, J, sgn, with_norm ? npart : nullptr);
+                       vec, N, J, sgn, with_norm ? npart : nullptr, flag);
   }
 
   // Restarted GMRES on A_prec sol = rhs; sol is updated in place.  Stops per RHS
@@ -424,17 +456,21 @@ struct Solver {
       bool done = false;
       for (; j < m && its < max_its; ++j) {
         double2* vj = V + (size_t)j * vlen;
+        double2* wv = V + (size_t)(j + 1) * vlen;  // w = A v_j is built in the slot of v_{j+1}
         // the FP32 copy of v_j was written by the scale kernel that produced it
-        if ((e = apply(prec, vj, w, prec == FMBEM_FP32 ? x32 : nullptr))) return e;
-        // CGS2: h = V^H w, w -= V h; h2 = V^H w, w -= V h2 (with |w|^2 partials), h += h2
-        mdot(V, j + 1, w, hc, 0);
-        maxpy(V, hc, w, j + 1, -1.0);
-        mdot(V, j + 1, w, hc, 3, y);
-        maxpy(V, y, w, j + 1, -1.0, true);
+        if ((e = apply(prec, vj, wv, prec == FMBEM_FP32 ? x32 : nullptr))) return e;
+        // Gram-Schmidt: h = V^H w (and ||w||^2 as the last dot), w -= V h (with |w|^2 partials);
+        // second pass h2 = V^H w, w -= V h2, h += h2 only where the DGKS criterion asks for it
+        mdot(V, j + 2, wv, hc, 0);
+        maxpy(V, hc, wv, j + 1, -1.0, true);
+        hipLaunchKernelGGL(reorth_check_kernel, dim3(R), dim3(256), 0, s, ortho, nb, npart, hc, hstride, j, jdone,
+                           reorth);
+        mdot(V, j + 1, wv, hc, 3, y, reorth);
+        maxpy(V, y, wv, j + 1, -1.0, true, reorth);
         const int slot = j & 1;
         hipLaunchKernelGGL(norm_givens_kernel, dim3(R), dim3(256), 0, s, npart, nb, m, j, hc, hstride, hn, H, cs, sn,
                            g, res, jdone, djd[slot], tol);
-        hipLaunchKernelGGL(scale_kernel, vgrid(), dim3(256), 0, s, w, hn, hstride, V + (size_t)(j + 1) * vlen,
+        hipLaunchKernelGGL(scale_kernel, vgrid(), dim3(256), 0, s, wv, hn, hstride, wv,
                            prec == FMBEM_FP32 ? x32 : nullptr, N);
         ++its;
         if ((e = hipEventRecord(ev[slot], s))) return e;
@@ -488,8 +524,11 @@ extern "C" fmbem_status fmbem_solve(fmbem_plan plan, const fmbem_solve_opts* opt
   if (!(P.precisions & 1u)) return FMBEM_ERR_UNSUPPORTED;  // the true residual needs the FP64 operator
   if (ip == FMBEM_FP32 && !(P.precisions & 2u)) return FMBEM_ERR_UNSUPPORTED;
   if ((size_t)n_rhs * P.C > (size_t)INT32_MAX / 2) return FMBEM_ERR_UNSUPPORTED;
+  if (opts->orthogonalization < FMBEM_ORTHO_DGKS || opts->orthogonalization > FMBEM_ORTHO_ONCE)
+    return FMBEM_ERR_INVALID_ARG;
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
   Solver S(P, s, n_rhs, m);
+  S.ortho = opts->orthogonalization;
   hipError_t e = S.setup(ip == FMBEM_FP32);
   if (e) return st_of(e);
   const int R = n_rhs;

@@ -149,6 +149,30 @@ def test_tiny_config_matvec_and_solve(tiny, form):
     assert rel(xr.cpu().numpy().ravel(), x_lu) < 1e-6
 
 
+@pytest.mark.parametrize("ortho", ["once", "twice"])
+def test_solve_gram_schmidt_modes(tiny, ortho):
+    # every Gram-Schmidt variant reaches the same LU solution (convergence is decided by the
+    # FP64 true residual), and an unknown mode is rejected before any work is enqueued
+    w, F, P = tiny["bm"]
+    b = bem.rhs_plane_wave(w.vertices, w.triangles, w.lattice, w.k, bem.default_alpha(w.k, "bm"),
+                           w.plane_waves)
+    x_lu = solve.lu_solve(F.dense(), b[0])
+    bd = P.incident_plane_wave(w.plane_waves)
+    for inner in ("fp64", "fp32"):
+        xs, info = P.solve(bd, tol=1e-9, inner=inner, ortho=ortho)
+        assert info[0]["rel_residual"] <= 1e-9
+        assert rel(xs.cpu().numpy().ravel(), x_lu) < 1e-6
+    import paper_2201_12050_amd as fm
+    from paper_2201_12050_amd import _lib
+    _lib.ORTHO["bogus"] = 7
+    try:
+        with pytest.raises(fm.FmbemError) as e:
+            P.solve(bd, tol=1e-9, ortho="bogus")
+        assert e.value.status == 1
+    finally:
+        del _lib.ORTHO["bogus"]
+
+
 def test_solve_not_converged_reports_status(tiny):
     w, F, P = tiny["bm"]
     bd = P.incident_plane_wave(w.plane_waves)
