@@ -63,14 +63,14 @@ typedef struct {
 } fmbem_cell_mesh;
 
 typedef struct {
-  int32_t grid[3];            /* M1, M2, M3 >= 1 */
+  int32_t grid[3];            /* M1, M2, M3 >= 1 (each <= 4096, else FMBEM_ERR_UNSUPPORTED) */
   double pitch[3];            /* lattice spacing per axis (m), > 0 */
   double k;                   /* wavenumber k = 2 pi f / c > 0 (1/m), Sec. 2.1 */
   int32_t order;              /* truncation number n_t in [0, 20]; p = (n_t+1)^2 (Sec. 3.1) */
   int32_t formulation;        /* fmbem_formulation */
   double alpha_re, alpha_im;  /* Burton-Miller coupling; both NaN => -i/k (Sec. 2.1) */
   int32_t near_radius[3];     /* near field: |d_a| <= near_radius_a cells (0 => 1) */
-  int32_t fft_shape[3];       /* 0 => smallest 2^a3^b5^c7^d >= 2 M_a - 1; else >= 2 M_a - 1 */
+  int32_t fft_shape[3];       /* 0 => smallest 2^a3^b5^c7^d >= 2 M_a - 1; else >= 2 M_a - 1 (<= 8192) */
   uint32_t precisions;        /* bitmask (1<<FMBEM_FP64) | (1<<FMBEM_FP32) of resident copies;
                                  0 => FP64 only */
 } fmbem_plan_desc;

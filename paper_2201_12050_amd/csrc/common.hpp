@@ -84,8 +84,6 @@ struct Plan {
     long long count[FMBEM_N_STAGES] = {0};
   };
   mutable Prof prof;
-  // autotuned near-field tile shape per (precision, columns = n_rhs * cells)
-  mutable std::vector<std::pair<long long, int>> near_shape;
 };
 
 // record the start / end of a stage when that stage is being profiled (returns the start event)
@@ -102,11 +100,14 @@ hipError_t matvec_launch(const Plan& P, int precision, int R, const void* x, voi
 // ---------------------------------------------------------------------------
 // kernels shared between translation units
 // ---------------------------------------------------------------------------
-constexpr int kMaxSeg = 32;  // near offsets per plan (3-D lattices with near radius 1 need 27)
+constexpr int kMaxSeg = 32;        // near offsets per plan (3-D lattices with near radius 1 need 27)
+constexpr int kMaxGridDim = 4096;  // lattice cells per axis
+constexpr int kMaxJobs = 40;       // GEMM jobs per grouped launch (larger groups are split)
 
-// grouped complex GEMM jobs on the near-field kernel (near.hip): C = A B with A complex
-// [M][K] row-major and B columns = cells (x RHS) of x, shifted by a cell offset, or
-// padded-grid bins
+// Grouped complex GEMM jobs on the near-field kernel (near.hip): out = A B with A complex
+// [M][K] row-major and N columns; column j is (RHS r, cell c) = (j / C, j % C) of the job's
+// lattice.  Its B column is x_{r, c - d} (SRC_X: src holds [R][C][K], zero outside the
+// lattice) or the padded-grid entry of cell c (SRC_GRID: src holds [bin][R][K]).
 enum NearSrc : int { SRC_X = 0, SRC_GRID = 1 };
 enum NearDest : int {
   DEST_SLICE = 0,  // out [N][M] column-major
@@ -116,28 +117,49 @@ enum NearDest : int {
 struct NearJob {
   const void* A;
   void* out;
-  int M, K;
-  int d0, d1, d2;  // cell offset of the B columns (SRC_X)
-  int src, dest;
-  int tile0;       // first workgroup of this job (set by near_launch)
+  const void* src;
   const void* part;
-  int nparts;
   void* out64;
+  int M, K, N;
+  int tile0;                 // first logical workgroup (set by near_launch)
+  int C, R;                  // cells and RHS of the job's lattice
+  short M0, M1, M2, N0, N1;  // lattice and padded-grid dims
+  short d0, d1, d2;          // cell offset of the B columns (SRC_X)
+  short nparts;
+  char src_kind, dest;
 };
 struct NearJobs {
   int count;
-  NearJob job[kMaxSeg + 1];
+  int total;  // workgroups
+  NearJob job[kMaxJobs];
 };
-struct NearGrid {
-  int C, R, M0, M1, M2, N0, N1;
-};
+inline NearJob near_job(const Plan& P, int R, const void* A, void* out, int M, int K, const void* src, int src_kind,
+                        int dest) {
+  NearJob j{};
+  j.A = A;
+  j.out = out;
+  j.src = src;
+  j.M = M;
+  j.K = K;
+  j.N = R * P.C;
+  j.C = P.C;
+  j.R = R;
+  j.M0 = (short)P.grid[0];
+  j.M1 = (short)P.grid[1];
+  j.M2 = (short)P.grid[2];
+  j.N0 = (short)P.fft[0];
+  j.N1 = (short)P.fft[1];
+  j.src_kind = (char)src_kind;
+  j.dest = (char)dest;
+  return j;
+}
 
-// shape < 0: default tile shape for this problem; else one of near_num_shapes() shapes.
-// x: B source for SRC_X jobs (stride n per cell column); grid: B source for SRC_GRID jobs.
-// kind 0 launches the tile body as near_kernel (near field + S2M), 1 as l2t_kernel (L2T).
+// Launch a list of jobs (split into launches of at most kMaxJobs).  shape < 0: default tile
+// shape; else one of near_num_shapes<T>() shapes.  kind 0 launches the tile body as
+// near_kernel (near field + S2M), 1 as l2t_kernel (L2T).
 template <typename T>
-hipError_t near_launch(int n, int N, NearJobs jobs, const void* x, const void* grid, const NearGrid& g,
-                       hipStream_t s, int shape = -1, int kind = 0);
+hipError_t near_launch(const std::vector<NearJob>& jobs, hipStream_t s, int shape = -1, int kind = 0);
+template <typename T>
 int near_num_shapes();
 // y = sum of ns partial slices (FP64 to y64 when set)
 template <typename T>

@@ -11,6 +11,8 @@
 // Workspace: [padded grid B x R x p][near partials n_near x R x C x n], 256-byte aligned.
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 
 #include "common.hpp"
 
@@ -48,88 +50,109 @@ void prof_end(const Plan& P, int stage, hipEvent_t start, hipStream_t s) {
 }
 
 // Autotuner of the tile shape of a grouped launch: on the first launch of a given
-// kind, precision and column count, every shape is launched once to warm up and
-// twice timed with HIP events on the caller's stream (the launches compute the real
-// products, which the launch that follows overwrites); the fastest is cached in the
-// plan.  Blocks the host once per key.
+// job-list signature (kind, precision, job sizes), every shape is launched once to
+// warm up and twice timed with HIP events on the caller's stream (the launches
+// compute the real products, which the launch that follows overwrites); the fastest
+// is cached for the process.  Blocks the host once per signature.
+static std::mutex g_tune_mu;
+static std::map<std::vector<long long>, int> g_tuned;
+
 template <typename T>
-static int tuned_shape(const Plan& P, int kind, int n, int N, const NearJobs& jobs, const void* x,
-                       const void* gridbuf, const NearGrid& g, hipStream_t s) {
-  const long long key = ((long long)N * 4 + kind) * 2 + (sizeof(T) == 8 ? 0 : 1);
-  for (const auto& kv : P.near_shape)
-    if (kv.first == key) return kv.second;
+int tuned_shape(int kind, const std::vector<NearJob>& jobs, hipStream_t s) {
+  std::vector<long long> key{kind, (long long)sizeof(T)};
+  for (const NearJob& j : jobs) {
+    key.push_back(j.M);
+    key.push_back(j.K);
+    key.push_back(j.N);
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) return it->second;
+  }
   int best = -1;
   hipEvent_t a = nullptr, b = nullptr;
   if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
     // two sweeps over the shapes, the minimum of each shape's timings counts
-    std::vector<float> t(near_num_shapes(), 1e30f);
+    const int ns = near_num_shapes<T>();
+    std::vector<float> t(ns, 1e30f);
     for (int sweep = 0; sweep < 2; ++sweep) {
-      for (int v = 0; v < near_num_shapes(); ++v) {
-        if (near_launch<T>(n, N, jobs, x, gridbuf, g, s, v, kind) != hipSuccess) continue;
+      for (int v = 0; v < ns; ++v) {
+        if (near_launch<T>(jobs, s, v, kind) != hipSuccess) continue;
         hipEventRecord(a, s);
-        near_launch<T>(n, N, jobs, x, gridbuf, g, s, v, kind);
-        near_launch<T>(n, N, jobs, x, gridbuf, g, s, v, kind);
+        near_launch<T>(jobs, s, v, kind);
+        near_launch<T>(jobs, s, v, kind);
         hipEventRecord(b, s);
         float ms = 0.f;
         if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) continue;
         t[v] = std::min(t[v], ms);
       }
     }
-    for (int v = 0; v < near_num_shapes(); ++v)
+    for (int v = 0; v < ns; ++v)
       if (t[v] < 1e29f && (best < 0 || t[v] < t[best])) best = v;
   }
   if (a) hipEventDestroy(a);
   if (b) hipEventDestroy(b);
-  P.near_shape.push_back({key, best});
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[key] = best;
   return best;
+}
+
+// workspace layout: [padded grid B x R x p][near partials n_near x R x C x n]
+template <typename T>
+static char* near_partials(const Plan& P, int R, void* ws) {
+  return reinterpret_cast<char*>(ws) + align256((size_t)P.B * R * P.p * sizeof(cplx<T>));
+}
+
+template <typename T>
+void near_s2m_jobs(const Plan& P, int R, const void* x, void* ws, std::vector<NearJob>& out) {
+  const int prec = sizeof(T) == 8 ? 0 : 1;
+  const int n = P.n;
+  const size_t el = sizeof(cplx<T>);
+  char* part = near_partials<T>(P, R, ws);
+  const size_t slice = (size_t)R * P.C * n;  // complex elements per near partial
+  const size_t blk = (size_t)n * n * el;
+  for (int d = 0; d < P.n_near; ++d) {
+    NearJob j = near_job(P, R, reinterpret_cast<const char*>(P.S[prec]) + d * blk, part + d * slice * el, n, n, x,
+                         SRC_X, DEST_SLICE);
+    j.d0 = (short)P.near_off[3 * d];
+    j.d1 = (short)P.near_off[3 * d + 1];
+    j.d2 = (short)P.near_off[3 * d + 2];
+    out.push_back(j);
+  }
+  if (P.n_far > 0) out.push_back(near_job(P, R, P.V0[prec], ws, P.p, n, x, SRC_X, DEST_GRID));
+}
+
+template <typename T>
+NearJob l2t_job(const Plan& P, int R, void* ws, void* y, void* y64) {
+  const int prec = sizeof(T) == 8 ? 0 : 1;
+  NearJob j = near_job(P, R, P.U0[prec], y, P.n, P.p, ws, SRC_GRID, DEST_FINAL);
+  j.part = near_partials<T>(P, R, ws);
+  j.nparts = (short)P.n_near;
+  j.out64 = y64;
+  return j;
 }
 
 template <typename T>
 static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* ws, hipStream_t s, void* y64) {
   const int prec = sizeof(T) == 8 ? 0 : 1;
-  const int n = P.n, C = P.C, p = P.p;
-  const int N = R * C;
-  const size_t el = sizeof(cplx<T>);
-  char* grid_buf = reinterpret_cast<char*>(ws);
-  char* part = grid_buf + align256((size_t)P.B * R * p * el);
-  const size_t slice = (size_t)N * n;  // complex elements per near partial
-  const NearGrid g{C, R, P.grid[0], P.grid[1], P.grid[2], P.fft[0], P.fft[1]};
+  const int p = P.p;
   P.prof.active = P.prof.mask != 0 && (P.prof.calls++ % P.prof.period) == 0;
-  auto job = [](const void* A, void* out, int M, int K, int src, int dest) {
-    NearJob j{};
-    j.A = A;
-    j.out = out;
-    j.M = M;
-    j.K = K;
-    j.src = src;
-    j.dest = dest;
-    return j;
-  };
   // [0] near field and S2M
   hipEvent_t ev = nullptr;
   {
-    NearJobs jobs;
-    jobs.count = 0;
-    const size_t blk = (size_t)n * n * el;
-    for (int d = 0; d < P.n_near; ++d) {
-      NearJob j = job(reinterpret_cast<const char*>(P.S[prec]) + d * blk, part + d * slice * el, n, n, SRC_X,
-                      DEST_SLICE);
-      j.d0 = P.near_off[3 * d];
-      j.d1 = P.near_off[3 * d + 1];
-      j.d2 = P.near_off[3 * d + 2];
-      jobs.job[jobs.count++] = j;
-    }
-    if (P.n_far > 0) jobs.job[jobs.count++] = job(P.V0[prec], grid_buf, p, n, SRC_X, DEST_GRID);
-    const int shape = tuned_shape<T>(P, 0, n, N, jobs, x, grid_buf, g, s);
+    std::vector<NearJob> jobs;
+    near_s2m_jobs<T>(P, R, x, ws, jobs);
+    const int shape = tuned_shape<T>(0, jobs, s);
     ev = prof_begin(P, 0 + 6 * prec, s);
-    hipError_t e = near_launch<T>(n, N, jobs, x, grid_buf, g, s, shape);
+    hipError_t e = near_launch<T>(jobs, s, shape, 0);
     if (e != hipSuccess) return e;
   }
   prof_end(P, 0 + 6 * prec, ev, s);
   if (P.n_far == 0) {
     // [1] sum of the near partials
     ev = prof_begin(P, 1 + 6 * prec, s);
-    hipError_t e = near_reduce_launch<T>(part, P.n_near, slice, y, y64, s);
+    hipError_t e = near_reduce_launch<T>(near_partials<T>(P, R, ws), P.n_near, (size_t)R * P.C * P.n, y, y64, s);
     if (e != hipSuccess) return e;
     prof_end(P, 1 + 6 * prec, ev, s);
     return hipSuccess;
@@ -149,15 +172,10 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
   prof_end(P, 4 + 6 * prec, ev, s);
   // [5] L2T with the fixed-order sum of the near partials
   {
-    NearJobs jobs;
-    jobs.count = 1;
-    jobs.job[0] = job(P.U0[prec], y, n, p, SRC_GRID, DEST_FINAL);
-    jobs.job[0].part = part;
-    jobs.job[0].nparts = P.n_near;
-    jobs.job[0].out64 = y64;
-    const int shape = tuned_shape<T>(P, 1, n, N, jobs, x, grid_buf, g, s);
+    std::vector<NearJob> jobs{l2t_job<T>(P, R, ws, y, y64)};
+    const int shape = tuned_shape<T>(1, jobs, s);
     ev = prof_begin(P, 5 + 6 * prec, s);
-    e = near_launch<T>(n, N, jobs, x, grid_buf, g, s, shape, 1);
+    e = near_launch<T>(jobs, s, shape, 1);
   }
   prof_end(P, 5 + 6 * prec, ev, s);
   return e;

@@ -6,17 +6,25 @@
 //   L2T         y[:, (r,c)]      = sum_d part_d[:, (r,c)] + U0 l[bin(c)][r]     (n x p, from the padded grid)
 //
 // A job is one GEMM whose B columns are the cells (x right-hand sides) of x,
-// shifted by the job's cell offset, or the bins of the padded grid.  A workgroup
-// owns a tile of ROWS complex rows of one job and COLS columns, so the job's A
-// tile is streamed from HBM once per column chunk while B stays in L2.  The near
-// partial products are summed in a fixed order in the L2T epilogue
-// (deterministic, independent of batching).
+// shifted by the job's cell offset, or the bins of the padded grid.  Jobs of
+// different lattices (plans) can share one launch: each job carries its own
+// lattice geometry.  The launch is a flat list of workgroups; workgroup w owns
+// row tile w / ctiles and column tile w % ctiles of its job, and the list is dealt
+// so that the column tiles of one row tile land on one XCD (the hardware deals
+// consecutive workgroup ids round-robin over the 8 XCDs), where the A tile is
+// read from HBM once into that XCD's L2.  The near partial products are summed in
+// a fixed order in the L2T epilogue (deterministic, independent of batching).
 //
-// Complex products use the real 2x2 split form [Re A, -Im A; Im A, Re A] x
-// [Re B; Im B] on 16x16x4 MFMA tiles: A is read in complex form and expanded
-// while staged into LDS, B columns are interleaved complex read as real columns
-// of length 2K.  Global loads for the next K step are issued before the MFMAs of
-// the current one.
+// Complex products take three real products per complex product (Gauss):
+//   P1 = Re A Re B,  P2 = Im A Im B,  P3 = (Re A + Im A)(Re B + Im B),
+//   Re = P1 - P2,    Im = P3 - P1 - P2,
+// on 16x16x4 MFMA tiles (FP32 or FP64), i.e. 3/4 of the matrix-core work of the
+// 2x2 real split form.  Within one step of KC complex k, the four k slots of an
+// MFMA are taken by lane group g = lane / 16 over k = g * KC/4 + t (t = 0 .. KC/4-1):
+// the sum over k is the same, and every lane reads its KC/4 operands of a row or
+// column with one 16-byte LDS load.  LDS holds two steps (ping-pong): the global
+// loads of step s+1 are issued before the MFMAs of step s and stored after them, one
+// barrier per step.
 #include <algorithm>
 
 #include "common.hpp"
@@ -26,70 +34,85 @@ namespace fmbem {
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-// Output layout of the 16x16x4 tiles (checked on gfx950): lane l holds column l%16
-// and four rows; f32: rows 4g..4g+3, f64: rows g, g+4, g+8, g+12 (g = l/16).
-// rowpos() places split-form row (complex row cr, component c) of a 16-row block so
-// that every lane holds (re, im) of complex rows 2g, 2g+1 in registers (0,1), (2,3).
+// Output layout of the 16x16x4 tiles (checked on gfx950): lane l holds column l % 16
+// and four rows q = 0..3: f32 rows 4g + q, f64 rows g + 4q (g = l / 16).
 template <typename T> struct nmf;
 template <> struct nmf<double> {
   using acc = v4d;
-  __device__ static inline int rowpos(int cr, int c) {
-    const int blk = cr >> 3, cb = cr & 7;
-    return 16 * blk + (cb >> 1) + 4 * (2 * (cb & 1) + c);
-  }
+  __device__ static inline int row(int g, int q) { return g + 4 * q; }
   __device__ static inline acc step(double a, double b, acc c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
 };
 template <> struct nmf<float> {
   using acc = v4f;
-  __device__ static inline int rowpos(int cr, int c) { return 2 * cr + c; }
+  __device__ static inline int row(int g, int q) { return 4 * g + q; }
   __device__ static inline acc step(float a, float b, acc c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
 };
 
-__device__ inline void cell_coords(const NearGrid& g, int j, int& r, int& i1, int& i2, int& i3) {
-  r = j / g.C;
-  const int c = j - r * g.C;
-  i1 = c % g.M0;
-  const int t = c / g.M0;
-  i2 = t % g.M1;
-  i3 = t / g.M1;
+__device__ inline void cell_coords(const NearJob& jb, int j, int& r, int& i1, int& i2, int& i3) {
+  r = j / jb.C;
+  const int c = j - r * jb.C;
+  i1 = c % jb.M0;
+  const int t = c / jb.M0;
+  i2 = t % jb.M1;
+  i3 = t / jb.M1;
 }
+
+// LDS layout of one operand tile: a row (of A) or column (of B) holds the KC k values of
+// one step in four 16-byte chunks (KC = 16 floats or 8 doubles); chunk c of row r sits
+// at slot 4 r + (c ^ ((r >> 2) & 3)).  The XOR makes both access patterns free of bank
+// conflicts without padding: a fragment read (16 rows, one chunk each) and a staging
+// write (consecutive rows, whole chunks) both touch 64 distinct banks per 16 lanes.
+__device__ inline int lds_slot(int r, int c) { return 4 * r + (c ^ ((r >> 2) & 3)); }
 
 // Tile: ROWS complex rows x COLS columns, 4 waves arranged WR x (4/WR), KC complex k per step.
 template <typename T, int ROWS, int COLS, int WR, int KC>
-__device__ __forceinline__ void near_tile(int n, int N, const NearJobs& jobs, const cplx<T>* __restrict__ x,
-                                          const cplx<T>* __restrict__ grid, const NearGrid& g) {
+__device__ __forceinline__ void near_tile(const NearJobs& jobs) {
   constexpr int WC = 4 / WR;
-  constexpr int RR = 2 * ROWS;          // real rows per tile
-  constexpr int RBW = RR / (16 * WR);   // 16-row MFMA blocks per wave
-  constexpr int CBW = COLS / (16 * WC); // 16-column MFMA blocks per wave
-  static_assert(RBW >= 1 && CBW >= 1, "tile too small for the wave grid");
-  constexpr int LDA = RR + 4;
-  constexpr int LDB = COLS + 4;
-  constexpr int BPT = COLS * KC / 256; // B complex elements per thread per step
-  constexpr int TPC = KC / BPT;        // threads per column
-  __shared__ T As[2 * KC][LDA];
-  __shared__ T Bs[2 * KC][LDB];
+  constexpr int RBW = ROWS / (16 * WR);  // 16-row MFMA blocks per wave
+  constexpr int CBW = COLS / (16 * WC);  // 16-column MFMA blocks per wave
+  static_assert(RBW >= 1 && CBW >= 1 && RBW * 16 * WR == ROWS && CBW * 16 * WC == COLS, "tile / wave grid");
+  constexpr int CW = 16 / sizeof(T);            // values per 16-byte chunk
+  static_assert(KC * sizeof(T) == 64, "one step = four 16-byte chunks per row");
+  constexpr int AT = ROWS * KC;                 // A complex elements per step
+  constexpr int APT = AT >= 256 ? AT / 256 : 1; // per thread (consecutive k)
+  constexpr int BPT = COLS * KC / 256;          // B complex elements per thread (consecutive k)
+  constexpr int TPC = KC / BPT;                 // threads per B column
+  static_assert(KC % APT == 0 && BPT >= 1 && KC % BPT == 0, "staging split");
+  static_assert((APT % CW == 0 || CW % APT == 0) && (BPT % CW == 0 || CW % BPT == 0), "chunk split");
+  typedef T VK __attribute__((ext_vector_type(CW)));
+  // two buffers (ping-pong over the k steps) x {Re, Im} of A and of B, in chunks; the
+  // sums Re + Im of the third product are formed in registers after the fragment loads
+  __shared__ VK Asm[2][2][ROWS * 4];
+  __shared__ VK Bsm[2][2][COLS * 4];
   using Acc = typename nmf<T>::acc;
 
-  // job lookup
+  // logical workgroup (XCD-aware deal), job and tile
+  int L = (int)blockIdx.x;
+  {
+    const int per = jobs.total / 8;
+    if (L < per * 8) L = (L % 8) * per + L / 8;
+  }
   int ji = 0;
-  while (ji + 1 < jobs.count && (int)blockIdx.x >= jobs.job[ji + 1].tile0) ++ji;
-  const NearJob jb = jobs.job[ji];
-  const int m0 = ((int)blockIdx.x - jb.tile0) * ROWS;
-  const int M = jb.M, K = jb.K;
+  while (ji + 1 < jobs.count && L >= jobs.job[ji + 1].tile0) ++ji;
+  const NearJob& jb = jobs.job[ji];
+  const int M = jb.M, K = jb.K, N = jb.N;
+  const int ctiles = (N + COLS - 1) / COLS;
+  const int local = L - jb.tile0;
+  const int m0 = (local / ctiles) * ROWS;
+  const int col0 = (local % ctiles) * COLS;
   const cplx<T>* A = reinterpret_cast<const cplx<T>*>(jb.A);
-  const int col0 = blockIdx.y * COLS;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wr = wave / WC, wc = wave % WC;
+  const int g = lane >> 4, li = lane & 15;
 
-  // B column of this thread; nullptr = zero column (shifted outside the grid)
+  // B column of this thread; nullptr = zero column (shifted outside the lattice)
   const int b_col = tid / TPC;
   const int b_k = (tid % TPC) * BPT;
   const cplx<T>* bcol = nullptr;
@@ -97,37 +120,45 @@ __device__ __forceinline__ void near_tile(int n, int N, const NearJobs& jobs, co
     const int j = col0 + b_col;
     if (j < N) {
       int r, i1, i2, i3;
-      cell_coords(g, j, r, i1, i2, i3);
-      if (jb.src == SRC_X) {
+      cell_coords(jb, j, r, i1, i2, i3);
+      const cplx<T>* src = reinterpret_cast<const cplx<T>*>(jb.src);
+      if (jb.src_kind == SRC_X) {
         const int s1 = i1 - jb.d0, s2 = i2 - jb.d1, s3 = i3 - jb.d2;
-        if (s1 >= 0 && s1 < g.M0 && s2 >= 0 && s2 < g.M1 && s3 >= 0 && s3 < g.M2)
-          bcol = x + ((size_t)r * g.C + (s1 + g.M0 * (s2 + g.M1 * s3))) * n;
+        if (s1 >= 0 && s1 < jb.M0 && s2 >= 0 && s2 < jb.M1 && s3 >= 0 && s3 < jb.M2)
+          bcol = src + ((size_t)r * jb.C + (s1 + jb.M0 * (s2 + jb.M1 * s3))) * K;
       } else {
-        const size_t bin = (size_t)i1 + (size_t)g.N0 * (i2 + (size_t)g.N1 * i3);
-        bcol = grid + (bin * g.R + r) * K;
+        const size_t bin = (size_t)i1 + (size_t)jb.N0 * (i2 + (size_t)jb.N1 * i3);
+        bcol = src + (bin * jb.R + r) * K;
       }
     }
   }
-  // A staging: ROWS x KC complex per step, APT per thread
-  constexpr int AT = ROWS * KC;
-  constexpr int APT = AT >= 256 ? AT / 256 : 1;
+  // A staging: thread t < AT / APT holds APT consecutive k of one row
+  const bool a_act = tid * APT < AT;
+  const int a_row = (tid * APT) / KC, a_k = (tid * APT) % KC;
+  const cplx<T>* arow = (a_act && m0 + a_row < M) ? A + (size_t)(m0 + a_row) * K : nullptr;
 
-  Acc acc[RBW][CBW];
+  Acc p1[RBW][CBW], p2[RBW][CBW], p3[RBW][CBW];
 #pragma unroll
   for (int i = 0; i < RBW; ++i)
 #pragma unroll
-    for (int j = 0; j < CBW; ++j) acc[i][j] = Acc{0, 0, 0, 0};
+    for (int j = 0; j < CBW; ++j) {
+      p1[i][j] = Acc{0, 0, 0, 0};
+      p2[i][j] = Acc{0, 0, 0, 0};
+      p3[i][j] = Acc{0, 0, 0, 0};
+    }
 
   cplx<T> ra[APT];
   cplx<T> rb[BPT];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < APT; ++q) {
-      ra[q] = mk<T>(0, 0);
-      const int e = tid + 256 * q;
-      if (e < AT) {
-        const int m = m0 + e / KC, kk = k0 + e % KC;
-        if (m < M && kk < K) ra[q] = A[(size_t)m * K + kk];
+    for (int q = 0; q < APT; ++q) ra[q] = mk<T>(0, 0);
+    if (arow) {
+      if (k0 + KC <= K) {
+#pragma unroll
+        for (int q = 0; q < APT; ++q) ra[q] = arow[k0 + a_k + q];
+      } else {
+        for (int q = 0; q < APT; ++q)
+          if (k0 + a_k + q < K) ra[q] = arow[k0 + a_k + q];
       }
     }
 #pragma unroll
@@ -142,76 +173,128 @@ __device__ __forceinline__ void near_tile(int n, int N, const NearJobs& jobs, co
       }
     }
   };
-  load(0);
-  for (int k0 = 0; k0 < K; k0 += KC) {
-    __syncthreads();
+  // staged values -> LDS buffer b (whole chunks as one 16-byte store, partial chunks element-wise)
+  auto store = [&](int b) {
+    if (a_act) {
+      if constexpr (APT >= CW) {
 #pragma unroll
-    for (int q = 0; q < APT; ++q) {
-      const int e = tid + 256 * q;
-      if (e < AT) {
-        const int row = e / KC, kc = e % KC;
-        const int pr = nmf<T>::rowpos(row, 0), pi = nmf<T>::rowpos(row, 1);
-        As[2 * kc][pr] = ra[q].x;
-        As[2 * kc + 1][pr] = -ra[q].y;
-        As[2 * kc][pi] = ra[q].y;
-        As[2 * kc + 1][pi] = ra[q].x;
+        for (int c = 0; c < APT / CW; ++c) {
+          VK vr, vi;
+#pragma unroll
+          for (int e = 0; e < CW; ++e) {
+            vr[e] = ra[c * CW + e].x;
+            vi[e] = ra[c * CW + e].y;
+          }
+          const int o = lds_slot(a_row, a_k / CW + c);
+          Asm[b][0][o] = vr;
+          Asm[b][1][o] = vi;
+        }
+      } else {
+        const int o = lds_slot(a_row, a_k / CW);
+        T* pr = reinterpret_cast<T*>(&Asm[b][0][o]) + a_k % CW;
+        T* pi = reinterpret_cast<T*>(&Asm[b][1][o]) + a_k % CW;
+#pragma unroll
+        for (int q = 0; q < APT; ++q) {
+          pr[q] = ra[q].x;
+          pi[q] = ra[q].y;
+        }
       }
     }
+    if constexpr (BPT >= CW) {
 #pragma unroll
-    for (int e = 0; e < BPT; ++e) {
-      Bs[2 * (b_k + e)][b_col] = rb[e].x;
-      Bs[2 * (b_k + e) + 1][b_col] = rb[e].y;
+      for (int c = 0; c < BPT / CW; ++c) {
+        VK vr, vi;
+#pragma unroll
+        for (int e = 0; e < CW; ++e) {
+          vr[e] = rb[c * CW + e].x;
+          vi[e] = rb[c * CW + e].y;
+        }
+        const int o = lds_slot(b_col, b_k / CW + c);
+        Bsm[b][0][o] = vr;
+        Bsm[b][1][o] = vi;
+      }
+    } else {
+      const int o = lds_slot(b_col, b_k / CW);
+      T* pr = reinterpret_cast<T*>(&Bsm[b][0][o]) + b_k % CW;
+      T* pi = reinterpret_cast<T*>(&Bsm[b][1][o]) + b_k % CW;
+#pragma unroll
+      for (int e = 0; e < BPT; ++e) {
+        pr[e] = rb[e].x;
+        pi[e] = rb[e].y;
+      }
     }
+  };
+
+  const int nsteps = (K + KC - 1) / KC;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int st = 0; st < nsteps; ++st) {
+    const int b = st & 1;
+    const bool more = st + 1 < nsteps;
+    if (more) load((st + 1) * KC);
+    VK ar[RBW], ai[RBW], as[RBW];
+#pragma unroll
+    for (int i = 0; i < RBW; ++i) {
+      const int o = lds_slot(16 * (RBW * wr + i) + li, g);
+      ar[i] = Asm[b][0][o];
+      ai[i] = Asm[b][1][o];
+      as[i] = ar[i] + ai[i];
+    }
+#pragma unroll
+    for (int j = 0; j < CBW; ++j) {
+      const int o = lds_slot(16 * (CBW * wc + j) + li, g);
+      const VK br = Bsm[b][0][o];
+      const VK bi = Bsm[b][1][o];
+      const VK bs = br + bi;
+#pragma unroll
+      for (int t = 0; t < CW; ++t)
+#pragma unroll
+        for (int i = 0; i < RBW; ++i) {
+          p1[i][j] = nmf<T>::step(ar[i][t], br[t], p1[i][j]);
+          p2[i][j] = nmf<T>::step(ai[i][t], bi[t], p2[i][j]);
+          p3[i][j] = nmf<T>::step(as[i][t], bs[t], p3[i][j]);
+        }
+    }
+    // the other buffer was last read before the previous barrier
+    if (more) store(b ^ 1);
     __syncthreads();
-    if (k0 + KC < K) load(k0 + KC);
-#pragma unroll
-    for (int ks = 0; ks < 2 * KC; ks += 4) {
-      const int kr = ks + (lane >> 4);
-      T af[RBW], bf[CBW];
-#pragma unroll
-      for (int i = 0; i < RBW; ++i) af[i] = As[kr][16 * (RBW * wr + i) + (lane & 15)];
-#pragma unroll
-      for (int j = 0; j < CBW; ++j) bf[j] = Bs[kr][16 * (CBW * wc + j) + (lane & 15)];
-#pragma unroll
-      for (int i = 0; i < RBW; ++i)
-#pragma unroll
-        for (int j = 0; j < CBW; ++j) acc[i][j] = nmf<T>::step(af[i], bf[j], acc[i][j]);
-    }
   }
 
-  // epilogue: (re, im) of complex rows 2g, 2g+1 of each 16-row block (see rowpos)
+  // epilogue: lane holds column li of each 16-column block and rows nmf<T>::row(g, q)
   cplx<T>* out = reinterpret_cast<cplx<T>*>(jb.out);
   const cplx<T>* part = reinterpret_cast<const cplx<T>*>(jb.part);
   double2* out64 = reinterpret_cast<double2*>(jb.out64);
   const size_t slice = (size_t)N * M;
 #pragma unroll
   for (int j = 0; j < CBW; ++j) {
-    const int col = col0 + 16 * (CBW * wc + j) + (lane & 15);
+    const int col = col0 + 16 * (CBW * wc + j) + li;
     if (col >= N) continue;
     size_t base;
     if (jb.dest == DEST_GRID) {
       int r, i1, i2, i3;
-      cell_coords(g, col, r, i1, i2, i3);
-      const size_t bin = (size_t)i1 + (size_t)g.N0 * (i2 + (size_t)g.N1 * i3);
-      base = (bin * g.R + r) * M;
+      cell_coords(jb, col, r, i1, i2, i3);
+      const size_t bin = (size_t)i1 + (size_t)jb.N0 * (i2 + (size_t)jb.N1 * i3);
+      base = (bin * jb.R + r) * M;
     } else {
       base = (size_t)col * M;
     }
 #pragma unroll
     for (int i = 0; i < RBW; ++i) {
-      const int m = m0 + 8 * (RBW * wr + i) + 2 * (lane >> 4);
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        if (m + h >= M) continue;
-        cplx<T> v = mk<T>(acc[i][j][2 * h], acc[i][j][2 * h + 1]);
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + 16 * (RBW * wr + i) + nmf<T>::row(g, q);
+        if (m >= M) continue;
+        const T a = p1[i][j][q], bb = p2[i][j][q];
+        cplx<T> v = mk<T>(a - bb, p3[i][j][q] - a - bb);
         if (jb.dest == DEST_FINAL) {
-          for (int q = 0; q < jb.nparts; ++q) v = cadd<T>(v, part[q * slice + base + m + h]);
+          for (int s = 0; s < jb.nparts; ++s) v = cadd<T>(v, part[s * slice + base + m]);
           if (out64) {
-            out64[base + m + h] = make_double2((double)v.x, (double)v.y);
+            out64[base + m] = make_double2((double)v.x, (double)v.y);
             continue;
           }
         }
-        out[base + m + h] = v;
+        out[base + m] = v;
       }
     }
   }
@@ -220,14 +303,12 @@ __device__ __forceinline__ void near_tile(int n, int N, const NearJobs& jobs, co
 // The same tile body under two kernel names, so that per-kernel profiles keep the near-field/S2M
 // launch apart from the L2T launch even when both use the same tile shape.
 template <typename T, int ROWS, int COLS, int WR, int KC>
-__global__ __launch_bounds__(256) void near_kernel(int n, int N, NearJobs jobs, const cplx<T>* __restrict__ x,
-                                                   const cplx<T>* __restrict__ grid, NearGrid g) {
-  near_tile<T, ROWS, COLS, WR, KC>(n, N, jobs, x, grid, g);
+__global__ __launch_bounds__(256) void near_kernel(NearJobs jobs) {
+  near_tile<T, ROWS, COLS, WR, KC>(jobs);
 }
 template <typename T, int ROWS, int COLS, int WR, int KC>
-__global__ __launch_bounds__(256) void l2t_kernel(int n, int N, NearJobs jobs, const cplx<T>* __restrict__ x,
-                                                  const cplx<T>* __restrict__ grid, NearGrid g) {
-  near_tile<T, ROWS, COLS, WR, KC>(n, N, jobs, x, grid, g);
+__global__ __launch_bounds__(256) void l2t_kernel(NearJobs jobs) {
+  near_tile<T, ROWS, COLS, WR, KC>(jobs);
 }
 
 // y[col][m] = sum_s part[s][col][m] in a fixed order (optionally written as FP64)
@@ -242,38 +323,58 @@ __global__ void near_reduce_kernel(const cplx<T>* __restrict__ part, int ns, siz
   }
 }
 
-// tile shapes: (complex rows, columns, wave rows, complex k per step)
+// tile shapes: (complex rows, columns, wave rows, complex k per step); FP32 steps over
+// 16 complex k (one 16-byte LDS load of 4 floats per operand), FP64 over 8 (2 doubles)
 struct NearShape {
   int rows, cols, wr, kc;
 };
-static const NearShape kShapes[] = {{16, 256, 1, 8}, {32, 256, 1, 8}, {32, 128, 2, 8},  {64, 64, 4, 8},
-                                    {32, 64, 2, 8},  {16, 128, 1, 8}, {16, 64, 1, 8},   {32, 128, 2, 16},
-                                    {64, 64, 4, 16}, {16, 128, 1, 16}, {64, 128, 2, 8}};
-constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+#define FMBEM_NEAR_SHAPES(KC)                                                                        \
+  X(0, 64, 128, 2, KC) X(1, 32, 128, 2, KC) X(2, 64, 64, 2, KC) X(3, 64, 64, 4, KC) X(4, 32, 64, 2, KC) \
+  X(5, 16, 128, 1, KC) X(6, 16, 256, 1, KC) X(7, 128, 64, 4, KC) X(8, 32, 128, 1, KC) X(9, 16, 64, 1, KC)
+constexpr int kNumShapes = 10;
+template <typename T> constexpr int shape_kc() { return sizeof(T) == 4 ? 16 : 8; }
 
-int near_num_shapes() { return kNumShapes; }
+template <typename T>
+static NearShape shape_of(int v) {
+  switch (v) {
+#define X(i, r, c, w, k) \
+  case i: return NearShape{r, c, w, k};
+    FMBEM_NEAR_SHAPES(shape_kc<T>())
+#undef X
+  }
+  return NearShape{64, 128, 2, shape_kc<T>()};
+}
 
-template <typename T, int ROWS, int COLS, int WR, int KC>
-static void launch_shape(dim3 grid, hipStream_t s, int kind, int n, int N, const NearJobs& jobs, const void* x,
-                         const void* gridbuf, const NearGrid& g) {
-  const cplx<T>* xs = reinterpret_cast<const cplx<T>*>(x);
-  const cplx<T>* gs = reinterpret_cast<const cplx<T>*>(gridbuf);
-  if (kind == 1)
-    hipLaunchKernelGGL((l2t_kernel<T, ROWS, COLS, WR, KC>), grid, dim3(256), 0, s, n, N, jobs, xs, gs, g);
-  else
-    hipLaunchKernelGGL((near_kernel<T, ROWS, COLS, WR, KC>), grid, dim3(256), 0, s, n, N, jobs, xs, gs, g);
+template <typename T>
+int near_num_shapes() {
+  return kNumShapes;
+}
+
+template <typename T>
+static void launch_shape(int v, int kind, unsigned blocks, const NearJobs& jobs, hipStream_t s) {
+  switch (v) {
+#define X(i, r, c, w, k)                                                                      \
+  case i:                                                                                     \
+    if (kind == 1) hipLaunchKernelGGL((l2t_kernel<T, r, c, w, k>), dim3(blocks), dim3(256), 0, s, jobs); \
+    else hipLaunchKernelGGL((near_kernel<T, r, c, w, k>), dim3(blocks), dim3(256), 0, s, jobs);          \
+    break;
+    FMBEM_NEAR_SHAPES(shape_kc<T>())
+#undef X
+  }
 }
 
 // default shape: the one whose workgroup count best fills whole rounds of 256 CUs
-static int near_default_shape(int N, const NearJobs& jobs) {
+template <typename T>
+static int near_default_shape(const std::vector<NearJob>& jobs) {
   int best = 0;
   double best_score = -1.0;
-  for (int v = 0; v < 4; ++v) {
-    long long tiles = 0;
-    for (int j = 0; j < jobs.count; ++j) tiles += (jobs.job[j].M + kShapes[v].rows - 1) / kShapes[v].rows;
-    const long long wg = tiles * ((N + kShapes[v].cols - 1) / kShapes[v].cols);
+  for (int v = 0; v < kNumShapes; ++v) {
+    const NearShape sh = shape_of<T>(v);
+    long long wg = 0;
+    for (const NearJob& j : jobs)
+      wg += (long long)((j.M + sh.rows - 1) / sh.rows) * ((j.N + sh.cols - 1) / sh.cols);
     const long long rounds = (wg + 255) / 256;
-    const double score = (double)wg / (double)(rounds * 256) + 1e-3 * kShapes[v].rows * kShapes[v].cols / 4096.0;
+    const double score = (double)wg / (double)(rounds * 256) + 1e-3 * sh.rows * sh.cols / 8192.0;
     if (score > best_score) {
       best_score = score;
       best = v;
@@ -283,30 +384,27 @@ static int near_default_shape(int N, const NearJobs& jobs) {
 }
 
 template <typename T>
-hipError_t near_launch(int n, int N, NearJobs jobs, const void* x, const void* gridbuf, const NearGrid& g,
-                       hipStream_t s, int shape, int kind) {
-  if (shape < 0 || shape >= kNumShapes) shape = near_default_shape(N, jobs);
-  const NearShape sh = kShapes[shape];
-  int tiles = 0;
-  for (int j = 0; j < jobs.count; ++j) {
-    jobs.job[j].tile0 = tiles;
-    tiles += (jobs.job[j].M + sh.rows - 1) / sh.rows;
+hipError_t near_launch(const std::vector<NearJob>& list, hipStream_t s, int shape, int kind) {
+  if (list.empty()) return hipSuccess;
+  if (shape < 0 || shape >= kNumShapes) shape = near_default_shape<T>(list);
+  const NearShape sh = shape_of<T>(shape);
+  for (size_t first = 0; first < list.size(); first += kMaxJobs) {
+    NearJobs jobs;
+    jobs.count = (int)std::min<size_t>(kMaxJobs, list.size() - first);
+    long long tiles = 0;
+    for (int j = 0; j < jobs.count; ++j) {
+      jobs.job[j] = list[first + j];
+      jobs.job[j].tile0 = (int)tiles;
+      tiles += (long long)((jobs.job[j].M + sh.rows - 1) / sh.rows) * ((jobs.job[j].N + sh.cols - 1) / sh.cols);
+    }
+    if (tiles == 0) continue;
+    if (tiles > INT32_MAX) return hipErrorInvalidValue;
+    jobs.total = (int)tiles;
+    launch_shape<T>(shape, kind, (unsigned)tiles, jobs, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  dim3 grid(tiles, (N + sh.cols - 1) / sh.cols);
-  switch (shape) {
-    case 0: launch_shape<T, 16, 256, 1, 8>(grid, s, kind, n, N, jobs, x, gridbuf, g); break;
-    case 1: launch_shape<T, 32, 256, 1, 8>(grid, s, kind, n, N, jobs, x, gridbuf, g); break;
-    case 2: launch_shape<T, 32, 128, 2, 8>(grid, s, kind, n, N, jobs, x, gridbuf, g); break;
-    case 3: launch_shape<T, 64, 64, 4, 8>(grid, s, kind, n, N, jobs, x, gridbuf, g); break;
-    case 4: launch_shape<T, 32, 64, 2, 8>(grid, s, kind, n, N, jobs, x, gridbuf, g); break;
-    case 5: launch_shape<T, 16, 128, 1, 8>(grid, s, kind, n, N, jobs, x, gridbuf, g); break;
-    case 6: launch_shape<T, 16, 64, 1, 8>(grid, s, kind, n, N, jobs, x, gridbuf, g); break;
-    case 7: launch_shape<T, 32, 128, 2, 16>(grid, s, kind, n, N, jobs, x, gridbuf, g); break;
-    case 8: launch_shape<T, 64, 64, 4, 16>(grid, s, kind, n, N, jobs, x, gridbuf, g); break;
-    case 9: launch_shape<T, 16, 128, 1, 16>(grid, s, kind, n, N, jobs, x, gridbuf, g); break;
-    default: launch_shape<T, 64, 128, 2, 8>(grid, s, kind, n, N, jobs, x, gridbuf, g); break;
-  }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 template <typename T>
@@ -317,10 +415,10 @@ hipError_t near_reduce_launch(const void* part, int ns, size_t len, void* y, voi
   return hipGetLastError();
 }
 
-template hipError_t near_launch<double>(int, int, NearJobs, const void*, const void*, const NearGrid&, hipStream_t,
-                                        int, int);
-template hipError_t near_launch<float>(int, int, NearJobs, const void*, const void*, const NearGrid&, hipStream_t,
-                                       int, int);
+template hipError_t near_launch<double>(const std::vector<NearJob>&, hipStream_t, int, int);
+template hipError_t near_launch<float>(const std::vector<NearJob>&, hipStream_t, int, int);
+template int near_num_shapes<double>();
+template int near_num_shapes<float>();
 template hipError_t near_reduce_launch<double>(const void*, int, size_t, void*, void*, hipStream_t);
 template hipError_t near_reduce_launch<float>(const void*, int, size_t, void*, void*, hipStream_t);
 

@@ -749,6 +749,7 @@ extern "C" fmbem_status fmbem_plan_create(const fmbem_cell_mesh* mesh, const fmb
     if (desc->near_radius[a] < 0 || desc->near_radius[a] > 3) return FMBEM_ERR_INVALID_ARG;
     if (desc->fft_shape[a] < 0) return FMBEM_ERR_INVALID_ARG;
     if (desc->fft_shape[a] > 0 && desc->fft_shape[a] < 2 * desc->grid[a] - 1) return FMBEM_ERR_INVALID_ARG;
+    if (desc->grid[a] > kMaxGridDim || desc->fft_shape[a] > 2 * kMaxGridDim) return FMBEM_ERR_UNSUPPORTED;
   }
   if (!(desc->k > 0.0) || !std::isfinite(desc->k)) return FMBEM_ERR_INVALID_ARG;
   if (desc->order < 0 || desc->order > 20) return FMBEM_ERR_INVALID_ARG;
