@@ -144,17 +144,35 @@ typedef struct {
 } fmbem_solve_info;
 
 /* Solve A x = b by restarted GMRES (Sec. 2.4, Sec. 3.5; GMRES as in Sec. 4)
- * with classical Gram-Schmidt and a second pass where the Daniel-Gragg-Kaufman-
- * Stewart criterion asks for one, Givens rotations, and (for
- * inner_precision = FMBEM_FP32) FP64 iterative refinement around FP32 inner
- * solves.  b, x: device complex128 [n_rhs][n_cells][n_dof_cell]; x holds the
- * initial guess on entry and the solution on return.  All right-hand sides
- * are iterated together.  Allocates its Krylov basis on the device for the
- * duration of the call.  Blocks until done; info (host, [n_rhs]) may be NULL.
- * Returns FMBEM_ERR_NOT_CONVERGED (x = last iterate, info filled) when some
- * right-hand side misses tol within the limits. */
+ * with classical Gram-Schmidt (a second pass per opts->orthogonalization),
+ * Givens rotations, and (for inner_precision = FMBEM_FP32) FP64 iterative
+ * refinement around FP32 inner solves.  With FP64 inner precision every
+ * restart cycle begins with the FP64 true residual, which decides convergence.
+ * b, x: device complex128 [n_rhs][n_cells][n_dof_cell]; x holds the initial
+ * guess on entry and the solution on return.  All right-hand sides are
+ * iterated together, each in its own Krylov space.  Allocates its Krylov basis
+ * on the device for the duration of the call.  Blocks until done; info (host,
+ * [n_rhs]) may be NULL.  Returns FMBEM_ERR_NOT_CONVERGED (x = last iterate,
+ * info filled) when some right-hand side misses tol within the limits;
+ * FMBEM_ERR_INVALID_ARG for bad options or a non-finite ||b||. */
 fmbem_status fmbem_solve(fmbem_plan plan, const fmbem_solve_opts* opts, int32_t n_rhs,
                          const void* b, void* x, fmbem_solve_info* info, void* hip_stream);
+
+/* Several independent solves (plans of different lattices, meshes, frequencies,
+ * right-hand-side counts and options) advanced in lockstep: in every round each
+ * unfinished problem applies its operator once, and the near-field + S2M GEMMs
+ * of all of them run as one grouped launch, as do their L2T GEMMs (Sec. 3.5,
+ * eq. (FMPBEMsystem), batched); the grid DFT / M2L stages run per plan.  Each
+ * problem follows fmbem_solve exactly (same iterates up to the rounding of the
+ * shared launches).  plans, opts, n_rhs, b, x: arrays of n (b[i], x[i] as in
+ * fmbem_solve for plan i); info: host [sum of n_rhs], problem i's entries after
+ * those of problems 0..i-1, may be NULL.  The first call for a new combination
+ * of problem sizes times the grouped launch's tile shapes.  Blocks until every
+ * problem is done.  Returns FMBEM_ERR_NOT_CONVERGED when some problem missed its
+ * tolerance (all x and info filled). */
+fmbem_status fmbem_solve_batch(int32_t n, const fmbem_plan* plans, const fmbem_solve_opts* opts,
+                               const int32_t* n_rhs, const void* const* b, void* const* x,
+                               fmbem_solve_info* info, void* hip_stream);
 
 /* Right-hand sides b = p_inc + alpha dp_inc/dn at the collocation points
  * (Sec. 2.1, eq. (bm)), device complex128 [n_rhs][n_cells][n_dof_cell].

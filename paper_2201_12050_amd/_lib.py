@@ -61,7 +61,7 @@ class SolveInfo(ct.Structure):
 
 EXPORTS = ["fmbem_plan_create", "fmbem_plan_query", "fmbem_plan_destroy", "fmbem_plan_export", "fmbem_matvec",
            "fmbem_solve", "fmbem_incident_plane_wave", "fmbem_incident_point_source", "fmbem_plan_profile",
-           "fmbem_plan_profile_read", "fmbem_status_string"]
+           "fmbem_plan_profile_read", "fmbem_status_string", "fmbem_solve_batch"]
 STAGES = tuple(f"{s}_{p}" for p in ("fp64", "fp32") for s in ("near", "reduce", "fft", "m2l", "ifft", "l2t"))
 
 _lib = None
@@ -82,14 +82,17 @@ def load():
     lib.fmbem_plan_export.argtypes = [vp, ct.c_int32, vp, ct.c_size_t]
     lib.fmbem_matvec.argtypes = [vp, ct.c_int32, ct.c_int32, vp, vp, vp, ct.c_size_t, vp]
     lib.fmbem_solve.argtypes = [vp, ct.POINTER(SolveOpts), ct.c_int32, vp, vp, ct.POINTER(SolveInfo), vp]
+    lib.fmbem_solve_batch.argtypes = [ct.c_int32, ct.POINTER(vp), ct.POINTER(SolveOpts), ct.POINTER(ct.c_int32),
+                                      ct.POINTER(vp), ct.POINTER(vp), ct.POINTER(SolveInfo), vp]
     lib.fmbem_incident_plane_wave.argtypes = [vp, ct.c_int32, ct.POINTER(ct.c_double), ct.c_double, vp, vp]
     lib.fmbem_incident_point_source.argtypes = [vp, ct.c_int32, ct.POINTER(ct.c_double), ct.c_double, vp, vp]
     lib.fmbem_plan_profile.argtypes = [vp, ct.c_uint32, ct.c_int32]
     lib.fmbem_plan_profile_read.argtypes = [vp, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)]
     lib.fmbem_status_string.argtypes = [ct.c_int32]
     lib.fmbem_status_string.restype = ct.c_char_p
-    for f in EXPORTS[:-1]:
-        getattr(lib, f).restype = ct.c_int32
+    for f in EXPORTS:
+        if f != "fmbem_status_string":
+            getattr(lib, f).restype = ct.c_int32
     _lib = lib
     return lib
 
@@ -103,6 +106,53 @@ def _stream_ptr(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return ct.c_void_p(s.cuda_stream)
+
+
+def solve_opts(tol=1e-8, restart=30, max_iters=1000, max_refinements=20, inner="fp64", inner_tol=1e-5,
+               ortho="dgks") -> SolveOpts:
+    return SolveOpts(tol, restart, max_iters, max_refinements, _precision(inner), inner_tol, ORTHO[ortho])
+
+
+def _info_dicts(info):
+    return [dict(iterations=i.iterations, refinements=i.refinements, rel_residual=i.rel_residual) for i in info]
+
+
+def solve_batch(problems, stream=None, raise_on_not_converged=True):
+    """Solve several independent problems in lockstep with grouped launches.
+
+    problems: list of (plan, b, x or None, options dict for solve_opts).  Returns the
+    list of (x, infos) in the same order."""
+    import torch
+    n = len(problems)
+    if n == 0:
+        return []
+    plans = (ct.c_void_p * n)()
+    opts = (SolveOpts * n)()
+    nr = (ct.c_int32 * n)()
+    bp = (ct.c_void_p * n)()
+    xp = (ct.c_void_p * n)()
+    xs = []
+    for i, (plan, b, x, kw) in enumerate(problems):
+        if b.dtype != torch.complex128 or not b.is_cuda or not b.is_contiguous():
+            raise ValueError("b must be a contiguous complex128 CUDA tensor")
+        if x is None:
+            x = torch.zeros_like(b)
+        plans[i] = plan._h
+        opts[i] = solve_opts(**(kw or {}))
+        nr[i] = b.numel() // plan.n_dof
+        bp[i] = b.data_ptr()
+        xp[i] = x.data_ptr()
+        xs.append(x)
+    info = (SolveInfo * sum(nr))()
+    lib = load()
+    st = lib.fmbem_solve_batch(n, plans, opts, nr, bp, xp, info, _stream_ptr(stream))
+    if st != 0 and (st != 5 or raise_on_not_converged):
+        check(st, "fmbem_solve_batch")
+    out, off = [], 0
+    for i in range(n):
+        out.append((xs[i], _info_dicts(info[off:off + nr[i]])))
+        off += nr[i]
+    return out
 
 
 def _precision(p) -> int:
@@ -233,7 +283,7 @@ class Plan:
         R = b.numel() // self.n_dof
         if x is None:
             x = torch.zeros_like(b)
-        o = SolveOpts(tol, restart, max_iters, max_refinements, _precision(inner), inner_tol, ORTHO[ortho])
+        o = solve_opts(tol, restart, max_iters, max_refinements, inner, inner_tol, ortho)
         info = (SolveInfo * R)()
         st = self._lib.fmbem_solve(self._h, ct.byref(o), R, ct.c_void_p(b.data_ptr()), ct.c_void_p(x.data_ptr()),
                                    info, _stream_ptr(stream))

@@ -97,6 +97,19 @@ size_t matvec_workspace_bytes_per_rhs(const Plan& P, int precision);
 hipError_t matvec_launch(const Plan& P, int precision, int R, const void* x, void* y, void* ws,
                          hipStream_t s, void* y64 = nullptr);
 
+// one operator application of a group (see matvec_group)
+struct GroupApply {
+  const Plan* P;
+  int R;
+  const void* x;   // [R][C][n] in the application's precision
+  void* y;         // [R][C][n] in that precision (unused when y64 is set)
+  void* ws;        // R * matvec_workspace_bytes_per_rhs(P, precision), 256-byte aligned
+  void* y64;       // FP32 only, optional: complex128 output
+};
+// Applications of several plans in one precision, their near-field + S2M and L2T GEMMs in
+// shared grouped launches; stream-ordered.  tune: autotune the combined tile shape.
+hipError_t matvec_group(int precision, const std::vector<GroupApply>& g, hipStream_t s, bool tune);
+
 // ---------------------------------------------------------------------------
 // kernels shared between translation units
 // ---------------------------------------------------------------------------

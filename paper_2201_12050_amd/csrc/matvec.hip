@@ -98,6 +98,20 @@ int tuned_shape(int kind, const std::vector<NearJob>& jobs, hipStream_t s) {
   return best;
 }
 
+// the tuned shape of this job-list signature if one was measured, else -1 (default shape)
+template <typename T>
+int cached_shape(int kind, const std::vector<NearJob>& jobs) {
+  std::vector<long long> key{kind, (long long)sizeof(T)};
+  for (const NearJob& j : jobs) {
+    key.push_back(j.M);
+    key.push_back(j.K);
+    key.push_back(j.N);
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find(key);
+  return it == g_tuned.end() ? -1 : it->second;
+}
+
 // workspace layout: [padded grid B x R x p][near partials n_near x R x C x n]
 template <typename T>
 static char* near_partials(const Plan& P, int R, void* ws) {
@@ -179,6 +193,43 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
   }
   prof_end(P, 5 + 6 * prec, ev, s);
   return e;
+}
+
+// Operator applications of several plans in one sequence: the near field + S2M jobs of all
+// of them share one grouped launch and so do the L2T jobs; the DFT / M2L / inverse DFT
+// stages run per plan.  tune: autotune the tile shape of the combined job list (blocks the
+// host once per composition); otherwise a cached shape of that composition or the default.
+template <typename T>
+static hipError_t matvec_group_t(const std::vector<GroupApply>& g, hipStream_t s, bool tune) {
+  const int prec = sizeof(T) == 8 ? 0 : 1;
+  std::vector<NearJob> jobs;
+  for (const GroupApply& a : g) near_s2m_jobs<T>(*a.P, a.R, a.x, a.ws, jobs);
+  int shape = tune ? tuned_shape<T>(0, jobs, s) : cached_shape<T>(0, jobs);
+  hipError_t e = near_launch<T>(jobs, s, shape, 0);
+  if (e != hipSuccess) return e;
+  std::vector<NearJob> l2t;
+  for (const GroupApply& a : g) {
+    const Plan& P = *a.P;
+    if (P.n_far == 0) {
+      e = near_reduce_launch<T>(near_partials<T>(P, a.R, a.ws), P.n_near, (size_t)a.R * P.C * P.n, a.y, a.y64, s);
+      if (e != hipSuccess) return e;
+      continue;
+    }
+    if ((e = grid_dft_launch<T>(a.ws, a.R * P.p, P.grid, P.fft, false, true, s)) != hipSuccess) return e;
+    if ((e = m2l_launch<T>(P.Lam[prec], a.ws, P.B, a.R, P.p, s)) != hipSuccess) return e;
+    if ((e = grid_dft_launch<T>(a.ws, a.R * P.p, P.grid, P.fft, true, true, s)) != hipSuccess) return e;
+    l2t.push_back(l2t_job<T>(P, a.R, a.ws, a.y, a.y64));
+  }
+  if (l2t.empty()) return hipSuccess;
+  shape = tune ? tuned_shape<T>(1, l2t, s) : cached_shape<T>(1, l2t);
+  return near_launch<T>(l2t, s, shape, 1);
+}
+
+hipError_t matvec_group(int precision, const std::vector<GroupApply>& g, hipStream_t s, bool tune) {
+  if (g.empty()) return hipSuccess;
+  if (g.size() == 1)
+    return matvec_launch(*g[0].P, precision, g[0].R, g[0].x, g[0].y, g[0].ws, s, g[0].y64);
+  return precision == FMBEM_FP64 ? matvec_group_t<double>(g, s, tune) : matvec_group_t<float>(g, s, tune);
 }
 
 hipError_t matvec_launch(const Plan& P, int precision, int R, const void* x, void* y, void* ws, hipStream_t s,

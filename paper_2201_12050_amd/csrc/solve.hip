@@ -14,6 +14,7 @@
 // host; a step queued after convergence is discarded by the per-RHS freeze.
 #include <algorithm>
 #include <cmath>
+#include <memory>
 #include <vector>
 
 #include "common.hpp"
@@ -303,6 +304,12 @@ __global__ __launch_bounds__(256) void backsolve_kernel(int m, int jcur, const d
   }
 }
 
+// out[r] = hn[r * hstride].x (residual norms into mapped host memory)
+__global__ void norm_out_kernel(const double2* __restrict__ hn, int hstride, int R, double* __restrict__ out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < R) out[r] = hn[(size_t)r * hstride].x;
+}
+
 // g = [beta, 0, ...], jdone = -1 (beta from the .x of hn); beta <= tol freezes at 0
 __global__ void gmres_init_kernel(int R, int m, const double2* __restrict__ beta, int hstride,
                                   const double* __restrict__ tol, double2* __restrict__ g, int* __restrict__ jdone,
@@ -317,62 +324,111 @@ __global__ void gmres_init_kernel(int R, int m, const double2* __restrict__ beta
   res[r] = b;
 }
 
-struct Solver {
+// One linear system set (a plan and R right-hand sides) advanced one operator application
+// per round.  A round of a group: pre() of every member (kernels that precede the
+// application and the application request), the group's applications (one grouped launch
+// sequence per precision), post() of every member (Gram-Schmidt, Givens, residuals), an
+// event; then the host reads the previous round's results (process()) while this round
+// runs.  Arnoldi steps continue speculatively on the one-round-late convergence flags (a
+// step queued after convergence is frozen on the device and discarded); true residuals
+// make the member wait one round for the host's decision.
+struct Member {
   const Plan& P;
   hipStream_t s;
   int R, m;
-  int ortho = 0;  // FMBEM_ORTHO_*
-  size_t N;       // DOFs per RHS
-  size_t vlen;    // R * N
+  int ortho = 0;   // FMBEM_ORTHO_*
+  int ip = 0;      // inner precision
+  double tol = 0, inner_tol = 0;
+  int max_its = 0, max_ref = 0;
+  const double2* b = nullptr;
+  double2* x = nullptr;
+  size_t N;        // DOFs per RHS
+  size_t vlen;     // R * N
   int nblk;
+  int hstride;
+  int nb;          // workgroups of the multi-axpy kernel (and of its norm partials)
   std::vector<void*> mem;
-  double2 *V = nullptr, *w = nullptr, *r = nullptr, *d = nullptr, *t = nullptr, *rin = nullptr;
-  float2 *x32 = nullptr, *y32 = nullptr;
+  double2 *V = nullptr, *r = nullptr, *d = nullptr, *t = nullptr, *rin = nullptr;
+  float2* x32 = nullptr;
   void* ws = nullptr;
   double2 *part = nullptr, *hc = nullptr, *hn = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr,
           *y = nullptr;
-  double *res = nullptr, *tol = nullptr, *npart = nullptr;
+  double *res = nullptr, *tolv = nullptr, *npart = nullptr;
   int* jdone = nullptr;
   int* reorth = nullptr;  // per-RHS second Gram-Schmidt pass flag
-  // freeze flags of two steps in flight, in mapped pinned host memory written by the device
+  // per round slot: freeze flags and residual norms written by the device into mapped host memory
   int* hjd[2] = {nullptr, nullptr};
   int* djd[2] = {nullptr, nullptr};
-  hipEvent_t ev[2] = {nullptr, nullptr};
-  int hstride;
-  int nb;  // workgroups of the multi-axpy kernel (and of its norm partials)
+  double* hres[2] = {nullptr, nullptr};
+  double* dres[2] = {nullptr, nullptr};
+  double* htol = nullptr;  // pinned staging of per-RHS tolerances
 
-  Solver(const Plan& p_, hipStream_t s_, int R_, int m_) : P(p_), s(s_), R(R_), m(m_) {
+  // state
+  enum Phase { RUN_TRUE, START_INNER, RUN_RESTART, RUN_ARN, CLOSE, WAIT, DONE };
+  enum Kind { K_NONE, K_TRUE, K_RESTART, K_ARN };
+  struct Rec {
+    int kind = K_NONE, j = 0, epoch = 0;
+  };
+  Rec rec[2];
+  int phase = RUN_TRUE;
+  int after_close = RUN_TRUE;
+  int gm_prec = 0;                 // precision of the current GMRES
+  const double2* gm_rhs = nullptr;
+  double2* gm_sol = nullptr;
+  int j = 0;                       // Arnoldi steps queued in the current cycle
+  int epoch = 0;
+  int its = 0, refs = 0;
+  bool ok = false;
+  hipError_t err = hipSuccess;
+  std::vector<double> bn, rel;
+  // this round's application
+  bool req = false;
+  int req_prec = 0;
+  const void* req_in = nullptr;
+  double2* req_out = nullptr;
+
+  Member(const Plan& p_, hipStream_t s_, int R_, int m_) : P(p_), s(s_), R(R_), m(m_) {
     N = (size_t)P.n * P.C;
     vlen = (size_t)R * N;
     nblk = (int)((N + kDotThreads * kDotEl - 1) / (kDotThreads * kDotEl));
     hstride = m + 2;
     nb = (int)std::min<size_t>((N + 255) / 256, 2048);
+    bn.assign(R, 0.0);
+    rel.assign(R, 0.0);
   }
-  ~Solver() {
+  ~Member() {
     for (void* q : mem) hipFree(q);
     for (int i = 0; i < 2; ++i) {
       if (hjd[i]) hipHostFree(hjd[i]);
-      if (ev[i]) hipEventDestroy(ev[i]);
+      if (hres[i]) hipHostFree(hres[i]);
     }
+    if (htol) hipHostFree(htol);
   }
   hipError_t alloc(void** q, size_t bytes) {
     hipError_t e = hipMalloc(q, std::max<size_t>(bytes, 256));
     if (e == hipSuccess) mem.push_back(*q);
     return e;
   }
+  // device bytes a member of this shape allocates (the engine's admission unit)
+  static size_t footprint(const Plan& P, int R, int m, bool need32) {
+    const size_t N = (size_t)P.n * P.C, vlen = (size_t)R * N;
+    const size_t nblk = (N + kDotThreads * kDotEl - 1) / (kDotThreads * kDotEl);
+    size_t b = (size_t)(m + 1) * vlen * 16 + 4 * vlen * 16 + (need32 ? vlen * 8 : 0);
+    b += (size_t)R * std::max(matvec_workspace_bytes_per_rhs(P, 0), need32 ? matvec_workspace_bytes_per_rhs(P, 1) : 0);
+    b += (size_t)R * (m + 1) * nblk * 16 + (size_t)R * (m + 2) * 16 * 3 + (size_t)R * (m + 1) * m * 16;
+    b += (size_t)R * (3 * m + 1) * 16 + (size_t)R * 2048 * 8 + (size_t)R * 32 + 18 * 256;
+    return b;
+  }
   hipError_t setup(bool need32) {
     hipError_t e;
     if ((e = alloc((void**)&V, (size_t)(m + 1) * vlen * sizeof(double2)))) return e;
-    if ((e = alloc((void**)&w, vlen * sizeof(double2)))) return e;
     if ((e = alloc((void**)&r, vlen * sizeof(double2)))) return e;
     if ((e = alloc((void**)&d, vlen * sizeof(double2)))) return e;
     if ((e = alloc((void**)&t, vlen * sizeof(double2)))) return e;
     if ((e = alloc((void**)&rin, vlen * sizeof(double2)))) return e;
-    if (need32) {
-      if ((e = alloc((void**)&x32, vlen * sizeof(float2)))) return e;
-      if ((e = alloc((void**)&y32, vlen * sizeof(float2)))) return e;
-    }
-    const size_t wsb = (size_t)R * std::max(matvec_workspace_bytes_per_rhs(P, 0), matvec_workspace_bytes_per_rhs(P, 1));
+    if (need32 && (e = alloc((void**)&x32, vlen * sizeof(float2)))) return e;
+    const size_t wsb = (size_t)R * std::max(matvec_workspace_bytes_per_rhs(P, 0),
+                                            need32 ? matvec_workspace_bytes_per_rhs(P, 1) : 0);
     if ((e = alloc(&ws, wsb))) return e;
     if ((e = alloc((void**)&part, (size_t)R * (m + 1) * nblk * sizeof(double2)))) return e;
     if ((e = alloc((void**)&hc, (size_t)R * hstride * sizeof(double2)))) return e;
@@ -383,30 +439,22 @@ struct Solver {
     if ((e = alloc((void**)&g, (size_t)R * (m + 1) * sizeof(double2)))) return e;
     if ((e = alloc((void**)&y, (size_t)R * hstride * sizeof(double2)))) return e;
     if ((e = alloc((void**)&res, R * sizeof(double)))) return e;
-    if ((e = alloc((void**)&tol, R * sizeof(double)))) return e;
+    if ((e = alloc((void**)&tolv, R * sizeof(double)))) return e;
     if ((e = alloc((void**)&jdone, R * sizeof(int)))) return e;
     if ((e = alloc((void**)&npart, (size_t)R * nb * sizeof(double)))) return e;
     if ((e = alloc((void**)&reorth, R * sizeof(int)))) return e;
     for (int i = 0; i < 2; ++i) {
-      if ((e = hipHostMalloc((void**)&hjd[i], R * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent)))
-        return e;
+      if ((e = hipHostMalloc((void**)&hjd[i], R * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent))) return e;
       if ((e = hipHostGetDevicePointer((void**)&djd[i], hjd[i], 0))) return e;
-      if ((e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming))) return e;
+      if ((e = hipHostMalloc((void**)&hres[i], R * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent)))
+        return e;
+      if ((e = hipHostGetDevicePointer((void**)&dres[i], hres[i], 0))) return e;
     }
+    if ((e = hipHostMalloc((void**)&htol, R * sizeof(double), hipHostMallocDefault))) return e;
     return hipSuccess;
   }
   dim3 vgrid() const { return dim3((unsigned)nb, R); }
   unsigned lgrid(size_t len) const { return (unsigned)std::min<size_t>((len + 255) / 256, 4096); }
-  // out = A in (FP64 vectors); prec selects the operator copy; in32 (optional) = in already cast
-  hipError_t apply(int prec, const double2* in, double2* out, const float2* in32 = nullptr) {
-    if (prec == FMBEM_FP64) return matvec_launch(P, FMBEM_FP64, R, in, out, ws, s);
-    if (!in32) {
-      hipLaunchKernelGGL(to32_kernel, dim3(lgrid(vlen)), dim3(256), 0, s, in, x32, vlen);
-      in32 = x32;
-    }
-    // the FP32 operator writes its result directly as FP64 into out
-    return matvec_launch(P, FMBEM_FP32, R, in32, y32, ws, s, out);
-  }
   // dots of the first J basis vectors with vec -> h (mode 0: h = dots; mode 3: h2 = dots, h += dots);
   // with flag, only for the RHS whose flag is set
   void mdot(const double2* Vb, int J, const double2* vec, double2* h, int mode, double2* h2 = nullptr,
@@ -430,71 +478,170 @@ struct Solver {
                        vec, N, J, sgn, with_norm ? npart : nullptr, flag);
   }
 
-  // Restarted GMRES on A_prec sol = rhs; sol is updated in place.  Stops per RHS
-  // when the residual estimate drops below tol_abs[r]; its counts operator applications
-  // of the Arnoldi steps.
-  hipError_t gmres(int prec, const double2* rhs, double2* sol, const std::vector<double>& tol_abs, int max_its,
-                   int& its) {
-    hipError_t e = hipMemcpyAsync(tol, tol_abs.data(), R * sizeof(double), hipMemcpyHostToDevice, s);
-    if (e) return e;
-    while (true) {
-      // r = rhs - A sol, beta = ||r||, v_0 = r / beta
-      if ((e = apply(prec, sol, t))) return e;
-      hipLaunchKernelGGL(sub_kernel, dim3(lgrid(vlen)), dim3(256), 0, s, rhs, t, r, vlen);
-      norm(r, hn);
-      hipLaunchKernelGGL(gmres_init_kernel, dim3((R + 63) / 64), dim3(64), 0, s, R, m, hn, hstride, tol, g, jdone,
-                         djd[0], res);
-      hipLaunchKernelGGL(scale_kernel, vgrid(), dim3(256), 0, s, r, hn, hstride, V, prec == FMBEM_FP32 ? x32 : nullptr,
-                         N);
-      if ((e = hipStreamSynchronize(s))) return e;
-      bool all = true;
-      for (int q = 0; q < R; ++q)
-        if (hjd[0][q] < 0) all = false;
-      if (all || its >= max_its) return hipSuccess;
-      int j = 0;
-      int pending = -1;  // step whose freeze flags are in flight
-      bool done = false;
-      for (; j < m && its < max_its; ++j) {
-        double2* vj = V + (size_t)j * vlen;
-        double2* wv = V + (size_t)(j + 1) * vlen;  // w = A v_j is built in the slot of v_{j+1}
-        // the FP32 copy of v_j was written by the scale kernel that produced it
-        if ((e = apply(prec, vj, wv, prec == FMBEM_FP32 ? x32 : nullptr))) return e;
+  // ||b|| per RHS (queued; read after the stream synchronises)
+  void start() {
+    norm(b, hn);
+    hipLaunchKernelGGL(norm_out_kernel, dim3((R + 63) / 64), dim3(64), 0, s, hn, hstride, R, dres[0]);
+  }
+  hipError_t started() {
+    for (int q = 0; q < R; ++q) {
+      bn[q] = hres[0][q];
+      if (!std::isfinite(bn[q])) return hipErrorInvalidValue;
+    }
+    if (ip == FMBEM_FP64) {
+      gm_prec = FMBEM_FP64;
+      gm_rhs = b;
+      gm_sol = x;
+      for (int q = 0; q < R; ++q) htol[q] = tol * bn[q];
+      hipError_t e = hipMemcpyAsync(tolv, htol, R * sizeof(double), hipMemcpyHostToDevice, s);
+      if (e) return e;
+    } else {
+      gm_prec = FMBEM_FP32;
+      gm_rhs = rin;
+      gm_sol = d;
+    }
+    phase = RUN_TRUE;
+    return hipSuccess;
+  }
+  // end of a GMRES cycle: sol += V y with y = H^-1 g over each RHS's own step count
+  void close_cycle() {
+    hipLaunchKernelGGL(backsolve_kernel, dim3(R), dim3(256), 0, s, m, j, H, g, jdone, y, hstride);
+    maxpy(V, y, gm_sol, j, 1.0);
+    ++epoch;
+  }
+  // cycle start on r (norm in hn): g, freeze flags, v_0 = r / beta (and its FP32 copy)
+  void init_cycle(int slot) {
+    hipLaunchKernelGGL(gmres_init_kernel, dim3((R + 63) / 64), dim3(64), 0, s, R, m, hn, hstride, tolv, g, jdone,
+                       djd[slot], res);
+    hipLaunchKernelGGL(scale_kernel, vgrid(), dim3(256), 0, s, r, hn, hstride, V,
+                       gm_prec == FMBEM_FP32 ? x32 : nullptr, N);
+    j = 0;
+  }
+
+  void pre(int slot) {
+    req = false;
+    rec[slot] = Rec{};
+    if (phase == DONE || phase == WAIT) return;
+    if (phase == CLOSE) {
+      close_cycle();
+      if (after_close == RUN_TRUE && ip == FMBEM_FP32)
+        hipLaunchKernelGGL(add_kernel, dim3(lgrid(vlen)), dim3(256), 0, s, x, d, vlen);
+      phase = after_close;
+    }
+    if (phase == START_INNER) {
+      // inner system A32 d = r from d = 0: the residual norm of the true-residual step is beta
+      hipLaunchKernelGGL(zero_kernel, dim3(lgrid(vlen)), dim3(256), 0, s, d, vlen);
+      hipLaunchKernelGGL(copy_kernel, dim3(lgrid(vlen)), dim3(256), 0, s, rin, r, vlen);
+      init_cycle(slot);
+      phase = RUN_ARN;
+    }
+    switch (phase) {
+      case RUN_TRUE:
+        req = true;
+        req_prec = FMBEM_FP64;
+        req_in = x;
+        req_out = t;
+        rec[slot] = Rec{K_TRUE, 0, epoch};
+        break;
+      case RUN_RESTART:
+        hipLaunchKernelGGL(to32_kernel, dim3(lgrid(vlen)), dim3(256), 0, s, d, x32, vlen);
+        req = true;
+        req_prec = FMBEM_FP32;
+        req_in = x32;
+        req_out = t;
+        rec[slot] = Rec{K_RESTART, 0, epoch};
+        break;
+      case RUN_ARN:
+        // the FP32 copy of v_j was written by the kernel that produced v_j
+        req = true;
+        req_prec = gm_prec;
+        req_in = gm_prec == FMBEM_FP32 ? (const void*)x32 : (const void*)(V + (size_t)j * vlen);
+        req_out = V + (size_t)(j + 1) * vlen;  // w = A v_j is built in the slot of v_{j+1}
+        rec[slot] = Rec{K_ARN, j, epoch};
+        break;
+      default:
+        break;
+    }
+  }
+
+  void post(int slot) {
+    switch (rec[slot].kind) {
+      case K_TRUE:
+        hipLaunchKernelGGL(sub_kernel, dim3(lgrid(vlen)), dim3(256), 0, s, b, t, r, vlen);
+        norm(r, hn);
+        hipLaunchKernelGGL(norm_out_kernel, dim3((R + 63) / 64), dim3(64), 0, s, hn, hstride, R, dres[slot]);
+        if (ip == FMBEM_FP64) init_cycle(slot);  // the true residual starts the next cycle
+        phase = WAIT;
+        break;
+      case K_RESTART:
+        hipLaunchKernelGGL(sub_kernel, dim3(lgrid(vlen)), dim3(256), 0, s, rin, t, r, vlen);
+        norm(r, hn);
+        init_cycle(slot);
+        phase = RUN_ARN;
+        break;
+      case K_ARN: {
+        double2* wv = V + (size_t)(j + 1) * vlen;
         // Gram-Schmidt: h = V^H w (and ||w||^2 as the last dot), w -= V h (with |w|^2 partials);
-        // second pass h2 = V^H w, w -= V h2, h += h2 only where the DGKS criterion asks for it
+        // second pass h2 = V^H w, w -= V h2, h += h2 where the DGKS criterion (or the mode) asks for it
         mdot(V, j + 2, wv, hc, 0);
         maxpy(V, hc, wv, j + 1, -1.0, true);
-        hipLaunchKernelGGL(reorth_check_kernel, dim3(R), dim3(256), 0, s, ortho, nb, npart, hc, hstride, j, jdone,
-                           reorth);
-        mdot(V, j + 1, wv, hc, 3, y, reorth);
-        maxpy(V, y, wv, j + 1, -1.0, true, reorth);
-        const int slot = j & 1;
-        hipLaunchKernelGGL(norm_givens_kernel, dim3(R), dim3(256), 0, s, npart, nb, m, j, hc, hstride, hn, H, cs, sn,
-                           g, res, jdone, djd[slot], tol);
-        hipLaunchKernelGGL(scale_kernel, vgrid(), dim3(256), 0, s, wv, hn, hstride, wv,
-                           prec == FMBEM_FP32 ? x32 : nullptr, N);
-        ++its;
-        if ((e = hipEventRecord(ev[slot], s))) return e;
-        // check the previous step while this one runs
-        if (pending >= 0) {
-          if ((e = hipEventSynchronize(ev[pending & 1]))) return e;
-          done = true;
-          for (int q = 0; q < R; ++q)
-            if (hjd[pending & 1][q] < 0) done = false;
-          if (done) {
-            ++j;
-            break;
-          }
+        if (ortho != FMBEM_ORTHO_ONCE) {
+          hipLaunchKernelGGL(reorth_check_kernel, dim3(R), dim3(256), 0, s, ortho, nb, npart, hc, hstride, j, jdone,
+                             reorth);
+          mdot(V, j + 1, wv, hc, 3, y, reorth);
+          maxpy(V, y, wv, j + 1, -1.0, true, reorth);
         }
-        pending = j;
+        hipLaunchKernelGGL(norm_givens_kernel, dim3(R), dim3(256), 0, s, npart, nb, m, j, hc, hstride, hn, H, cs, sn,
+                           g, res, jdone, djd[slot], tolv);
+        hipLaunchKernelGGL(scale_kernel, vgrid(), dim3(256), 0, s, wv, hn, hstride, wv,
+                           gm_prec == FMBEM_FP32 ? x32 : nullptr, N);
+        ++its;
+        ++j;
+        // a full cycle (or the iteration budget) ends here; what follows needs this step's flags
+        if (j == m || its >= max_its) phase = WAIT;
+        break;
       }
-      if (!done && pending >= 0) {
-        // last step of the cycle: nothing left to overlap with
-        if ((e = hipEventSynchronize(ev[pending & 1]))) return e;
+      default:
+        break;
+    }
+  }
+
+  // host: results of the step queued in round slot (its event has completed)
+  void process(int slot) {
+    const Rec rc = rec[slot];
+    if (rc.kind == K_NONE || phase == DONE || rc.epoch != epoch) return;
+    if (rc.kind == K_TRUE) {
+      ok = true;
+      for (int q = 0; q < R; ++q) {
+        rel[q] = bn[q] > 0 ? hres[slot][q] / bn[q] : 0.0;
+        if (!(rel[q] <= tol)) ok = false;
       }
-      // sol += V y
-      hipLaunchKernelGGL(backsolve_kernel, dim3(R), dim3(256), 0, s, m, j, H, g, jdone, y, hstride);
-      maxpy(V, y, sol, j, 1.0);  // y is zero beyond each RHS's own step count
-      if ((e = hipGetLastError())) return e;
+      if (ok || its >= max_its || (ip == FMBEM_FP32 && refs >= max_ref)) {
+        phase = DONE;
+        return;
+      }
+      if (ip == FMBEM_FP64) {
+        phase = RUN_ARN;  // the cycle was started by the true-residual step
+      } else {
+        // inner tolerance: inner_tol * ||r||, and not below what the outer test needs
+        for (int q = 0; q < R; ++q) htol[q] = std::max(inner_tol * rel[q] * bn[q], 0.5 * tol * bn[q]);
+        hipError_t e = hipMemcpyAsync(tolv, htol, R * sizeof(double), hipMemcpyHostToDevice, s);
+        if (e) err = e;
+        ++refs;
+        phase = START_INNER;
+      }
+      return;
+    }
+    // K_RESTART (flags of the cycle start) or K_ARN (flags after step rc.j)
+    bool all = true;
+    for (int q = 0; q < R; ++q)
+      if (hjd[slot][q] < 0) all = false;
+    const bool last = rc.kind == K_ARN && (rc.j + 1 == m || its >= max_its) && rc.j + 1 == j;
+    if (all || last) {
+      // close the cycle; in FP32 mode the inner solve ends when it converged or the budget is spent
+      phase = CLOSE;
+      after_close = (ip == FMBEM_FP64 || all || its >= max_its) ? RUN_TRUE : RUN_RESTART;
+      if (rc.kind == K_ARN && !all) j = rc.j + 1;  // steps of this cycle (all of them were processed)
     }
   }
 };
@@ -502,6 +649,101 @@ struct Solver {
 static fmbem_status st_of(hipError_t e) {
   if (e == hipSuccess) return FMBEM_OK;
   return e == hipErrorOutOfMemory ? FMBEM_ERR_OUT_OF_MEMORY : FMBEM_ERR_DEVICE;
+}
+
+// validated solve options (defaults filled in)
+struct SolveCfg {
+  double tol, inner_tol;
+  int m, max_its, max_ref, ip, ortho;
+};
+static fmbem_status solve_cfg(const Plan& P, const fmbem_solve_opts* opts, int n_rhs, SolveCfg& c) {
+  if (!opts || n_rhs < 1) return FMBEM_ERR_INVALID_ARG;
+  if (!(opts->tol > 0.0) || !std::isfinite(opts->tol)) return FMBEM_ERR_INVALID_ARG;
+  c.tol = opts->tol;
+  c.m = opts->restart == 0 ? 30 : opts->restart;
+  if (c.m < 1 || c.m > kMaxRestart) return FMBEM_ERR_INVALID_ARG;
+  c.max_its = opts->max_iters == 0 ? 1000 : opts->max_iters;
+  c.max_ref = opts->max_refinements == 0 ? 20 : opts->max_refinements;
+  c.inner_tol = opts->inner_tol == 0.0 ? 1e-5 : opts->inner_tol;
+  if (c.max_its < 1 || c.max_ref < 1 || !(c.inner_tol > 0.0) || c.inner_tol >= 1.0) return FMBEM_ERR_INVALID_ARG;
+  c.ip = opts->inner_precision;
+  if (c.ip != FMBEM_FP64 && c.ip != FMBEM_FP32) return FMBEM_ERR_INVALID_ARG;
+  c.ortho = opts->orthogonalization;
+  if (c.ortho < FMBEM_ORTHO_DGKS || c.ortho > FMBEM_ORTHO_ONCE) return FMBEM_ERR_INVALID_ARG;
+  if (!(P.precisions & 1u)) return FMBEM_ERR_UNSUPPORTED;  // the true residual needs the FP64 operator
+  if (c.ip == FMBEM_FP32 && !(P.precisions & 2u)) return FMBEM_ERR_UNSUPPORTED;
+  if ((size_t)n_rhs * P.C > (size_t)INT32_MAX / 2) return FMBEM_ERR_UNSUPPORTED;
+  return FMBEM_OK;
+}
+
+static void configure(Member& mb, const SolveCfg& c, const void* b, void* x) {
+  mb.ortho = c.ortho;
+  mb.ip = c.ip;
+  mb.tol = c.tol;
+  mb.inner_tol = c.inner_tol;
+  mb.max_its = c.max_its;
+  mb.max_ref = c.max_ref;
+  mb.b = reinterpret_cast<const double2*>(b);
+  mb.x = reinterpret_cast<double2*>(x);
+}
+
+// One round over the members (see Member); t counts rounds.
+static hipError_t run_round(const std::vector<Member*>& ms, long long t, hipStream_t s, hipEvent_t ev[2], bool tune) {
+  const int slot = (int)(t & 1);
+  std::vector<GroupApply> g64, g32;
+  for (Member* mb : ms) {
+    mb->pre(slot);
+    if (!mb->req) continue;
+    const bool f32 = mb->req_prec == FMBEM_FP32;
+    GroupApply a{&mb->P, mb->R, mb->req_in, f32 ? nullptr : (void*)mb->req_out, mb->ws,
+                 f32 ? (void*)mb->req_out : nullptr};
+    (f32 ? g32 : g64).push_back(a);
+  }
+  hipError_t e = matvec_group(FMBEM_FP64, g64, s, tune);
+  if (!e) e = matvec_group(FMBEM_FP32, g32, s, tune);
+  if (e) return e;
+  for (Member* mb : ms) mb->post(slot);
+  if ((e = hipEventRecord(ev[slot], s))) return e;
+  if (t > 0) {
+    if ((e = hipEventSynchronize(ev[slot ^ 1]))) return e;
+    for (Member* mb : ms) {
+      mb->process(slot ^ 1);
+      if (mb->err) return mb->err;
+    }
+  }
+  return hipSuccess;
+}
+
+// Solve every member to completion in lockstep rounds.
+static hipError_t run_group(const std::vector<Member*>& ms, hipStream_t s, bool tune) {
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < 2 && !e; ++i) e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+  if (!e) {
+    for (Member* mb : ms) mb->start();
+    e = hipStreamSynchronize(s);
+    for (Member* mb : ms)
+      if (!e) e = mb->started();
+  }
+  for (long long t = 0; !e; ++t) {
+    bool live = false;
+    for (Member* mb : ms)
+      if (mb->phase != Member::DONE) live = true;
+    if (!live) break;
+    e = run_round(ms, t, s, ev, tune);
+  }
+  if (!e) e = hipStreamSynchronize(s);
+  for (int i = 0; i < 2; ++i)
+    if (ev[i]) hipEventDestroy(ev[i]);
+  return e;
+}
+
+static void fill_info(const Member& mb, fmbem_solve_info* info) {
+  for (int q = 0; q < mb.R; ++q) {
+    info[q].iterations = mb.its;
+    info[q].refinements = mb.refs;
+    info[q].rel_residual = mb.rel[q];
+  }
 }
 
 }  // namespace fmbem
@@ -512,89 +754,50 @@ extern "C" fmbem_status fmbem_solve(fmbem_plan plan, const fmbem_solve_opts* opt
                                     void* x, fmbem_solve_info* info, void* hip_stream) {
   if (!plan || !opts || !b || !x || n_rhs < 1) return FMBEM_ERR_INVALID_ARG;
   const Plan& P = *reinterpret_cast<Plan*>(plan);
-  if (!(opts->tol > 0.0) || !std::isfinite(opts->tol)) return FMBEM_ERR_INVALID_ARG;
-  const int m = opts->restart == 0 ? 30 : opts->restart;
-  if (m < 1 || m > 200) return FMBEM_ERR_INVALID_ARG;
-  const int max_its = opts->max_iters == 0 ? 1000 : opts->max_iters;
-  const int max_ref = opts->max_refinements == 0 ? 20 : opts->max_refinements;
-  const double inner_tol = opts->inner_tol == 0.0 ? 1e-5 : opts->inner_tol;
-  if (max_its < 1 || max_ref < 1 || !(inner_tol > 0.0) || inner_tol >= 1.0) return FMBEM_ERR_INVALID_ARG;
-  const int ip = opts->inner_precision;
-  if (ip != FMBEM_FP64 && ip != FMBEM_FP32) return FMBEM_ERR_INVALID_ARG;
-  if (!(P.precisions & 1u)) return FMBEM_ERR_UNSUPPORTED;  // the true residual needs the FP64 operator
-  if (ip == FMBEM_FP32 && !(P.precisions & 2u)) return FMBEM_ERR_UNSUPPORTED;
-  if ((size_t)n_rhs * P.C > (size_t)INT32_MAX / 2) return FMBEM_ERR_UNSUPPORTED;
-  if (opts->orthogonalization < FMBEM_ORTHO_DGKS || opts->orthogonalization > FMBEM_ORTHO_ONCE)
-    return FMBEM_ERR_INVALID_ARG;
+  SolveCfg c;
+  fmbem_status st = solve_cfg(P, opts, n_rhs, c);
+  if (st != FMBEM_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-  Solver S(P, s, n_rhs, m);
-  S.ortho = opts->orthogonalization;
-  hipError_t e = S.setup(ip == FMBEM_FP32);
+  Member mb(P, s, n_rhs, c.m);
+  configure(mb, c, b, x);
+  hipError_t e = mb.setup(c.ip == FMBEM_FP32);
   if (e) return st_of(e);
-  const int R = n_rhs;
-  const double2* bb = reinterpret_cast<const double2*>(b);
-  double2* xx = reinterpret_cast<double2*>(x);
-  // ||b||
-  std::vector<double2> hb(R * S.hstride);
-  S.norm(bb, S.hn);
-  e = hipMemcpyAsync(hb.data(), S.hn, R * S.hstride * sizeof(double2), hipMemcpyDeviceToHost, s);
-  if (!e) e = hipStreamSynchronize(s);
+  e = run_group({&mb}, s, true);
+  if (e == hipErrorInvalidValue) return FMBEM_ERR_INVALID_ARG;  // non-finite b
   if (e) return st_of(e);
-  std::vector<double> bn(R), tabs(R);
-  for (int q = 0; q < R; ++q) {
-    bn[q] = hb[(size_t)q * S.hstride].x;
-    if (!std::isfinite(bn[q])) return FMBEM_ERR_INVALID_ARG;
+  if (info) fill_info(mb, info);
+  return mb.ok ? FMBEM_OK : FMBEM_ERR_NOT_CONVERGED;
+}
+
+extern "C" fmbem_status fmbem_solve_batch(int32_t n, const fmbem_plan* plans, const fmbem_solve_opts* opts,
+                                          const int32_t* n_rhs, const void* const* b, void* const* x,
+                                          fmbem_solve_info* info, void* hip_stream) {
+  if (n < 1 || !plans || !opts || !n_rhs || !b || !x) return FMBEM_ERR_INVALID_ARG;
+  std::vector<SolveCfg> cfg(n);
+  for (int i = 0; i < n; ++i) {
+    if (!plans[i] || !b[i] || !x[i]) return FMBEM_ERR_INVALID_ARG;
+    fmbem_status st = solve_cfg(*reinterpret_cast<Plan*>(plans[i]), &opts[i], n_rhs[i], cfg[i]);
+    if (st != FMBEM_OK) return st;
   }
-  int its = 0, refs = 0;
-  std::vector<double> rel(R, 0.0);
-  auto true_residual = [&]() -> hipError_t {
-    hipError_t ee = S.apply(FMBEM_FP64, xx, S.t);
-    if (ee) return ee;
-    hipLaunchKernelGGL(sub_kernel, dim3(S.lgrid(S.vlen)), dim3(256), 0, s, bb, S.t, S.r, S.vlen);
-    S.norm(S.r, S.hn);
-    ee = hipMemcpyAsync(hb.data(), S.hn, R * S.hstride * sizeof(double2), hipMemcpyDeviceToHost, s);
-    if (!ee) ee = hipStreamSynchronize(s);
-    for (int q = 0; q < R; ++q) rel[q] = bn[q] > 0 ? hb[(size_t)q * S.hstride].x / bn[q] : 0.0;
-    return ee;
-  };
-  bool ok = false;
-  if (ip == FMBEM_FP64) {
-    for (int q = 0; q < R; ++q) tabs[q] = opts->tol * bn[q];
-    // GMRES estimates can drift from the true residual; re-enter while the true residual misses tol
-    for (int rep = 0; rep < max_ref && !ok; ++rep) {
-      e = S.gmres(FMBEM_FP64, bb, xx, tabs, max_its, its);
-      if (e) return st_of(e);
-      e = true_residual();
-      if (e) return st_of(e);
-      ok = true;
-      for (int q = 0; q < R; ++q)
-        if (!(rel[q] <= opts->tol)) ok = false;
-      if (its >= max_its) break;
-    }
-  } else {
-    for (refs = 0; refs < max_ref; ++refs) {
-      e = true_residual();
-      if (e) return st_of(e);
-      ok = true;
-      for (int q = 0; q < R; ++q)
-        if (!(rel[q] <= opts->tol)) ok = false;
-      if (ok || its >= max_its) break;
-      // inner: A32 d = r, d0 = 0, to inner_tol * ||r|| (and not below what the outer needs);
-      // the inner right-hand side lives in its own buffer since gmres() reuses r, t and w
-      for (int q = 0; q < R; ++q) tabs[q] = std::max(inner_tol * rel[q] * bn[q], 0.5 * opts->tol * bn[q]);
-      hipLaunchKernelGGL(zero_kernel, dim3(S.lgrid(S.vlen)), dim3(256), 0, s, S.d, S.vlen);
-      hipLaunchKernelGGL(copy_kernel, dim3(S.lgrid(S.vlen)), dim3(256), 0, s, S.rin, S.r, S.vlen);
-      e = S.gmres(FMBEM_FP32, S.rin, S.d, tabs, max_its, its);
-      if (e) return st_of(e);
-      hipLaunchKernelGGL(add_kernel, dim3(S.lgrid(S.vlen)), dim3(256), 0, s, xx, S.d, S.vlen);
-    }
+  hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+  std::vector<std::unique_ptr<Member>> own;
+  std::vector<Member*> ms;
+  for (int i = 0; i < n; ++i) {
+    own.emplace_back(new Member(*reinterpret_cast<Plan*>(plans[i]), s, n_rhs[i], cfg[i].m));
+    configure(*own.back(), cfg[i], b[i], x[i]);
+    hipError_t e = own.back()->setup(cfg[i].ip == FMBEM_FP32);
+    if (e) return st_of(e);
+    ms.push_back(own.back().get());
   }
-  if (info) {
-    for (int q = 0; q < R; ++q) {
-      info[q].iterations = its;
-      info[q].refinements = refs;
-      info[q].rel_residual = rel[q];
-    }
+  hipError_t e = run_group(ms, s, true);
+  if (e == hipErrorInvalidValue) return FMBEM_ERR_INVALID_ARG;
+  if (e) return st_of(e);
+  bool ok = true;
+  size_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    if (info) fill_info(*ms[i], info + off);
+    off += n_rhs[i];
+    if (!ms[i]->ok) ok = false;
   }
   return ok ? FMBEM_OK : FMBEM_ERR_NOT_CONVERGED;
 }
