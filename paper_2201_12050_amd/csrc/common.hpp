@@ -115,13 +115,16 @@ hipError_t matvec_group(int precision, const std::vector<GroupApply>& g, hipStre
 // ---------------------------------------------------------------------------
 constexpr int kMaxSeg = 32;        // near offsets per plan (3-D lattices with near radius 1 need 27)
 constexpr int kMaxGridDim = 4096;  // lattice cells per axis
-constexpr int kMaxJobs = 40;       // GEMM jobs per grouped launch (larger groups are split)
+constexpr int kMaxJobs = 36;       // GEMM jobs per grouped launch (larger groups are split)
 
 // Grouped complex GEMM jobs on the near-field kernel (near.hip): out = A B with A complex
-// [M][K] row-major and N columns; column j is (RHS r, cell c) = (j / C, j % C) of the job's
-// lattice.  Its B column is x_{r, c - d} (SRC_X: src holds [R][C][K], zero outside the
-// lattice) or the padded-grid entry of cell c (SRC_GRID: src holds [bin][R][K]).
-enum NearSrc : int { SRC_X = 0, SRC_GRID = 1 };
+// [M][K] row-major (row stride lda) and N columns; column j is (RHS r, cell c) =
+// (j / C, j % C) of the job's lattice.  Its B column is x_{r, c - d} (SRC_X: src holds
+// [R][C][K], zero outside the lattice) or the padded-grid entry of cell c (SRC_GRID: src
+// holds [bin][R][K]).  A batched job (SRC_BATCH, M2L kernel) is batch independent GEMMs:
+// A_b column-major [K][lda] at A + b K lda, B_b columns at src + (b N + j) K, output
+// column j of product b at out + (b N + j) M.
+enum NearSrc : int { SRC_X = 0, SRC_GRID = 1, SRC_BATCH = 2 };
 enum NearDest : int {
   DEST_SLICE = 0,  // out [N][M] column-major
   DEST_GRID = 1,   // out padded grid [bin][R][M]
@@ -134,6 +137,8 @@ struct NearJob {
   const void* part;
   void* out64;
   int M, K, N;
+  int lda;                   // A row stride (row-major) or column stride (SRC_BATCH)
+  int batch;                 // products in a SRC_BATCH job (1 otherwise)
   int tile0;                 // first logical workgroup (set by near_launch)
   int C, R;                  // cells and RHS of the job's lattice
   short M0, M1, M2, N0, N1;  // lattice and padded-grid dims
@@ -154,6 +159,8 @@ inline NearJob near_job(const Plan& P, int R, const void* A, void* out, int M, i
   j.src = src;
   j.M = M;
   j.K = K;
+  j.lda = K;
+  j.batch = 1;
   j.N = R * P.C;
   j.C = P.C;
   j.R = R;
@@ -168,12 +175,13 @@ inline NearJob near_job(const Plan& P, int R, const void* A, void* out, int M, i
 }
 
 // Launch a list of jobs (split into launches of at most kMaxJobs).  shape < 0: default tile
-// shape; else one of near_num_shapes<T>() shapes.  kind 0 launches the tile body as
-// near_kernel (near field + S2M), 1 as l2t_kernel (L2T).
+// shape; else one of near_num_shapes<T>(kind) shapes.  kind 0 launches the tile body as
+// near_kernel (near field + S2M), 1 as l2t_kernel (L2T), 2 as m2l_kernel (SRC_BATCH jobs,
+// column-major A).
 template <typename T>
 hipError_t near_launch(const std::vector<NearJob>& jobs, hipStream_t s, int shape = -1, int kind = 0);
 template <typename T>
-int near_num_shapes();
+int near_num_shapes(int kind);
 // y = sum of ns partial slices (FP64 to y64 when set)
 template <typename T>
 hipError_t near_reduce_launch(const void* part, int ns, size_t len, void* y, void* y64, hipStream_t s);
@@ -184,7 +192,10 @@ hipError_t grid_dft_launch(void* buf, int channels, const int M[3], const int N[
 
 // column stride (complex elements) of the per-bin column-major Lambda blocks
 int lambda_ld(int p);
+// per-bin M2L GEMV, in place in buf [B][R][p]
 template <typename T>
 hipError_t m2l_launch(const void* Lam, void* buf, int B, int R, int p, hipStream_t s);
+// right-hand-side count from which the M2L runs as a batched MFMA GEMM into a second buffer
+constexpr int kM2lGemmRhs = 8;
 
 }  // namespace fmbem

@@ -22,7 +22,7 @@ static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 size_t matvec_workspace_bytes_per_rhs(const Plan& P, int precision) {
   const size_t el = precision == FMBEM_FP64 ? 16 : 8;
-  return align256((size_t)P.B * P.p * el) + align256((size_t)P.n_near * P.C * P.n * el);
+  return 2 * align256((size_t)P.B * P.p * el) + align256((size_t)P.n_near * P.C * P.n * el);
 }
 
 static hipEvent_t prof_record(const Plan& P, hipStream_t s) {
@@ -74,7 +74,7 @@ int tuned_shape(int kind, const std::vector<NearJob>& jobs, hipStream_t s) {
   hipEvent_t a = nullptr, b = nullptr;
   if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
     // two sweeps over the shapes, the minimum of each shape's timings counts
-    const int ns = near_num_shapes<T>();
+    const int ns = near_num_shapes<T>(kind);
     std::vector<float> t(ns, 1e30f);
     for (int sweep = 0; sweep < 2; ++sweep) {
       for (int v = 0; v < ns; ++v) {
@@ -112,10 +112,33 @@ int cached_shape(int kind, const std::vector<NearJob>& jobs) {
   return it == g_tuned.end() ? -1 : it->second;
 }
 
-// workspace layout: [padded grid B x R x p][near partials n_near x R x C x n]
+// workspace layout: [padded grid B x R x p][second grid B x R x p][near partials n_near x R x C x n]
+template <typename T>
+static char* second_grid(const Plan& P, int R, void* ws) {
+  return reinterpret_cast<char*>(ws) + align256((size_t)P.B * R * P.p * sizeof(cplx<T>));
+}
 template <typename T>
 static char* near_partials(const Plan& P, int R, void* ws) {
-  return reinterpret_cast<char*>(ws) + align256((size_t)P.B * R * P.p * sizeof(cplx<T>));
+  return reinterpret_cast<char*>(ws) + 2 * align256((size_t)P.B * R * P.p * sizeof(cplx<T>));
+}
+
+// lhat_b = Lambda_b mhat_b for every bin: a GEMV in place for few right-hand sides, a
+// batched MFMA GEMM into the second grid from kM2lGemmRhs on; returns the buffer of lhat
+template <typename T>
+static hipError_t m2l_apply(const Plan& P, int R, void* ws, hipStream_t s, void** lhat) {
+  const int prec = sizeof(T) == 8 ? 0 : 1;
+  if (R < kM2lGemmRhs) {
+    *lhat = ws;
+    return m2l_launch<T>(P.Lam[prec], ws, P.B, R, P.p, s);
+  }
+  void* out = second_grid<T>(P, R, ws);
+  NearJob j = near_job(P, R, P.Lam[prec], out, P.p, P.p, ws, SRC_BATCH, DEST_SLICE);
+  j.N = R;
+  j.lda = lambda_ld(P.p);
+  j.batch = P.B;
+  std::vector<NearJob> jobs{j};
+  *lhat = out;
+  return near_launch<T>(jobs, s, tuned_shape<T>(2, jobs, s), 2);
 }
 
 template <typename T>
@@ -138,9 +161,9 @@ void near_s2m_jobs(const Plan& P, int R, const void* x, void* ws, std::vector<Ne
 }
 
 template <typename T>
-NearJob l2t_job(const Plan& P, int R, void* ws, void* y, void* y64) {
+NearJob l2t_job(const Plan& P, int R, void* ws, const void* lhat, void* y, void* y64) {
   const int prec = sizeof(T) == 8 ? 0 : 1;
-  NearJob j = near_job(P, R, P.U0[prec], y, P.n, P.p, ws, SRC_GRID, DEST_FINAL);
+  NearJob j = near_job(P, R, P.U0[prec], y, P.n, P.p, lhat, SRC_GRID, DEST_FINAL);
   j.part = near_partials<T>(P, R, ws);
   j.nparts = (short)P.n_near;
   j.out64 = y64;
@@ -177,16 +200,17 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
   if (e != hipSuccess) return e;
   prof_end(P, 2 + 6 * prec, ev, s);
   ev = prof_begin(P, 3 + 6 * prec, s);
-  e = m2l_launch<T>(P.Lam[prec], ws, P.B, R, p, s);
+  void* lhat = nullptr;
+  e = m2l_apply<T>(P, R, ws, s, &lhat);
   if (e != hipSuccess) return e;
   prof_end(P, 3 + 6 * prec, ev, s);
   ev = prof_begin(P, 4 + 6 * prec, s);
-  e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, true, true, s);
+  e = grid_dft_launch<T>(lhat, R * p, P.grid, P.fft, true, true, s);
   if (e != hipSuccess) return e;
   prof_end(P, 4 + 6 * prec, ev, s);
   // [5] L2T with the fixed-order sum of the near partials
   {
-    std::vector<NearJob> jobs{l2t_job<T>(P, R, ws, y, y64)};
+    std::vector<NearJob> jobs{l2t_job<T>(P, R, ws, lhat, y, y64)};
     const int shape = tuned_shape<T>(1, jobs, s);
     ev = prof_begin(P, 5 + 6 * prec, s);
     e = near_launch<T>(jobs, s, shape, 1);
@@ -215,10 +239,11 @@ static hipError_t matvec_group_t(const std::vector<GroupApply>& g, hipStream_t s
       if (e != hipSuccess) return e;
       continue;
     }
+    void* lhat = nullptr;
     if ((e = grid_dft_launch<T>(a.ws, a.R * P.p, P.grid, P.fft, false, true, s)) != hipSuccess) return e;
-    if ((e = m2l_launch<T>(P.Lam[prec], a.ws, P.B, a.R, P.p, s)) != hipSuccess) return e;
-    if ((e = grid_dft_launch<T>(a.ws, a.R * P.p, P.grid, P.fft, true, true, s)) != hipSuccess) return e;
-    l2t.push_back(l2t_job<T>(P, a.R, a.ws, a.y, a.y64));
+    if ((e = m2l_apply<T>(P, a.R, a.ws, s, &lhat)) != hipSuccess) return e;
+    if ((e = grid_dft_launch<T>(lhat, a.R * P.p, P.grid, P.fft, true, true, s)) != hipSuccess) return e;
+    l2t.push_back(l2t_job<T>(P, a.R, a.ws, lhat, a.y, a.y64));
   }
   if (l2t.empty()) return hipSuccess;
   shape = tune ? tuned_shape<T>(1, l2t, s) : cached_shape<T>(1, l2t);

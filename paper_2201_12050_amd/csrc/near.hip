@@ -69,7 +69,8 @@ __device__ inline void cell_coords(const NearJob& jb, int j, int& r, int& i1, in
 __device__ inline int lds_slot(int r, int c) { return 4 * r + (c ^ ((r >> 2) & 3)); }
 
 // Tile: ROWS complex rows x COLS columns, 4 waves arranged WR x (4/WR), KC complex k per step.
-template <typename T, int ROWS, int COLS, int WR, int KC>
+// ACOL: batched job with column-major A (the M2L products).
+template <typename T, int ROWS, int COLS, int WR, int KC, bool ACOL = false>
 __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
   constexpr int WC = 4 / WR;
   constexpr int RBW = ROWS / (16 * WR);  // 16-row MFMA blocks per wave
@@ -81,8 +82,8 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
   constexpr int APT = AT >= 256 ? AT / 256 : 1; // per thread (consecutive k)
   constexpr int BPT = COLS * KC / 256;          // B complex elements per thread (consecutive k)
   constexpr int TPC = KC / BPT;                 // threads per B column
-  static_assert(KC % APT == 0 && BPT >= 1 && KC % BPT == 0, "staging split");
-  static_assert((APT % CW == 0 || CW % APT == 0) && (BPT % CW == 0 || CW % BPT == 0), "chunk split");
+  static_assert(BPT >= 1 && KC % BPT == 0 && (BPT % CW == 0 || CW % BPT == 0), "B staging split");
+  static_assert(ACOL ? ROWS % APT == 0 : (KC % APT == 0 && (APT % CW == 0 || CW % APT == 0)), "A staging split");
   typedef T VK __attribute__((ext_vector_type(CW)));
   // two buffers (ping-pong over the k steps) x {Re, Im} of A and of B, in chunks; the
   // sums Re + Im of the third product are formed in registers after the fragment loads
@@ -99,12 +100,18 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
   int ji = 0;
   while (ji + 1 < jobs.count && L >= jobs.job[ji + 1].tile0) ++ji;
   const NearJob& jb = jobs.job[ji];
-  const int M = jb.M, K = jb.K, N = jb.N;
+  const int M = jb.M, K = jb.K, N = jb.N, lda = jb.lda;
   const int ctiles = (N + COLS - 1) / COLS;
-  const int local = L - jb.tile0;
+  int local = L - jb.tile0;
+  int bb = 0;  // product of a batched job
+  if constexpr (ACOL) {
+    const int per = ((M + ROWS - 1) / ROWS) * ctiles;
+    bb = local / per;
+    local -= bb * per;
+  }
   const int m0 = (local / ctiles) * ROWS;
   const int col0 = (local % ctiles) * COLS;
-  const cplx<T>* A = reinterpret_cast<const cplx<T>*>(jb.A);
+  const cplx<T>* A = reinterpret_cast<const cplx<T>*>(jb.A) + (ACOL ? (size_t)bb * K * lda : 0);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -122,7 +129,9 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
       int r, i1, i2, i3;
       cell_coords(jb, j, r, i1, i2, i3);
       const cplx<T>* src = reinterpret_cast<const cplx<T>*>(jb.src);
-      if (jb.src_kind == SRC_X) {
+      if (ACOL) {
+        bcol = src + ((size_t)bb * N + j) * K;
+      } else if (jb.src_kind == SRC_X) {
         const int s1 = i1 - jb.d0, s2 = i2 - jb.d1, s3 = i3 - jb.d2;
         if (s1 >= 0 && s1 < jb.M0 && s2 >= 0 && s2 < jb.M1 && s3 >= 0 && s3 < jb.M2)
           bcol = src + ((size_t)r * jb.C + (s1 + jb.M0 * (s2 + jb.M1 * s3))) * K;
@@ -132,10 +141,12 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
       }
     }
   }
-  // A staging: thread t < AT / APT holds APT consecutive k of one row
+  // A staging: thread t < AT / APT holds APT consecutive k of one row (row-major A) or
+  // APT consecutive rows of one k (column-major A)
   const bool a_act = tid * APT < AT;
-  const int a_row = (tid * APT) / KC, a_k = (tid * APT) % KC;
-  const cplx<T>* arow = (a_act && m0 + a_row < M) ? A + (size_t)(m0 + a_row) * K : nullptr;
+  const int a_row = ACOL ? (tid * APT) % ROWS : (tid * APT) / KC;
+  const int a_k = ACOL ? (tid * APT) / ROWS : (tid * APT) % KC;
+  const cplx<T>* arow = (!ACOL && a_act && m0 + a_row < M) ? A + (size_t)(m0 + a_row) * lda : nullptr;
 
   Acc p1[RBW][CBW], p2[RBW][CBW], p3[RBW][CBW];
 #pragma unroll
@@ -152,7 +163,18 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
   auto load = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < APT; ++q) ra[q] = mk<T>(0, 0);
-    if (arow) {
+    if (ACOL) {
+      if (a_act && k0 + a_k < K) {
+        const cplx<T>* acol = A + (size_t)(k0 + a_k) * lda + m0 + a_row;
+        if (m0 + a_row + APT <= M) {
+#pragma unroll
+          for (int q = 0; q < APT; ++q) ra[q] = acol[q];
+        } else {
+          for (int q = 0; q < APT; ++q)
+            if (m0 + a_row + q < M) ra[q] = acol[q];
+        }
+      }
+    } else if (arow) {
       if (k0 + KC <= K) {
 #pragma unroll
         for (int q = 0; q < APT; ++q) ra[q] = arow[k0 + a_k + q];
@@ -175,7 +197,18 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
   };
   // staged values -> LDS buffer b (whole chunks as one 16-byte store, partial chunks element-wise)
   auto store = [&](int b) {
-    if (a_act) {
+    if (ACOL) {
+      if (a_act) {
+        // APT rows of one k: element-wise into their rows' chunks
+        const int c = a_k / CW, w = a_k % CW;
+#pragma unroll
+        for (int q = 0; q < APT; ++q) {
+          const int o = lds_slot(a_row + q, c);
+          reinterpret_cast<T*>(&Asm[b][0][o])[w] = ra[q].x;
+          reinterpret_cast<T*>(&Asm[b][1][o])[w] = ra[q].y;
+        }
+      }
+    } else if (a_act) {
       if constexpr (APT >= CW) {
 #pragma unroll
         for (int c = 0; c < APT / CW; ++c) {
@@ -271,7 +304,9 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
     const int col = col0 + 16 * (CBW * wc + j) + li;
     if (col >= N) continue;
     size_t base;
-    if (jb.dest == DEST_GRID) {
+    if (ACOL) {
+      base = ((size_t)bb * N + col) * M;
+    } else if (jb.dest == DEST_GRID) {
       int r, i1, i2, i3;
       cell_coords(jb, col, r, i1, i2, i3);
       const size_t bin = (size_t)i1 + (size_t)jb.N0 * (i2 + (size_t)jb.N1 * i3);
@@ -310,6 +345,10 @@ template <typename T, int ROWS, int COLS, int WR, int KC>
 __global__ __launch_bounds__(256) void l2t_kernel(NearJobs jobs) {
   near_tile<T, ROWS, COLS, WR, KC>(jobs);
 }
+template <typename T, int ROWS, int COLS, int WR, int KC>
+__global__ __launch_bounds__(256) void m2l_kernel(NearJobs jobs) {
+  near_tile<T, ROWS, COLS, WR, KC, true>(jobs);
+}
 
 // y[col][m] = sum_s part[s][col][m] in a fixed order (optionally written as FP64)
 template <typename T>
@@ -332,10 +371,23 @@ struct NearShape {
   X(0, 64, 128, 2, KC) X(1, 32, 128, 2, KC) X(2, 64, 64, 2, KC) X(3, 64, 64, 4, KC) X(4, 32, 64, 2, KC) \
   X(5, 16, 128, 1, KC) X(6, 16, 256, 1, KC) X(7, 128, 64, 4, KC) X(8, 32, 128, 1, KC) X(9, 16, 64, 1, KC)
 constexpr int kNumShapes = 10;
+// M2L products: p rows (121 at n_t = 10) by R columns per bin
+#define FMBEM_M2L_SHAPES(KC) \
+  X(0, 64, 64, 4, KC) X(1, 32, 64, 2, KC) X(2, 64, 32, 2, KC) X(3, 32, 32, 2, KC) X(4, 16, 64, 1, KC) X(5, 128, 64, 4, KC)
+constexpr int kNumM2lShapes = 6;
 template <typename T> constexpr int shape_kc() { return sizeof(T) == 4 ? 16 : 8; }
 
 template <typename T>
-static NearShape shape_of(int v) {
+static NearShape shape_of(int kind, int v) {
+  if (kind == 2) {
+    switch (v) {
+#define X(i, r, c, w, k) \
+  case i: return NearShape{r, c, w, k};
+      FMBEM_M2L_SHAPES(shape_kc<T>())
+#undef X
+    }
+    return NearShape{64, 64, 4, shape_kc<T>()};
+  }
   switch (v) {
 #define X(i, r, c, w, k) \
   case i: return NearShape{r, c, w, k};
@@ -346,12 +398,21 @@ static NearShape shape_of(int v) {
 }
 
 template <typename T>
-int near_num_shapes() {
-  return kNumShapes;
+int near_num_shapes(int kind) {
+  return kind == 2 ? kNumM2lShapes : kNumShapes;
 }
 
 template <typename T>
 static void launch_shape(int v, int kind, unsigned blocks, const NearJobs& jobs, hipStream_t s) {
+  if (kind == 2) {
+    switch (v) {
+#define X(i, r, c, w, k) \
+  case i: hipLaunchKernelGGL((m2l_kernel<T, r, c, w, k>), dim3(blocks), dim3(256), 0, s, jobs); break;
+      FMBEM_M2L_SHAPES(shape_kc<T>())
+#undef X
+    }
+    return;
+  }
   switch (v) {
 #define X(i, r, c, w, k)                                                                      \
   case i:                                                                                     \
@@ -363,16 +424,20 @@ static void launch_shape(int v, int kind, unsigned blocks, const NearJobs& jobs,
   }
 }
 
+template <typename T>
+static long long job_tiles(const NearJob& j, const NearShape& sh) {
+  return (long long)j.batch * ((j.M + sh.rows - 1) / sh.rows) * ((j.N + sh.cols - 1) / sh.cols);
+}
+
 // default shape: the one whose workgroup count best fills whole rounds of 256 CUs
 template <typename T>
-static int near_default_shape(const std::vector<NearJob>& jobs) {
+static int near_default_shape(const std::vector<NearJob>& jobs, int kind) {
   int best = 0;
   double best_score = -1.0;
-  for (int v = 0; v < kNumShapes; ++v) {
-    const NearShape sh = shape_of<T>(v);
+  for (int v = 0; v < near_num_shapes<T>(kind); ++v) {
+    const NearShape sh = shape_of<T>(kind, v);
     long long wg = 0;
-    for (const NearJob& j : jobs)
-      wg += (long long)((j.M + sh.rows - 1) / sh.rows) * ((j.N + sh.cols - 1) / sh.cols);
+    for (const NearJob& j : jobs) wg += job_tiles<T>(j, sh);
     const long long rounds = (wg + 255) / 256;
     const double score = (double)wg / (double)(rounds * 256) + 1e-3 * sh.rows * sh.cols / 8192.0;
     if (score > best_score) {
@@ -386,8 +451,8 @@ static int near_default_shape(const std::vector<NearJob>& jobs) {
 template <typename T>
 hipError_t near_launch(const std::vector<NearJob>& list, hipStream_t s, int shape, int kind) {
   if (list.empty()) return hipSuccess;
-  if (shape < 0 || shape >= kNumShapes) shape = near_default_shape<T>(list);
-  const NearShape sh = shape_of<T>(shape);
+  if (shape < 0 || shape >= near_num_shapes<T>(kind)) shape = near_default_shape<T>(list, kind);
+  const NearShape sh = shape_of<T>(kind, shape);
   for (size_t first = 0; first < list.size(); first += kMaxJobs) {
     NearJobs jobs;
     jobs.count = (int)std::min<size_t>(kMaxJobs, list.size() - first);
@@ -395,7 +460,7 @@ hipError_t near_launch(const std::vector<NearJob>& list, hipStream_t s, int shap
     for (int j = 0; j < jobs.count; ++j) {
       jobs.job[j] = list[first + j];
       jobs.job[j].tile0 = (int)tiles;
-      tiles += (long long)((jobs.job[j].M + sh.rows - 1) / sh.rows) * ((jobs.job[j].N + sh.cols - 1) / sh.cols);
+      tiles += job_tiles<T>(jobs.job[j], sh);
     }
     if (tiles == 0) continue;
     if (tiles > INT32_MAX) return hipErrorInvalidValue;
@@ -417,8 +482,8 @@ hipError_t near_reduce_launch(const void* part, int ns, size_t len, void* y, voi
 
 template hipError_t near_launch<double>(const std::vector<NearJob>&, hipStream_t, int, int);
 template hipError_t near_launch<float>(const std::vector<NearJob>&, hipStream_t, int, int);
-template int near_num_shapes<double>();
-template int near_num_shapes<float>();
+template int near_num_shapes<double>(int);
+template int near_num_shapes<float>(int);
 template hipError_t near_reduce_launch<double>(const void*, int, size_t, void*, void*, hipStream_t);
 template hipError_t near_reduce_launch<float>(const void*, int, size_t, void*, void*, hipStream_t);
 

@@ -80,8 +80,9 @@ def test_operator_data_matches_oracle(cases, name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("R", [1, 3])
+@pytest.mark.parametrize("R", [1, 3, 9])
 def test_matvec_matches_oracle(cases, name, R):
+    # R = 9 takes the batched MFMA GEMM form of the per-bin M2L product
     F, P, lat = cases[name]
     x = random_complex((R, lat.n_cells, F.n), 100 + R)
     ref = F.matvec(x)
@@ -96,12 +97,20 @@ def test_matvec_matches_oracle(cases, name, R):
 
 
 def test_matvec_batched_equals_alone(cases):
+    # below the M2L GEMM threshold every stage computes each column in the same order
+    # whatever the batch, so a batched apply equals the single ones bit for bit
     F, P, lat = cases["sphere80_5x3_ragged"]
     x = torch.from_numpy(random_complex((5, lat.n_cells, F.n), 7)).cuda().to(torch.complex64)
     yb = P.matvec(x, precision="fp32")
     for r in range(5):
         ya = P.matvec(x[r:r + 1].contiguous(), precision="fp32")
         assert torch.equal(yb[r:r + 1], ya)
+    # from 8 right-hand sides on the M2L product is a GEMM: equal to FP32 rounding
+    x = torch.from_numpy(random_complex((12, lat.n_cells, F.n), 8)).cuda().to(torch.complex64)
+    yb = P.matvec(x, precision="fp32")
+    for r in (0, 7, 11):
+        ya = P.matvec(x[r:r + 1].contiguous(), precision="fp32")
+        assert (torch.linalg.vector_norm(yb[r] - ya[0]) / torch.linalg.vector_norm(ya)).item() < 1e-6
 
 
 def test_incident_fields_match_oracle(cases):
