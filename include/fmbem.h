@@ -44,13 +44,15 @@ typedef enum {
   FMBEM_ERR_OUT_OF_MEMORY = 3, /* a device allocation failed; nothing leaked */
   FMBEM_ERR_DEVICE = 4,        /* a HIP call failed (no device, launch failure) */
   FMBEM_ERR_NOT_CONVERGED = 5, /* solve stopped at its iteration limit; x = last iterate */
-  FMBEM_ERR_WORKSPACE = 6      /* caller workspace smaller than fmbem_plan_info says */
+  FMBEM_ERR_WORKSPACE = 6,     /* caller workspace smaller than fmbem_plan_info says */
+  FMBEM_ERR_ADMISSION = 7      /* serving engine: the request can never fit the byte budget */
 } fmbem_status;
 
 typedef enum { FMBEM_FP64 = 0, FMBEM_FP32 = 1 } fmbem_precision;
 typedef enum { FMBEM_BURTON_MILLER = 0, FMBEM_CBIE = 1 } fmbem_formulation;
 
 typedef struct fmbem_plan_s* fmbem_plan;
+typedef struct fmbem_engine_s* fmbem_engine;
 
 /* Unit-cell mesh in cell-local coordinates: the cell centre (= expansion centre
  * of its FMM box, Sec. 3.2) is the origin.  Copied during fmbem_plan_create. */
@@ -173,6 +175,43 @@ fmbem_status fmbem_solve(fmbem_plan plan, const fmbem_solve_opts* opts, int32_t 
 fmbem_status fmbem_solve_batch(int32_t n, const fmbem_plan* plans, const fmbem_solve_opts* opts,
                                const int32_t* n_rhs, const void* const* b, void* const* x,
                                fmbem_solve_info* info, void* hip_stream);
+
+/* Serving engine: continuous batching of solve requests on one stream (the
+ * batched form of fmbem_solve for a stream of requests arriving over time).
+ * Requests wait in arrival order; at the start of each fmbem_engine_step the
+ * head of the queue is admitted while fewer than max_slots problems are active
+ * and its device footprint fits hbm_budget_bytes minus what the active problems
+ * hold.  The footprint of a request is its Krylov basis ((restart + 1) vectors),
+ * four work vectors and the FP32 copy ([n_rhs][N] each) plus the operator
+ * workspace; plans are the caller's and stay resident.  A step advances every
+ * active problem by one round: one operator application each, with the
+ * near-field + S2M and the L2T GEMMs of all of them in shared grouped launches,
+ * then their Gram-Schmidt, Givens and residual kernels; finished problems free
+ * their memory.  Each problem follows fmbem_solve.  Steps block for the previous
+ * round's results only (one round stays in flight).  Not safe for concurrent
+ * calls on one engine except submit/poll/stats, which lock.
+ *
+ * create: hip_stream is the stream every step uses; out receives the engine.
+ * submit: plan, b and x (device complex128 [n_rhs][n_cells][n_dof_cell], x the
+ *   initial guess, overwritten with the solution) must stay valid until the
+ *   ticket is polled done.  Validates opts like fmbem_solve; returns
+ *   FMBEM_ERR_ADMISSION (nothing queued) when the footprint exceeds the budget.
+ * step: returns FMBEM_OK when idle.
+ * poll: *done = 0 while pending (FMBEM_OK); when finished *done = 1, info (host
+ *   [n_rhs], may be NULL) is filled and the solve's status is returned
+ *   (FMBEM_OK, FMBEM_ERR_NOT_CONVERGED, FMBEM_ERR_INVALID_ARG for a non-finite b,
+ *   FMBEM_ERR_OUT_OF_MEMORY); a ticket is reported once, after which it is unknown
+ *   (FMBEM_ERR_INVALID_ARG).
+ * stats: active problems, queued requests, device bytes held (any may be NULL).
+ * destroy: waits for the stream, frees every active problem, drops the queue. */
+fmbem_status fmbem_engine_create(size_t hbm_budget_bytes, int32_t max_slots, void* hip_stream,
+                                 fmbem_engine* out);
+fmbem_status fmbem_engine_submit(fmbem_engine engine, fmbem_plan plan, const fmbem_solve_opts* opts,
+                                 int32_t n_rhs, const void* b, void* x, int64_t* ticket);
+fmbem_status fmbem_engine_step(fmbem_engine engine);
+fmbem_status fmbem_engine_poll(fmbem_engine engine, int64_t ticket, int32_t* done, fmbem_solve_info* info);
+fmbem_status fmbem_engine_stats(fmbem_engine engine, int32_t* active, int32_t* queued, size_t* bytes_in_use);
+fmbem_status fmbem_engine_destroy(fmbem_engine engine);
 
 /* Right-hand sides b = p_inc + alpha dp_inc/dn at the collocation points
  * (Sec. 2.1, eq. (bm)), device complex128 [n_rhs][n_cells][n_dof_cell].

@@ -61,7 +61,9 @@ class SolveInfo(ct.Structure):
 
 EXPORTS = ["fmbem_plan_create", "fmbem_plan_query", "fmbem_plan_destroy", "fmbem_plan_export", "fmbem_matvec",
            "fmbem_solve", "fmbem_incident_plane_wave", "fmbem_incident_point_source", "fmbem_plan_profile",
-           "fmbem_plan_profile_read", "fmbem_status_string", "fmbem_solve_batch"]
+           "fmbem_plan_profile_read", "fmbem_status_string", "fmbem_solve_batch", "fmbem_engine_create",
+           "fmbem_engine_submit", "fmbem_engine_step", "fmbem_engine_poll", "fmbem_engine_stats",
+           "fmbem_engine_destroy"]
 STAGES = tuple(f"{s}_{p}" for p in ("fp64", "fp32") for s in ("near", "reduce", "fft", "m2l", "ifft", "l2t"))
 
 _lib = None
@@ -82,6 +84,12 @@ def load():
     lib.fmbem_plan_export.argtypes = [vp, ct.c_int32, vp, ct.c_size_t]
     lib.fmbem_matvec.argtypes = [vp, ct.c_int32, ct.c_int32, vp, vp, vp, ct.c_size_t, vp]
     lib.fmbem_solve.argtypes = [vp, ct.POINTER(SolveOpts), ct.c_int32, vp, vp, ct.POINTER(SolveInfo), vp]
+    lib.fmbem_engine_create.argtypes = [ct.c_size_t, ct.c_int32, vp, ct.POINTER(vp)]
+    lib.fmbem_engine_submit.argtypes = [vp, vp, ct.POINTER(SolveOpts), ct.c_int32, vp, vp, ct.POINTER(ct.c_int64)]
+    lib.fmbem_engine_step.argtypes = [vp]
+    lib.fmbem_engine_poll.argtypes = [vp, ct.c_int64, ct.POINTER(ct.c_int32), ct.POINTER(SolveInfo)]
+    lib.fmbem_engine_stats.argtypes = [vp, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32), ct.POINTER(ct.c_size_t)]
+    lib.fmbem_engine_destroy.argtypes = [vp]
     lib.fmbem_solve_batch.argtypes = [ct.c_int32, ct.POINTER(vp), ct.POINTER(SolveOpts), ct.POINTER(ct.c_int32),
                                       ct.POINTER(vp), ct.POINTER(vp), ct.POINTER(SolveInfo), vp]
     lib.fmbem_incident_plane_wave.argtypes = [vp, ct.c_int32, ct.POINTER(ct.c_double), ct.c_double, vp, vp]
@@ -153,6 +161,68 @@ def solve_batch(problems, stream=None, raise_on_not_converged=True):
         out.append((xs[i], _info_dicts(info[off:off + nr[i]])))
         off += nr[i]
     return out
+
+
+class Engine:
+    """Serving engine (continuous batching of solve requests, admission by device bytes).
+
+    submit() queues a request and returns a ticket; step() advances every admitted
+    problem by one operator application; poll() returns None while pending, else
+    (x, infos, status).  The engine keeps b and x alive until the ticket is polled."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 16, stream=None):
+        self._lib = load()
+        self._stream = stream
+        h = ct.c_void_p()
+        check(self._lib.fmbem_engine_create(int(hbm_budget_bytes), int(max_slots), _stream_ptr(stream),
+                                            ct.byref(h)), "fmbem_engine_create")
+        self._h = h
+        self._held = {}
+
+    def close(self):
+        if self._h:
+            self._lib.fmbem_engine_destroy(self._h)
+            self._h = None
+            self._held.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, plan, b, x=None, **opts) -> int:
+        import torch
+        if b.dtype != torch.complex128 or not b.is_cuda or not b.is_contiguous():
+            raise ValueError("b must be a contiguous complex128 CUDA tensor")
+        if x is None:
+            x = torch.zeros_like(b)
+        R = b.numel() // plan.n_dof
+        o = solve_opts(**opts)
+        t = ct.c_int64()
+        check(self._lib.fmbem_engine_submit(self._h, plan._h, ct.byref(o), R, ct.c_void_p(b.data_ptr()),
+                                            ct.c_void_p(x.data_ptr()), ct.byref(t)), "fmbem_engine_submit")
+        self._held[t.value] = (plan, b, x, R)
+        return t.value
+
+    def step(self):
+        check(self._lib.fmbem_engine_step(self._h), "fmbem_engine_step")
+
+    def poll(self, ticket: int):
+        plan, b, x, R = self._held[ticket]
+        done = ct.c_int32()
+        info = (SolveInfo * R)()
+        st = self._lib.fmbem_engine_poll(self._h, ticket, ct.byref(done), info)
+        if not done.value:
+            check(st, "fmbem_engine_poll")
+            return None
+        del self._held[ticket]
+        return x, _info_dicts(info), st
+
+    def stats(self):
+        a, q, u = ct.c_int32(), ct.c_int32(), ct.c_size_t()
+        check(self._lib.fmbem_engine_stats(self._h, ct.byref(a), ct.byref(q), ct.byref(u)), "fmbem_engine_stats")
+        return dict(active=a.value, queued=q.value, bytes_in_use=u.value)
 
 
 def _precision(p) -> int:

@@ -335,6 +335,7 @@ extern "C" const char* fmbem_status_string(int32_t status) {
     case FMBEM_ERR_DEVICE: return "device error";
     case FMBEM_ERR_NOT_CONVERGED: return "not converged";
     case FMBEM_ERR_WORKSPACE: return "workspace too small";
+    case FMBEM_ERR_ADMISSION: return "request exceeds the engine's memory budget";
     default: return "unknown status";
   }
 }

@@ -14,7 +14,10 @@
 // host; a step queued after convergence is discarded by the per-RHS freeze.
 #include <algorithm>
 #include <cmath>
+#include <deque>
 #include <memory>
+#include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "common.hpp"
@@ -100,7 +103,7 @@ __global__ void mdot_finish(const double2* __restrict__ part, int nblk, int R, i
   if (lane != 0) return;
   double2* o = h + (size_t)r * hstride + i;
   if (mode == 0) *o = make_double2(sx, sy);
-  else if (mode == 2) *o = make_double2(sqrt(fmax(sx, 0.0)), 0.0);
+  else if (mode == 2) *o = make_double2(isnan(sx) ? sx : sqrt(fmax(sx, 0.0)), 0.0);  // NaN stays visible
   else {
     h2[(size_t)r * hstride + i] = make_double2(sx, sy);
     o->x += sx;
@@ -365,7 +368,7 @@ struct Member {
 
   // state
   enum Phase { RUN_TRUE, START_INNER, RUN_RESTART, RUN_ARN, CLOSE, WAIT, DONE };
-  enum Kind { K_NONE, K_TRUE, K_RESTART, K_ARN };
+  enum Kind { K_NONE, K_INIT, K_TRUE, K_RESTART, K_ARN };
   struct Rec {
     int kind = K_NONE, j = 0, epoch = 0;
   };
@@ -379,6 +382,7 @@ struct Member {
   int epoch = 0;
   int its = 0, refs = 0;
   bool ok = false;
+  bool bad_input = false;
   hipError_t err = hipSuccess;
   std::vector<double> bn, rel;
   // this round's application
@@ -404,45 +408,49 @@ struct Member {
     }
     if (htol) hipHostFree(htol);
   }
-  hipError_t alloc(void** q, size_t bytes) {
-    hipError_t e = hipMalloc(q, std::max<size_t>(bytes, 256));
-    if (e == hipSuccess) mem.push_back(*q);
-    return e;
+  // device buffers of a member, in allocation order (footprint() sums exactly these)
+  struct Buf {
+    void** ptr;
+    size_t bytes;
+  };
+  std::vector<Buf> buffers(bool need32) {
+    const size_t wsb = (size_t)R * std::max(matvec_workspace_bytes_per_rhs(P, 0),
+                                            need32 ? matvec_workspace_bytes_per_rhs(P, 1) : 0);
+    std::vector<Buf> v{{(void**)&V, (size_t)(m + 1) * vlen * sizeof(double2)},
+                       {(void**)&r, vlen * sizeof(double2)},
+                       {(void**)&d, vlen * sizeof(double2)},
+                       {(void**)&t, vlen * sizeof(double2)},
+                       {(void**)&rin, vlen * sizeof(double2)},
+                       {&ws, wsb},
+                       {(void**)&part, (size_t)R * (m + 1) * nblk * sizeof(double2)},
+                       {(void**)&hc, (size_t)R * hstride * sizeof(double2)},
+                       {(void**)&hn, (size_t)R * hstride * sizeof(double2)},
+                       {(void**)&H, (size_t)R * (m + 1) * m * sizeof(double2)},
+                       {(void**)&cs, (size_t)R * m * sizeof(double2)},
+                       {(void**)&sn, (size_t)R * m * sizeof(double2)},
+                       {(void**)&g, (size_t)R * (m + 1) * sizeof(double2)},
+                       {(void**)&y, (size_t)R * hstride * sizeof(double2)},
+                       {(void**)&res, R * sizeof(double)},
+                       {(void**)&tolv, R * sizeof(double)},
+                       {(void**)&jdone, R * sizeof(int)},
+                       {(void**)&npart, (size_t)R * nb * sizeof(double)},
+                       {(void**)&reorth, R * sizeof(int)}};
+    if (need32) v.push_back({(void**)&x32, vlen * sizeof(float2)});
+    for (Buf& q : v) q.bytes = std::max<size_t>((q.bytes + 255) / 256 * 256, 256);
+    return v;
   }
-  // device bytes a member of this shape allocates (the engine's admission unit)
-  static size_t footprint(const Plan& P, int R, int m, bool need32) {
-    const size_t N = (size_t)P.n * P.C, vlen = (size_t)R * N;
-    const size_t nblk = (N + kDotThreads * kDotEl - 1) / (kDotThreads * kDotEl);
-    size_t b = (size_t)(m + 1) * vlen * 16 + 4 * vlen * 16 + (need32 ? vlen * 8 : 0);
-    b += (size_t)R * std::max(matvec_workspace_bytes_per_rhs(P, 0), need32 ? matvec_workspace_bytes_per_rhs(P, 1) : 0);
-    b += (size_t)R * (m + 1) * nblk * 16 + (size_t)R * (m + 2) * 16 * 3 + (size_t)R * (m + 1) * m * 16;
-    b += (size_t)R * (3 * m + 1) * 16 + (size_t)R * 2048 * 8 + (size_t)R * 32 + 18 * 256;
-    return b;
+  // device bytes this member allocates (the serving engine's admission unit)
+  size_t footprint(bool need32) {
+    size_t sum = 0;
+    for (const Buf& q : buffers(need32)) sum += q.bytes;
+    return sum;
   }
   hipError_t setup(bool need32) {
     hipError_t e;
-    if ((e = alloc((void**)&V, (size_t)(m + 1) * vlen * sizeof(double2)))) return e;
-    if ((e = alloc((void**)&r, vlen * sizeof(double2)))) return e;
-    if ((e = alloc((void**)&d, vlen * sizeof(double2)))) return e;
-    if ((e = alloc((void**)&t, vlen * sizeof(double2)))) return e;
-    if ((e = alloc((void**)&rin, vlen * sizeof(double2)))) return e;
-    if (need32 && (e = alloc((void**)&x32, vlen * sizeof(float2)))) return e;
-    const size_t wsb = (size_t)R * std::max(matvec_workspace_bytes_per_rhs(P, 0),
-                                            need32 ? matvec_workspace_bytes_per_rhs(P, 1) : 0);
-    if ((e = alloc(&ws, wsb))) return e;
-    if ((e = alloc((void**)&part, (size_t)R * (m + 1) * nblk * sizeof(double2)))) return e;
-    if ((e = alloc((void**)&hc, (size_t)R * hstride * sizeof(double2)))) return e;
-    if ((e = alloc((void**)&hn, (size_t)R * hstride * sizeof(double2)))) return e;
-    if ((e = alloc((void**)&H, (size_t)R * (m + 1) * m * sizeof(double2)))) return e;
-    if ((e = alloc((void**)&cs, (size_t)R * m * sizeof(double2)))) return e;
-    if ((e = alloc((void**)&sn, (size_t)R * m * sizeof(double2)))) return e;
-    if ((e = alloc((void**)&g, (size_t)R * (m + 1) * sizeof(double2)))) return e;
-    if ((e = alloc((void**)&y, (size_t)R * hstride * sizeof(double2)))) return e;
-    if ((e = alloc((void**)&res, R * sizeof(double)))) return e;
-    if ((e = alloc((void**)&tolv, R * sizeof(double)))) return e;
-    if ((e = alloc((void**)&jdone, R * sizeof(int)))) return e;
-    if ((e = alloc((void**)&npart, (size_t)R * nb * sizeof(double)))) return e;
-    if ((e = alloc((void**)&reorth, R * sizeof(int)))) return e;
+    for (const Buf& q : buffers(need32)) {
+      if ((e = hipMalloc(q.ptr, q.bytes))) return e;
+      mem.push_back(*q.ptr);
+    }
     for (int i = 0; i < 2; ++i) {
       if ((e = hipHostMalloc((void**)&hjd[i], R * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent))) return e;
       if ((e = hipHostGetDevicePointer((void**)&djd[i], hjd[i], 0))) return e;
@@ -478,14 +486,16 @@ struct Member {
                        vec, N, J, sgn, with_norm ? npart : nullptr, flag);
   }
 
-  // ||b|| per RHS (queued; read after the stream synchronises)
-  void start() {
+  // ||b|| per RHS into the round slot's mapped norms (read by started() once that round completed)
+  void start(int slot) {
     norm(b, hn);
-    hipLaunchKernelGGL(norm_out_kernel, dim3((R + 63) / 64), dim3(64), 0, s, hn, hstride, R, dres[0]);
+    hipLaunchKernelGGL(norm_out_kernel, dim3((R + 63) / 64), dim3(64), 0, s, hn, hstride, R, dres[slot]);
+    rec[slot] = Rec{K_INIT, 0, epoch};
+    phase = WAIT;
   }
-  hipError_t started() {
+  hipError_t started(int slot) {
     for (int q = 0; q < R; ++q) {
-      bn[q] = hres[0][q];
+      bn[q] = hres[slot][q];
       if (!std::isfinite(bn[q])) return hipErrorInvalidValue;
     }
     if (ip == FMBEM_FP64) {
@@ -610,6 +620,16 @@ struct Member {
   void process(int slot) {
     const Rec rc = rec[slot];
     if (rc.kind == K_NONE || phase == DONE || rc.epoch != epoch) return;
+    if (rc.kind == K_INIT) {
+      const hipError_t e = started(slot);
+      if (e == hipErrorInvalidValue) {
+        bad_input = true;  // non-finite ||b||: this problem ends, the others go on
+        phase = DONE;
+      } else {
+        err = e;
+      }
+      return;
+    }
     if (rc.kind == K_TRUE) {
       ok = true;
       for (int q = 0; q < R; ++q) {
@@ -687,9 +707,9 @@ static void configure(Member& mb, const SolveCfg& c, const void* b, void* x) {
   mb.x = reinterpret_cast<double2*>(x);
 }
 
-// One round over the members (see Member); t counts rounds.
-static hipError_t run_round(const std::vector<Member*>& ms, long long t, hipStream_t s, hipEvent_t ev[2], bool tune) {
-  const int slot = (int)(t & 1);
+// The work of one round: pre() of every member, the members' operator applications in
+// grouped launches (one sequence per precision), post() of every member.
+static hipError_t round_enqueue(const std::vector<Member*>& ms, int slot, hipStream_t s, bool tune) {
   std::vector<GroupApply> g64, g32;
   for (Member* mb : ms) {
     mb->pre(slot);
@@ -703,6 +723,14 @@ static hipError_t run_round(const std::vector<Member*>& ms, long long t, hipStre
   if (!e) e = matvec_group(FMBEM_FP32, g32, s, tune);
   if (e) return e;
   for (Member* mb : ms) mb->post(slot);
+  return hipGetLastError();
+}
+
+// End of round t: its event, then the host reads round t-1's results (which finished
+// while round t runs).
+static hipError_t round_finish(const std::vector<Member*>& ms, long long t, hipStream_t s, hipEvent_t ev[2]) {
+  const int slot = (int)(t & 1);
+  hipError_t e;
   if ((e = hipEventRecord(ev[slot], s))) return e;
   if (t > 0) {
     if ((e = hipEventSynchronize(ev[slot ^ 1]))) return e;
@@ -720,17 +748,20 @@ static hipError_t run_group(const std::vector<Member*>& ms, hipStream_t s, bool 
   hipError_t e = hipSuccess;
   for (int i = 0; i < 2 && !e; ++i) e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
   if (!e) {
-    for (Member* mb : ms) mb->start();
+    for (Member* mb : ms) mb->start(0);
     e = hipStreamSynchronize(s);
-    for (Member* mb : ms)
-      if (!e) e = mb->started();
+    for (Member* mb : ms) {
+      if (!e) e = mb->started(0);
+      mb->rec[0] = Member::Rec{};
+    }
   }
   for (long long t = 0; !e; ++t) {
     bool live = false;
     for (Member* mb : ms)
       if (mb->phase != Member::DONE) live = true;
     if (!live) break;
-    e = run_round(ms, t, s, ev, tune);
+    e = round_enqueue(ms, (int)(t & 1), s, tune);
+    if (!e) e = round_finish(ms, t, s, ev);
   }
   if (!e) e = hipStreamSynchronize(s);
   for (int i = 0; i < 2; ++i)
@@ -745,6 +776,101 @@ static void fill_info(const Member& mb, fmbem_solve_info* info) {
     info[q].rel_residual = mb.rel[q];
   }
 }
+
+// Serving engine: continuous batching of solve requests.  Requests queue in arrival
+// order; at the start of every step the queue head is admitted while a slot is free
+// and its device footprint (Krylov basis, work vectors, operator workspace) fits the
+// byte budget.  A step is one round (see Member) over every admitted problem, whose
+// operator applications share grouped launches; finished problems free their memory
+// and leave their results for poll().  Plans stay resident with their owners.
+struct Engine {
+  hipStream_t s = nullptr;
+  size_t budget = 0;
+  int max_slots = 1;
+  size_t used = 0;
+  long long next_ticket = 1;
+  long long t = 0;  // rounds
+  struct Req {
+    long long ticket;
+    const Plan* P;
+    SolveCfg c;
+    int R;
+    const void* b;
+    void* x;
+    size_t bytes;
+  };
+  std::deque<Req> queue;
+  struct Slot {
+    std::unique_ptr<Member> mb;
+    long long ticket;
+    size_t bytes;
+  };
+  std::vector<Slot> active;
+  struct Result {
+    fmbem_status st;
+    std::vector<fmbem_solve_info> info;
+  };
+  std::unordered_map<long long, Result> results;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  std::mutex mu;
+
+  ~Engine() {
+    if (s) hipStreamSynchronize(s);
+    active.clear();
+    for (int i = 0; i < 2; ++i)
+      if (ev[i]) hipEventDestroy(ev[i]);
+  }
+
+  static size_t footprint(const Plan& P, const SolveCfg& c, int R) {
+    Member probe(P, nullptr, R, c.m);
+    return probe.footprint(c.ip == FMBEM_FP32);
+  }
+
+  void finish(Slot& sl, fmbem_status st) {
+    Result r{st, std::vector<fmbem_solve_info>(sl.mb->R)};
+    fill_info(*sl.mb, r.info.data());
+    results[sl.ticket] = std::move(r);
+    used -= sl.bytes;
+    sl.mb.reset();
+  }
+
+  hipError_t step() {
+    std::vector<Member*> ms;
+    for (Slot& sl : active) ms.push_back(sl.mb.get());
+    const int slot = (int)(t & 1);
+    hipError_t e = round_enqueue(ms, slot, s, false);
+    if (e) return e;
+    // admission in arrival order: the queue head waits until it fits
+    while (!queue.empty() && (int)active.size() < max_slots && used + queue.front().bytes <= budget) {
+      Req q = queue.front();
+      queue.pop_front();
+      Slot sl{std::unique_ptr<Member>(new Member(*q.P, s, q.R, q.c.m)), q.ticket, q.bytes};
+      configure(*sl.mb, q.c, q.b, q.x);
+      e = sl.mb->setup(q.c.ip == FMBEM_FP32);
+      if (e) {
+        results[q.ticket] = Result{st_of(e), std::vector<fmbem_solve_info>(q.R)};
+        if (e == hipErrorOutOfMemory) {
+          (void)hipGetLastError();
+          continue;
+        }
+        return e;
+      }
+      sl.mb->start(slot);
+      used += q.bytes;
+      ms.push_back(sl.mb.get());
+      active.push_back(std::move(sl));
+    }
+    if ((e = round_finish(ms, t, s, ev))) return e;
+    ++t;
+    // retire: a finished problem has no work in flight (its last step was the true residual
+    // read above, and it queued nothing since)
+    for (Slot& sl : active)
+      if (sl.mb->phase == Member::DONE)
+        finish(sl, sl.mb->bad_input ? FMBEM_ERR_INVALID_ARG : (sl.mb->ok ? FMBEM_OK : FMBEM_ERR_NOT_CONVERGED));
+    active.erase(std::remove_if(active.begin(), active.end(), [](const Slot& sl) { return !sl.mb; }), active.end());
+    return hipSuccess;
+  }
+};
 
 }  // namespace fmbem
 
@@ -800,4 +926,83 @@ extern "C" fmbem_status fmbem_solve_batch(int32_t n, const fmbem_plan* plans, co
     if (!ms[i]->ok) ok = false;
   }
   return ok ? FMBEM_OK : FMBEM_ERR_NOT_CONVERGED;
+}
+
+extern "C" fmbem_status fmbem_engine_create(size_t hbm_budget_bytes, int32_t max_slots, void* hip_stream,
+                                            fmbem_engine* out) {
+  if (!out || max_slots < 1 || hbm_budget_bytes == 0) return FMBEM_ERR_INVALID_ARG;
+  *out = nullptr;
+  std::unique_ptr<Engine> e(new Engine);
+  e->s = reinterpret_cast<hipStream_t>(hip_stream);
+  e->budget = hbm_budget_bytes;
+  e->max_slots = max_slots;
+  for (int i = 0; i < 2; ++i)
+    if (hipEventCreateWithFlags(&e->ev[i], hipEventDisableTiming) != hipSuccess) return FMBEM_ERR_DEVICE;
+  *out = reinterpret_cast<fmbem_engine>(e.release());
+  return FMBEM_OK;
+}
+
+extern "C" fmbem_status fmbem_engine_submit(fmbem_engine engine, fmbem_plan plan, const fmbem_solve_opts* opts,
+                                            int32_t n_rhs, const void* b, void* x, int64_t* ticket) {
+  if (!engine || !plan || !opts || !b || !x || !ticket || n_rhs < 1) return FMBEM_ERR_INVALID_ARG;
+  Engine& E = *reinterpret_cast<Engine*>(engine);
+  const Plan& P = *reinterpret_cast<Plan*>(plan);
+  SolveCfg c;
+  const fmbem_status st = solve_cfg(P, opts, n_rhs, c);
+  if (st != FMBEM_OK) return st;
+  const size_t bytes = Engine::footprint(P, c, n_rhs);
+  std::lock_guard<std::mutex> lk(E.mu);
+  if (bytes > E.budget) return FMBEM_ERR_ADMISSION;
+  *ticket = E.next_ticket++;
+  E.queue.push_back(Engine::Req{*ticket, &P, c, n_rhs, b, x, bytes});
+  return FMBEM_OK;
+}
+
+extern "C" fmbem_status fmbem_engine_step(fmbem_engine engine) {
+  if (!engine) return FMBEM_ERR_INVALID_ARG;
+  Engine& E = *reinterpret_cast<Engine*>(engine);
+  std::lock_guard<std::mutex> lk(E.mu);
+  if (E.active.empty() && E.queue.empty()) return FMBEM_OK;
+  return st_of(E.step());
+}
+
+extern "C" fmbem_status fmbem_engine_poll(fmbem_engine engine, int64_t ticket, int32_t* done,
+                                          fmbem_solve_info* info) {
+  if (!engine || !done) return FMBEM_ERR_INVALID_ARG;
+  Engine& E = *reinterpret_cast<Engine*>(engine);
+  std::lock_guard<std::mutex> lk(E.mu);
+  auto it = E.results.find(ticket);
+  if (it == E.results.end()) {
+    if (ticket < 1 || ticket >= E.next_ticket) return FMBEM_ERR_INVALID_ARG;
+    bool known = false;
+    for (const auto& q : E.queue)
+      if (q.ticket == ticket) known = true;
+    for (const auto& sl : E.active)
+      if (sl.ticket == ticket) known = true;
+    if (!known) return FMBEM_ERR_INVALID_ARG;  // already collected
+    *done = 0;
+    return FMBEM_OK;
+  }
+  *done = 1;
+  if (info) std::copy(it->second.info.begin(), it->second.info.end(), info);
+  const fmbem_status st = it->second.st;
+  E.results.erase(it);
+  return st;
+}
+
+extern "C" fmbem_status fmbem_engine_stats(fmbem_engine engine, int32_t* active, int32_t* queued,
+                                           size_t* bytes_in_use) {
+  if (!engine) return FMBEM_ERR_INVALID_ARG;
+  Engine& E = *reinterpret_cast<Engine*>(engine);
+  std::lock_guard<std::mutex> lk(E.mu);
+  if (active) *active = (int32_t)E.active.size();
+  if (queued) *queued = (int32_t)E.queue.size();
+  if (bytes_in_use) *bytes_in_use = E.used;
+  return FMBEM_OK;
+}
+
+extern "C" fmbem_status fmbem_engine_destroy(fmbem_engine engine) {
+  if (!engine) return FMBEM_ERR_INVALID_ARG;
+  delete reinterpret_cast<Engine*>(engine);
+  return FMBEM_OK;
 }

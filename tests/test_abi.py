@@ -98,6 +98,13 @@ def test_other_entry_points_reject_null_plan():
     assert lib.fmbem_plan_export(None, 0, None, 0) == 1
     assert lib.fmbem_solve(None, None, 1, None, None, None, None) == 1
     assert lib.fmbem_solve_batch(0, None, None, None, None, None, None, None) == 1
+    assert lib.fmbem_engine_create(0, 1, None, None) == 1
+    assert lib.fmbem_engine_submit(None, None, None, 1, None, None, None) == 1
+    assert lib.fmbem_engine_step(None) == 1
+    assert lib.fmbem_engine_poll(None, 1, None, None) == 1
+    assert lib.fmbem_engine_stats(None, None, None, None) == 1
+    assert lib.fmbem_engine_destroy(None) == 1
+    assert lib.fmbem_status_string(7) == b"request exceeds the engine's memory budget"
     assert lib.fmbem_incident_plane_wave(None, 1, None, 1.0, None, None) == 1
     assert lib.fmbem_status_string(5) == b"not converged"
     assert lib.fmbem_status_string(99) == b"unknown status"

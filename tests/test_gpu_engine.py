@@ -1,0 +1,144 @@
+"""Serving engine (continuous batching with admission by device bytes) through the C ABI:
+results against the oracle's dense LU (1e-6) and against fmbem_solve of the same problem
+(1e-9: shared launches may round differently), admission and error paths."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import bem, operator as op, solve
+from workloads import icosphere, tube_segment, Lattice
+from workloads.rng import unit_directions
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+# name: (geometry, grid, frequency Hz, n_t, n_rhs, inner precision)
+REQUESTS = [
+    ("sphere80_3x2", 1, (3, 2, 1), 700.0, 6, 2, "fp32"),
+    ("sphere80_4x3", 1, (4, 3, 1), 1100.0, 8, 1, "fp64"),
+    ("tube192_2x1x3", "tube", (2, 1, 3), 600.0, 6, 3, "fp32"),
+    ("sphere80_6x1", 1, (6, 1, 1), 400.0, 4, 2, "fp32"),
+    ("sphere80_2x2", 1, (2, 2, 1), 1500.0, 8, 1, "fp64"),
+]
+
+
+def _geometry(kind):
+    if kind == "tube":
+        v, t = tube_segment(0.08, 0.25, 32, 3)
+        return v, t, (0.2, 0.2, 0.25)
+    v, t = icosphere(kind, 0.1)
+    return v, t, (0.3, 0.3, 0.3)
+
+
+@pytest.fixture(scope="module")
+def requests():
+    import paper_2201_12050_amd as fm
+    out = []
+    for i, (name, kind, grid, f, nt, R, inner) in enumerate(REQUESTS):
+        v, t, pitch = _geometry(kind)
+        lat = Lattice(grid, pitch)
+        k = 2 * np.pi * f / 343.0
+        a = -1j / k
+        F = op.FMPBEM(v, t, lat, k, nt, a)
+        P = fm.Plan(v, t, grid, pitch, k, nt)
+        dirs = unit_directions(R, 300 + i)
+        b = bem.rhs_plane_wave(v, t, lat, k, a, dirs)
+        Ad = F.dense()
+        x_lu = np.stack([solve.lu_solve(Ad, b[q]) for q in range(R)])
+        out.append(dict(name=name, P=P, b=P.incident_plane_wave(dirs), x_lu=x_lu,
+                        opts=dict(tol=1e-9, inner=inner, ortho="dgks")))
+    return out
+
+
+def _drain(E, tickets, limit=100000):
+    out = {}
+    for _ in range(limit):
+        for t in list(tickets):
+            r = E.poll(t)
+            if r is not None:
+                out[t] = r
+                tickets.remove(t)
+        if not tickets:
+            return out
+        E.step()
+    raise AssertionError("engine did not finish")
+
+
+def test_engine_results_match_oracle_and_solve(requests):
+    import paper_2201_12050_amd as fm
+    E = fm.Engine(hbm_budget_bytes=8 << 30, max_slots=2)
+    tickets = {}
+    # two requests before the first step, the rest arrive while the engine runs
+    for i in (0, 1):
+        tickets[E.submit(requests[i]["P"], requests[i]["b"], **requests[i]["opts"])] = i
+    for _ in range(5):
+        E.step()
+    for i in (2, 3, 4):
+        tickets[E.submit(requests[i]["P"], requests[i]["b"], **requests[i]["opts"])] = i
+        E.step()
+        assert E.stats()["active"] <= 2
+    res = _drain(E, set(tickets))
+    for t, (x, infos, st) in res.items():
+        p = requests[tickets[t]]
+        assert st == 0, p["name"]
+        assert max(i["rel_residual"] for i in infos) <= 1e-9, p["name"]
+        xe = x.cpu().numpy().reshape(p["x_lu"].shape)
+        assert rel(xe, p["x_lu"]) < 1e-6, p["name"]
+        xa, _ = p["P"].solve(p["b"], **p["opts"])
+        assert rel(xe, xa.cpu().numpy().reshape(xe.shape)) < 1e-9, p["name"]
+    assert E.stats() == dict(active=0, queued=0, bytes_in_use=0)
+    E.close()
+
+
+def test_engine_admission_by_bytes(requests):
+    import paper_2201_12050_amd as fm
+    p = requests[1]
+    # a budget below one request: rejected at submit, nothing queued
+    E = fm.Engine(hbm_budget_bytes=4096, max_slots=4)
+    with pytest.raises(fm.FmbemError) as e:
+        E.submit(p["P"], p["b"], **p["opts"])
+    assert e.value.status == 7
+    assert E.stats()["queued"] == 0
+    E.close()
+    # a budget of one request at a time: the second waits in the queue until the first leaves
+    E = fm.Engine(hbm_budget_bytes=8 << 30, max_slots=4)
+    t0 = E.submit(p["P"], p["b"], **p["opts"])
+    E.step()
+    one = E.stats()["bytes_in_use"]
+    E.close()
+    E = fm.Engine(hbm_budget_bytes=one + one // 2, max_slots=4)
+    ta = E.submit(p["P"], p["b"], **p["opts"])
+    tb = E.submit(p["P"], p["b"].clone(), **p["opts"])
+    E.step()
+    assert E.stats() == dict(active=1, queued=1, bytes_in_use=one)
+    res = _drain(E, {ta, tb})
+    assert all(r[2] == 0 for r in res.values())
+    E.close()
+
+
+def test_engine_bad_input_and_unknown_ticket(requests):
+    import paper_2201_12050_amd as fm
+    p, q = requests[3], requests[4]
+    E = fm.Engine(hbm_budget_bytes=8 << 30, max_slots=4)
+    bad = p["b"].clone()
+    bad[0, 0, 0] = complex(float("nan"), 0.0)
+    tb = E.submit(p["P"], bad, **p["opts"])
+    tg = E.submit(q["P"], q["b"], **q["opts"])
+    res = _drain(E, {tb, tg})
+    assert res[tb][2] == 1
+    assert res[tg][2] == 0 and rel(res[tg][0].cpu().numpy().reshape(q["x_lu"].shape), q["x_lu"]) < 1e-6
+    d = __import__("ctypes").c_int32()
+    assert E._lib.fmbem_engine_poll(E._h, tg, __import__("ctypes").byref(d), None) == 1  # already collected
+    assert E._lib.fmbem_engine_poll(E._h, 12345, __import__("ctypes").byref(d), None) == 1
+    E.close()

@@ -182,6 +182,16 @@ def test_solve_gram_schmidt_modes(tiny, ortho):
         del _lib.ORTHO["bogus"]
 
 
+def test_solve_rejects_non_finite_rhs(tiny):
+    import paper_2201_12050_amd as fm
+    w, F, P = tiny["bm"]
+    bd = P.incident_plane_wave(w.plane_waves)
+    bd[0, 1, 2] = complex(float("nan"), 0.0)
+    with pytest.raises(fm.FmbemError) as e:
+        P.solve(bd, tol=1e-9, inner="fp32")
+    assert e.value.status == 1
+
+
 def test_solve_not_converged_reports_status(tiny):
     w, F, P = tiny["bm"]
     bd = P.incident_plane_wave(w.plane_waves)
