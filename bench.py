@@ -84,6 +84,111 @@ def cpu_baseline(w, its_per_solve, seconds_budget=30.0):
                        f"solves/s = 1 / (apply time x {its_per_solve} operator applications of the GPU FP64 solve)")}
 
 
+def batched_grids(fm, torch, args):
+    """Three uneven lattices (8x8, 12x20, 32x4 of 320-triangle spheres, 800 Hz, n_t = 10), 64
+    seeded plane waves each, solved together by one batched solve (grouped launches over the
+    three plans); 8 sampled right-hand sides checked against FP64 reference solves."""
+    from workloads import config_batched_grids
+    ws = config_batched_grids(args.batch_rhs)
+    plans = [fm.Plan.from_workload(w) for w in ws]
+    bs = [P.incident_plane_wave(w.plane_waves) for P, w in zip(plans, ws)]
+    out = {"workload": "sphere lattices 8x8, 12x20, 32x4 (320 triangles/cell, N = 20480/76800/40960), 800 Hz, "
+                       f"n_t=10, {args.batch_rhs} plane waves each", "n_rhs": 3 * args.batch_rhs}
+    rng = np.random.default_rng(2201120503)
+    sample = [(int(g), int(q)) for g, q in zip(rng.integers(0, 3, 8), rng.integers(0, args.batch_rhs, 8))]
+    refs = {}
+    for g, q in sample:
+        if (g, q) not in refs:
+            refs[(g, q)] = plans[g].solve(bs[g][q:q + 1].contiguous(), tol=1e-12, inner="fp64")[0]
+    for mode in ("fp32", "fp64"):
+        opts = dict(tol=args.tol, inner=mode, ortho=args.ortho)
+        fm.solve_batch([(P, b, None, opts) for P, b in zip(plans, bs)])  # warm-up (tile tuning)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = fm.solve_batch([(P, b, None, opts) for P, b in zip(plans, bs)])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        err = max(torch.linalg.vector_norm(res[g][0][q] - refs[(g, q)][0]).item() /
+                  torch.linalg.vector_norm(refs[(g, q)][0]).item() for g, q in sample)
+        out[mode] = {"rhs_per_s": 3 * args.batch_rhs / dt, "ms": dt * 1e3,
+                     "iterations": [r[1][0]["iterations"] for r in res],
+                     "max_rel_residual": max(i["rel_residual"] for r in res for i in r[1]),
+                     "sampled_solution_error": err}
+    for P in plans:
+        P.close()
+    return out
+
+
+def serving(fm, torch, args, mode):
+    """Continuous-batching engine under seeded Poisson arrivals: lattices n1 x n2 (n1 ~ U{4..64},
+    n2 ~ U{1..16}) of 320-triangle spheres, f ~ U[200, 2000] Hz (n_t = 10 up to 1.2 kHz, else 12),
+    R ~ U{1..32} plane waves per request.  Each request's plan is built at its arrival; latency =
+    completion - scheduled arrival.  Every request's FP64 true residual is checked, and 8 sampled
+    requests against an FP64 reference solve after the run."""
+    from workloads import icosphere, serving_stream
+    from workloads.rng import unit_directions
+    v, t = icosphere(2, 0.1)
+    n_warm, n_meas = args.serving_warmup, args.serving_requests
+    reqs = serving_stream(n_warm + n_meas, rate=args.serving_rate)
+    E = fm.Engine(hbm_budget_bytes=int(args.serving_budget_gib * 2**30), max_slots=args.serving_slots)
+    opts = dict(tol=args.tol, inner=mode, ortho=args.ortho)
+    rng = np.random.default_rng(2201120506)
+    sampled = set(int(i) for i in rng.choice(np.arange(n_warm, n_warm + n_meas), size=min(8, n_meas), replace=False))
+    keep = {}
+    pending = {}
+    lat, worst_res, rhs_done = [], 0.0, 0
+    t_first = t_last = None
+    nxt = 0
+    finished = 0
+    torch.cuda.synchronize()
+    start = time.perf_counter()
+    while finished < len(reqs):
+        now = time.perf_counter() - start
+        while nxt < len(reqs) and reqs[nxt][0] <= now:
+            arr, grid, f, R, seed = reqs[nxt]
+            k = 2 * np.pi * f / 343.0
+            P = fm.Plan(v, t, grid, (0.3, 0.3, 0.3), k, 10 if f <= 1200.0 else 12)
+            b = P.incident_plane_wave(unit_directions(R, seed))
+            pending[E.submit(P, b, **opts)] = (nxt, arr, P, b)
+            nxt += 1
+            now = time.perf_counter() - start
+        if not pending:
+            time.sleep(max(0.0, min(reqs[nxt][0] - now, 0.01)))
+            continue
+        E.step()
+        for tk in list(pending):
+            r = E.poll(tk)
+            if r is None:
+                continue
+            idx, arr, P, b = pending.pop(tk)
+            x, infos, st = r
+            t_done = time.perf_counter() - start
+            finished += 1
+            if idx >= n_warm:
+                lat.append(t_done - arr)
+                t_first = arr if t_first is None else min(t_first, arr)
+                t_last = t_done if t_last is None else max(t_last, t_done)
+                rhs_done += len(infos)
+                worst_res = max(worst_res, max(i["rel_residual"] for i in infos))
+            if idx in sampled:
+                keep[idx] = (P, b, x)
+            else:
+                P.close()
+    E.close()
+    errs = []
+    for idx, (P, b, x) in keep.items():
+        xr = P.solve(b, tol=1e-12, inner="fp64")[0]
+        errs.append(torch.linalg.vector_norm(x - xr).item() / torch.linalg.vector_norm(xr).item())
+        P.close()
+    span = t_last - t_first
+    return {"mode": mode, "requests": n_meas, "warmup_requests": n_warm, "arrival_rate_per_s": args.serving_rate,
+            "latency_ms": {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3,
+                           "max": max(lat) * 1e3},
+            "requests_per_s": n_meas / span, "rhs_per_s": rhs_done / span,
+            "max_rel_residual": worst_res, "sampled_solution_error": max(errs) if errs else None,
+            "budget_gib": args.serving_budget_gib, "max_slots": args.serving_slots}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +202,14 @@ def main():
     ap.add_argument("--matvec-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--grid", type=int, nargs=2, default=(16, 16))
+    ap.add_argument("--batch-rhs", type=int, default=64, help="plane waves per lattice of the batched-grids run")
+    ap.add_argument("--no-batched-grids", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=100, help="measured requests of the serving run")
+    ap.add_argument("--serving-warmup", type=int, default=10)
+    ap.add_argument("--serving-rate", type=float, default=20.0, help="Poisson arrival rate (requests/s)")
+    ap.add_argument("--serving-budget-gib", type=float, default=96.0)
+    ap.add_argument("--serving-slots", type=int, default=32)
+    ap.add_argument("--serving-modes", nargs="*", default=["fp32"], choices=["fp32", "fp64"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -232,11 +345,17 @@ def main():
                      "avg_launch_us": avg_near * 1e6, "algorithmic_flops_per_launch": flops_near},
         "cpu_baseline": None,
     }
+    P.close()
+    if not args.no_batched_grids:
+        out["batched_grids"] = batched_grids(fm, torch, args)
+        print(f"[bench] batched grids {out['batched_grids']}", file=sys.stderr, flush=True)
+    if args.serving_requests > 0:
+        out["serving"] = [serving(fm, torch, args, m) for m in args.serving_modes]
+        print(f"[bench] serving {out['serving']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         its64 = inf64[-1]["iterations"] + 2
         out["cpu_baseline"] = cpu_baseline(w, its64)
     print(json.dumps(out), flush=True)
-    P.close()
     return 0
 
 

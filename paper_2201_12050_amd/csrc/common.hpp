@@ -94,8 +94,10 @@ size_t matvec_workspace_bytes_per_rhs(const Plan& P, int precision);
 
 // stream-ordered operator application (all arguments validated by the caller);
 // y64 (FP32 only, optional): write the result as complex128 there instead of y
+// tune: autotune the tile shapes of a new problem signature (blocks the host once per
+// signature); otherwise a shape tuned earlier for the same signature, or the default.
 hipError_t matvec_launch(const Plan& P, int precision, int R, const void* x, void* y, void* ws,
-                         hipStream_t s, void* y64 = nullptr);
+                         hipStream_t s, void* y64 = nullptr, bool tune = true);
 
 // one operator application of a group (see matvec_group)
 struct GroupApply {

@@ -125,7 +125,7 @@ static char* near_partials(const Plan& P, int R, void* ws) {
 // lhat_b = Lambda_b mhat_b for every bin: a GEMV in place for few right-hand sides, a
 // batched MFMA GEMM into the second grid from kM2lGemmRhs on; returns the buffer of lhat
 template <typename T>
-static hipError_t m2l_apply(const Plan& P, int R, void* ws, hipStream_t s, void** lhat) {
+static hipError_t m2l_apply(const Plan& P, int R, void* ws, hipStream_t s, void** lhat, bool tune) {
   const int prec = sizeof(T) == 8 ? 0 : 1;
   if (R < kM2lGemmRhs) {
     *lhat = ws;
@@ -138,7 +138,7 @@ static hipError_t m2l_apply(const Plan& P, int R, void* ws, hipStream_t s, void*
   j.batch = P.B;
   std::vector<NearJob> jobs{j};
   *lhat = out;
-  return near_launch<T>(jobs, s, tuned_shape<T>(2, jobs, s), 2);
+  return near_launch<T>(jobs, s, tune ? tuned_shape<T>(2, jobs, s) : cached_shape<T>(2, jobs), 2);
 }
 
 template <typename T>
@@ -171,7 +171,8 @@ NearJob l2t_job(const Plan& P, int R, void* ws, const void* lhat, void* y, void*
 }
 
 template <typename T>
-static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* ws, hipStream_t s, void* y64) {
+static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* ws, hipStream_t s, void* y64,
+                           bool tune) {
   const int prec = sizeof(T) == 8 ? 0 : 1;
   const int p = P.p;
   P.prof.active = P.prof.mask != 0 && (P.prof.calls++ % P.prof.period) == 0;
@@ -180,7 +181,7 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
   {
     std::vector<NearJob> jobs;
     near_s2m_jobs<T>(P, R, x, ws, jobs);
-    const int shape = tuned_shape<T>(0, jobs, s);
+    const int shape = tune ? tuned_shape<T>(0, jobs, s) : cached_shape<T>(0, jobs);
     ev = prof_begin(P, 0 + 6 * prec, s);
     hipError_t e = near_launch<T>(jobs, s, shape, 0);
     if (e != hipSuccess) return e;
@@ -201,7 +202,7 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
   prof_end(P, 2 + 6 * prec, ev, s);
   ev = prof_begin(P, 3 + 6 * prec, s);
   void* lhat = nullptr;
-  e = m2l_apply<T>(P, R, ws, s, &lhat);
+  e = m2l_apply<T>(P, R, ws, s, &lhat, tune);
   if (e != hipSuccess) return e;
   prof_end(P, 3 + 6 * prec, ev, s);
   ev = prof_begin(P, 4 + 6 * prec, s);
@@ -211,7 +212,7 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
   // [5] L2T with the fixed-order sum of the near partials
   {
     std::vector<NearJob> jobs{l2t_job<T>(P, R, ws, lhat, y, y64)};
-    const int shape = tuned_shape<T>(1, jobs, s);
+    const int shape = tune ? tuned_shape<T>(1, jobs, s) : cached_shape<T>(1, jobs);
     ev = prof_begin(P, 5 + 6 * prec, s);
     e = near_launch<T>(jobs, s, shape, 1);
   }
@@ -241,7 +242,7 @@ static hipError_t matvec_group_t(const std::vector<GroupApply>& g, hipStream_t s
     }
     void* lhat = nullptr;
     if ((e = grid_dft_launch<T>(a.ws, a.R * P.p, P.grid, P.fft, false, true, s)) != hipSuccess) return e;
-    if ((e = m2l_apply<T>(P, a.R, a.ws, s, &lhat)) != hipSuccess) return e;
+    if ((e = m2l_apply<T>(P, a.R, a.ws, s, &lhat, tune)) != hipSuccess) return e;
     if ((e = grid_dft_launch<T>(lhat, a.R * P.p, P.grid, P.fft, true, true, s)) != hipSuccess) return e;
     l2t.push_back(l2t_job<T>(P, a.R, a.ws, lhat, a.y, a.y64));
   }
@@ -253,14 +254,14 @@ static hipError_t matvec_group_t(const std::vector<GroupApply>& g, hipStream_t s
 hipError_t matvec_group(int precision, const std::vector<GroupApply>& g, hipStream_t s, bool tune) {
   if (g.empty()) return hipSuccess;
   if (g.size() == 1)
-    return matvec_launch(*g[0].P, precision, g[0].R, g[0].x, g[0].y, g[0].ws, s, g[0].y64);
+    return matvec_launch(*g[0].P, precision, g[0].R, g[0].x, g[0].y, g[0].ws, s, g[0].y64, tune);
   return precision == FMBEM_FP64 ? matvec_group_t<double>(g, s, tune) : matvec_group_t<float>(g, s, tune);
 }
 
 hipError_t matvec_launch(const Plan& P, int precision, int R, const void* x, void* y, void* ws, hipStream_t s,
-                         void* y64) {
-  return precision == FMBEM_FP64 ? matvec_t<double>(P, R, x, y, ws, s, nullptr)
-                                 : matvec_t<float>(P, R, x, y, ws, s, y64);
+                         void* y64, bool tune) {
+  return precision == FMBEM_FP64 ? matvec_t<double>(P, R, x, y, ws, s, nullptr, tune)
+                                 : matvec_t<float>(P, R, x, y, ws, s, y64, tune);
 }
 
 }  // namespace fmbem
