@@ -53,6 +53,7 @@ typedef enum { FMBEM_BURTON_MILLER = 0, FMBEM_CBIE = 1 } fmbem_formulation;
 
 typedef struct fmbem_plan_s* fmbem_plan;
 typedef struct fmbem_engine_s* fmbem_engine;
+typedef struct fmbem_solver_s* fmbem_solver;
 
 /* Unit-cell mesh in cell-local coordinates: the cell centre (= expansion centre
  * of its FMM box, Sec. 3.2) is the origin.  Copied during fmbem_plan_create. */
@@ -159,6 +160,27 @@ typedef struct {
  * FMBEM_ERR_INVALID_ARG for bad options or a non-finite ||b||. */
 fmbem_status fmbem_solve(fmbem_plan plan, const fmbem_solve_opts* opts, int32_t n_rhs,
                          const void* b, void* x, fmbem_solve_info* info, void* hip_stream);
+
+/* Persistent form of fmbem_solve for repeated solves with one plan and one
+ * right-hand-side count (Sec. 2.4, Sec. 3.5, Sec. 4, as fmbem_solve): the
+ * Krylov basis, work vectors and operator workspace are allocated once by
+ * fmbem_solver_create (opts validated and fixed there) and reused by every
+ * fmbem_solver_run.  The solver runs on its own stream (default priority),
+ * ordered after the work queued on hip_stream when run is called; run blocks
+ * until the solution is in x.  b, x: device complex128 [n_rhs][n_cells]
+ * [n_dof_cell], staged into the solver's buffers (x is the initial guess).
+ * use_graphs = 1: each Arnoldi step that neither starts nor ends a restart
+ * cycle is captured as a HIP graph per (step index, round parity) the second
+ * time it occurs and replayed from then on, also in later runs; the iterates
+ * are identical to eager execution.  Status and info as fmbem_solve.  A solver
+ * is not safe for concurrent runs; the plan must outlive it.
+ * graph_stats: graphs instantiated and rounds replayed so far (either may be NULL). */
+fmbem_status fmbem_solver_create(fmbem_plan plan, const fmbem_solve_opts* opts, int32_t n_rhs,
+                                 int32_t use_graphs, fmbem_solver* out);
+fmbem_status fmbem_solver_run(fmbem_solver solver, const void* b, void* x, fmbem_solve_info* info,
+                              void* hip_stream);
+fmbem_status fmbem_solver_graph_stats(fmbem_solver solver, int32_t* graphs, int64_t* replays);
+fmbem_status fmbem_solver_destroy(fmbem_solver solver);
 
 /* Several independent solves (plans of different lattices, meshes, frequencies,
  * right-hand-side counts and options) advanced in lockstep: in every round each

@@ -63,7 +63,8 @@ EXPORTS = ["fmbem_plan_create", "fmbem_plan_query", "fmbem_plan_destroy", "fmbem
            "fmbem_solve", "fmbem_incident_plane_wave", "fmbem_incident_point_source", "fmbem_plan_profile",
            "fmbem_plan_profile_read", "fmbem_status_string", "fmbem_solve_batch", "fmbem_engine_create",
            "fmbem_engine_submit", "fmbem_engine_step", "fmbem_engine_poll", "fmbem_engine_stats",
-           "fmbem_engine_destroy"]
+           "fmbem_engine_destroy", "fmbem_solver_create", "fmbem_solver_run", "fmbem_solver_graph_stats",
+           "fmbem_solver_destroy"]
 STAGES = tuple(f"{s}_{p}" for p in ("fp64", "fp32") for s in ("near", "reduce", "fft", "m2l", "ifft", "l2t"))
 
 _lib = None
@@ -84,6 +85,10 @@ def load():
     lib.fmbem_plan_export.argtypes = [vp, ct.c_int32, vp, ct.c_size_t]
     lib.fmbem_matvec.argtypes = [vp, ct.c_int32, ct.c_int32, vp, vp, vp, ct.c_size_t, vp]
     lib.fmbem_solve.argtypes = [vp, ct.POINTER(SolveOpts), ct.c_int32, vp, vp, ct.POINTER(SolveInfo), vp]
+    lib.fmbem_solver_create.argtypes = [vp, ct.POINTER(SolveOpts), ct.c_int32, ct.c_int32, ct.POINTER(vp)]
+    lib.fmbem_solver_run.argtypes = [vp, vp, vp, ct.POINTER(SolveInfo), vp]
+    lib.fmbem_solver_graph_stats.argtypes = [vp, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int64)]
+    lib.fmbem_solver_destroy.argtypes = [vp]
     lib.fmbem_engine_create.argtypes = [ct.c_size_t, ct.c_int32, vp, ct.POINTER(vp)]
     lib.fmbem_engine_submit.argtypes = [vp, vp, ct.POINTER(SolveOpts), ct.c_int32, vp, vp, ct.POINTER(ct.c_int64)]
     lib.fmbem_engine_step.argtypes = [vp]
@@ -161,6 +166,52 @@ def solve_batch(problems, stream=None, raise_on_not_converged=True):
         out.append((xs[i], _info_dicts(info[off:off + nr[i]])))
         off += nr[i]
     return out
+
+
+class Solver:
+    """Persistent solver for repeated solves with one plan and RHS count (buffers allocated
+    once; optional HIP-graph replay of the Arnoldi steps)."""
+
+    def __init__(self, plan, n_rhs: int = 1, graphs: bool = False, **opts):
+        self._lib = load()
+        self.plan = plan
+        self.n_rhs = int(n_rhs)
+        o = solve_opts(**opts)
+        h = ct.c_void_p()
+        check(self._lib.fmbem_solver_create(plan._h, ct.byref(o), self.n_rhs, 1 if graphs else 0, ct.byref(h)),
+              "fmbem_solver_create")
+        self._h = h
+
+    def close(self):
+        if self._h:
+            self._lib.fmbem_solver_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, b, x=None, stream=None, raise_on_not_converged=True):
+        import torch
+        if b.dtype != torch.complex128 or not b.is_cuda or not b.is_contiguous():
+            raise ValueError("b must be a contiguous complex128 CUDA tensor")
+        if b.numel() != self.n_rhs * self.plan.n_dof:
+            raise ValueError("b does not match the solver's right-hand-side count")
+        if x is None:
+            x = torch.zeros_like(b)
+        info = (SolveInfo * self.n_rhs)()
+        st = self._lib.fmbem_solver_run(self._h, ct.c_void_p(b.data_ptr()), ct.c_void_p(x.data_ptr()), info,
+                                        _stream_ptr(stream))
+        if st != 0 and (st != 5 or raise_on_not_converged):
+            check(st, "fmbem_solver_run")
+        return x, _info_dicts(info)
+
+    def graph_stats(self):
+        g, r = ct.c_int32(), ct.c_int64()
+        check(self._lib.fmbem_solver_graph_stats(self._h, ct.byref(g), ct.byref(r)), "fmbem_solver_graph_stats")
+        return dict(graphs=g.value, replays=r.value)
 
 
 class Engine:

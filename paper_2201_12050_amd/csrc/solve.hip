@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <deque>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <unordered_map>
@@ -383,6 +384,7 @@ struct Member {
   int its = 0, refs = 0;
   bool ok = false;
   bool bad_input = false;
+  bool emit = true;  // false: post() updates host state only (a captured graph replays the kernels)
   hipError_t err = hipSuccess;
   std::vector<double> bn, rel;
   // this round's application
@@ -486,6 +488,18 @@ struct Member {
                        vec, N, J, sgn, with_norm ? npart : nullptr, flag);
   }
 
+  // back to the state before start() (a persistent solver runs several solves)
+  void reset() {
+    phase = RUN_TRUE;
+    after_close = RUN_TRUE;
+    j = 0;
+    ++epoch;
+    rec[0] = rec[1] = Rec{};
+    its = refs = 0;
+    ok = bad_input = false;
+    emit = true;
+    err = hipSuccess;
+  }
   // ||b|| per RHS into the round slot's mapped norms (read by started() once that round completed)
   void start(int slot) {
     norm(b, hn);
@@ -590,21 +604,23 @@ struct Member {
         phase = RUN_ARN;
         break;
       case K_ARN: {
-        double2* wv = V + (size_t)(j + 1) * vlen;
-        // Gram-Schmidt: h = V^H w (and ||w||^2 as the last dot), w -= V h (with |w|^2 partials);
-        // second pass h2 = V^H w, w -= V h2, h += h2 where the DGKS criterion (or the mode) asks for it
-        mdot(V, j + 2, wv, hc, 0);
-        maxpy(V, hc, wv, j + 1, -1.0, true);
-        if (ortho != FMBEM_ORTHO_ONCE) {
-          hipLaunchKernelGGL(reorth_check_kernel, dim3(R), dim3(256), 0, s, ortho, nb, npart, hc, hstride, j, jdone,
-                             reorth);
-          mdot(V, j + 1, wv, hc, 3, y, reorth);
-          maxpy(V, y, wv, j + 1, -1.0, true, reorth);
+        if (emit) {
+          double2* wv = V + (size_t)(j + 1) * vlen;
+          // Gram-Schmidt: h = V^H w (and ||w||^2 as the last dot), w -= V h (with |w|^2 partials);
+          // second pass h2 = V^H w, w -= V h2, h += h2 where the DGKS criterion (or the mode) asks for it
+          mdot(V, j + 2, wv, hc, 0);
+          maxpy(V, hc, wv, j + 1, -1.0, true);
+          if (ortho != FMBEM_ORTHO_ONCE) {
+            hipLaunchKernelGGL(reorth_check_kernel, dim3(R), dim3(256), 0, s, ortho, nb, npart, hc, hstride, j, jdone,
+                               reorth);
+            mdot(V, j + 1, wv, hc, 3, y, reorth);
+            maxpy(V, y, wv, j + 1, -1.0, true, reorth);
+          }
+          hipLaunchKernelGGL(norm_givens_kernel, dim3(R), dim3(256), 0, s, npart, nb, m, j, hc, hstride, hn, H, cs,
+                             sn, g, res, jdone, djd[slot], tolv);
+          hipLaunchKernelGGL(scale_kernel, vgrid(), dim3(256), 0, s, wv, hn, hstride, wv,
+                             gm_prec == FMBEM_FP32 ? x32 : nullptr, N);
         }
-        hipLaunchKernelGGL(norm_givens_kernel, dim3(R), dim3(256), 0, s, npart, nb, m, j, hc, hstride, hn, H, cs, sn,
-                           g, res, jdone, djd[slot], tolv);
-        hipLaunchKernelGGL(scale_kernel, vgrid(), dim3(256), 0, s, wv, hn, hstride, wv,
-                           gm_prec == FMBEM_FP32 ? x32 : nullptr, N);
         ++its;
         ++j;
         // a full cycle (or the iteration budget) ends here; what follows needs this step's flags
@@ -872,6 +888,108 @@ struct Engine {
   }
 };
 
+// Persistent solver: one Member whose buffers live across solves, on an internal stream
+// (ordered after the caller's stream on entry; the call blocks until done).  With graphs,
+// every pure Arnoldi round (no cycle start or end in it) is captured once per (Arnoldi index,
+// round parity) after it ran eagerly once (so that tile shapes are tuned), and later rounds
+// with the same key replay the graph while the host state advances as in an eager round.
+// b and x are staged in the solver's own buffers so that the graphs see fixed addresses.
+struct Solver {
+  const Plan& P;
+  SolveCfg c;
+  int R;
+  bool graphs = false;
+  hipStream_t si = nullptr;
+  std::unique_ptr<Member> mb;
+  double2* bbuf = nullptr;
+  double2* xbuf = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipEvent_t join = nullptr;
+  std::map<std::pair<int, int>, int> seen;
+  std::map<std::pair<int, int>, hipGraphExec_t> execs;
+  long long replays = 0;
+
+  Solver(const Plan& p, const SolveCfg& c_, int R_) : P(p), c(c_), R(R_) {}
+  ~Solver() {
+    if (si) hipStreamSynchronize(si);
+    for (auto& kv : execs) hipGraphExecDestroy(kv.second);
+    mb.reset();
+    if (bbuf) hipFree(bbuf);
+    if (xbuf) hipFree(xbuf);
+    for (int i = 0; i < 2; ++i)
+      if (ev[i]) hipEventDestroy(ev[i]);
+    if (join) hipEventDestroy(join);
+    if (si) hipStreamDestroy(si);
+  }
+  hipError_t setup() {
+    hipError_t e;
+    if ((e = hipStreamCreateWithFlags(&si, hipStreamNonBlocking))) return e;
+    for (int i = 0; i < 2; ++i)
+      if ((e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming))) return e;
+    if ((e = hipEventCreateWithFlags(&join, hipEventDisableTiming))) return e;
+    mb.reset(new Member(P, si, R, c.m));
+    const size_t vb = (size_t)R * P.n * P.C * sizeof(double2);
+    if ((e = hipMalloc((void**)&bbuf, vb))) return e;
+    if ((e = hipMalloc((void**)&xbuf, vb))) return e;
+    configure(*mb, c, bbuf, xbuf);
+    return mb->setup(c.ip == FMBEM_FP32);
+  }
+  // one round, eager, captured, or replayed
+  hipError_t round(long long t) {
+    Member& m = *mb;
+    const int slot = (int)(t & 1);
+    const bool pure = graphs && m.phase == Member::RUN_ARN && P.prof.mask == 0;
+    if (!pure) return round_enqueue({&m}, slot, si, true);
+    const std::pair<int, int> key{m.j, slot};
+    auto it = execs.find(key);
+    if (it != execs.end()) {
+      m.emit = false;
+      m.pre(slot);
+      m.post(slot);
+      m.emit = true;
+      ++replays;
+      return hipGraphLaunch(it->second, si);
+    }
+    if (seen[key]++ == 0) return round_enqueue({&m}, slot, si, true);
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamBeginCapture(si, hipStreamCaptureModeThreadLocal);
+    if (e) return e;
+    const hipError_t er = round_enqueue({&m}, slot, si, true);
+    e = hipStreamEndCapture(si, &gr);
+    if (er) {
+      if (gr) hipGraphDestroy(gr);
+      return er;
+    }
+    if (e) return e;
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    hipGraphDestroy(gr);
+    if (e) return e;
+    execs[key] = ex;
+    return hipGraphLaunch(ex, si);
+  }
+  hipError_t run(const void* b, void* x, hipStream_t caller) {
+    const size_t vb = (size_t)R * P.n * P.C * sizeof(double2);
+    hipError_t e;
+    if ((e = hipEventRecord(join, caller))) return e;
+    if ((e = hipStreamWaitEvent(si, join, 0))) return e;
+    if ((e = hipMemcpyAsync(bbuf, b, vb, hipMemcpyDeviceToDevice, si))) return e;
+    if ((e = hipMemcpyAsync(xbuf, x, vb, hipMemcpyDeviceToDevice, si))) return e;
+    Member& m = *mb;
+    m.reset();
+    m.start(0);
+    if ((e = hipStreamSynchronize(si))) return e;
+    if ((e = m.started(0))) return e;
+    m.rec[0] = Member::Rec{};
+    for (long long t = 0; m.phase != Member::DONE; ++t) {
+      if ((e = round(t))) return e;
+      if ((e = round_finish({&m}, t, si, ev))) return e;
+    }
+    if ((e = hipMemcpyAsync(x, xbuf, vb, hipMemcpyDeviceToDevice, si))) return e;
+    return hipStreamSynchronize(si);
+  }
+};
+
 }  // namespace fmbem
 
 using namespace fmbem;
@@ -1004,5 +1122,46 @@ extern "C" fmbem_status fmbem_engine_stats(fmbem_engine engine, int32_t* active,
 extern "C" fmbem_status fmbem_engine_destroy(fmbem_engine engine) {
   if (!engine) return FMBEM_ERR_INVALID_ARG;
   delete reinterpret_cast<Engine*>(engine);
+  return FMBEM_OK;
+}
+
+extern "C" fmbem_status fmbem_solver_create(fmbem_plan plan, const fmbem_solve_opts* opts, int32_t n_rhs,
+                                            int32_t use_graphs, fmbem_solver* out) {
+  if (!plan || !opts || !out || n_rhs < 1 || (use_graphs != 0 && use_graphs != 1)) return FMBEM_ERR_INVALID_ARG;
+  *out = nullptr;
+  const Plan& P = *reinterpret_cast<Plan*>(plan);
+  SolveCfg c;
+  const fmbem_status st = solve_cfg(P, opts, n_rhs, c);
+  if (st != FMBEM_OK) return st;
+  std::unique_ptr<Solver> sv(new Solver(P, c, n_rhs));
+  sv->graphs = use_graphs == 1;
+  const hipError_t e = sv->setup();
+  if (e) return st_of(e);
+  *out = reinterpret_cast<fmbem_solver>(sv.release());
+  return FMBEM_OK;
+}
+
+extern "C" fmbem_status fmbem_solver_run(fmbem_solver solver, const void* b, void* x, fmbem_solve_info* info,
+                                         void* hip_stream) {
+  if (!solver || !b || !x) return FMBEM_ERR_INVALID_ARG;
+  Solver& sv = *reinterpret_cast<Solver*>(solver);
+  const hipError_t e = sv.run(b, x, reinterpret_cast<hipStream_t>(hip_stream));
+  if (e == hipErrorInvalidValue) return FMBEM_ERR_INVALID_ARG;
+  if (e) return st_of(e);
+  if (info) fill_info(*sv.mb, info);
+  return sv.mb->ok ? FMBEM_OK : FMBEM_ERR_NOT_CONVERGED;
+}
+
+extern "C" fmbem_status fmbem_solver_graph_stats(fmbem_solver solver, int32_t* graphs, int64_t* replays) {
+  if (!solver) return FMBEM_ERR_INVALID_ARG;
+  const Solver& sv = *reinterpret_cast<Solver*>(solver);
+  if (graphs) *graphs = (int32_t)sv.execs.size();
+  if (replays) *replays = sv.replays;
+  return FMBEM_OK;
+}
+
+extern "C" fmbem_status fmbem_solver_destroy(fmbem_solver solver) {
+  if (!solver) return FMBEM_ERR_INVALID_ARG;
+  delete reinterpret_cast<Solver*>(solver);
   return FMBEM_OK;
 }

@@ -104,6 +104,10 @@ def test_other_entry_points_reject_null_plan():
     assert lib.fmbem_engine_poll(None, 1, None, None) == 1
     assert lib.fmbem_engine_stats(None, None, None, None) == 1
     assert lib.fmbem_engine_destroy(None) == 1
+    assert lib.fmbem_solver_create(None, None, 1, 0, None) == 1
+    assert lib.fmbem_solver_run(None, None, None, None, None) == 1
+    assert lib.fmbem_solver_graph_stats(None, None, None) == 1
+    assert lib.fmbem_solver_destroy(None) == 1
     assert lib.fmbem_status_string(7) == b"request exceeds the engine's memory budget"
     assert lib.fmbem_incident_plane_wave(None, 1, None, 1.0, None, None) == 1
     assert lib.fmbem_status_string(5) == b"not converged"
