@@ -9,7 +9,8 @@ one unit plane wave at 30 degrees azimuth.  Synthetic, seeded inputs.
 A step is one solve of A x = b: FP64 GMRES(30) Arnoldi around the FP32 operator
 (near field, S2M, grid DFT, M2L, inverse DFT, L2T on the device) with FP64
 iterative refinement until the FP64 true relative residual is <= tol.  The
-plan (operator data) is built before the timed region and stays resident.
+plan (operator data) and the persistent solver's buffers are set up before the
+timed region and stay resident.
 `value` = solves/s of that FP32-refined form; the FP64 form, matvec rates and
 latencies are reported beside it.
 
@@ -242,8 +243,10 @@ def main():
         return torch.linalg.vector_norm(x - xref).item() / xref_n
 
     def timed_solves(inner, steps, warmup, profile):
+        # persistent solver: Krylov basis and work buffers allocated here, before the timed region
+        sv = fm.Solver(P, 1, tol=args.tol, inner=inner, ortho=args.ortho)
         for _ in range(warmup):
-            P.solve(b, tol=args.tol, inner=inner, ortho=args.ortho)
+            sv.run(b)
         torch.cuda.synchronize()
         if profile:
             # only the dominant kernel is bracketed by events inside the timed region, on every
@@ -254,7 +257,7 @@ def main():
         t_start = time.perf_counter()
         for _ in range(steps):
             t1 = time.perf_counter()
-            x, info = P.solve(b, tol=args.tol, inner=inner, ortho=args.ortho)
+            x, info = sv.run(b)
             lat.append(time.perf_counter() - t1)
             infos.append(info[0])
             xs.append(x)
@@ -264,6 +267,7 @@ def main():
         if profile:
             P.profile([])
         errs = [solution_error(x) for x in xs]   # every solution checked, outside the timed region
+        sv.close()
         return total, lat, infos, errs, prof
 
     tot32, lat32, inf32, err32, prof = timed_solves("fp32", args.steps, args.warmup, True)

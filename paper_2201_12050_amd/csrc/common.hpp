@@ -5,6 +5,8 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -84,6 +86,12 @@ struct Plan {
     long long count[FMBEM_N_STAGES] = {0};
   };
   mutable Prof prof;
+  // second stream (default priority) on which the far-field chain of a single-plan apply runs
+  // while the near field runs on the caller's stream; fork/join events; the lock keeps the
+  // event pair consistent between concurrent applications
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  std::unique_ptr<std::mutex> aux_mu{new std::mutex};
 };
 
 // record the start / end of a stage when that stage is being profiled (returns the start event)

@@ -57,8 +57,18 @@ void prof_end(const Plan& P, int stage, hipEvent_t start, hipStream_t s) {
 static std::mutex g_tune_mu;
 static std::map<std::vector<long long>, int> g_tuned;
 
+static bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+}
+
+template <typename T>
+int cached_shape(int kind, const std::vector<NearJob>& jobs);
+
 template <typename T>
 int tuned_shape(int kind, const std::vector<NearJob>& jobs, hipStream_t s) {
+  // no timing launches into a stream that is being captured: a shape measured earlier or the default
+  if (capturing(s)) return cached_shape<T>(kind, jobs);
   std::vector<long long> key{kind, (long long)sizeof(T)};
   for (const NearJob& j : jobs) {
     key.push_back(j.M);
@@ -170,12 +180,64 @@ NearJob l2t_job(const Plan& P, int R, void* ws, const void* lhat, void* y, void*
   return j;
 }
 
+// Far-field chain of one plan on the plan's second stream, overlapping the near field on the
+// caller's stream: fork after x is ready, S2M -> DFT -> M2L -> inverse DFT on the second
+// stream, join before the L2T GEMM.  Not used while the caller's stream is being captured.
+template <typename T>
+static hipError_t matvec_overlap(const Plan& P, int R, const void* x, void* y, void* ws, hipStream_t s, void* y64,
+                                 bool tune) {
+  const int prec = sizeof(T) == 8 ? 0 : 1;
+  const int n = P.n, p = P.p;
+  std::lock_guard<std::mutex> lk(*P.aux_mu);
+  hipError_t e;
+  if ((e = hipEventRecord(P.ev_fork, s))) return e;
+  if ((e = hipStreamWaitEvent(P.aux, P.ev_fork, 0))) return e;
+  // far chain [2]-[4] (S2M counted with the DFT stage)
+  hipEvent_t ev = prof_begin(P, 2 + 6 * prec, P.aux);
+  {
+    std::vector<NearJob> s2m{near_job(P, R, P.V0[prec], ws, p, n, x, SRC_X, DEST_GRID)};
+    const int shape = tune ? tuned_shape<T>(0, s2m, P.aux) : cached_shape<T>(0, s2m);
+    if ((e = near_launch<T>(s2m, P.aux, shape, 0))) return e;
+  }
+  if ((e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, false, true, P.aux))) return e;
+  prof_end(P, 2 + 6 * prec, ev, P.aux);
+  ev = prof_begin(P, 3 + 6 * prec, P.aux);
+  void* lhat = nullptr;
+  if ((e = m2l_apply<T>(P, R, ws, P.aux, &lhat, tune))) return e;
+  prof_end(P, 3 + 6 * prec, ev, P.aux);
+  ev = prof_begin(P, 4 + 6 * prec, P.aux);
+  if ((e = grid_dft_launch<T>(lhat, R * p, P.grid, P.fft, true, true, P.aux))) return e;
+  prof_end(P, 4 + 6 * prec, ev, P.aux);
+  if ((e = hipEventRecord(P.ev_join, P.aux))) return e;
+  // [0] near field on the caller's stream
+  {
+    std::vector<NearJob> jobs;
+    near_s2m_jobs<T>(P, R, x, ws, jobs);
+    jobs.pop_back();  // the S2M job ran on the second stream
+    const int shape = tune ? tuned_shape<T>(0, jobs, s) : cached_shape<T>(0, jobs);
+    ev = prof_begin(P, 0 + 6 * prec, s);
+    if ((e = near_launch<T>(jobs, s, shape, 0))) return e;
+    prof_end(P, 0 + 6 * prec, ev, s);
+  }
+  if ((e = hipStreamWaitEvent(s, P.ev_join, 0))) return e;
+  // [5] L2T with the fixed-order sum of the near partials
+  std::vector<NearJob> jobs{l2t_job<T>(P, R, ws, lhat, y, y64)};
+  const int shape = tune ? tuned_shape<T>(1, jobs, s) : cached_shape<T>(1, jobs);
+  ev = prof_begin(P, 5 + 6 * prec, s);
+  e = near_launch<T>(jobs, s, shape, 1);
+  prof_end(P, 5 + 6 * prec, ev, s);
+  return e;
+}
+
 template <typename T>
 static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* ws, hipStream_t s, void* y64,
                            bool tune) {
   const int prec = sizeof(T) == 8 ? 0 : 1;
   const int p = P.p;
   P.prof.active = P.prof.mask != 0 && (P.prof.calls++ % P.prof.period) == 0;
+  // FP64 only: the FP32 near-field GEMM keeps every CU occupied until it drains, so a
+  // concurrent far chain only delays it (measured on gfx950); the FP64 one leaves room
+  if (sizeof(T) == 8 && P.aux && P.n_far > 0 && !capturing(s)) return matvec_overlap<T>(P, R, x, y, ws, s, y64, tune);
   // [0] near field and S2M
   hipEvent_t ev = nullptr;
   {

@@ -605,6 +605,12 @@ void plan_release(Plan* P) {
     hipEventDestroy(m.second.second);
   }
   for (hipEvent_t e : P->prof.pool) hipEventDestroy(e);
+  if (P->aux) {
+    hipStreamSynchronize(P->aux);
+    hipStreamDestroy(P->aux);
+  }
+  if (P->ev_fork) hipEventDestroy(P->ev_fork);
+  if (P->ev_join) hipEventDestroy(P->ev_join);
   free_list(P->allocations);
   hipSetDevice(cur);
   delete P;
@@ -849,6 +855,9 @@ extern "C" fmbem_status fmbem_plan_create(const fmbem_cell_mesh* mesh, const fmb
   P->scale = std::min(1.0, std::max(1e-3, P->k * rmax));
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
   hipError_t e = plan_build(*P, geo, s);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming);
   if (e != hipSuccess) {
     plan_release(P);
     return to_status(e);
