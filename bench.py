@@ -349,7 +349,7 @@ def main():
         "m2l_fp32_GBps": m2l_bytes / m2l_avg / 1e9 if m2l_avg > 0 else None,
         "roofline": {"bound": "mfma", "kernel": "near field + S2M grouped GEMM (FP32 MFMA, three real products per complex product)",
                      "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_MFMA, "traffic": NEAR_FP32_TRAFFIC_BYTES,
+                     "frac": achieved / PEAK_FP32_MFMA, "traffic": None,
                      "avg_launch_us": avg_near * 1e6, "algorithmic_flops_per_launch": flops_near},
         "cpu_baseline": None,
     }

@@ -34,6 +34,10 @@ namespace fmbem {
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { using type = float4; };
+template <> struct Vec16<double> { using type = double2; };
+
 // Output layout of the 16x16x4 tiles (checked on gfx950): lane l holds column l % 16
 // and four rows q = 0..3: f32 rows 4g + q, f64 rows g + 4q (g = l / 16).
 template <typename T> struct nmf;
@@ -160,41 +164,72 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
 
   cplx<T> ra[APT];
   cplx<T> rb[BPT];
-  auto load = [&](int k0) {
-#pragma unroll
-    for (int q = 0; q < APT; ++q) ra[q] = mk<T>(0, 0);
-    if (ACOL) {
-      if (a_act && k0 + a_k < K) {
-        const cplx<T>* acol = A + (size_t)(k0 + a_k) * lda + m0 + a_row;
-        if (m0 + a_row + APT <= M) {
-#pragma unroll
-          for (int q = 0; q < APT; ++q) ra[q] = acol[q];
-        } else {
-          for (int q = 0; q < APT; ++q)
-            if (m0 + a_row + q < M) ra[q] = acol[q];
-        }
-      }
-    } else if (arow) {
-      if (k0 + KC <= K) {
-#pragma unroll
-        for (int q = 0; q < APT; ++q) ra[q] = arow[k0 + a_k + q];
-      } else {
-        for (int q = 0; q < APT; ++q)
-          if (k0 + a_k + q < K) ra[q] = arow[k0 + a_k + q];
-      }
-    }
-#pragma unroll
-    for (int e = 0; e < BPT; ++e) rb[e] = mk<T>(0, 0);
-    if (bcol) {
-      if (k0 + KC <= K) {
-#pragma unroll
-        for (int e = 0; e < BPT; ++e) rb[e] = bcol[k0 + b_k + e];
-      } else {
-        for (int e = 0; e < BPT; ++e)
-          if (k0 + b_k + e < K) rb[e] = bcol[k0 + b_k + e];
-      }
+  uint32_t amask = 0, bmask = 0;  // valid staged elements (bit q); invalid ones are stored as zero
+  // Global loads of one step, branch-free: every load reads a valid address (out-of-range
+  // rows, columns and k read a valid stand-in, masked to zero at the LDS store), so the
+  // loads stay in flight across the MFMAs of the current step.  When K is a multiple of
+  // the 16-byte unit (two FP32 or one FP64 complex value), whole units are loaded.
+  constexpr int EPL = 16 / sizeof(cplx<T>);
+  using VL = typename Vec16<T>::type;
+  const bool vec_ok = (K % EPL) == 0;
+  const bool a_in = !ACOL && a_act && m0 + a_row < M;
+  const cplx<T>* arow_ld = A + (size_t)(a_in ? m0 + a_row : 0) * lda;
+  const bool b_in = bcol != nullptr;
+  const cplx<T>* bcol_ld = b_in ? bcol : reinterpret_cast<const cplx<T>*>(jb.src);
+  auto unpack = [](const VL& v, cplx<T>* r) {
+    if constexpr (EPL == 2) {
+      r[0] = mk<T>(v.x, v.y);
+      r[1] = mk<T>(v.z, v.w);
+    } else {
+      r[0] = mk<T>(v.x, v.y);
     }
   };
+  // full step (k0 + KC <= K): whole 16-byte units, no per-step address or mask arithmetic
+  auto load_full = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < APT / EPL; ++q)
+      unpack(*reinterpret_cast<const VL*>(arow_ld + k0 + a_k + q * EPL), ra + q * EPL);
+    amask = a_in ? 0xFFFFFFFFu : 0u;
+#pragma unroll
+    for (int q = 0; q < BPT / EPL; ++q)
+      unpack(*reinterpret_cast<const VL*>(bcol_ld + k0 + b_k + q * EPL), rb + q * EPL);
+    bmask = b_in ? 0xFFFFFFFFu : 0u;
+  };
+  // any step: element loads from clamped indices, per-element masks
+  auto load_any = [&](int k0) {
+    amask = 0;
+    if (ACOL) {
+      const bool kin = a_act && k0 + a_k < K;
+      const cplx<T>* acol = A + (size_t)(kin ? k0 + a_k : 0) * lda + m0 + a_row;
+#pragma unroll
+      for (int q = 0; q < APT; ++q) {
+        const bool v = kin && m0 + a_row + q < M;
+        ra[q] = v ? acol[q] : mk<T>(0, 0);
+        amask |= (v ? 1u : 0u) << q;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < APT; ++q) {
+        const int kk = k0 + a_k + q;
+        const bool v = a_in && kk < K;
+        ra[q] = arow_ld[v ? kk : 0];
+        amask |= (v ? 1u : 0u) << q;
+      }
+    }
+    bmask = 0;
+#pragma unroll
+    for (int e = 0; e < BPT; ++e) {
+      const int kk = k0 + b_k + e;
+      const bool v = b_in && kk < K;
+      rb[e] = bcol_ld[v ? kk : 0];
+      bmask |= (v ? 1u : 0u) << e;
+    }
+  };
+  // the full-step path needs 16-byte aligned rows / columns and whole units per thread
+  constexpr bool kVecShape = !ACOL && APT % EPL == 0 && BPT % EPL == 0;
+  const bool vec_steps = kVecShape && vec_ok;
+  auto av = [&](int q, T x) { return ((amask >> q) & 1u) ? x : T(0); };
+  auto bv = [&](int q, T x) { return ((bmask >> q) & 1u) ? x : T(0); };
   // staged values -> LDS buffer b (whole chunks as one 16-byte store, partial chunks element-wise)
   auto store = [&](int b) {
     if (ACOL) {
@@ -204,8 +239,8 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
 #pragma unroll
         for (int q = 0; q < APT; ++q) {
           const int o = lds_slot(a_row + q, c);
-          reinterpret_cast<T*>(&Asm[b][0][o])[w] = ra[q].x;
-          reinterpret_cast<T*>(&Asm[b][1][o])[w] = ra[q].y;
+          reinterpret_cast<T*>(&Asm[b][0][o])[w] = av(q, ra[q].x);
+          reinterpret_cast<T*>(&Asm[b][1][o])[w] = av(q, ra[q].y);
         }
       }
     } else if (a_act) {
@@ -215,8 +250,8 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
           VK vr, vi;
 #pragma unroll
           for (int e = 0; e < CW; ++e) {
-            vr[e] = ra[c * CW + e].x;
-            vi[e] = ra[c * CW + e].y;
+            vr[e] = av(c * CW + e, ra[c * CW + e].x);
+            vi[e] = av(c * CW + e, ra[c * CW + e].y);
           }
           const int o = lds_slot(a_row, a_k / CW + c);
           Asm[b][0][o] = vr;
@@ -228,8 +263,8 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
         T* pi = reinterpret_cast<T*>(&Asm[b][1][o]) + a_k % CW;
 #pragma unroll
         for (int q = 0; q < APT; ++q) {
-          pr[q] = ra[q].x;
-          pi[q] = ra[q].y;
+          pr[q] = av(q, ra[q].x);
+          pi[q] = av(q, ra[q].y);
         }
       }
     }
@@ -239,8 +274,8 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
         VK vr, vi;
 #pragma unroll
         for (int e = 0; e < CW; ++e) {
-          vr[e] = rb[c * CW + e].x;
-          vi[e] = rb[c * CW + e].y;
+          vr[e] = bv(c * CW + e, rb[c * CW + e].x);
+          vi[e] = bv(c * CW + e, rb[c * CW + e].y);
         }
         const int o = lds_slot(b_col, b_k / CW + c);
         Bsm[b][0][o] = vr;
@@ -252,20 +287,14 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
       T* pi = reinterpret_cast<T*>(&Bsm[b][1][o]) + b_k % CW;
 #pragma unroll
       for (int e = 0; e < BPT; ++e) {
-        pr[e] = rb[e].x;
-        pi[e] = rb[e].y;
+        pr[e] = bv(e, rb[e].x);
+        pi[e] = bv(e, rb[e].y);
       }
     }
   };
 
-  const int nsteps = (K + KC - 1) / KC;
-  load(0);
-  store(0);
-  __syncthreads();
-  for (int st = 0; st < nsteps; ++st) {
-    const int b = st & 1;
-    const bool more = st + 1 < nsteps;
-    if (more) load((st + 1) * KC);
+  // MFMAs of one step from LDS buffer b
+  auto compute = [&](int b) {
     VK ar[RBW], ai[RBW], as[RBW];
 #pragma unroll
     for (int i = 0; i < RBW; ++i) {
@@ -289,8 +318,31 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
           p3[i][j] = nmf<T>::step(as[i][t], bs[t], p3[i][j]);
         }
     }
-    // the other buffer was last read before the previous barrier
-    if (more) store(b ^ 1);
+  };
+  // Pipeline over the k steps: the loads of step s+1 are issued before the MFMAs of step s
+  // and stored into the other LDS buffer after them (one barrier per step).  Steps whose
+  // successor is a full step run in a loop with only the 16-byte loads in its body; the
+  // last step and a ragged tail step are peeled off.
+  const int nsteps = (K + KC - 1) / KC;
+  const int nvec = vec_steps ? K / KC : 0;  // steps loaded by load_full
+  if (nvec > 0) load_full(0);
+  else load_any(0);
+  store(0);
+  __syncthreads();
+  int st = 0;
+  for (; st + 1 < nvec; ++st) {
+    load_full((st + 1) * KC);
+    // keep the loads ahead of the MFMAs (the scheduler would sink them to reuse registers)
+    __builtin_amdgcn_sched_barrier(0);
+    compute(st & 1);
+    store((st + 1) & 1);
+    __syncthreads();
+  }
+  for (; st < nsteps; ++st) {
+    const bool more = st + 1 < nsteps;
+    if (more) load_any((st + 1) * KC);
+    compute(st & 1);
+    if (more) store((st + 1) & 1);
     __syncthreads();
   }
 
