@@ -38,7 +38,7 @@ PEAK_HBM = 8.0e12
 # HBM bytes per launch of the FP32 near-field kernel on this workload (near_kernel<float, 64, 64, 4, 16>):
 # FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 from two rocprofv3 counter runs, the factors calibrated on a plain
 # 1 GiB device copy (profiles/near_kernel_fp32_sphere16x16_traffic.md); valid for the kernel as measured
-NEAR_FP32_TRAFFIC_BYTES = 170.7e6
+NEAR_FP32_TRAFFIC_BYTES = 187.3e6
 
 
 def percentile(v, q):
@@ -349,7 +349,7 @@ def main():
         "m2l_fp32_GBps": m2l_bytes / m2l_avg / 1e9 if m2l_avg > 0 else None,
         "roofline": {"bound": "mfma", "kernel": "near field + S2M grouped GEMM (FP32 MFMA, three real products per complex product)",
                      "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_MFMA, "traffic": None,
+                     "frac": achieved / PEAK_FP32_MFMA, "traffic": NEAR_FP32_TRAFFIC_BYTES,
                      "avg_launch_us": avg_near * 1e6, "algorithmic_flops_per_launch": flops_near},
         "cpu_baseline": None,
     }
