@@ -71,7 +71,12 @@ struct Plan {
   void* S[2] = {nullptr, nullptr};    // [n_near][n][n] complex, row-major
   void* V0[2] = {nullptr, nullptr};   // [p][n] complex, row-major, scaled
   void* U0[2] = {nullptr, nullptr};   // [n][p] complex, row-major, scaled
-  void* Lam[2] = {nullptr, nullptr};  // [B][p(col)][ldp] complex: per-bin column-major, scaled, /B
+  void* Lam[2] = {nullptr, nullptr};  // [Bc][p(col)][ldp] complex: per canonical bin, column-major, scaled, /B
+  // Lambda of bin -w is D Lambda(w) D, D = diag((-1)^n) (reciprocity of the translations), so only
+  // canonical bins (linear index <= that of the partner bin -w) are stored.
+  int Bc = 0;                // canonical bins
+  int* d_canon = nullptr;    // [B] canonical slot of every bin
+  int* d_pairs = nullptr;    // [Bc][2] (bin, partner bin or -1 when the bin is its own partner)
   size_t resident = 0;
   std::vector<void*> allocations;
   // stage profiling (HIP events on the caller's stream)
@@ -125,14 +130,15 @@ hipError_t matvec_group(int precision, const std::vector<GroupApply>& g, hipStre
 // ---------------------------------------------------------------------------
 constexpr int kMaxSeg = 32;        // near offsets per plan (3-D lattices with near radius 1 need 27)
 constexpr int kMaxGridDim = 4096;  // lattice cells per axis
-constexpr int kMaxJobs = 36;       // GEMM jobs per grouped launch (larger groups are split)
+constexpr int kMaxJobs = 34;       // GEMM jobs per grouped launch (larger groups are split)
 
 // Grouped complex GEMM jobs on the near-field kernel (near.hip): out = A B with A complex
 // [M][K] row-major (row stride lda) and N columns; column j is (RHS r, cell c) =
 // (j / C, j % C) of the job's lattice.  Its B column is x_{r, c - d} (SRC_X: src holds
 // [R][C][K], zero outside the lattice) or the padded-grid entry of cell c (SRC_GRID: src
 // holds [bin][R][K]).  A batched job (SRC_BATCH, M2L kernel) is batch independent GEMMs:
-// A_b column-major [K][lda] at A + b K lda, B_b columns at src + (b N + j) K, output
+// A_b column-major [K][lda] at A + slot(b) K lda (slot(b) = amap[b], or b without a map),
+// B_b columns at src + (b N + j) K, output
 // column j of product b at out + (b N + j) M.
 enum NearSrc : int { SRC_X = 0, SRC_GRID = 1, SRC_BATCH = 2 };
 enum NearDest : int {
@@ -146,6 +152,7 @@ struct NearJob {
   const void* src;
   const void* part;
   void* out64;
+  const int* amap;           // SRC_BATCH: A slot of every product (nullptr: slot = product index)
   int M, K, N;
   int lda;                   // A row stride (row-major) or column stride (SRC_BATCH)
   int batch;                 // products in a SRC_BATCH job (1 otherwise)
@@ -196,15 +203,19 @@ int near_num_shapes(int kind);
 template <typename T>
 hipError_t near_reduce_launch(const void* part, int ns, size_t len, void* y, void* y64, hipStream_t s);
 
+// flip_p > 0: the channels are [..][p] multipole coefficients and the spectrum of every
+// non-canonical bin carries the factor D = diag((-1)^n): applied to the forward output and
+// removed from the inverse input (then Lambda of the canonical partner serves that bin).
 template <typename T>
 hipError_t grid_dft_launch(void* buf, int channels, const int M[3], const int N[3], bool inverse,
-                           bool pruned, hipStream_t s);
+                           bool pruned, hipStream_t s, int flip_p = 0);
 
 // column stride (complex elements) of the per-bin column-major Lambda blocks
 int lambda_ld(int p);
-// per-bin M2L GEMV, in place in buf [B][R][p]
+// per-bin M2L GEMV, in place in buf [B][R][p]; one workgroup per canonical bin applies its Lambda
+// to the R vectors of the bin and of its partner
 template <typename T>
-hipError_t m2l_launch(const void* Lam, void* buf, int B, int R, int p, hipStream_t s);
+hipError_t m2l_launch(const void* Lam, const int* pairs, int Bc, void* buf, int R, int p, hipStream_t s);
 // right-hand-side count from which the M2L runs as a batched MFMA GEMM into a second buffer
 constexpr int kM2lGemmRhs = 8;
 

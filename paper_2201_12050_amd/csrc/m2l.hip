@@ -1,12 +1,14 @@
 // Per-bin M2L product of the diagonalised far field (Sec. 2.4, eq. (diagonalized);
 // Sec. 3.5, eq. (FMPBEMsystem)):  lhat_b = Lambda_b mhat_b  for every FFT bin b.
 //
-// HBM-bound for one right-hand side: Lambda (B p^2 complex) is streamed once.
-// Lambda_b is stored column-major with an even column stride ldp, so that two
-// consecutive rows form one aligned 16-byte (FP32) / 32-byte (FP64) load.  A
-// workgroup owns one bin: 4 wave groups split the columns j, each thread of a
-// group accumulates two rows for up to kRhs right-hand sides, and the groups are
-// summed in LDS.  The product is in place in the [bin][R][p] spectrum buffer.
+// HBM-bound for one right-hand side: Lambda (Bc p^2 complex, one matrix per pair of
+// bins w, -w) is streamed once.  Lambda is stored column-major with an even column
+// stride ldp, so that two consecutive rows form one aligned 16-byte (FP32) / 32-byte
+// (FP64) load.  A workgroup owns one canonical bin and applies its matrix to the R
+// vectors of the bin and the R vectors of its partner (whose spectrum carries the
+// factor D of the symmetry, see grid_dft_launch): 4 wave groups split the columns j,
+// each thread of a group accumulates two rows for up to kRhs vectors, and the groups
+// are summed in LDS.  The product is in place in the [bin][R][p] spectrum buffer.
 #include "common.hpp"
 
 namespace fmbem {
@@ -18,25 +20,33 @@ template <typename T> struct Pair;
 template <> struct Pair<float> { using type = float4; };
 template <> struct Pair<double> { using type = double4; };
 
+// vector t of the pair (bin a: t < R, partner: t >= R) in the spectrum buffer
 template <typename T>
-__global__ __launch_bounds__(256) void m2l_gemv_kernel(const cplx<T>* __restrict__ Lam, cplx<T>* __restrict__ buf,
-                                                       int R, int p, int ldp) {
+__device__ inline cplx<T>* pair_vec(cplx<T>* buf, int a, int b, int R, int p, int t) {
+  return buf + ((size_t)(t < R ? a : b) * R + (t < R ? t : t - R)) * p;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void m2l_gemv_kernel(const cplx<T>* __restrict__ Lam, const int* __restrict__ pairs,
+                                                       cplx<T>* __restrict__ buf, int R, int p, int ldp) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* xs = reinterpret_cast<cplx<T>*>(smem_raw);        // [kRhs][p]
   cplx<T>* red = xs + kRhs * p;                               // [kGroups][64][kRhs][2]
   using P2 = typename Pair<T>::type;
-  const int bin = blockIdx.x;
-  const cplx<T>* Lb = Lam + (size_t)bin * p * ldp;
-  cplx<T>* vb = buf + (size_t)bin * R * p;
+  const int c = blockIdx.x;
+  const int ba = pairs[2 * c], bb = pairs[2 * c + 1];
+  const int nv = bb >= 0 ? 2 * R : R;
+  const cplx<T>* Lb = Lam + (size_t)c * p * ldp;
   const int g = threadIdx.x / 64;
   const int rp = threadIdx.x % 64;                 // row pair (rows 2rp, 2rp+1); p <= 128
   const int jc = (p + kGroups - 1) / kGroups;
   const int j0 = g * jc, j1 = min(p, j0 + jc);
   const bool active = 2 * rp < p;
-  for (int r0 = 0; r0 < R; r0 += kRhs) {
-    const int nr = min(kRhs, R - r0);
+  for (int r0 = 0; r0 < nv; r0 += kRhs) {
+    const int nr = min(kRhs, nv - r0);
     __syncthreads();
-    for (int t = threadIdx.x; t < nr * p; t += blockDim.x) xs[t] = vb[(size_t)r0 * p + t];
+    for (int t = threadIdx.x; t < nr * p; t += blockDim.x)
+      xs[t] = pair_vec<T>(buf, ba, bb, R, p, r0 + t / p)[t % p];
     __syncthreads();
     cplx<T> a0[kRhs], a1[kRhs];
 #pragma unroll
@@ -76,8 +86,9 @@ __global__ __launch_bounds__(256) void m2l_gemv_kernel(const cplx<T>* __restrict
             s0 = cadd<T>(s0, red[((q * 64 + rp) * kRhs + r) * 2]);
             s1 = cadd<T>(s1, red[((q * 64 + rp) * kRhs + r) * 2 + 1]);
           }
-          vb[(size_t)(r0 + r) * p + 2 * rp] = s0;
-          if (2 * rp + 1 < p) vb[(size_t)(r0 + r) * p + 2 * rp + 1] = s1;
+          cplx<T>* out = pair_vec<T>(buf, ba, bb, R, p, r0 + r);
+          out[2 * rp] = s0;
+          if (2 * rp + 1 < p) out[2 * rp + 1] = s1;
         }
       }
     }
@@ -86,16 +97,19 @@ __global__ __launch_bounds__(256) void m2l_gemv_kernel(const cplx<T>* __restrict
 
 // generic fallback for p > 128: one thread per row
 template <typename T>
-__global__ void m2l_rows_kernel(const cplx<T>* __restrict__ Lam, cplx<T>* __restrict__ buf, int R, int p, int ldp) {
+__global__ void m2l_rows_kernel(const cplx<T>* __restrict__ Lam, const int* __restrict__ pairs,
+                                cplx<T>* __restrict__ buf, int R, int p, int ldp) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* xs = reinterpret_cast<cplx<T>*>(smem_raw);  // [kRhs][p]
-  const int bin = blockIdx.x;
-  const cplx<T>* Lb = Lam + (size_t)bin * p * ldp;
-  cplx<T>* vb = buf + (size_t)bin * R * p;
-  for (int r0 = 0; r0 < R; r0 += kRhs) {
-    const int nr = min(kRhs, R - r0);
+  const int c = blockIdx.x;
+  const int ba = pairs[2 * c], bb = pairs[2 * c + 1];
+  const int nv = bb >= 0 ? 2 * R : R;
+  const cplx<T>* Lb = Lam + (size_t)c * p * ldp;
+  for (int r0 = 0; r0 < nv; r0 += kRhs) {
+    const int nr = min(kRhs, nv - r0);
     __syncthreads();
-    for (int t = threadIdx.x; t < nr * p; t += blockDim.x) xs[t] = vb[(size_t)r0 * p + t];
+    for (int t = threadIdx.x; t < nr * p; t += blockDim.x)
+      xs[t] = pair_vec<T>(buf, ba, bb, R, p, r0 + t / p)[t % p];
     __syncthreads();
     for (int i = threadIdx.x; i < p; i += blockDim.x) {
       cplx<T> acc[kRhs];
@@ -109,7 +123,7 @@ __global__ void m2l_rows_kernel(const cplx<T>* __restrict__ Lam, cplx<T>* __rest
       }
 #pragma unroll
       for (int r = 0; r < kRhs; ++r)
-        if (r < nr) vb[(size_t)(r0 + r) * p + i] = acc[r];
+        if (r < nr) pair_vec<T>(buf, ba, bb, R, p, r0 + r)[i] = acc[r];
     }
   }
 }
@@ -117,21 +131,21 @@ __global__ void m2l_rows_kernel(const cplx<T>* __restrict__ Lam, cplx<T>* __rest
 int lambda_ld(int p) { return p + (p & 1); }
 
 template <typename T>
-hipError_t m2l_launch(const void* Lam, void* buf, int B, int R, int p, hipStream_t s) {
+hipError_t m2l_launch(const void* Lam, const int* pairs, int Bc, void* buf, int R, int p, hipStream_t s) {
   const int ldp = lambda_ld(p);
   if (p <= 128) {
     const size_t lds = (size_t)(kRhs * p + kGroups * 64 * kRhs * 2) * sizeof(cplx<T>);
-    hipLaunchKernelGGL(m2l_gemv_kernel<T>, dim3(B), dim3(256), lds, s, reinterpret_cast<const cplx<T>*>(Lam),
+    hipLaunchKernelGGL(m2l_gemv_kernel<T>, dim3(Bc), dim3(256), lds, s, reinterpret_cast<const cplx<T>*>(Lam), pairs,
                        reinterpret_cast<cplx<T>*>(buf), R, p, ldp);
   } else {
     const int threads = min(512, ((p + 63) / 64) * 64);
-    hipLaunchKernelGGL(m2l_rows_kernel<T>, dim3(B), dim3(threads), kRhs * p * sizeof(cplx<T>), s,
-                       reinterpret_cast<const cplx<T>*>(Lam), reinterpret_cast<cplx<T>*>(buf), R, p, ldp);
+    hipLaunchKernelGGL(m2l_rows_kernel<T>, dim3(Bc), dim3(threads), kRhs * p * sizeof(cplx<T>), s,
+                       reinterpret_cast<const cplx<T>*>(Lam), pairs, reinterpret_cast<cplx<T>*>(buf), R, p, ldp);
   }
   return hipGetLastError();
 }
 
-template hipError_t m2l_launch<double>(const void*, void*, int, int, int, hipStream_t);
-template hipError_t m2l_launch<float>(const void*, void*, int, int, int, hipStream_t);
+template hipError_t m2l_launch<double>(const void*, const int*, int, void*, int, int, hipStream_t);
+template hipError_t m2l_launch<float>(const void*, const int*, int, void*, int, int, hipStream_t);
 
 }  // namespace fmbem

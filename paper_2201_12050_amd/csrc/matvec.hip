@@ -139,13 +139,14 @@ static hipError_t m2l_apply(const Plan& P, int R, void* ws, hipStream_t s, void*
   const int prec = sizeof(T) == 8 ? 0 : 1;
   if (R < kM2lGemmRhs) {
     *lhat = ws;
-    return m2l_launch<T>(P.Lam[prec], ws, P.B, R, P.p, s);
+    return m2l_launch<T>(P.Lam[prec], P.d_pairs, P.Bc, ws, R, P.p, s);
   }
   void* out = second_grid<T>(P, R, ws);
   NearJob j = near_job(P, R, P.Lam[prec], out, P.p, P.p, ws, SRC_BATCH, DEST_SLICE);
   j.N = R;
   j.lda = lambda_ld(P.p);
   j.batch = P.B;
+  j.amap = P.d_canon;
   std::vector<NearJob> jobs{j};
   *lhat = out;
   return near_launch<T>(jobs, s, tune ? tuned_shape<T>(2, jobs, s) : cached_shape<T>(2, jobs), 2);
@@ -199,14 +200,14 @@ static hipError_t matvec_overlap(const Plan& P, int R, const void* x, void* y, v
     const int shape = tune ? tuned_shape<T>(0, s2m, P.aux) : cached_shape<T>(0, s2m);
     if ((e = near_launch<T>(s2m, P.aux, shape, 0))) return e;
   }
-  if ((e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, false, true, P.aux))) return e;
+  if ((e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, false, true, P.aux, p))) return e;
   prof_end(P, 2 + 6 * prec, ev, P.aux);
   ev = prof_begin(P, 3 + 6 * prec, P.aux);
   void* lhat = nullptr;
   if ((e = m2l_apply<T>(P, R, ws, P.aux, &lhat, tune))) return e;
   prof_end(P, 3 + 6 * prec, ev, P.aux);
   ev = prof_begin(P, 4 + 6 * prec, P.aux);
-  if ((e = grid_dft_launch<T>(lhat, R * p, P.grid, P.fft, true, true, P.aux))) return e;
+  if ((e = grid_dft_launch<T>(lhat, R * p, P.grid, P.fft, true, true, P.aux, p))) return e;
   prof_end(P, 4 + 6 * prec, ev, P.aux);
   if ((e = hipEventRecord(P.ev_join, P.aux))) return e;
   // [0] near field on the caller's stream
@@ -259,7 +260,7 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
   }
   // [2]-[4] DFT, M2L, inverse DFT
   ev = prof_begin(P, 2 + 6 * prec, s);
-  hipError_t e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, false, true, s);
+  hipError_t e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, false, true, s, p);
   if (e != hipSuccess) return e;
   prof_end(P, 2 + 6 * prec, ev, s);
   ev = prof_begin(P, 3 + 6 * prec, s);
@@ -268,7 +269,7 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
   if (e != hipSuccess) return e;
   prof_end(P, 3 + 6 * prec, ev, s);
   ev = prof_begin(P, 4 + 6 * prec, s);
-  e = grid_dft_launch<T>(lhat, R * p, P.grid, P.fft, true, true, s);
+  e = grid_dft_launch<T>(lhat, R * p, P.grid, P.fft, true, true, s, p);
   if (e != hipSuccess) return e;
   prof_end(P, 4 + 6 * prec, ev, s);
   // [5] L2T with the fixed-order sum of the near partials
@@ -303,9 +304,9 @@ static hipError_t matvec_group_t(const std::vector<GroupApply>& g, hipStream_t s
       continue;
     }
     void* lhat = nullptr;
-    if ((e = grid_dft_launch<T>(a.ws, a.R * P.p, P.grid, P.fft, false, true, s)) != hipSuccess) return e;
+    if ((e = grid_dft_launch<T>(a.ws, a.R * P.p, P.grid, P.fft, false, true, s, P.p)) != hipSuccess) return e;
     if ((e = m2l_apply<T>(P, a.R, a.ws, s, &lhat, tune)) != hipSuccess) return e;
-    if ((e = grid_dft_launch<T>(lhat, a.R * P.p, P.grid, P.fft, true, true, s)) != hipSuccess) return e;
+    if ((e = grid_dft_launch<T>(lhat, a.R * P.p, P.grid, P.fft, true, true, s, P.p)) != hipSuccess) return e;
     l2t.push_back(l2t_job<T>(P, a.R, a.ws, lhat, a.y, a.y64));
   }
   if (l2t.empty()) return hipSuccess;

@@ -115,7 +115,7 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
   }
   const int m0 = (local / ctiles) * ROWS;
   const int col0 = (local % ctiles) * COLS;
-  const cplx<T>* A = reinterpret_cast<const cplx<T>*>(jb.A) + (ACOL ? (size_t)bb * K * lda : 0);
+  const cplx<T>* A = reinterpret_cast<const cplx<T>*>(jb.A) + (ACOL ? (size_t)(jb.amap ? jb.amap[bb] : bb) * K * lda : 0);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;

@@ -431,13 +431,15 @@ __global__ void ogrid_kernel(int B, int N0, int N1, int N2, int M0, int M1, int 
   }
 }
 
-// Lambda'_b[j][i] (column-major per bin) = s^{n+n'}/B * sum_terms coef * Ohat_b[oidx]
-__global__ void lambda_kernel(const double2* __restrict__ Oh, int P2, int p, int B, const int* __restrict__ ptr,
-                              const double2* __restrict__ coef, const int* __restrict__ oidx,
-                              const double* __restrict__ sig, const int* __restrict__ nof, double invB,
-                              int ldp, double2* __restrict__ L64, float2* __restrict__ L32) {
+// Lambda'_c[j][i] (column-major per canonical bin c) = s^{n+n'}/B * sum_terms coef * Ohat_bin(c)[oidx]
+__global__ void lambda_kernel(const double2* __restrict__ Oh, int P2, int p, const int* __restrict__ pairs,
+                              const int* __restrict__ ptr, const double2* __restrict__ coef,
+                              const int* __restrict__ oidx, const double* __restrict__ sig,
+                              const int* __restrict__ nof, double invB, int ldp, double2* __restrict__ L64,
+                              float2* __restrict__ L32) {
   extern __shared__ double2 so[];
-  const int bin = blockIdx.y;
+  const int slot = blockIdx.y;
+  const int bin = pairs[2 * slot];
   for (int t = threadIdx.x; t < P2; t += blockDim.x) so[t] = Oh[(size_t)bin * P2 + t];
   __syncthreads();
   const size_t pp = (size_t)p * p;
@@ -454,7 +456,7 @@ __global__ void lambda_kernel(const double2* __restrict__ Oh, int P2, int p, int
     }
     const double f = sig[nof[i]] * sig[nof[j]] * invB;
     const double2 v = make_double2(re * f, im * f);
-    const size_t o = ((size_t)bin * p + j) * ldp + i;
+    const size_t o = ((size_t)slot * p + j) * ldp + i;
     L64[o] = v;
     if (L32) L32[o] = make_float2((float)v.x, (float)v.y);
     if (i == p - 1 && ldp > p) {  // zero the padding row of the column
@@ -721,14 +723,33 @@ static hipError_t plan_build(Plan& P, const std::vector<double>& geo, hipStream_
     hipMemcpyAsync(d_oidx, T.oidx.data(), T.oidx.size() * sizeof(int), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(d_coef, T.coef.data(), T.coef.size() * sizeof(double2), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(d_nof, nof.data(), p * sizeof(int), hipMemcpyHostToDevice, s);
+    // canonical bins: linear index not above that of the partner bin -w
+    std::vector<int> canon(P.B), pairs;
+    for (int b2 = 0; b2 < P.fft[2]; ++b2)
+      for (int b1 = 0; b1 < P.fft[1]; ++b1)
+        for (int b0 = 0; b0 < P.fft[0]; ++b0) {
+          const int L = b0 + P.fft[0] * (b1 + P.fft[1] * b2);
+          const int Lp = (P.fft[0] - b0) % P.fft[0] +
+                         P.fft[0] * ((P.fft[1] - b1) % P.fft[1] + P.fft[1] * ((P.fft[2] - b2) % P.fft[2]));
+          if (L > Lp) continue;
+          canon[L] = canon[Lp] = (int)(pairs.size() / 2);
+          pairs.push_back(L);
+          pairs.push_back(Lp == L ? -1 : Lp);
+        }
+    P.Bc = (int)(pairs.size() / 2);
+    if ((err = plan_alloc(P, (void**)&P.d_canon, P.B * sizeof(int))) != hipSuccess) break;
+    if ((err = plan_alloc(P, (void**)&P.d_pairs, pairs.size() * sizeof(int))) != hipSuccess) break;
+    hipMemcpyAsync(P.d_canon, canon.data(), P.B * sizeof(int), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(P.d_pairs, pairs.data(), pairs.size() * sizeof(int), hipMemcpyHostToDevice, s);
     const int ldp = lambda_ld(p);
-    const size_t nl = (size_t)P.B * p * ldp;
+    const size_t nl = (size_t)P.Bc * p * ldp;
     if ((err = plan_alloc(P, &P.Lam[0], nl * sizeof(double2))) != hipSuccess) break;
     if (want32 && (err = plan_alloc(P, &P.Lam[1], nl * sizeof(float2))) != hipSuccess) break;
     {
       const int bx = (int)std::min<size_t>(((size_t)p * p + 255) / 256, 64);
-      hipLaunchKernelGGL(lambda_kernel, dim3(bx, P.B), dim3(256), P2 * sizeof(double2), s, Og, P2, p, P.B, d_ptr,
-                         d_coef, d_oidx, d_sig, d_nof, 1.0 / P.B, ldp, (double2*)P.Lam[0], (float2*)P.Lam[1]);
+      hipLaunchKernelGGL(lambda_kernel, dim3(bx, P.Bc), dim3(256), P2 * sizeof(double2), s, Og, P2, p, P.d_pairs,
+                         d_ptr, d_coef, d_oidx, d_sig, d_nof, 1.0 / P.B, ldp, (double2*)P.Lam[0],
+                         (float2*)P.Lam[1]);
       if ((err = hipGetLastError()) != hipSuccess) break;
     }
     // host vectors (T) must outlive the async copies
@@ -931,20 +952,30 @@ extern "C" fmbem_status fmbem_plan_export(fmbem_plan plan, int32_t what, void* h
         break;
       }
       const size_t ldp = (size_t)lambda_ld(p);
-      tmp.resize((size_t)P.B * p * ldp);
+      tmp.resize((size_t)P.Bc * p * ldp);
       st = to_status(hipMemcpy(tmp.data(), P.Lam[0], tmp.size() * sizeof(double2), hipMemcpyDeviceToHost));
+      if (st != FMBEM_OK) break;
+      std::vector<int> canon(P.B), pairs(2 * (size_t)P.Bc);
+      st = to_status(hipMemcpy(canon.data(), P.d_canon, P.B * sizeof(int), hipMemcpyDeviceToHost));
+      if (st == FMBEM_OK)
+        st = to_status(hipMemcpy(pairs.data(), P.d_pairs, pairs.size() * sizeof(int), hipMemcpyDeviceToHost));
       if (st != FMBEM_OK) break;
       double2* h = reinterpret_cast<double2*>(host);
       std::vector<int> nof(p);
       for (int nn = 0; nn <= P.order; ++nn)
         for (int m = -nn; m <= nn; ++m) nof[nn * nn + nn + m] = nn;
-      for (int b = 0; b < P.B; ++b)
+      for (int b = 0; b < P.B; ++b) {
+        // a non-canonical bin holds D Lambda D of its canonical partner
+        const int c = canon[b];
+        const bool flip = pairs[2 * c] != b;
         for (int j = 0; j < p; ++j)
           for (int i = 0; i < p; ++i) {
-            const double f = P.B / (std::pow(P.scale, nof[i]) * std::pow(P.scale, nof[j]));
-            const double2 v = tmp[((size_t)b * p + j) * ldp + i];
+            double f = P.B / (std::pow(P.scale, nof[i]) * std::pow(P.scale, nof[j]));
+            if (flip && ((nof[i] + nof[j]) & 1)) f = -f;
+            const double2 v = tmp[((size_t)c * p + j) * ldp + i];
             h[(size_t)b * pp + (size_t)i * p + j] = make_double2(v.x * f, v.y * f);
           }
+      }
       break;
     }
     case 4: {
