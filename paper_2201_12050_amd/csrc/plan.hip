@@ -311,43 +311,41 @@ __device__ inline void regular_m(const double* v, const double* nrm, double k, i
 }
 
 // V0: one thread per (element b, m >= 0); q = 8 Duffy rule
-__global__ void p2m_kernel(const double* __restrict__ geom, int n, int nt, double k, QuadTab Qt,
-                           const double* __restrict__ isig, double2* __restrict__ V0) {
-  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= n * (nt + 1)) return;
-  const int b = tid / (nt + 1);
-  const int m = tid - b * (nt + 1);
+// V0: one wave per (element b, m >= 0), one lane per point of the 8x8 Duffy rule; the
+// lane contributions are summed by a fixed shuffle tree.
+__device__ inline double wave_sum64(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(64) void p2m_kernel(const double* __restrict__ geom, int n, int nt, double k,
+                                                 QuadTab Qt, const double* __restrict__ isig,
+                                                 double2* __restrict__ V0) {
+  const int b = blockIdx.x / (nt + 1);
+  const int m = blockIdx.x - b * (nt + 1);
+  const int lane = threadIdx.x;
   const Geo e = load_geo(geom, b);
-  double2 accp[21], accm[21];
-  for (int i = 0; i <= nt; ++i) { accp[i] = make_double2(0, 0); accm[i] = make_double2(0, 0); }
   double ba[3], cb[3], ca[3];
   for (int t = 0; t < 3; ++t) { ba[t] = e.b[t] - e.a[t]; cb[t] = e.c[t] - e.b[t]; ca[t] = e.c[t] - e.a[t]; }
   double cr[3] = {ba[1] * ca[2] - ba[2] * ca[1], ba[2] * ca[0] - ba[0] * ca[2], ba[0] * ca[1] - ba[1] * ca[0]};
   const double jac = sqrt(dot3(cr, cr));
   const int o = quad_off(8);
+  const int ia = lane / 8, ib = lane % 8;
+  const double u = Qt.t[o + ia], v = Qt.t[o + ib];
+  const double wt = Qt.w[o + ia] * u * jac * Qt.w[o + ib];
+  double y[3];
+  for (int t = 0; t < 3; ++t) y[t] = e.a[t] + u * (ba[t] + v * cb[t]);
   RegularWork W;
   double2 cI[21], dn[21];
+  regular_m(y, e.nrm, k, nt, m, W, cI, dn);
   const double sg = (m & 1) ? -1.0 : 1.0;
-  for (int ia = 0; ia < 8; ++ia) {
-    const double u = Qt.t[o + ia];
-    for (int ib = 0; ib < 8; ++ib) {
-      const double v = Qt.t[o + ib];
-      const double wt = Qt.w[o + ia] * u * jac * Qt.w[o + ib];
-      double y[3];
-      for (int t = 0; t < 3; ++t) y[t] = e.a[t] + u * (ba[t] + v * cb[t]);
-      regular_m(y, e.nrm, k, nt, m, W, cI, dn);
-      for (int nn = m; nn <= nt; ++nn) {
-        accp[nn].x += wt * dn[nn].x;
-        accp[nn].y += wt * dn[nn].y;
-        // conj(I_n^{-m}) = (-1)^m I_n^m => its gradient is (-1)^m conj(grad conj(I_n^m))
-        accm[nn].x += wt * sg * dn[nn].x;
-        accm[nn].y -= wt * sg * dn[nn].y;
-      }
-    }
-  }
   for (int nn = m; nn <= nt; ++nn) {
-    V0[(size_t)(nn * nn + nn + m) * n + b] = cscale<double>(accp[nn], isig[nn]);
-    if (m > 0) V0[(size_t)(nn * nn + nn - m) * n + b] = cscale<double>(accm[nn], isig[nn]);
+    const double re = wave_sum64(wt * dn[nn].x), im = wave_sum64(wt * dn[nn].y);
+    if (lane == 0) {
+      V0[(size_t)(nn * nn + nn + m) * n + b] = cscale<double>(make_double2(re, im), isig[nn]);
+      // conj(I_n^{-m}) = (-1)^m I_n^m => its gradient is (-1)^m conj(grad conj(I_n^m))
+      if (m > 0) V0[(size_t)(nn * nn + nn - m) * n + b] = cscale<double>(make_double2(sg * re, -sg * im), isig[nn]);
+    }
   }
 }
 
@@ -679,8 +677,7 @@ static hipError_t plan_build(Plan& P, const std::vector<double>& geo, hipStream_
     if ((err = plan_alloc(P, &P.U0[0], (size_t)p * n * sizeof(double2))) != hipSuccess) break;
     {
       const int th = n * (nt + 1);
-      hipLaunchKernelGGL(p2m_kernel, dim3((th + 63) / 64), dim3(64), 0, s, P.geom, n, nt, P.k, Q, d_isig,
-                         (double2*)P.V0[0]);
+      hipLaunchKernelGGL(p2m_kernel, dim3(th), dim3(64), 0, s, P.geom, n, nt, P.k, Q, d_isig, (double2*)P.V0[0]);
       hipLaunchKernelGGL(l2p_kernel, dim3((th + 63) / 64), dim3(64), 0, s, P.geom, n, nt, P.k, alpha, d_isig,
                          (double2*)P.U0[0]);
       if ((err = hipGetLastError()) != hipSuccess) break;

@@ -158,6 +158,18 @@ def test_tiny_config_matvec_and_solve(tiny, form):
     assert rel(xr.cpu().numpy().ravel(), x_lu) < 1e-6
 
 
+def test_matvec_many_rhs_matches_oracle(tiny):
+    # 832 right-hand sides on the 4x1 line of 320-triangle spheres: thousands of near-field
+    # workgroups in one launch and the M2L as a batched GEMM
+    w, F, P = tiny["bm"]
+    R = 832
+    x = random_complex((R, w.lattice.n_cells, w.n_dof_cell), 17)
+    ref = F.matvec(x)
+    xd = torch.from_numpy(x).cuda()
+    assert rel(P.matvec(xd, precision="fp64").cpu().numpy(), ref) < 1e-12
+    assert rel(P.matvec(xd.to(torch.complex64), precision="fp32").cpu().numpy(), ref) < 1e-5
+
+
 @pytest.mark.parametrize("ortho", ["once", "twice"])
 def test_solve_gram_schmidt_modes(tiny, ortho):
     # every Gram-Schmidt variant reaches the same LU solution (convergence is decided by the
