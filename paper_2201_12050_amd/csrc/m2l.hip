@@ -26,19 +26,21 @@ __device__ inline cplx<T>* pair_vec(cplx<T>* buf, int a, int b, int R, int p, in
   return buf + ((size_t)(t < R ? a : b) * R + (t < R ? t : t - R)) * p;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void m2l_gemv_kernel(const cplx<T>* __restrict__ Lam, const int* __restrict__ pairs,
-                                                       cplx<T>* __restrict__ buf, int R, int p, int ldp) {
+// RP row-pair threads per column group (p <= 2 RP) and kGroups groups: RP * kGroups threads
+template <typename T, int RP>
+__global__ __launch_bounds__(RP * kGroups) void m2l_gemv_kernel(const cplx<T>* __restrict__ Lam,
+                                                                 const int* __restrict__ pairs,
+                                                                 cplx<T>* __restrict__ buf, int R, int p, int ldp) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* xs = reinterpret_cast<cplx<T>*>(smem_raw);        // [kRhs][p]
-  cplx<T>* red = xs + kRhs * p;                               // [kGroups][64][kRhs][2]
+  cplx<T>* red = xs + kRhs * p;                               // [kGroups][RP][kRhs][2]
   using P2 = typename Pair<T>::type;
   const int c = blockIdx.x;
   const int ba = pairs[2 * c], bb = pairs[2 * c + 1];
   const int nv = bb >= 0 ? 2 * R : R;
   const cplx<T>* Lb = Lam + (size_t)c * p * ldp;
-  const int g = threadIdx.x / 64;
-  const int rp = threadIdx.x % 64;                 // row pair (rows 2rp, 2rp+1); p <= 128
+  const int g = threadIdx.x / RP;
+  const int rp = threadIdx.x % RP;                 // row pair (rows 2rp, 2rp+1)
   const int jc = (p + kGroups - 1) / kGroups;
   const int j0 = g * jc, j1 = min(p, j0 + jc);
   const bool active = 2 * rp < p;
@@ -73,8 +75,8 @@ __global__ __launch_bounds__(256) void m2l_gemv_kernel(const cplx<T>* __restrict
     }
 #pragma unroll
     for (int r = 0; r < kRhs; ++r) {
-      red[((g * 64 + rp) * kRhs + r) * 2] = a0[r];
-      red[((g * 64 + rp) * kRhs + r) * 2 + 1] = a1[r];
+      red[((g * RP + rp) * kRhs + r) * 2] = a0[r];
+      red[((g * RP + rp) * kRhs + r) * 2 + 1] = a1[r];
     }
     __syncthreads();
     if (g == 0 && active) {
@@ -83,8 +85,8 @@ __global__ __launch_bounds__(256) void m2l_gemv_kernel(const cplx<T>* __restrict
         if (r < nr) {
           cplx<T> s0 = red[(rp * kRhs + r) * 2], s1 = red[(rp * kRhs + r) * 2 + 1];
           for (int q = 1; q < kGroups; ++q) {
-            s0 = cadd<T>(s0, red[((q * 64 + rp) * kRhs + r) * 2]);
-            s1 = cadd<T>(s1, red[((q * 64 + rp) * kRhs + r) * 2 + 1]);
+            s0 = cadd<T>(s0, red[((q * RP + rp) * kRhs + r) * 2]);
+            s1 = cadd<T>(s1, red[((q * RP + rp) * kRhs + r) * 2 + 1]);
           }
           cplx<T>* out = pair_vec<T>(buf, ba, bb, R, p, r0 + r);
           out[2 * rp] = s0;
@@ -95,7 +97,7 @@ __global__ __launch_bounds__(256) void m2l_gemv_kernel(const cplx<T>* __restrict
   }
 }
 
-// generic fallback for p > 128: one thread per row
+// generic fallback for p > 256 (n_t >= 16): one thread per row
 template <typename T>
 __global__ void m2l_rows_kernel(const cplx<T>* __restrict__ Lam, const int* __restrict__ pairs,
                                 cplx<T>* __restrict__ buf, int R, int p, int ldp) {
@@ -135,8 +137,12 @@ hipError_t m2l_launch(const void* Lam, const int* pairs, int Bc, void* buf, int 
   const int ldp = lambda_ld(p);
   if (p <= 128) {
     const size_t lds = (size_t)(kRhs * p + kGroups * 64 * kRhs * 2) * sizeof(cplx<T>);
-    hipLaunchKernelGGL(m2l_gemv_kernel<T>, dim3(Bc), dim3(256), lds, s, reinterpret_cast<const cplx<T>*>(Lam), pairs,
-                       reinterpret_cast<cplx<T>*>(buf), R, p, ldp);
+    hipLaunchKernelGGL((m2l_gemv_kernel<T, 64>), dim3(Bc), dim3(64 * kGroups), lds, s,
+                       reinterpret_cast<const cplx<T>*>(Lam), pairs, reinterpret_cast<cplx<T>*>(buf), R, p, ldp);
+  } else if (p <= 256) {
+    const size_t lds = (size_t)(kRhs * p + kGroups * 128 * kRhs * 2) * sizeof(cplx<T>);
+    hipLaunchKernelGGL((m2l_gemv_kernel<T, 128>), dim3(Bc), dim3(128 * kGroups), lds, s,
+                       reinterpret_cast<const cplx<T>*>(Lam), pairs, reinterpret_cast<cplx<T>*>(buf), R, p, ldp);
   } else {
     const int threads = min(512, ((p + 63) / 64) * 64);
     hipLaunchKernelGGL(m2l_rows_kernel<T>, dim3(Bc), dim3(threads), kRhs * p * sizeof(cplx<T>), s,

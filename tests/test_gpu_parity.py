@@ -35,6 +35,8 @@ CASES = {
     "sphere80_5x3_ragged": (1, (5, 3, 1), 800.0, 4),
     "sphere80_line7": (1, (7, 1, 1), 1200.0, 8),
     "tube192_3x2x3": ("tube", (3, 2, 3), 600.0, 6),
+    # n_t = 12: p = 169 > 128 takes the wide form of the M2L GEMV
+    "sphere80_4x2_nt12": (1, (4, 2, 1), 1500.0, 12),
 }
 
 
