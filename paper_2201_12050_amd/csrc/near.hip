@@ -91,8 +91,10 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
   typedef T VK __attribute__((ext_vector_type(CW)));
   // two buffers (ping-pong over the k steps) x {Re, Im} of A and of B, in chunks; the
   // sums Re + Im of the third product are formed in registers after the fragment loads
-  __shared__ VK Asm[2][2][ROWS * 4];
-  __shared__ VK Bsm[2][2][COLS * 4];
+  // one LDS block: the operand buffers during the k loop, the output tile in the epilogue
+  __shared__ VK Ops[2 * 2 * (ROWS + COLS) * 4];
+  auto Asm = [&](int b, int c) -> VK* { return Ops + ((b * 2 + c) * (ROWS + COLS)) * 4; };
+  auto Bsm = [&](int b, int c) -> VK* { return Ops + ((b * 2 + c) * (ROWS + COLS) + ROWS) * 4; };
   using Acc = typename nmf<T>::acc;
 
   // logical workgroup (XCD-aware deal), job and tile
@@ -239,8 +241,8 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
 #pragma unroll
         for (int q = 0; q < APT; ++q) {
           const int o = lds_slot(a_row + q, c);
-          reinterpret_cast<T*>(&Asm[b][0][o])[w] = av(q, ra[q].x);
-          reinterpret_cast<T*>(&Asm[b][1][o])[w] = av(q, ra[q].y);
+          reinterpret_cast<T*>(&Asm(b, 0)[o])[w] = av(q, ra[q].x);
+          reinterpret_cast<T*>(&Asm(b, 1)[o])[w] = av(q, ra[q].y);
         }
       }
     } else if (a_act) {
@@ -254,13 +256,13 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
             vi[e] = av(c * CW + e, ra[c * CW + e].y);
           }
           const int o = lds_slot(a_row, a_k / CW + c);
-          Asm[b][0][o] = vr;
-          Asm[b][1][o] = vi;
+          Asm(b, 0)[o] = vr;
+          Asm(b, 1)[o] = vi;
         }
       } else {
         const int o = lds_slot(a_row, a_k / CW);
-        T* pr = reinterpret_cast<T*>(&Asm[b][0][o]) + a_k % CW;
-        T* pi = reinterpret_cast<T*>(&Asm[b][1][o]) + a_k % CW;
+        T* pr = reinterpret_cast<T*>(&Asm(b, 0)[o]) + a_k % CW;
+        T* pi = reinterpret_cast<T*>(&Asm(b, 1)[o]) + a_k % CW;
 #pragma unroll
         for (int q = 0; q < APT; ++q) {
           pr[q] = av(q, ra[q].x);
@@ -278,13 +280,13 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
           vi[e] = bv(c * CW + e, rb[c * CW + e].y);
         }
         const int o = lds_slot(b_col, b_k / CW + c);
-        Bsm[b][0][o] = vr;
-        Bsm[b][1][o] = vi;
+        Bsm(b, 0)[o] = vr;
+        Bsm(b, 1)[o] = vi;
       }
     } else {
       const int o = lds_slot(b_col, b_k / CW);
-      T* pr = reinterpret_cast<T*>(&Bsm[b][0][o]) + b_k % CW;
-      T* pi = reinterpret_cast<T*>(&Bsm[b][1][o]) + b_k % CW;
+      T* pr = reinterpret_cast<T*>(&Bsm(b, 0)[o]) + b_k % CW;
+      T* pi = reinterpret_cast<T*>(&Bsm(b, 1)[o]) + b_k % CW;
 #pragma unroll
       for (int e = 0; e < BPT; ++e) {
         pr[e] = bv(e, rb[e].x);
@@ -299,15 +301,15 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
 #pragma unroll
     for (int i = 0; i < RBW; ++i) {
       const int o = lds_slot(16 * (RBW * wr + i) + li, g);
-      ar[i] = Asm[b][0][o];
-      ai[i] = Asm[b][1][o];
+      ar[i] = Asm(b, 0)[o];
+      ai[i] = Asm(b, 1)[o];
       as[i] = ar[i] + ai[i];
     }
 #pragma unroll
     for (int j = 0; j < CBW; ++j) {
       const int o = lds_slot(16 * (CBW * wc + j) + li, g);
-      const VK br = Bsm[b][0][o];
-      const VK bi = Bsm[b][1][o];
+      const VK br = Bsm(b, 0)[o];
+      const VK bi = Bsm(b, 1)[o];
       const VK bs = br + bi;
 #pragma unroll
       for (int t = 0; t < CW; ++t)
@@ -346,43 +348,60 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
     __syncthreads();
   }
 
-  // epilogue: lane holds column li of each 16-column block and rows nmf<T>::row(g, q)
+  // Epilogue through LDS: the output tile is staged column by column (lane: column li of each
+  // 16-column block, rows nmf<T>::row(g, q)), then consecutive threads finish consecutive rows
+  // of a column, so partial-slice reads and output writes are contiguous runs (coalesced).
+  // The operand buffers hold the tile, in column chunks when it does not fit at once.
+  constexpr int LDC = ROWS + 1;  // padded column pitch (complex), spreads the lanes over banks
+  constexpr int CAP = (int)(sizeof(Ops) / sizeof(cplx<T>)) / LDC;
+  constexpr int CPP = CAP >= COLS ? COLS : (CAP >= 32 ? 32 : 16);  // columns per pass
+  static_assert(CAP >= 16, "LDS too small for the output tile");
+  cplx<T>* Cst = reinterpret_cast<cplx<T>*>(Ops);
   cplx<T>* out = reinterpret_cast<cplx<T>*>(jb.out);
   const cplx<T>* part = reinterpret_cast<const cplx<T>*>(jb.part);
   double2* out64 = reinterpret_cast<double2*>(jb.out64);
   const size_t slice = (size_t)N * M;
+  const int dest = jb.dest, nparts = jb.nparts;
+  for (int cb = 0; cb < COLS; cb += CPP) {
+    __syncthreads();  // previous readers of the LDS block are done
 #pragma unroll
-  for (int j = 0; j < CBW; ++j) {
-    const int col = col0 + 16 * (CBW * wc + j) + li;
-    if (col >= N) continue;
-    size_t base;
-    if (ACOL) {
-      base = ((size_t)bb * N + col) * M;
-    } else if (jb.dest == DEST_GRID) {
-      int r, i1, i2, i3;
-      cell_coords(jb, col, r, i1, i2, i3);
-      const size_t bin = (size_t)i1 + (size_t)jb.N0 * (i2 + (size_t)jb.N1 * i3);
-      base = (bin * jb.R + r) * M;
-    } else {
-      base = (size_t)col * M;
-    }
+    for (int j = 0; j < CBW; ++j) {
+      const int cl = 16 * (CBW * wc + j) + li - cb;
+      if (cl < 0 || cl >= CPP) continue;
 #pragma unroll
-    for (int i = 0; i < RBW; ++i) {
+      for (int i = 0; i < RBW; ++i)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int m = m0 + 16 * (RBW * wr + i) + nmf<T>::row(g, q);
-        if (m >= M) continue;
-        const T a = p1[i][j][q], bb = p2[i][j][q];
-        cplx<T> v = mk<T>(a - bb, p3[i][j][q] - a - bb);
-        if (jb.dest == DEST_FINAL) {
-          for (int s = 0; s < jb.nparts; ++s) v = cadd<T>(v, part[s * slice + base + m]);
-          if (out64) {
-            out64[base + m] = make_double2((double)v.x, (double)v.y);
-            continue;
-          }
+        for (int q = 0; q < 4; ++q) {
+          const int rl = 16 * (RBW * wr + i) + nmf<T>::row(g, q);
+          const T a = p1[i][j][q], b2 = p2[i][j][q];
+          Cst[cl * LDC + rl] = mk<T>(a - b2, p3[i][j][q] - a - b2);
         }
-        out[base + m] = v;
+    }
+    __syncthreads();
+    for (int e = tid; e < CPP * ROWS; e += 256) {
+      const int cl = e / ROWS, rl = e - cl * ROWS;
+      const int col = col0 + cb + cl, m = m0 + rl;
+      if (col >= N || m >= M) continue;
+      size_t base;
+      if (ACOL) {
+        base = ((size_t)bb * N + col) * M;
+      } else if (dest == DEST_GRID) {
+        int r, i1, i2, i3;
+        cell_coords(jb, col, r, i1, i2, i3);
+        const size_t bin = (size_t)i1 + (size_t)jb.N0 * (i2 + (size_t)jb.N1 * i3);
+        base = (bin * jb.R + r) * M;
+      } else {
+        base = (size_t)col * M;
       }
+      cplx<T> v = Cst[cl * LDC + rl];
+      if (dest == DEST_FINAL) {
+        for (int s2 = 0; s2 < nparts; ++s2) v = cadd<T>(v, part[s2 * slice + base + m]);
+        if (out64) {
+          out64[base + m] = make_double2((double)v.x, (double)v.y);
+          continue;
+        }
+      }
+      out[base + m] = v;
     }
   }
 }
