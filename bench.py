@@ -124,7 +124,59 @@ def batched_grids(fm, torch, args):
     return out
 
 
-def serving(fm, torch, args, mode):
+def barrier_sweep(fm, torch, args):
+    """Sonic-crystal barrier: 40 x 2 x 8 lattice of open tube cells (192 triangles, N = 122,880), a
+    point source 2 m in front, frequencies spread over 100 Hz - 2 kHz (n_t = 10 up to 1 kHz, else 14),
+    FP32-refined solves.  The plan of the next frequency is built on a worker thread (own stream)
+    while the current one solves; 2 frequencies are checked against FP64 reference solves."""
+    import queue
+    import threading
+    from workloads import config_barrier_r4b
+    idx = [int(round(i)) for i in np.linspace(0, 95, args.barrier_freqs)]
+    ready = queue.Queue(maxsize=1)
+    build_stream = torch.cuda.Stream()
+
+    def builder():
+        with torch.cuda.stream(build_stream):
+            for fi in idx:
+                w = config_barrier_r4b(fi)
+                t0 = time.perf_counter()
+                P = fm.Plan.from_workload(w, stream=build_stream)
+                b = P.incident_point_source(w.point_sources, stream=build_stream)
+                build_stream.synchronize()
+                ready.put((w, P, b, time.perf_counter() - t0))
+
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    th = threading.Thread(target=builder, daemon=True)
+    th.start()
+    rows, checks = [], []
+    for k in range(len(idx)):
+        w, P, b, t_build = ready.get()
+        t0 = time.perf_counter()
+        x, info = P.solve(b, tol=args.tol, inner="fp32", ortho=args.ortho, raise_on_not_converged=False)
+        torch.cuda.synchronize()
+        rows.append({"f_hz": round(w.frequency, 1), "n_t": w.order, "iterations": info[0]["iterations"],
+                     "rel_residual": info[0]["rel_residual"], "solve_ms": (time.perf_counter() - t0) * 1e3,
+                     "plan_build_ms": t_build * 1e3})
+        if k in (0, len(idx) - 1):
+            checks.append((P, b, x))
+        else:
+            P.close()
+    total = time.perf_counter() - t_start
+    th.join()
+    errs = []
+    for P, b, x in checks:
+        xr = P.solve(b, tol=1e-12, inner="fp64", raise_on_not_converged=False)[0]
+        errs.append(torch.linalg.vector_norm(x - xr).item() / torch.linalg.vector_norm(xr).item())
+        P.close()
+    return {"workload": "barrier 40x2x8 open tube cells (192 triangles, N = 122,880), point source, "
+                        f"{len(idx)} frequencies 100 Hz - 2 kHz", "frequencies_per_s": len(idx) / total,
+            "total_s": total, "max_rel_residual": max(r["rel_residual"] for r in rows),
+            "sampled_solution_error": max(errs), "per_frequency": rows}
+
+
+def serving(fm, torch, args, mode, rate):
     """Continuous-batching engine under seeded Poisson arrivals: lattices n1 x n2 (n1 ~ U{4..64},
     n2 ~ U{1..16}) of 320-triangle spheres, f ~ U[200, 2000] Hz (n_t = 10 up to 1.2 kHz, else 12),
     R ~ U{1..32} plane waves per request.  Each request's plan and incident field are built at
@@ -137,7 +189,7 @@ def serving(fm, torch, args, mode):
     from workloads.rng import unit_directions
     v, t = icosphere(2, 0.1)
     n_warm, n_meas = args.serving_warmup, args.serving_requests
-    reqs = serving_stream(n_warm + n_meas, rate=args.serving_rate)
+    reqs = serving_stream(n_warm + n_meas, rate=rate)
     E = fm.Engine(hbm_budget_bytes=int(args.serving_budget_gib * 2**30), max_slots=args.serving_slots)
     opts = dict(tol=args.tol, inner=mode, ortho=args.ortho)
     rng = np.random.default_rng(2201120506)
@@ -201,7 +253,7 @@ def serving(fm, torch, args, mode):
         errs.append(torch.linalg.vector_norm(x - xr).item() / torch.linalg.vector_norm(xr).item())
         P.close()
     span = t_last - t_first
-    return {"mode": mode, "requests": n_meas, "warmup_requests": n_warm, "arrival_rate_per_s": args.serving_rate,
+    return {"mode": mode, "requests": n_meas, "warmup_requests": n_warm, "arrival_rate_per_s": rate,
             "latency_ms": {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3,
                            "max": max(lat) * 1e3},
             "requests_per_s": n_meas / span, "rhs_per_s": rhs_done / span,
@@ -226,7 +278,9 @@ def main():
     ap.add_argument("--no-batched-grids", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=100, help="measured requests of the serving run")
     ap.add_argument("--serving-warmup", type=int, default=10)
-    ap.add_argument("--serving-rate", type=float, default=20.0, help="Poisson arrival rate (requests/s)")
+    ap.add_argument("--serving-rates", type=float, nargs="*", default=[20.0, 8.0],
+                    help="Poisson arrival rates (requests/s), one run each")
+    ap.add_argument("--barrier-freqs", type=int, default=8, help="frequencies of the barrier sweep (0: skip)")
     ap.add_argument("--serving-budget-gib", type=float, default=96.0)
     ap.add_argument("--serving-slots", type=int, default=32)
     ap.add_argument("--serving-modes", nargs="*", default=["fp32"], choices=["fp32", "fp64"])
@@ -372,8 +426,12 @@ def main():
     if not args.no_batched_grids:
         out["batched_grids"] = batched_grids(fm, torch, args)
         print(f"[bench] batched grids {out['batched_grids']}", file=sys.stderr, flush=True)
+    if args.barrier_freqs > 0:
+        out["barrier_sweep"] = barrier_sweep(fm, torch, args)
+        print(f"[bench] barrier sweep {out['barrier_sweep']['frequencies_per_s']:.2f} frequencies/s",
+              file=sys.stderr, flush=True)
     if args.serving_requests > 0:
-        out["serving"] = [serving(fm, torch, args, m) for m in args.serving_modes]
+        out["serving"] = [serving(fm, torch, args, m, r) for m in args.serving_modes for r in args.serving_rates]
         print(f"[bench] serving {out['serving']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         its64 = inf64[-1]["iterations"] + 2
