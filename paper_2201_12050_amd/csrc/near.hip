@@ -395,7 +395,17 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
       }
       cplx<T> v = Cst[cl * LDC + rl];
       if (dest == DEST_FINAL) {
-        for (int s2 = 0; s2 < nparts; ++s2) v = cadd<T>(v, part[s2 * slice + base + m]);
+        // the partial slices are loaded eight at a time (independent loads in flight together),
+        // then added in slice order
+        for (int s0 = 0; s0 < nparts; s0 += 8) {
+          cplx<T> pv[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            pv[q] = s0 + q < nparts ? part[(size_t)(s0 + q) * slice + base + m] : mk<T>(0, 0);
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            if (s0 + q < nparts) v = cadd<T>(v, pv[q]);
+        }
         if (out64) {
           out64[base + m] = make_double2((double)v.x, (double)v.y);
           continue;
