@@ -26,6 +26,7 @@
 // loads of step s+1 are issued before the MFMAs of step s and stored after them, one
 // barrier per step.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.hpp"
 
@@ -73,8 +74,10 @@ __device__ inline void cell_coords(const NearJob& jb, int j, int& r, int& i1, in
 __device__ inline int lds_slot(int r, int c) { return 4 * r + (c ^ ((r >> 2) & 3)); }
 
 // Tile: ROWS complex rows x COLS columns, 4 waves arranged WR x (4/WR), KC complex k per step.
-// ACOL: batched job with column-major A (the M2L products).
-template <typename T, int ROWS, int COLS, int WR, int KC, bool ACOL = false>
+// ACOL: batched job with column-major A (the M2L products).  PIPE: k steps whose global loads
+// are in flight at once (1: the next step during the MFMAs of the current one; 2: also the one
+// after, in a second register set).
+template <typename T, int ROWS, int COLS, int WR, int KC, int PIPE, bool ACOL = false>
 __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
   constexpr int WC = 4 / WR;
   constexpr int RBW = ROWS / (16 * WR);  // 16-row MFMA blocks per wave
@@ -164,9 +167,10 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
       p3[i][j] = Acc{0, 0, 0, 0};
     }
 
-  cplx<T> ra[APT];
-  cplx<T> rb[BPT];
-  uint32_t amask = 0, bmask = 0;  // valid staged elements (bit q); invalid ones are stored as zero
+  // staged global loads, one register set per step in flight
+  cplx<T> ra2[PIPE][APT];
+  cplx<T> rb2[PIPE][BPT];
+  uint32_t amask2[PIPE], bmask2[PIPE];  // valid staged elements (bit q); invalid ones are stored as zero
   // Global loads of one step, branch-free: every load reads a valid address (out-of-range
   // rows, columns and k read a valid stand-in, masked to zero at the LDS store), so the
   // loads stay in flight across the MFMAs of the current step.  When K is a multiple of
@@ -187,7 +191,11 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
     }
   };
   // full step (k0 + KC <= K): whole 16-byte units, no per-step address or mask arithmetic
-  auto load_full = [&](int k0) {
+  auto load_full = [&](int k0, auto set) {
+    cplx<T>* ra = ra2[decltype(set)::value];
+    cplx<T>* rb = rb2[decltype(set)::value];
+    uint32_t& amask = amask2[decltype(set)::value];
+    uint32_t& bmask = bmask2[decltype(set)::value];
 #pragma unroll
     for (int q = 0; q < APT / EPL; ++q)
       unpack(*reinterpret_cast<const VL*>(arow_ld + k0 + a_k + q * EPL), ra + q * EPL);
@@ -198,7 +206,11 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
     bmask = b_in ? 0xFFFFFFFFu : 0u;
   };
   // any step: element loads from clamped indices, per-element masks
-  auto load_any = [&](int k0) {
+  auto load_any = [&](int k0, auto set) {
+    cplx<T>* ra = ra2[decltype(set)::value];
+    cplx<T>* rb = rb2[decltype(set)::value];
+    uint32_t& amask = amask2[decltype(set)::value];
+    uint32_t& bmask = bmask2[decltype(set)::value];
     amask = 0;
     if (ACOL) {
       const bool kin = a_act && k0 + a_k < K;
@@ -230,10 +242,14 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
   // the full-step path needs 16-byte aligned rows / columns and whole units per thread
   constexpr bool kVecShape = !ACOL && APT % EPL == 0 && BPT % EPL == 0;
   const bool vec_steps = kVecShape && vec_ok;
-  auto av = [&](int q, T x) { return ((amask >> q) & 1u) ? x : T(0); };
-  auto bv = [&](int q, T x) { return ((bmask >> q) & 1u) ? x : T(0); };
-  // staged values -> LDS buffer b (whole chunks as one 16-byte store, partial chunks element-wise)
-  auto store = [&](int b) {
+  // staged values of a register set -> LDS buffer b (whole chunks as one 16-byte store, partial
+  // chunks element-wise)
+  auto store = [&](int b, auto set) {
+    const cplx<T>* ra = ra2[decltype(set)::value];
+    const cplx<T>* rb = rb2[decltype(set)::value];
+    const uint32_t amask = amask2[decltype(set)::value], bmask = bmask2[decltype(set)::value];
+    auto av = [&](int q, T x) { return ((amask >> q) & 1u) ? x : T(0); };
+    auto bv = [&](int q, T x) { return ((bmask >> q) & 1u) ? x : T(0); };
     if (ACOL) {
       if (a_act) {
         // APT rows of one k: element-wise into their rows' chunks
@@ -324,27 +340,56 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
   // Pipeline over the k steps: the loads of step s+1 are issued before the MFMAs of step s
   // and stored into the other LDS buffer after them (one barrier per step).  Steps whose
   // successor is a full step run in a loop with only the 16-byte loads in its body; the
-  // last step and a ragged tail step are peeled off.
+  // last step and a ragged tail step are peeled off.  With PIPE = 2 the full steps keep two
+  // steps of loads in flight (register sets alternate, the loop is unrolled by two).
   const int nsteps = (K + KC - 1) / KC;
   const int nvec = vec_steps ? K / KC : 0;  // steps loaded by load_full
-  if (nvec > 0) load_full(0);
-  else load_any(0);
-  store(0);
-  __syncthreads();
+  constexpr std::integral_constant<int, 0> set0{};
+  if (nvec > 0) load_full(0, set0);
+  else load_any(0, set0);
+  store(0, set0);
   int st = 0;
+  if constexpr (PIPE == 2) {
+    constexpr std::integral_constant<int, 1> set1{};
+    if (nvec >= 3) {
+      // entering each iteration: step st in LDS buffer 0, step st + 1 in flight in set 1
+      load_full(KC, set1);
+      __syncthreads();
+      for (; st + 3 < nvec; st += 2) {
+        load_full((st + 2) * KC, set0);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(0);
+        store(1, set1);
+        __syncthreads();
+        load_full((st + 3) * KC, set1);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(1);
+        store(0, set0);
+        __syncthreads();
+      }
+      compute(0);
+      store(1, set1);
+      __syncthreads();
+      ++st;
+    } else {
+      __syncthreads();
+    }
+  } else {
+    __syncthreads();
+  }
   for (; st + 1 < nvec; ++st) {
-    load_full((st + 1) * KC);
+    load_full((st + 1) * KC, set0);
     // keep the loads ahead of the MFMAs (the scheduler would sink them to reuse registers)
     __builtin_amdgcn_sched_barrier(0);
     compute(st & 1);
-    store((st + 1) & 1);
+    store((st + 1) & 1, set0);
     __syncthreads();
   }
   for (; st < nsteps; ++st) {
     const bool more = st + 1 < nsteps;
-    if (more) load_any((st + 1) * KC);
+    if (more) load_any((st + 1) * KC, set0);
     compute(st & 1);
-    if (more) store((st + 1) & 1);
+    if (more) store((st + 1) & 1, set0);
     __syncthreads();
   }
 
@@ -417,18 +462,20 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
 }
 
 // The same tile body under two kernel names, so that per-kernel profiles keep the near-field/S2M
-// launch apart from the L2T launch even when both use the same tile shape.
-template <typename T, int ROWS, int COLS, int WR, int KC>
-__global__ __launch_bounds__(256) void near_kernel(NearJobs jobs) {
-  near_tile<T, ROWS, COLS, WR, KC>(jobs);
+// launch apart from the L2T launch even when both use the same tile shape.  WPE: waves per SIMD
+// the register allocation must leave room for (3 keeps the MFMA accumulators in ordinary VGPRs
+// and three workgroups of four waves per CU; 1 lets the large tiles use the accumulator file).
+template <typename T, int ROWS, int COLS, int WR, int KC, int WPE, int PIPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void near_kernel(NearJobs jobs) {
+  near_tile<T, ROWS, COLS, WR, KC, PIPE>(jobs);
 }
-template <typename T, int ROWS, int COLS, int WR, int KC>
-__global__ __launch_bounds__(256) void l2t_kernel(NearJobs jobs) {
-  near_tile<T, ROWS, COLS, WR, KC>(jobs);
+template <typename T, int ROWS, int COLS, int WR, int KC, int WPE, int PIPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void l2t_kernel(NearJobs jobs) {
+  near_tile<T, ROWS, COLS, WR, KC, PIPE>(jobs);
 }
-template <typename T, int ROWS, int COLS, int WR, int KC>
-__global__ __launch_bounds__(256) void m2l_kernel(NearJobs jobs) {
-  near_tile<T, ROWS, COLS, WR, KC, true>(jobs);
+template <typename T, int ROWS, int COLS, int WR, int KC, int WPE, int PIPE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void m2l_kernel(NearJobs jobs) {
+  near_tile<T, ROWS, COLS, WR, KC, 1, true>(jobs);
 }
 
 // y[col][m] = sum_s part[s][col][m] in a fixed order (optionally written as FP64)
@@ -443,38 +490,44 @@ __global__ void near_reduce_kernel(const cplx<T>* __restrict__ part, int ns, siz
   }
 }
 
-// tile shapes: (complex rows, columns, wave rows, complex k per step); FP32 steps over
-// 16 complex k (one 16-byte LDS load of 4 floats per operand), FP64 over 8 (2 doubles)
+// tile shapes: (complex rows, columns, wave rows, complex k per step, waves per SIMD, k steps in
+// flight); FP32 steps over 16 complex k (one 16-byte LDS load of 4 floats per operand), FP64 over
+// 8 (2 doubles).  The last two were picked per shape by measurement on gfx950 (1280 x 1280
+// blocks, 256 columns); the 64 x 128 and 128 x 64 FP64 tiles do not fit three waves per SIMD.
 struct NearShape {
   int rows, cols, wr, kc;
 };
-#define FMBEM_NEAR_SHAPES(KC)                                                                        \
-  X(0, 64, 128, 2, KC) X(1, 32, 128, 2, KC) X(2, 64, 64, 2, KC) X(3, 64, 64, 4, KC) X(4, 32, 64, 2, KC) \
-  X(5, 16, 128, 1, KC) X(6, 16, 256, 1, KC) X(7, 128, 64, 4, KC) X(8, 32, 128, 1, KC) X(9, 16, 64, 1, KC)
+#define FMBEM_NEAR_SHAPES_F32                                                                   \
+  X(0, 64, 128, 2, 16, 3, 1) X(1, 32, 128, 2, 16, 3, 2) X(2, 64, 64, 2, 16, 3, 2)               \
+  X(3, 64, 64, 4, 16, 3, 2) X(4, 32, 64, 2, 16, 3, 2) X(5, 16, 128, 1, 16, 3, 1)                \
+  X(6, 16, 256, 1, 16, 3, 1) X(7, 128, 64, 4, 16, 3, 1) X(8, 32, 128, 1, 16, 3, 2) X(9, 16, 64, 1, 16, 3, 2)
+#define FMBEM_NEAR_SHAPES_F64                                                                   \
+  X(0, 64, 128, 2, 8, 1, 1) X(1, 32, 128, 2, 8, 3, 1) X(2, 64, 64, 2, 8, 3, 1)                  \
+  X(3, 64, 64, 4, 8, 3, 1) X(4, 32, 64, 2, 8, 3, 2) X(5, 16, 128, 1, 8, 3, 2)                   \
+  X(6, 16, 256, 1, 8, 3, 2) X(7, 128, 64, 4, 8, 1, 1) X(8, 32, 128, 1, 8, 3, 1) X(9, 16, 64, 1, 8, 3, 2)
 constexpr int kNumShapes = 10;
 // M2L products: p rows (121 at n_t = 10) by R columns per bin
-#define FMBEM_M2L_SHAPES(KC) \
-  X(0, 64, 64, 4, KC) X(1, 32, 64, 2, KC) X(2, 64, 32, 2, KC) X(3, 32, 32, 2, KC) X(4, 16, 64, 1, KC) X(5, 128, 64, 4, KC)
+#define FMBEM_M2L_SHAPES(KC, W5)                                                                 \
+  X(0, 64, 64, 4, KC, 3, 1) X(1, 32, 64, 2, KC, 3, 1) X(2, 64, 32, 2, KC, 3, 1) X(3, 32, 32, 2, KC, 3, 1) \
+  X(4, 16, 64, 1, KC, 3, 1) X(5, 128, 64, 4, KC, W5, 1)
 constexpr int kNumM2lShapes = 6;
 template <typename T> constexpr int shape_kc() { return sizeof(T) == 4 ? 16 : 8; }
+template <typename T> constexpr int m2l_w5() { return sizeof(T) == 4 ? 3 : 1; }
 
 template <typename T>
 static NearShape shape_of(int kind, int v) {
-  if (kind == 2) {
-    switch (v) {
-#define X(i, r, c, w, k) \
+#define X(i, r, c, w, k, wpe, pipe) \
   case i: return NearShape{r, c, w, k};
-      FMBEM_M2L_SHAPES(shape_kc<T>())
-#undef X
-    }
+  if (kind == 2) {
+    switch (v) { FMBEM_M2L_SHAPES(shape_kc<T>(), m2l_w5<T>()) }
     return NearShape{64, 64, 4, shape_kc<T>()};
   }
-  switch (v) {
-#define X(i, r, c, w, k) \
-  case i: return NearShape{r, c, w, k};
-    FMBEM_NEAR_SHAPES(shape_kc<T>())
-#undef X
+  if constexpr (sizeof(T) == 4) {
+    switch (v) { FMBEM_NEAR_SHAPES_F32 }
+  } else {
+    switch (v) { FMBEM_NEAR_SHAPES_F64 }
   }
+#undef X
   return NearShape{64, 128, 2, shape_kc<T>()};
 }
 
@@ -487,22 +540,24 @@ template <typename T>
 static void launch_shape(int v, int kind, unsigned blocks, const NearJobs& jobs, hipStream_t s) {
   if (kind == 2) {
     switch (v) {
-#define X(i, r, c, w, k) \
-  case i: hipLaunchKernelGGL((m2l_kernel<T, r, c, w, k>), dim3(blocks), dim3(256), 0, s, jobs); break;
-      FMBEM_M2L_SHAPES(shape_kc<T>())
+#define X(i, r, c, w, k, wpe, pipe) \
+  case i: hipLaunchKernelGGL((m2l_kernel<T, r, c, w, k, wpe, pipe>), dim3(blocks), dim3(256), 0, s, jobs); break;
+      FMBEM_M2L_SHAPES(shape_kc<T>(), m2l_w5<T>())
 #undef X
     }
     return;
   }
-  switch (v) {
-#define X(i, r, c, w, k)                                                                      \
-  case i:                                                                                     \
-    if (kind == 1) hipLaunchKernelGGL((l2t_kernel<T, r, c, w, k>), dim3(blocks), dim3(256), 0, s, jobs); \
-    else hipLaunchKernelGGL((near_kernel<T, r, c, w, k>), dim3(blocks), dim3(256), 0, s, jobs);          \
+#define X(i, r, c, w, k, wpe, pipe)                                                                             \
+  case i:                                                                                                      \
+    if (kind == 1) hipLaunchKernelGGL((l2t_kernel<T, r, c, w, k, wpe, pipe>), dim3(blocks), dim3(256), 0, s, jobs); \
+    else hipLaunchKernelGGL((near_kernel<T, r, c, w, k, wpe, pipe>), dim3(blocks), dim3(256), 0, s, jobs);          \
     break;
-    FMBEM_NEAR_SHAPES(shape_kc<T>())
-#undef X
+  if constexpr (sizeof(T) == 4) {
+    switch (v) { FMBEM_NEAR_SHAPES_F32 }
+  } else {
+    switch (v) { FMBEM_NEAR_SHAPES_F64 }
   }
+#undef X
 }
 
 template <typename T>
@@ -512,8 +567,8 @@ static long long job_tiles(const NearJob& j, const NearShape& sh) {
 
 // Relative throughput of each near-field shape on a large problem (1280 x 1280 blocks, 256
 // columns; measured on gfx950), the prior of the default choice.
-static const double kPriorF32[kNumShapes] = {0.76, 0.95, 0.99, 1.0, 0.98, 0.75, 0.43, 0.71, 0.93, 0.88};
-static const double kPriorF64[kNumShapes] = {0.64, 0.70, 0.74, 0.74, 1.0, 0.88, 0.51, 0.63, 0.66, 0.96};
+static const double kPriorF32[kNumShapes] = {0.75, 0.94, 1.0, 0.99, 0.93, 0.66, 0.36, 0.66, 0.94, 0.72};
+static const double kPriorF64[kNumShapes] = {0.50, 0.97, 1.0, 1.0, 0.96, 0.89, 0.54, 0.50, 0.96, 0.90};
 
 // default shape (untuned signatures): measured prior x fill of the last round of workgroups
 template <typename T>
