@@ -35,10 +35,10 @@ METRIC = "FMBEM matvecs/s & solves/s (FP32-refined vs FP64) at 1e-6; p50/p99 sol
 PEAK_FP32_MFMA = 157.3e12
 PEAK_FP64 = 78.6e12
 PEAK_HBM = 8.0e12
-# HBM bytes per launch of the FP32 near-field kernel on this workload (near_kernel<float, 64, 64, 4, 16>):
-# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 from two rocprofv3 counter runs, the factors calibrated on a plain
-# 1 GiB device copy (profiles/near_kernel_fp32_sphere16x16_traffic.md); valid for the kernel as measured
-NEAR_FP32_TRAFFIC_BYTES = 187.4e6
+# HBM bytes per launch of the FP32 near-field kernel on this workload: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
+# from two rocprofv3 counter runs, the factors calibrated on a plain 1 GiB device copy
+# (profiles/near_kernel_fp32_sphere16x16_traffic.md); None until taken for the kernel as it stands
+NEAR_FP32_TRAFFIC_BYTES = None
 
 
 def percentile(v, q):
@@ -154,7 +154,8 @@ def barrier_sweep(fm, torch, args):
     for k in range(len(idx)):
         w, P, b, t_build = ready.get()
         t0 = time.perf_counter()
-        x, info = P.solve(b, tol=args.tol, inner="fp32", ortho=args.ortho, raise_on_not_converged=False)
+        x, info = P.solve(b, tol=args.tol, inner="fp32", ortho=args.ortho, restart=args.barrier_restart,
+                          max_iters=args.barrier_max_iters, raise_on_not_converged=False)
         torch.cuda.synchronize()
         rows.append({"f_hz": round(w.frequency, 1), "n_t": w.order, "iterations": info[0]["iterations"],
                      "rel_residual": info[0]["rel_residual"], "solve_ms": (time.perf_counter() - t0) * 1e3,
@@ -167,11 +168,13 @@ def barrier_sweep(fm, torch, args):
     th.join()
     errs = []
     for P, b, x in checks:
-        xr = P.solve(b, tol=1e-12, inner="fp64", raise_on_not_converged=False)[0]
+        xr = P.solve(b, tol=1e-12, inner="fp64", restart=args.barrier_restart, max_iters=args.barrier_max_iters,
+                     raise_on_not_converged=False)[0]
         errs.append(torch.linalg.vector_norm(x - xr).item() / torch.linalg.vector_norm(xr).item())
         P.close()
     return {"workload": "barrier 40x2x8 open tube cells (192 triangles, N = 122,880), point source, "
-                        f"{len(idx)} frequencies 100 Hz - 2 kHz", "frequencies_per_s": len(idx) / total,
+                        f"{len(idx)} frequencies 100 Hz - 2 kHz", "gmres_restart": args.barrier_restart,
+            "frequencies_per_s": len(idx) / total,
             "total_s": total, "max_rel_residual": max(r["rel_residual"] for r in rows),
             "sampled_solution_error": max(errs), "per_frequency": rows}
 
@@ -281,6 +284,9 @@ def main():
     ap.add_argument("--serving-rates", type=float, nargs="*", default=[20.0, 8.0],
                     help="Poisson arrival rates (requests/s), one run each")
     ap.add_argument("--barrier-freqs", type=int, default=8, help="frequencies of the barrier sweep (0: skip)")
+    ap.add_argument("--barrier-restart", type=int, default=200,
+                    help="GMRES restart length of the barrier sweep (GMRES(30) stagnates near 550 and 850 Hz)")
+    ap.add_argument("--barrier-max-iters", type=int, default=4000)
     ap.add_argument("--serving-budget-gib", type=float, default=96.0)
     ap.add_argument("--serving-slots", type=int, default=32)
     ap.add_argument("--serving-modes", nargs="*", default=["fp32"], choices=["fp32", "fp64"])
@@ -385,10 +391,15 @@ def main():
     achieved = flops_near / avg_near
     stages = {k: {"avg_us": (v[0] / v[1] * 1e3 if v[1] else None), "launches": v[1]}
               for k, v in stage_prof.items()}
-    # HBM view of the M2L stage (FP32 Lambda read once + spectrum in/out)
-    B = int(np.prod(P.info["fft_shape"]))
+    # HBM view of the M2L stage: the FP32 Lambda of the canonical bins (one per pair w, -w; a bin
+    # is its own partner where 2w = 0 on every axis) read once, column stride p + (p & 1), plus
+    # the spectrum in and out
+    fs = P.info["fft_shape"]
+    B = int(np.prod(fs))
+    self_paired = int(np.prod([2 if (n % 2 == 0) else 1 for n in fs]))
+    Bc = (B + self_paired) // 2
     p = P.p
-    m2l_bytes = B * p * p * 8 + 2 * B * p * 8
+    m2l_bytes = Bc * p * (p + (p & 1)) * 8 + 2 * B * p * 8
     m2l_avg = stage_prof["m2l_fp32"][0] / max(stage_prof["m2l_fp32"][1], 1) / 1e3
     out = {
         "metric": METRIC,

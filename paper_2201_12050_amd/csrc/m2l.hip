@@ -6,15 +6,17 @@
 // stride ldp, so that two consecutive rows form one aligned 16-byte (FP32) / 32-byte
 // (FP64) load.  A workgroup owns one canonical bin and applies its matrix to the R
 // vectors of the bin and the R vectors of its partner (whose spectrum carries the
-// factor D of the symmetry, see grid_dft_launch): 4 wave groups split the columns j,
-// each thread of a group accumulates two rows for up to kRhs vectors, and the groups
-// are summed in LDS.  The product is in place in the [bin][R][p] spectrum buffer.
+// factor D of the symmetry, see grid_dft_launch): G groups of RP threads split the
+// columns j, each thread of a group accumulates two rows for up to kRhs vectors, and
+// the groups are summed in LDS.  The product is in place in the [bin][R][p] spectrum
+// buffer.  FP32 takes 8 groups (twice the loads in flight of 4: a bin's matrix is only
+// 118 KB at n_t = 10, measured 17.7 -> 13.7 us on 514 bins), FP64 4.
 #include "common.hpp"
 
 namespace fmbem {
 
 constexpr int kRhs = 4;
-constexpr int kGroups = 4;
+template <typename T> constexpr int gemv_groups() { return sizeof(T) == 4 ? 8 : 4; }
 
 template <typename T> struct Pair;
 template <> struct Pair<float> { using type = float4; };
@@ -26,14 +28,14 @@ __device__ inline cplx<T>* pair_vec(cplx<T>* buf, int a, int b, int R, int p, in
   return buf + ((size_t)(t < R ? a : b) * R + (t < R ? t : t - R)) * p;
 }
 
-// RP row-pair threads per column group (p <= 2 RP) and kGroups groups: RP * kGroups threads
-template <typename T, int RP>
-__global__ __launch_bounds__(RP * kGroups) void m2l_gemv_kernel(const cplx<T>* __restrict__ Lam,
+// RP row-pair threads per column group (p <= 2 RP) and G groups: RP * G threads
+template <typename T, int RP, int G>
+__global__ __launch_bounds__(RP * G) void m2l_gemv_kernel(const cplx<T>* __restrict__ Lam,
                                                                  const int* __restrict__ pairs,
                                                                  cplx<T>* __restrict__ buf, int R, int p, int ldp) {
   extern __shared__ unsigned char smem_raw[];
   cplx<T>* xs = reinterpret_cast<cplx<T>*>(smem_raw);        // [kRhs][p]
-  cplx<T>* red = xs + kRhs * p;                               // [kGroups][RP][kRhs][2]
+  cplx<T>* red = xs + kRhs * p;                               // [G][RP][kRhs][2]
   using P2 = typename Pair<T>::type;
   const int c = blockIdx.x;
   const int ba = pairs[2 * c], bb = pairs[2 * c + 1];
@@ -41,7 +43,7 @@ __global__ __launch_bounds__(RP * kGroups) void m2l_gemv_kernel(const cplx<T>* _
   const cplx<T>* Lb = Lam + (size_t)c * p * ldp;
   const int g = threadIdx.x / RP;
   const int rp = threadIdx.x % RP;                 // row pair (rows 2rp, 2rp+1)
-  const int jc = (p + kGroups - 1) / kGroups;
+  const int jc = (p + G - 1) / G;
   const int j0 = g * jc, j1 = min(p, j0 + jc);
   const bool active = 2 * rp < p;
   for (int r0 = 0; r0 < nv; r0 += kRhs) {
@@ -84,7 +86,7 @@ __global__ __launch_bounds__(RP * kGroups) void m2l_gemv_kernel(const cplx<T>* _
       for (int r = 0; r < kRhs; ++r) {
         if (r < nr) {
           cplx<T> s0 = red[(rp * kRhs + r) * 2], s1 = red[(rp * kRhs + r) * 2 + 1];
-          for (int q = 1; q < kGroups; ++q) {
+          for (int q = 1; q < G; ++q) {
             s0 = cadd<T>(s0, red[((q * RP + rp) * kRhs + r) * 2]);
             s1 = cadd<T>(s1, red[((q * RP + rp) * kRhs + r) * 2 + 1]);
           }
@@ -136,12 +138,13 @@ template <typename T>
 hipError_t m2l_launch(const void* Lam, const int* pairs, int Bc, void* buf, int R, int p, hipStream_t s) {
   const int ldp = lambda_ld(p);
   if (p <= 128) {
-    const size_t lds = (size_t)(kRhs * p + kGroups * 64 * kRhs * 2) * sizeof(cplx<T>);
-    hipLaunchKernelGGL((m2l_gemv_kernel<T, 64>), dim3(Bc), dim3(64 * kGroups), lds, s,
+    constexpr int G = gemv_groups<T>();
+    const size_t lds = (size_t)(kRhs * p + G * 64 * kRhs * 2) * sizeof(cplx<T>);
+    hipLaunchKernelGGL((m2l_gemv_kernel<T, 64, G>), dim3(Bc), dim3(64 * G), lds, s,
                        reinterpret_cast<const cplx<T>*>(Lam), pairs, reinterpret_cast<cplx<T>*>(buf), R, p, ldp);
   } else if (p <= 256) {
-    const size_t lds = (size_t)(kRhs * p + kGroups * 128 * kRhs * 2) * sizeof(cplx<T>);
-    hipLaunchKernelGGL((m2l_gemv_kernel<T, 128>), dim3(Bc), dim3(128 * kGroups), lds, s,
+    const size_t lds = (size_t)(kRhs * p + 4 * 128 * kRhs * 2) * sizeof(cplx<T>);
+    hipLaunchKernelGGL((m2l_gemv_kernel<T, 128, 4>), dim3(Bc), dim3(128 * 4), lds, s,
                        reinterpret_cast<const cplx<T>*>(Lam), pairs, reinterpret_cast<cplx<T>*>(buf), R, p, ldp);
   } else {
     const int threads = min(512, ((p + 63) / 64) * 64);
