@@ -45,27 +45,32 @@ __global__ __launch_bounds__(kDotThreads) void mdot_kernel(const double2* __rest
   const int nblk = gridDim.x;
   const size_t base = (size_t)blockIdx.x * kDotThreads * kDotEl + threadIdx.x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // every load first, from clamped indices (an element past N has w = 0, a vector past J is
+  // never written out), so that all kDotVec x kDotEl loads are in flight together
   double2 wl[kDotEl];
+  size_t nc[kDotEl];
 #pragma unroll
   for (int e = 0; e < kDotEl; ++e) {
     const size_t n = base + (size_t)e * kDotThreads;
-    wl[e] = n < N ? w[(size_t)r * N + n] : make_double2(0, 0);
+    nc[e] = n < N ? n : N - 1;
+    wl[e] = w[(size_t)r * N + nc[e]];
+    if (n >= N) wl[e] = make_double2(0, 0);
+  }
+  double2 a[kDotVec][kDotEl];
+#pragma unroll
+  for (int q = 0; q < kDotVec; ++q) {
+    const double2* vi = V + (size_t)min(i0 + q, J - 1) * vstride + (size_t)r * N;
+#pragma unroll
+    for (int e = 0; e < kDotEl; ++e) a[q][e] = vi[nc[e]];
   }
   double2 acc[kDotVec];
 #pragma unroll
   for (int q = 0; q < kDotVec; ++q) {
     acc[q] = make_double2(0, 0);
-    if (i0 + q < J) {
-      const double2* vi = V + (size_t)(i0 + q) * vstride + (size_t)r * N;
 #pragma unroll
-      for (int e = 0; e < kDotEl; ++e) {
-        const size_t n = base + (size_t)e * kDotThreads;
-        if (n < N) {
-          const double2 a = vi[n];
-          acc[q].x += a.x * wl[e].x + a.y * wl[e].y;
-          acc[q].y += a.x * wl[e].y - a.y * wl[e].x;
-        }
-      }
+    for (int e = 0; e < kDotEl; ++e) {
+      acc[q].x += a[q][e].x * wl[e].x + a[q][e].y * wl[e].y;
+      acc[q].y += a[q][e].x * wl[e].y - a[q][e].y * wl[e].x;
     }
   }
 #pragma unroll
@@ -209,27 +214,42 @@ __global__ void to64_kernel(const float2* __restrict__ a, double2* __restrict__ 
     b[i] = make_double2((double)a[i].x, (double)a[i].y);
 }
 
-// One workgroup per RHS: hn = sqrt(sum of the |w|^2 block partials), then the Givens
-// update of Hessenberg column j (rotations [[conj(c), conj(s)], [-s, c]]) and of g on
-// LDS copies, the residual estimate |g_{j+1}| and the freeze flag (also written to
-// mapped host memory for the host's convergence check).
-constexpr int kMaxRestart = 200;
-__global__ __launch_bounds__(256) void norm_givens_kernel(const double* __restrict__ npart, int nb, int m, int j,
-                                                          const double2* __restrict__ hc, int hstride,
-                                                          double2* __restrict__ hn, double2* __restrict__ H,
-                                                          double2* __restrict__ cs, double2* __restrict__ sn,
-                                                          double2* __restrict__ g, double* __restrict__ res,
-                                                          int* __restrict__ jdone, int* __restrict__ jdone_host,
-                                                          const double* __restrict__ tol) {
-  __shared__ double2 col[kMaxRestart + 2], lc[kMaxRestart], ls[kMaxRestart];
+// sqrt of the sum of RHS r's nb |w|^2 block partials, the same fixed order in every workgroup
+__device__ inline double partial_norm(const double* __restrict__ npart, int nb, int r) {
   __shared__ double red[4];
-  const int r = blockIdx.x;
   double s = 0.0;
   for (int b = threadIdx.x; b < nb; b += blockDim.x) s += npart[(size_t)r * nb + b];
   s = wave_sum(s);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  const double nrm = sqrt(fmax(red[0] + red[1] + red[2] + red[3], 0.0));
+  return sqrt(fmax(red[0] + red[1] + red[2] + red[3], 0.0));
+}
+
+// Arnoldi step close: v_{j+1} = w / ||w|| (and its FP32 copy), ||w|| from the multi-axpy's
+// partials, recomputed by every workgroup.  Workgroup (0, r) also writes hn and does the
+// Givens update of Hessenberg column j (rotations [[conj(c), conj(s)], [-s, c]]) and of g on
+// LDS copies, the residual estimate |g_{j+1}| and the freeze flag (also written to mapped
+// host memory for the host's convergence check).  Grid (blocks, R), 256 threads.
+constexpr int kMaxRestart = 200;
+__global__ __launch_bounds__(256) void scale_givens_kernel(const double* __restrict__ npart, int nb, int m, int j,
+                                                           const double2* __restrict__ hc, int hstride,
+                                                           double2* __restrict__ hn, double2* __restrict__ H,
+                                                           double2* __restrict__ cs, double2* __restrict__ sn,
+                                                           double2* __restrict__ g, double* __restrict__ res,
+                                                           int* __restrict__ jdone, int* __restrict__ jdone_host,
+                                                           const double* __restrict__ tol, double2* __restrict__ w,
+                                                           float2* __restrict__ w32, size_t N) {
+  const int r = blockIdx.y;
+  const double nrm = partial_norm(npart, nb, r);
+  const double f = nrm > 0 ? 1.0 / nrm : 0.0;
+  for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (size_t)gridDim.x * blockDim.x) {
+    const double2 v = w[(size_t)r * N + n];
+    const double2 o = make_double2(v.x * f, v.y * f);
+    w[(size_t)r * N + n] = o;
+    if (w32) w32[(size_t)r * N + n] = make_float2((float)o.x, (float)o.y);
+  }
+  if (blockIdx.x != 0) return;
+  __shared__ double2 col[kMaxRestart + 2], lc[kMaxRestart], ls[kMaxRestart];
   const int frozen = jdone[r];
   if (threadIdx.x == 0) hn[(size_t)r * hstride] = make_double2(nrm, 0.0);
   if (frozen >= 0) {
@@ -398,7 +418,8 @@ struct Member {
     vlen = (size_t)R * N;
     nblk = (int)((N + kDotThreads * kDotEl - 1) / (kDotThreads * kDotEl));
     hstride = m + 2;
-    nb = (int)std::min<size_t>((N + 255) / 256, 2048);
+    // multi-axpy workgroups: each step-closing workgroup re-sums their |w|^2 partials
+    nb = (int)std::min<size_t>((N + 255) / 256, 512);
     bn.assign(R, 0.0);
     rel.assign(R, 0.0);
   }
@@ -616,10 +637,8 @@ struct Member {
             mdot(V, j + 1, wv, hc, 3, y, reorth);
             maxpy(V, y, wv, j + 1, -1.0, true, reorth);
           }
-          hipLaunchKernelGGL(norm_givens_kernel, dim3(R), dim3(256), 0, s, npart, nb, m, j, hc, hstride, hn, H, cs,
-                             sn, g, res, jdone, djd[slot], tolv);
-          hipLaunchKernelGGL(scale_kernel, vgrid(), dim3(256), 0, s, wv, hn, hstride, wv,
-                             gm_prec == FMBEM_FP32 ? x32 : nullptr, N);
+          hipLaunchKernelGGL(scale_givens_kernel, vgrid(), dim3(256), 0, s, npart, nb, m, j, hc, hstride, hn, H, cs,
+                             sn, g, res, jdone, djd[slot], tolv, wv, gm_prec == FMBEM_FP32 ? x32 : nullptr, N);
         }
         ++its;
         ++j;
