@@ -76,8 +76,9 @@ __device__ inline int lds_slot(int r, int c) { return 4 * r + (c ^ ((r >> 2) & 3
 // Tile: ROWS complex rows x COLS columns, 4 waves arranged WR x (4/WR), KC complex k per step.
 // ACOL: batched job with column-major A (the M2L products).  PIPE: k steps whose global loads
 // are in flight at once (1: the next step during the MFMAs of the current one; 2: also the one
-// after, in a second register set).
-template <typename T, int ROWS, int COLS, int WR, int KC, int PIPE, bool ACOL = false>
+// after, in a second register set).  FINAL: the kernel takes DEST_FINAL jobs (the L2T launch
+// only, so that the other launches do not carry the registers of its epilogue).
+template <typename T, int ROWS, int COLS, int WR, int KC, int PIPE, bool ACOL = false, bool FINAL = false>
 __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
   constexpr int WC = 4 / WR;
   constexpr int RBW = ROWS / (16 * WR);  // 16-row MFMA blocks per wave
@@ -423,6 +424,45 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
         }
     }
     __syncthreads();
+    if (FINAL && dest == DEST_FINAL) {
+      // all outputs of this thread at once: the partial slices are loaded QS at a time for all UPT
+      // outputs (up to 32 FP32 / 16 FP64 independent loads in flight), then added in slice order
+      constexpr int UPT = CPP * ROWS / 256;
+      static_assert(UPT * 256 == CPP * ROWS, "whole outputs per thread");
+      constexpr int kLoads = sizeof(T) == 4 ? 32 : 16;
+      constexpr int QS = UPT >= kLoads ? 1 : kLoads / UPT;
+      size_t at[UPT];
+      bool ok[UPT];
+      cplx<T> v[UPT];
+#pragma unroll
+      for (int u = 0; u < UPT; ++u) {
+        const int e = tid + 256 * u;
+        const int cl = e / ROWS, rl = e - cl * ROWS;
+        const int col = col0 + cb + cl, m = m0 + rl;
+        ok[u] = col < N && m < M;
+        at[u] = ok[u] ? (size_t)col * M + m : 0;  // out-of-range outputs read a valid stand-in
+        v[u] = Cst[cl * LDC + rl];
+      }
+      for (int s0 = 0; s0 < nparts; s0 += QS) {
+        cplx<T> pv[UPT][QS];
+#pragma unroll
+        for (int q = 0; q < QS; ++q)
+#pragma unroll
+          for (int u = 0; u < UPT; ++u) pv[u][q] = part[(size_t)min(s0 + q, nparts - 1) * slice + at[u]];
+#pragma unroll
+        for (int q = 0; q < QS; ++q)
+          if (s0 + q < nparts)
+#pragma unroll
+            for (int u = 0; u < UPT; ++u) v[u] = cadd<T>(v[u], pv[u][q]);
+      }
+#pragma unroll
+      for (int u = 0; u < UPT; ++u) {
+        if (!ok[u]) continue;
+        if (out64) out64[at[u]] = make_double2((double)v[u].x, (double)v[u].y);
+        else out[at[u]] = v[u];
+      }
+      continue;
+    }
     for (int e = tid; e < CPP * ROWS; e += 256) {
       const int cl = e / ROWS, rl = e - cl * ROWS;
       const int col = col0 + cb + cl, m = m0 + rl;
@@ -438,25 +478,7 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
       } else {
         base = (size_t)col * M;
       }
-      cplx<T> v = Cst[cl * LDC + rl];
-      if (dest == DEST_FINAL) {
-        // the partial slices are loaded eight at a time (independent loads in flight together),
-        // then added in slice order
-        for (int s0 = 0; s0 < nparts; s0 += 8) {
-          cplx<T> pv[8];
-#pragma unroll
-          for (int q = 0; q < 8; ++q)
-            pv[q] = s0 + q < nparts ? part[(size_t)(s0 + q) * slice + base + m] : mk<T>(0, 0);
-#pragma unroll
-          for (int q = 0; q < 8; ++q)
-            if (s0 + q < nparts) v = cadd<T>(v, pv[q]);
-        }
-        if (out64) {
-          out64[base + m] = make_double2((double)v.x, (double)v.y);
-          continue;
-        }
-      }
-      out[base + m] = v;
+      out[base + m] = Cst[cl * LDC + rl];
     }
   }
 }
@@ -471,7 +493,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
 }
 template <typename T, int ROWS, int COLS, int WR, int KC, int WPE, int PIPE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void l2t_kernel(NearJobs jobs) {
-  near_tile<T, ROWS, COLS, WR, KC, PIPE>(jobs);
+  near_tile<T, ROWS, COLS, WR, KC, PIPE, false, true>(jobs);
 }
 template <typename T, int ROWS, int COLS, int WR, int KC, int WPE, int PIPE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void m2l_kernel(NearJobs jobs) {
@@ -594,6 +616,9 @@ static int near_default_shape(const std::vector<NearJob>& jobs, int kind) {
 template <typename T>
 hipError_t near_launch(const std::vector<NearJob>& list, hipStream_t s, int shape, int kind) {
   if (list.empty()) return hipSuccess;
+  // DEST_FINAL jobs need the L2T kernel's epilogue, and only those go to it
+  for (const NearJob& j : list)
+    if ((j.dest == DEST_FINAL) != (kind == 1)) return hipErrorInvalidValue;
   if (shape < 0 || shape >= near_num_shapes<T>(kind)) shape = near_default_shape<T>(list, kind);
   const NearShape sh = shape_of<T>(kind, shape);
   for (size_t first = 0; first < list.size(); first += kMaxJobs) {
