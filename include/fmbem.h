@@ -73,7 +73,7 @@ typedef struct {
   int32_t formulation;        /* fmbem_formulation */
   double alpha_re, alpha_im;  /* Burton-Miller coupling; both NaN => -i/k (Sec. 2.1) */
   int32_t near_radius[3];     /* near field: |d_a| <= near_radius_a cells (0 => 1) */
-  int32_t fft_shape[3];       /* 0 => smallest 2^a3^b5^c7^d >= 2 M_a - 1; else >= 2 M_a - 1 (<= 8192) */
+  int32_t fft_shape[3];       /* 0 => 2 M_a - 1 (the smallest exact embedding); else >= 2 M_a - 1 (<= 8192) */
   uint32_t precisions;        /* bitmask (1<<FMBEM_FP64) | (1<<FMBEM_FP32) of resident copies;
                                  0 => FP64 only */
 } fmbem_plan_desc;

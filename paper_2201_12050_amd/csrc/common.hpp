@@ -206,9 +206,14 @@ hipError_t near_reduce_launch(const void* part, int ns, size_t len, void* y, voi
 // flip_p > 0: the channels are [..][p] multipole coefficients and the spectrum of every
 // non-canonical bin carries the factor D = diag((-1)^n): applied to the forward output and
 // removed from the inverse input (then Lambda of the canonical partner serves that bin).
+// schedule: 0 separate axis passes, 1 the fused two-axis kernel where it applies (else the
+// passes), -1 the built-in rule (fused for at most 256 channels).
 template <typename T>
 hipError_t grid_dft_launch(void* buf, int channels, const int M[3], const int N[3], bool inverse,
-                           bool pruned, hipStream_t s, int flip_p = 0);
+                           bool pruned, hipStream_t s, int flip_p = 0, int schedule = -1);
+// whether the fused two-axis kernel applies (N3 = 1, N1 > 1, pruned, one channel fits its LDS)
+template <typename T>
+bool dft_fused_applies(int channels, const int M[3], const int N[3], bool pruned);
 
 // column stride (complex elements) of the per-bin column-major Lambda blocks
 int lambda_ld(int p);

@@ -264,21 +264,32 @@ __global__ __launch_bounds__(256) void dft2_kernel(cplx<T>* __restrict__ buf, in
 constexpr size_t kDft2Lds = 64 * 1024;
 
 template <typename T>
+static size_t dft2_per_channel(const int M[3], const int N[3], bool inverse) {
+  return (size_t)(inverse ? N[1] * N[0] + M[1] * N[0] : M[1] * M[0] + M[1] * N[0]) * sizeof(cplx<T>);
+}
+
+template <typename T>
+bool dft_fused_applies(int channels, const int M[3], const int N[3], bool pruned) {
+  if (!pruned || N[2] != 1 || M[2] != 1 || N[0] <= 1 || channels < 1) return false;
+  const size_t fixed = (size_t)(N[0] + N[1]) * sizeof(cplx<T>);
+  const size_t per_ch = std::max(dft2_per_channel<T>(M, N, false), dft2_per_channel<T>(M, N, true));
+  return fixed + per_ch <= kDft2Lds;
+}
+
+template <typename T>
 hipError_t grid_dft_launch(void* bufv, int channels, const int M[3], const int N[3], bool inverse, bool pruned,
-                           hipStream_t s, int flip_p) {
+                           hipStream_t s, int flip_p, int schedule) {
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(bufv);
-  // fused form: N3 = 1, N0 > 1, pruned, few channels, at least one channel per workgroup in LDS
-  if (pruned && N[2] == 1 && M[2] == 1 && N[0] > 1 && channels <= kDft2MaxChannels) {
-    const size_t per_ch = (size_t)(inverse ? N[1] * N[0] + M[1] * N[0] : M[1] * M[0] + M[1] * N[0]) * sizeof(cplx<T>);
+  if (schedule < 0) schedule = channels <= kDft2MaxChannels ? 1 : 0;
+  if (schedule == 1 && dft_fused_applies<T>(channels, M, N, pruned)) {
+    // channels per workgroup: enough workgroups to cover the CUs, within the LDS budget
+    const size_t per_ch = dft2_per_channel<T>(M, N, inverse);
     const size_t fixed = (size_t)(N[0] + N[1]) * sizeof(cplx<T>);
-    if (fixed + per_ch <= kDft2Lds) {
-      // channels per workgroup: enough workgroups to cover the CUs, within the LDS budget
-      int CT = std::max(1, std::min<int>((int)((kDft2Lds - fixed) / per_ch), (channels + 255) / 256));
-      const int blocks = (channels + CT - 1) / CT;
-      hipLaunchKernelGGL(dft2_kernel<T>, dim3(blocks), dim3(256), fixed + per_ch * CT, s, buf, channels, CT, N[0],
-                         N[1], M[0], M[1], inverse ? 1 : -1, flip_p);
-      return hipGetLastError();
-    }
+    const int CT = std::max(1, std::min<int>((int)((kDft2Lds - fixed) / per_ch), (channels + 255) / 256));
+    const int blocks = (channels + CT - 1) / CT;
+    hipLaunchKernelGGL(dft2_kernel<T>, dim3(blocks), dim3(256), fixed + per_ch * CT, s, buf, channels, CT, N[0],
+                       N[1], M[0], M[1], inverse ? 1 : -1, flip_p);
+    return hipGetLastError();
   }
   long long str[3] = {channels, (long long)N[0] * channels, (long long)N[0] * N[1] * channels};
   int ext[3];
@@ -312,7 +323,9 @@ hipError_t grid_dft_launch(void* bufv, int channels, const int M[3], const int N
   return hipSuccess;
 }
 
-template hipError_t grid_dft_launch<double>(void*, int, const int*, const int*, bool, bool, hipStream_t, int);
-template hipError_t grid_dft_launch<float>(void*, int, const int*, const int*, bool, bool, hipStream_t, int);
+template hipError_t grid_dft_launch<double>(void*, int, const int*, const int*, bool, bool, hipStream_t, int, int);
+template hipError_t grid_dft_launch<float>(void*, int, const int*, const int*, bool, bool, hipStream_t, int, int);
+template bool dft_fused_applies<double>(int, const int*, const int*, bool);
+template bool dft_fused_applies<float>(int, const int*, const int*, bool);
 
 }  // namespace fmbem

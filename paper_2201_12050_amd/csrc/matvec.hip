@@ -122,6 +122,47 @@ int cached_shape(int kind, const std::vector<NearJob>& jobs) {
   return it == g_tuned.end() ? -1 : it->second;
 }
 
+// Autotuner of the DFT schedule (the fused two-axis kernel or separate axis passes) of a
+// plan's grid with R right-hand sides: on the first application of a signature (precision,
+// lattice, transform lengths, channels) where the fused form applies, both schedules run a
+// forward + inverse transform pair on the workspace grid (before the S2M product writes it)
+// twice, timed with HIP events; the faster is cached for the process.  Otherwise, or while the
+// stream is being captured, a schedule measured earlier or the built-in rule (-1).
+template <typename T>
+static int dft_schedule(const Plan& P, int R, void* ws, hipStream_t s, bool tune) {
+  const int ch = R * P.p;
+  if (P.n_far == 0 || !dft_fused_applies<T>(ch, P.grid, P.fft, true)) return 0;
+  const std::vector<long long> key{3, (long long)sizeof(T), P.grid[0], P.grid[1], P.grid[2],
+                                   P.fft[0], P.fft[1], P.fft[2], ch};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end()) return it->second;
+  }
+  if (!tune || capturing(s)) return -1;
+  hipEvent_t a = nullptr, b = nullptr;
+  float t[2] = {1e30f, 1e30f};
+  if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
+    for (int sweep = 0; sweep < 2; ++sweep)
+      for (int v = 0; v < 2; ++v) {
+        if (grid_dft_launch<T>(ws, ch, P.grid, P.fft, false, true, s, P.p, v) != hipSuccess) continue;
+        hipEventRecord(a, s);
+        grid_dft_launch<T>(ws, ch, P.grid, P.fft, false, true, s, P.p, v);
+        grid_dft_launch<T>(ws, ch, P.grid, P.fft, true, true, s, P.p, v);
+        hipEventRecord(b, s);
+        float ms = 0.f;
+        if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) continue;
+        t[v] = std::min(t[v], ms);
+      }
+  }
+  if (a) hipEventDestroy(a);
+  if (b) hipEventDestroy(b);
+  const int best = t[1] < t[0] ? 1 : 0;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[key] = best;
+  return best;
+}
+
 // workspace layout: [padded grid B x R x p][second grid B x R x p][near partials n_near x R x C x n]
 template <typename T>
 static char* second_grid(const Plan& P, int R, void* ws) {
@@ -189,6 +230,7 @@ static hipError_t matvec_overlap(const Plan& P, int R, const void* x, void* y, v
                                  bool tune) {
   const int prec = sizeof(T) == 8 ? 0 : 1;
   const int n = P.n, p = P.p;
+  const int dsched = dft_schedule<T>(P, R, ws, s, tune);
   std::lock_guard<std::mutex> lk(*P.aux_mu);
   hipError_t e;
   if ((e = hipEventRecord(P.ev_fork, s))) return e;
@@ -200,14 +242,14 @@ static hipError_t matvec_overlap(const Plan& P, int R, const void* x, void* y, v
     const int shape = tune ? tuned_shape<T>(0, s2m, P.aux) : cached_shape<T>(0, s2m);
     if ((e = near_launch<T>(s2m, P.aux, shape, 0))) return e;
   }
-  if ((e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, false, true, P.aux, p))) return e;
+  if ((e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, false, true, P.aux, p, dsched))) return e;
   prof_end(P, 2 + 6 * prec, ev, P.aux);
   ev = prof_begin(P, 3 + 6 * prec, P.aux);
   void* lhat = nullptr;
   if ((e = m2l_apply<T>(P, R, ws, P.aux, &lhat, tune))) return e;
   prof_end(P, 3 + 6 * prec, ev, P.aux);
   ev = prof_begin(P, 4 + 6 * prec, P.aux);
-  if ((e = grid_dft_launch<T>(lhat, R * p, P.grid, P.fft, true, true, P.aux, p))) return e;
+  if ((e = grid_dft_launch<T>(lhat, R * p, P.grid, P.fft, true, true, P.aux, p, dsched))) return e;
   prof_end(P, 4 + 6 * prec, ev, P.aux);
   if ((e = hipEventRecord(P.ev_join, P.aux))) return e;
   // [0] near field on the caller's stream
@@ -239,6 +281,7 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
   // FP64 only: the FP32 near-field GEMM keeps every CU occupied until it drains, so a
   // concurrent far chain only delays it (measured on gfx950); the FP64 one leaves room
   if (sizeof(T) == 8 && P.aux && P.n_far > 0 && !capturing(s)) return matvec_overlap<T>(P, R, x, y, ws, s, y64, tune);
+  const int dsched = dft_schedule<T>(P, R, ws, s, tune);
   // [0] near field and S2M
   hipEvent_t ev = nullptr;
   {
@@ -260,7 +303,7 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
   }
   // [2]-[4] DFT, M2L, inverse DFT
   ev = prof_begin(P, 2 + 6 * prec, s);
-  hipError_t e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, false, true, s, p);
+  hipError_t e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, false, true, s, p, dsched);
   if (e != hipSuccess) return e;
   prof_end(P, 2 + 6 * prec, ev, s);
   ev = prof_begin(P, 3 + 6 * prec, s);
@@ -269,7 +312,7 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
   if (e != hipSuccess) return e;
   prof_end(P, 3 + 6 * prec, ev, s);
   ev = prof_begin(P, 4 + 6 * prec, s);
-  e = grid_dft_launch<T>(lhat, R * p, P.grid, P.fft, true, true, s, p);
+  e = grid_dft_launch<T>(lhat, R * p, P.grid, P.fft, true, true, s, p, dsched);
   if (e != hipSuccess) return e;
   prof_end(P, 4 + 6 * prec, ev, s);
   // [5] L2T with the fixed-order sum of the near partials
@@ -291,12 +334,15 @@ template <typename T>
 static hipError_t matvec_group_t(const std::vector<GroupApply>& g, hipStream_t s, bool tune) {
   const int prec = sizeof(T) == 8 ? 0 : 1;
   std::vector<NearJob> jobs;
+  std::vector<int> dsched;
+  for (const GroupApply& a : g) dsched.push_back(dft_schedule<T>(*a.P, a.R, a.ws, s, tune));
   for (const GroupApply& a : g) near_s2m_jobs<T>(*a.P, a.R, a.x, a.ws, jobs);
   int shape = tune ? tuned_shape<T>(0, jobs, s) : cached_shape<T>(0, jobs);
   hipError_t e = near_launch<T>(jobs, s, shape, 0);
   if (e != hipSuccess) return e;
   std::vector<NearJob> l2t;
-  for (const GroupApply& a : g) {
+  for (size_t q = 0; q < g.size(); ++q) {
+    const GroupApply& a = g[q];
     const Plan& P = *a.P;
     if (P.n_far == 0) {
       e = near_reduce_launch<T>(near_partials<T>(P, a.R, a.ws), P.n_near, (size_t)a.R * P.C * P.n, a.y, a.y64, s);
@@ -304,9 +350,11 @@ static hipError_t matvec_group_t(const std::vector<GroupApply>& g, hipStream_t s
       continue;
     }
     void* lhat = nullptr;
-    if ((e = grid_dft_launch<T>(a.ws, a.R * P.p, P.grid, P.fft, false, true, s, P.p)) != hipSuccess) return e;
+    if ((e = grid_dft_launch<T>(a.ws, a.R * P.p, P.grid, P.fft, false, true, s, P.p, dsched[q])) != hipSuccess)
+      return e;
     if ((e = m2l_apply<T>(P, a.R, a.ws, s, &lhat, tune)) != hipSuccess) return e;
-    if ((e = grid_dft_launch<T>(lhat, a.R * P.p, P.grid, P.fft, true, true, s, P.p)) != hipSuccess) return e;
+    if ((e = grid_dft_launch<T>(lhat, a.R * P.p, P.grid, P.fft, true, true, s, P.p, dsched[q])) != hipSuccess)
+      return e;
     l2t.push_back(l2t_job<T>(P, a.R, a.ws, lhat, a.y, a.y64));
   }
   if (l2t.empty()) return hipSuccess;

@@ -78,15 +78,6 @@ static void gauss_legendre_host(int q, std::vector<double>& x, std::vector<doubl
   }
 }
 
-static int smooth_at_least(int n) {
-  for (int v = std::max(n, 1);; ++v) {
-    int t = v;
-    for (int f : {2, 3, 5, 7})
-      while (t % f == 0) t /= f;
-    if (t == 1) return v;
-  }
-}
-
 // ---------------------------------------------------------------------------
 // device: quadrature tables  t in [0,1], w = Gauss weight / 2 (per [0,1] map)
 //   layout: q=4 at 0, q=8 at 4, q=16 at 12 (28 entries)
@@ -828,7 +819,9 @@ extern "C" fmbem_status fmbem_plan_create(const fmbem_cell_mesh* mesh, const fmb
     P->near_radius[a] = desc->near_radius[a] == 0 ? 1 : desc->near_radius[a];
     P->C *= desc->grid[a];
     const int need = 2 * desc->grid[a] - 1;
-    P->fft[a] = desc->fft_shape[a] > 0 ? desc->fft_shape[a] : smooth_at_least(need);
+    // the DFT is a direct pruned transform over any length, so the smallest exact circulant
+    // embedding (2 M - 1 per axis) has the fewest bins and the least work
+    P->fft[a] = desc->fft_shape[a] > 0 ? desc->fft_shape[a] : need;
     if (desc->grid[a] == 1) P->fft[a] = 1;
   }
   P->B = P->fft[0] * P->fft[1] * P->fft[2];

@@ -98,6 +98,24 @@ def test_matvec_matches_oracle(cases, name, R):
         assert rel(y64[r], ref[r]) < 1e-12
 
 
+def test_explicit_fft_shape_matches_oracle(cases):
+    # the default transform lengths are the minimal 2M - 1 (odd); an explicit even, larger
+    # embedding is exact as well and takes the other bin-pairing pattern (self-paired bins at
+    # N/2) through the DFT, Lambda and M2L
+    import paper_2201_12050_amd as fm
+    F, P, lat = cases["sphere80_5x3_ragged"]
+    assert P.info["fft_shape"] == (9, 5, 1)
+    v, t, pitch = _geometry(1)
+    Q = fm.Plan(v, t, lat.grid, pitch, F.k, F.order, "bm", fft_shape=(12, 8, 0))
+    assert Q.info["fft_shape"] == (12, 8, 1)
+    for R in (1, 9):
+        x = random_complex((R, lat.n_cells, F.n), 300 + R)
+        ref = F.matvec(x)
+        xd = torch.from_numpy(x).cuda()
+        assert rel(Q.matvec(xd, precision="fp64").cpu().numpy(), ref) < 1e-12
+        assert rel(Q.matvec(xd.to(torch.complex64), precision="fp32").cpu().numpy(), ref) < 1e-5
+
+
 def test_matvec_batched_equals_alone(cases):
     # below the M2L GEMM threshold every stage computes each column in the same order
     # whatever the batch, so a batched apply equals the single ones bit for bit
