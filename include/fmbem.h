@@ -76,7 +76,15 @@ typedef struct {
   int32_t fft_shape[3];       /* 0 => 2 M_a - 1 (the smallest exact embedding); else >= 2 M_a - 1 (<= 8192) */
   uint32_t precisions;        /* bitmask (1<<FMBEM_FP64) | (1<<FMBEM_FP32) of resident copies;
                                  0 => FP64 only */
+  int32_t dft_schedule;       /* FMBEM_DFT_*: how the grid DFT (Sec. 2.4) runs; AUTO measures the
+                                 applicable schedules on first use of each problem signature; a
+                                 forced schedule that does not apply falls back to AXES */
 } fmbem_plan_desc;
+
+#define FMBEM_DFT_AUTO 0    /* autotuned */
+#define FMBEM_DFT_AXES 1    /* one direct pruned DFT pass per axis */
+#define FMBEM_DFT_FUSED 2   /* both axes of an N3 = 1 grid in one launch through LDS */
+#define FMBEM_DFT_GEMM 3    /* axis passes as MFMA GEMMs with the DFT matrices (N_a <= 128) */
 
 typedef struct {
   int32_t n_dof_cell;         /* n (triangles per cell) */

@@ -36,7 +36,10 @@ class PlanDesc(ct.Structure):
     _fields_ = [("grid", ct.c_int32 * 3), ("pitch", ct.c_double * 3), ("k", ct.c_double),
                 ("order", ct.c_int32), ("formulation", ct.c_int32), ("alpha_re", ct.c_double),
                 ("alpha_im", ct.c_double), ("near_radius", ct.c_int32 * 3), ("fft_shape", ct.c_int32 * 3),
-                ("precisions", ct.c_uint32)]
+                ("precisions", ct.c_uint32), ("dft_schedule", ct.c_int32)]
+
+
+DFT_SCHEDULE = {"auto": 0, "axes": 1, "fused": 2, "gemm": 3}
 
 
 class PlanInfo(ct.Structure):
@@ -288,7 +291,8 @@ class Plan:
     """A device-resident FMPBEM operator (fmbem_plan_create)."""
 
     def __init__(self, vertices, triangles, grid, pitch, k, order, formulation="bm", alpha=None,
-                 near_radius=(1, 1, 1), fft_shape=(0, 0, 0), precisions=("fp64", "fp32"), stream=None):
+                 near_radius=(1, 1, 1), fft_shape=(0, 0, 0), precisions=("fp64", "fp32"), stream=None,
+                 dft_schedule="auto"):
         lib = load()
         self._lib = lib
         v = np.ascontiguousarray(vertices, dtype=np.float64)
@@ -309,6 +313,7 @@ class Plan:
         else:
             d.alpha_re, d.alpha_im = float(np.real(alpha)), float(np.imag(alpha))
         d.precisions = sum(1 << _precision(p) for p in precisions)
+        d.dft_schedule = DFT_SCHEDULE[dft_schedule]
         h = ct.c_void_p()
         check(lib.fmbem_plan_create(ct.byref(mesh), ct.byref(d), _stream_ptr(stream), ct.byref(h)),
               "fmbem_plan_create")

@@ -47,6 +47,7 @@ __host__ __device__ inline void cfma(cplx<T>& a, cplx<T> b, cplx<T> c) {
 // plan
 // ---------------------------------------------------------------------------
 constexpr int kMaxNear = 343;   // (2*3+1)^3 near offsets at near radius 3
+constexpr int kDftGemmMaxOut = 128;  // widest output count of a DFT pass as a GEMM (one tile width)
 
 struct Plan {
   int device = 0;
@@ -72,6 +73,11 @@ struct Plan {
   void* V0[2] = {nullptr, nullptr};   // [p][n] complex, row-major, scaled
   void* U0[2] = {nullptr, nullptr};   // [n][p] complex, row-major, scaled
   void* Lam[2] = {nullptr, nullptr};  // [Bc][p(col)][ldp] complex: per canonical bin, column-major, scaled, /B
+  // DFT matrices of the grid axes (GEMM schedule), per precision: forward of axis a at [a]
+  // ([N_a][M_a], w^(k j) with w = e^(-2 pi i / N_a)), inverse at [3 + a] ([M_a][N_a], conjugate
+  // kernel); only for 1 < N_a <= kDftGemmMaxOut, else nullptr
+  void* dftF[2][6] = {};
+  int dft_forced = -1;       // DFT schedule forced by the plan descriptor (0 axes, 1 fused, 2 GEMM), -1: tuned
   // Lambda of bin -w is D Lambda(w) D, D = diag((-1)^n) (reciprocity of the translations), so only
   // canonical bins (linear index <= that of the partner bin -w) are stored.
   int Bc = 0;                // canonical bins
@@ -203,14 +209,74 @@ int near_num_shapes(int kind);
 template <typename T>
 hipError_t near_reduce_launch(const void* part, int ns, size_t len, void* y, void* y64, hipStream_t s);
 
+// Spectrum symmetry: Lambda(-w) = D Lambda(w) D with D = diag((-1)^n) over the multipole
+// index (n, m).  Bins whose linear index exceeds that of their partner -w carry the factor D
+// (flip_mode 1: on the output of the last forward pass, 2: removed from the input of the
+// first inverse pass), so that the M2L product can use the partner's Lambda.
+struct DftFlip {
+  int mode;       // 0 none, 1 output, 2 input
+  int p;          // multipole coefficients per channel group
+  int axis;       // transformed axis; the line index u, v runs over the other two (ascending)
+  int N[3];       // full grid
+};
+
+__device__ inline bool bin_flipped(const DftFlip& f, int pos, int u, int v) {
+  int c[3];
+  const int b = f.axis == 0 ? 1 : 0, d = f.axis == 2 ? 1 : 2;
+  c[f.axis] = pos;
+  c[b] = u;
+  c[d] = v;
+  const long long L = c[0] + (long long)f.N[0] * (c[1] + (long long)f.N[1] * c[2]);
+  const long long Lp = (f.N[0] - c[0]) % f.N[0] + (long long)f.N[0] * ((f.N[1] - c[1]) % f.N[1] +
+                       (long long)f.N[1] * ((f.N[2] - c[2]) % f.N[2]));
+  return L > Lp;
+}
+
+// (-1)^n of channel ch, whose multipole index is ch % p = n^2 + n + m
+__device__ inline bool odd_degree(int ch, int p) {
+  const int idx = ch % p;
+  int n = (int)sqrtf((float)idx + 0.5f);
+  while (n * n > idx) --n;
+  while ((n + 1) * (n + 1) <= idx) ++n;
+  return n & 1;
+}
+
+// One axis pass of the grid DFT as a batched MFMA GEMM on the tile body of near.hip, in place:
+// for every line (u, v) of the pass, the transposed form out_line^T = X_line^T F^T with rows =
+// channels (contiguous), k = input positions along the axis (element stride lda), columns =
+// output positions.  The job is SRC_BATCH-like: A = the grid buffer, src = F [Mout][Min] (the
+// column of output k is row k of F, contiguous), out = the grid buffer, batch = lines.  In
+// place is safe because one workgroup holds every output column of its channels (N <= the tile
+// width, checked by the launcher) and reads all of its inputs before it writes.
+struct DftGemm {
+  long long su, sv;  // element offsets of line indices u (< U) and v
+  int U;
+  DftFlip flip;      // mode 1: negate the flipped outputs, 2: negate the flipped inputs
+};
+struct DftGemmJobs {  // one job, with the list interface of the tile body
+  int count;
+  int total;
+  NearJob job[1];
+  DftGemm dg;
+};
+template <typename T>
+hipError_t dft_gemm_launch(const NearJob& job, const DftGemm& dg, hipStream_t s);
+
 // flip_p > 0: the channels are [..][p] multipole coefficients and the spectrum of every
 // non-canonical bin carries the factor D = diag((-1)^n): applied to the forward output and
 // removed from the inverse input (then Lambda of the canonical partner serves that bin).
 // schedule: 0 separate axis passes, 1 the fused two-axis kernel where it applies (else the
-// passes), -1 the built-in rule (fused for at most 256 channels).
+// passes), 2 axis passes as MFMA GEMMs with the DFT matrices fmat (forward of axis a at
+// fmat[a], inverse at fmat[3 + a]) where they apply (else the passes), -1 the built-in rule
+// (fused for at most 256 channels).
 template <typename T>
 hipError_t grid_dft_launch(void* buf, int channels, const int M[3], const int N[3], bool inverse,
-                           bool pruned, hipStream_t s, int flip_p = 0, int schedule = -1);
+                           bool pruned, hipStream_t s, int flip_p = 0, int schedule = -1,
+                           const void* const* fmat = nullptr);
+// whether the GEMM schedule applies (matrices present for every transformed axis, pruned, every
+// pass has at most kDftGemmMaxOut outputs and int-sized strides)
+template <typename T>
+bool dft_gemm_applies(int channels, const int M[3], const int N[3], bool pruned, const void* const* fmat);
 // whether the fused two-axis kernel applies (N3 = 1, N1 > 1, pruned, one channel fits its LDS)
 template <typename T>
 bool dft_fused_applies(int channels, const int M[3], const int N[3], bool pruned);

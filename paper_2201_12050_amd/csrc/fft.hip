@@ -30,38 +30,6 @@ template <typename T> struct DftTile { static constexpr int ch = sizeof(T) == 8 
 // the separate passes are faster)
 constexpr int kDft2MaxChannels = 256;
 
-// Spectrum symmetry: Lambda(-w) = D Lambda(w) D with D = diag((-1)^n) over the multipole
-// index (n, m).  Bins whose linear index exceeds that of their partner -w carry the factor D
-// (flip_mode 1: on the output of the last forward pass, 2: removed from the input of the
-// first inverse pass), so that the M2L product can use the partner's Lambda.
-struct DftFlip {
-  int mode;       // 0 none, 1 output, 2 input
-  int p;          // multipole coefficients per channel group
-  int axis;       // transformed axis; the line index u, v runs over the other two (ascending)
-  int N[3];       // full grid
-};
-
-__device__ inline bool bin_flipped(const DftFlip& f, int pos, int u, int v) {
-  int c[3];
-  const int b = f.axis == 0 ? 1 : 0, d = f.axis == 2 ? 1 : 2;
-  c[f.axis] = pos;
-  c[b] = u;
-  c[d] = v;
-  const long long L = c[0] + (long long)f.N[0] * (c[1] + (long long)f.N[1] * c[2]);
-  const long long Lp = (f.N[0] - c[0]) % f.N[0] + (long long)f.N[0] * ((f.N[1] - c[1]) % f.N[1] +
-                       (long long)f.N[1] * ((f.N[2] - c[2]) % f.N[2]));
-  return L > Lp;
-}
-
-// (-1)^n of channel ch, whose multipole index is ch % p = n^2 + n + m
-__device__ inline bool odd_degree(int ch, int p) {
-  const int idx = ch % p;
-  int n = (int)sqrtf((float)idx + 0.5f);
-  while (n * n > idx) --n;
-  while ((n + 1) * (n + 1) <= idx) ++n;
-  return n & 1;
-}
-
 template <typename T>
 __global__ __launch_bounds__(256) void dft_axis_kernel(cplx<T>* __restrict__ buf, int channels, int N, int Min,
                                                        int Mout, int sign, long long estride, int U,
@@ -277,10 +245,22 @@ bool dft_fused_applies(int channels, const int M[3], const int N[3], bool pruned
 }
 
 template <typename T>
+bool dft_gemm_applies(int channels, const int M[3], const int N[3], bool pruned, const void* const* fmat) {
+  if (!pruned || !fmat || channels < 1) return false;
+  long long str = channels;
+  for (int a = 0; a < 3; ++a) {
+    if (N[a] > 1 && (!fmat[a] || !fmat[3 + a] || N[a] > kDftGemmMaxOut || str > INT32_MAX)) return false;
+    str *= N[a];
+  }
+  return true;
+}
+
+template <typename T>
 hipError_t grid_dft_launch(void* bufv, int channels, const int M[3], const int N[3], bool inverse, bool pruned,
-                           hipStream_t s, int flip_p, int schedule) {
+                           hipStream_t s, int flip_p, int schedule, const void* const* fmat) {
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(bufv);
   if (schedule < 0) schedule = channels <= kDft2MaxChannels ? 1 : 0;
+  const bool gemm = schedule == 2 && dft_gemm_applies<T>(channels, M, N, pruned, fmat);
   if (schedule == 1 && dft_fused_applies<T>(channels, M, N, pruned)) {
     // channels per workgroup: enough workgroups to cover the CUs, within the LDS budget
     const size_t per_ch = dft2_per_channel<T>(M, N, inverse);
@@ -311,6 +291,23 @@ hipError_t grid_dft_launch(void* bufv, int channels, const int M[3], const int N
     const int Min = ext[a];
     const int Mout = inverse ? (pruned ? M[a] : N[a]) : N[a];
     const int lines = ext[b] * ext[c];
+    if (gemm) {
+      NearJob j{};
+      j.A = buf;
+      j.out = buf;
+      j.src = fmat[(inverse ? 3 : 0) + a];
+      j.M = channels;
+      j.K = Min;
+      j.N = Mout;
+      j.lda = (int)str[a];
+      j.batch = lines;
+      j.src_kind = SRC_BATCH;
+      j.dest = DEST_SLICE;
+      hipError_t e = dft_gemm_launch<T>(j, DftGemm{str[b], str[c], ext[b], fl}, s);
+      if (e != hipSuccess) return e;
+      ext[a] = Mout;
+      continue;
+    }
     constexpr int ch = DftTile<T>::ch;
     dim3 grid((channels + ch - 1) / ch, lines);
     const size_t lds = (size_t)(N[a] + Min * ch) * sizeof(cplx<T>);
@@ -323,8 +320,12 @@ hipError_t grid_dft_launch(void* bufv, int channels, const int M[3], const int N
   return hipSuccess;
 }
 
-template hipError_t grid_dft_launch<double>(void*, int, const int*, const int*, bool, bool, hipStream_t, int, int);
-template hipError_t grid_dft_launch<float>(void*, int, const int*, const int*, bool, bool, hipStream_t, int, int);
+template hipError_t grid_dft_launch<double>(void*, int, const int*, const int*, bool, bool, hipStream_t, int, int,
+                                            const void* const*);
+template hipError_t grid_dft_launch<float>(void*, int, const int*, const int*, bool, bool, hipStream_t, int, int,
+                                           const void* const*);
+template bool dft_gemm_applies<double>(int, const int*, const int*, bool, const void* const*);
+template bool dft_gemm_applies<float>(int, const int*, const int*, bool, const void* const*);
 template bool dft_fused_applies<double>(int, const int*, const int*, bool);
 template bool dft_fused_applies<float>(int, const int*, const int*, bool);
 

@@ -122,16 +122,22 @@ int cached_shape(int kind, const std::vector<NearJob>& jobs) {
   return it == g_tuned.end() ? -1 : it->second;
 }
 
-// Autotuner of the DFT schedule (the fused two-axis kernel or separate axis passes) of a
-// plan's grid with R right-hand sides: on the first application of a signature (precision,
-// lattice, transform lengths, channels) where the fused form applies, both schedules run a
-// forward + inverse transform pair on the workspace grid (before the S2M product writes it)
-// twice, timed with HIP events; the faster is cached for the process.  Otherwise, or while the
-// stream is being captured, a schedule measured earlier or the built-in rule (-1).
+// Autotuner of the DFT schedule (separate axis passes, the fused two-axis kernel, or axis passes
+// as MFMA GEMMs with the plan's DFT matrices) of a plan's grid with R right-hand sides: on the
+// first application of a signature (precision, lattice, transform lengths, channels) where more
+// than one schedule applies, each runs a forward + inverse transform pair on the workspace grid
+// (before the S2M product writes it) twice, timed with HIP events; the fastest is cached for
+// the process.  Otherwise, or while the stream is being captured, a schedule measured earlier or
+// the built-in rule (-1).
 template <typename T>
 static int dft_schedule(const Plan& P, int R, void* ws, hipStream_t s, bool tune) {
+  const int prec = sizeof(T) == 8 ? 0 : 1;
   const int ch = R * P.p;
-  if (P.n_far == 0 || !dft_fused_applies<T>(ch, P.grid, P.fft, true)) return 0;
+  if (P.n_far == 0) return 0;
+  const bool ok[3] = {true, dft_fused_applies<T>(ch, P.grid, P.fft, true),
+                      dft_gemm_applies<T>(ch, P.grid, P.fft, true, P.dftF[prec])};
+  if (!ok[1] && !ok[2]) return 0;
+  if (P.dft_forced >= 0) return ok[P.dft_forced] ? P.dft_forced : 0;
   const std::vector<long long> key{3, (long long)sizeof(T), P.grid[0], P.grid[1], P.grid[2],
                                    P.fft[0], P.fft[1], P.fft[2], ch};
   {
@@ -141,14 +147,15 @@ static int dft_schedule(const Plan& P, int R, void* ws, hipStream_t s, bool tune
   }
   if (!tune || capturing(s)) return -1;
   hipEvent_t a = nullptr, b = nullptr;
-  float t[2] = {1e30f, 1e30f};
+  float t[3] = {1e30f, 1e30f, 1e30f};
   if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
     for (int sweep = 0; sweep < 2; ++sweep)
-      for (int v = 0; v < 2; ++v) {
-        if (grid_dft_launch<T>(ws, ch, P.grid, P.fft, false, true, s, P.p, v) != hipSuccess) continue;
+      for (int v = 0; v < 3; ++v) {
+        if (!ok[v]) continue;
+        if (grid_dft_launch<T>(ws, ch, P.grid, P.fft, false, true, s, P.p, v, P.dftF[prec]) != hipSuccess) continue;
         hipEventRecord(a, s);
-        grid_dft_launch<T>(ws, ch, P.grid, P.fft, false, true, s, P.p, v);
-        grid_dft_launch<T>(ws, ch, P.grid, P.fft, true, true, s, P.p, v);
+        grid_dft_launch<T>(ws, ch, P.grid, P.fft, false, true, s, P.p, v, P.dftF[prec]);
+        grid_dft_launch<T>(ws, ch, P.grid, P.fft, true, true, s, P.p, v, P.dftF[prec]);
         hipEventRecord(b, s);
         float ms = 0.f;
         if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) continue;
@@ -157,7 +164,9 @@ static int dft_schedule(const Plan& P, int R, void* ws, hipStream_t s, bool tune
   }
   if (a) hipEventDestroy(a);
   if (b) hipEventDestroy(b);
-  const int best = t[1] < t[0] ? 1 : 0;
+  int best = 0;
+  for (int v = 1; v < 3; ++v)
+    if (t[v] < t[best]) best = v;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tuned[key] = best;
   return best;
@@ -242,14 +251,14 @@ static hipError_t matvec_overlap(const Plan& P, int R, const void* x, void* y, v
     const int shape = tune ? tuned_shape<T>(0, s2m, P.aux) : cached_shape<T>(0, s2m);
     if ((e = near_launch<T>(s2m, P.aux, shape, 0))) return e;
   }
-  if ((e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, false, true, P.aux, p, dsched))) return e;
+  if ((e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, false, true, P.aux, p, dsched, P.dftF[prec]))) return e;
   prof_end(P, 2 + 6 * prec, ev, P.aux);
   ev = prof_begin(P, 3 + 6 * prec, P.aux);
   void* lhat = nullptr;
   if ((e = m2l_apply<T>(P, R, ws, P.aux, &lhat, tune))) return e;
   prof_end(P, 3 + 6 * prec, ev, P.aux);
   ev = prof_begin(P, 4 + 6 * prec, P.aux);
-  if ((e = grid_dft_launch<T>(lhat, R * p, P.grid, P.fft, true, true, P.aux, p, dsched))) return e;
+  if ((e = grid_dft_launch<T>(lhat, R * p, P.grid, P.fft, true, true, P.aux, p, dsched, P.dftF[prec]))) return e;
   prof_end(P, 4 + 6 * prec, ev, P.aux);
   if ((e = hipEventRecord(P.ev_join, P.aux))) return e;
   // [0] near field on the caller's stream
@@ -303,7 +312,7 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
   }
   // [2]-[4] DFT, M2L, inverse DFT
   ev = prof_begin(P, 2 + 6 * prec, s);
-  hipError_t e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, false, true, s, p, dsched);
+  hipError_t e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, false, true, s, p, dsched, P.dftF[prec]);
   if (e != hipSuccess) return e;
   prof_end(P, 2 + 6 * prec, ev, s);
   ev = prof_begin(P, 3 + 6 * prec, s);
@@ -312,7 +321,7 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
   if (e != hipSuccess) return e;
   prof_end(P, 3 + 6 * prec, ev, s);
   ev = prof_begin(P, 4 + 6 * prec, s);
-  e = grid_dft_launch<T>(lhat, R * p, P.grid, P.fft, true, true, s, p, dsched);
+  e = grid_dft_launch<T>(lhat, R * p, P.grid, P.fft, true, true, s, p, dsched, P.dftF[prec]);
   if (e != hipSuccess) return e;
   prof_end(P, 4 + 6 * prec, ev, s);
   // [5] L2T with the fixed-order sum of the near partials
@@ -350,11 +359,11 @@ static hipError_t matvec_group_t(const std::vector<GroupApply>& g, hipStream_t s
       continue;
     }
     void* lhat = nullptr;
-    if ((e = grid_dft_launch<T>(a.ws, a.R * P.p, P.grid, P.fft, false, true, s, P.p, dsched[q])) != hipSuccess)
-      return e;
+    e = grid_dft_launch<T>(a.ws, a.R * P.p, P.grid, P.fft, false, true, s, P.p, dsched[q], P.dftF[prec]);
+    if (e != hipSuccess) return e;
     if ((e = m2l_apply<T>(P, a.R, a.ws, s, &lhat, tune)) != hipSuccess) return e;
-    if ((e = grid_dft_launch<T>(lhat, a.R * P.p, P.grid, P.fft, true, true, s, P.p, dsched[q])) != hipSuccess)
-      return e;
+    e = grid_dft_launch<T>(lhat, a.R * P.p, P.grid, P.fft, true, true, s, P.p, dsched[q], P.dftF[prec]);
+    if (e != hipSuccess) return e;
     l2t.push_back(l2t_job<T>(P, a.R, a.ws, lhat, a.y, a.y64));
   }
   if (l2t.empty()) return hipSuccess;

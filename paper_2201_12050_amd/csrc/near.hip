@@ -77,9 +77,14 @@ __device__ inline int lds_slot(int r, int c) { return 4 * r + (c ^ ((r >> 2) & 3
 // ACOL: batched job with column-major A (the M2L products).  PIPE: k steps whose global loads
 // are in flight at once (1: the next step during the MFMAs of the current one; 2: also the one
 // after, in a second register set).  FINAL: the kernel takes DEST_FINAL jobs (the L2T launch
-// only, so that the other launches do not carry the registers of its epilogue).
-template <typename T, int ROWS, int COLS, int WR, int KC, int PIPE, bool ACOL = false, bool FINAL = false>
-__device__ __forceinline__ void near_tile(const NearJobs& jobs) {
+// only, so that the other launches do not carry the registers of its epilogue).  JL: the job
+// list; DftGemmJobs makes the tile an axis pass of the grid DFT (column-major A = the grid
+// lines, product b = line b, one DFT matrix as B, in-place output, symmetry signs).
+template <typename T, int ROWS, int COLS, int WR, int KC, int PIPE, bool ACOL = false, bool FINAL = false,
+          typename JL = NearJobs>
+__device__ __forceinline__ void near_tile(const JL& jobs) {
+  constexpr bool DFTG = std::is_same<JL, DftGemmJobs>::value;
+  static_assert(!DFTG || ACOL, "the DFT passes use the column-major A form");
   constexpr int WC = 4 / WR;
   constexpr int RBW = ROWS / (16 * WR);  // 16-row MFMA blocks per wave
   constexpr int CBW = COLS / (16 * WC);  // 16-column MFMA blocks per wave
@@ -121,7 +126,16 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
   }
   const int m0 = (local / ctiles) * ROWS;
   const int col0 = (local % ctiles) * COLS;
-  const cplx<T>* A = reinterpret_cast<const cplx<T>*>(jb.A) + (ACOL ? (size_t)(jb.amap ? jb.amap[bb] : bb) * K * lda : 0);
+  // DFT pass: line bb = (u, v) of the pass starts at u su + v sv
+  long long line_off = 0;
+  int line_u = 0, line_v = 0;
+  if constexpr (DFTG) {
+    line_u = bb % jobs.dg.U;
+    line_v = bb / jobs.dg.U;
+    line_off = line_u * jobs.dg.su + line_v * jobs.dg.sv;
+  }
+  const cplx<T>* A = reinterpret_cast<const cplx<T>*>(jb.A) +
+                     (DFTG ? (size_t)line_off : ACOL ? (size_t)(jb.amap ? jb.amap[bb] : bb) * K * lda : 0);
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -139,7 +153,9 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
       int r, i1, i2, i3;
       cell_coords(jb, j, r, i1, i2, i3);
       const cplx<T>* src = reinterpret_cast<const cplx<T>*>(jb.src);
-      if (ACOL) {
+      if (DFTG) {
+        bcol = src + (size_t)j * K;  // one DFT matrix for every line
+      } else if (ACOL) {
         bcol = src + ((size_t)bb * N + j) * K;
       } else if (jb.src_kind == SRC_X) {
         const int s1 = i1 - jb.d0, s2 = i2 - jb.d1, s3 = i3 - jb.d2;
@@ -221,6 +237,15 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
         const bool v = kin && m0 + a_row + q < M;
         ra[q] = v ? acol[q] : mk<T>(0, 0);
         amask |= (v ? 1u : 0u) << q;
+      }
+      if constexpr (DFTG) {
+        // first inverse pass: the factor D leaves the non-canonical bins on the way in
+        const DftFlip& fl = jobs.dg.flip;
+        if (fl.mode == 2 && kin && bin_flipped(fl, k0 + a_k, line_u, line_v)) {
+#pragma unroll
+          for (int q = 0; q < APT; ++q)
+            if (odd_degree(m0 + a_row + q, fl.p)) ra[q] = mk<T>(-ra[q].x, -ra[q].y);
+        }
       }
     } else {
 #pragma unroll
@@ -467,6 +492,15 @@ __device__ __forceinline__ void near_tile(const NearJobs& jobs) {
       const int cl = e / ROWS, rl = e - cl * ROWS;
       const int col = col0 + cb + cl, m = m0 + rl;
       if (col >= N || m >= M) continue;
+      if constexpr (DFTG) {
+        // output position col of the line, channel m; the last forward pass puts D on the
+        // non-canonical bins
+        cplx<T> v = Cst[cl * LDC + rl];
+        const DftFlip& fl = jobs.dg.flip;
+        if (fl.mode == 1 && odd_degree(m, fl.p) && bin_flipped(fl, col, line_u, line_v)) v = mk<T>(-v.x, -v.y);
+        out[(size_t)line_off + (size_t)col * lda + m] = v;
+        continue;
+      }
       size_t base;
       if (ACOL) {
         base = ((size_t)bb * N + col) * M;
@@ -498,6 +532,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
 template <typename T, int ROWS, int COLS, int WR, int KC, int WPE, int PIPE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void m2l_kernel(NearJobs jobs) {
   near_tile<T, ROWS, COLS, WR, KC, 1, true>(jobs);
+}
+template <typename T, int ROWS, int COLS, int WR, int KC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void dft_gemm_kernel(DftGemmJobs jobs) {
+  near_tile<T, ROWS, COLS, WR, KC, 1, true, false, DftGemmJobs>(jobs);
 }
 
 // y[col][m] = sum_s part[s][col][m] in a fixed order (optionally written as FP64)
@@ -640,6 +678,30 @@ hipError_t near_launch(const std::vector<NearJob>& list, hipStream_t s, int shap
   return hipSuccess;
 }
 
+// DFT passes: the tile width is the smallest of 32 / 64 / 128 output columns that holds every
+// output of the pass (one column tile per line, so the pass can run in place); rows = channels
+template <typename T>
+hipError_t dft_gemm_launch(const NearJob& job, const DftGemm& dg, hipStream_t s) {
+  if (job.N > kDftGemmMaxOut || job.batch < 1 || job.M < 1 || job.K < 1 || !job.A || !job.src) return hipErrorInvalidValue;
+  constexpr int kc = shape_kc<T>();
+  DftGemmJobs jl;
+  jl.count = 1;
+  jl.job[0] = job;
+  jl.job[0].tile0 = 0;
+  jl.dg = dg;
+  const int rows = job.N <= 64 ? 64 : 32;
+  const long long tiles = (long long)job.batch * ((job.M + rows - 1) / rows);
+  if (tiles > INT32_MAX) return hipErrorInvalidValue;
+  jl.total = (int)tiles;
+  if (job.N <= 32)
+    hipLaunchKernelGGL((dft_gemm_kernel<T, 64, 32, 2, kc>), dim3((unsigned)tiles), dim3(256), 0, s, jl);
+  else if (job.N <= 64)
+    hipLaunchKernelGGL((dft_gemm_kernel<T, 64, 64, 4, kc>), dim3((unsigned)tiles), dim3(256), 0, s, jl);
+  else
+    hipLaunchKernelGGL((dft_gemm_kernel<T, 32, 128, 1, kc>), dim3((unsigned)tiles), dim3(256), 0, s, jl);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t near_reduce_launch(const void* part, int ns, size_t len, void* y, void* y64, hipStream_t s) {
   const unsigned blocks = (unsigned)std::min<size_t>((len + 255) / 256, 8192);
@@ -648,6 +710,8 @@ hipError_t near_reduce_launch(const void* part, int ns, size_t len, void* y, voi
   return hipGetLastError();
 }
 
+template hipError_t dft_gemm_launch<double>(const NearJob&, const DftGemm&, hipStream_t);
+template hipError_t dft_gemm_launch<float>(const NearJob&, const DftGemm&, hipStream_t);
 template hipError_t near_launch<double>(const std::vector<NearJob>&, hipStream_t, int, int);
 template hipError_t near_launch<float>(const std::vector<NearJob>&, hipStream_t, int, int);
 template int near_num_shapes<double>(int);

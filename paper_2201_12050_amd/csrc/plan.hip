@@ -629,6 +629,47 @@ static hipError_t plan_build(Plan& P, const std::vector<double>& geo, hipStream_
     }
   }
   const bool want32 = (P.precisions & (1u << FMBEM_FP32)) != 0;
+  // DFT matrices of the axes for the GEMM schedule of the grid DFT (Sec. 2.4, the DFT over the
+  // grid as products with the Fourier matrices): forward [N][M] (pruned input), inverse [M][N]
+  // (cropped output, conjugate kernel; the 1/B of the inverse is folded into Lambda)
+  std::vector<double2> fm64[6];
+  std::vector<float2> fm32[6];
+  auto dft_mats = [&]() -> hipError_t {
+    for (int a = 0; a < 3; ++a) {
+      const int Nn = P.fft[a], Mm = P.grid[a];
+      if (Nn <= 1 || Nn > kDftGemmMaxOut) continue;
+      for (int dir = 0; dir < 2; ++dir) {
+        const int rows = dir == 0 ? Nn : Mm, cols = dir == 0 ? Mm : Nn;
+        const double sgn = dir == 0 ? -1.0 : 1.0;
+        const int slot = 3 * dir + a;
+        std::vector<double2>& h = fm64[slot];
+        h.resize((size_t)rows * cols);
+        for (int k = 0; k < rows; ++k)
+          for (int j = 0; j < cols; ++j) {
+            const double ang = 2.0 * M_PI * (double)(((long long)k * j) % Nn) / Nn;
+            h[(size_t)k * cols + j] = make_double2(std::cos(ang), sgn * std::sin(ang));
+          }
+        FM_CHECK(plan_alloc(P, &P.dftF[0][slot], h.size() * sizeof(double2)));
+        FM_CHECK(hipMemcpyAsync(P.dftF[0][slot], h.data(), h.size() * sizeof(double2), hipMemcpyHostToDevice, s));
+        if (want32) {
+          std::vector<float2>& h32 = fm32[slot];
+          h32.resize(h.size());
+          for (size_t i = 0; i < h.size(); ++i) h32[i] = make_float2((float)h[i].x, (float)h[i].y);
+          FM_CHECK(plan_alloc(P, &P.dftF[1][slot], h32.size() * sizeof(float2)));
+          FM_CHECK(hipMemcpyAsync(P.dftF[1][slot], h32.data(), h32.size() * sizeof(float2), hipMemcpyHostToDevice,
+                                  s));
+        }
+      }
+    }
+    return hipSuccess;
+  };
+  {
+    // the host tables must outlive their copies, also when a step fails
+    const hipError_t e1 = dft_mats();
+    const hipError_t e2 = hipStreamSynchronize(s);
+    FM_CHECK(e1);
+    FM_CHECK(e2);
+  }
   const double2 alpha = make_double2(P.alpha_re, P.alpha_im);
   const int hyper = (P.alpha_re != 0.0 || P.alpha_im != 0.0) ? 1 : 0;
   // near blocks
@@ -770,6 +811,7 @@ extern "C" fmbem_status fmbem_plan_create(const fmbem_cell_mesh* mesh, const fmb
   if (desc->order < 0 || desc->order > 20) return FMBEM_ERR_INVALID_ARG;
   if (desc->formulation != FMBEM_BURTON_MILLER && desc->formulation != FMBEM_CBIE) return FMBEM_ERR_INVALID_ARG;
   if (desc->precisions & ~3u) return FMBEM_ERR_INVALID_ARG;
+  if (desc->dft_schedule < FMBEM_DFT_AUTO || desc->dft_schedule > FMBEM_DFT_GEMM) return FMBEM_ERR_INVALID_ARG;
   const int n = mesh->n_triangles;
   // geometry on the host: a, b, c, centroid, unit normal, longest edge, area
   std::vector<double> geo((size_t)n * 18, 0.0);
@@ -841,6 +883,7 @@ extern "C" fmbem_status fmbem_plan_create(const fmbem_cell_mesh* mesh, const fmb
     P->alpha_im = desc->alpha_im;
   }
   P->precisions = desc->precisions == 0 ? 1u : desc->precisions;
+  P->dft_forced = desc->dft_schedule - 1;
   // near offsets (Chebyshev radius, axes with a single cell dropped)
   int rr[3];
   for (int a = 0; a < 3; ++a) rr[a] = P->grid[a] > 1 ? std::min(P->near_radius[a], P->grid[a] - 1) : 0;

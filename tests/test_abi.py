@@ -58,7 +58,7 @@ def _mesh(v, t):
 
 
 @pytest.mark.parametrize("case", ["null", "bad_index", "degenerate", "order", "fft", "k", "grid", "formulation",
-                                  "nan_vertex", "radius"])
+                                  "nan_vertex", "radius", "dft_schedule"])
 def test_plan_create_rejects_invalid_arguments(case):
     lib = fm.load()
     v, t = icosphere(1, 0.1)
@@ -85,6 +85,8 @@ def test_plan_create_rejects_invalid_arguments(case):
         desc = _desc(formulation=7)
     elif case == "radius":
         desc = _desc(near_radius=(4, 1, 1))
+    elif case == "dft_schedule":
+        desc = _desc(dft_schedule=4)
     mesh, keep = _mesh(v, t)
     assert lib.fmbem_plan_create(ct.byref(mesh), ct.byref(desc), None, ct.byref(out)) == 1
     assert out.value is None
