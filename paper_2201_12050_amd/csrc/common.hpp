@@ -268,7 +268,7 @@ hipError_t dft_gemm_launch(const NearJob& job, const DftGemm& dg, hipStream_t s)
 // schedule: 0 separate axis passes, 1 the fused two-axis kernel where it applies (else the
 // passes), 2 axis passes as MFMA GEMMs with the DFT matrices fmat (forward of axis a at
 // fmat[a], inverse at fmat[3 + a]) where they apply (else the passes), -1 the built-in rule
-// (fused for at most 256 channels).
+// (fused for at most 256 channels, else the GEMM passes where they apply).
 template <typename T>
 hipError_t grid_dft_launch(void* buf, int channels, const int M[3], const int N[3], bool inverse,
                            bool pruned, hipStream_t s, int flip_p = 0, int schedule = -1,

@@ -25,9 +25,11 @@ namespace fmbem {
 // channels per workgroup (16 complex doubles or 32 complex floats = 256 bytes per row),
 // and output groups so that a workgroup has 256 threads
 template <typename T> struct DftTile { static constexpr int ch = sizeof(T) == 8 ? 16 : 32; };
-// channel count up to which small two-axis grids take the fused kernel (measured on a 32 x 32
-// grid: 121 channels 18.5 + 21.3 -> 14.6 + 14.1 us forward + inverse; from about 500 channels
-// the separate passes are faster)
+// built-in schedule (no measurement, e.g. engine rounds): the fused kernel up to this channel
+// count (measured on a 32 x 32 grid: 121 channels 18.5 + 21.3 -> 14.6 + 14.1 us forward +
+// inverse; from about 500 channels the separate passes are faster), above it the GEMM passes
+// where they apply (faster than the direct passes from about 1000 channels), else the direct
+// passes
 constexpr int kDft2MaxChannels = 256;
 
 template <typename T>
@@ -259,7 +261,7 @@ template <typename T>
 hipError_t grid_dft_launch(void* bufv, int channels, const int M[3], const int N[3], bool inverse, bool pruned,
                            hipStream_t s, int flip_p, int schedule, const void* const* fmat) {
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(bufv);
-  if (schedule < 0) schedule = channels <= kDft2MaxChannels ? 1 : 0;
+  if (schedule < 0) schedule = channels <= kDft2MaxChannels ? 1 : 2;
   const bool gemm = schedule == 2 && dft_gemm_applies<T>(channels, M, N, pruned, fmat);
   if (schedule == 1 && dft_fused_applies<T>(channels, M, N, pruned)) {
     // channels per workgroup: enough workgroups to cover the CUs, within the LDS budget
