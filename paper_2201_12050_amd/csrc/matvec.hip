@@ -100,6 +100,14 @@ int tuned_shape(int kind, const std::vector<NearJob>& jobs, hipStream_t s) {
     }
     for (int v = 0; v < ns; ++v)
       if (t[v] < 1e29f && (best < 0 || t[v] < t[best])) best = v;
+    // the lowest-numbered shape within 2 % of the fastest: timing noise would otherwise flip the
+    // choice between near-equal shapes from one process to the next
+    if (best >= 0)
+      for (int v = 0; v < best; ++v)
+        if (t[v] <= 1.02f * t[best]) {
+          best = v;
+          break;
+        }
   }
   if (a) hipEventDestroy(a);
   if (b) hipEventDestroy(b);
