@@ -402,6 +402,7 @@ struct Member {
   int j = 0;                       // Arnoldi steps queued in the current cycle
   int epoch = 0;
   int its = 0, refs = 0;
+  bool x_zero = false;  // every RHS starts from x = 0 (set by started(), cleared by the first true residual)
   bool ok = false;
   bool bad_input = false;
   bool emit = true;  // false: post() updates host state only (a captured graph replays the kernels)
@@ -477,7 +478,7 @@ struct Member {
     for (int i = 0; i < 2; ++i) {
       if ((e = hipHostMalloc((void**)&hjd[i], R * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent))) return e;
       if ((e = hipHostGetDevicePointer((void**)&djd[i], hjd[i], 0))) return e;
-      if ((e = hipHostMalloc((void**)&hres[i], R * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent)))
+      if ((e = hipHostMalloc((void**)&hres[i], 2 * R * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent)))
         return e;
       if ((e = hipHostGetDevicePointer((void**)&dres[i], hres[i], 0))) return e;
     }
@@ -521,17 +522,22 @@ struct Member {
     emit = true;
     err = hipSuccess;
   }
-  // ||b|| per RHS into the round slot's mapped norms (read by started() once that round completed)
+  // ||b|| and ||x|| per RHS into the round slot's mapped norms (read by started() once that round
+  // completed)
   void start(int slot) {
     norm(b, hn);
     hipLaunchKernelGGL(norm_out_kernel, dim3((R + 63) / 64), dim3(64), 0, s, hn, hstride, R, dres[slot]);
+    norm(x, hn);
+    hipLaunchKernelGGL(norm_out_kernel, dim3((R + 63) / 64), dim3(64), 0, s, hn, hstride, R, dres[slot] + R);
     rec[slot] = Rec{K_INIT, 0, epoch};
     phase = WAIT;
   }
   hipError_t started(int slot) {
+    x_zero = true;
     for (int q = 0; q < R; ++q) {
       bn[q] = hres[slot][q];
       if (!std::isfinite(bn[q])) return hipErrorInvalidValue;
+      if (hres[slot][R + q] != 0.0) x_zero = false;
     }
     if (ip == FMBEM_FP64) {
       gm_prec = FMBEM_FP64;
@@ -582,10 +588,16 @@ struct Member {
     }
     switch (phase) {
       case RUN_TRUE:
-        req = true;
-        req_prec = FMBEM_FP64;
-        req_in = x;
-        req_out = t;
+        if (x_zero) {
+          // zero initial guess: A x = 0, the first true residual is b without an operator application
+          hipLaunchKernelGGL(zero_kernel, dim3(lgrid(vlen)), dim3(256), 0, s, t, vlen);
+          x_zero = false;
+        } else {
+          req = true;
+          req_prec = FMBEM_FP64;
+          req_in = x;
+          req_out = t;
+        }
         rec[slot] = Rec{K_TRUE, 0, epoch};
         break;
       case RUN_RESTART:

@@ -238,6 +238,31 @@ def test_solve_gram_schmidt_modes(tiny, ortho):
         del _lib.ORTHO["bogus"]
 
 
+def test_solve_initial_guess(tiny):
+    # a nonzero initial guess takes the operator application of the first true residual (a zero
+    # one skips it: A 0 = 0); warm start from the LU solution stops before any iteration; a zero
+    # and a nonzero guess in one multi-RHS solve
+    w, F, P = tiny["bm"]
+    a = bem.default_alpha(w.k, "bm")
+    b = bem.rhs_plane_wave(w.vertices, w.triangles, w.lattice, w.k, a, w.plane_waves)
+    x_lu = solve.lu_solve(F.dense(), b[0])
+    bd = P.incident_plane_wave(w.plane_waves)
+    shape = bd.shape
+    for inner in ("fp64", "fp32"):
+        x0 = torch.from_numpy(random_complex(shape, 31)).cuda()
+        xs, info = P.solve(bd, x=x0, tol=1e-9, inner=inner)
+        assert info[0]["rel_residual"] <= 1e-9 and rel(xs.cpu().numpy().ravel(), x_lu) < 1e-6
+        warm = torch.from_numpy(x_lu.reshape(shape)).cuda()
+        xw, info = P.solve(bd, x=warm, tol=1e-9, inner=inner)
+        assert info[0]["iterations"] == 0 and info[0]["rel_residual"] <= 1e-9
+    b2 = torch.cat([bd, bd]).contiguous()
+    x2 = torch.cat([torch.zeros_like(bd), torch.from_numpy(random_complex(shape, 32)).cuda()]).contiguous()
+    xs, info = P.solve(b2, x=x2, tol=1e-9, inner="fp32")
+    for q in range(2):
+        assert info[q]["rel_residual"] <= 1e-9
+        assert rel(xs[q].cpu().numpy().ravel(), x_lu) < 1e-6
+
+
 def test_solve_rejects_non_finite_rhs(tiny):
     import paper_2201_12050_amd as fm
     w, F, P = tiny["bm"]
