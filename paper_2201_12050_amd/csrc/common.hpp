@@ -220,6 +220,9 @@ struct DftFlip {
   int N[3];       // full grid
 };
 
+// -c mod n for 0 <= c < n, without a division
+__device__ inline int neg_mod(int c, int n) { return c == 0 ? 0 : n - c; }
+
 __device__ inline bool bin_flipped(const DftFlip& f, int pos, int u, int v) {
   int c[3];
   const int b = f.axis == 0 ? 1 : 0, d = f.axis == 2 ? 1 : 2;
@@ -227,8 +230,8 @@ __device__ inline bool bin_flipped(const DftFlip& f, int pos, int u, int v) {
   c[b] = u;
   c[d] = v;
   const long long L = c[0] + (long long)f.N[0] * (c[1] + (long long)f.N[1] * c[2]);
-  const long long Lp = (f.N[0] - c[0]) % f.N[0] + (long long)f.N[0] * ((f.N[1] - c[1]) % f.N[1] +
-                       (long long)f.N[1] * ((f.N[2] - c[2]) % f.N[2]));
+  const long long Lp = neg_mod(c[0], f.N[0]) +
+                       (long long)f.N[0] * (neg_mod(c[1], f.N[1]) + (long long)f.N[1] * neg_mod(c[2], f.N[2]));
   return L > Lp;
 }
 

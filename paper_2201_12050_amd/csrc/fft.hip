@@ -132,7 +132,7 @@ constexpr int kQ = 1;
 
 __device__ inline bool flipped2(int k0, int k1, int N0, int N1) {
   const long long L = k0 + (long long)N0 * k1;
-  const long long Lp = (N0 - k0) % N0 + (long long)N0 * ((N1 - k1) % N1);
+  const long long Lp = neg_mod(k0, N0) + (long long)N0 * neg_mod(k1, N1);
   return L > Lp;
 }
 
