@@ -119,9 +119,46 @@ def batched_grids(fm, torch, args):
                      "iterations": [r[1][0]["iterations"] for r in res],
                      "max_rel_residual": max(i["rel_residual"] for r in res for i in r[1]),
                      "sampled_solution_error": err}
+    out["stage_rooflines_fp32"] = batched_stage_rooflines(torch, plans, bs, ws)
     for P in plans:
         P.close()
     return out
+
+
+def batched_stage_rooflines(torch, plans, bs, ws):
+    """Per-stage device times of FP32 operator applications with all RHS of each lattice (HIP
+    events around every stage, outside the timed solves) and their roofline fractions: DFT and
+    inverse DFT by algorithmic bytes 8 p R (C + B) per transform (pruned input or cropped
+    output, all bins) against 8 TB/s; M2L by 8 p^2 B R flop against the FP32 MFMA peak; near +
+    S2M by its algorithmic flop count against the same peak."""
+    rows = []
+    for P, b, w in zip(plans, bs, ws):
+        R = b.shape[0]
+        x = b.to(torch.complex64)
+        wsb = P.workspace(R, "fp32")
+        y = torch.empty_like(x)
+        for _ in range(2):
+            P.matvec(x, y, "fp32", wsb)
+        torch.cuda.synchronize()
+        P.profile()
+        for _ in range(10):
+            P.matvec(x, y, "fp32", wsb)
+        torch.cuda.synchronize()
+        pr = P.profile_read()
+        P.profile([])
+        st = {k[:-5]: v[0] / v[1] * 1e-3 for k, v in pr.items() if v[1] and k.endswith("_fp32")}
+        p, C, n = P.p, w.lattice.n_cells, w.n_dof_cell
+        B = int(np.prod(P.info["fft_shape"]))
+        dft_bytes = 8.0 * p * R * (C + B)
+        m2l_flops = 8.0 * p * p * B * R
+        near_flops = 8.0 * n * n * near_pairs(w.lattice.grid) * R + 8.0 * p * n * C * R
+        rows.append({"lattice": "x".join(str(g) for g in w.lattice.grid[:2]), "n_rhs": R, "bins": B,
+                     "stage_us": {k: v * 1e6 for k, v in st.items()},
+                     "dft_frac_hbm": dft_bytes / st["fft"] / PEAK_HBM,
+                     "idft_frac_hbm": dft_bytes / st["ifft"] / PEAK_HBM,
+                     "m2l_frac_mfma": m2l_flops / st["m2l"] / PEAK_FP32_MFMA,
+                     "near_frac_mfma": near_flops / st["near"] / PEAK_FP32_MFMA})
+    return rows
 
 
 def barrier_sweep(fm, torch, args):
