@@ -8,7 +8,8 @@ and the ``cpu_baseline`` leg of ``bench.py`` may import it; the product path
 Contents (paper sections in brackets):
   quadrature  Gauss-Legendre nodes by Newton's method; Duffy-collapsed triangle rules
   kernels     Green's function G and its normal derivatives [Sec. 2.1, eq. (green3dFull), (hbie), (bm)]
-  bem         collocation entries, near-field blocks S_d, dense exact BEM (O1), incident fields [Sec. 2.1-2.2]
+  bem         collocation entries, near-field blocks S_d, dense exact BEM (O1), incident fields [Sec. 2.1-2.2];
+              pressure at points of the fluid, insertion loss [eq. (cbie) with c = 1, eq. (insertionloss)]
   specfun     spherical Bessel/Hankel (SciPy), harmonics, Wigner 3j (Racah, exact integers)
   fmm         P2M (V0), L2P (U0), M2L (K_d) operators [Sec. 3.1, Appendix A]
   operator    FMPBEM operator S + U K V applied block by block, no FFT (O2) [Sec. 3.2]

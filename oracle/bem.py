@@ -22,6 +22,11 @@ implementations follow):
     (1/4pi) int [e^{ikR}(1-ikR) - 1] R^-3 dA, a weakly singular remainder
     integrated with a 16 x 16 Duffy rule on each of the three sub-triangles
     (x, v_a, v_b) collapsed at x.
+
+Post-processing (Sec. 2.1, eq. (cbie) with c = 1; eq. (insertionloss)): the pressure
+at points of the fluid is the incident field minus the double-layer potential of the
+surface pressure, integrated with the same non-self Duffy rule (the paper does not
+state a field quadrature; points must lie in the fluid, off the surface).
 """
 from __future__ import annotations
 
@@ -190,3 +195,74 @@ def rhs_point_source(vertices, triangles, lattice, k, alpha, sources, amplitude=
         dp = amplitude * np.exp(1j * k * R) * (1j * k * R - 1.0) / R ** 2 * (r * n).sum(1) / R
         out.append(p + alpha * dp)
     return np.array(out)
+
+
+# ---------------------------------------------------------------------------
+# Post-processing: pressure at points in the fluid and insertion loss
+# ---------------------------------------------------------------------------
+
+def incident_plane_wave_at(points, k, directions, amplitude=1.0):
+    """p_inc = A e^{ik d.x} (eq. (planewave)) at arbitrary points; [R, M]."""
+    x = np.asarray(points, dtype=np.float64)
+    return np.array([amplitude * np.exp(1j * k * (x @ np.asarray(d))) for d in np.atleast_2d(directions)])
+
+
+def incident_point_source_at(points, k, sources, amplitude=1.0):
+    """Monopole p_inc = A e^{ikR}/R, R = |x - s| (Sec. 4.2) at arbitrary points; [R, M]."""
+    x = np.asarray(points, dtype=np.float64)
+    out = []
+    for s in np.atleast_2d(sources):
+        R = np.linalg.norm(x - s, axis=1)
+        out.append(amplitude * np.exp(1j * k * R) / R)
+    return np.array(out)
+
+
+def field_weights(vertices, triangles, lattice, k, points, chunk: int = 1 << 15):
+    """W[m, j] = int_{Delta_j} dG/dn_y(x_m, y) dA(y) for every element j of every cell
+    (ordered [cell][element], as the surface unknowns), the non-self Duffy rule of the
+    module docstring chosen by |x_m - centroid_j| against the longest edge of j."""
+    geom = element_geometry(vertices, triangles)
+    x = np.asarray(points, dtype=np.float64)
+    n = geom["centroid"].shape[0]
+    C = lattice.n_cells
+    W = np.zeros((x.shape[0], C * n), dtype=np.complex128)
+    for c in range(C):
+        o = lattice.cell_origin(c)
+        sa, sb, sc = geom["a"] + o, geom["b"] + o, geom["c"] + o
+        dist = np.linalg.norm(x[:, None, :] - (geom["centroid"] + o)[None, :, :], axis=-1)
+        order = rule_order(dist, geom["longest"][None, :])
+        for q in (4, 8, 16):
+            im, jb = np.nonzero(order == q)
+            for s in range(0, im.size, chunk):
+                i_ = im[s:s + chunk]
+                j_ = jb[s:s + chunk]
+                pts, w = duffy_points(sa[j_], sb[j_], sc[j_], q)
+                vals = kernels.dgreen_dny(x[i_][:, None, :], pts, geom["normal"][j_][:, None, :], k)
+                W[i_, c * n + j_] = (vals * w).sum(-1)
+    return W
+
+
+def field(vertices, triangles, lattice, k, points, p_surface, p_inc=None):
+    """Pressure at points x_m of the fluid from the surface pressure of a rigid scatterer:
+    the CBIE (eq. (cbie)) with c(x) = 1 for x in the domain and dp/dn = 0 on the surface,
+
+        p(x_m) = p_inc(x_m) - sum_j p_j int_{Delta_j} dG/dn_y(x_m, y) dA(y).
+
+    p_surface: [R, N] (or [N]); p_inc: [R, M] at the points, or None for the scattered
+    part alone.  Returns [R, M] (or [M])."""
+    ps = np.asarray(p_surface, dtype=np.complex128)
+    single = ps.ndim == 1
+    ps = np.atleast_2d(ps)
+    W = field_weights(vertices, triangles, lattice, k, points)
+    out = -(ps @ W.T)
+    if p_inc is not None:
+        out = out + np.atleast_2d(p_inc)
+    return out[0] if single else out
+
+
+def insertion_loss(p_inc, p):
+    """IL = 20 log10( sum_i |p_inc(x_i)| / sum_i |p(x_i)| ) over the observation points
+    (eq. (insertionloss)); inputs [R, M] (or [M]), returns [R] (or a scalar)."""
+    a = np.abs(np.asarray(p_inc)).sum(-1)
+    b = np.abs(np.asarray(p)).sum(-1)
+    return 20.0 * np.log10(a / b)

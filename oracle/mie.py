@@ -7,14 +7,17 @@ the total surface pressure
     p(a, t) = sum_n i^n (2n+1) [j_n(ka) - j_n'(ka) h_n(ka) / h_n'(ka)] P_n(cos t)
             = sum_n i^{n+1} (2n+1) P_n(cos t) / ((ka)^2 h_n'(ka)),
 
-the second form by the Wronskian j_n y_n' - j_n' y_n = 1/x^2.
+the second form by the Wronskian j_n y_n' - j_n' y_n = 1/x^2.  Off the surface, at
+r >= a, the total pressure is
+
+    p(r, t) = sum_n i^n (2n+1) [j_n(kr) - j_n'(ka) h_n(kr) / h_n'(ka)] P_n(cos t).
 """
 from __future__ import annotations
 
 import numpy as np
 from scipy import special
 
-from .specfun import sph_hd
+from .specfun import sph_h, sph_hd, sph_j, sph_jd
 
 
 def rigid_sphere_surface_pressure(points, radius, k, direction=(1.0, 0.0, 0.0), n_terms=None):
@@ -26,4 +29,19 @@ def rigid_sphere_surface_pressure(points, radius, k, direction=(1.0, 0.0, 0.0), 
     out = np.zeros(pts.shape[0], dtype=np.complex128)
     for n in range(N + 1):
         out += (1j ** ((n + 1) % 4)) * (2 * n + 1) * special.eval_legendre(n, ct) / (ka * ka * sph_hd(n, ka))
+    return out
+
+
+def rigid_sphere_total_field(points, radius, k, direction=(1.0, 0.0, 0.0), n_terms=None):
+    """Total pressure (incident + scattered) at points with |x| >= radius."""
+    pts = np.asarray(points, dtype=np.float64)
+    d = np.asarray(direction, dtype=np.float64)
+    r = np.linalg.norm(pts, axis=1)
+    ct = (pts @ d) / r
+    ka = k * radius
+    N = int(k * r.max() + 30) if n_terms is None else n_terms
+    out = np.zeros(pts.shape[0], dtype=np.complex128)
+    for n in range(N + 1):
+        radial = sph_j(n, k * r) - sph_jd(n, ka) * sph_h(n, k * r) / sph_hd(n, ka)
+        out += (1j ** (n % 4)) * (2 * n + 1) * radial * special.eval_legendre(n, ct)
     return out
