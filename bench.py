@@ -164,12 +164,15 @@ def batched_stage_rooflines(torch, plans, bs, ws):
 def barrier_sweep(fm, torch, args):
     """Sonic-crystal barrier: 40 x 2 x 8 lattice of open tube cells (192 triangles, N = 122,880), a
     point source 2 m in front, frequencies spread over 100 Hz - 2 kHz (n_t = 10 up to 1 kHz, else 14),
-    FP32-refined solves.  The plan of the next frequency is built on a worker thread (own stream)
-    while the current one solves; 2 frequencies are checked against FP64 reference solves."""
+    FP32-refined solves, then the insertion loss at 64 receivers behind the barrier (field
+    evaluation, eq. (cbie) with c = 1; eq. (insertionloss)).  The plan of the next frequency is
+    built on a worker thread (own stream) while the current one solves; 2 frequencies are checked
+    against FP64 reference solves (solution and insertion loss)."""
     import queue
     import threading
-    from workloads import config_barrier_r4b
+    from workloads import barrier_receivers, config_barrier_r4b
     idx = [int(round(i)) for i in np.linspace(0, 95, args.barrier_freqs)]
+    rec = barrier_receivers()
     ready = queue.Queue(maxsize=1)
     build_stream = torch.cuda.Stream()
 
@@ -194,26 +197,35 @@ def barrier_sweep(fm, torch, args):
         x, info = P.solve(b, tol=args.tol, inner="fp32", ortho=args.ortho, restart=args.barrier_restart,
                           max_iters=args.barrier_max_iters, raise_on_not_converged=False)
         torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        # insertion loss at the receivers (eq. (insertionloss)): incident and total pressure there
+        pin = P.incident_at_points("point_source", w.point_sources, rec)
+        il = fm.insertion_loss(pin, P.field(x, rec, pin))
+        il_db = float(il[0])
+        t2 = time.perf_counter()
         rows.append({"f_hz": round(w.frequency, 1), "n_t": w.order, "iterations": info[0]["iterations"],
-                     "rel_residual": info[0]["rel_residual"], "solve_ms": (time.perf_counter() - t0) * 1e3,
-                     "plan_build_ms": t_build * 1e3})
+                     "rel_residual": info[0]["rel_residual"], "solve_ms": (t1 - t0) * 1e3,
+                     "field_ms": (t2 - t1) * 1e3, "il_db": il_db, "plan_build_ms": t_build * 1e3})
         if k in (0, len(idx) - 1):
-            checks.append((P, b, x))
+            checks.append((P, b, x, pin, il_db))
         else:
             P.close()
     total = time.perf_counter() - t_start
     th.join()
-    errs = []
-    for P, b, x in checks:
+    errs, il_diff = [], []
+    for P, b, x, pin, il_db in checks:
         xr = P.solve(b, tol=1e-12, inner="fp64", restart=args.barrier_restart, max_iters=args.barrier_max_iters,
                      raise_on_not_converged=False)[0]
         errs.append(torch.linalg.vector_norm(x - xr).item() / torch.linalg.vector_norm(xr).item())
+        il_diff.append(abs(il_db - float(fm.insertion_loss(pin, P.field(xr, rec, pin))[0])))
         P.close()
     return {"workload": "barrier 40x2x8 open tube cells (192 triangles, N = 122,880), point source, "
                         f"{len(idx)} frequencies 100 Hz - 2 kHz", "gmres_restart": args.barrier_restart,
             "frequencies_per_s": len(idx) / total,
             "total_s": total, "max_rel_residual": max(r["rel_residual"] for r in rows),
-            "sampled_solution_error": max(errs), "per_frequency": rows}
+            "sampled_solution_error": max(errs), "receivers": int(rec.shape[0]),
+            "sampled_il_diff_vs_fp64_db": max(il_diff),
+            "field_ms_mean": float(np.mean([r["field_ms"] for r in rows])), "per_frequency": rows}
 
 
 def serving(fm, torch, args, mode, rate):

@@ -254,6 +254,39 @@ fmbem_status fmbem_incident_plane_wave(fmbem_plan plan, int32_t n_rhs, const dou
 fmbem_status fmbem_incident_point_source(fmbem_plan plan, int32_t n_rhs, const double* src,
                                          double amplitude, void* b, void* hip_stream);
 
+/* Incident pressure at arbitrary points (no normal-derivative term): kind
+ * FMBEM_INCIDENT_PLANE_WAVE, p_inc = A e^{ik d.x} (Sec. 4.1, eq. (planewave)), src =
+ * unit directions; kind FMBEM_INCIDENT_POINT_SOURCE, p_inc = A e^{ikR}/R (Sec. 4.2), src =
+ * source positions.  src host [n_rhs][3]; points host [n_points][3] absolute positions (m);
+ * p_inc device complex128 [n_rhs][n_points].  A point at a source gives inf.  Blocks until
+ * the result is written (the host arrays are read on the stream). */
+#define FMBEM_INCIDENT_PLANE_WAVE 0
+#define FMBEM_INCIDENT_POINT_SOURCE 1
+fmbem_status fmbem_incident_at_points(fmbem_plan plan, int32_t kind, int32_t n_rhs, const double* src,
+                                      double amplitude, int32_t n_points, const double* points,
+                                      void* p_inc, void* hip_stream);
+
+/* Pressure at points of the fluid from the solved surface pressure of the rigid
+ * scatterer: the CBIE (Sec. 2.1, eq. (cbie)) with c(x) = 1 off the surface and dp/dn = 0,
+ *   p(x_m) = p_inc(x_m) - sum_j x_j int_{Delta_j} dG/dn_y(x_m, y) dA(y),
+ * j over the elements of every cell, integrated with the plan's non-self Duffy rule
+ * (q x q points, q = 16 / 8 / 4 for |x_m - centroid_j| below 1 / 3 / above 3 longest
+ * edges of element j), in FP64.  x: device complex128 [n_rhs][n_cells][n_dof_cell] (the
+ * solution of fmbem_solve).  points: host [n_points][3], absolute positions in the fluid
+ * (not on the surface; a point on a quadrature point gives inf or NaN).  p_inc: device
+ * complex128 [n_rhs][n_points] or NULL (then p is the scattered pressure alone).  p:
+ * device complex128 [n_rhs][n_points]; p may equal p_inc, must not overlap x.  Allocates
+ * a stream-ordered partial-sum buffer of n_rhs * n_points * ceil(N / 1024) * 16 bytes.
+ * Blocks until p is written. */
+fmbem_status fmbem_field(fmbem_plan plan, int32_t n_rhs, const void* x, int32_t n_points,
+                         const double* points, const void* p_inc, void* p, void* hip_stream);
+
+/* Insertion loss over observation points (eq. (insertionloss)):
+ * il[r] = 20 log10( sum_m |p_inc[r][m]| / sum_m |p[r][m]| ).  p_inc, p: device complex128
+ * [n_rhs][n_points]; il: device double [n_rhs] (inf when sum |p| = 0).  Stream-ordered. */
+fmbem_status fmbem_insertion_loss(int32_t n_rhs, int32_t n_points, const void* p_inc, const void* p,
+                                  double* il, void* hip_stream);
+
 /* Per-stage device time of the operator applications made with this plan
  * (fmbem_matvec and the ones inside fmbem_solve), measured with HIP events
  * recorded on the call's stream around each selected stage.  stage_mask != 0

@@ -67,7 +67,7 @@ EXPORTS = ["fmbem_plan_create", "fmbem_plan_query", "fmbem_plan_destroy", "fmbem
            "fmbem_plan_profile_read", "fmbem_status_string", "fmbem_solve_batch", "fmbem_engine_create",
            "fmbem_engine_submit", "fmbem_engine_step", "fmbem_engine_poll", "fmbem_engine_stats",
            "fmbem_engine_destroy", "fmbem_solver_create", "fmbem_solver_run", "fmbem_solver_graph_stats",
-           "fmbem_solver_destroy"]
+           "fmbem_solver_destroy", "fmbem_incident_at_points", "fmbem_field", "fmbem_insertion_loss"]
 STAGES = tuple(f"{s}_{p}" for p in ("fp64", "fp32") for s in ("near", "reduce", "fft", "m2l", "ifft", "l2t"))
 
 _lib = None
@@ -102,6 +102,10 @@ def load():
                                       ct.POINTER(vp), ct.POINTER(vp), ct.POINTER(SolveInfo), vp]
     lib.fmbem_incident_plane_wave.argtypes = [vp, ct.c_int32, ct.POINTER(ct.c_double), ct.c_double, vp, vp]
     lib.fmbem_incident_point_source.argtypes = [vp, ct.c_int32, ct.POINTER(ct.c_double), ct.c_double, vp, vp]
+    dp = ct.POINTER(ct.c_double)
+    lib.fmbem_incident_at_points.argtypes = [vp, ct.c_int32, ct.c_int32, dp, ct.c_double, ct.c_int32, dp, vp, vp]
+    lib.fmbem_field.argtypes = [vp, ct.c_int32, vp, ct.c_int32, dp, vp, vp, vp]
+    lib.fmbem_insertion_loss.argtypes = [ct.c_int32, ct.c_int32, vp, vp, vp, vp]
     lib.fmbem_plan_profile.argtypes = [vp, ct.c_uint32, ct.c_int32]
     lib.fmbem_plan_profile_read.argtypes = [vp, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)]
     lib.fmbem_status_string.argtypes = [ct.c_int32]
@@ -435,3 +439,64 @@ class Plan:
                                                     float(amplitude), ct.c_void_p(out.data_ptr()),
                                                     _stream_ptr(stream)), "fmbem_incident_point_source")
         return out
+
+    def incident_at_points(self, kind, sources, points, amplitude=1.0, stream=None):
+        """Incident pressure at points (fmbem_incident_at_points); kind "plane_wave" (sources =
+        unit directions) or "point_source" (sources = positions).  Returns complex128 [R, M]."""
+        import torch
+        kinds = {"plane_wave": 0, "point_source": 1}
+        if kind not in kinds:
+            raise ValueError(f"kind must be one of {sorted(kinds)}")
+        src = np.ascontiguousarray(np.atleast_2d(sources), dtype=np.float64)
+        pts = np.ascontiguousarray(np.atleast_2d(points), dtype=np.float64)
+        if src.shape[1] != 3 or pts.shape[1] != 3:
+            raise ValueError("sources and points must be [.., 3]")
+        out = torch.empty((src.shape[0], pts.shape[0]), dtype=torch.complex128, device="cuda")
+        dp = ct.POINTER(ct.c_double)
+        check(self._lib.fmbem_incident_at_points(self._h, kinds[kind], src.shape[0], src.ctypes.data_as(dp),
+                                                 float(amplitude), pts.shape[0], pts.ctypes.data_as(dp),
+                                                 ct.c_void_p(out.data_ptr()), _stream_ptr(stream)),
+              "fmbem_incident_at_points")
+        return out
+
+    def field(self, x, points, p_inc=None, stream=None):
+        """Pressure at points of the fluid from the surface pressure x ([R, C, n] or [R, N],
+        complex128 on the device): fmbem_field.  p_inc ([R, M] complex128 on the device) is
+        added when given.  Returns complex128 [R, M]."""
+        import torch
+        if x.dtype != torch.complex128 or not x.is_cuda or not x.is_contiguous():
+            raise ValueError("x must be a contiguous complex128 device tensor")
+        R = x.shape[0] if x.dim() > 1 else 1
+        if x.numel() != R * self.n_cells * self.n:
+            raise ValueError("x must hold [R][n_cells][n] values")
+        pts = np.ascontiguousarray(np.atleast_2d(points), dtype=np.float64)
+        if pts.shape[1] != 3:
+            raise ValueError("points must be [M, 3]")
+        M = pts.shape[0]
+        if p_inc is not None:
+            if p_inc.dtype != torch.complex128 or not p_inc.is_cuda or not p_inc.is_contiguous() \
+                    or p_inc.numel() != R * M:
+                raise ValueError("p_inc must be a contiguous complex128 device tensor of R x M values")
+        out = torch.empty((R, M), dtype=torch.complex128, device="cuda")
+        check(self._lib.fmbem_field(self._h, R, ct.c_void_p(x.data_ptr()), M,
+                                    pts.ctypes.data_as(ct.POINTER(ct.c_double)),
+                                    ct.c_void_p(p_inc.data_ptr() if p_inc is not None else 0),
+                                    ct.c_void_p(out.data_ptr()), _stream_ptr(stream)), "fmbem_field")
+        return out
+
+
+def insertion_loss(p_inc, p, stream=None):
+    """IL in dB per right-hand side over the observation points (fmbem_insertion_loss);
+    p_inc, p: complex128 device tensors [R, M].  Returns float64 [R] on the device."""
+    import torch
+    for t in (p_inc, p):
+        if t.dtype != torch.complex128 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("p_inc and p must be contiguous complex128 device tensors")
+    if p_inc.shape != p.shape or p.dim() not in (1, 2):
+        raise ValueError("p_inc and p must have the same shape [R, M]")
+    R, M = (1, p.shape[0]) if p.dim() == 1 else p.shape
+    il = torch.empty(R, dtype=torch.float64, device="cuda")
+    lib = load()
+    check(lib.fmbem_insertion_loss(R, M, ct.c_void_p(p_inc.data_ptr()), ct.c_void_p(p.data_ptr()),
+                                   ct.c_void_p(il.data_ptr()), _stream_ptr(stream)), "fmbem_insertion_loss")
+    return il

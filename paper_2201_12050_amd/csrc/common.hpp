@@ -49,6 +49,13 @@ __host__ __device__ inline void cfma(cplx<T>& a, cplx<T> b, cplx<T> c) {
 constexpr int kMaxNear = 343;   // (2*3+1)^3 near offsets at near radius 3
 constexpr int kDftGemmMaxOut = 128;  // widest output count of a DFT pass as a GEMM (one tile width)
 
+// Gauss-Legendre rules on [0, 1] (nodes t, weights w) for q = 4, 8, 16 points,
+// stored at offsets 0, 4 and 12 (28 entries)
+struct QuadTab {
+  double t[28];
+  double w[28];
+};
+
 struct Plan {
   int device = 0;
   int n = 0;                 // triangles (DOFs) per cell
@@ -67,6 +74,7 @@ struct Plan {
   int n_near = 0, n_far = 0;
   std::vector<int> near_off; // [n_near][3]
   // device arrays (owned)
+  QuadTab quad{};            // element quadrature rules (see QuadTab)
   double* geom = nullptr;    // [n][18]: a(3) b(3) c(3) centroid(3) normal(3) longest, area, pad
   int* d_near = nullptr;     // [n_near][3]
   void* S[2] = {nullptr, nullptr};    // [n_near][n][n] complex, row-major
@@ -104,6 +112,12 @@ struct Plan {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::unique_ptr<std::mutex> aux_mu{new std::mutex};
 };
+
+inline fmbem_status to_status(hipError_t e) {
+  if (e == hipSuccess) return FMBEM_OK;
+  if (e == hipErrorOutOfMemory) return FMBEM_ERR_OUT_OF_MEMORY;
+  return FMBEM_ERR_DEVICE;
+}
 
 // record the start / end of a stage when that stage is being profiled (returns the start event)
 hipEvent_t prof_begin(const Plan& P, int stage, hipStream_t s);

@@ -112,6 +112,10 @@ def test_other_entry_points_reject_null_plan():
     assert lib.fmbem_solver_destroy(None) == 1
     assert lib.fmbem_status_string(7) == b"request exceeds the engine's memory budget"
     assert lib.fmbem_incident_plane_wave(None, 1, None, 1.0, None, None) == 1
+    assert lib.fmbem_incident_at_points(None, 0, 1, None, 1.0, 1, None, None, None) == 1
+    assert lib.fmbem_field(None, 1, None, 1, None, None, None, None) == 1
+    assert lib.fmbem_insertion_loss(1, 1, None, None, None, None) == 1
+    assert lib.fmbem_insertion_loss(0, 1, 8, 8, 8, None) == 1
     assert lib.fmbem_status_string(5) == b"not converged"
     assert lib.fmbem_status_string(99) == b"unknown status"
 

@@ -125,7 +125,18 @@ def config_barrier_r4b(freq_index: int = 95) -> Workload:
     lat = Lattice((40, 2, 8), (0.2, 0.2, 0.25))
     src = np.array([[39 * 0.2 / 2.0, -2.0, 7 * 0.25 / 2.0]])
     order = 10 if f <= 1000.0 else 14
-    return Workload(f"barrier_40x2x8_{f:.1f}Hz", v, t, lat, f, order, "bm", point_sources=src)
+    return Workload(f"barrier_40x2x8_{f:.1f}Hz", v, t, lat, f, order, "bm", point_sources=src,
+                    extra={"receivers": barrier_receivers()})
+
+
+def barrier_receivers(n_along: int = 8, n_up: int = 8) -> np.ndarray:
+    """Observation points of the barrier: a vertical n_along x n_up grid 2 m behind the
+    back row (y = 0.2 + 2), spanning +-2 m along the barrier about its middle (x = 3.9)
+    and heights 0.25 - 1.75 m above the cylinders' base (z = -0.125); [n_along*n_up, 3]."""
+    xs = 39 * 0.2 / 2.0 + np.linspace(-2.0, 2.0, n_along)
+    zs = -0.125 + np.linspace(0.25, 1.75, n_up)
+    X, Z = np.meshgrid(xs, zs, indexing="ij")
+    return np.stack([X.ravel(), np.full(X.size, 0.2 + 2.0), Z.ravel()], axis=1)
 
 
 def serving_stream(n_requests: int, rate: float = 20.0, seed: int = 2201120505):
