@@ -85,6 +85,8 @@ typedef struct {
 #define FMBEM_DFT_AXES 1    /* one direct pruned DFT pass per axis */
 #define FMBEM_DFT_FUSED 2   /* both axes of an N3 = 1 grid in one launch through LDS */
 #define FMBEM_DFT_GEMM 3    /* axis passes as MFMA GEMMs with the DFT matrices (N_a <= 128) */
+#define FMBEM_DFT_FUSED_MFMA 4 /* both axes of an N3 = 1 grid in one launch, as MFMA products with the
+                                  DFT matrices, the intermediate in LDS (1 < N_a <= 128) */
 
 typedef struct {
   int32_t n_dof_cell;         /* n (triangles per cell) */

@@ -39,7 +39,7 @@ class PlanDesc(ct.Structure):
                 ("precisions", ct.c_uint32), ("dft_schedule", ct.c_int32)]
 
 
-DFT_SCHEDULE = {"auto": 0, "axes": 1, "fused": 2, "gemm": 3}
+DFT_SCHEDULE = {"auto": 0, "axes": 1, "fused": 2, "gemm": 3, "mfma": 4}
 
 
 class PlanInfo(ct.Structure):

@@ -294,6 +294,8 @@ hipError_t grid_dft_launch(void* buf, int channels, const int M[3], const int N[
 // pass has at most kDftGemmMaxOut outputs and int-sized strides)
 template <typename T>
 bool dft_gemm_applies(int channels, const int M[3], const int N[3], bool pruned, const void* const* fmat);
+template <typename T>
+bool dft_mfma_applies(int channels, const int M[3], const int N[3], bool pruned, const void* const* fmat);
 // whether the fused two-axis kernel applies (N3 = 1, N1 > 1, pruned, one channel fits its LDS)
 template <typename T>
 bool dft_fused_applies(int channels, const int M[3], const int N[3], bool pruned);

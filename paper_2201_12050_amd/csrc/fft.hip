@@ -15,10 +15,17 @@
 // the inputs.  Small grids of at most two transformed axes (N3 = 1) with few
 // channels take a fused form instead: one workgroup per slice of channels does
 // both axis passes through LDS in one launch (the separate passes are bound by
-// launch and memory latency there, not by bandwidth).
+// launch and memory latency there, not by bandwidth).  Two more schedules use
+// the matrix cores with the plan's DFT matrices: each axis pass as a GEMM
+// (dft_gemm_launch), or both axes of an N3 = 1 grid in one launch with the
+// slab of a 16-channel slice in LDS (dft2m_kernel, for many channels).
 #include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <type_traits>
 
 #include "common.hpp"
+#include "mfma.hpp"
 
 namespace fmbem {
 
@@ -31,6 +38,9 @@ template <typename T> struct DftTile { static constexpr int ch = sizeof(T) == 8 
 // where they apply (faster than the direct passes from about 1000 channels), else the direct
 // passes
 constexpr int kDft2MaxChannels = 256;
+// ... and the fused matrix-core kernel from this many channels (measured on the 8 x 8, 12 x 20 and
+// 32 x 4 lattices: at 968 channels the GEMM passes are faster, at 7744 the fused kernel)
+constexpr int kDftmMinChannels = 4096;
 
 template <typename T>
 __global__ __launch_bounds__(256) void dft_axis_kernel(cplx<T>* __restrict__ buf, int channels, int N, int Min,
@@ -230,6 +240,238 @@ __global__ __launch_bounds__(256) void dft2_kernel(cplx<T>* __restrict__ buf, in
   }
 }
 
+// Fused two-axis DFT on the matrix cores, for N3 = 1 grids with many channels and
+// 1 < N_a <= kDftGemmMaxOut.  One workgroup of four waves per slice of kDftmCh channels (one tile
+// column).  The slice's inputs are staged into LDS first with every load in flight at once (the
+// D factor of the inverse removed on the way), then both axis passes run from LDS: each
+// multiplies the lines of the slice by that axis's DFT matrix ([outputs][inputs]: forward
+// [N_a][M_a], inverse [M_a][N_a]) on 16x16x4 tiles, a complex product as four real ones
+// accumulated in the tile precision.  The first pass writes its outputs over its own inputs
+// (a line only touches its own row or column of the slab), the second writes to the grid:
+//   forward: X (M1 x M0) -> axis 0 -> T (M1 x N0) -> axis 1 -> all N1 x N0 bins, D applied;
+//   inverse: all N1 x N0 bins -> axis 1 -> T (M1 x N0) -> axis 0 -> the first M1 x M0 entries.
+// The slab has row stride N0: [M1][N0] forward, [N1][N0] inverse.
+constexpr int kDftmCh = 16;
+constexpr int kDftmGroup = 4;
+
+// One sweep over the inputs of line L for output tiles mb0 .. mb0 + MBT - 1:
+//   out(L, o, c) = sum_j A[o][j] in(L, j, c),  o in those tiles, o < nout.
+// The k steps go four at a time, then the last one to three together (the matrix image is
+// zero-padded to whole k steps and in() returns 0 past the last input): all fragments of a group
+// are read first, then its MFMAs, with no branch inside a group, so the reads are issued together
+// and the accumulators of consecutive MFMAs differ.
+template <typename T, int MBT, typename In, typename Out>
+__device__ inline void dftm_sweep(const cplx<T>* __restrict__ A, int lda, int mb0, int nout, int KS, int L, In in,
+                                  Out out) {
+  using MF = nmf<T>;
+  using acc_t = typename MF::acc;
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  acc_t re[MBT], im[MBT];
+#pragma unroll
+  for (int q = 0; q < MBT; ++q) {
+    re[q] = acc_t{0, 0, 0, 0};
+    im[q] = acc_t{0, 0, 0, 0};
+  }
+  const cplx<T>* Ar = A + (16 * mb0 + c) * lda + g;
+  auto group = [&](int k0, auto nsteps) {
+    constexpr int NS = decltype(nsteps)::value;
+    cplx<T> x[NS], a[NS][MBT];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      x[u] = in(L, 4 * (k0 + u) + g, c);
+#pragma unroll
+      for (int q = 0; q < MBT; ++q) a[u][q] = Ar[16 * q * lda + 4 * (k0 + u)];
+    }
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+#pragma unroll
+      for (int q = 0; q < MBT; ++q) {
+        re[q] = MF::step(a[u][q].x, x[u].x, re[q]);
+        im[q] = MF::step(a[u][q].x, x[u].y, im[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < MBT; ++q) {
+        re[q] = MF::step(-a[u][q].y, x[u].y, re[q]);
+        im[q] = MF::step(a[u][q].y, x[u].x, im[q]);
+      }
+    }
+  };
+  int k0 = 0;
+  for (; k0 + 4 <= KS; k0 += 4) group(k0, std::integral_constant<int, 4>{});
+  // the last one to three k steps (wave-uniform)
+  const int tail = KS - k0;
+  if (tail == 3)
+    group(k0, std::integral_constant<int, 3>{});
+  else if (tail == 2)
+    group(k0, std::integral_constant<int, 2>{});
+  else if (tail == 1)
+    group(k0, std::integral_constant<int, 1>{});
+  // every input of the line has been read: the outputs may overwrite them
+#pragma unroll
+  for (int q = 0; q < MBT; ++q) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int o = 16 * (mb0 + q) + MF::row(g, r);
+      if (o < nout) out(L, o, c, mk<T>(re[q][r], im[q][r]));
+    }
+  }
+}
+
+// out(L, o, c) = sum_{j < nin} A[o][j] in(L, j, c) for o < nout and every line L = w + 4 i of
+// wave w; the output tiles of a line in sweeps of at most kDftmGroup tiles.
+template <typename T, typename In, typename Out>
+__device__ inline void dftm_pass(const cplx<T>* __restrict__ A, int lda, int nout, int nin, int lines, In in,
+                                 Out out) {
+  // the wave index is uniform over the wave: made scalar so that the loops branch on scalars
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int MB = (nout + 15) >> 4, KS = (nin + 3) >> 2;
+  for (int L = w; L < lines; L += 4) {
+    for (int mb0 = 0; mb0 < MB;) {
+      const int rem = MB - mb0;
+      if (rem >= 4) {
+        dftm_sweep<T, 4>(A, lda, mb0, nout, KS, L, in, out);
+        mb0 += 4;
+      } else if (rem == 3) {
+        dftm_sweep<T, 3>(A, lda, mb0, nout, KS, L, in, out);
+        mb0 += 3;
+      } else if (rem == 2) {
+        dftm_sweep<T, 2>(A, lda, mb0, nout, KS, L, in, out);
+        mb0 += 2;
+      } else {
+        dftm_sweep<T, 1>(A, lda, mb0, nout, KS, L, in, out);
+        mb0 += 1;
+      }
+    }
+  }
+}
+
+// padded LDS image of an [nout][nin] matrix: 16-row tiles, columns padded to whole k steps (4)
+// plus one, the odd stride putting the 16 rows of a fragment in distinct banks
+__host__ __device__ inline int dftm_rows(int nout) { return 16 * ((nout + 15) / 16); }
+__host__ __device__ inline int dftm_lda(int nin) { return 4 * ((nin + 3) / 4) + 1; }
+
+// FP32: at most 128 registers (two waves per SIMD); FP64 needs more for its register sets
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1))) void dft2m_kernel(
+    cplx<T>* __restrict__ buf, int channels, int N0, int N1, int M0, int M1, int inverse, int flip_p,
+    const cplx<T>* __restrict__ P1, const cplx<T>* __restrict__ P2) {
+  extern __shared__ unsigned char smem_raw[];
+  // pass 1 transforms axis 0 (forward) or axis 1 (inverse); pass 2 the other axis
+  const int out1 = inverse ? M1 : N0, in1 = inverse ? N1 : M0;
+  const int out2 = inverse ? M0 : N1, in2 = inverse ? N0 : M1;
+  const int lda1 = dftm_lda(in1), lda2 = dftm_lda(in2);
+  cplx<T>* A1 = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* A2 = A1 + (size_t)dftm_rows(out1) * lda1;
+  cplx<T>* S = A2 + (size_t)dftm_rows(out2) * lda2;  // slab [rows][N0][kDftmCh]
+  const int c0 = blockIdx.x * kDftmCh;
+  const int c = threadIdx.x & 15;  // the channel of this thread in every staging step
+  const int ch = c0 + c;
+  const bool valid = ch < channels;
+  const bool odd = valid && flip_p > 0 && odd_degree(ch, flip_p);
+  auto sl = [&](int r, int k0, int cc) -> cplx<T>& { return S[((size_t)r * N0 + k0) * kDftmCh + cc]; };
+  // stage the slab: forward X[i1][i0] (i1 < M1, i0 < M0); inverse Y[k1][k0], D removed.  With
+  // 16-byte aligned channel rows (FP64 always, FP32 for an even channel count) every load takes
+  // 16 bytes, two FP32 channels per thread; sixteen loads per thread are issued before their
+  // LDS stores, so that enough bytes are in flight per CU to cover the memory latency.
+  {
+    const int rows = inverse ? N1 : M1, cols = inverse ? N0 : M0;
+    constexpr int CPL = 16 / sizeof(cplx<T>);  // channels per 16-byte load
+    if ((channels % CPL) == 0) {
+      using V = typename Vec16<T>::type;
+      constexpr int TPR = kDftmCh / CPL;       // threads per staged row of the slice
+      const int cl = (threadIdx.x % TPR) * CPL;  // first channel of this thread in the slice
+      const bool ok = c0 + cl < channels;        // whole load in range (channels % CPL == 0)
+      bool odd2[CPL];
+#pragma unroll
+      for (int h = 0; h < CPL; ++h) odd2[h] = ok && flip_p > 0 && odd_degree(c0 + cl + h, flip_p);
+      const int total = rows * cols * TPR;
+#pragma unroll 16
+      for (int e = threadIdx.x; e < total; e += 256) {
+        const int rc = e / TPR, col = rc % cols, row = rc / cols;
+        V v{};
+        if (ok) v = *reinterpret_cast<const V*>(buf + ((size_t)row * N0 + col) * channels + c0 + cl);
+        cplx<T> u[CPL];
+        memcpy(u, &v, sizeof(V));
+        const bool fl = inverse && flipped2(col, row, N0, N1);
+#pragma unroll
+        for (int h = 0; h < CPL; ++h) {
+          if (fl && odd2[h]) u[h] = mk<T>(-u[h].x, -u[h].y);
+          sl(row, col, cl + h) = u[h];
+        }
+      }
+    } else {
+#pragma unroll 8
+      for (int e = threadIdx.x; e < rows * cols * kDftmCh; e += 256) {
+        const int rc = e >> 4, col = rc % cols, row = rc / cols;
+        cplx<T> v = valid ? buf[((size_t)row * N0 + col) * channels + ch] : mk<T>(0, 0);
+        if (inverse && odd && flipped2(col, row, N0, N1)) v = mk<T>(-v.x, -v.y);
+        sl(row, col, c) = v;
+      }
+    }
+  }
+#pragma unroll 4
+  for (int e = threadIdx.x; e < dftm_rows(out1) * lda1; e += 256) {
+    const int r = e / lda1, k = e - r * lda1;
+    A1[e] = (r < out1 && k < in1) ? P1[r * in1 + k] : mk<T>(0, 0);
+  }
+#pragma unroll 4
+  for (int e = threadIdx.x; e < dftm_rows(out2) * lda2; e += 256) {
+    const int r = e / lda2, k = e - r * lda2;
+    A2[e] = (r < out2 && k < in2) ? P2[r * in2 + k] : mk<T>(0, 0);
+  }
+  __syncthreads();
+  if (!inverse) {
+    // axis 0 over the rows i1 < M1, in place: T[i1][k0] = sum_{i0 < M0} F0[k0][i0] X[i1][i0]
+    dftm_pass<T>(
+        A1, lda1, N0, M0, M1, [&](int L, int j, int cc) { return j < M0 ? sl(L, j, cc) : mk<T>(0, 0); },
+        [&](int L, int o, int cc, cplx<T> v) { sl(L, o, cc) = v; });
+    __syncthreads();
+    // axis 1 over the columns k0 < N0: Y[k1][k0] = sum_{i1 < M1} F1[k1][i1] T[i1][k0], D on flipped bins
+    dftm_pass<T>(
+        A2, lda2, N1, M1, N0, [&](int L, int j, int cc) { return j < M1 ? sl(j, L, cc) : mk<T>(0, 0); },
+        [&](int L, int o, int, cplx<T> v) {
+          if (!valid) return;
+          if (odd && flipped2(L, o, N0, N1)) v = mk<T>(-v.x, -v.y);
+          buf[((size_t)o * N0 + L) * channels + ch] = v;
+        });
+  } else {
+    // axis 1 over the columns k0 < N0, in place: T[i1][k0] = sum_{k1 < N1} G1[i1][k1] Y[k1][k0]
+    dftm_pass<T>(
+        A1, lda1, M1, N1, N0, [&](int L, int j, int cc) { return j < N1 ? sl(j, L, cc) : mk<T>(0, 0); },
+        [&](int L, int o, int cc, cplx<T> v) { sl(o, L, cc) = v; });
+    __syncthreads();
+    // axis 0 over the rows i1 < M1: X[i1][i0] = sum_{k0 < N0} G0[i0][k0] T[i1][k0], i0 < M0
+    dftm_pass<T>(
+        A2, lda2, M0, N0, M1, [&](int L, int j, int cc) { return j < N0 ? sl(L, j, cc) : mk<T>(0, 0); },
+        [&](int L, int o, int, cplx<T> v) {
+          if (valid) buf[((size_t)L * N0 + o) * channels + ch] = v;
+        });
+  }
+}
+
+template <typename T>
+static size_t dftm_lds(const int M[3], const int N[3], bool inverse) {
+  const int out1 = inverse ? M[1] : N[0], in1 = inverse ? N[1] : M[0];
+  const int out2 = inverse ? M[0] : N[1], in2 = inverse ? N[0] : M[1];
+  const size_t slab = (size_t)(inverse ? N[1] : M[1]) * N[0] * kDftmCh;
+  return ((size_t)dftm_rows(out1) * dftm_lda(in1) + (size_t)dftm_rows(out2) * dftm_lda(in2) + slab) *
+         sizeof(cplx<T>);
+}
+
+// LDS limit of one workgroup
+constexpr size_t kLdsMax = 160 * 1024;
+
+template <typename T>
+bool dft_mfma_applies(int channels, const int M[3], const int N[3], bool pruned, const void* const* fmat) {
+  if (!pruned || !fmat || channels < 1 || N[2] != 1 || M[2] != 1) return false;
+  for (int a = 0; a < 2; ++a)
+    if (N[a] <= 1 || N[a] > kDftGemmMaxOut || !fmat[a] || !fmat[3 + a]) return false;
+  if ((long long)N[0] * N[1] * channels > INT32_MAX) return false;
+  // the first pass works in place, so a line's outputs must come from one sweep over its inputs
+  if (N[0] > 16 * kDftmGroup || M[1] > 16 * kDftmGroup) return false;
+  return std::max(dftm_lds<T>(M, N, false), dftm_lds<T>(M, N, true)) <= kLdsMax;
+}
+
 // LDS budget of the fused form per workgroup
 constexpr size_t kDft2Lds = 64 * 1024;
 
@@ -261,7 +503,27 @@ template <typename T>
 hipError_t grid_dft_launch(void* bufv, int channels, const int M[3], const int N[3], bool inverse, bool pruned,
                            hipStream_t s, int flip_p, int schedule, const void* const* fmat) {
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(bufv);
-  if (schedule < 0) schedule = channels <= kDft2MaxChannels ? 1 : 2;
+  if (schedule < 0) schedule = channels <= kDft2MaxChannels ? 1 : (channels >= kDftmMinChannels ? 3 : 2);
+  if (schedule == 3 && !dft_mfma_applies<T>(channels, M, N, pruned, fmat)) schedule = 2;
+  if (schedule == 3) {
+    const size_t lds = dftm_lds<T>(M, N, inverse);
+    // dynamic LDS beyond 64 KB must be allowed per kernel
+    static std::once_flag once;
+    static hipError_t attr = hipSuccess;
+    std::call_once(once, [] {
+      attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&dft2m_kernel<T>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
+    });
+    if (attr != hipSuccess) return attr;
+    const int off = inverse ? 3 : 0;
+    // pass 1 is axis 0 forward, axis 1 inverse
+    const void* p1 = fmat[off + (inverse ? 1 : 0)];
+    const void* p2 = fmat[off + (inverse ? 0 : 1)];
+    hipLaunchKernelGGL(dft2m_kernel<T>, dim3((unsigned)((channels + kDftmCh - 1) / kDftmCh)), dim3(256), lds, s, buf,
+                       channels, N[0], N[1], M[0], M[1], inverse ? 1 : 0, flip_p,
+                       reinterpret_cast<const cplx<T>*>(p1), reinterpret_cast<const cplx<T>*>(p2));
+    return hipGetLastError();
+  }
   const bool gemm = schedule == 2 && dft_gemm_applies<T>(channels, M, N, pruned, fmat);
   if (schedule == 1 && dft_fused_applies<T>(channels, M, N, pruned)) {
     // channels per workgroup: enough workgroups to cover the CUs, within the LDS budget
@@ -329,6 +591,8 @@ template hipError_t grid_dft_launch<float>(void*, int, const int*, const int*, b
 template bool dft_gemm_applies<double>(int, const int*, const int*, bool, const void* const*);
 template bool dft_gemm_applies<float>(int, const int*, const int*, bool, const void* const*);
 template bool dft_fused_applies<double>(int, const int*, const int*, bool);
+template bool dft_mfma_applies<double>(int, const int*, const int*, bool, const void* const*);
+template bool dft_mfma_applies<float>(int, const int*, const int*, bool, const void* const*);
 template bool dft_fused_applies<float>(int, const int*, const int*, bool);
 
 }  // namespace fmbem

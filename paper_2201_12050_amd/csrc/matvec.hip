@@ -130,22 +130,31 @@ int cached_shape(int kind, const std::vector<NearJob>& jobs) {
   return it == g_tuned.end() ? -1 : it->second;
 }
 
-// Autotuner of the DFT schedule (separate axis passes, the fused two-axis kernel, or axis passes
-// as MFMA GEMMs with the plan's DFT matrices) of a plan's grid with R right-hand sides: on the
-// first application of a signature (precision, lattice, transform lengths, channels) where more
-// than one schedule applies, each runs a forward + inverse transform pair on the workspace grid
-// (before the S2M product writes it) twice, timed with HIP events; the fastest is cached for
-// the process.  Otherwise, or while the stream is being captured, a schedule measured earlier or
-// the built-in rule (-1).
+// Autotuner of the DFT schedule (separate axis passes, the fused two-axis kernel, axis passes
+// as MFMA GEMMs with the plan's DFT matrices, or both axes fused on the matrix cores) of a plan's
+// grid with R right-hand sides, chosen for the forward and the inverse transform separately: on
+// the first application of a signature (precision, lattice, transform lengths, channels) where
+// more than one schedule applies, each runs a forward and an inverse transform on the workspace
+// grid (before the S2M product writes it) twice, timed with HIP events; the fastest of each
+// direction is cached for the process.  Otherwise, or while the stream is being captured, a
+// choice measured earlier or the built-in rule.  Returns forward | inverse << 4, or -1 for the
+// built-in rule in both directions.
+static inline int sched_fwd(int d) { return d < 0 ? -1 : (d & 15); }
+static inline int sched_inv(int d) { return d < 0 ? -1 : (d >> 4); }
+
 template <typename T>
 static int dft_schedule(const Plan& P, int R, void* ws, hipStream_t s, bool tune) {
   const int prec = sizeof(T) == 8 ? 0 : 1;
   const int ch = R * P.p;
   if (P.n_far == 0) return 0;
-  const bool ok[3] = {true, dft_fused_applies<T>(ch, P.grid, P.fft, true),
-                      dft_gemm_applies<T>(ch, P.grid, P.fft, true, P.dftF[prec])};
-  if (!ok[1] && !ok[2]) return 0;
-  if (P.dft_forced >= 0) return ok[P.dft_forced] ? P.dft_forced : 0;
+  const bool ok[4] = {true, dft_fused_applies<T>(ch, P.grid, P.fft, true),
+                      dft_gemm_applies<T>(ch, P.grid, P.fft, true, P.dftF[prec]),
+                      dft_mfma_applies<T>(ch, P.grid, P.fft, true, P.dftF[prec])};
+  if (!ok[1] && !ok[2] && !ok[3]) return 0;
+  if (P.dft_forced >= 0) {
+    const int f = ok[P.dft_forced] ? P.dft_forced : 0;
+    return f | (f << 4);
+  }
   const std::vector<long long> key{3, (long long)sizeof(T), P.grid[0], P.grid[1], P.grid[2],
                                    P.fft[0], P.fft[1], P.fft[2], ch};
   {
@@ -154,30 +163,37 @@ static int dft_schedule(const Plan& P, int R, void* ws, hipStream_t s, bool tune
     if (it != g_tuned.end()) return it->second;
   }
   if (!tune || capturing(s)) return -1;
-  hipEvent_t a = nullptr, b = nullptr;
-  float t[3] = {1e30f, 1e30f, 1e30f};
-  if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess) {
+  hipEvent_t a = nullptr, b = nullptr, c = nullptr;
+  float t[2][4] = {{1e30f, 1e30f, 1e30f, 1e30f}, {1e30f, 1e30f, 1e30f, 1e30f}};
+  if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess && hipEventCreate(&c) == hipSuccess) {
     for (int sweep = 0; sweep < 2; ++sweep)
-      for (int v = 0; v < 3; ++v) {
+      for (int v = 0; v < 4; ++v) {
         if (!ok[v]) continue;
         if (grid_dft_launch<T>(ws, ch, P.grid, P.fft, false, true, s, P.p, v, P.dftF[prec]) != hipSuccess) continue;
         hipEventRecord(a, s);
         grid_dft_launch<T>(ws, ch, P.grid, P.fft, false, true, s, P.p, v, P.dftF[prec]);
-        grid_dft_launch<T>(ws, ch, P.grid, P.fft, true, true, s, P.p, v, P.dftF[prec]);
         hipEventRecord(b, s);
-        float ms = 0.f;
-        if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) continue;
-        t[v] = std::min(t[v], ms);
+        grid_dft_launch<T>(ws, ch, P.grid, P.fft, true, true, s, P.p, v, P.dftF[prec]);
+        hipEventRecord(c, s);
+        float ms0 = 0.f, ms1 = 0.f;
+        if (hipEventSynchronize(c) != hipSuccess || hipEventElapsedTime(&ms0, a, b) != hipSuccess ||
+            hipEventElapsedTime(&ms1, b, c) != hipSuccess)
+          continue;
+        t[0][v] = std::min(t[0][v], ms0);
+        t[1][v] = std::min(t[1][v], ms1);
       }
   }
   if (a) hipEventDestroy(a);
   if (b) hipEventDestroy(b);
-  int best = 0;
-  for (int v = 1; v < 3; ++v)
-    if (t[v] < t[best]) best = v;
+  if (c) hipEventDestroy(c);
+  int best[2] = {0, 0};
+  for (int d = 0; d < 2; ++d)
+    for (int v = 1; v < 4; ++v)
+      if (t[d][v] < t[d][best[d]]) best[d] = v;
+  const int code = best[0] | (best[1] << 4);
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tuned[key] = best;
-  return best;
+  g_tuned[key] = code;
+  return code;
 }
 
 // workspace layout: [padded grid B x R x p][second grid B x R x p][near partials n_near x R x C x n]
@@ -259,14 +275,14 @@ static hipError_t matvec_overlap(const Plan& P, int R, const void* x, void* y, v
     const int shape = tune ? tuned_shape<T>(0, s2m, P.aux) : cached_shape<T>(0, s2m);
     if ((e = near_launch<T>(s2m, P.aux, shape, 0))) return e;
   }
-  if ((e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, false, true, P.aux, p, dsched, P.dftF[prec]))) return e;
+  if ((e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, false, true, P.aux, p, sched_fwd(dsched), P.dftF[prec]))) return e;
   prof_end(P, 2 + 6 * prec, ev, P.aux);
   ev = prof_begin(P, 3 + 6 * prec, P.aux);
   void* lhat = nullptr;
   if ((e = m2l_apply<T>(P, R, ws, P.aux, &lhat, tune))) return e;
   prof_end(P, 3 + 6 * prec, ev, P.aux);
   ev = prof_begin(P, 4 + 6 * prec, P.aux);
-  if ((e = grid_dft_launch<T>(lhat, R * p, P.grid, P.fft, true, true, P.aux, p, dsched, P.dftF[prec]))) return e;
+  if ((e = grid_dft_launch<T>(lhat, R * p, P.grid, P.fft, true, true, P.aux, p, sched_inv(dsched), P.dftF[prec]))) return e;
   prof_end(P, 4 + 6 * prec, ev, P.aux);
   if ((e = hipEventRecord(P.ev_join, P.aux))) return e;
   // [0] near field on the caller's stream
@@ -320,7 +336,7 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
   }
   // [2]-[4] DFT, M2L, inverse DFT
   ev = prof_begin(P, 2 + 6 * prec, s);
-  hipError_t e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, false, true, s, p, dsched, P.dftF[prec]);
+  hipError_t e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, false, true, s, p, sched_fwd(dsched), P.dftF[prec]);
   if (e != hipSuccess) return e;
   prof_end(P, 2 + 6 * prec, ev, s);
   ev = prof_begin(P, 3 + 6 * prec, s);
@@ -329,7 +345,7 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
   if (e != hipSuccess) return e;
   prof_end(P, 3 + 6 * prec, ev, s);
   ev = prof_begin(P, 4 + 6 * prec, s);
-  e = grid_dft_launch<T>(lhat, R * p, P.grid, P.fft, true, true, s, p, dsched, P.dftF[prec]);
+  e = grid_dft_launch<T>(lhat, R * p, P.grid, P.fft, true, true, s, p, sched_inv(dsched), P.dftF[prec]);
   if (e != hipSuccess) return e;
   prof_end(P, 4 + 6 * prec, ev, s);
   // [5] L2T with the fixed-order sum of the near partials
@@ -367,10 +383,10 @@ static hipError_t matvec_group_t(const std::vector<GroupApply>& g, hipStream_t s
       continue;
     }
     void* lhat = nullptr;
-    e = grid_dft_launch<T>(a.ws, a.R * P.p, P.grid, P.fft, false, true, s, P.p, dsched[q], P.dftF[prec]);
+    e = grid_dft_launch<T>(a.ws, a.R * P.p, P.grid, P.fft, false, true, s, P.p, sched_fwd(dsched[q]), P.dftF[prec]);
     if (e != hipSuccess) return e;
     if ((e = m2l_apply<T>(P, a.R, a.ws, s, &lhat, tune)) != hipSuccess) return e;
-    e = grid_dft_launch<T>(lhat, a.R * P.p, P.grid, P.fft, true, true, s, P.p, dsched[q], P.dftF[prec]);
+    e = grid_dft_launch<T>(lhat, a.R * P.p, P.grid, P.fft, true, true, s, P.p, sched_inv(dsched[q]), P.dftF[prec]);
     if (e != hipSuccess) return e;
     l2t.push_back(l2t_job<T>(P, a.R, a.ws, lhat, a.y, a.y64));
   }

@@ -746,7 +746,7 @@ extern "C" fmbem_status fmbem_plan_create(const fmbem_cell_mesh* mesh, const fmb
   if (desc->order < 0 || desc->order > 20) return FMBEM_ERR_INVALID_ARG;
   if (desc->formulation != FMBEM_BURTON_MILLER && desc->formulation != FMBEM_CBIE) return FMBEM_ERR_INVALID_ARG;
   if (desc->precisions & ~3u) return FMBEM_ERR_INVALID_ARG;
-  if (desc->dft_schedule < FMBEM_DFT_AUTO || desc->dft_schedule > FMBEM_DFT_GEMM) return FMBEM_ERR_INVALID_ARG;
+  if (desc->dft_schedule < FMBEM_DFT_AUTO || desc->dft_schedule > FMBEM_DFT_FUSED_MFMA) return FMBEM_ERR_INVALID_ARG;
   const int n = mesh->n_triangles;
   // geometry on the host: a, b, c, centroid, unit normal, longest edge, area
   std::vector<double> geo((size_t)n * 18, 0.0);

@@ -86,7 +86,7 @@ def test_plan_create_rejects_invalid_arguments(case):
     elif case == "radius":
         desc = _desc(near_radius=(4, 1, 1))
     elif case == "dft_schedule":
-        desc = _desc(dft_schedule=4)
+        desc = _desc(dft_schedule=5)
     mesh, keep = _mesh(v, t)
     assert lib.fmbem_plan_create(ct.byref(mesh), ct.byref(desc), None, ct.byref(out)) == 1
     assert out.value is None

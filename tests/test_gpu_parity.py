@@ -120,7 +120,8 @@ def test_explicit_fft_shape_matches_oracle(cases):
 def test_dft_schedules_match_oracle(cases, name):
     # each way of running the grid DFT, forced through the plan descriptor: direct axis passes,
     # the fused two-axis kernel (2-D grids only; the 3-D tube lattice falls back to the passes)
-    # and the axis passes as MFMA GEMMs with the DFT matrices
+    # the axis passes as MFMA GEMMs with the DFT matrices, and both axes fused on the matrix
+    # cores (2-D grids only, else the passes)
     import paper_2201_12050_amd as fm
     F, P, lat = cases[name]
     kind = CASES[name][0]
@@ -130,7 +131,7 @@ def test_dft_schedules_match_oracle(cases, name):
         ref = F.matvec(x)
         xd = torch.from_numpy(x).cuda()
         out = {}
-        for sched in ("axes", "fused", "gemm"):
+        for sched in ("axes", "fused", "gemm", "mfma"):
             Q = fm.Plan(v, t, lat.grid, pitch, F.k, F.order, "bm", dft_schedule=sched)
             out[sched] = Q.matvec(xd, precision="fp64").cpu().numpy()
             assert rel(out[sched], ref) < 1e-12, (sched, R)
@@ -138,6 +139,25 @@ def test_dft_schedules_match_oracle(cases, name):
             assert rel(y32, ref) < 1e-5, (sched, R)
         # the fused kernel sums in the order of the axis passes: equal bit for bit
         assert np.array_equal(out["axes"], out["fused"])
+
+
+def test_dft_mfma_long_axis_matches_oracle():
+    # 2 x 40 lattice: 79 bins along axis 1, so the fused matrix-core DFT takes the output tiles of
+    # a forward line in two groups and the inverse first pass has more inputs per line than its
+    # register sets hold; 3 x 16 = 48 channels (n_t = 3), R = 3
+    import paper_2201_12050_amd as fm
+    v, t = icosphere(1, 0.1)
+    lat = Lattice((2, 40, 1), (0.3, 0.3, 0.3))
+    k = 2 * np.pi * 700.0 / 343.0
+    F = op.FMPBEM(v, t, lat, k, 3, -1j / k)
+    x = random_complex((3, lat.n_cells, t.shape[0]), 911)
+    ref = F.matvec(x)
+    xd = torch.from_numpy(x).cuda()
+    for sched in ("axes", "mfma"):
+        Q = fm.Plan(v, t, lat.grid, lat.pitch, k, 3, "bm", dft_schedule=sched)
+        assert rel(Q.matvec(xd, precision="fp64").cpu().numpy(), ref) < 1e-12, sched
+        assert rel(Q.matvec(xd.to(torch.complex64), precision="fp32").cpu().numpy(), ref) < 1e-5, sched
+        Q.close()
 
 
 def test_matvec_batched_equals_alone(cases):
