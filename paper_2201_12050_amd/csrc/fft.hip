@@ -241,8 +241,8 @@ __global__ __launch_bounds__(256) void dft2_kernel(cplx<T>* __restrict__ buf, in
 }
 
 // Fused two-axis DFT on the matrix cores, for N3 = 1 grids with many channels and
-// 1 < N_a <= kDftGemmMaxOut.  One workgroup of four waves per slice of kDftmCh channels (one tile
-// column).  The slice's inputs are staged into LDS first with every load in flight at once (the
+// 1 < N_a <= kDftGemmMaxOut.  One workgroup of kDftmWaves waves per slice of kDftmCh channels (one
+// tile column).  The slice's inputs are staged into LDS first with every load in flight at once (the
 // D factor of the inverse removed on the way), then both axis passes run from LDS: each
 // multiplies the lines of the slice by that axis's DFT matrix ([outputs][inputs]: forward
 // [N_a][M_a], inverse [M_a][N_a]) on 16x16x4 tiles, a complex product as four real ones
@@ -253,6 +253,12 @@ __global__ __launch_bounds__(256) void dft2_kernel(cplx<T>* __restrict__ buf, in
 // The slab has row stride N0: [M1][N0] forward, [N1][N0] inverse.
 constexpr int kDftmCh = 16;
 constexpr int kDftmGroup = 4;
+#ifndef FMBEM_DFTM_WAVES
+#define FMBEM_DFTM_WAVES 8
+#endif
+// waves per workgroup: two per SIMD, so that one wave's LDS reads overlap the other's MFMAs
+constexpr int kDftmWaves = FMBEM_DFTM_WAVES;
+constexpr int kDftmThreads = 64 * kDftmWaves;
 
 // One sweep over the inputs of line L for output tiles mb0 .. mb0 + MBT - 1:
 //   out(L, o, c) = sum_j A[o][j] in(L, j, c),  o in those tiles, o < nout.
@@ -317,15 +323,15 @@ __device__ inline void dftm_sweep(const cplx<T>* __restrict__ A, int lda, int mb
   }
 }
 
-// out(L, o, c) = sum_{j < nin} A[o][j] in(L, j, c) for o < nout and every line L = w + 4 i of
-// wave w; the output tiles of a line in sweeps of at most kDftmGroup tiles.
+// out(L, o, c) = sum_{j < nin} A[o][j] in(L, j, c) for o < nout and every line L = w + kDftmWaves i
+// of wave w; the output tiles of a line in sweeps of at most kDftmGroup tiles.
 template <typename T, typename In, typename Out>
 __device__ inline void dftm_pass(const cplx<T>* __restrict__ A, int lda, int nout, int nin, int lines, In in,
                                  Out out) {
   // the wave index is uniform over the wave: made scalar so that the loops branch on scalars
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int MB = (nout + 15) >> 4, KS = (nin + 3) >> 2;
-  for (int L = w; L < lines; L += 4) {
+  for (int L = w; L < lines; L += kDftmWaves) {
     for (int mb0 = 0; mb0 < MB;) {
       const int rem = MB - mb0;
       if (rem >= 4) {
@@ -352,7 +358,7 @@ __host__ __device__ inline int dftm_lda(int nin) { return 4 * ((nin + 3) / 4) + 
 
 // FP32: at most 128 registers (two waves per SIMD); FP64 needs more for its register sets
 template <typename T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1))) void dft2m_kernel(
+__global__ __launch_bounds__(kDftmThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1))) void dft2m_kernel(
     cplx<T>* __restrict__ buf, int channels, int N0, int N1, int M0, int M1, int inverse, int flip_p,
     const cplx<T>* __restrict__ P1, const cplx<T>* __restrict__ P2) {
   extern __shared__ unsigned char smem_raw[];
@@ -386,7 +392,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       for (int h = 0; h < CPL; ++h) odd2[h] = ok && flip_p > 0 && odd_degree(c0 + cl + h, flip_p);
       const int total = rows * cols * TPR;
 #pragma unroll 16
-      for (int e = threadIdx.x; e < total; e += 256) {
+      for (int e = threadIdx.x; e < total; e += kDftmThreads) {
         const int rc = e / TPR, col = rc % cols, row = rc / cols;
         V v{};
         if (ok) v = *reinterpret_cast<const V*>(buf + ((size_t)row * N0 + col) * channels + c0 + cl);
@@ -401,7 +407,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       }
     } else {
 #pragma unroll 8
-      for (int e = threadIdx.x; e < rows * cols * kDftmCh; e += 256) {
+      for (int e = threadIdx.x; e < rows * cols * kDftmCh; e += kDftmThreads) {
         const int rc = e >> 4, col = rc % cols, row = rc / cols;
         cplx<T> v = valid ? buf[((size_t)row * N0 + col) * channels + ch] : mk<T>(0, 0);
         if (inverse && odd && flipped2(col, row, N0, N1)) v = mk<T>(-v.x, -v.y);
@@ -410,12 +416,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     }
   }
 #pragma unroll 4
-  for (int e = threadIdx.x; e < dftm_rows(out1) * lda1; e += 256) {
+  for (int e = threadIdx.x; e < dftm_rows(out1) * lda1; e += kDftmThreads) {
     const int r = e / lda1, k = e - r * lda1;
     A1[e] = (r < out1 && k < in1) ? P1[r * in1 + k] : mk<T>(0, 0);
   }
 #pragma unroll 4
-  for (int e = threadIdx.x; e < dftm_rows(out2) * lda2; e += 256) {
+  for (int e = threadIdx.x; e < dftm_rows(out2) * lda2; e += kDftmThreads) {
     const int r = e / lda2, k = e - r * lda2;
     A2[e] = (r < out2 && k < in2) ? P2[r * in2 + k] : mk<T>(0, 0);
   }
@@ -519,7 +525,7 @@ hipError_t grid_dft_launch(void* bufv, int channels, const int M[3], const int N
     // pass 1 is axis 0 forward, axis 1 inverse
     const void* p1 = fmat[off + (inverse ? 1 : 0)];
     const void* p2 = fmat[off + (inverse ? 0 : 1)];
-    hipLaunchKernelGGL(dft2m_kernel<T>, dim3((unsigned)((channels + kDftmCh - 1) / kDftmCh)), dim3(256), lds, s, buf,
+    hipLaunchKernelGGL(dft2m_kernel<T>, dim3((unsigned)((channels + kDftmCh - 1) / kDftmCh)), dim3(kDftmThreads), lds, s, buf,
                        channels, N[0], N[1], M[0], M[1], inverse ? 1 : 0, flip_p,
                        reinterpret_cast<const cplx<T>*>(p1), reinterpret_cast<const cplx<T>*>(p2));
     return hipGetLastError();
