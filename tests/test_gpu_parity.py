@@ -322,3 +322,45 @@ def test_grid16_full_size_sampled_rows():
     ref = op.sampled_apply(w.vertices, w.triangles, w.lattice, w.k, w.order, -1j / w.k, x, dofs)
     assert rel(y64[:, dofs], ref) < 1e-12
     assert rel(y32[:, dofs], ref) < 1e-5
+
+
+@pytest.mark.parametrize("grid", [(1, 1, 1), (2, 2, 1), (2, 1, 1), (2, 2, 2)])
+def test_all_near_lattices_match_oracle(grid):
+    # degenerate lattices where every cell pair is in the near field (no far field, no DFT, no
+    # M2L): the operator is the near-field block-Toeplitz product alone; a single cell is one
+    # dense block.  Matvec in both precisions, and a solve against LU of the dense matrix.
+    import paper_2201_12050_amd as fm
+    v, t = icosphere(1, 0.1)
+    lat = Lattice(grid, (0.3, 0.3, 0.3))
+    k = 2 * np.pi * 900.0 / 343.0
+    F = op.FMPBEM(v, t, lat, k, 4, -1j / k)
+    P = fm.Plan(v, t, grid, (0.3, 0.3, 0.3), k, 4)
+    assert P.info["n_far"] == 0
+    x = random_complex((3, lat.n_cells, t.shape[0]), 70 + lat.n_cells)
+    ref = F.matvec(x)
+    xd = torch.from_numpy(x).cuda()
+    assert rel(P.matvec(xd, precision="fp64").cpu().numpy(), ref) < 1e-12
+    assert rel(P.matvec(xd.to(torch.complex64), precision="fp32").cpu().numpy(), ref) < 1e-5
+    b = P.incident_plane_wave([[0.0, 0.6, 0.8]])
+    xs, info = P.solve(b, tol=1e-10, inner="fp32")
+    xl = solve.lu_solve(bem.dense_exact(v, t, lat, k, -1j / k), b.cpu().numpy().ravel())
+    assert info[0]["rel_residual"] <= 1e-10
+    assert rel(xs.cpu().numpy().ravel(), xl) < 1e-6
+    P.close()
+
+
+def test_wider_near_field_matches_oracle():
+    # near radius 2 on a 6 x 5 lattice: 25 near blocks, the far field starts two cells away
+    import paper_2201_12050_amd as fm
+    v, t = icosphere(1, 0.1)
+    lat = Lattice((6, 5, 1), (0.3, 0.3, 0.3))
+    k = 2 * np.pi * 1100.0 / 343.0
+    F = op.FMPBEM(v, t, lat, k, 6, -1j / k, near_radius=(2, 2, 2))
+    P = fm.Plan(v, t, lat.grid, lat.pitch, k, 6, near_radius=(2, 2, 2))
+    assert P.info["n_near"] == 25
+    x = random_complex((2, lat.n_cells, t.shape[0]), 808)
+    ref = F.matvec(x)
+    xd = torch.from_numpy(x).cuda()
+    assert rel(P.matvec(xd, precision="fp64").cpu().numpy(), ref) < 1e-12
+    assert rel(P.matvec(xd.to(torch.complex64), precision="fp32").cpu().numpy(), ref) < 1e-5
+    P.close()
