@@ -14,6 +14,8 @@ Contents (paper sections in brackets):
   fmm         P2M (V0), L2P (U0), M2L (K_d) operators [Sec. 3.1, Appendix A]
   operator    FMPBEM operator S + U K V applied block by block, no FFT (O2) [Sec. 3.2]
   solve       dense LU and restarted GMRES [Sec. 3.5, Sec. 4]
+  halfspace   half-space Green's function: image blocks, image multipole chain, incident fields
+              and field evaluation with the image terms [eq. (green3dHalf), Sec. 2.3, Sec. 3.4]
   mie         Mie series for a rigid sphere (analytic pin, not from the paper)
 
 Every function here is pinned by a ``-m "not gpu"`` test against closed forms,
