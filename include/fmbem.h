@@ -79,6 +79,17 @@ typedef struct {
   int32_t dft_schedule;       /* FMBEM_DFT_*: how the grid DFT (Sec. 2.4) runs; AUTO measures the
                                  applicable schedules on first use of each problem signature; a
                                  forced schedule that does not apply falls back to AXES */
+  /* Half-space (Sec. 2.1, eq. (green3dHalf); Sec. 2.3; Sec. 3.4): halfspace = 1 adds to every
+   * interaction the image term R_p G(x, y^), y^ the mirror image of y in the plane
+   * z = plane_z, applied as image near blocks and an image multipole chain (Appendix A,
+   * eq. (greenFMMhalfspace)); the incident fields get their images too.  The plane must be
+   * parallel to every periodic direction (grid[2] == 1) and the cell mesh must not cross it
+   * (else FMBEM_ERR_INVALID_ARG).  The image block of offset d is near when d is a near offset
+   * and |2 plane_z| < (near_radius[2] + 1) pitch[2].  halfspace = 0: full space (the other
+   * three fields are ignored). */
+  int32_t halfspace;
+  double plane_z;
+  double reflection_re, reflection_im;  /* R_p */
 } fmbem_plan_desc;
 
 #define FMBEM_DFT_AUTO 0    /* autotuned */
@@ -95,7 +106,8 @@ typedef struct {
   int32_t p;                  /* (n_t+1)^2 */
   int32_t fft_shape[3];       /* N1, N2, N3 */
   int32_t n_near;             /* number of near-field offsets (unique blocks S_d) */
-  int32_t n_far;              /* number of far offsets in the Toeplitz structure */
+  int32_t n_far;              /* number of far offsets in the Toeplitz structure (plus the far
+                                 image offsets in the half-space) */
   uint32_t precisions;        /* resident operator copies */
   size_t resident_bytes;      /* device memory owned by the plan */
   size_t workspace_bytes_per_rhs[2]; /* matvec workspace per right-hand side, [FP64, FP32] */

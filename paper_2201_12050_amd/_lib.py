@@ -36,7 +36,8 @@ class PlanDesc(ct.Structure):
     _fields_ = [("grid", ct.c_int32 * 3), ("pitch", ct.c_double * 3), ("k", ct.c_double),
                 ("order", ct.c_int32), ("formulation", ct.c_int32), ("alpha_re", ct.c_double),
                 ("alpha_im", ct.c_double), ("near_radius", ct.c_int32 * 3), ("fft_shape", ct.c_int32 * 3),
-                ("precisions", ct.c_uint32), ("dft_schedule", ct.c_int32)]
+                ("precisions", ct.c_uint32), ("dft_schedule", ct.c_int32), ("halfspace", ct.c_int32),
+                ("plane_z", ct.c_double), ("reflection_re", ct.c_double), ("reflection_im", ct.c_double)]
 
 
 DFT_SCHEDULE = {"auto": 0, "axes": 1, "fused": 2, "gemm": 3, "mfma": 4}
@@ -296,7 +297,9 @@ class Plan:
 
     def __init__(self, vertices, triangles, grid, pitch, k, order, formulation="bm", alpha=None,
                  near_radius=(1, 1, 1), fft_shape=(0, 0, 0), precisions=("fp64", "fp32"), stream=None,
-                 dft_schedule="auto"):
+                 dft_schedule="auto", halfspace=None):
+        """halfspace: None (full space) or (plane_z, R_p): the half-space Green's function with the
+        plane z = plane_z and reflection coefficient R_p (grid[2] must be 1)."""
         lib = load()
         self._lib = lib
         v = np.ascontiguousarray(vertices, dtype=np.float64)
@@ -318,6 +321,11 @@ class Plan:
             d.alpha_re, d.alpha_im = float(np.real(alpha)), float(np.imag(alpha))
         d.precisions = sum(1 << _precision(p) for p in precisions)
         d.dft_schedule = DFT_SCHEDULE[dft_schedule]
+        if halfspace is not None:
+            zg, rp = halfspace
+            d.halfspace = 1
+            d.plane_z = float(zg)
+            d.reflection_re, d.reflection_im = float(np.real(rp)), float(np.imag(rp))
         h = ct.c_void_p()
         check(lib.fmbem_plan_create(ct.byref(mesh), ct.byref(d), _stream_ptr(stream), ct.byref(h)),
               "fmbem_plan_create")

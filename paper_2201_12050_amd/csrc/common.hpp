@@ -85,7 +85,17 @@ struct Plan {
   // ([N_a][M_a], w^(k j) with w = e^(-2 pi i / N_a)), inverse at [3 + a] ([M_a][N_a], conjugate
   // kernel); only for 1 < N_a <= kDftGemmMaxOut, else nullptr
   void* dftF[2][6] = {};
-  int dft_forced = -1;       // DFT schedule forced by the plan descriptor (0 axes, 1 fused, 2 GEMM), -1: tuned
+  int dft_forced = -1;       // DFT schedule forced by the plan descriptor (0 axes, 1 fused, 2 GEMM, 3 fused
+                             // on the matrix cores), -1: tuned
+  // half-space: image term R_p G(x, y^) with y^ mirrored in z = zg (grid[2] == 1)
+  bool half = false;
+  double zg = 0.0, rp_re = 0.0, rp_im = 0.0;
+  bool img_near = false;     // the image blocks of the near offsets are near blocks too
+  int n_far_img = 0;         // image offsets applied through the multipole chain
+  // the canonical-bin pairing Lambda(-w) = D Lambda(w) D holds (off in the half-space, whose
+  // image part pairs differently): when off every bin is stored and the DFT applies no D
+  bool paired = true;
+  int flip_p() const { return paired ? p : 0; }
   // Lambda of bin -w is D Lambda(w) D, D = diag((-1)^n) (reciprocity of the translations), so only
   // canonical bins (linear index <= that of the partner bin -w) are stored.
   int Bc = 0;                // canonical bins

@@ -9,6 +9,8 @@
 // non-self Duffy rule of the plan build: q x q points collapsed at the first vertex,
 // q = 16 / 8 / 4 for |x - centroid_j| < L_j / < 3 L_j / otherwise.
 // The insertion loss (eq. (insertionloss)) is 20 log10(sum_i |p_inc(x_i)| / sum_i |p(x_i)|).
+// In the half-space the Green's function carries the image term (Sec. 2.1, eq. (green3dHalf)):
+// W_j gains R_p times the weight of the mirrored element, and the incident field its image.
 //
 // Work split: one workgroup per (point, chunk of kFieldPerThread * 256 elements, group of
 // up to kFieldRhs right-hand sides).  Each thread integrates W_j for its elements once and
@@ -69,11 +71,33 @@ __device__ inline double2 dl_weight(const double* x, const Geo& e, const double*
   return make_double2(re, im);
 }
 
-// grid: x = point * chunks + chunk, y = group of kFieldRhs right-hand sides
+// the element e of the cell at origin o mirrored in the plane z = zg, vertices (a, c, b) so that
+// its normal is the mirrored normal
+__device__ inline Geo mirrored(const Geo& e, const double* o, double zg) {
+  Geo m;
+  for (int t = 0; t < 3; ++t) {
+    m.a[t] = e.a[t] + o[t];
+    m.b[t] = e.c[t] + o[t];
+    m.c[t] = e.b[t] + o[t];
+    m.cen[t] = e.cen[t] + o[t];
+    m.nrm[t] = e.nrm[t];
+  }
+  m.a[2] = 2.0 * zg - m.a[2];
+  m.b[2] = 2.0 * zg - m.b[2];
+  m.c[2] = 2.0 * zg - m.c[2];
+  m.cen[2] = 2.0 * zg - m.cen[2];
+  m.nrm[2] = -m.nrm[2];
+  m.longest = e.longest;
+  m.area = e.area;
+  return m;
+}
+
+// grid: x = point * chunks + chunk, y = group of kFieldRhs right-hand sides.  half != 0 adds
+// R_p times the double-layer weight of the mirrored element (half-space Green's function).
 __global__ __launch_bounds__(kFieldThreads) void field_kernel(
     const double* __restrict__ geom, int n, int C, int g0, int g1, double p0, double p1, double p2, double k,
-    QuadTab Q, const double* __restrict__ pts, int chunks, const double2* __restrict__ xs, int R, int M,
-    double2* __restrict__ part) {
+    QuadTab Q, const double* __restrict__ pts, int chunks, const double2* __restrict__ xs, int R, int M, int half,
+    double zg, double2 rp, double2* __restrict__ part) {
   __shared__ double red[4];
   const int m = blockIdx.x / chunks;
   const int chunk = blockIdx.x - m * chunks;
@@ -90,7 +114,12 @@ __global__ __launch_bounds__(kFieldThreads) void field_kernel(
     const int c = (int)(j / n);
     const int i = (int)(j - (size_t)c * n);
     const double o[3] = {(c % g0) * p0, ((c / g0) % g1) * p1, (c / (g0 * g1)) * p2};
-    const double2 w = dl_weight(x, load_geo(geom, i), o, k, Q);
+    const Geo el = load_geo(geom, i);
+    double2 w = dl_weight(x, el, o, k, Q);
+    if (half) {
+      const double o0[3] = {0.0, 0.0, 0.0};
+      w = cadd<double>(w, cmul<double>(rp, dl_weight(x, mirrored(el, o, zg), o0, k, Q)));
+    }
 #pragma unroll
     for (int r = 0; r < kFieldRhs; ++r)
       if (r < nr) cfma<double>(acc[r], w, xs[(size_t)(r0 + r) * N + j]);
@@ -123,13 +152,8 @@ __global__ void field_finish_kernel(const double2* __restrict__ part, int chunks
 
 // incident pressure at arbitrary points: plane wave A e^{ik d.x} (Sec. 4.1, eq. (planewave))
 // or monopole A e^{ikR}/R (Sec. 4.2); out [R][M]
-__global__ void incident_points_kernel(double k, int R, const double* __restrict__ src, int point, double amp,
-                                       const double* __restrict__ pts, int M, double2* __restrict__ out) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= R * M) return;
-  const int r = idx / M, m = idx - r * M;
-  const double* s = src + 3 * r;
-  const double* x = pts + 3 * m;
+// (half != 0: plus R_p times the incident field at the mirrored point, the image of the field)
+__device__ inline double2 incident_value(const double* x, const double* s, int point, double k, double amp) {
   double ph, mag;
   if (!point) {
     ph = k * dot3(s, x);
@@ -142,7 +166,23 @@ __global__ void incident_points_kernel(double k, int R, const double* __restrict
   }
   double sn, cs;
   sincos(ph, &sn, &cs);
-  out[idx] = make_double2(mag * cs, mag * sn);
+  return make_double2(mag * cs, mag * sn);
+}
+
+__global__ void incident_points_kernel(double k, int R, const double* __restrict__ src, int point, double amp,
+                                       const double* __restrict__ pts, int M, int half, double zg, double2 rp,
+                                       double2* __restrict__ out) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= R * M) return;
+  const int r = idx / M, m = idx - r * M;
+  const double* s = src + 3 * r;
+  const double* x = pts + 3 * m;
+  double2 v = incident_value(x, s, point, k, amp);
+  if (half) {
+    const double xm[3] = {x[0], x[1], 2.0 * zg - x[2]};
+    v = cadd<double>(v, cmul<double>(rp, incident_value(xm, s, point, k, amp)));
+  }
+  out[idx] = v;
 }
 
 // il[r] = 20 log10(sum_m |p_inc[r][m]| / sum_m |p[r][m]|), one workgroup per right-hand side
@@ -196,7 +236,8 @@ extern "C" fmbem_status fmbem_incident_at_points(fmbem_plan plan, int32_t kind, 
   if (e == hipSuccess) {
     const int total = n_rhs * n_points;
     hipLaunchKernelGGL(incident_points_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, P.k, n_rhs,
-                       d_src, kind, amplitude, d_pts, n_points, (double2*)p_inc);
+                       d_src, kind, amplitude, d_pts, n_points, P.half ? 1 : 0, P.zg, make_double2(P.rp_re, P.rp_im),
+                       (double2*)p_inc);
     e = hipGetLastError();
   }
   const hipError_t e2 = hipStreamSynchronize(s);  // src and points are host memory owned by the caller
@@ -225,7 +266,8 @@ extern "C" fmbem_status fmbem_field(fmbem_plan plan, int32_t n_rhs, const void* 
   if (e == hipSuccess) {
     hipLaunchKernelGGL(field_kernel, dim3((unsigned)(chunks * n_points), (unsigned)groups), dim3(kFieldThreads), 0,
                        s, P.geom, P.n, P.C, P.grid[0], P.grid[1], P.pitch[0], P.pitch[1], P.pitch[2], P.k, P.quad,
-                       d_pts, (int)chunks, (const double2*)x, n_rhs, n_points, part);
+                       d_pts, (int)chunks, (const double2*)x, n_rhs, n_points, P.half ? 1 : 0, P.zg,
+                       make_double2(P.rp_re, P.rp_im), part);
     e = hipGetLastError();
   }
   if (e == hipSuccess) {

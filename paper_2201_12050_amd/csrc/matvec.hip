@@ -169,11 +169,11 @@ static int dft_schedule(const Plan& P, int R, void* ws, hipStream_t s, bool tune
     for (int sweep = 0; sweep < 2; ++sweep)
       for (int v = 0; v < 4; ++v) {
         if (!ok[v]) continue;
-        if (grid_dft_launch<T>(ws, ch, P.grid, P.fft, false, true, s, P.p, v, P.dftF[prec]) != hipSuccess) continue;
+        if (grid_dft_launch<T>(ws, ch, P.grid, P.fft, false, true, s, P.flip_p(), v, P.dftF[prec]) != hipSuccess) continue;
         hipEventRecord(a, s);
-        grid_dft_launch<T>(ws, ch, P.grid, P.fft, false, true, s, P.p, v, P.dftF[prec]);
+        grid_dft_launch<T>(ws, ch, P.grid, P.fft, false, true, s, P.flip_p(), v, P.dftF[prec]);
         hipEventRecord(b, s);
-        grid_dft_launch<T>(ws, ch, P.grid, P.fft, true, true, s, P.p, v, P.dftF[prec]);
+        grid_dft_launch<T>(ws, ch, P.grid, P.fft, true, true, s, P.flip_p(), v, P.dftF[prec]);
         hipEventRecord(c, s);
         float ms0 = 0.f, ms1 = 0.f;
         if (hipEventSynchronize(c) != hipSuccess || hipEventElapsedTime(&ms0, a, b) != hipSuccess ||
@@ -275,14 +275,14 @@ static hipError_t matvec_overlap(const Plan& P, int R, const void* x, void* y, v
     const int shape = tune ? tuned_shape<T>(0, s2m, P.aux) : cached_shape<T>(0, s2m);
     if ((e = near_launch<T>(s2m, P.aux, shape, 0))) return e;
   }
-  if ((e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, false, true, P.aux, p, sched_fwd(dsched), P.dftF[prec]))) return e;
+  if ((e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, false, true, P.aux, P.flip_p(), sched_fwd(dsched), P.dftF[prec]))) return e;
   prof_end(P, 2 + 6 * prec, ev, P.aux);
   ev = prof_begin(P, 3 + 6 * prec, P.aux);
   void* lhat = nullptr;
   if ((e = m2l_apply<T>(P, R, ws, P.aux, &lhat, tune))) return e;
   prof_end(P, 3 + 6 * prec, ev, P.aux);
   ev = prof_begin(P, 4 + 6 * prec, P.aux);
-  if ((e = grid_dft_launch<T>(lhat, R * p, P.grid, P.fft, true, true, P.aux, p, sched_inv(dsched), P.dftF[prec]))) return e;
+  if ((e = grid_dft_launch<T>(lhat, R * p, P.grid, P.fft, true, true, P.aux, P.flip_p(), sched_inv(dsched), P.dftF[prec]))) return e;
   prof_end(P, 4 + 6 * prec, ev, P.aux);
   if ((e = hipEventRecord(P.ev_join, P.aux))) return e;
   // [0] near field on the caller's stream
@@ -336,7 +336,7 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
   }
   // [2]-[4] DFT, M2L, inverse DFT
   ev = prof_begin(P, 2 + 6 * prec, s);
-  hipError_t e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, false, true, s, p, sched_fwd(dsched), P.dftF[prec]);
+  hipError_t e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, false, true, s, P.flip_p(), sched_fwd(dsched), P.dftF[prec]);
   if (e != hipSuccess) return e;
   prof_end(P, 2 + 6 * prec, ev, s);
   ev = prof_begin(P, 3 + 6 * prec, s);
@@ -345,7 +345,7 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
   if (e != hipSuccess) return e;
   prof_end(P, 3 + 6 * prec, ev, s);
   ev = prof_begin(P, 4 + 6 * prec, s);
-  e = grid_dft_launch<T>(lhat, R * p, P.grid, P.fft, true, true, s, p, sched_inv(dsched), P.dftF[prec]);
+  e = grid_dft_launch<T>(lhat, R * p, P.grid, P.fft, true, true, s, P.flip_p(), sched_inv(dsched), P.dftF[prec]);
   if (e != hipSuccess) return e;
   prof_end(P, 4 + 6 * prec, ev, s);
   // [5] L2T with the fixed-order sum of the near partials
@@ -383,10 +383,10 @@ static hipError_t matvec_group_t(const std::vector<GroupApply>& g, hipStream_t s
       continue;
     }
     void* lhat = nullptr;
-    e = grid_dft_launch<T>(a.ws, a.R * P.p, P.grid, P.fft, false, true, s, P.p, sched_fwd(dsched[q]), P.dftF[prec]);
+    e = grid_dft_launch<T>(a.ws, a.R * P.p, P.grid, P.fft, false, true, s, P.flip_p(), sched_fwd(dsched[q]), P.dftF[prec]);
     if (e != hipSuccess) return e;
     if ((e = m2l_apply<T>(P, a.R, a.ws, s, &lhat, tune)) != hipSuccess) return e;
-    e = grid_dft_launch<T>(lhat, a.R * P.p, P.grid, P.fft, true, true, s, P.p, sched_inv(dsched[q]), P.dftF[prec]);
+    e = grid_dft_launch<T>(lhat, a.R * P.p, P.grid, P.fft, true, true, s, P.flip_p(), sched_inv(dsched[q]), P.dftF[prec]);
     if (e != hipSuccess) return e;
     l2t.push_back(l2t_job<T>(P, a.R, a.ws, lhat, a.y, a.y64));
   }

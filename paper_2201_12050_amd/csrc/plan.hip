@@ -128,10 +128,41 @@ __device__ double2 hyper_self(const Geo& e, double k, const QuadTab& Q) {
   return make_double2((fp + re) / kFourPi, im / kFourPi);
 }
 
-// one entry S_d[i][j] per thread; entries ordered (d, i, j) with j fastest
+// int over the flat triangle with first vertex a, edges ba = b - a and cb = c - b (Duffy rule
+// collapsed at a, q x q points, q by the distance from x to the centroid) of the kernel at x
+// (ca = c - a for the Jacobian)
+__device__ inline double2 elem_integral(const double* x, const double* nx, const double* a, const double* ba,
+                                       const double* cb, const double* ca, const double* cen, double longest,
+                                       const double* ny, double k, double2 alpha, int hyper, const QuadTab& Q) {
+  double dc[3] = {x[0] - cen[0], x[1] - cen[1], x[2] - cen[2]};
+  const double dist = sqrt(dot3(dc, dc));
+  const int q = dist < longest ? 16 : (dist < 3.0 * longest ? 8 : 4);
+  const int o = quad_off(q);
+  double cr[3] = {ba[1] * ca[2] - ba[2] * ca[1], ba[2] * ca[0] - ba[0] * ca[2], ba[0] * ca[1] - ba[1] * ca[0]};
+  const double jac = sqrt(dot3(cr, cr));
+  double re = 0.0, im = 0.0;
+  for (int ia = 0; ia < q; ++ia) {
+    const double u = Q.t[o + ia];
+    const double wu = Q.w[o + ia] * u * jac;
+    for (int ib = 0; ib < q; ++ib) {
+      const double v = Q.t[o + ib];
+      double r[3];
+      for (int t = 0; t < 3; ++t) r[t] = x[t] - (a[t] + u * (ba[t] + v * cb[t]));
+      const double2 kv = bm_kernel(r, nx, ny, k, alpha, hyper != 0);
+      const double wt = wu * Q.w[o + ib];
+      re += wt * kv.x;
+      im += wt * kv.y;
+    }
+  }
+  return make_double2(re, im);
+}
+
+// one entry S_d[i][j] per thread; entries ordered (d, i, j) with j fastest.  In the half-space
+// (img != 0) every near block also holds R_p times its image block: the source element of the
+// shifted cell mirrored in z = zg, vertices (a, c, b) so that its normal is the mirrored normal.
 __global__ void assemble_near_kernel(const double* __restrict__ geom, int n, const int* __restrict__ offs, int n_near,
                             double p0, double p1, double p2, double k, double2 alpha, int hyper, QuadTab Q,
-                            double2* __restrict__ S64, float2* __restrict__ S32) {
+                            int img, double zg, double2 rp, double2* __restrict__ S64, float2* __restrict__ S32) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t nn = (size_t)n * n;
   if (idx >= nn * n_near) return;
@@ -142,41 +173,38 @@ __global__ void assemble_near_kernel(const double* __restrict__ geom, int n, con
   const int o0 = offs[3 * d], o1 = offs[3 * d + 1], o2 = offs[3 * d + 2];
   const double sh[3] = {-o0 * p0, -o1 * p1, -o2 * p2};
   const Geo ex = load_geo(geom, i);
+  const Geo ey = load_geo(geom, j);
   double2 val;
   if (o0 == 0 && o1 == 0 && o2 == 0 && i == j) {
     val = make_double2(0.5, 0.0);
     if (hyper) val = cadd<double>(val, cmul<double>(alpha, hyper_self(ex, k, Q)));
   } else {
-    const Geo ey = load_geo(geom, j);
-    double a[3], ba[3], cb[3];
+    double a[3], ba[3], cb[3], ca[3], cen[3];
     for (int t = 0; t < 3; ++t) {
       a[t] = ey.a[t] + sh[t];
       ba[t] = ey.b[t] - ey.a[t];
       cb[t] = ey.c[t] - ey.b[t];
+      ca[t] = ey.c[t] - ey.a[t];
+      cen[t] = ey.cen[t] + sh[t];
     }
-    double dc[3] = {ex.cen[0] - (ey.cen[0] + sh[0]), ex.cen[1] - (ey.cen[1] + sh[1]),
-                    ex.cen[2] - (ey.cen[2] + sh[2])};
-    const double dist = sqrt(dot3(dc, dc));
-    const int q = dist < ey.longest ? 16 : (dist < 3.0 * ey.longest ? 8 : 4);
-    const int o = quad_off(q);
-    double ca[3] = {ey.c[0] - ey.a[0], ey.c[1] - ey.a[1], ey.c[2] - ey.a[2]};
-    double cr[3] = {ba[1] * ca[2] - ba[2] * ca[1], ba[2] * ca[0] - ba[0] * ca[2], ba[0] * ca[1] - ba[1] * ca[0]};
-    const double jac = sqrt(dot3(cr, cr));
-    double re = 0.0, im = 0.0;
-    for (int ia = 0; ia < q; ++ia) {
-      const double u = Q.t[o + ia];
-      const double wu = Q.w[o + ia] * u * jac;
-      for (int ib = 0; ib < q; ++ib) {
-        const double v = Q.t[o + ib];
-        double r[3];
-        for (int t = 0; t < 3; ++t) r[t] = ex.cen[t] - (a[t] + u * (ba[t] + v * cb[t]));
-        const double2 kv = bm_kernel(r, ex.nrm, ey.nrm, k, alpha, hyper != 0);
-        const double wt = wu * Q.w[o + ib];
-        re += wt * kv.x;
-        im += wt * kv.y;
-      }
+    val = elem_integral(ex.cen, ex.nrm, a, ba, cb, ca, cen, ey.longest, ey.nrm, k, alpha, hyper, Q);
+  }
+  if (img) {
+    // mirrored element (a, c, b): z -> 2 zg - z after the lattice shift
+    double a[3] = {ey.a[0] + sh[0], ey.a[1] + sh[1], 2.0 * zg - (ey.a[2] + sh[2])};
+    double c[3] = {ey.c[0] + sh[0], ey.c[1] + sh[1], 2.0 * zg - (ey.c[2] + sh[2])};
+    double b[3] = {ey.b[0] + sh[0], ey.b[1] + sh[1], 2.0 * zg - (ey.b[2] + sh[2])};
+    // the mirrored triangle (a, c, b): edges c - a and b - c, Jacobian from b - a
+    double ca[3], bc[3], ba[3];
+    for (int t = 0; t < 3; ++t) {
+      ca[t] = c[t] - a[t];
+      bc[t] = b[t] - c[t];
+      ba[t] = b[t] - a[t];
     }
-    val = make_double2(re, im);
+    const double cen[3] = {ey.cen[0] + sh[0], ey.cen[1] + sh[1], 2.0 * zg - (ey.cen[2] + sh[2])};
+    const double ny[3] = {ey.nrm[0], ey.nrm[1], -ey.nrm[2]};
+    const double2 w = elem_integral(ex.cen, ex.nrm, a, ca, bc, ba, cen, ey.longest, ny, k, alpha, hyper, Q);
+    val = cadd<double>(val, cmul<double>(rp, w));
   }
   S64[idx] = val;
   if (S32) S32[idx] = make_float2((float)val.x, (float)val.y);
@@ -310,8 +338,11 @@ __global__ void l2p_kernel(const double* __restrict__ geom, int n, int nt, doubl
 
 // O_l^mu(d * pitch) on the circulant grid, zero at near offsets and padding gaps.
 // one thread per (bin, mu >= 0); output [bin][(2nt+1)^2]
+// zoff is added to the z component of every offset (the image offsets of the half-space);
+// mask_near = 0 keeps the near offsets too (image blocks that are all far)
 __global__ void ogrid_kernel(int B, int N0, int N1, int N2, int M0, int M1, int M2, int r0, int r1, int r2,
-                             double p0, double p1, double p2, double k, int L, double2* __restrict__ O) {
+                             double p0, double p1, double p2, double k, int L, double zoff, int mask_near,
+                             double2* __restrict__ O) {
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= B * (L + 1)) return;
   const int bin = tid / (L + 1);
@@ -327,7 +358,7 @@ __global__ void ogrid_kernel(int B, int N0, int N1, int N2, int M0, int M1, int 
   };
   bool g0, g1, g2;
   const int d0 = off(b0, N0, M0, g0), d1 = off(b1, N1, M1, g1), d2 = off(b2, N2, M2, g2);
-  const bool near = (abs(d0) <= r0 && abs(d1) <= r1 && abs(d2) <= r2);
+  const bool near = mask_near && (abs(d0) <= r0 && abs(d1) <= r1 && abs(d2) <= r2);
   double2* out = O + (size_t)bin * P2;
   if (g0 || g1 || g2 || near) {
     for (int l = mu; l <= L; ++l) {
@@ -336,7 +367,7 @@ __global__ void ogrid_kernel(int B, int N0, int N1, int N2, int M0, int M1, int 
     }
     return;
   }
-  const double D[3] = {d0 * p0, d1 * p1, d2 * p2};
+  const double D[3] = {d0 * p0, d1 * p1, d2 * p2 + zoff};
   const double rho2 = D[0] * D[0] + D[1] * D[1];
   const double r = sqrt(rho2 + D[2] * D[2]);
   const double rho = sqrt(rho2);
@@ -361,16 +392,22 @@ __global__ void ogrid_kernel(int B, int N0, int N1, int N2, int M0, int M1, int 
   }
 }
 
-// Lambda'_c[j][i] (column-major per canonical bin c) = s^{n+n'}/B * sum_terms coef * Ohat_bin(c)[oidx]
-__global__ void lambda_kernel(const double2* __restrict__ Oh, int P2, int p, const int* __restrict__ pairs,
-                              const int* __restrict__ ptr, const double2* __restrict__ coef,
-                              const int* __restrict__ oidx, const double* __restrict__ sig,
-                              const int* __restrict__ nof, double invB, int ldp, double2* __restrict__ L64,
-                              float2* __restrict__ L32) {
+// Lambda'_c[j][i] (column-major per canonical bin c) = s^{n+n'}/B * sum_terms coef * Ohat_bin(c)[oidx].
+// Half-space (Ohi != nullptr): plus R_p (-1)^{n'+m'} sum_terms coef * Ohi_bin(c)[oidx], the image
+// translations acting on the reflected moments D_z V0 x (Appendix A, eq. (greenFMMhalfspace)).
+__global__ void lambda_kernel(const double2* __restrict__ Oh, const double2* __restrict__ Ohi, double2 rp, int P2,
+                              int p, const int* __restrict__ pairs, const int* __restrict__ ptr,
+                              const double2* __restrict__ coef, const int* __restrict__ oidx,
+                              const double* __restrict__ sig, const int* __restrict__ nof, double invB, int ldp,
+                              double2* __restrict__ L64, float2* __restrict__ L32) {
   extern __shared__ double2 so[];
+  double2* soi = so + P2;
   const int slot = blockIdx.y;
   const int bin = pairs[2 * slot];
-  for (int t = threadIdx.x; t < P2; t += blockDim.x) so[t] = Oh[(size_t)bin * P2 + t];
+  for (int t = threadIdx.x; t < P2; t += blockDim.x) {
+    so[t] = Oh[(size_t)bin * P2 + t];
+    if (Ohi) soi[t] = Ohi[(size_t)bin * P2 + t];
+  }
   __syncthreads();
   const size_t pp = (size_t)p * p;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < pp; e += (size_t)gridDim.x * blockDim.x) {
@@ -383,6 +420,19 @@ __global__ void lambda_kernel(const double2* __restrict__ Oh, int P2, int p, con
       const double2 o = so[oidx[t]];
       re += c.x * o.x - c.y * o.y;
       im += c.x * o.y + c.y * o.x;
+    }
+    if (Ohi) {
+      double ri = 0.0, ii = 0.0;
+      for (int t = ptr[te]; t < ptr[te + 1]; ++t) {
+        const double2 c = coef[t];
+        const double2 o = soi[oidx[t]];
+        ri += c.x * o.x - c.y * o.y;
+        ii += c.x * o.y + c.y * o.x;
+      }
+      const int nj = nof[j], mj = j - nj * nj - nj;
+      const double sg = ((nj + mj) & 1) ? -1.0 : 1.0;
+      re += sg * (rp.x * ri - rp.y * ii);
+      im += sg * (rp.x * ii + rp.y * ri);
     }
     const double f = sig[nof[i]] * sig[nof[j]] * invB;
     const double2 v = make_double2(re * f, im * f);
@@ -402,9 +452,32 @@ __global__ void cast_kernel(const double2* __restrict__ a, float2* __restrict__ 
 }
 
 // incident fields: b = p_inc + alpha dp_inc/dn at every collocation point
+// p_inc and dp_inc/dn of a plane wave (complex amplitude a, unit direction s) or a monopole at s
+__device__ inline void incident_at(const double* x, const double* nx, const double* s, int point, double k,
+                                   double2 a, double2& pv, double2& dp) {
+  if (!point) {
+    double sn, cs;
+    sincos(k * dot3(s, x), &sn, &cs);
+    pv = cmul<double>(a, make_double2(cs, sn));
+    dp = cmul<double>(make_double2(0.0, k * dot3(s, nx)), pv);
+  } else {
+    const double d[3] = {x[0] - s[0], x[1] - s[1], x[2] - s[2]};
+    const double R = sqrt(dot3(d, d));
+    double sn, cs;
+    sincos(k * R, &sn, &cs);
+    pv = cmul<double>(a, make_double2(cs / R, sn / R));
+    // dp/dn = A e^{ikR} (ikR - 1)/R^2 * (d.n)/R
+    const double f = dot3(d, nx) / (R * R * R);
+    dp = cmul<double>(cmul<double>(a, make_double2(cs * f, sn * f)), make_double2(-1.0, k * R));
+  }
+}
+
+// half != 0: plus R_p times the image of the incident field in the plane z = zg, i.e. a plane
+// wave of direction (s0, s1, -s2) and amplitude R_p A e^{2ik zg s2}, or a monopole R_p A at the
+// mirrored source (Sec. 2.1, eq. (green3dHalf))
 __global__ void incident_kernel(const double* __restrict__ geom, int n, int C, int g0, int g1, double p0,
                                 double p1, double p2, double k, double2 alpha, int R, const double* __restrict__ src,
-                                int point, double amp, double2* __restrict__ out) {
+                                int point, double amp, int half, double zg, double2 rp, double2* __restrict__ out) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t N = (size_t)n * C;
   if (idx >= N * R) return;
@@ -418,21 +491,18 @@ __global__ void incident_kernel(const double* __restrict__ geom, int n, int C, i
   const double nx[3] = {g[12], g[13], g[14]};
   const double* s = src + 3 * r;
   double2 pv, dp;
-  if (!point) {
-    const double ph = k * dot3(s, x);
-    double sn, cs;
-    sincos(ph, &sn, &cs);
-    pv = make_double2(amp * cs, amp * sn);
-    dp = cmul<double>(make_double2(0.0, k * dot3(s, nx)), pv);
-  } else {
-    const double d[3] = {x[0] - s[0], x[1] - s[1], x[2] - s[2]};
-    const double R = sqrt(dot3(d, d));
-    double sn, cs;
-    sincos(k * R, &sn, &cs);
-    pv = make_double2(amp * cs / R, amp * sn / R);
-    // dp/dn = A e^{ikR} (ikR - 1)/R^2 * (d.n)/R
-    const double f = dot3(d, nx) / (R * R * R);
-    dp = cmul<double>(make_double2(amp * cs * f, amp * sn * f), make_double2(-1.0, k * R));
+  incident_at(x, nx, s, point, k, make_double2(amp, 0.0), pv, dp);
+  if (half) {
+    double2 a = cscale<double>(rp, amp), pi, di;
+    double si[3] = {s[0], s[1], point ? 2.0 * zg - s[2] : -s[2]};
+    if (!point) {
+      double sn, cs;
+      sincos(2.0 * k * zg * s[2], &sn, &cs);
+      a = cmul<double>(a, make_double2(cs, sn));
+    }
+    incident_at(x, nx, si, point, k, a, pi, di);
+    pv = cadd<double>(pv, pi);
+    dp = cadd<double>(dp, di);
   }
   out[idx] = cadd<double>(pv, cmul<double>(alpha, dp));
 }
@@ -614,8 +684,8 @@ static hipError_t plan_build(Plan& P, const std::vector<double>& geo, hipStream_
   {
     const size_t blocks = (ns + 255) / 256;
     hipLaunchKernelGGL(assemble_near_kernel, dim3((unsigned)blocks), dim3(256), 0, s, P.geom, n, P.d_near, P.n_near,
-                       P.pitch[0], P.pitch[1], P.pitch[2], P.k, alpha, hyper, Q, (double2*)P.S[0],
-                       (float2*)P.S[1]);
+                       P.pitch[0], P.pitch[1], P.pitch[2], P.k, alpha, hyper, Q, P.img_near ? 1 : 0, P.zg,
+                       make_double2(P.rp_re, P.rp_im), (double2*)P.S[0], (float2*)P.S[1]);
     FM_CHECK(hipGetLastError());
   }
   // scaling s^n
@@ -660,18 +730,25 @@ static hipError_t plan_build(Plan& P, const std::vector<double>& geo, hipStream_
     if (P.n_far == 0) break;
     // O grid -> FFT -> Lambda
     const int L = 2 * nt, P2 = (L + 1) * (L + 1);
-    double2* Og = nullptr;
+    double2 *Og = nullptr, *Ogi = nullptr;
     if ((err = salloc((void**)&Og, (size_t)P.B * P2 * sizeof(double2))) != hipSuccess) break;
+    if (P.half && (err = salloc((void**)&Ogi, (size_t)P.B * P2 * sizeof(double2))) != hipSuccess) break;
     {
       const int th = P.B * (L + 1);
       int rr[3];
       for (int a = 0; a < 3; ++a) rr[a] = P.grid[a] > 1 ? std::min(P.near_radius[a], P.grid[a] - 1) : 0;
       hipLaunchKernelGGL(ogrid_kernel, dim3((th + 127) / 128), dim3(128), 0, s, P.B, P.fft[0], P.fft[1], P.fft[2],
                          P.grid[0], P.grid[1], P.grid[2], rr[0], rr[1], rr[2], P.pitch[0], P.pitch[1],
-                         P.pitch[2], P.k, L, Og);
+                         P.pitch[2], P.k, L, 0.0, 1, Og);
+      // image translations: target centre minus mirrored source centre, (d0 p0, d1 p1, -2 zg)
+      if (P.half)
+        hipLaunchKernelGGL(ogrid_kernel, dim3((th + 127) / 128), dim3(128), 0, s, P.B, P.fft[0], P.fft[1],
+                           P.fft[2], P.grid[0], P.grid[1], P.grid[2], rr[0], rr[1], rr[2], P.pitch[0], P.pitch[1],
+                           P.pitch[2], P.k, L, -2.0 * P.zg, P.img_near ? 1 : 0, Ogi);
       if ((err = hipGetLastError()) != hipSuccess) break;
     }
     if ((err = grid_dft_launch<double>(Og, P2, P.fft, P.fft, false, false, s)) != hipSuccess) break;
+    if (P.half && (err = grid_dft_launch<double>(Ogi, P2, P.fft, P.fft, false, false, s)) != hipSuccess) break;
     M2LTable T;
     m2l_table(nt, T);
     int *d_ptr = nullptr, *d_oidx = nullptr, *d_nof = nullptr;
@@ -687,14 +764,17 @@ static hipError_t plan_build(Plan& P, const std::vector<double>& geo, hipStream_
     hipMemcpyAsync(d_oidx, T.oidx.data(), T.oidx.size() * sizeof(int), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(d_coef, T.coef.data(), T.coef.size() * sizeof(double2), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(d_nof, nof.data(), p * sizeof(int), hipMemcpyHostToDevice, s);
-    // canonical bins: linear index not above that of the partner bin -w
+    // canonical bins: linear index not above that of the partner bin -w (without the pairing,
+    // every bin is its own canonical bin)
     std::vector<int> canon(P.B), pairs;
     for (int b2 = 0; b2 < P.fft[2]; ++b2)
       for (int b1 = 0; b1 < P.fft[1]; ++b1)
         for (int b0 = 0; b0 < P.fft[0]; ++b0) {
           const int L = b0 + P.fft[0] * (b1 + P.fft[1] * b2);
-          const int Lp = (P.fft[0] - b0) % P.fft[0] +
-                         P.fft[0] * ((P.fft[1] - b1) % P.fft[1] + P.fft[1] * ((P.fft[2] - b2) % P.fft[2]));
+          const int Lp = !P.paired ? L
+                                   : (P.fft[0] - b0) % P.fft[0] +
+                                         P.fft[0] * ((P.fft[1] - b1) % P.fft[1] +
+                                                     P.fft[1] * ((P.fft[2] - b2) % P.fft[2]));
           if (L > Lp) continue;
           canon[L] = canon[Lp] = (int)(pairs.size() / 2);
           pairs.push_back(L);
@@ -711,9 +791,9 @@ static hipError_t plan_build(Plan& P, const std::vector<double>& geo, hipStream_
     if (want32 && (err = plan_alloc(P, &P.Lam[1], nl * sizeof(float2))) != hipSuccess) break;
     {
       const int bx = (int)std::min<size_t>(((size_t)p * p + 255) / 256, 64);
-      hipLaunchKernelGGL(lambda_kernel, dim3(bx, P.Bc), dim3(256), P2 * sizeof(double2), s, Og, P2, p, P.d_pairs,
-                         d_ptr, d_coef, d_oidx, d_sig, d_nof, 1.0 / P.B, ldp, (double2*)P.Lam[0],
-                         (float2*)P.Lam[1]);
+      hipLaunchKernelGGL(lambda_kernel, dim3(bx, P.Bc), dim3(256), (P.half ? 2 : 1) * P2 * sizeof(double2), s, Og,
+                         Ogi, make_double2(P.rp_re, P.rp_im), P2, p, P.d_pairs, d_ptr, d_coef, d_oidx, d_sig, d_nof,
+                         1.0 / P.B, ldp, (double2*)P.Lam[0], (float2*)P.Lam[1]);
       if ((err = hipGetLastError()) != hipSuccess) break;
     }
     // host vectors (T) must outlive the async copies
@@ -747,6 +827,20 @@ extern "C" fmbem_status fmbem_plan_create(const fmbem_cell_mesh* mesh, const fmb
   if (desc->formulation != FMBEM_BURTON_MILLER && desc->formulation != FMBEM_CBIE) return FMBEM_ERR_INVALID_ARG;
   if (desc->precisions & ~3u) return FMBEM_ERR_INVALID_ARG;
   if (desc->dft_schedule < FMBEM_DFT_AUTO || desc->dft_schedule > FMBEM_DFT_FUSED_MFMA) return FMBEM_ERR_INVALID_ARG;
+  if (desc->halfspace != 0 && desc->halfspace != 1) return FMBEM_ERR_INVALID_ARG;
+  if (desc->halfspace == 1) {
+    if (desc->grid[2] != 1 || !std::isfinite(desc->plane_z) || !std::isfinite(desc->reflection_re) ||
+        !std::isfinite(desc->reflection_im))
+      return FMBEM_ERR_INVALID_ARG;
+    // the surface stays on one side of the plane (vertices on it allowed)
+    bool above = true, below = true;
+    for (int v = 0; v < mesh->n_vertices; ++v) {
+      const double z = mesh->vertices[3 * v + 2];
+      above = above && z >= desc->plane_z;
+      below = below && z <= desc->plane_z;
+    }
+    if (!above && !below) return FMBEM_ERR_INVALID_ARG;
+  }
   const int n = mesh->n_triangles;
   // geometry on the host: a, b, c, centroid, unit normal, longest edge, area
   std::vector<double> geo((size_t)n * 18, 0.0);
@@ -835,6 +929,18 @@ extern "C" fmbem_status fmbem_plan_create(const fmbem_cell_mesh* mesh, const fmb
     return FMBEM_ERR_UNSUPPORTED;
   }
   P->n_far = (2 * P->grid[0] - 1) * (2 * P->grid[1] - 1) * (2 * P->grid[2] - 1) - P->n_near;
+  if (desc->halfspace == 1) {
+    // image blocks: near for the near offsets when the mirrored cells lie within the near range
+    // along z (|2 zg| < (r + 1) pitch_z), all through the multipole chain otherwise
+    P->half = true;
+    P->paired = false;
+    P->zg = desc->plane_z;
+    P->rp_re = desc->reflection_re;
+    P->rp_im = desc->reflection_im;
+    P->img_near = std::fabs(2.0 * P->zg) < (P->near_radius[2] + 1) * P->pitch[2];
+    P->n_far_img = (2 * P->grid[0] - 1) * (2 * P->grid[1] - 1) - (P->img_near ? P->n_near : 0);
+    P->n_far += P->n_far_img;
+  }
   // scaling: s = k * (largest distance of a vertex from the cell centre), at most 1
   double rmax = 0.0;
   for (int v = 0; v < mesh->n_vertices; ++v) {
@@ -973,7 +1079,8 @@ static fmbem_status incident(fmbem_plan plan, int32_t R, const double* src, doub
   if (e == hipSuccess) {
     hipLaunchKernelGGL(incident_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, P.geom, P.n, P.C,
                        P.grid[0], P.grid[1], P.pitch[0], P.pitch[1], P.pitch[2], P.k,
-                       make_double2(P.alpha_re, P.alpha_im), R, d_src, point, amp, (double2*)b);
+                       make_double2(P.alpha_re, P.alpha_im), R, d_src, point, amp, P.half ? 1 : 0, P.zg,
+                       make_double2(P.rp_re, P.rp_im), (double2*)b);
     e = hipGetLastError();
   }
   hipError_t e2 = hipStreamSynchronize(s);  // src is host memory owned by the caller

@@ -58,7 +58,8 @@ def _mesh(v, t):
 
 
 @pytest.mark.parametrize("case", ["null", "bad_index", "degenerate", "order", "fft", "k", "grid", "formulation",
-                                  "nan_vertex", "radius", "dft_schedule"])
+                                  "nan_vertex", "radius", "dft_schedule", "halfspace_flag", "halfspace_grid",
+                                  "halfspace_crossing", "halfspace_nan"])
 def test_plan_create_rejects_invalid_arguments(case):
     lib = fm.load()
     v, t = icosphere(1, 0.1)
@@ -87,6 +88,14 @@ def test_plan_create_rejects_invalid_arguments(case):
         desc = _desc(near_radius=(4, 1, 1))
     elif case == "dft_schedule":
         desc = _desc(dft_schedule=5)
+    elif case == "halfspace_flag":
+        desc = _desc(halfspace=2, plane_z=0.2)
+    elif case == "halfspace_grid":        # the plane must be parallel to every periodic axis
+        desc = _desc(halfspace=1, plane_z=0.2, grid=(3, 3, 2))
+    elif case == "halfspace_crossing":    # the sphere of radius 0.1 crosses z = 0.05
+        desc = _desc(halfspace=1, plane_z=0.05, reflection_re=1.0)
+    elif case == "halfspace_nan":
+        desc = _desc(halfspace=1, plane_z=math.nan)
     mesh, keep = _mesh(v, t)
     assert lib.fmbem_plan_create(ct.byref(mesh), ct.byref(desc), None, ct.byref(out)) == 1
     assert out.value is None
