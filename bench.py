@@ -228,6 +228,38 @@ def barrier_sweep(fm, torch, args):
             "field_ms_mean": float(np.mean([r["field_ms"] for r in rows])), "per_frequency": rows}
 
 
+def ground_solves(fm, torch, args):
+    """The 16x16 lattice of the headline above a sound-hard plane 0.05 m below the spheres (image
+    blocks near, R_p = 1), a plane wave travelling down toward it: FP32-refined solves with the
+    half-space Green's function, checked against an FP64 reference solve."""
+    from workloads import config_grid16_ground
+    w = config_grid16_ground()
+    zg, rp = w.extra["plane_z"], w.extra["reflection"]
+    t0 = time.perf_counter()
+    P = fm.Plan.from_workload(w, halfspace=(zg, rp))
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    b = P.incident_plane_wave(w.plane_waves)
+    xr = P.solve(b, tol=1e-12, inner="fp64", ortho=args.ortho, max_iters=2000)[0]
+    sv = fm.Solver(P, 1, tol=args.tol, inner="fp32", ortho=args.ortho)
+    x, info = sv.run(b)
+    torch.cuda.synchronize()
+    reps = max(1, args.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        x, info = sv.run(b)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    err = torch.linalg.vector_norm(x - xr).item() / torch.linalg.vector_norm(xr).item()
+    out = {"workload": "16x16 lattice of 1280-triangle spheres above a sound-hard plane z = -0.15 m (R_p = 1), "
+                       "1 kHz, n_t = 10, plane wave 30 deg down", "solves_per_s": 1.0 / dt, "ms": dt * 1e3,
+           "iterations": info[0], "solution_error_vs_fp64": err, "plan_build_s": build_s,
+           "resident_mib": P.info["resident_bytes"] / 2 ** 20}
+    sv.close()
+    P.close()
+    return out
+
+
 def serving(fm, torch, args, mode, rate):
     """Continuous-batching engine under seeded Poisson arrivals: lattices n1 x n2 (n1 ~ U{4..64},
     n2 ~ U{1..16}) of 320-triangle spheres, f ~ U[200, 2000] Hz (n_t = 10 up to 1.2 kHz, else 12),
@@ -328,6 +360,7 @@ def main():
     ap.add_argument("--grid", type=int, nargs=2, default=(16, 16))
     ap.add_argument("--batch-rhs", type=int, default=64, help="plane waves per lattice of the batched-grids run")
     ap.add_argument("--no-batched-grids", action="store_true")
+    ap.add_argument("--no-ground", action="store_true", help="skip the half-space 16x16 solves")
     ap.add_argument("--serving-requests", type=int, default=100, help="measured requests of the serving run")
     ap.add_argument("--serving-warmup", type=int, default=10)
     ap.add_argument("--serving-rates", type=float, nargs="*", default=[20.0, 8.0],
@@ -486,6 +519,9 @@ def main():
     if not args.no_batched_grids:
         out["batched_grids"] = batched_grids(fm, torch, args)
         print(f"[bench] batched grids {out['batched_grids']}", file=sys.stderr, flush=True)
+    if not args.no_ground:
+        out["halfspace_grid16"] = ground_solves(fm, torch, args)
+        print(f"[bench] half-space 16x16 {out['halfspace_grid16']}", file=sys.stderr, flush=True)
     if args.barrier_freqs > 0:
         out["barrier_sweep"] = barrier_sweep(fm, torch, args)
         print(f"[bench] barrier sweep {out['barrier_sweep']['frequencies_per_s']:.2f} frequencies/s",

@@ -97,6 +97,16 @@ def config_grid16(grid=(16, 16, 1), level: int = 3, order: int = 10) -> Workload
                     plane_waves=np.array([[math.cos(a), math.sin(a), 0.0]]))
 
 
+def config_grid16_ground(plane_z: float = -0.15, reflection: complex = 1.0) -> Workload:
+    """The 16x16 sphere lattice above a plane z = plane_z (sound-hard for reflection 1), one
+    plane wave at 30 degrees azimuth travelling 30 degrees downwards, toward the plane."""
+    w = config_grid16()
+    a, e = math.radians(30.0), math.radians(30.0)
+    d = np.array([[math.cos(e) * math.cos(a), math.cos(e) * math.sin(a), -math.sin(e)]])
+    return w.with_(name="grid16x16_l3_1kHz_ground", plane_waves=d,
+                   extra={"plane_z": plane_z, "reflection": reflection})
+
+
 BATCHED_GRIDS = ((8, 8, 1), (12, 20, 1), (32, 4, 1))
 BATCHED_SEEDS = (2201120503, 2201120504, 2201120505)
 
