@@ -106,3 +106,27 @@ def test_halfspace_field(cases):
     got = P.field(torch.from_numpy(x).cuda(), pts).cpu().numpy()
     ref = hs.field(v, t, lat, k, pts, x.reshape(2, -1), zg, rp)
     assert rel(got, ref) < 1e-12
+
+
+def test_tubes_standing_on_the_plane():
+    # open tube segments whose lower rim lies on a sound-hard plane (the barrier setting of
+    # Sec. 4.2 with one layer of cells): image elements touch their originals along the rim
+    import paper_2201_12050_amd as fm
+    from workloads import tube_segment
+    v, t = tube_segment(0.08, 0.25, 32, 3)
+    lat = Lattice((3, 2, 1), (0.2, 0.2, 0.25))
+    k = 2 * np.pi * 800.0 / 343.0
+    zg = float(v[:, 2].min())
+    H = hs.FMPBEMHalfSpace(v, t, lat, k, 6, -1j / k, zg, 1.0)
+    P = fm.Plan(v, t, lat.grid, lat.pitch, k, 6, halfspace=(zg, 1.0))
+    x = random_complex((2, lat.n_cells, t.shape[0]), 77)
+    xd = torch.from_numpy(x).cuda()
+    ref = H.matvec(x)
+    assert rel(P.matvec(xd, precision="fp64").cpu().numpy(), ref) < 1e-12
+    assert rel(P.matvec(xd.to(torch.complex64), precision="fp32").cpu().numpy(), ref) < 1e-5
+    src = np.array([[0.2, -1.5, 0.4]])
+    b = P.incident_point_source(src)
+    assert rel(b.cpu().numpy().ravel(), hs.rhs_point_source(v, t, lat, k, -1j / k, src, zg, 1.0)[0]) < 1e-12
+    xs, info = P.solve(b, tol=1e-10, inner="fp32")
+    assert rel(xs.cpu().numpy().ravel(), solve.lu_solve(H.dense(), b.cpu().numpy().ravel())) < 1e-6
+    P.close()
