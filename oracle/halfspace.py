@@ -8,20 +8,23 @@ image part the source element is the mirrored element, whose outward normal is
 the mirrored normal, so d/dn_y G(x, y^) is the normal derivative at the image
 point along the mirrored normal (and alpha d2/dn_x dn_y likewise for eq. (bm)).
 
-Reading (Sec. 3.4, first case): the plane is parallel to every periodic direction,
-i.e. the lattice has one layer of cells along z (grid[2] == 1) and the plane is
-z = z_g.  The image part is then block Toeplitz like the direct part: the image
-of source cell j sits at the mirrored centre, and the block of target cell i and
-source cell j depends on d = i - j only, through the image offset
-    t^_d = (d1 p1, d2 p2, -2 z_g).
-Near / far for the image part (eq. (admissibilityMirror)), in the same Chebyshev
-reading as the direct part: the image block is near when |d1| <= r1, |d2| <= r2
-and |2 z_g| < (r3 + 1) p3 (r = near radius, p = pitch); otherwise it is applied
-through the multipole chain.  The multipole moments of a mirrored cell about its
-mirrored centre are D_z V0 x with D_z = diag((-1)^(n+m)) (a reflection in z maps
-theta to pi - theta, and Y_n^m to (-1)^(n+m) Y_n^m), so the far image block is
-U0 K(t^_d) D_z V0 (Appendix A, eq. (greenFMMhalfspace); U and V are shared by
-both parts).  The surface must not cross the plane.
+Readings (Sec. 3.4).  The plane is z = z_g, normal to the third lattice axis.
+  * First case, the plane parallel to every periodic direction (grid[2] == 1): the image part is
+    block Toeplitz like the direct part; the block of target cell i and source cell j depends
+    on d = i - j through the image offset t^_d = (d1 p1, d2 p2, -2 z_g).
+  * Second case, periodicity along z (grid[2] > 1): the image of source cell j sits at
+    z = 2 z_g - j3 p3, so the block depends on (d1, d2, s = i3 + j3) (block Hankel along z),
+    t^ = (d1 p1, d2 p2, s p3 - 2 z_g).  Reversing the source cells along z (P x, cell index
+    M3 - 1 - j3) turns it into a Toeplitz product in e = i3 - (M3 - 1 - j3) = s - (M3 - 1), the
+    column permutation of Sec. 2.3 and Sec. 3.5.
+Near / far for the image part (eq. (admissibilityMirror)), in the Chebyshev reading of the
+direct part: an image block is near when |d1| <= r1, |d2| <= r2 and its z offset
+|s p3 - 2 z_g| < (r3 + 1) p3 (r = near radius, p = pitch; s = 0 in the first case);
+otherwise it is applied through the multipole chain.  The multipole moments of a mirrored
+cell about its mirrored centre are D_z V0 x with D_z = diag((-1)^(n+m)) (a reflection in z
+maps theta to pi - theta, and Y_n^m to (-1)^(n+m) Y_n^m), so the far image block is
+U0 K(t^) D_z V0 (Appendix A, eq. (greenFMMhalfspace); U and V are shared by both parts).
+The surface of the whole lattice must not cross the plane.
 
 Incident fields in the half-space are the free field plus R_p times its mirror
 image: a point source s gets the image source s^, a plane wave A e^{ik d.x} gets
@@ -87,31 +90,51 @@ def cross_block(tgeom, sgeom, k, alpha, target_shift, source_shift, chunk: int =
 
 def check_side(vertices, lattice, zg):
     z = np.asarray(vertices)[:, 2]
-    if lattice.grid[2] != 1:
-        raise ValueError("the plane must be parallel to every periodic direction (grid[2] == 1)")
-    if not (np.all(z >= zg) or np.all(z <= zg)):
+    lo = z.min()
+    hi = z.max() + (lattice.grid[2] - 1) * lattice.pitch[2]
+    if not (lo >= zg or hi <= zg):
         raise ValueError("the surface crosses the plane")
 
 
+def all_offsets(grid):
+    """Image offsets (d1, d2, s): d = target - source in x, y; s = target + source along z."""
+    return [(d1, d2, s) for s in range(0, 2 * grid[2] - 1) for d2 in range(-(grid[1] - 1), grid[1])
+            for d1 in range(-(grid[0] - 1), grid[0])]
+
+
 def image_near_offsets(grid, pitch, zg, near_radius=(1, 1, 1)):
-    if abs(2.0 * zg) >= (near_radius[2] + 1) * pitch[2]:
-        return []
     r1 = min(near_radius[0], grid[0] - 1)
     r2 = min(near_radius[1], grid[1] - 1)
-    return [(d1, d2, 0) for d2 in range(-r2, r2 + 1) for d1 in range(-r1, r1 + 1)]
+    return [o for o in all_offsets(grid)
+            if abs(o[0]) <= r1 and abs(o[1]) <= r2 and abs(o[2] * pitch[2] - 2.0 * zg) < (near_radius[2] + 1) * pitch[2]]
 
 
-def all_offsets(grid):
-    return [(d1, d2, 0) for d2 in range(-(grid[1] - 1), grid[1]) for d1 in range(-(grid[0] - 1), grid[0])]
+def image_offset_vector(o, pitch, zg):
+    return np.array([o[0] * pitch[0], o[1] * pitch[1], o[2] * pitch[2] - 2.0 * zg])
 
 
 def image_blocks(vertices, triangles, lattice, k, alpha, zg, offsets):
-    """Image blocks for the listed offsets d (target cell minus source cell), in cell-local
-    coordinates: target at the origin, mirrored source cell shifted by -d*pitch in x, y."""
+    """Image blocks for the listed offsets (d1, d2, s), in the target cell's local coordinates:
+    the source cell shifted by (-d1 p1, -d2 p2) and by s p3 along z relative to the target's
+    lattice position (source z + target z = s p3), then mirrored in the plane z = z_g."""
     geom = bem.element_geometry(vertices, triangles)
-    mgeom = mirrored_geometry(vertices, triangles, zg)
     pitch = np.asarray(lattice.pitch)
-    return {d: cross_block(geom, mgeom, k, alpha, np.zeros(3), -np.asarray(d) * pitch) for d in offsets}
+    out = {}
+    for o in offsets:
+        shift = np.array([-o[0] * pitch[0], -o[1] * pitch[1], o[2] * pitch[2]])
+        mgeom = mirrored_geometry(np.asarray(vertices) + shift, triangles, zg)
+        out[o] = cross_block(geom, mgeom, k, alpha, np.zeros(3), np.zeros(3))
+    return out
+
+
+def image_pairs(grid, o):
+    """(target cells, source cells) with target - source = (d1, d2) and target + source = s."""
+    g = grid_coords(grid)
+    src = np.stack([g[:, 0] - o[0], g[:, 1] - o[1], o[2] - g[:, 2]], 1)
+    ok = np.all((src >= 0) & (src < np.asarray(grid)[None, :]), axis=1)
+    tgt = np.nonzero(ok)[0]
+    s = src[ok]
+    return tgt, s[:, 0] + grid[0] * (s[:, 1] + grid[1] * s[:, 2])
 
 
 def dense_exact(vertices, triangles, lattice, k, alpha, zg, rp):
@@ -125,15 +148,15 @@ def dense_exact(vertices, triangles, lattice, k, alpha, zg, rp):
         oi = lattice.cell_origin(i)
         for j in range(C):
             oj = lattice.cell_origin(j)
-            # the mirror of cell j's elements: mirror the shifted vertices (z shifts are zero)
+            # the mirror of cell j's elements
             mgeom = mirrored_geometry(np.asarray(vertices) + oj, triangles, zg)
             A[i * n:(i + 1) * n, j * n:(j + 1) * n] += rp * cross_block(geom, mgeom, k, alpha, oi, np.zeros(3))
     return A
 
 
 class FMPBEMHalfSpace(FMPBEM):
-    """The FMPBEM operator of eq. (2dPeriodicFMM_halfspace) for the first case of Sec. 3.4:
-    (S + U K V) + R_p (S^ + U K^ D_z V), blocks by offset d."""
+    """The FMPBEM operator of eq. (2dPeriodicFMM_halfspace): (S + U K V) + R_p (S^ + U K^ D_z V),
+    the image blocks keyed by (d1, d2, s) (both cases of Sec. 3.4)."""
 
     def __init__(self, vertices, triangles, lattice, k, order, alpha, zg, rp, near_radius=(1, 1, 1)):
         check_side(vertices, lattice, zg)
@@ -146,40 +169,40 @@ class FMPBEMHalfSpace(FMPBEM):
         self.img_far = [d for d in all_offsets(self.grid) if d not in set(self.img_near)]
         D = dz_signs(order)
         if self.img_far:
-            t = np.asarray(self.img_far, dtype=np.float64) * pitch[None, :]
-            t[:, 2] = -2.0 * zg
+            t = np.array([image_offset_vector(o, pitch, zg) for o in self.img_far])
             Ks = fmm.m2l(t, k, order) * D[None, None, :]
         else:
             Ks = np.zeros((0, self.p, self.p), dtype=np.complex128)
-        self.Kimg = {d: Ks[i] for i, d in enumerate(self.img_far)}
-        for d in self.img_near + self.img_far:
-            if d not in self._pairs:
-                self._pairs[d] = pairs(self.grid, d)
+        self.Kimg = {o: Ks[i] for i, o in enumerate(self.img_far)}
+        self._ipairs = {o: image_pairs(self.grid, o) for o in self.img_near + self.img_far}
+
+    def image_key(self, i, j):
+        g = grid_coords(self.grid)
+        return (int(g[i][0] - g[j][0]), int(g[i][1] - g[j][1]), int(g[i][2] + g[j][2]))
 
     def near_apply(self, x):
         y = super().near_apply(x)
-        for d in self.img_near:
-            t, s = self._pairs[d]
-            y[:, t, :] += self.rp * (x[:, s, :] @ self.Simg[d].T)
+        for o in self.img_near:
+            t, s = self._ipairs[o]
+            y[:, t, :] += self.rp * (x[:, s, :] @ self.Simg[o].T)
         return y
 
     def far_apply(self, x):
         y = super().far_apply(x)
         m = x @ self.V0.T
         loc = np.zeros(m.shape, dtype=np.complex128)
-        for d in self.img_far:
-            t, s = self._pairs[d]
-            loc[:, t, :] += m[:, s, :] @ self.Kimg[d].T
+        for o in self.img_far:
+            t, s = self._ipairs[o]
+            loc[:, t, :] += m[:, s, :] @ self.Kimg[o].T
         return y + self.rp * (loc @ self.U0.T)
 
     def dense(self):
         A = super().dense()
         C, n = self.n_cells, self.n
-        g = grid_coords(self.grid)
         for i in range(C):
             for j in range(C):
-                d = tuple(int(v) for v in (g[i] - g[j]))
-                blk = self.Simg[d] if d in self.Simg else self.U0 @ self.Kimg[d] @ self.V0
+                o = self.image_key(i, j)
+                blk = self.Simg[o] if o in self.Simg else self.U0 @ self.Kimg[o] @ self.V0
                 A[i * n:(i + 1) * n, j * n:(j + 1) * n] += self.rp * blk
         return A
 
@@ -218,8 +241,12 @@ def field(vertices, triangles, lattice, k, points, p_surface, zg, rp, p_inc=None
     (eq. (cbie) with c = 1 and the half-space Green's function)."""
     ps = np.atleast_2d(np.asarray(p_surface, dtype=np.complex128))
     W = bem.field_weights(vertices, triangles, lattice, k, points)
-    # mirrored lattice surface: mirror each cell's shifted vertices (z shifts are zero), reversed order
-    Wm = bem.field_weights(mirror_points(vertices, zg), np.asarray(triangles)[:, [0, 2, 1]], lattice, k, points)
+    # mirrored lattice surface: each cell's shifted vertices mirrored, order (a, c, b)
+    from workloads import Lattice
+    one = Lattice((1, 1, 1), lattice.pitch)
+    tm = np.asarray(triangles)[:, [0, 2, 1]]
+    Wm = np.concatenate([bem.field_weights(mirror_points(np.asarray(vertices) + lattice.cell_origin(c), zg), tm,
+                                           one, k, points) for c in range(lattice.n_cells)], axis=1)
     out = -(ps @ (W + rp * Wm).T)
     if p_inc is not None:
         out = out + np.atleast_2d(p_inc)

@@ -97,3 +97,41 @@ def test_surface_must_not_cross_plane():
         hs.dense_exact(v, t, LAT1, 3.0, 0.0, 0.05, 1.0)
     with pytest.raises(ValueError):
         hs.FMPBEMHalfSpace(v, t, Lattice((2, 2, 2), (0.3, 0.3, 0.3)), 3.0, 4, 0.0, 0.2, 1.0)
+
+
+@pytest.mark.parametrize("rp", [1.0, -1.0])
+def test_method_of_images_periodic_normal_to_plane(rp):
+    # second case of Sec. 3.4: two spheres stacked along z (pitch 0.3) above the plane z = -0.15;
+    # with their two images this is a 1 x 1 x 4 full-space lattice, shifted up by 0.6 so that its
+    # cells sit at z = 0, 0.3 (images) and 0.6, 0.9 (the originals)
+    v, t = icosphere(1, 0.1)
+    k = 2 * np.pi * 500.0 / 343.0
+    a = bem.default_alpha(k, "bm")
+    zg = -0.15
+    lat = Lattice((1, 1, 2), (0.3, 0.3, 0.3))
+    src = np.array([[0.5, -0.4, 0.2]])
+    xh = solve.lu_solve(hs.dense_exact(v, t, lat, k, a, zg, rp), hs.rhs_point_source(v, t, lat, k, a, src, zg, rp)[0])
+    lat4 = Lattice((1, 1, 4), (0.3, 0.3, 0.3))
+    up = np.array([[0.0, 0.0, 0.6]])
+    img = src.copy()
+    img[:, 2] = 2 * zg - img[:, 2]
+    b = (bem.rhs_point_source(v, t, lat4, k, a, src + up)[0] +
+         bem.rhs_point_source(v, t, lat4, k, a, img + up, rp)[0])
+    xf = solve.lu_solve(bem.dense_exact(v, t, lat4, k, a), b)
+    n = t.shape[0]
+    assert np.linalg.norm(xh - xf[2 * n:]) < 1e-8 * np.linalg.norm(xf[2 * n:])
+
+
+def test_multipole_image_converges_to_dense_periodic_normal_to_plane():
+    # 3 x 1 x 3 lattice standing on the plane: image blocks near for the lowest layer only
+    v, t = icosphere(1, 0.1)
+    lat = Lattice((3, 1, 3), (0.3, 0.3, 0.3))
+    k = 2 * np.pi * 500.0 / 343.0
+    zg = -0.15
+    A1 = hs.dense_exact(v, t, lat, k, -1j / k, zg, 0.8 + 0.2j)
+    errs = []
+    for nt in (4, 8):
+        H = hs.FMPBEMHalfSpace(v, t, lat, k, nt, -1j / k, zg, 0.8 + 0.2j)
+        assert sorted({o[2] for o in H.img_near}) == [0]
+        errs.append(np.linalg.norm(H.dense() - A1) / np.linalg.norm(A1))
+    assert errs[0] < 1e-4 and errs[1] < errs[0] / 100
