@@ -87,11 +87,17 @@ struct Plan {
   void* dftF[2][6] = {};
   int dft_forced = -1;       // DFT schedule forced by the plan descriptor (0 axes, 1 fused, 2 GEMM, 3 fused
                              // on the matrix cores), -1: tuned
-  // half-space: image term R_p G(x, y^) with y^ mirrored in z = zg (grid[2] == 1)
-  bool half = false;
+  // half-space: image term R_p G(x, y^) with y^ mirrored in z = zg.  half: the incident fields
+  // and the field evaluation carry the image; fold (plane parallel to every periodic axis,
+  // grid[2] == 1): the image blocks are added to this plan's S and Lambda; otherwise (periodic
+  // along z) the image part, block Hankel along z, is the sub-plan img applied to the input
+  // reversed along z (Sec. 2.3, Sec. 3.5: the column permutation P)
+  bool half = false, fold = false;
   double zg = 0.0, rp_re = 0.0, rp_im = 0.0;
-  bool img_near = false;     // the image blocks of the near offsets are near blocks too
-  int n_far_img = 0;         // image offsets applied through the multipole chain
+  bool img_near = false;     // fold: the image blocks of the near offsets are near blocks too
+  int n_far_img = 0;         // fold: image offsets applied through the multipole chain
+  struct Plan* img = nullptr;        // image sub-plan (owned), periodic along z
+  const struct Plan* parent = nullptr;  // set in an image sub-plan: geometry, V0, U0, DFT matrices shared
   // the canonical-bin pairing Lambda(-w) = D Lambda(w) D holds (off in the half-space, whose
   // image part pairs differently): when off every bin is stored and the DFT applies no D
   bool paired = true;

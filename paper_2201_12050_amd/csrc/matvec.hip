@@ -20,9 +20,20 @@ namespace fmbem {
 
 static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
-size_t matvec_workspace_bytes_per_rhs(const Plan& P, int precision) {
+static size_t direct_ws_per_rhs(const Plan& P, int precision) {
   const size_t el = precision == FMBEM_FP64 ? 16 : 8;
   return 2 * align256((size_t)P.B * P.p * el) + align256((size_t)P.n_near * P.C * P.n * el);
+}
+
+// workspace per RHS: the plan's own; with an image sub-plan (half-space periodic along z) also
+// the input reversed along z, the image part's output and the sub-plan's workspace
+size_t matvec_workspace_bytes_per_rhs(const Plan& P, int precision) {
+  size_t b = direct_ws_per_rhs(P, precision);
+  if (P.img) {
+    const size_t el = precision == FMBEM_FP64 ? 16 : 8;
+    b += 2 * align256((size_t)P.C * P.n * el) + direct_ws_per_rhs(*P.img, precision);
+  }
+  return b;
 }
 
 static hipEvent_t prof_record(const Plan& P, hipStream_t s) {
@@ -395,17 +406,81 @@ static hipError_t matvec_group_t(const std::vector<GroupApply>& g, hipStream_t s
   return near_launch<T>(l2t, s, shape, 1);
 }
 
+// xr[r][i0, i1, M2 - 1 - i2][:] = x[r][i0, i1, i2][:] (cells reversed along z)
+template <typename T>
+__global__ void reverse_z_kernel(const cplx<T>* __restrict__ x, cplx<T>* __restrict__ xr, int n, int M0, int M1,
+                                 int M2, size_t total) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const size_t cellsz = (size_t)n;
+  const size_t rc = idx / cellsz, i = idx - rc * cellsz;
+  const int C = M0 * M1 * M2;
+  const size_t r = rc / C;
+  const int c = (int)(rc - r * C);
+  const int i2 = c / (M0 * M1), rest = c - i2 * M0 * M1;
+  const int cr = rest + M0 * M1 * (M2 - 1 - i2);
+  xr[(r * C + cr) * cellsz + i] = x[idx];
+}
+
+// y += a (T), or y64 += a when y64 is set
+template <typename T>
+__global__ void add_kernel(cplx<T>* __restrict__ y, double2* __restrict__ y64, const cplx<T>* __restrict__ a,
+                           size_t total) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const cplx<T> v = a[idx];
+  if (y64) {
+    y64[idx].x += (double)v.x;
+    y64[idx].y += (double)v.y;
+  } else {
+    y[idx] = cadd<T>(y[idx], v);
+  }
+}
+
+// the image part of a half-space plan periodic along z: y (or y64) += A_img (P x), the sub-plan
+// applied to the input reversed along z; its buffers follow the plan's own workspace
+template <typename T>
+static hipError_t image_apply(const Plan& P, int R, const void* x, void* y, void* ws, hipStream_t s, void* y64,
+                              bool tune) {
+  const int prec = sizeof(T) == 8 ? FMBEM_FP64 : FMBEM_FP32;
+  const size_t el = sizeof(cplx<T>);
+  const size_t N = (size_t)P.C * P.n;
+  char* base = reinterpret_cast<char*>(ws) + (size_t)R * direct_ws_per_rhs(P, prec);
+  cplx<T>* xr = reinterpret_cast<cplx<T>*>(base);
+  cplx<T>* yi = reinterpret_cast<cplx<T>*>(base + (size_t)R * align256(N * el));
+  void* wsi = base + 2 * (size_t)R * align256(N * el);
+  const size_t total = (size_t)R * N;
+  const unsigned blocks = (unsigned)((total + 255) / 256);
+  hipLaunchKernelGGL(reverse_z_kernel<T>, dim3(blocks), dim3(256), 0, s, reinterpret_cast<const cplx<T>*>(x), xr,
+                     P.n, P.grid[0], P.grid[1], P.grid[2], total);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = matvec_t<T>(*P.img, R, xr, yi, wsi, s, nullptr, tune)) != hipSuccess) return e;
+  hipLaunchKernelGGL(add_kernel<T>, dim3(blocks), dim3(256), 0, s, reinterpret_cast<cplx<T>*>(y),
+                     reinterpret_cast<double2*>(y64), yi, total);
+  return hipGetLastError();
+}
+
 hipError_t matvec_group(int precision, const std::vector<GroupApply>& g, hipStream_t s, bool tune) {
   if (g.empty()) return hipSuccess;
   if (g.size() == 1)
     return matvec_launch(*g[0].P, precision, g[0].R, g[0].x, g[0].y, g[0].ws, s, g[0].y64, tune);
-  return precision == FMBEM_FP64 ? matvec_group_t<double>(g, s, tune) : matvec_group_t<float>(g, s, tune);
+  hipError_t e = precision == FMBEM_FP64 ? matvec_group_t<double>(g, s, tune) : matvec_group_t<float>(g, s, tune);
+  for (const GroupApply& a : g) {
+    if (e != hipSuccess || !a.P->img) continue;
+    e = precision == FMBEM_FP64 ? image_apply<double>(*a.P, a.R, a.x, a.y, a.ws, s, nullptr, tune)
+                                : image_apply<float>(*a.P, a.R, a.x, a.y, a.ws, s, a.y64, tune);
+  }
+  return e;
 }
 
 hipError_t matvec_launch(const Plan& P, int precision, int R, const void* x, void* y, void* ws, hipStream_t s,
                          void* y64, bool tune) {
-  return precision == FMBEM_FP64 ? matvec_t<double>(P, R, x, y, ws, s, nullptr, tune)
-                                 : matvec_t<float>(P, R, x, y, ws, s, y64, tune);
+  hipError_t e = precision == FMBEM_FP64 ? matvec_t<double>(P, R, x, y, ws, s, nullptr, tune)
+                                         : matvec_t<float>(P, R, x, y, ws, s, y64, tune);
+  if (e != hipSuccess || !P.img) return e;
+  return precision == FMBEM_FP64 ? image_apply<double>(P, R, x, y, ws, s, nullptr, tune)
+                                 : image_apply<float>(P, R, x, y, ws, s, y64, tune);
 }
 
 }  // namespace fmbem

@@ -157,12 +157,16 @@ __device__ inline double2 elem_integral(const double* x, const double* nx, const
   return make_double2(re, im);
 }
 
-// one entry S_d[i][j] per thread; entries ordered (d, i, j) with j fastest.  In the half-space
-// (img != 0) every near block also holds R_p times its image block: the source element of the
-// shifted cell mirrored in z = zg, vertices (a, c, b) so that its normal is the mirrored normal.
+// one entry S_d[i][j] per thread; entries ordered (d, i, j) with j fastest.  Half-space:
+// img = 1 (plane parallel to the periodic axes) adds R_p times the image block to every near
+// block: the source element of the shifted cell mirrored in z = zg, vertices (a, c, b) so that
+// its normal is the mirrored normal; img = 2 (the image sub-plan of a lattice periodic along z)
+// holds the image block alone, for offset (d0, d1, e) the source cell shifted by (e + zbase) p2
+// along z before the mirroring (zbase = M3 - 1: e indexes the input reversed along z).
 __global__ void assemble_near_kernel(const double* __restrict__ geom, int n, const int* __restrict__ offs, int n_near,
                             double p0, double p1, double p2, double k, double2 alpha, int hyper, QuadTab Q,
-                            int img, double zg, double2 rp, double2* __restrict__ S64, float2* __restrict__ S32) {
+                            int img, int zbase, double zg, double2 rp, double2* __restrict__ S64,
+                            float2* __restrict__ S32) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t nn = (size_t)n * n;
   if (idx >= nn * n_near) return;
@@ -174,8 +178,10 @@ __global__ void assemble_near_kernel(const double* __restrict__ geom, int n, con
   const double sh[3] = {-o0 * p0, -o1 * p1, -o2 * p2};
   const Geo ex = load_geo(geom, i);
   const Geo ey = load_geo(geom, j);
-  double2 val;
-  if (o0 == 0 && o1 == 0 && o2 == 0 && i == j) {
+  double2 val = make_double2(0.0, 0.0);
+  if (img == 2) {
+    // image block only
+  } else if (o0 == 0 && o1 == 0 && o2 == 0 && i == j) {
     val = make_double2(0.5, 0.0);
     if (hyper) val = cadd<double>(val, cmul<double>(alpha, hyper_self(ex, k, Q)));
   } else {
@@ -191,9 +197,10 @@ __global__ void assemble_near_kernel(const double* __restrict__ geom, int n, con
   }
   if (img) {
     // mirrored element (a, c, b): z -> 2 zg - z after the lattice shift
-    double a[3] = {ey.a[0] + sh[0], ey.a[1] + sh[1], 2.0 * zg - (ey.a[2] + sh[2])};
-    double c[3] = {ey.c[0] + sh[0], ey.c[1] + sh[1], 2.0 * zg - (ey.c[2] + sh[2])};
-    double b[3] = {ey.b[0] + sh[0], ey.b[1] + sh[1], 2.0 * zg - (ey.b[2] + sh[2])};
+    const double shz = img == 2 ? (o2 + zbase) * p2 : sh[2];
+    double a[3] = {ey.a[0] + sh[0], ey.a[1] + sh[1], 2.0 * zg - (ey.a[2] + shz)};
+    double c[3] = {ey.c[0] + sh[0], ey.c[1] + sh[1], 2.0 * zg - (ey.c[2] + shz)};
+    double b[3] = {ey.b[0] + sh[0], ey.b[1] + sh[1], 2.0 * zg - (ey.b[2] + shz)};
     // the mirrored triangle (a, c, b): edges c - a and b - c, Jacobian from b - a
     double ca[3], bc[3], ba[3];
     for (int t = 0; t < 3; ++t) {
@@ -201,7 +208,7 @@ __global__ void assemble_near_kernel(const double* __restrict__ geom, int n, con
       bc[t] = b[t] - c[t];
       ba[t] = b[t] - a[t];
     }
-    const double cen[3] = {ey.cen[0] + sh[0], ey.cen[1] + sh[1], 2.0 * zg - (ey.cen[2] + sh[2])};
+    const double cen[3] = {ey.cen[0] + sh[0], ey.cen[1] + sh[1], 2.0 * zg - (ey.cen[2] + shz)};
     const double ny[3] = {ey.nrm[0], ey.nrm[1], -ey.nrm[2]};
     const double2 w = elem_integral(ex.cen, ex.nrm, a, ca, bc, ba, cen, ey.longest, ny, k, alpha, hyper, Q);
     val = cadd<double>(val, cmul<double>(rp, w));
@@ -338,11 +345,14 @@ __global__ void l2p_kernel(const double* __restrict__ geom, int n, int nt, doubl
 
 // O_l^mu(d * pitch) on the circulant grid, zero at near offsets and padding gaps.
 // one thread per (bin, mu >= 0); output [bin][(2nt+1)^2]
-// zoff is added to the z component of every offset (the image offsets of the half-space);
-// mask_near = 0 keeps the near offsets too (image blocks that are all far)
+// the z component of offset d is (d2 + zbase) p2 - zsub (zbase = zsub = 0 for the direct part; the
+// image offsets of the half-space shift it, computed in the same order as the host's near list);
+// mask_near: 1 zeroes the near offsets (Chebyshev radius r per axis), 0 keeps them all (image
+// blocks that are all far), 2 zeroes those with |d0| <= r0, |d1| <= r1 and |z offset| <
+// (r2 + 1) p2 (the image blocks of a lattice periodic along z)
 __global__ void ogrid_kernel(int B, int N0, int N1, int N2, int M0, int M1, int M2, int r0, int r1, int r2,
-                             double p0, double p1, double p2, double k, int L, double zoff, int mask_near,
-                             double2* __restrict__ O) {
+                             double p0, double p1, double p2, double k, int L, int zbase, double zsub,
+                             int mask_near, double2* __restrict__ O) {
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= B * (L + 1)) return;
   const int bin = tid / (L + 1);
@@ -358,7 +368,11 @@ __global__ void ogrid_kernel(int B, int N0, int N1, int N2, int M0, int M1, int 
   };
   bool g0, g1, g2;
   const int d0 = off(b0, N0, M0, g0), d1 = off(b1, N1, M1, g1), d2 = off(b2, N2, M2, g2);
-  const bool near = mask_near && (abs(d0) <= r0 && abs(d1) <= r1 && abs(d2) <= r2);
+  // product and difference rounded separately, as on the host (no fused multiply-add), so that
+  // the near / far decision at |z| = (r2 + 1) p2 agrees with the near list
+  const double D[3] = {d0 * p0, d1 * p1, __dsub_rn(__dmul_rn((double)(d2 + zbase), p2), zsub)};
+  const bool near = mask_near == 2 ? (abs(d0) <= r0 && abs(d1) <= r1 && fabs(D[2]) < (r2 + 1) * p2)
+                                   : mask_near && (abs(d0) <= r0 && abs(d1) <= r1 && abs(d2) <= r2);
   double2* out = O + (size_t)bin * P2;
   if (g0 || g1 || g2 || near) {
     for (int l = mu; l <= L; ++l) {
@@ -367,7 +381,6 @@ __global__ void ogrid_kernel(int B, int N0, int N1, int N2, int M0, int M1, int 
     }
     return;
   }
-  const double D[3] = {d0 * p0, d1 * p1, d2 * p2 + zoff};
   const double rho2 = D[0] * D[0] + D[1] * D[1];
   const double r = sqrt(rho2 + D[2] * D[2]);
   const double rho = sqrt(rho2);
@@ -405,7 +418,7 @@ __global__ void lambda_kernel(const double2* __restrict__ Oh, const double2* __r
   const int slot = blockIdx.y;
   const int bin = pairs[2 * slot];
   for (int t = threadIdx.x; t < P2; t += blockDim.x) {
-    so[t] = Oh[(size_t)bin * P2 + t];
+    so[t] = Oh ? Oh[(size_t)bin * P2 + t] : make_double2(0.0, 0.0);
     if (Ohi) soi[t] = Ohi[(size_t)bin * P2 + t];
   }
   __syncthreads();
@@ -592,6 +605,10 @@ static void m2l_table(int nt, M2LTable& T) {
 
 void plan_release(Plan* P) {
   if (!P) return;
+  if (P->img) {
+    plan_release(P->img);
+    P->img = nullptr;
+  }
   int cur = 0;
   hipGetDevice(&cur);
   hipSetDevice(P->device);
@@ -614,9 +631,13 @@ void plan_release(Plan* P) {
 
 static hipError_t plan_build(Plan& P, const std::vector<double>& geo, hipStream_t s) {
   const int n = P.n;
-  // geometry
-  FM_CHECK(plan_alloc(P, (void**)&P.geom, geo.size() * sizeof(double)));
-  FM_CHECK(hipMemcpyAsync(P.geom, geo.data(), geo.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  // geometry (an image sub-plan shares its parent's)
+  if (P.parent) {
+    P.geom = P.parent->geom;
+  } else {
+    FM_CHECK(plan_alloc(P, (void**)&P.geom, geo.size() * sizeof(double)));
+    FM_CHECK(hipMemcpyAsync(P.geom, geo.data(), geo.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  }
   FM_CHECK(plan_alloc(P, (void**)&P.d_near, std::max<size_t>(1, P.near_off.size()) * sizeof(int)));
   FM_CHECK(hipMemcpyAsync(P.d_near, P.near_off.data(), P.near_off.size() * sizeof(int), hipMemcpyHostToDevice, s));
   // quadrature table
@@ -668,7 +689,12 @@ static hipError_t plan_build(Plan& P, const std::vector<double>& geo, hipStream_
     }
     return hipSuccess;
   };
-  {
+  if (P.parent) {
+    for (int a = 0; a < 6; ++a) {
+      P.dftF[0][a] = P.parent->dftF[0][a];
+      P.dftF[1][a] = P.parent->dftF[1][a];
+    }
+  } else {
     // the host tables must outlive their copies, also when a step fails
     const hipError_t e1 = dft_mats();
     const hipError_t e2 = hipStreamSynchronize(s);
@@ -679,12 +705,13 @@ static hipError_t plan_build(Plan& P, const std::vector<double>& geo, hipStream_
   const int hyper = (P.alpha_re != 0.0 || P.alpha_im != 0.0) ? 1 : 0;
   // near blocks
   const size_t ns = (size_t)P.n_near * n * n;
-  FM_CHECK(plan_alloc(P, &P.S[0], ns * sizeof(double2)));
-  if (want32) FM_CHECK(plan_alloc(P, &P.S[1], ns * sizeof(float2)));
-  {
+  FM_CHECK(plan_alloc(P, &P.S[0], std::max<size_t>(1, ns) * sizeof(double2)));
+  if (want32) FM_CHECK(plan_alloc(P, &P.S[1], std::max<size_t>(1, ns) * sizeof(float2)));
+  if (ns > 0) {
     const size_t blocks = (ns + 255) / 256;
     hipLaunchKernelGGL(assemble_near_kernel, dim3((unsigned)blocks), dim3(256), 0, s, P.geom, n, P.d_near, P.n_near,
-                       P.pitch[0], P.pitch[1], P.pitch[2], P.k, alpha, hyper, Q, P.img_near ? 1 : 0, P.zg,
+                       P.pitch[0], P.pitch[1], P.pitch[2], P.k, alpha, hyper, Q,
+                       P.parent ? 2 : (P.fold && P.img_near ? 1 : 0), P.grid[2] - 1, P.zg,
                        make_double2(P.rp_re, P.rp_im), (double2*)P.S[0], (float2*)P.S[1]);
     FM_CHECK(hipGetLastError());
   }
@@ -709,17 +736,23 @@ static hipError_t plan_build(Plan& P, const std::vector<double>& geo, hipStream_
     if ((err = salloc((void**)&d_isig, isig.size() * sizeof(double))) != hipSuccess) break;
     hipMemcpyAsync(d_sig, sig.data(), sig.size() * sizeof(double), hipMemcpyHostToDevice, s);
     hipMemcpyAsync(d_isig, isig.data(), isig.size() * sizeof(double), hipMemcpyHostToDevice, s);
-    // V0, U0
-    if ((err = plan_alloc(P, &P.V0[0], (size_t)p * n * sizeof(double2))) != hipSuccess) break;
-    if ((err = plan_alloc(P, &P.U0[0], (size_t)p * n * sizeof(double2))) != hipSuccess) break;
-    {
+    // V0, U0 (an image sub-plan shares its parent's)
+    if (P.parent) {
+      for (int q = 0; q < 2; ++q) {
+        P.V0[q] = P.parent->V0[q];
+        P.U0[q] = P.parent->U0[q];
+      }
+    }
+    if (!P.parent && (err = plan_alloc(P, &P.V0[0], (size_t)p * n * sizeof(double2))) != hipSuccess) break;
+    if (!P.parent && (err = plan_alloc(P, &P.U0[0], (size_t)p * n * sizeof(double2))) != hipSuccess) break;
+    if (!P.parent) {
       const int th = n * (nt + 1);
       hipLaunchKernelGGL(p2m_kernel, dim3(th), dim3(64), 0, s, P.geom, n, nt, P.k, Q, d_isig, (double2*)P.V0[0]);
       hipLaunchKernelGGL(l2p_kernel, dim3((th + 63) / 64), dim3(64), 0, s, P.geom, n, nt, P.k, alpha, d_isig,
                          (double2*)P.U0[0]);
       if ((err = hipGetLastError()) != hipSuccess) break;
     }
-    if (want32) {
+    if (want32 && !P.parent) {
       if ((err = plan_alloc(P, &P.V0[1], (size_t)p * n * sizeof(float2))) != hipSuccess) break;
       if ((err = plan_alloc(P, &P.U0[1], (size_t)p * n * sizeof(float2))) != hipSuccess) break;
       hipLaunchKernelGGL(cast_kernel, dim3(256), dim3(256), 0, s, (const double2*)P.V0[0], (float2*)P.V0[1],
@@ -730,25 +763,33 @@ static hipError_t plan_build(Plan& P, const std::vector<double>& geo, hipStream_
     if (P.n_far == 0) break;
     // O grid -> FFT -> Lambda
     const int L = 2 * nt, P2 = (L + 1) * (L + 1);
+    // direct translations (none in an image sub-plan); image translations: target centre minus
+    // mirrored source centre, (d0 p0, d1 p1, -2 zg) with the plane parallel to the periodic axes,
+    // (d0 p0, d1 p1, (e + M3 - 1) p2 - 2 zg) for offset e of the z-reversed input in a sub-plan
+    const bool direct = !P.parent, image = P.fold || P.parent;
     double2 *Og = nullptr, *Ogi = nullptr;
-    if ((err = salloc((void**)&Og, (size_t)P.B * P2 * sizeof(double2))) != hipSuccess) break;
-    if (P.half && (err = salloc((void**)&Ogi, (size_t)P.B * P2 * sizeof(double2))) != hipSuccess) break;
+    if (direct && (err = salloc((void**)&Og, (size_t)P.B * P2 * sizeof(double2))) != hipSuccess) break;
+    if (image && (err = salloc((void**)&Ogi, (size_t)P.B * P2 * sizeof(double2))) != hipSuccess) break;
     {
       const int th = P.B * (L + 1);
       int rr[3];
       for (int a = 0; a < 3; ++a) rr[a] = P.grid[a] > 1 ? std::min(P.near_radius[a], P.grid[a] - 1) : 0;
-      hipLaunchKernelGGL(ogrid_kernel, dim3((th + 127) / 128), dim3(128), 0, s, P.B, P.fft[0], P.fft[1], P.fft[2],
-                         P.grid[0], P.grid[1], P.grid[2], rr[0], rr[1], rr[2], P.pitch[0], P.pitch[1],
-                         P.pitch[2], P.k, L, 0.0, 1, Og);
-      // image translations: target centre minus mirrored source centre, (d0 p0, d1 p1, -2 zg)
-      if (P.half)
+      if (direct)
         hipLaunchKernelGGL(ogrid_kernel, dim3((th + 127) / 128), dim3(128), 0, s, P.B, P.fft[0], P.fft[1],
                            P.fft[2], P.grid[0], P.grid[1], P.grid[2], rr[0], rr[1], rr[2], P.pitch[0], P.pitch[1],
-                           P.pitch[2], P.k, L, -2.0 * P.zg, P.img_near ? 1 : 0, Ogi);
+                           P.pitch[2], P.k, L, 0, 0.0, 1, Og);
+      if (P.fold)
+        hipLaunchKernelGGL(ogrid_kernel, dim3((th + 127) / 128), dim3(128), 0, s, P.B, P.fft[0], P.fft[1],
+                           P.fft[2], P.grid[0], P.grid[1], P.grid[2], rr[0], rr[1], rr[2], P.pitch[0], P.pitch[1],
+                           P.pitch[2], P.k, L, 0, 2.0 * P.zg, P.img_near ? 1 : 0, Ogi);
+      if (P.parent)
+        hipLaunchKernelGGL(ogrid_kernel, dim3((th + 127) / 128), dim3(128), 0, s, P.B, P.fft[0], P.fft[1],
+                           P.fft[2], P.grid[0], P.grid[1], P.grid[2], rr[0], rr[1], P.near_radius[2], P.pitch[0],
+                           P.pitch[1], P.pitch[2], P.k, L, P.grid[2] - 1, 2.0 * P.zg, 2, Ogi);
       if ((err = hipGetLastError()) != hipSuccess) break;
     }
-    if ((err = grid_dft_launch<double>(Og, P2, P.fft, P.fft, false, false, s)) != hipSuccess) break;
-    if (P.half && (err = grid_dft_launch<double>(Ogi, P2, P.fft, P.fft, false, false, s)) != hipSuccess) break;
+    if (direct && (err = grid_dft_launch<double>(Og, P2, P.fft, P.fft, false, false, s)) != hipSuccess) break;
+    if (image && (err = grid_dft_launch<double>(Ogi, P2, P.fft, P.fft, false, false, s)) != hipSuccess) break;
     M2LTable T;
     m2l_table(nt, T);
     int *d_ptr = nullptr, *d_oidx = nullptr, *d_nof = nullptr;
@@ -791,7 +832,7 @@ static hipError_t plan_build(Plan& P, const std::vector<double>& geo, hipStream_
     if (want32 && (err = plan_alloc(P, &P.Lam[1], nl * sizeof(float2))) != hipSuccess) break;
     {
       const int bx = (int)std::min<size_t>(((size_t)p * p + 255) / 256, 64);
-      hipLaunchKernelGGL(lambda_kernel, dim3(bx, P.Bc), dim3(256), (P.half ? 2 : 1) * P2 * sizeof(double2), s, Og,
+      hipLaunchKernelGGL(lambda_kernel, dim3(bx, P.Bc), dim3(256), 2 * P2 * sizeof(double2), s, Og,
                          Ogi, make_double2(P.rp_re, P.rp_im), P2, p, P.d_pairs, d_ptr, d_coef, d_oidx, d_sig, d_nof,
                          1.0 / P.B, ldp, (double2*)P.Lam[0], (float2*)P.Lam[1]);
       if ((err = hipGetLastError()) != hipSuccess) break;
@@ -808,6 +849,72 @@ static hipError_t plan_build(Plan& P, const std::vector<double>& geo, hipStream_
 }  // namespace fmbem
 
 using namespace fmbem;
+
+// The image part of a half-space lattice periodic along z (block Hankel along z, Sec. 2.3):
+// applied to the input reversed along z it is block Toeplitz in (d0, d1, e), e = target - reversed
+// source index, so it is a plan of its own over the same grid: near blocks for the image offsets
+// within the near range (|d0| <= r0, |d1| <= r1, |(e + M3 - 1) p2 - 2 zg| < (r2 + 1) p2), the
+// other image offsets through the multipole chain with the reflected moments (Sec. 3.4,
+// Appendix A, eq. (greenFMMhalfspace)); geometry, V0, U0 and the DFT matrices are the parent's.
+static hipError_t image_plan_create(Plan& P, const std::vector<double>& geo, hipStream_t s) {
+  Plan* I = new (std::nothrow) Plan();
+  if (!I) return hipErrorOutOfMemory;
+  I->device = P.device;
+  I->n = P.n;
+  I->C = P.C;
+  for (int a = 0; a < 3; ++a) {
+    I->grid[a] = P.grid[a];
+    I->pitch[a] = P.pitch[a];
+    I->near_radius[a] = P.near_radius[a];
+    I->fft[a] = P.fft[a];
+  }
+  I->B = P.B;
+  I->k = P.k;
+  I->order = P.order;
+  I->p = P.p;
+  I->p2 = P.p2;
+  I->formulation = P.formulation;
+  I->alpha_re = P.alpha_re;
+  I->alpha_im = P.alpha_im;
+  I->precisions = P.precisions;
+  I->scale = P.scale;
+  I->dft_forced = P.dft_forced;
+  I->parent = &P;
+  I->paired = false;
+  I->zg = P.zg;
+  I->rp_re = P.rp_re;
+  I->rp_im = P.rp_im;
+  const int M3 = P.grid[2];
+  int rr[2];
+  for (int a = 0; a < 2; ++a) rr[a] = P.grid[a] > 1 ? std::min(P.near_radius[a], P.grid[a] - 1) : 0;
+  int total = 0;
+  for (int e3 = -(M3 - 1); e3 <= M3 - 1; ++e3) {
+    const double dz = (e3 + M3 - 1) * P.pitch[2] - 2.0 * P.zg;
+    const bool znear = std::fabs(dz) < (P.near_radius[2] + 1) * P.pitch[2];
+    for (int d1 = -(P.grid[1] - 1); d1 <= P.grid[1] - 1; ++d1)
+      for (int d0 = -(P.grid[0] - 1); d0 <= P.grid[0] - 1; ++d0) {
+        ++total;
+        if (znear && std::abs(d0) <= rr[0] && std::abs(d1) <= rr[1]) {
+          I->near_off.push_back(d0);
+          I->near_off.push_back(d1);
+          I->near_off.push_back(e3);
+        }
+      }
+  }
+  I->n_near = (int)I->near_off.size() / 3;
+  I->n_far = total - I->n_near;
+  hipError_t e = I->n_near > kMaxSeg ? hipErrorInvalidValue : hipSuccess;
+  if (e == hipSuccess) e = plan_build(*I, geo, s);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&I->aux, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&I->ev_join, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    plan_release(I);
+    return e;
+  }
+  P.img = I;
+  return hipSuccess;
+}
 
 extern "C" fmbem_status fmbem_plan_create(const fmbem_cell_mesh* mesh, const fmbem_plan_desc* desc, void* hip_stream,
                                           fmbem_plan* out) {
@@ -829,17 +936,16 @@ extern "C" fmbem_status fmbem_plan_create(const fmbem_cell_mesh* mesh, const fmb
   if (desc->dft_schedule < FMBEM_DFT_AUTO || desc->dft_schedule > FMBEM_DFT_FUSED_MFMA) return FMBEM_ERR_INVALID_ARG;
   if (desc->halfspace != 0 && desc->halfspace != 1) return FMBEM_ERR_INVALID_ARG;
   if (desc->halfspace == 1) {
-    if (desc->grid[2] != 1 || !std::isfinite(desc->plane_z) || !std::isfinite(desc->reflection_re) ||
-        !std::isfinite(desc->reflection_im))
+    if (!std::isfinite(desc->plane_z) || !std::isfinite(desc->reflection_re) || !std::isfinite(desc->reflection_im))
       return FMBEM_ERR_INVALID_ARG;
-    // the surface stays on one side of the plane (vertices on it allowed)
-    bool above = true, below = true;
+    // the surface of every layer stays on one side of the plane (vertices on it allowed)
+    double zmin = HUGE_VAL, zmax = -HUGE_VAL;
     for (int v = 0; v < mesh->n_vertices; ++v) {
-      const double z = mesh->vertices[3 * v + 2];
-      above = above && z >= desc->plane_z;
-      below = below && z <= desc->plane_z;
+      zmin = std::min(zmin, mesh->vertices[3 * v + 2]);
+      zmax = std::max(zmax, mesh->vertices[3 * v + 2]);
     }
-    if (!above && !below) return FMBEM_ERR_INVALID_ARG;
+    zmax += (desc->grid[2] - 1) * desc->pitch[2];
+    if (!(zmin >= desc->plane_z || zmax <= desc->plane_z)) return FMBEM_ERR_INVALID_ARG;
   }
   const int n = mesh->n_triangles;
   // geometry on the host: a, b, c, centroid, unit normal, longest edge, area
@@ -930,16 +1036,20 @@ extern "C" fmbem_status fmbem_plan_create(const fmbem_cell_mesh* mesh, const fmb
   }
   P->n_far = (2 * P->grid[0] - 1) * (2 * P->grid[1] - 1) * (2 * P->grid[2] - 1) - P->n_near;
   if (desc->halfspace == 1) {
-    // image blocks: near for the near offsets when the mirrored cells lie within the near range
-    // along z (|2 zg| < (r + 1) pitch_z), all through the multipole chain otherwise
     P->half = true;
-    P->paired = false;
     P->zg = desc->plane_z;
     P->rp_re = desc->reflection_re;
     P->rp_im = desc->reflection_im;
-    P->img_near = std::fabs(2.0 * P->zg) < (P->near_radius[2] + 1) * P->pitch[2];
-    P->n_far_img = (2 * P->grid[0] - 1) * (2 * P->grid[1] - 1) - (P->img_near ? P->n_near : 0);
-    P->n_far += P->n_far_img;
+    if (P->grid[2] == 1) {
+      // plane parallel to every periodic axis: image blocks near for the near offsets when the
+      // mirrored cells lie within the near range along z (|2 zg| < (r + 1) pitch_z), all through
+      // the multipole chain otherwise, folded into this plan
+      P->fold = true;
+      P->paired = false;
+      P->img_near = std::fabs(2.0 * P->zg) < (P->near_radius[2] + 1) * P->pitch[2];
+      P->n_far_img = (2 * P->grid[0] - 1) * (2 * P->grid[1] - 1) - (P->img_near ? P->n_near : 0);
+      P->n_far += P->n_far_img;
+    }
   }
   // scaling: s = k * (largest distance of a vertex from the cell centre), at most 1
   double rmax = 0.0;
@@ -953,6 +1063,7 @@ extern "C" fmbem_status fmbem_plan_create(const fmbem_cell_mesh* mesh, const fmb
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming);
+  if (e == hipSuccess && P->half && !P->fold) e = image_plan_create(*P, geo, s);
   if (e != hipSuccess) {
     plan_release(P);
     return to_status(e);
@@ -976,9 +1087,9 @@ extern "C" fmbem_status fmbem_plan_query(fmbem_plan plan, fmbem_plan_info* out) 
   out->p = P.p;
   for (int a = 0; a < 3; ++a) out->fft_shape[a] = P.fft[a];
   out->n_near = P.n_near;
-  out->n_far = P.n_far;
+  out->n_far = P.n_far + (P.img ? P.img->n_far : 0);
   out->precisions = P.precisions;
-  out->resident_bytes = P.resident;
+  out->resident_bytes = P.resident + (P.img ? P.img->resident : 0);
   out->workspace_bytes_per_rhs[0] = matvec_workspace_bytes_per_rhs(P, FMBEM_FP64);
   out->workspace_bytes_per_rhs[1] = matvec_workspace_bytes_per_rhs(P, FMBEM_FP32);
   out->scale = P.scale;

@@ -90,7 +90,7 @@ def test_plan_create_rejects_invalid_arguments(case):
         desc = _desc(dft_schedule=5)
     elif case == "halfspace_flag":
         desc = _desc(halfspace=2, plane_z=0.2)
-    elif case == "halfspace_grid":        # the plane must be parallel to every periodic axis
+    elif case == "halfspace_grid":        # the second layer (z up to 0.4) crosses z = 0.2
         desc = _desc(halfspace=1, plane_z=0.2, grid=(3, 3, 2))
     elif case == "halfspace_crossing":    # the sphere of radius 0.1 crosses z = 0.05
         desc = _desc(halfspace=1, plane_z=0.05, reflection_re=1.0)

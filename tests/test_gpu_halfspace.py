@@ -130,3 +130,49 @@ def test_tubes_standing_on_the_plane():
     xs, info = P.solve(b, tol=1e-10, inner="fp32")
     assert rel(xs.cpu().numpy().ravel(), solve.lu_solve(H.dense(), b.cpu().numpy().ravel())) < 1e-6
     P.close()
+
+
+@pytest.mark.parametrize("R", [1, 9])
+def test_stacked_lattice_over_plane_matches_oracle(R):
+    # second case of Sec. 3.4: the lattice is periodic along z, normal to the plane, so the image
+    # part is block Hankel along z and runs as a sub-plan on the input reversed along z
+    import paper_2201_12050_amd as fm
+    v, t = icosphere(1, 0.1)
+    lat = Lattice((3, 2, 3), (0.3, 0.3, 0.3))
+    k = 2 * np.pi * 600.0 / 343.0
+    zg, rp = -0.15, 0.8 + 0.2j
+    H = hs.FMPBEMHalfSpace(v, t, lat, k, 6, -1j / k, zg, rp)
+    P = fm.Plan(v, t, lat.grid, lat.pitch, k, 6, halfspace=(zg, rp))
+    x = random_complex((R, lat.n_cells, t.shape[0]), 640 + R)
+    xd = torch.from_numpy(x).cuda()
+    ref = H.matvec(x)
+    assert rel(P.matvec(xd, precision="fp64").cpu().numpy(), ref) < 1e-12
+    assert rel(P.matvec(xd.to(torch.complex64), precision="fp32").cpu().numpy(), ref) < 1e-5
+    if R == 1:
+        b = P.incident_plane_wave([[0.6, 0.0, -0.8]])
+        assert rel(b.cpu().numpy().ravel(),
+                   hs.rhs_plane_wave(v, t, lat, k, -1j / k, [[0.6, 0.0, -0.8]], zg, rp)[0]) < 1e-12
+        xs, info = P.solve(b, tol=1e-10, inner="fp32")
+        assert rel(xs.cpu().numpy().ravel(), solve.lu_solve(H.dense(), b.cpu().numpy().ravel())) < 1e-6
+        pts = np.array([[0.45, 0.2, 0.75], [1.5, -1.0, 0.1], [0.15, 0.15, -0.05]])
+        got = P.field(xs, pts).cpu().numpy()
+        assert rel(got, hs.field(v, t, lat, k, pts, xs.cpu().numpy().reshape(1, -1), zg, rp)) < 1e-12
+    P.close()
+
+
+def test_barrier_segments_on_the_plane():
+    # open tube segments stacked three high on a sound-hard plane, the lowest rim on the plane
+    import paper_2201_12050_amd as fm
+    from workloads import tube_segment
+    v, t = tube_segment(0.08, 0.25, 32, 3)
+    lat = Lattice((4, 2, 3), (0.2, 0.2, 0.25))
+    k = 2 * np.pi * 700.0 / 343.0
+    zg = float(v[:, 2].min())
+    H = hs.FMPBEMHalfSpace(v, t, lat, k, 6, -1j / k, zg, 1.0)
+    P = fm.Plan(v, t, lat.grid, lat.pitch, k, 6, halfspace=(zg, 1.0))
+    x = random_complex((3, lat.n_cells, t.shape[0]), 78)
+    xd = torch.from_numpy(x).cuda()
+    ref = H.matvec(x)
+    assert rel(P.matvec(xd, precision="fp64").cpu().numpy(), ref) < 1e-12
+    assert rel(P.matvec(xd.to(torch.complex64), precision="fp32").cpu().numpy(), ref) < 1e-5
+    P.close()
