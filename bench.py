@@ -228,6 +228,40 @@ def barrier_sweep(fm, torch, args):
             "field_ms_mean": float(np.mean([r["field_ms"] for r in rows])), "per_frequency": rows}
 
 
+def barrier_ground_sweep(fm, torch, args):
+    """The barrier of the sweep standing on sound-hard ground (half-space, the lattice periodic
+    normal to the plane: the image part runs as a sub-plan on the input reversed along z), a
+    point source 1 m above the ground; FP32-refined solves and the insertion loss at the 64
+    receivers against the free field over the ground (direct + reflected)."""
+    from workloads import config_barrier_ground
+    idx = [int(round(i)) for i in np.linspace(0, 95, args.ground_freqs)]
+    rows = []
+    t_start = time.perf_counter()
+    for fi in idx:
+        w = config_barrier_ground(fi)
+        zg, rp, rec = w.extra["plane_z"], w.extra["reflection"], w.extra["receivers"]
+        t0 = time.perf_counter()
+        P = fm.Plan.from_workload(w, halfspace=(zg, rp))
+        b = P.incident_point_source(w.point_sources)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x, info = P.solve(b, tol=args.tol, inner="fp32", ortho=args.ortho, restart=args.barrier_restart,
+                          max_iters=args.barrier_max_iters, raise_on_not_converged=False)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        pin = P.incident_at_points("point_source", w.point_sources, rec)
+        il = float(fm.insertion_loss(pin, P.field(x, rec, pin))[0])
+        rows.append({"f_hz": round(w.frequency, 1), "iterations": info[0]["iterations"],
+                     "rel_residual": info[0]["rel_residual"], "solve_ms": (t2 - t1) * 1e3,
+                     "plan_build_ms": (t1 - t0) * 1e3, "il_db": il})
+        P.close()
+    total = time.perf_counter() - t_start
+    return {"workload": "barrier 40x2x8 open tube cells (N = 122,880) on sound-hard ground z = -0.125 m, point "
+                        f"source 1 m above ground, {len(idx)} frequencies 100 Hz - 2 kHz",
+            "frequencies_per_s": len(idx) / total, "max_rel_residual": max(r["rel_residual"] for r in rows),
+            "per_frequency": rows}
+
+
 def ground_solves(fm, torch, args):
     """The 16x16 lattice of the headline above a sound-hard plane 0.05 m below the spheres (image
     blocks near, R_p = 1), a plane wave travelling down toward it: FP32-refined solves with the
@@ -361,6 +395,8 @@ def main():
     ap.add_argument("--batch-rhs", type=int, default=64, help="plane waves per lattice of the batched-grids run")
     ap.add_argument("--no-batched-grids", action="store_true")
     ap.add_argument("--no-ground", action="store_true", help="skip the half-space 16x16 solves")
+    ap.add_argument("--ground-freqs", type=int, default=4,
+                    help="frequencies of the barrier-on-ground sweep (0: skip)")
     ap.add_argument("--serving-requests", type=int, default=100, help="measured requests of the serving run")
     ap.add_argument("--serving-warmup", type=int, default=10)
     ap.add_argument("--serving-rates", type=float, nargs="*", default=[20.0, 8.0],
@@ -522,6 +558,9 @@ def main():
     if not args.no_ground:
         out["halfspace_grid16"] = ground_solves(fm, torch, args)
         print(f"[bench] half-space 16x16 {out['halfspace_grid16']}", file=sys.stderr, flush=True)
+    if args.ground_freqs > 0:
+        out["barrier_ground_sweep"] = barrier_ground_sweep(fm, torch, args)
+        print(f"[bench] barrier on ground {out['barrier_ground_sweep']}", file=sys.stderr, flush=True)
     if args.barrier_freqs > 0:
         out["barrier_sweep"] = barrier_sweep(fm, torch, args)
         print(f"[bench] barrier sweep {out['barrier_sweep']['frequencies_per_s']:.2f} frequencies/s",

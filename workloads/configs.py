@@ -139,6 +139,16 @@ def config_barrier_r4b(freq_index: int = 95) -> Workload:
                     extra={"receivers": barrier_receivers()})
 
 
+def config_barrier_ground(freq_index: int = 95) -> Workload:
+    """The barrier of config_barrier_r4b standing on sound-hard ground: the plane z = -0.125 m
+    through the lower rim of the lowest segments (reflection 1), the point source 1 m above the
+    ground, 2 m in front of the front row, mid-length."""
+    w = config_barrier_r4b(freq_index)
+    src = np.array([[39 * 0.2 / 2.0, -2.0, -0.125 + 1.0]])
+    return w.with_(name=w.name + "_ground", point_sources=src,
+                   extra={"receivers": w.extra["receivers"], "plane_z": -0.125, "reflection": 1.0})
+
+
 def barrier_receivers(n_along: int = 8, n_up: int = 8) -> np.ndarray:
     """Observation points of the barrier: a vertical n_along x n_up grid 2 m behind the
     back row (y = 0.2 + 2), spanning +-2 m along the barrier about its middle (x = 3.9)
