@@ -82,10 +82,14 @@ typedef struct {
   /* Half-space (Sec. 2.1, eq. (green3dHalf); Sec. 2.3; Sec. 3.4): halfspace = 1 adds to every
    * interaction the image term R_p G(x, y^), y^ the mirror image of y in the plane
    * z = plane_z, applied as image near blocks and an image multipole chain (Appendix A,
-   * eq. (greenFMMhalfspace)); the incident fields get their images too.  The plane must be
-   * parallel to every periodic direction (grid[2] == 1) and the cell mesh must not cross it
-   * (else FMBEM_ERR_INVALID_ARG).  The image block of offset d is near when d is a near offset
-   * and |2 plane_z| < (near_radius[2] + 1) pitch[2].  halfspace = 0: full space (the other
+   * eq. (greenFMMhalfspace)); the incident fields and fmbem_field get their images too.  With
+   * grid[2] == 1 (the plane parallel to every periodic direction) the image part is block
+   * Toeplitz and shares the plan's operator; with grid[2] > 1 it is block Hankel along z and
+   * is applied as a second operator to the input reversed along z (a second apply per
+   * fmbem_matvec, more workspace).  No layer of cells may cross the plane (touching is allowed;
+   * else FMBEM_ERR_INVALID_ARG).  An image block is near when its in-plane offset is a near
+   * offset and its z offset |s pitch[2] - 2 plane_z| < (near_radius[2] + 1) pitch[2], s = the
+   * sum of the target's and the source's z indices.  halfspace = 0: full space (the other
    * three fields are ignored). */
   int32_t halfspace;
   double plane_z;

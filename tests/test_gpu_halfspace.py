@@ -176,3 +176,42 @@ def test_barrier_segments_on_the_plane():
     assert rel(P.matvec(xd, precision="fp64").cpu().numpy(), ref) < 1e-12
     assert rel(P.matvec(xd.to(torch.complex64), precision="fp32").cpu().numpy(), ref) < 1e-5
     P.close()
+
+
+def test_halfspace_plans_in_a_batch_and_the_engine():
+    # grouped applies: a stacked half-space plan (image sub-plan), a folded one and a full-space
+    # plan solved in lockstep, and the same through the serving engine; each as alone
+    import paper_2201_12050_amd as fm
+    v, t = icosphere(1, 0.1)
+    k = 2 * np.pi * 600.0 / 343.0
+    plans = [fm.Plan(v, t, (3, 2, 3), (0.3, 0.3, 0.3), k, 6, halfspace=(-0.15, 1.0)),
+             fm.Plan(v, t, (4, 3, 1), (0.3, 0.3, 0.3), k, 6, halfspace=(0.15, 0.7 - 0.3j)),
+             fm.Plan(v, t, (3, 3, 1), (0.3, 0.3, 0.3), k, 6)]
+    bs = [P.incident_plane_wave(unit_directions(2, 40 + i)) for i, P in enumerate(plans)]
+    for inner in ("fp64", "fp32"):
+        opts = dict(tol=1e-9, inner=inner)
+        res = fm.solve_batch([(P, b, None, opts) for P, b in zip(plans, bs)])
+        for P, b, (x, infos) in zip(plans, bs, res):
+            assert max(i["rel_residual"] for i in infos) <= 1e-9
+            xa, _ = P.solve(b, **opts)
+            assert rel(x.cpu().numpy(), xa.cpu().numpy()) < 1e-8
+    eng = fm.Engine(8 << 30, max_slots=4)
+    tickets = [eng.submit(P, b, tol=1e-9, inner="fp32") for P, b in zip(plans, bs)]
+    done = {}
+    for _ in range(100000):
+        eng.step()
+        for tk in tickets:
+            if tk not in done:
+                r = eng.poll(tk)
+                if r is not None:
+                    done[tk] = r
+        if len(done) == len(tickets):
+            break
+    assert len(done) == len(tickets)
+    for P, b, tk in zip(plans, bs, tickets):
+        xa, _ = P.solve(b, tol=1e-9, inner="fp32")
+        x = done[tk][0] if isinstance(done[tk], tuple) else done[tk]
+        assert rel(x.cpu().numpy(), xa.cpu().numpy()) < 1e-8
+    eng.close()
+    for P in plans:
+        P.close()
