@@ -135,7 +135,9 @@ fmbem_status fmbem_plan_destroy(fmbem_plan plan);
  *   what = 2: U0           [n][p]   (unscaled)
  *   what = 3: Lambda       [B][p][p] row-major, unscaled and without the 1/B factor
  *   what = 4: near offsets int32 [n_near][3]
- * host_bytes must be at least the size of the requested array. Blocks. */
+ * host_bytes must be at least the size of the requested array.  In the half-space with
+ * grid[2] == 1 the exported S_d and Lambda include the image terms; with grid[2] > 1 they are
+ * the direct part only (the image part is a second operator).  Blocks. */
 fmbem_status fmbem_plan_export(fmbem_plan plan, int32_t what, void* host, size_t host_bytes);
 
 /* y = A x (Sec. 3.5, eq. (FMPBEMsystem)): near-field block-Toeplitz product,
