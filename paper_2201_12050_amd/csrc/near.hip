@@ -167,12 +167,22 @@ __device__ __forceinline__ void near_tile(const JL& jobs) {
   // Global loads of one step, branch-free: every load reads a valid address (out-of-range
   // rows, columns and k read a valid stand-in, masked to zero at the LDS store), so the
   // loads stay in flight across the MFMAs of the current step.  When K is a multiple of
-  // the 16-byte unit (two FP32 or one FP64 complex value), whole units are loaded.
+  // the 16-byte unit (two FP32 or one FP64 complex value), whole units are loaded; in the
+  // column-major form (batched products) the A columns are loaded in whole units when the
+  // column stride lda is a multiple of the unit, and the B columns element by element.
   constexpr int EPL = 16 / sizeof(cplx<T>);
   using VL = typename Vec16<T>::type;
-  const bool vec_ok = (K % EPL) == 0;
+  const bool vec_ok = ACOL ? (lda % EPL) == 0 && (reinterpret_cast<uintptr_t>(jb.A) % 16) == 0 : (K % EPL) == 0;
   const bool a_in = !ACOL && a_act && m0 + a_row < M;
   const cplx<T>* arow_ld = A + (size_t)(a_in ? m0 + a_row : 0) * lda;
+  // column-major A: valid rows of this thread's APT (bit q), and the column offset of its k
+  // (threads without a k of the step read column k0 of the step, masked)
+  uint32_t acol_rows = 0;
+  if constexpr (ACOL) {
+#pragma unroll
+    for (int q = 0; q < APT; ++q) acol_rows |= ((a_act && m0 + a_row + q < M) ? 1u : 0u) << q;
+  }
+  const int a_k_ld = a_act ? a_k : 0;
   const bool b_in = bcol != nullptr;
   const cplx<T>* bcol_ld = b_in ? bcol : reinterpret_cast<const cplx<T>*>(jb.src);
   auto unpack = [](const VL& v, cplx<T>* r) {
@@ -189,13 +199,27 @@ __device__ __forceinline__ void near_tile(const JL& jobs) {
     cplx<T>* rb = rb2[decltype(set)::value];
     uint32_t& amask = amask2[decltype(set)::value];
     uint32_t& bmask = bmask2[decltype(set)::value];
+    if constexpr (ACOL) {
+      // a unit starting at row r < lda lies inside the column (r and lda multiples of EPL);
+      // units from row lda on read row 0 of the column instead (masked)
+      const cplx<T>* acol = A + (size_t)(k0 + a_k_ld) * lda;
 #pragma unroll
-    for (int q = 0; q < APT / EPL; ++q)
-      unpack(*reinterpret_cast<const VL*>(arow_ld + k0 + a_k + q * EPL), ra + q * EPL);
-    amask = a_in ? 0xFFFFFFFFu : 0u;
+      for (int q = 0; q < APT / EPL; ++q) {
+        const int r = m0 + a_row + q * EPL;
+        unpack(*reinterpret_cast<const VL*>(acol + (r < lda ? r : 0)), ra + q * EPL);
+      }
+      amask = acol_rows;
 #pragma unroll
-    for (int q = 0; q < BPT / EPL; ++q)
-      unpack(*reinterpret_cast<const VL*>(bcol_ld + k0 + b_k + q * EPL), rb + q * EPL);
+      for (int e = 0; e < BPT; ++e) rb[e] = bcol_ld[k0 + b_k + e];
+    } else {
+#pragma unroll
+      for (int q = 0; q < APT / EPL; ++q)
+        unpack(*reinterpret_cast<const VL*>(arow_ld + k0 + a_k + q * EPL), ra + q * EPL);
+      amask = a_in ? 0xFFFFFFFFu : 0u;
+#pragma unroll
+      for (int q = 0; q < BPT / EPL; ++q)
+        unpack(*reinterpret_cast<const VL*>(bcol_ld + k0 + b_k + q * EPL), rb + q * EPL);
+    }
     bmask = b_in ? 0xFFFFFFFFu : 0u;
   };
   // any step: element loads from clamped indices, per-element masks
@@ -241,8 +265,9 @@ __device__ __forceinline__ void near_tile(const JL& jobs) {
       bmask |= (v ? 1u : 0u) << e;
     }
   };
-  // the full-step path needs 16-byte aligned rows / columns and whole units per thread
-  constexpr bool kVecShape = !ACOL && APT % EPL == 0 && BPT % EPL == 0;
+  // the full-step path needs 16-byte aligned rows / columns and whole units per thread (the DFT
+  // passes keep the element loads, which apply the symmetry signs)
+  constexpr bool kVecShape = ACOL ? (!DFTG && APT % EPL == 0) : (APT % EPL == 0 && BPT % EPL == 0);
   const bool vec_steps = kVecShape && vec_ok;
   // staged values of a register set -> LDS buffer b (whole chunks as one 16-byte store, partial
   // chunks element-wise)
@@ -507,7 +532,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void
 }
 template <typename T, int ROWS, int COLS, int WR, int KC, int WPE, int PIPE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(WPE))) void m2l_kernel(NearJobs jobs) {
-  near_tile<T, ROWS, COLS, WR, KC, 1, true>(jobs);
+  near_tile<T, ROWS, COLS, WR, KC, PIPE, true>(jobs);
 }
 template <typename T, int ROWS, int COLS, int WR, int KC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void dft_gemm_kernel(DftGemmJobs jobs) {
@@ -545,10 +570,11 @@ constexpr int kNumShapes = 10;
 // M2L products: p rows (121 at n_t = 10) by R columns per bin
 #define FMBEM_M2L_SHAPES(KC, W5)                                                                 \
   X(0, 64, 64, 4, KC, 3, 1) X(1, 32, 64, 2, KC, 3, 1) X(2, 64, 32, 2, KC, 3, 1) X(3, 32, 32, 2, KC, 3, 1) \
-  X(4, 16, 64, 1, KC, 3, 1) X(5, 128, 64, 4, KC, W5, 1)
-constexpr int kNumM2lShapes = 6;
+  X(4, 16, 64, 1, KC, 3, 1) X(5, 128, 64, 4, KC, W5, 1) X(6, 32, 64, 2, KC, 3, 2) X(7, 64, 32, 2, KC, 3, 2)     \
+  X(8, 64, 64, 4, KC, 2, 2) X(9, 64, 64, 2, KC, 2, 2)
+constexpr int kNumM2lShapes = 10;
 template <typename T> constexpr int shape_kc() { return sizeof(T) == 4 ? 16 : 8; }
-template <typename T> constexpr int m2l_w5() { return sizeof(T) == 4 ? 3 : 1; }
+template <typename T> constexpr int m2l_w5() { return sizeof(T) == 4 ? 2 : 1; }
 
 template <typename T>
 static NearShape shape_of(int kind, int v) {
