@@ -38,7 +38,7 @@ PEAK_HBM = 8.0e12
 # HBM bytes per launch of the FP32 near-field kernel on this workload: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
 # from two rocprofv3 counter runs, the factors calibrated on a plain 1 GiB device copy
 # (profiles/near_kernel_fp32_sphere16x16_traffic.md), for near_kernel<float, 64, 64, 2, 16, 3, 2> as it stands
-NEAR_FP32_TRAFFIC_BYTES = 207.2e6
+NEAR_FP32_TRAFFIC_BYTES = 207.3e6
 
 
 def percentile(v, q):
