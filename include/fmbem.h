@@ -94,7 +94,17 @@ typedef struct {
   int32_t halfspace;
   double plane_z;
   double reflection_re, reflection_im;  /* R_p */
+  /* Tile shape of the grouped MFMA launches of this plan, [near field + S2M, L2T, M2L GEMM]:
+   * 0 => autotuned (measured on first use of each launch signature); v in
+   * 1..FMBEM_TILE_SHAPES => shape v - 1 of that launch's list, so that every shape can be
+   * checked.  The M2L GEMM shape holds wherever the plan is applied; the near-field and L2T
+   * shapes hold for the plan's own applies (fmbem_matvec, fmbem_solve, fmbem_solver_*), while
+   * batched solves and the engine tune the launches they share between plans.  Outside
+   * 0..FMBEM_TILE_SHAPES => FMBEM_ERR_INVALID_ARG. */
+  int32_t tile_shape[3];
 } fmbem_plan_desc;
+
+#define FMBEM_TILE_SHAPES 10
 
 #define FMBEM_DFT_AUTO 0    /* autotuned */
 #define FMBEM_DFT_AXES 1    /* one direct pruned DFT pass per axis */

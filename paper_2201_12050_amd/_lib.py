@@ -37,7 +37,8 @@ class PlanDesc(ct.Structure):
                 ("order", ct.c_int32), ("formulation", ct.c_int32), ("alpha_re", ct.c_double),
                 ("alpha_im", ct.c_double), ("near_radius", ct.c_int32 * 3), ("fft_shape", ct.c_int32 * 3),
                 ("precisions", ct.c_uint32), ("dft_schedule", ct.c_int32), ("halfspace", ct.c_int32),
-                ("plane_z", ct.c_double), ("reflection_re", ct.c_double), ("reflection_im", ct.c_double)]
+                ("plane_z", ct.c_double), ("reflection_re", ct.c_double), ("reflection_im", ct.c_double),
+                ("tile_shape", ct.c_int32 * 3)]
 
 
 DFT_SCHEDULE = {"auto": 0, "axes": 1, "fused": 2, "gemm": 3, "mfma": 4}
@@ -297,9 +298,10 @@ class Plan:
 
     def __init__(self, vertices, triangles, grid, pitch, k, order, formulation="bm", alpha=None,
                  near_radius=(1, 1, 1), fft_shape=(0, 0, 0), precisions=("fp64", "fp32"), stream=None,
-                 dft_schedule="auto", halfspace=None):
+                 dft_schedule="auto", halfspace=None, tile_shape=(0, 0, 0)):
         """halfspace: None (full space) or (plane_z, R_p): the half-space Green's function with the
-        plane z = plane_z and reflection coefficient R_p (grid[2] must be 1)."""
+        plane z = plane_z and reflection coefficient R_p.  tile_shape: forced tile shapes of the
+        near-field, L2T and M2L GEMM launches (0 = autotuned, v = shape v - 1)."""
         lib = load()
         self._lib = lib
         v = np.ascontiguousarray(vertices, dtype=np.float64)
@@ -321,6 +323,8 @@ class Plan:
             d.alpha_re, d.alpha_im = float(np.real(alpha)), float(np.imag(alpha))
         d.precisions = sum(1 << _precision(p) for p in precisions)
         d.dft_schedule = DFT_SCHEDULE[dft_schedule]
+        for a in range(3):
+            d.tile_shape[a] = int(tile_shape[a])
         if halfspace is not None:
             zg, rp = halfspace
             d.halfspace = 1

@@ -85,6 +85,7 @@ struct Plan {
   // ([N_a][M_a], w^(k j) with w = e^(-2 pi i / N_a)), inverse at [3 + a] ([M_a][N_a], conjugate
   // kernel); only for 1 < N_a <= kDftGemmMaxOut, else nullptr
   void* dftF[2][6] = {};
+  int tile_forced[3] = {-1, -1, -1};  // tile shapes forced by the plan descriptor (-1: tuned)
   int dft_forced = -1;       // DFT schedule forced by the plan descriptor (0 axes, 1 fused, 2 GEMM, 3 fused
                              // on the matrix cores), -1: tuned
   // half-space: image term R_p G(x, y^) with y^ mirrored in z = zg.  half: the incident fields

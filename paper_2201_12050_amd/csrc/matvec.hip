@@ -127,6 +127,14 @@ int tuned_shape(int kind, const std::vector<NearJob>& jobs, hipStream_t s) {
   return best;
 }
 
+// tile shape of one of a plan's grouped launches (kind 0 near field + S2M, 1 L2T, 2 M2L GEMM):
+// the plan's forced shape, else the tuned one (tune) or the cached / default one
+template <typename T>
+static int plan_shape(const Plan& P, int kind, const std::vector<NearJob>& jobs, hipStream_t s, bool tune) {
+  if (P.tile_forced[kind] >= 0) return P.tile_forced[kind];
+  return tune ? tuned_shape<T>(kind, jobs, s) : cached_shape<T>(kind, jobs);
+}
+
 // the tuned shape of this job-list signature if one was measured, else -1 (default shape)
 template <typename T>
 int cached_shape(int kind, const std::vector<NearJob>& jobs) {
@@ -234,7 +242,7 @@ static hipError_t m2l_apply(const Plan& P, int R, void* ws, hipStream_t s, void*
   j.amap = P.d_canon;
   std::vector<NearJob> jobs{j};
   *lhat = out;
-  return near_launch<T>(jobs, s, tune ? tuned_shape<T>(2, jobs, s) : cached_shape<T>(2, jobs), 2);
+  return near_launch<T>(jobs, s, plan_shape<T>(P, 2, jobs, s, tune), 2);
 }
 
 template <typename T>
@@ -283,7 +291,7 @@ static hipError_t matvec_overlap(const Plan& P, int R, const void* x, void* y, v
   hipEvent_t ev = prof_begin(P, 2 + 6 * prec, P.aux);
   {
     std::vector<NearJob> s2m{near_job(P, R, P.V0[prec], ws, p, n, x, SRC_X, DEST_GRID)};
-    const int shape = tune ? tuned_shape<T>(0, s2m, P.aux) : cached_shape<T>(0, s2m);
+    const int shape = plan_shape<T>(P, 0, s2m, P.aux, tune);
     if ((e = near_launch<T>(s2m, P.aux, shape, 0))) return e;
   }
   if ((e = grid_dft_launch<T>(ws, R * p, P.grid, P.fft, false, true, P.aux, P.flip_p(), sched_fwd(dsched), P.dftF[prec]))) return e;
@@ -301,7 +309,7 @@ static hipError_t matvec_overlap(const Plan& P, int R, const void* x, void* y, v
     std::vector<NearJob> jobs;
     near_s2m_jobs<T>(P, R, x, ws, jobs);
     jobs.pop_back();  // the S2M job ran on the second stream
-    const int shape = tune ? tuned_shape<T>(0, jobs, s) : cached_shape<T>(0, jobs);
+    const int shape = plan_shape<T>(P, 0, jobs, s, tune);
     ev = prof_begin(P, 0 + 6 * prec, s);
     if ((e = near_launch<T>(jobs, s, shape, 0))) return e;
     prof_end(P, 0 + 6 * prec, ev, s);
@@ -309,7 +317,7 @@ static hipError_t matvec_overlap(const Plan& P, int R, const void* x, void* y, v
   if ((e = hipStreamWaitEvent(s, P.ev_join, 0))) return e;
   // [5] L2T with the fixed-order sum of the near partials
   std::vector<NearJob> jobs{l2t_job<T>(P, R, ws, lhat, y, y64)};
-  const int shape = tune ? tuned_shape<T>(1, jobs, s) : cached_shape<T>(1, jobs);
+  const int shape = plan_shape<T>(P, 1, jobs, s, tune);
   ev = prof_begin(P, 5 + 6 * prec, s);
   e = near_launch<T>(jobs, s, shape, 1);
   prof_end(P, 5 + 6 * prec, ev, s);
@@ -331,7 +339,7 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
   {
     std::vector<NearJob> jobs;
     near_s2m_jobs<T>(P, R, x, ws, jobs);
-    const int shape = tune ? tuned_shape<T>(0, jobs, s) : cached_shape<T>(0, jobs);
+    const int shape = plan_shape<T>(P, 0, jobs, s, tune);
     ev = prof_begin(P, 0 + 6 * prec, s);
     hipError_t e = near_launch<T>(jobs, s, shape, 0);
     if (e != hipSuccess) return e;
@@ -362,7 +370,7 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
   // [5] L2T with the fixed-order sum of the near partials
   {
     std::vector<NearJob> jobs{l2t_job<T>(P, R, ws, lhat, y, y64)};
-    const int shape = tune ? tuned_shape<T>(1, jobs, s) : cached_shape<T>(1, jobs);
+    const int shape = plan_shape<T>(P, 1, jobs, s, tune);
     ev = prof_begin(P, 5 + 6 * prec, s);
     e = near_launch<T>(jobs, s, shape, 1);
   }

@@ -879,6 +879,7 @@ static hipError_t image_plan_create(Plan& P, const std::vector<double>& geo, hip
   I->precisions = P.precisions;
   I->scale = P.scale;
   I->dft_forced = P.dft_forced;
+  for (int a = 0; a < 3; ++a) I->tile_forced[a] = P.tile_forced[a];
   I->parent = &P;
   I->paired = false;
   I->zg = P.zg;
@@ -935,6 +936,8 @@ extern "C" fmbem_status fmbem_plan_create(const fmbem_cell_mesh* mesh, const fmb
   if (desc->precisions & ~3u) return FMBEM_ERR_INVALID_ARG;
   if (desc->dft_schedule < FMBEM_DFT_AUTO || desc->dft_schedule > FMBEM_DFT_FUSED_MFMA) return FMBEM_ERR_INVALID_ARG;
   if (desc->halfspace != 0 && desc->halfspace != 1) return FMBEM_ERR_INVALID_ARG;
+  for (int a = 0; a < 3; ++a)
+    if (desc->tile_shape[a] < 0 || desc->tile_shape[a] > FMBEM_TILE_SHAPES) return FMBEM_ERR_INVALID_ARG;
   if (desc->halfspace == 1) {
     if (!std::isfinite(desc->plane_z) || !std::isfinite(desc->reflection_re) || !std::isfinite(desc->reflection_im))
       return FMBEM_ERR_INVALID_ARG;
@@ -1019,6 +1022,7 @@ extern "C" fmbem_status fmbem_plan_create(const fmbem_cell_mesh* mesh, const fmb
   }
   P->precisions = desc->precisions == 0 ? 1u : desc->precisions;
   P->dft_forced = desc->dft_schedule - 1;
+  for (int a = 0; a < 3; ++a) P->tile_forced[a] = desc->tile_shape[a] - 1;
   // near offsets (Chebyshev radius, axes with a single cell dropped)
   int rr[3];
   for (int a = 0; a < 3; ++a) rr[a] = P->grid[a] > 1 ? std::min(P->near_radius[a], P->grid[a] - 1) : 0;

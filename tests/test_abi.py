@@ -42,7 +42,7 @@ def _desc(**kw):
     d.alpha_re = d.alpha_im = math.nan
     d.precisions = 3
     for key, v in kw.items():
-        if key in ("grid", "pitch", "fft_shape", "near_radius"):
+        if key in ("grid", "pitch", "fft_shape", "near_radius", "tile_shape"):
             for a in range(3):
                 getattr(d, key)[a] = v[a]
         else:
@@ -59,7 +59,7 @@ def _mesh(v, t):
 
 @pytest.mark.parametrize("case", ["null", "bad_index", "degenerate", "order", "fft", "k", "grid", "formulation",
                                   "nan_vertex", "radius", "dft_schedule", "halfspace_flag", "halfspace_grid",
-                                  "halfspace_crossing", "halfspace_nan"])
+                                  "halfspace_crossing", "halfspace_nan", "tile_shape_high", "tile_shape_negative"])
 def test_plan_create_rejects_invalid_arguments(case):
     lib = fm.load()
     v, t = icosphere(1, 0.1)
@@ -96,6 +96,10 @@ def test_plan_create_rejects_invalid_arguments(case):
         desc = _desc(halfspace=1, plane_z=0.05, reflection_re=1.0)
     elif case == "halfspace_nan":
         desc = _desc(halfspace=1, plane_z=math.nan)
+    elif case == "tile_shape_high":
+        desc = _desc(tile_shape=(0, 0, 11))
+    elif case == "tile_shape_negative":
+        desc = _desc(tile_shape=(-1, 0, 0))
     mesh, keep = _mesh(v, t)
     assert lib.fmbem_plan_create(ct.byref(mesh), ct.byref(desc), None, ct.byref(out)) == 1
     assert out.value is None

@@ -141,6 +141,25 @@ def test_dft_schedules_match_oracle(cases, name):
         assert np.array_equal(out["axes"], out["fused"])
 
 
+@pytest.mark.parametrize("name", ["sphere80_line7", "sphere80_4x2_nt12"])
+def test_every_tile_shape_matches_oracle(cases, name):
+    # every tile shape of the near-field + S2M, L2T and M2L GEMM launches, forced through the plan
+    # descriptor (the autotuner runs only the fastest): 9 RHS take the M2L GEMM; p = 81 and 169
+    # leave ragged row tiles and a ragged last k step, with enough full k steps for the shapes
+    # that keep two steps of loads in flight
+    import paper_2201_12050_amd as fm
+    F, P, lat = cases[name]
+    v, t, pitch = _geometry(CASES[name][0])
+    x = random_complex((9, lat.n_cells, F.n), 4242)
+    ref = F.matvec(x)
+    xd = torch.from_numpy(x).cuda()
+    for shape in range(1, 11):
+        Q = fm.Plan(v, t, lat.grid, pitch, F.k, F.order, "bm", tile_shape=(shape, shape, shape))
+        assert rel(Q.matvec(xd, precision="fp64").cpu().numpy(), ref) < 1e-12, shape
+        assert rel(Q.matvec(xd.to(torch.complex64), precision="fp32").cpu().numpy(), ref) < 1e-5, shape
+        Q.close()
+
+
 def test_dft_mfma_long_axis_matches_oracle():
     # 2 x 40 lattice: 79 bins along axis 1, so the fused matrix-core DFT takes the output tiles of
     # a forward line in two groups and the inverse first pass has more inputs per line than its
