@@ -160,6 +160,47 @@ def test_every_tile_shape_matches_oracle(cases, name):
         Q.close()
 
 
+def test_more_than_256_moments_matches_oracle():
+    # n_t = 16: p = 289 > 256 takes the one-row-per-thread form of the M2L GEMV (R = 1, 3) and the
+    # M2L GEMM with three row tiles of 128 (R = 9)
+    import paper_2201_12050_amd as fm
+    v, t = icosphere(1, 0.1)
+    lat = Lattice((3, 1, 1), (0.3, 0.3, 0.3))
+    k = 2 * np.pi * 2000.0 / 343.0
+    F = op.FMPBEM(v, t, lat, k, 16, -1j / k)
+    P = fm.Plan(v, t, lat.grid, lat.pitch, k, 16)
+    for R in (1, 3, 9):
+        x = random_complex((R, lat.n_cells, F.n), 600 + R)
+        ref = F.matvec(x)
+        xd = torch.from_numpy(x).cuda()
+        assert rel(P.matvec(xd, precision="fp64").cpu().numpy(), ref) < 1e-12, R
+        assert rel(P.matvec(xd.to(torch.complex64), precision="fp32").cpu().numpy(), ref) < 1e-5, R
+    P.close()
+
+
+def test_maximum_order_matches_dense_operator():
+    # n_t = 20 (p = 441), the largest order the plan accepts, at 4 kHz (k d = 44 at the far
+    # offsets, above 2 n_t): the multipole operator against the dense direct-kernel product within
+    # the truncation error of the expansion (the oracle's own multipole apply is 1.1e-6 from it
+    # here); FP32 against FP64
+    import paper_2201_12050_amd as fm
+    v, t = icosphere(1, 0.1)
+    lat = Lattice((3, 1, 1), (0.3, 0.3, 0.3))
+    k = 2 * np.pi * 4000.0 / 343.0
+    A = bem.dense_exact(v, t, lat, k, -1j / k)
+    P = fm.Plan(v, t, lat.grid, lat.pitch, k, 20)
+    assert P.p == 441
+    for R in (1, 9):
+        x = random_complex((R, lat.n_cells, t.shape[0]), 700 + R)
+        ref = (A @ x.reshape(R, -1).T).T
+        xd = torch.from_numpy(x).cuda()
+        y64 = P.matvec(xd, precision="fp64").cpu().numpy().reshape(R, -1)
+        assert rel(y64, ref) < 1e-5, R
+        y32 = P.matvec(xd.to(torch.complex64), precision="fp32").cpu().numpy().reshape(R, -1)
+        assert rel(y32, y64) < 1e-5, R
+    P.close()
+
+
 def test_dft_mfma_long_axis_matches_oracle():
     # 2 x 40 lattice: 79 bins along axis 1, so the fused matrix-core DFT takes the output tiles of
     # a forward line in two groups and the inverse first pass has more inputs per line than its
