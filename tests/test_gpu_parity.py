@@ -201,6 +201,30 @@ def test_maximum_order_matches_dense_operator():
     P.close()
 
 
+def test_empty_inputs_are_rejected(tiny):
+    # zero and negative counts of right-hand sides or points return FMBEM_ERR_INVALID_ARG before any
+    # work is queued, and the plan stays usable
+    import ctypes as ct
+    from paper_2201_12050_amd import _lib
+    w, _, P = tiny["bm"]
+    lib = P._lib
+    n = w.lattice.n_cells * w.n_dof_cell
+    x = torch.zeros((1, n), dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(x)
+    xp, yp = ct.c_void_p(x.data_ptr()), ct.c_void_p(y.data_ptr())
+    for r in (0, -1):
+        assert lib.fmbem_matvec(P._h, 0, r, xp, yp, None, 0, None) == 1
+        info = (_lib.SolveInfo * 1)()
+        assert lib.fmbem_solve(P._h, ct.byref(_lib.solve_opts()), r, xp, yp, info, None) == 1
+    pts = np.zeros((1, 3))
+    dp = pts.ctypes.data_as(ct.POINTER(ct.c_double))
+    assert lib.fmbem_field(P._h, 1, xp, 0, dp, yp, yp, None) == 1
+    assert lib.fmbem_insertion_loss(1, 0, yp, yp, yp, None) == 1
+    torch.cuda.synchronize()
+    xr = torch.from_numpy(random_complex((1, n), 88)).cuda()
+    assert rel(P.matvec(xr).cpu().numpy(), P.matvec(xr).cpu().numpy()) == 0.0
+
+
 def test_dft_mfma_long_axis_matches_oracle():
     # 2 x 40 lattice: 79 bins along axis 1, so the fused matrix-core DFT takes the output tiles of
     # a forward line in two groups and the inverse first pass has more inputs per line than its
