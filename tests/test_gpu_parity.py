@@ -82,9 +82,9 @@ def test_operator_data_matches_oracle(cases, name):
 
 
 @pytest.mark.parametrize("name", list(CASES))
-@pytest.mark.parametrize("R", [1, 3, 9])
+@pytest.mark.parametrize("R", [1, 3, 9, 32])
 def test_matvec_matches_oracle(cases, name, R):
-    # R = 9 takes the batched MFMA GEMM form of the per-bin M2L product
+    # R = 9 and 32 take the batched MFMA GEMM form of the per-bin M2L product
     F, P, lat = cases[name]
     x = random_complex((R, lat.n_cells, F.n), 100 + R)
     ref = F.matvec(x)
@@ -144,13 +144,13 @@ def test_dft_schedules_match_oracle(cases, name):
 @pytest.mark.parametrize("name", ["sphere80_line7", "sphere80_4x2_nt12"])
 def test_every_tile_shape_matches_oracle(cases, name):
     # every tile shape of the near-field + S2M, L2T and M2L GEMM launches, forced through the plan
-    # descriptor (the autotuner runs only the fastest): 9 RHS take the M2L GEMM; p = 81 and 169
+    # descriptor (the autotuner runs only the fastest): 24 RHS take the M2L GEMM; p = 81 and 169
     # leave ragged row tiles and a ragged last k step, with enough full k steps for the shapes
     # that keep two steps of loads in flight
     import paper_2201_12050_amd as fm
     F, P, lat = cases[name]
     v, t, pitch = _geometry(CASES[name][0])
-    x = random_complex((9, lat.n_cells, F.n), 4242)
+    x = random_complex((24, lat.n_cells, F.n), 4242)
     ref = F.matvec(x)
     xd = torch.from_numpy(x).cuda()
     for shape in range(1, 11):
