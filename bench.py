@@ -410,7 +410,7 @@ def main():
     ap.add_argument("--serving-modes", nargs="*", default=["fp32"], choices=["fp32", "fp64"])
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         return 2
 
