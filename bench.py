@@ -309,7 +309,7 @@ def serving(fm, torch, args, mode, rate):
     n_warm, n_meas = args.serving_warmup, args.serving_requests
     reqs = serving_stream(n_warm + n_meas, rate=rate)
     E = fm.Engine(hbm_budget_bytes=int(args.serving_budget_gib * 2**30), max_slots=args.serving_slots)
-    opts = dict(tol=args.tol, inner=mode, ortho=args.ortho)
+    opts = dict(tol=args.tol, inner=mode, ortho=args.ortho, max_iters=args.serving_max_iters)
     rng = np.random.default_rng(2201120506)
     sampled = set(int(i) for i in rng.choice(np.arange(n_warm, n_warm + n_meas), size=min(8, n_meas), replace=False))
     ready = queue.Queue()
@@ -399,6 +399,8 @@ def main():
                     help="frequencies of the barrier-on-ground sweep (0: skip)")
     ap.add_argument("--serving-requests", type=int, default=100, help="measured requests of the serving run")
     ap.add_argument("--serving-warmup", type=int, default=10)
+    ap.add_argument("--serving-max-iters", type=int, default=4000,
+                    help="GMRES iteration cap of a serving request (slowly converging lattices need more than 1000)")
     ap.add_argument("--serving-rates", type=float, nargs="*", default=[20.0, 8.0],
                     help="Poisson arrival rates (requests/s), one run each")
     ap.add_argument("--barrier-freqs", type=int, default=8, help="frequencies of the barrier sweep (0: skip)")
