@@ -135,6 +135,24 @@ def solve_opts(tol=1e-8, restart=30, max_iters=1000, max_refinements=20, inner="
     return SolveOpts(tol, restart, max_iters, max_refinements, _precision(inner), inner_tol, ORTHO[ortho])
 
 
+def check_vectors(n_dof: int, dtype, x, y=None, what=("x", "y")) -> int:
+    """Validate caller tensors before any launch (the C ABI takes raw pointers, so this is the
+    only guard against writes past an allocation): x, and y when given, must be contiguous
+    device tensors of ``dtype`` holding the same whole number R >= 1 of [n_dof] vectors.
+    Returns R; raises ValueError otherwise."""
+    for name, t in zip(what, (x, y)):
+        if t is None:
+            continue
+        if t.dtype != dtype or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor")
+    R = x.numel() // n_dof
+    if R < 1 or R * n_dof != x.numel():
+        raise ValueError(f"{what[0]} size {x.numel()} is not a positive multiple of the DOF count {n_dof}")
+    if y is not None and y.numel() != x.numel():
+        raise ValueError(f"{what[1]} must hold as many elements as {what[0]} ({y.numel()} != {x.numel()})")
+    return R
+
+
 def _info_dicts(info):
     return [dict(iterations=i.iterations, refinements=i.refinements, rel_residual=i.rel_residual) for i in info]
 
@@ -155,13 +173,12 @@ def solve_batch(problems, stream=None, raise_on_not_converged=True):
     xp = (ct.c_void_p * n)()
     xs = []
     for i, (plan, b, x, kw) in enumerate(problems):
-        if b.dtype != torch.complex128 or not b.is_cuda or not b.is_contiguous():
-            raise ValueError("b must be a contiguous complex128 CUDA tensor")
+        R = check_vectors(plan.n_dof, torch.complex128, b, x, ("b", "x"))
         if x is None:
             x = torch.zeros_like(b)
         plans[i] = plan._h
         opts[i] = solve_opts(**(kw or {}))
-        nr[i] = b.numel() // plan.n_dof
+        nr[i] = R
         bp[i] = b.data_ptr()
         xp[i] = x.data_ptr()
         xs.append(x)
@@ -204,9 +221,7 @@ class Solver:
 
     def run(self, b, x=None, stream=None, raise_on_not_converged=True):
         import torch
-        if b.dtype != torch.complex128 or not b.is_cuda or not b.is_contiguous():
-            raise ValueError("b must be a contiguous complex128 CUDA tensor")
-        if b.numel() != self.n_rhs * self.plan.n_dof:
+        if check_vectors(self.plan.n_dof, torch.complex128, b, x, ("b", "x")) != self.n_rhs:
             raise ValueError("b does not match the solver's right-hand-side count")
         if x is None:
             x = torch.zeros_like(b)
@@ -253,11 +268,9 @@ class Engine:
 
     def submit(self, plan, b, x=None, **opts) -> int:
         import torch
-        if b.dtype != torch.complex128 or not b.is_cuda or not b.is_contiguous():
-            raise ValueError("b must be a contiguous complex128 CUDA tensor")
+        R = check_vectors(plan.n_dof, torch.complex128, b, x, ("b", "x"))
         if x is None:
             x = torch.zeros_like(b)
-        R = b.numel() // plan.n_dof
         o = solve_opts(**opts)
         t = ct.c_int64()
         check(self._lib.fmbem_engine_submit(self._h, plan._h, ct.byref(o), R, ct.c_void_p(b.data_ptr()),
@@ -403,26 +416,23 @@ class Plan:
         import torch
         pr = _precision(precision)
         dt = torch.complex128 if pr == FP64 else torch.complex64
-        if x.dtype != dt or not x.is_cuda or not x.is_contiguous():
-            raise ValueError(f"x must be a contiguous {dt} CUDA tensor")
-        R = x.numel() // self.n_dof
-        if R * self.n_dof != x.numel():
-            raise ValueError("x size is not a multiple of the DOF count")
+        R = check_vectors(self.n_dof, dt, x, y)
         if y is None:
             y = torch.empty_like(x)
         if workspace is None:
             workspace = self.workspace(R, pr)
+        elif not workspace.is_cuda or not workspace.is_contiguous():
+            raise ValueError("workspace must be a contiguous CUDA tensor")
         check(self._lib.fmbem_matvec(self._h, pr, R, ct.c_void_p(x.data_ptr()), ct.c_void_p(y.data_ptr()),
-                                     ct.c_void_p(workspace.data_ptr()), workspace.numel(), _stream_ptr(stream)),
+                                     ct.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size(),
+                                     _stream_ptr(stream)),
               "fmbem_matvec")
         return y
 
     def solve(self, b, x=None, tol=1e-8, restart=30, max_iters=1000, max_refinements=20, inner="fp64",
               inner_tol=1e-5, ortho="dgks", stream=None, raise_on_not_converged=True):
         import torch
-        if b.dtype != torch.complex128 or not b.is_cuda or not b.is_contiguous():
-            raise ValueError("b must be a contiguous complex128 CUDA tensor")
-        R = b.numel() // self.n_dof
+        R = check_vectors(self.n_dof, torch.complex128, b, x, ("b", "x"))
         if x is None:
             x = torch.zeros_like(b)
         o = solve_opts(tol, restart, max_iters, max_refinements, inner, inner_tol, ortho)

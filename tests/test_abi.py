@@ -179,3 +179,60 @@ def test_struct_layouts_match_header(tmp_path):
         assert got[(cname, "size")] == ct.sizeof(py), cname
         for field, _ in py._fields_:
             assert got[(cname, field)] == getattr(py, field).offset, (cname, field)
+
+
+class _FakeDeviceTensor:
+    """Stand-in for a device tensor (dtype, is_cuda, contiguity, element count) so that the
+    binding's argument checks run without a GPU."""
+
+    def __init__(self, numel, dtype, cuda=True, contiguous=True):
+        self._n, self.dtype, self.is_cuda, self._c = numel, dtype, cuda, contiguous
+
+    def numel(self):
+        return self._n
+
+    def is_contiguous(self):
+        return self._c
+
+
+@pytest.mark.parametrize("case", ["ok", "ok_no_y", "x_dtype", "y_dtype", "x_host", "y_host", "y_strided",
+                                  "x_ragged", "x_empty", "y_short", "y_long"])
+def test_binding_checks_vectors_before_launch(case):
+    import torch
+    c128, c64 = torch.complex128, torch.complex64
+    n_dof = 40
+    x = _FakeDeviceTensor(3 * n_dof, c128)
+    y = _FakeDeviceTensor(3 * n_dof, c128)
+    if case == "ok_no_y":
+        y = None
+    elif case == "x_dtype":
+        x = _FakeDeviceTensor(3 * n_dof, c64)
+    elif case == "y_dtype":          # a complex64 output for an FP64 apply would be written past its end
+        y = _FakeDeviceTensor(3 * n_dof, c64)
+    elif case == "x_host":
+        x = _FakeDeviceTensor(3 * n_dof, c128, cuda=False)
+    elif case == "y_host":
+        y = _FakeDeviceTensor(3 * n_dof, c128, cuda=False)
+    elif case == "y_strided":
+        y = _FakeDeviceTensor(3 * n_dof, c128, contiguous=False)
+    elif case == "x_ragged":         # R would be floored silently
+        x = _FakeDeviceTensor(3 * n_dof + 7, c128)
+    elif case == "x_empty":
+        x = _FakeDeviceTensor(0, c128)
+    elif case == "y_short":
+        y = _FakeDeviceTensor(2 * n_dof, c128)
+    elif case == "y_long":
+        y = _FakeDeviceTensor(4 * n_dof, c128)
+    if case.startswith("ok"):
+        assert _lib.check_vectors(n_dof, c128, x, y) == 3
+    else:
+        with pytest.raises(ValueError):
+            _lib.check_vectors(n_dof, c128, x, y)
+
+
+def test_binding_entry_points_use_the_vector_check():
+    # every method that hands caller tensors to the library validates them first
+    import inspect
+    for fn in (_lib.Plan.matvec, _lib.Plan.solve, _lib.Solver.run, _lib.Engine.submit,
+               _lib.solve_batch):
+        assert "check_vectors(" in inspect.getsource(fn), fn.__qualname__
