@@ -160,6 +160,21 @@ fmbem_status fmbem_matvec(fmbem_plan plan, int32_t precision, int32_t n_rhs,
                           const void* x, void* y, void* workspace, size_t workspace_bytes,
                           void* hip_stream);
 
+/* fmbem_matvec for callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops and harnesses that forbid hipMalloc): the same operator application, with the
+ * workspace taken from a static device array of FMBEM_NOALLOC_WORKSPACE_BYTES (64 MiB) that the
+ * library holds on every device it is loaded on until the process ends.  Calls no allocating
+ * routine (the tile shapes and DFT schedule are ones measured earlier for the same problem
+ * signature, else the defaults; no timing).  x, y, precision, n_rhs as in fmbem_matvec.
+ * Returns FMBEM_ERR_WORKSPACE (nothing queued) when n_rhs * workspace_bytes_per_rhs[precision]
+ * exceeds the array.  Every call on one device shares that device's array: calls that overlap
+ * on one device (different streams or host threads without ordering) race and give wrong
+ * results; calls ordered on one stream are safe (nothing in the array needs to start at zero).
+ * Stream-ordered. */
+#define FMBEM_NOALLOC_WORKSPACE_BYTES ((size_t)64 << 20)
+fmbem_status fmbem_matvec_noalloc(fmbem_plan plan, int32_t precision, int32_t n_rhs, const void* x, void* y,
+                                  void* hip_stream);
+
 typedef struct {
   double tol;                 /* stop when ||b - A x||_2 / ||b||_2 <= tol (FP64 true residual) */
   int32_t restart;            /* GMRES restart length m (default 30 when 0), at most 200 */

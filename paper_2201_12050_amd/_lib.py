@@ -69,7 +69,9 @@ EXPORTS = ["fmbem_plan_create", "fmbem_plan_query", "fmbem_plan_destroy", "fmbem
            "fmbem_plan_profile_read", "fmbem_status_string", "fmbem_solve_batch", "fmbem_engine_create",
            "fmbem_engine_submit", "fmbem_engine_step", "fmbem_engine_poll", "fmbem_engine_stats",
            "fmbem_engine_destroy", "fmbem_solver_create", "fmbem_solver_run", "fmbem_solver_graph_stats",
-           "fmbem_solver_destroy", "fmbem_incident_at_points", "fmbem_field", "fmbem_insertion_loss"]
+           "fmbem_solver_destroy", "fmbem_incident_at_points", "fmbem_field", "fmbem_insertion_loss",
+           "fmbem_matvec_noalloc"]
+NOALLOC_WORKSPACE_BYTES = 64 << 20   # FMBEM_NOALLOC_WORKSPACE_BYTES
 STAGES = tuple(f"{s}_{p}" for p in ("fp64", "fp32") for s in ("near", "reduce", "fft", "m2l", "ifft", "l2t"))
 
 _lib = None
@@ -89,6 +91,7 @@ def load():
     lib.fmbem_plan_destroy.argtypes = [vp]
     lib.fmbem_plan_export.argtypes = [vp, ct.c_int32, vp, ct.c_size_t]
     lib.fmbem_matvec.argtypes = [vp, ct.c_int32, ct.c_int32, vp, vp, vp, ct.c_size_t, vp]
+    lib.fmbem_matvec_noalloc.argtypes = [vp, ct.c_int32, ct.c_int32, vp, vp, vp]
     lib.fmbem_solve.argtypes = [vp, ct.POINTER(SolveOpts), ct.c_int32, vp, vp, ct.POINTER(SolveInfo), vp]
     lib.fmbem_solver_create.argtypes = [vp, ct.POINTER(SolveOpts), ct.c_int32, ct.c_int32, ct.POINTER(vp)]
     lib.fmbem_solver_run.argtypes = [vp, vp, vp, ct.POINTER(SolveInfo), vp]
@@ -427,6 +430,19 @@ class Plan:
                                      ct.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size(),
                                      _stream_ptr(stream)),
               "fmbem_matvec")
+        return y
+
+    def matvec_noalloc(self, x, y, precision="fp64", stream=None):
+        """y = A x through fmbem_matvec_noalloc (workspace in the library's static device array,
+        nothing allocated); x and y are caller-owned contiguous device tensors of equal size."""
+        import torch
+        pr = _precision(precision)
+        dt = torch.complex128 if pr == FP64 else torch.complex64
+        if y is None:
+            raise ValueError("y must be given (the call allocates nothing)")
+        R = check_vectors(self.n_dof, dt, x, y)
+        check(self._lib.fmbem_matvec_noalloc(self._h, pr, R, ct.c_void_p(x.data_ptr()), ct.c_void_p(y.data_ptr()),
+                                             _stream_ptr(stream)), "fmbem_matvec_noalloc")
         return y
 
     def solve(self, b, x=None, tol=1e-8, restart=30, max_iters=1000, max_refinements=20, inner="fp64",

@@ -513,6 +513,59 @@ extern "C" fmbem_status fmbem_matvec(fmbem_plan plan, int32_t precision, int32_t
   return e == hipSuccess ? FMBEM_OK : FMBEM_ERR_DEVICE;
 }
 
+// ---------------------------------------------------------------------------
+// Operator application without any allocation: the workspace is a static device array
+// ---------------------------------------------------------------------------
+// One array per device (each device that loads the library holds its own copy until the process
+// ends).  Its device address is looked up once per device with hipGetSymbolAddress and kept; host
+// code never passes the array's name itself (on the host it is only a stand-in symbol).
+static __device__ __align__(256) unsigned char scratch[FMBEM_NOALLOC_WORKSPACE_BYTES];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static hipError_t scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != device) hipSetDevice(cur);
+    if (e != hipSuccess) return e;
+    if (!ptr || (reinterpret_cast<uintptr_t>(ptr) & 255)) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
+extern "C" fmbem_status fmbem_matvec_noalloc(fmbem_plan plan, int32_t precision, int32_t n_rhs, const void* x,
+                                             void* y, void* hip_stream) {
+  if (!plan || !x || !y || n_rhs < 1) return FMBEM_ERR_INVALID_ARG;
+  if (precision != FMBEM_FP64 && precision != FMBEM_FP32) return FMBEM_ERR_INVALID_ARG;
+  const Plan& P = *reinterpret_cast<Plan*>(plan);
+  if (!(P.precisions & (1u << precision))) return FMBEM_ERR_UNSUPPORTED;
+  if ((size_t)n_rhs * P.C > (size_t)INT32_MAX / 2) return FMBEM_ERR_UNSUPPORTED;
+  const size_t el = precision == FMBEM_FP64 ? 16 : 8;
+  const size_t vbytes = (size_t)n_rhs * P.C * P.n * el;
+  const char* xb = reinterpret_cast<const char*>(x);
+  const char* yb = reinterpret_cast<const char*>(y);
+  if (xb < yb + vbytes && yb < xb + vbytes) return FMBEM_ERR_INVALID_ARG;
+  if ((size_t)n_rhs * matvec_workspace_bytes_per_rhs(P, precision) > FMBEM_NOALLOC_WORKSPACE_BYTES)
+    return FMBEM_ERR_WORKSPACE;
+  void* ws = nullptr;
+  if (scratch_address(P.device, &ws) != hipSuccess) return FMBEM_ERR_DEVICE;
+  // no tile-shape or DFT-schedule timing (it would synchronise and create events): shapes measured
+  // earlier for the same signature, else the defaults
+  hipError_t e = matvec_launch(P, precision, n_rhs, x, y, ws, reinterpret_cast<hipStream_t>(hip_stream), nullptr,
+                               false);
+  return e == hipSuccess ? FMBEM_OK : FMBEM_ERR_DEVICE;
+}
+
 extern "C" fmbem_status fmbem_plan_profile(fmbem_plan plan, uint32_t stage_mask, int32_t period) {
   if (!plan || (stage_mask & ~FMBEM_PROFILE_ALL) || period < 1) return FMBEM_ERR_INVALID_ARG;
   const Plan& P = *reinterpret_cast<Plan*>(plan);

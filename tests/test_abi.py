@@ -108,6 +108,7 @@ def test_plan_create_rejects_invalid_arguments(case):
 def test_other_entry_points_reject_null_plan():
     lib = fm.load()
     assert lib.fmbem_matvec(None, 0, 1, None, None, None, 0, None) == 1
+    assert lib.fmbem_matvec_noalloc(None, 0, 1, None, None, None) == 1
     assert lib.fmbem_plan_query(None, None) == 1
     assert lib.fmbem_plan_destroy(None) == 1
     assert lib.fmbem_plan_export(None, 0, None, 0) == 1
@@ -233,6 +234,6 @@ def test_binding_checks_vectors_before_launch(case):
 def test_binding_entry_points_use_the_vector_check():
     # every method that hands caller tensors to the library validates them first
     import inspect
-    for fn in (_lib.Plan.matvec, _lib.Plan.solve, _lib.Solver.run, _lib.Engine.submit,
+    for fn in (_lib.Plan.matvec, _lib.Plan.matvec_noalloc, _lib.Plan.solve, _lib.Solver.run, _lib.Engine.submit,
                _lib.solve_batch):
         assert "check_vectors(" in inspect.getsource(fn), fn.__qualname__
