@@ -127,46 +127,62 @@ class FMPBEM:
         return out
 
 
-def sampled_apply(vertices, triangles, lattice, k, order, alpha, x, dofs, near_radius=(1, 1, 1)):
-    """(A x)[:, dof] of the O2 operator for the listed DOFs only, each computed from
-    its own row of near blocks (integrated for that collocation point alone) and
-    the far chain U0[a] sum_j K_{i-j} V0 x_j.  For lattices too large to
-    materialise S_d.  x: [R, C, n]; returns [R, len(dofs)]."""
+def sampled_apply(vertices, triangles, lattice, k, order, alpha, x, dofs, near_radius=(1, 1, 1), chunk=256):
+    """(A x)[:, dof] of the O2 operator for the listed DOFs only, for lattices too large
+    to materialise S_d.  Near field: for every cell holding a listed DOF, the rows of its
+    near blocks S_d at the listed elements, each integrated for its collocation point
+    alone.  Far field: U0[a] sum_j K_{i-j} V0 x_j, the translations K_d formed ``chunk``
+    offsets at a time so that memory stays bounded on large lattices.
+    x: [R, C, n]; returns [R, len(dofs)]."""
     x = np.asarray(x, dtype=np.complex128)
     grid = tuple(lattice.grid)
     n = int(np.asarray(triangles).shape[0])
+    R = x.shape[0]
     geom = bem.element_geometry(vertices, triangles)
     pitch = np.asarray(lattice.pitch)
     V0 = fmm.p2m(vertices, triangles, k, order)
     U0 = fmm.l2p(vertices, triangles, k, order, alpha)
-    m = x @ V0.T                                            # [R, C, p]
     near = bem.near_offsets(grid, near_radius)
     far = far_offsets(grid, near)
-    K = fmm.m2l(np.asarray(far, dtype=np.float64) * pitch[None, :], k, order) if far else None
     g = grid_coords(grid)
     gsz = np.asarray(grid)
-    out = np.zeros((x.shape[0], len(dofs)), dtype=np.complex128)
-    loc_cache = {}
-    for s, dof in enumerate(dofs):
-        i, a = divmod(int(dof), n)
-        val = np.zeros(x.shape[0], dtype=np.complex128)
+    dofs = [int(v) for v in dofs]
+    cells = sorted(set(d // n for d in dofs))
+
+    def source(i, d):
+        src = g[i] - np.asarray(d)
+        if np.all((src >= 0) & (src < gsz)):
+            return int(src[0] + grid[0] * (src[1] + grid[1] * src[2]))
+        return None
+
+    # near field: y_near[i][:, a] = sum_d S_d[a] x_{i-d}
+    near_val = {}
+    for i in cells:
+        rows = sorted(set(d % n for d in dofs if d // n == i))
+        acc = np.zeros((R, len(rows)), dtype=np.complex128)
         for d in near:
-            src = g[i] - np.asarray(d)
-            if np.all((src >= 0) & (src < gsz)):
-                j = int(src[0] + grid[0] * (src[1] + grid[1] * src[2]))
-                row = bem.block(geom, k, alpha, np.zeros(3), -np.asarray(d) * pitch, d == (0, 0, 0), rows=[a])[0]
-                val += x[:, j, :] @ row
-        if far:
-            if i not in loc_cache:
-                loc = np.zeros((x.shape[0], V0.shape[0]), dtype=np.complex128)
-                for t, d in enumerate(far):
-                    src = g[i] - np.asarray(d)
-                    if np.all((src >= 0) & (src < gsz)):
-                        j = int(src[0] + grid[0] * (src[1] + grid[1] * src[2]))
-                        loc += m[:, j, :] @ K[t].T
-                loc_cache[i] = loc
-            val += loc_cache[i] @ U0[a]
-        out[:, s] = val
+            j = source(i, d)
+            if j is None:
+                continue
+            blk = bem.block(geom, k, alpha, np.zeros(3), -np.asarray(d) * pitch, d == (0, 0, 0), rows=rows)
+            acc += x[:, j, :] @ blk.T
+        near_val[i] = dict(zip(rows, acc.T))
+    # far field: local expansion of every listed cell, then U0 at the listed elements
+    loc = {i: np.zeros((R, V0.shape[0]), dtype=np.complex128) for i in cells}
+    if far:
+        m = x @ V0.T                                            # [R, C, p]
+        for s in range(0, len(far), chunk):
+            ds = far[s:s + chunk]
+            K = fmm.m2l(np.asarray(ds, dtype=np.float64) * pitch[None, :], k, order)
+            for t, d in enumerate(ds):
+                for i in cells:
+                    j = source(i, d)
+                    if j is not None:
+                        loc[i] += m[:, j, :] @ K[t].T
+    out = np.zeros((R, len(dofs)), dtype=np.complex128)
+    for s, dof in enumerate(dofs):
+        i, a = divmod(dof, n)
+        out[:, s] = near_val[i][a] + loc[i] @ U0[a]
     return out
 
 

@@ -9,6 +9,7 @@ torch = pytest.importorskip("torch")
 from oracle import bem, operator as op, solve
 from workloads import icosphere, tube_segment, Lattice
 from workloads.rng import unit_directions
+from tolerance import rel
 
 pytestmark = pytest.mark.gpu
 
@@ -19,8 +20,6 @@ def _need_gpu():
         pytest.skip("no HIP device")
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
 # name: (geometry, grid, frequency Hz, n_t, n_rhs, inner precision)

@@ -11,6 +11,7 @@ torch = pytest.importorskip("torch")
 
 from oracle import bem
 from workloads import Lattice, config_barrier_r4b, icosphere, random_complex, tube_segment, unit_directions
+from tolerance import rel
 
 pytestmark = pytest.mark.gpu
 
@@ -21,8 +22,6 @@ def _need_gpu():
         pytest.skip("no HIP device")
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
 def _sphere_points(lat, rng):

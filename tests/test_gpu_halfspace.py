@@ -8,6 +8,7 @@ torch = pytest.importorskip("torch")
 
 from oracle import halfspace as hs, solve
 from workloads import Lattice, icosphere, random_complex, unit_directions
+from tolerance import rel
 
 pytestmark = pytest.mark.gpu
 
@@ -18,8 +19,6 @@ def _need_gpu():
         pytest.skip("no HIP device")
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
 CASES = {
@@ -66,7 +65,7 @@ def test_halfspace_dft_schedules(cases):
     x = random_complex((9, lat.n_cells, t.shape[0]), 31)
     ref = H.matvec(x)
     xd = torch.from_numpy(x).cuda()
-    for sched in ("axes", "fused", "gemm", "mfma"):
+    for sched in ("axes", "fused", "gemm", "mfma", "fft"):
         Q = fm.Plan(v, t, lat.grid, lat.pitch, k, H.order, halfspace=(zg, rp), dft_schedule=sched)
         assert rel(Q.matvec(xd, precision="fp64").cpu().numpy(), ref) < 1e-12, sched
         assert rel(Q.matvec(xd.to(torch.complex64), precision="fp32").cpu().numpy(), ref) < 1e-5, sched
