@@ -73,7 +73,9 @@ typedef struct {
   int32_t formulation;        /* fmbem_formulation */
   double alpha_re, alpha_im;  /* Burton-Miller coupling; both NaN => -i/k (Sec. 2.1) */
   int32_t near_radius[3];     /* near field: |d_a| <= near_radius_a cells (0 => 1) */
-  int32_t fft_shape[3];       /* 0 => 2 M_a - 1 (the smallest exact embedding); else >= 2 M_a - 1 (<= 8192) */
+  int32_t fft_shape[3];       /* 0 => 2 M_a on the axes of a lattice with M3 = 1 (even lengths for the
+                                 FFT schedule), 2 M_a - 1 (the smallest exact embedding) otherwise,
+                                 1 where M_a = 1; else >= 2 M_a - 1 (<= 8192) */
   uint32_t precisions;        /* bitmask (1<<FMBEM_FP64) | (1<<FMBEM_FP32) of resident copies;
                                  0 => FP64 only */
   int32_t dft_schedule;       /* FMBEM_DFT_*: how the grid DFT (Sec. 2.4) runs; AUTO measures the
@@ -112,6 +114,9 @@ typedef struct {
 #define FMBEM_DFT_GEMM 3    /* axis passes as MFMA GEMMs with the DFT matrices (N_a <= 128) */
 #define FMBEM_DFT_FUSED_MFMA 4 /* both axes of an N3 = 1 grid in one launch, as MFMA products with the
                                   DFT matrices, the intermediate in LDS (1 < N_a <= 128) */
+#define FMBEM_DFT_FFT 5     /* both axes of an N3 = 1 grid in one launch as mixed-radix FFTs on the
+                               vector units (radix 8, 4 or 2 by the axis length, else a direct
+                               DFT), the intermediate in LDS; the default where it applies */
 
 typedef struct {
   int32_t n_dof_cell;         /* n (triangles per cell) */

@@ -41,7 +41,7 @@ class PlanDesc(ct.Structure):
                 ("tile_shape", ct.c_int32 * 3)]
 
 
-DFT_SCHEDULE = {"auto": 0, "axes": 1, "fused": 2, "gemm": 3, "mfma": 4}
+DFT_SCHEDULE = {"auto": 0, "axes": 1, "fused": 2, "gemm": 3, "mfma": 4, "fft": 5}
 
 
 class PlanInfo(ct.Structure):

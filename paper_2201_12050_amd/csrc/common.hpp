@@ -301,8 +301,9 @@ hipError_t dft_gemm_launch(const NearJob& job, const DftGemm& dg, hipStream_t s)
 // removed from the inverse input (then Lambda of the canonical partner serves that bin).
 // schedule: 0 separate axis passes, 1 the fused two-axis kernel where it applies (else the
 // passes), 2 axis passes as MFMA GEMMs with the DFT matrices fmat (forward of axis a at
-// fmat[a], inverse at fmat[3 + a]) where they apply (else the passes), -1 the built-in rule
-// (fused for at most 256 channels, else the GEMM passes where they apply).
+// fmat[a], inverse at fmat[3 + a]) where they apply (else the passes), 3 both axes on the
+// matrix cores, 4 both axes as mixed-radix FFTs in one launch, -1 the built-in rule (the FFT
+// where it applies; else fused for at most 256 channels, the GEMM passes where they apply).
 template <typename T>
 hipError_t grid_dft_launch(void* buf, int channels, const int M[3], const int N[3], bool inverse,
                            bool pruned, hipStream_t s, int flip_p = 0, int schedule = -1,
@@ -316,6 +317,9 @@ bool dft_mfma_applies(int channels, const int M[3], const int N[3], bool pruned,
 // whether the fused two-axis kernel applies (N3 = 1, N1 > 1, pruned, one channel fits its LDS)
 template <typename T>
 bool dft_fused_applies(int channels, const int M[3], const int N[3], bool pruned);
+// whether the fused two-axis FFT applies (N3 = 1, pruned, the slab of one channel fits the LDS)
+template <typename T>
+bool dft_fft_applies(int channels, const int M[3], const int N[3], bool pruned);
 
 // column stride (complex elements) of the per-bin column-major Lambda blocks
 int lambda_ld(int p);

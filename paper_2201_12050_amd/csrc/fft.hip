@@ -505,11 +505,395 @@ bool dft_gemm_applies(int channels, const int M[3], const int N[3], bool pruned,
   return true;
 }
 
+// ---------------------------------------------------------------------------
+// Schedule 4: both axes of an N3 = 1 grid in one launch as mixed-radix FFTs on the vector
+// units.  A line of length N = P Q is split into P interleaved output sets: task t < P forms
+// the outputs o = t + P s (s < Q) from the inputs j < nin as
+//   z_t[q] = w^(q t) sum_u x[Q u + q] w^(Q u t)                (a pruned length-P stage, the "fold")
+//   out[t + P s] = sum_{q < Q} z_t[q] e^(sign 2 pi i q s / Q)   (radix-2 length-Q DFT in registers)
+// with w = e^(sign 2 pi i / N); this is exact because w^(j (t + P s)) = w^(j t) e^(sign 2 pi i (j mod Q) s / Q).
+// A line costs about P nin + P Q (1 + log2 Q) complex operations against N nin for the direct
+// DFT, only the inputs that exist are read (pruned input) and only the outputs that are kept are
+// written (cropped output).  The radix Q of an axis depends on its length alone (the largest of
+// 8, 4, 2, 1 dividing N), so every channel is summed in the same order whatever the number of
+// channels.
+//
+// One workgroup per slice of CT channels; the slice's intermediate T (one transformed axis, the
+// other still pruned) sits in LDS.  The axis transformed first is the one that makes the two
+// passes cheaper (fewer fold products, see fft_first_axis).  Forward: pass A reads the inputs
+// X (M1 x M0) from the grid and transforms axis a into T (M_b lines of N_a); pass B transforms
+// axis b of T and writes all N1 x N0 bins (the factor D on the flipped bins of odd-degree
+// channels).  Inverse: pass A reads all bins (D removed) and transforms axis a into T (N_b lines
+// of M_a); pass B transforms axis b and writes the first M_b x M_a entries.  Every input of
+// the slice is read in pass A and every output written in pass B, after a barrier, so the
+// transform runs in place.  A task covers CP adjacent channels (one 16-byte access for two FP32
+// or one FP64 channel), which share its twiddles.
+template <typename T, int CP> struct FftPack { cplx<T> c[CP]; };
+
+// a += b c as four fused multiply-adds (two per component)
+__device__ inline void fcma(cplx<float>& a, cplx<float> b, cplx<float> c) {
+  a.x = __builtin_fmaf(b.x, c.x, a.x);
+  a.x = __builtin_fmaf(-b.y, c.y, a.x);
+  a.y = __builtin_fmaf(b.x, c.y, a.y);
+  a.y = __builtin_fmaf(b.y, c.x, a.y);
+}
+__device__ inline void fcma(cplx<double>& a, cplx<double> b, cplx<double> c) {
+  a.x = __builtin_fma(b.x, c.x, a.x);
+  a.x = __builtin_fma(-b.y, c.y, a.x);
+  a.y = __builtin_fma(b.x, c.y, a.y);
+  a.y = __builtin_fma(b.y, c.x, a.y);
+}
+
+// a b with an explicit rounding order (the same in every instantiation of the FFT kernels)
+__device__ inline cplx<float> fcmul(cplx<float> a, cplx<float> b) {
+  return mk<float>(__builtin_fmaf(a.x, b.x, -(a.y * b.y)), __builtin_fmaf(a.x, b.y, a.y * b.x));
+}
+__device__ inline cplx<double> fcmul(cplx<double> a, cplx<double> b) {
+  return mk<double>(__builtin_fma(a.x, b.x, -(a.y * b.y)), __builtin_fma(a.x, b.y, a.y * b.x));
+}
+
+template <typename T, int CP>
+__device__ inline FftPack<T, CP> fft_ld(const cplx<T>* p) {
+  FftPack<T, CP> r;
+  if constexpr (CP == 2) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    r.c[0] = mk<T>(v.x, v.y);
+    r.c[1] = mk<T>(v.z, v.w);
+  } else {
+    r.c[0] = *p;
+  }
+  return r;
+}
+
+template <typename T, int CP>
+__device__ inline void fft_st(cplx<T>* p, const FftPack<T, CP>& v) {
+  if constexpr (CP == 2) {
+    *reinterpret_cast<float4*>(p) = make_float4(v.c[0].x, v.c[0].y, v.c[1].x, v.c[1].y);
+  } else {
+    *p = v.c[0];
+  }
+}
+
+// a * (S i), S = +1 or -1
+template <int S, typename T>
+__device__ inline cplx<T> mul_si(cplx<T> a) {
+  return S > 0 ? mk<T>(-a.y, a.x) : mk<T>(a.y, -a.x);
+}
+
+// in-place length-4 DFT with kernel e^(S 2 pi i / 4)
+template <int S, typename T>
+__device__ inline void dft4(cplx<T>& a0, cplx<T>& a1, cplx<T>& a2, cplx<T>& a3) {
+  const cplx<T> s0 = cadd<T>(a0, a2), s1 = csub<T>(a0, a2), s2 = cadd<T>(a1, a3);
+  const cplx<T> s3 = mul_si<S, T>(csub<T>(a1, a3));
+  a0 = cadd<T>(s0, s2);
+  a2 = csub<T>(s0, s2);
+  a1 = cadd<T>(s1, s3);
+  a3 = csub<T>(s1, s3);
+}
+
+// in-place length-Q DFT, out[s] = sum_q z[q] e^(S 2 pi i q s / Q), natural order (radix 2)
+template <int Q, int S, typename T>
+__device__ inline void dft_q(cplx<T> (&z)[Q]) {
+  if constexpr (Q == 2) {
+    const cplx<T> a = z[0], b = z[1];
+    z[0] = cadd<T>(a, b);
+    z[1] = csub<T>(a, b);
+  } else if constexpr (Q == 4) {
+    dft4<S, T>(z[0], z[1], z[2], z[3]);
+  } else if constexpr (Q == 8) {
+    cplx<T> e0 = z[0], e1 = z[2], e2 = z[4], e3 = z[6];
+    cplx<T> o0 = z[1], o1 = z[3], o2 = z[5], o3 = z[7];
+    dft4<S, T>(e0, e1, e2, e3);
+    dft4<S, T>(o0, o1, o2, o3);
+    // o_k *= e^(S 2 pi i k / 8): (1 + S i)/sqrt2, S i, (-1 + S i)/sqrt2
+    const T h = (T)0.70710678118654752440;
+    o1 = mk<T>(h * (o1.x - S * o1.y), h * (o1.y + S * o1.x));
+    o2 = mul_si<S, T>(o2);
+    o3 = mk<T>(h * (-o3.x - S * o3.y), h * (-o3.y + S * o3.x));
+    z[0] = cadd<T>(e0, o0);
+    z[4] = csub<T>(e0, o0);
+    z[1] = cadd<T>(e1, o1);
+    z[5] = csub<T>(e1, o1);
+    z[2] = cadd<T>(e2, o2);
+    z[6] = csub<T>(e2, o2);
+    z[3] = cadd<T>(e3, o3);
+    z[7] = csub<T>(e3, o3);
+  }
+}
+
+// radix of an axis: the largest of 8, 4, 2 dividing its length, else 1 (a direct DFT)
+__host__ __device__ inline int fft_radix(int N) { return N % 8 == 0 ? 8 : N % 4 == 0 ? 4 : N % 2 == 0 ? 2 : 1; }
+
+// One pass over `lines` lines of length N = P Q: task (line L, residue t) of this thread's
+// channel pack forms the outputs o = t + P s < nout of line L from its inputs j < nin.
+// ld(L, j) returns a pack, st(L, o, pack) consumes one; tw[e] = e^(S 2 pi i e / N).  Tasks are
+// dealt to the LS thread rows r0, r0 + LS, ... of the workgroup (the threads of one channel pack).
+template <typename T, int CP, int Q, int S, typename Ld, typename St>
+__device__ inline void fft_pass(int lines, int r0, int LS, int N, int nin, int nout, const cplx<T>* tw, Ld ld,
+                                St st) {
+  const int P = N / Q;
+  const int tasks = lines * P;
+  for (int id = r0; id < tasks; id += LS) {
+    const int t = id % P, L = id / P;
+    if (t >= nout) continue;  // every output of the task cropped (o = t + P s >= t)
+    FftPack<T, CP> z[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int c = 0; c < CP; ++c) z[q].c[c] = mk<T>(0, 0);
+    // fold: z[q] = sum_u x[Q u + q] w^(Q u t), the exponent Q u t kept below N
+    const int step = Q * t;  // < N
+    int e = 0;
+    int j0 = 0;
+    for (; j0 + Q <= nin; j0 += Q) {
+      const cplx<T> w = tw[e];
+      FftPack<T, CP> x[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) x[q] = ld(L, j0 + q);
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int c = 0; c < CP; ++c) fcma(z[q].c[c], x[q].c[c], w);
+      e += step;
+      if (e >= N) e -= N;
+    }
+    if (j0 < nin) {
+      const cplx<T> w = tw[e];
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+        if (j0 + q < nin) {
+          const FftPack<T, CP> x = ld(L, j0 + q);
+#pragma unroll
+          for (int c = 0; c < CP; ++c) fcma(z[q].c[c], x.c[c], w);
+        }
+    }
+    // z[q] *= w^(q t) (q t < N), then the length-Q DFT of every channel
+#pragma unroll
+    for (int q = 1; q < Q; ++q) {
+      const cplx<T> w = tw[q * t];
+#pragma unroll
+      for (int c = 0; c < CP; ++c) z[q].c[c] = fcmul(z[q].c[c], w);
+    }
+#pragma unroll
+    for (int c = 0; c < CP; ++c) {
+      cplx<T> v[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) v[q] = z[q].c[c];
+      dft_q<Q, S, T>(v);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) z[q].c[c] = v[q];
+    }
+#pragma unroll
+    for (int s = 0; s < Q; ++s) {
+      const int o = t + P * s;
+      if (o < nout) st(L, o, z[s]);
+    }
+  }
+}
+
+// the pass with the radix of its axis (runtime, uniform over the workgroup)
+template <typename T, int CP, int S, typename Ld, typename St>
+__device__ inline void fft_pass_q(int lines, int r0, int LS, int N, int nin, int nout, const cplx<T>* tw, Ld ld,
+                                  St st) {
+  switch (fft_radix(N)) {
+    case 8: fft_pass<T, CP, 8, S>(lines, r0, LS, N, nin, nout, tw, ld, st); break;
+    case 4: fft_pass<T, CP, 4, S>(lines, r0, LS, N, nin, nout, tw, ld, st); break;
+    case 2: fft_pass<T, CP, 2, S>(lines, r0, LS, N, nin, nout, tw, ld, st); break;
+    default: fft_pass<T, CP, 1, S>(lines, r0, LS, N, nin, nout, tw, ld, st); break;
+  }
+}
+
+// whether bin (k0, k1) has a larger linear index k0 + N0 k1 than its partner (-k0, -k1)
+__device__ inline bool bin_after_partner(int k0, int k1, int N0, int N1) {
+  const int n1 = k1 == 0 ? 0 : N1 - k1;
+  if (k1 != n1) return k1 > n1;
+  return k0 > (k0 == 0 ? 0 : N0 - k0);
+}
+
+// fold products of the two passes (lines x residues x inputs) when axis a goes first
+__host__ __device__ inline long long fft_cost(const int M[3], const int N[3], bool inverse, int a) {
+  const int b = 1 - a;
+  const long long Pa = N[a] / fft_radix(N[a]), Pb = N[b] / fft_radix(N[b]);
+  if (!inverse) return (long long)M[b] * Pa * M[a] + (long long)N[a] * Pb * M[b];
+  return (long long)N[b] * Pa * N[a] + (long long)M[a] * Pb * N[b];
+}
+__host__ __device__ inline int fft_first_axis(const int M[3], const int N[3], bool inverse) {
+  return fft_cost(M, N, inverse, 1) < fft_cost(M, N, inverse, 0) ? 1 : 0;
+}
+
+// grid entry (k0, k1) at (k1 N0 + k0) channels; T entry (line, pos) at (line LT + pos) CT
+template <typename T, int CP, int S>
+__device__ inline void fft2_body(cplx<T>* __restrict__ buf, int channels, int CT, const int M[2], const int N[2],
+                                 int a, int flip_p, const cplx<T>* twa, const cplx<T>* twb, cplx<T>* Tm) {
+  const int b = 1 - a;
+  const int c0 = blockIdx.x * CT;
+  const int NCP = CT / CP;
+  const int npk = (min(CT, channels - c0) + CP - 1) / CP;  // packs of the slice in range
+  // the block size is a multiple of NCP, so a thread keeps its channel pack in every task
+  const int cp = threadIdx.x % NCP;
+  const int r0 = threadIdx.x / NCP, LS = blockDim.x / NCP;
+  const bool valid = cp < npk;
+  int odd = 0;  // bit c: channel c of the pack has odd degree n (factor D of the spectrum symmetry)
+  if (flip_p > 0 && valid)
+#pragma unroll
+    for (int c = 0; c < CP; ++c)
+      if (odd_degree(c0 + cp * CP + c, flip_p)) odd |= 1 << c;
+  auto negate = [&](FftPack<T, CP>& v) {
+#pragma unroll
+    for (int c = 0; c < CP; ++c)
+      if (odd & (1 << c)) v.c[c] = mk<T>(-v.c[c].x, -v.c[c].y);
+  };
+  const long long sa = a == 0 ? channels : (long long)N[0] * channels;  // grid stride along axis a
+  const long long sb = a == 0 ? (long long)N[0] * channels : channels;  // ... and along axis b
+  cplx<T>* g = buf + c0 + cp * CP;
+  cplx<T>* tp = Tm + cp * CP;
+  // bin (ka, kb) -> (k0, k1)
+  auto flipped = [&](int ka, int kb) {
+    return a == 0 ? bin_after_partner(ka, kb, N[0], N[1]) : bin_after_partner(kb, ka, N[0], N[1]);
+  };
+  if (S < 0) {
+    const int LT = N[a];  // T: M_b lines of N_a
+    // pass A: lines kb < M_b, axis a (M_a inputs -> N_a outputs) into T
+    if (valid)
+      fft_pass_q<T, CP, S>(
+          M[b], r0, LS, N[a], M[a], N[a], twa,
+          [&](int L, int j) { return fft_ld<T, CP>(g + L * sb + j * sa); },
+          [&](int L, int o, const FftPack<T, CP>& v) { fft_st<T, CP>(tp + ((size_t)L * LT + o) * CT, v); });
+    __syncthreads();
+    // pass B: lines ka < N_a, axis b (M_b inputs -> N_b outputs) to the grid, D on the flipped bins
+    if (valid)
+      fft_pass_q<T, CP, S>(
+          N[a], r0, LS, N[b], M[b], N[b], twb,
+          [&](int L, int j) { return fft_ld<T, CP>(tp + ((size_t)j * LT + L) * CT); },
+          [&](int L, int o, FftPack<T, CP> v) {
+            if (odd && flipped(L, o)) negate(v);
+            fft_st<T, CP>(g + L * sa + o * sb, v);
+          });
+  } else {
+    const int LT = M[a];  // T: N_b lines of M_a
+    // pass A: lines kb < N_b, axis a (all N_a bins, D removed -> M_a outputs) into T
+    if (valid)
+      fft_pass_q<T, CP, S>(
+          N[b], r0, LS, N[a], N[a], M[a], twa,
+          [&](int L, int j) {
+            FftPack<T, CP> v = fft_ld<T, CP>(g + L * sb + j * sa);
+            if (odd && flipped(j, L)) negate(v);
+            return v;
+          },
+          [&](int L, int o, const FftPack<T, CP>& v) { fft_st<T, CP>(tp + ((size_t)L * LT + o) * CT, v); });
+    __syncthreads();
+    // pass B: lines ia < M_a, axis b (N_b inputs -> the first M_b entries) to the grid
+    if (valid)
+      fft_pass_q<T, CP, S>(
+          M[a], r0, LS, N[b], N[b], M[b], twb,
+          [&](int L, int j) { return fft_ld<T, CP>(tp + ((size_t)j * LT + L) * CT); },
+          [&](int L, int o, const FftPack<T, CP>& v) { fft_st<T, CP>(g + L * sa + o * sb, v); });
+  }
+}
+
+constexpr int kFftThreads = 512;
+
+template <typename T, int CP>
+__global__ __launch_bounds__(kFftThreads) void fft2_kernel(cplx<T>* __restrict__ buf, int channels, int CT, int N0,
+                                                           int N1, int M0, int M1, int inverse, int a, int flip_p) {
+  extern __shared__ unsigned char smem_raw[];
+  const int N[2] = {N0, N1}, M[2] = {M0, M1};
+  cplx<T>* twa = reinterpret_cast<cplx<T>*>(smem_raw);  // [N_a]
+  cplx<T>* twb = twa + N[a];                            // [N_b]
+  constexpr int kAl = 16 / sizeof(cplx<T>);
+  cplx<T>* Tm = twa + (N0 + N1 + kAl - 1) / kAl * kAl;  // the slab, 16-byte aligned
+  const double sg = inverse ? 1.0 : -1.0;
+  for (int e = threadIdx.x; e < N0 + N1; e += blockDim.x) {
+    const int n = e < N[a] ? N[a] : N[1 - a], k = e < N[a] ? e : e - N[a];
+    double sn, cs;
+    sincospi(2.0 * k / n, &sn, &cs);
+    twa[e] = mk<T>((T)cs, (T)(sg * sn));
+  }
+  __syncthreads();
+  if (inverse)
+    fft2_body<T, CP, 1>(buf, channels, CT, M, N, a, flip_p, twa, twb, Tm);
+  else
+    fft2_body<T, CP, -1>(buf, channels, CT, M, N, a, flip_p, twa, twb, Tm);
+}
+
+// LDS bytes of the FFT schedule for a slice of CT channels (the larger direction's slab)
+template <typename T>
+static size_t fft2_lds(const int M[3], const int N[3], int CT) {
+  const size_t tw = (size_t)(N[0] + N[1] + 2) * sizeof(cplx<T>);
+  size_t slab = 0;
+  for (int inv = 0; inv < 2; ++inv) {
+    const int a = fft_first_axis(M, N, inv != 0), b = 1 - a;
+    slab = std::max(slab, (size_t)(inv ? N[b] * M[a] : M[b] * N[a]));
+  }
+  return tw + slab * CT * sizeof(cplx<T>);
+}
+
+template <typename T>
+bool dft_fft_applies(int channels, const int M[3], const int N[3], bool pruned) {
+  if (!pruned || channels < 1 || N[2] != 1 || M[2] != 1) return false;
+  if ((long long)N[0] * N[1] * channels > INT32_MAX) return false;
+  return fft2_lds<T>(M, N, 1) <= kLdsMax;
+}
+
+// channels per workgroup: 128 bytes of channels per grid entry (16 FP32 or 8 FP64), halved while
+// the launch would leave CUs without a workgroup or the slab would exceed 64 KB; CP channels per
+// task (two FP32 channels in one 16-byte access when the channel count is even)
+template <typename T>
+static hipError_t fft2_launch(cplx<T>* buf, int channels, const int M[3], const int N[3], bool inverse, int flip_p,
+                              hipStream_t s) {
+  const int CP = (sizeof(T) == 4 && channels % 2 == 0) ? 2 : 1;
+  int CT = 128 / (int)sizeof(cplx<T>);
+  while (CT > CP && ((channels + CT - 1) / CT < 256 || fft2_lds<T>(M, N, CT) > 64 * 1024)) CT /= 2;
+  const size_t lds = fft2_lds<T>(M, N, CT);
+  if (lds > kLdsMax) return hipErrorInvalidValue;
+  if (lds > 64 * 1024) {
+    static std::once_flag once;
+    static hipError_t attr = hipSuccess;
+    std::call_once(once, [] {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fft2_kernel<T, 1>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
+      if constexpr (sizeof(T) == 4)
+        if (e == hipSuccess)
+          e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fft2_kernel<T, 2>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
+      attr = e;
+    });
+    if (attr != hipSuccess) return attr;
+  }
+  const int a = fft_first_axis(M, N, inverse), b = 1 - a;
+  // threads: the larger pass's task count, whole waves, at most kFftThreads (a multiple of the
+  // channel packs per slice, so that every thread keeps one pack)
+  const int NCP = CT / CP;
+  const int Pa = N[a] / fft_radix(N[a]), Pb = N[b] / fft_radix(N[b]);
+  const long long ta = (long long)(inverse ? N[b] : M[b]) * Pa, tb = (long long)(inverse ? M[a] : N[a]) * Pb;
+  const int threads = (int)std::min<long long>(kFftThreads, (std::max(ta, tb) * NCP + 63) / 64 * 64);
+  const int blocks = (channels + CT - 1) / CT;
+  if constexpr (sizeof(T) == 4) {
+    if (CP == 2) {
+      hipLaunchKernelGGL((fft2_kernel<T, 2>), dim3(blocks), dim3(threads), lds, s, buf, channels, CT, N[0], N[1],
+                         M[0], M[1], inverse ? 1 : 0, a, flip_p);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((fft2_kernel<T, 1>), dim3(blocks), dim3(threads), lds, s, buf, channels, CT, N[0], N[1], M[0],
+                     M[1], inverse ? 1 : 0, a, flip_p);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t grid_dft_launch(void* bufv, int channels, const int M[3], const int N[3], bool inverse, bool pruned,
                            hipStream_t s, int flip_p, int schedule, const void* const* fmat) {
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(bufv);
-  if (schedule < 0) schedule = channels <= kDft2MaxChannels ? 1 : (channels >= kDftmMinChannels ? 3 : 2);
+  if (schedule < 0) {
+    if (dft_fft_applies<T>(channels, M, N, pruned))
+      schedule = 4;
+    else
+      schedule = channels <= kDft2MaxChannels ? 1 : (channels >= kDftmMinChannels ? 3 : 2);
+  }
+  if (schedule == 4) {
+    if (dft_fft_applies<T>(channels, M, N, pruned)) return fft2_launch<T>(buf, channels, M, N, inverse, flip_p, s);
+    schedule = 0;
+  }
   if (schedule == 3 && !dft_mfma_applies<T>(channels, M, N, pruned, fmat)) schedule = 2;
   if (schedule == 3) {
     const size_t lds = dftm_lds<T>(M, N, inverse);
@@ -600,5 +984,7 @@ template bool dft_fused_applies<double>(int, const int*, const int*, bool);
 template bool dft_mfma_applies<double>(int, const int*, const int*, bool, const void* const*);
 template bool dft_mfma_applies<float>(int, const int*, const int*, bool, const void* const*);
 template bool dft_fused_applies<float>(int, const int*, const int*, bool);
+template bool dft_fft_applies<double>(int, const int*, const int*, bool);
+template bool dft_fft_applies<float>(int, const int*, const int*, bool);
 
 }  // namespace fmbem

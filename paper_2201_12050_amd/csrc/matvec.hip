@@ -150,7 +150,8 @@ int cached_shape(int kind, const std::vector<NearJob>& jobs) {
 }
 
 // Autotuner of the DFT schedule (separate axis passes, the fused two-axis kernel, axis passes
-// as MFMA GEMMs with the plan's DFT matrices, or both axes fused on the matrix cores) of a plan's
+// as MFMA GEMMs with the plan's DFT matrices, both axes fused on the matrix cores, or both axes
+// as mixed-radix FFTs in one launch) of a plan's
 // grid with R right-hand sides, chosen for the forward and the inverse transform separately: on
 // the first application of a signature (precision, lattice, transform lengths, channels) where
 // more than one schedule applies, each runs a forward and an inverse transform on the workspace
@@ -166,14 +167,21 @@ static int dft_schedule(const Plan& P, int R, void* ws, hipStream_t s, bool tune
   const int prec = sizeof(T) == 8 ? 0 : 1;
   const int ch = R * P.p;
   if (P.n_far == 0) return 0;
-  const bool ok[4] = {true, dft_fused_applies<T>(ch, P.grid, P.fft, true),
-                      dft_gemm_applies<T>(ch, P.grid, P.fft, true, P.dftF[prec]),
-                      dft_mfma_applies<T>(ch, P.grid, P.fft, true, P.dftF[prec])};
-  if (!ok[1] && !ok[2] && !ok[3]) return 0;
+  constexpr int NS = 5;
+  const bool ok[NS] = {true, dft_fused_applies<T>(ch, P.grid, P.fft, true),
+                       dft_gemm_applies<T>(ch, P.grid, P.fft, true, P.dftF[prec]),
+                       dft_mfma_applies<T>(ch, P.grid, P.fft, true, P.dftF[prec]),
+                       dft_fft_applies<T>(ch, P.grid, P.fft, true)};
+  if (!ok[1] && !ok[2] && !ok[3] && !ok[4]) return 0;
   if (P.dft_forced >= 0) {
     const int f = ok[P.dft_forced] ? P.dft_forced : 0;
     return f | (f << 4);
   }
+  // where the FFT applies it is the fastest schedule (measured on the sphere lattices from 8 x 8 to
+  // 32 x 32 at 1 to 64 right-hand sides) and it is not timed against the others: its result per
+  // channel does not depend on the channel count, so an apply of many right-hand sides equals the
+  // applies of each alone bit for bit
+  if (ok[4]) return 4 | (4 << 4);
   const std::vector<long long> key{3, (long long)sizeof(T), P.grid[0], P.grid[1], P.grid[2],
                                    P.fft[0], P.fft[1], P.fft[2], ch};
   {
@@ -183,10 +191,12 @@ static int dft_schedule(const Plan& P, int R, void* ws, hipStream_t s, bool tune
   }
   if (!tune || capturing(s)) return -1;
   hipEvent_t a = nullptr, b = nullptr, c = nullptr;
-  float t[2][4] = {{1e30f, 1e30f, 1e30f, 1e30f}, {1e30f, 1e30f, 1e30f, 1e30f}};
+  float t[2][NS];
+  for (int d = 0; d < 2; ++d)
+    for (int v = 0; v < NS; ++v) t[d][v] = 1e30f;
   if (hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess && hipEventCreate(&c) == hipSuccess) {
     for (int sweep = 0; sweep < 2; ++sweep)
-      for (int v = 0; v < 4; ++v) {
+      for (int v = 0; v < NS; ++v) {
         if (!ok[v]) continue;
         if (grid_dft_launch<T>(ws, ch, P.grid, P.fft, false, true, s, P.flip_p(), v, P.dftF[prec]) != hipSuccess) continue;
         hipEventRecord(a, s);
@@ -207,7 +217,7 @@ static int dft_schedule(const Plan& P, int R, void* ws, hipStream_t s, bool tune
   if (c) hipEventDestroy(c);
   int best[2] = {0, 0};
   for (int d = 0; d < 2; ++d)
-    for (int v = 1; v < 4; ++v)
+    for (int v = 1; v < NS; ++v)
       if (t[d][v] < t[d][best[d]]) best[d] = v;
   const int code = best[0] | (best[1] << 4);
   std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -934,7 +934,7 @@ extern "C" fmbem_status fmbem_plan_create(const fmbem_cell_mesh* mesh, const fmb
   if (desc->order < 0 || desc->order > 20) return FMBEM_ERR_INVALID_ARG;
   if (desc->formulation != FMBEM_BURTON_MILLER && desc->formulation != FMBEM_CBIE) return FMBEM_ERR_INVALID_ARG;
   if (desc->precisions & ~3u) return FMBEM_ERR_INVALID_ARG;
-  if (desc->dft_schedule < FMBEM_DFT_AUTO || desc->dft_schedule > FMBEM_DFT_FUSED_MFMA) return FMBEM_ERR_INVALID_ARG;
+  if (desc->dft_schedule < FMBEM_DFT_AUTO || desc->dft_schedule > FMBEM_DFT_FFT) return FMBEM_ERR_INVALID_ARG;
   if (desc->halfspace != 0 && desc->halfspace != 1) return FMBEM_ERR_INVALID_ARG;
   for (int a = 0; a < 3; ++a)
     if (desc->tile_shape[a] < 0 || desc->tile_shape[a] > FMBEM_TILE_SHAPES) return FMBEM_ERR_INVALID_ARG;
@@ -999,9 +999,11 @@ extern "C" fmbem_status fmbem_plan_create(const fmbem_cell_mesh* mesh, const fmb
     P->near_radius[a] = desc->near_radius[a] == 0 ? 1 : desc->near_radius[a];
     P->C *= desc->grid[a];
     const int need = 2 * desc->grid[a] - 1;
-    // the DFT is a direct pruned transform over any length, so the smallest exact circulant
-    // embedding (2 M - 1 per axis) has the fewest bins and the least work
-    P->fft[a] = desc->fft_shape[a] > 0 ? desc->fft_shape[a] : need;
+    // any length N >= 2 M - 1 embeds the block Toeplitz product exactly; on lattices with M3 = 1
+    // the grid transform runs as FFTs over even lengths (radix 2, 4 or 8 by divisibility), so the
+    // default is 2 M there (one bin more per axis than the smallest embedding); 3-D lattices keep
+    // 2 M - 1 (the direct pruned axis passes take any length)
+    P->fft[a] = desc->fft_shape[a] > 0 ? desc->fft_shape[a] : (desc->grid[2] == 1 ? need + 1 : need);
     if (desc->grid[a] == 1) P->fft[a] = 1;
   }
   P->B = P->fft[0] * P->fft[1] * P->fft[2];

@@ -87,7 +87,7 @@ def test_plan_create_rejects_invalid_arguments(case):
     elif case == "radius":
         desc = _desc(near_radius=(4, 1, 1))
     elif case == "dft_schedule":
-        desc = _desc(dft_schedule=5)
+        desc = _desc(dft_schedule=6)
     elif case == "halfspace_flag":
         desc = _desc(halfspace=2, plane_z=0.2)
     elif case == "halfspace_grid":        # the second layer (z up to 0.4) crosses z = 0.2

@@ -11,6 +11,7 @@ torch = pytest.importorskip("torch")
 from oracle import bem, operator as op, solve
 from workloads import icosphere, tube_segment, Lattice, config_tiny, config_grid16
 from workloads.rng import random_complex, unit_directions
+from tolerance import rel
 
 pytestmark = pytest.mark.gpu
 
@@ -21,8 +22,6 @@ def _need_gpu():
         pytest.skip("no HIP device")
 
 
-def rel(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
 def _plan(fm_mod, v, t, grid, pitch, k, nt, formulation="bm"):
@@ -99,29 +98,32 @@ def test_matvec_matches_oracle(cases, name, R):
 
 
 def test_explicit_fft_shape_matches_oracle(cases):
-    # the default transform lengths are the minimal 2M - 1 (odd); an explicit even, larger
-    # embedding is exact as well and takes the other bin-pairing pattern (self-paired bins at
-    # N/2) through the DFT, Lambda and M2L
+    # the default transform lengths of a lattice with M3 = 1 are 2M (even, self-paired bins at
+    # N/2); the minimal odd embedding 2M - 1 and a larger one are exact as well and take the
+    # other radices and bin-pairing patterns through the DFT, Lambda and M2L
     import paper_2201_12050_amd as fm
     F, P, lat = cases["sphere80_5x3_ragged"]
-    assert P.info["fft_shape"] == (9, 5, 1)
+    assert P.info["fft_shape"] == (10, 6, 1)
+    assert cases["tube192_3x2x3"][1].info["fft_shape"] == (5, 3, 5)
     v, t, pitch = _geometry(1)
-    Q = fm.Plan(v, t, lat.grid, pitch, F.k, F.order, "bm", fft_shape=(12, 8, 0))
-    assert Q.info["fft_shape"] == (12, 8, 1)
-    for R in (1, 9):
-        x = random_complex((R, lat.n_cells, F.n), 300 + R)
-        ref = F.matvec(x)
-        xd = torch.from_numpy(x).cuda()
-        assert rel(Q.matvec(xd, precision="fp64").cpu().numpy(), ref) < 1e-12
-        assert rel(Q.matvec(xd.to(torch.complex64), precision="fp32").cpu().numpy(), ref) < 1e-5
+    for shape in ((9, 5, 0), (12, 8, 0)):
+        Q = fm.Plan(v, t, lat.grid, pitch, F.k, F.order, "bm", fft_shape=shape)
+        assert Q.info["fft_shape"] == shape[:2] + (1,)
+        for R in (1, 9):
+            x = random_complex((R, lat.n_cells, F.n), 300 + R)
+            ref = F.matvec(x)
+            xd = torch.from_numpy(x).cuda()
+            assert rel(Q.matvec(xd, precision="fp64").cpu().numpy(), ref) < 1e-12, shape
+            assert rel(Q.matvec(xd.to(torch.complex64), precision="fp32").cpu().numpy(), ref) < 1e-5, shape
+        Q.close()
 
 
 @pytest.mark.parametrize("name", ["sphere80_5x3_ragged", "tube192_3x2x3", "sphere80_4x2_nt12"])
 def test_dft_schedules_match_oracle(cases, name):
     # each way of running the grid DFT, forced through the plan descriptor: direct axis passes,
     # the fused two-axis kernel (2-D grids only; the 3-D tube lattice falls back to the passes)
-    # the axis passes as MFMA GEMMs with the DFT matrices, and both axes fused on the matrix
-    # cores (2-D grids only, else the passes)
+    # the axis passes as MFMA GEMMs with the DFT matrices, both axes fused on the matrix
+    # cores and both axes as mixed-radix FFTs (2-D grids only, else the passes)
     import paper_2201_12050_amd as fm
     F, P, lat = cases[name]
     kind = CASES[name][0]
@@ -131,7 +133,7 @@ def test_dft_schedules_match_oracle(cases, name):
         ref = F.matvec(x)
         xd = torch.from_numpy(x).cuda()
         out = {}
-        for sched in ("axes", "fused", "gemm", "mfma"):
+        for sched in ("axes", "fused", "gemm", "mfma", "fft"):
             Q = fm.Plan(v, t, lat.grid, pitch, F.k, F.order, "bm", dft_schedule=sched)
             out[sched] = Q.matvec(xd, precision="fp64").cpu().numpy()
             assert rel(out[sched], ref) < 1e-12, (sched, R)
@@ -237,11 +239,38 @@ def test_dft_mfma_long_axis_matches_oracle():
     x = random_complex((3, lat.n_cells, t.shape[0]), 911)
     ref = F.matvec(x)
     xd = torch.from_numpy(x).cuda()
-    for sched in ("axes", "mfma"):
+    for sched in ("axes", "mfma", "fft"):
         Q = fm.Plan(v, t, lat.grid, lat.pitch, k, 3, "bm", dft_schedule=sched)
         assert rel(Q.matvec(xd, precision="fp64").cpu().numpy(), ref) < 1e-12, sched
         assert rel(Q.matvec(xd.to(torch.complex64), precision="fp32").cpu().numpy(), ref) < 1e-5, sched
         Q.close()
+
+
+@pytest.mark.parametrize("grid,shape", [((6, 5, 1), (0, 0, 0)), ((4, 3, 1), (0, 0, 0)), ((1, 7, 1), (0, 0, 0)),
+                                        ((5, 4, 1), (9, 7, 0)), ((3, 3, 1), (8, 5, 0))])
+def test_fft_radices_match_oracle(grid, shape):
+    # the mixed-radix FFT schedule over every radix: default lengths 2M give radix 4 x 2 (12 x 10),
+    # 8 x 2 (8 x 6) and a single transformed axis (1 x 14); explicit odd lengths take the direct
+    # DFT (radix 1) on one or both axes.  Odd channel counts (one RHS, p = 25) move one channel per
+    # task, even ones two; 64 RHS fill whole 16-channel slices.
+    import paper_2201_12050_amd as fm
+    v, t = icosphere(1, 0.1)
+    lat = Lattice(grid, (0.3, 0.3, 0.3))
+    k = 2 * np.pi * 950.0 / 343.0
+    F = op.FMPBEM(v, t, lat, k, 4, -1j / k)
+    Q = fm.Plan(v, t, lat.grid, lat.pitch, k, 4, "bm", dft_schedule="fft", fft_shape=shape)
+    A = fm.Plan(v, t, lat.grid, lat.pitch, k, 4, "bm", dft_schedule="axes", fft_shape=shape)
+    for R in (1, 2, 64):
+        x = random_complex((R, lat.n_cells, F.n), 1200 + R)
+        ref = F.matvec(x)
+        xd = torch.from_numpy(x).cuda()
+        y64 = Q.matvec(xd, precision="fp64").cpu().numpy()
+        assert rel(y64, ref) < 1e-12, R
+        assert rel(Q.matvec(xd.to(torch.complex64), precision="fp32").cpu().numpy(), ref) < 1e-5, R
+        # the same operator with the direct axis passes agrees to rounding
+        assert rel(y64, A.matvec(xd, precision="fp64").cpu().numpy()) < 1e-13, R
+    Q.close()
+    A.close()
 
 
 def test_matvec_batched_equals_alone(cases):
