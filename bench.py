@@ -161,6 +161,26 @@ def batched_stage_rooflines(torch, plans, bs, ws):
     return rows
 
 
+def operator_rows_vs_oracle(P, w, name):
+    """FP64 and FP32 operator applications to the seeded vector of a stored oracle fixture
+    (tests/golden, written from the FP64 CPU oracle alone), compared on its sampled rows:
+    relative l2 and max-norm errors."""
+    import torch
+    from workloads.rng import random_complex
+    path = os.path.join(ROOT, "tests", "golden", name)
+    if not os.path.exists(path):
+        return None
+    fx = np.load(path, allow_pickle=False)
+    x = torch.from_numpy(random_complex((1, w.lattice.n_cells, w.n_dof_cell), int(fx["x_seed"]))).cuda()
+    out = {}
+    for prec, xx in (("fp64", x), ("fp32", x.to(torch.complex64))):
+        y = P.matvec(xx, None, prec, P.workspace(1, prec)).reshape(-1).cpu().numpy()[fx["dofs"]]
+        out[prec] = {"rel_l2": float(np.linalg.norm(y - fx["y"]) / np.linalg.norm(fx["y"])),
+                     "rel_max": float(np.abs(y - fx["y"]).max() / np.abs(fx["y"]).max())}
+    out["rows"] = int(fx["dofs"].size)
+    return out
+
+
 def barrier_sweep(fm, torch, args):
     """Sonic-crystal barrier: 40 x 2 x 8 lattice of open tube cells (192 triangles, N = 122,880), a
     point source 2 m in front, frequencies spread over 100 Hz - 2 kHz (n_t = 10 up to 1 kHz, else 14),
@@ -207,17 +227,19 @@ def barrier_sweep(fm, torch, args):
                      "rel_residual": info[0]["rel_residual"], "solve_ms": (t1 - t0) * 1e3,
                      "field_ms": (t2 - t1) * 1e3, "il_db": il_db, "plan_build_ms": t_build * 1e3})
         if k in (0, len(idx) - 1):
-            checks.append((P, b, x, pin, il_db))
+            checks.append((P, b, x, pin, il_db, w))
         else:
             P.close()
     total = time.perf_counter() - t_start
     th.join()
-    errs, il_diff = [], []
-    for P, b, x, pin, il_db in checks:
+    errs, il_diff, oracle_rows = [], [], {}
+    for P, b, x, pin, il_db, w in checks:
         xr = P.solve(b, tol=1e-12, inner="fp64", restart=args.barrier_restart, max_iters=args.barrier_max_iters,
                      raise_on_not_converged=False)[0]
         errs.append(torch.linalg.vector_norm(x - xr).item() / torch.linalg.vector_norm(xr).item())
         il_diff.append(abs(il_db - float(fm.insertion_loss(pin, P.field(xr, rec, pin))[0])))
+        oracle_rows[f"{w.frequency:.0f}Hz"] = operator_rows_vs_oracle(P, w,
+                                                                      f"barrier_rows_{int(round(w.frequency))}Hz.npz")
         P.close()
     return {"workload": "barrier 40x2x8 open tube cells (192 triangles, N = 122,880), point source, "
                         f"{len(idx)} frequencies 100 Hz - 2 kHz", "gmres_restart": args.barrier_restart,
@@ -225,6 +247,7 @@ def barrier_sweep(fm, torch, args):
             "total_s": total, "max_rel_residual": max(r["rel_residual"] for r in rows),
             "sampled_solution_error": max(errs), "receivers": int(rec.shape[0]),
             "sampled_il_diff_vs_fp64_db": max(il_diff),
+            "operator_rows_vs_oracle": oracle_rows,
             "field_ms_mean": float(np.mean([r["field_ms"] for r in rows])), "per_frequency": rows}
 
 
@@ -314,33 +337,46 @@ def serving(fm, torch, args, mode, rate):
     sampled = set(int(i) for i in rng.choice(np.arange(n_warm, n_warm + n_meas), size=min(8, n_meas), replace=False))
     ready = queue.Queue()
     build_stream = torch.cuda.Stream()
+    build_s = []
     torch.cuda.synchronize()
     start = time.perf_counter()
 
     def builder():
-        with torch.cuda.stream(build_stream):
-            for idx, (arr, grid, f, R, seed) in enumerate(reqs):
-                wait = arr - (time.perf_counter() - start)
-                if wait > 0:
-                    time.sleep(wait)
-                k = 2 * np.pi * f / 343.0
-                P = fm.Plan(v, t, grid, (0.3, 0.3, 0.3), k, 10 if f <= 1200.0 else 12, stream=build_stream)
-                b = P.incident_plane_wave(unit_directions(R, seed), stream=build_stream)
-                build_stream.synchronize()
-                ready.put((idx, arr, P, b))
+        # plan and incident field of each request at its arrival time; an exception ends the run
+        # (it is handed to the main loop)
+        try:
+            with torch.cuda.stream(build_stream):
+                for idx, (arr, grid, f, R, seed) in enumerate(reqs):
+                    wait = arr - (time.perf_counter() - start)
+                    if wait > 0:
+                        time.sleep(wait)
+                    t0 = time.perf_counter()
+                    k = 2 * np.pi * f / 343.0
+                    P = fm.Plan(v, t, grid, (0.3, 0.3, 0.3), k, 10 if f <= 1200.0 else 12, stream=build_stream)
+                    b = P.incident_plane_wave(unit_directions(R, seed), stream=build_stream)
+                    build_stream.synchronize()
+                    build_s.append(time.perf_counter() - t0)
+                    ready.put((idx, arr, P, b))
+        except BaseException as exc:  # noqa: BLE001
+            ready.put(exc)
 
     th = threading.Thread(target=builder, daemon=True)
     th.start()
     keep, pending = {}, {}
     lat, worst_res, rhs_done = [], 0.0, 0
+    failed = []
     t_first = t_last = None
     finished = 0
     while finished < len(reqs):
         while True:
             try:
-                idx, arr, P, b = ready.get_nowait() if pending else ready.get(timeout=0.05)
+                item = ready.get_nowait() if pending else ready.get(timeout=0.05)
             except queue.Empty:
                 break
+            if isinstance(item, BaseException):
+                E.close()
+                raise RuntimeError("serving: building a request's plan failed") from item
+            idx, arr, P, b = item
             pending[E.submit(P, b, **opts)] = (idx, arr, P, b)
         if not pending:
             continue
@@ -354,29 +390,42 @@ def serving(fm, torch, args, mode, rate):
             t_done = time.perf_counter() - start
             finished += 1
             if idx >= n_warm:
-                lat.append(t_done - arr)
-                t_first = arr if t_first is None else min(t_first, arr)
-                t_last = t_done if t_last is None else max(t_last, t_done)
-                rhs_done += len(infos)
-                worst_res = max(worst_res, max(i["rel_residual"] for i in infos))
-            if idx in sampled:
+                if st != 0:
+                    # not converged, out of memory or invalid input: reported, never counted as served
+                    failed.append({"request": idx, "status": fm.STATUS.get(st, st)})
+                else:
+                    lat.append(t_done - arr)
+                    t_first = arr if t_first is None else min(t_first, arr)
+                    t_last = t_done if t_last is None else max(t_last, t_done)
+                    rhs_done += len(infos)
+                    worst_res = max(worst_res, max(i["rel_residual"] for i in infos))
+            if idx in sampled and st == 0:
                 keep[idx] = (P, b, x)
             else:
                 P.close()
     th.join()
+    tm = E.timing()
     E.close()
     errs = []
     for idx, (P, b, x) in keep.items():
         xr = P.solve(b, tol=1e-12, inner="fp64")[0]
         errs.append(torch.linalg.vector_norm(x - xr).item() / torch.linalg.vector_norm(xr).item())
         P.close()
-    span = t_last - t_first
+    span = (t_last - t_first) if lat else float("nan")
+    rounds = max(tm["rounds"], 1)
     return {"mode": mode, "requests": n_meas, "warmup_requests": n_warm, "arrival_rate_per_s": rate,
+            "served": len(lat), "failed": failed,
             "latency_ms": {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3,
-                           "max": max(lat) * 1e3},
-            "requests_per_s": n_meas / span, "rhs_per_s": rhs_done / span,
+                           "max": max(lat) * 1e3 if lat else None},
+            "requests_per_s": len(lat) / span, "rhs_per_s": rhs_done / span,
             "max_rel_residual": worst_res, "sampled_solution_error": max(errs) if errs else None,
-            "budget_gib": args.serving_budget_gib, "max_slots": args.serving_slots}
+            "budget_gib": args.serving_budget_gib, "max_slots": args.serving_slots,
+            # where the engine's host time went (whole run, warm-up included), per round
+            "rounds": tm["rounds"], "mean_active": tm["member_rounds"] / rounds,
+            "per_round_ms": {"enqueue": tm["enqueue_s"] / rounds * 1e3, "wait": tm["wait_s"] / rounds * 1e3,
+                             "admit": tm["admit_s"] / rounds * 1e3, "retire": tm["retire_s"] / rounds * 1e3},
+            "plan_build_ms_per_request": {"mean": float(np.mean(build_s)) * 1e3,
+                                          "p99": percentile(build_s, 99) * 1e3}}
 
 
 def main():
@@ -403,13 +452,15 @@ def main():
                     help="GMRES iteration cap of a serving request (slowly converging lattices need more than 1000)")
     ap.add_argument("--serving-rates", type=float, nargs="*", default=[20.0, 8.0],
                     help="Poisson arrival rates (requests/s), one run each")
-    ap.add_argument("--barrier-freqs", type=int, default=8, help="frequencies of the barrier sweep (0: skip)")
-    ap.add_argument("--barrier-restart", type=int, default=200,
-                    help="GMRES restart length of the barrier sweep (GMRES(30) stagnates near 550 and 850 Hz)")
+    ap.add_argument("--barrier-freqs", type=int, default=96,
+                    help="frequencies of the barrier sweep, log-spaced 100 Hz - 2 kHz (0: skip)")
+    ap.add_argument("--barrier-restart", type=int, default=1000,
+                    help="GMRES restart length of the barrier sweep (between about 550 and 900 Hz GMRES(30) and "
+                         "GMRES(200) stagnate; GMRES(1000) converges there in 850-1650 iterations)")
     ap.add_argument("--barrier-max-iters", type=int, default=4000)
     ap.add_argument("--serving-budget-gib", type=float, default=96.0)
     ap.add_argument("--serving-slots", type=int, default=32)
-    ap.add_argument("--serving-modes", nargs="*", default=["fp32"], choices=["fp32", "fp64"])
+    ap.add_argument("--serving-modes", nargs="*", default=["fp32", "fp64"], choices=["fp32", "fp64"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1)",
@@ -441,6 +492,19 @@ def main():
     def solution_error(x):
         return torch.linalg.vector_norm(x - xref).item() / xref_n
 
+    # the oracle's solution of the same system (stored by tests/golden/make_fixtures.py from the
+    # FP64 CPU oracle alone: every unknown of 12 corner, edge and interior cells and the norm)
+    golden = os.path.join(ROOT, "tests", "golden", "grid16_solution.npz")
+    fx = np.load(golden, allow_pickle=False) if tuple(args.grid) == (16, 16) and os.path.exists(golden) else None
+
+    def oracle_error(x):
+        if fx is None:
+            return None
+        xs = x.reshape(-1).cpu().numpy()[fx["dofs"]]
+        l2 = float(np.linalg.norm(xs - fx["x"]) / np.linalg.norm(fx["x"]))
+        mx = float(np.abs(xs - fx["x"]).max() / np.abs(fx["x"]).max())
+        return {"rel_l2": l2, "rel_max": mx}
+
     def timed_solves(inner, steps, warmup, profile):
         # persistent solver: Krylov basis and work buffers allocated here, before the timed region
         sv = fm.Solver(P, 1, tol=args.tol, inner=inner, ortho=args.ortho)
@@ -466,13 +530,14 @@ def main():
         if profile:
             P.profile([])
         errs = [solution_error(x) for x in xs]   # every solution checked, outside the timed region
+        oerr = oracle_error(xs[-1])
         sv.close()
-        return total, lat, infos, errs, prof
+        return total, lat, infos, errs, prof, oerr
 
-    tot32, lat32, inf32, err32, prof = timed_solves("fp32", args.steps, args.warmup, True)
+    tot32, lat32, inf32, err32, prof, oerr32 = timed_solves("fp32", args.steps, args.warmup, True)
     print(f"[bench] fp32-refined: {args.steps} solves in {tot32:.3f} s, {inf32[-1]}, err {max(err32):.2e}",
           file=sys.stderr, flush=True)
-    tot64, lat64, inf64, err64, _ = timed_solves("fp64", args.steps, args.warmup, False)
+    tot64, lat64, inf64, err64, _, oerr64 = timed_solves("fp64", args.steps, args.warmup, False)
     print(f"[bench] fp64: {args.steps} solves in {tot64:.3f} s, {inf64[-1]}, err {max(err64):.2e}",
           file=sys.stderr, flush=True)
 
@@ -493,6 +558,9 @@ def main():
         torch.cuda.synchronize()
         mv[prec] = args.matvec_reps / (e0.elapsed_time(e1) / 1e3)
     print(f"[bench] matvecs/s {mv}", file=sys.stderr, flush=True)
+
+    # the operator itself against the oracle's stored rows (288 rows of corner, edge and interior cells)
+    rows_vs_oracle = operator_rows_vs_oracle(P, w, "grid16_rows.npz") if tuple(args.grid) == (16, 16) else None
 
     # per-stage breakdown from one more FP32-refined solve with every stage bracketed by events
     # (outside the timed region: the events themselves add gaps between stages)
@@ -542,7 +610,13 @@ def main():
                        "fp64": {"p50": percentile(lat64, 50) * 1e3, "p99": percentile(lat64, 99) * 1e3}},
         "matvecs_per_s": mv,
         "solution_error_vs_fp64": {"fp32_refined": max(err32), "fp64": max(err64)},
-        "accuracy_ok": bool(max(err32) <= 1e-6 and max(err64) <= 1e-6),
+        "operator_rows_vs_oracle": rows_vs_oracle,
+        "solution_error_vs_oracle": ({"fp32_refined": oerr32, "fp64": oerr64,
+                                      "sample": "every unknown of 12 corner, edge and interior cells (15,360)"}
+                                     if oerr32 is not None else None),
+        "accuracy_ok": bool(max(err32) <= 1e-6 and max(err64) <= 1e-6 and
+                            (oerr32 is None or max(oerr32["rel_l2"], oerr32["rel_max"],
+                                                   oerr64["rel_l2"], oerr64["rel_max"]) <= 1e-6)),
         "iterations": {"fp32_refined": inf32[-1], "fp64": inf64[-1]},
         "plan_build_s": plan_s,
         "stages_fp32_refined": stages,
@@ -550,7 +624,11 @@ def main():
         "roofline": {"bound": "mfma", "kernel": "near field + S2M grouped GEMM (FP32 MFMA, three real products per complex product)",
                      "achieved": achieved / 1e12, "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_MFMA, "traffic": NEAR_FP32_TRAFFIC_BYTES,
-                     "avg_launch_us": avg_near * 1e6, "algorithmic_flops_per_launch": flops_near},
+                     "avg_launch_us": avg_near * 1e6, "algorithmic_flops_per_launch": flops_near,
+                     # achieved counts 8 flop per complex multiply-add (four real products); the
+                     # kernel runs three real products (Gauss), so the matrix cores execute 3/4 of it
+                     "flop_count": "8 per complex multiply-add (four-real-product equivalent)",
+                     "mfma_executed_frac": 0.75 * achieved / PEAK_FP32_MFMA},
         "cpu_baseline": None,
     }
     P.close()

@@ -182,7 +182,7 @@ fmbem_status fmbem_matvec_noalloc(fmbem_plan plan, int32_t precision, int32_t n_
 
 typedef struct {
   double tol;                 /* stop when ||b - A x||_2 / ||b||_2 <= tol (FP64 true residual) */
-  int32_t restart;            /* GMRES restart length m (default 30 when 0), at most 200 */
+  int32_t restart;            /* GMRES restart length m (default 30 when 0), at most 1000 */
   int32_t max_iters;          /* total inner iterations (default 1000 when 0) */
   int32_t max_refinements;    /* outer refinement steps for FP32 inner solves (default 20 when 0) */
   int32_t inner_precision;    /* FMBEM_FP64: plain FP64 GMRES; FMBEM_FP32: FP32 operator inside
@@ -292,6 +292,20 @@ fmbem_status fmbem_engine_step(fmbem_engine engine);
 fmbem_status fmbem_engine_poll(fmbem_engine engine, int64_t ticket, int32_t* done, fmbem_solve_info* info);
 fmbem_status fmbem_engine_stats(fmbem_engine engine, int32_t* active, int32_t* queued, size_t* bytes_in_use);
 fmbem_status fmbem_engine_destroy(fmbem_engine engine);
+
+/* Where an engine's host time went since it was created (accounting of the serving loop;
+ * not part of the method).  enqueue: queueing each round's kernels (every active problem's
+ * Gram-Schmidt / Givens / vector kernels and their operator applications, grouped by
+ * precision); admit: admitting queued problems (allocation of their buffers and their first
+ * kernels); wait: blocking for the previous round's results (the device is busy meanwhile:
+ * wait time is device time the host did not have to cover); retire: finishing problems
+ * (freeing their buffers).  rounds counts steps with at least one active problem,
+ * member_rounds the active problems summed over those steps.  Locks like stats. */
+typedef struct {
+  int64_t rounds, member_rounds, admitted, retired;
+  double enqueue_s, admit_s, wait_s, retire_s;
+} fmbem_engine_timing;
+fmbem_status fmbem_engine_timing_read(fmbem_engine engine, fmbem_engine_timing* out);
 
 /* Right-hand sides b = p_inc + alpha dp_inc/dn at the collocation points
  * (Sec. 2.1, eq. (bm)), device complex128 [n_rhs][n_cells][n_dof_cell].

@@ -64,13 +64,19 @@ class SolveInfo(ct.Structure):
     _fields_ = [("iterations", ct.c_int32), ("refinements", ct.c_int32), ("rel_residual", ct.c_double)]
 
 
+class EngineTiming(ct.Structure):
+    _fields_ = [("rounds", ct.c_int64), ("member_rounds", ct.c_int64), ("admitted", ct.c_int64),
+                ("retired", ct.c_int64), ("enqueue_s", ct.c_double), ("admit_s", ct.c_double),
+                ("wait_s", ct.c_double), ("retire_s", ct.c_double)]
+
+
 EXPORTS = ["fmbem_plan_create", "fmbem_plan_query", "fmbem_plan_destroy", "fmbem_plan_export", "fmbem_matvec",
            "fmbem_solve", "fmbem_incident_plane_wave", "fmbem_incident_point_source", "fmbem_plan_profile",
            "fmbem_plan_profile_read", "fmbem_status_string", "fmbem_solve_batch", "fmbem_engine_create",
            "fmbem_engine_submit", "fmbem_engine_step", "fmbem_engine_poll", "fmbem_engine_stats",
            "fmbem_engine_destroy", "fmbem_solver_create", "fmbem_solver_run", "fmbem_solver_graph_stats",
            "fmbem_solver_destroy", "fmbem_incident_at_points", "fmbem_field", "fmbem_insertion_loss",
-           "fmbem_matvec_noalloc"]
+           "fmbem_matvec_noalloc", "fmbem_engine_timing_read"]
 NOALLOC_WORKSPACE_BYTES = 64 << 20   # FMBEM_NOALLOC_WORKSPACE_BYTES
 STAGES = tuple(f"{s}_{p}" for p in ("fp64", "fp32") for s in ("near", "reduce", "fft", "m2l", "ifft", "l2t"))
 
@@ -102,6 +108,7 @@ def load():
     lib.fmbem_engine_step.argtypes = [vp]
     lib.fmbem_engine_poll.argtypes = [vp, ct.c_int64, ct.POINTER(ct.c_int32), ct.POINTER(SolveInfo)]
     lib.fmbem_engine_stats.argtypes = [vp, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32), ct.POINTER(ct.c_size_t)]
+    lib.fmbem_engine_timing_read.argtypes = [vp, ct.POINTER(EngineTiming)]
     lib.fmbem_engine_destroy.argtypes = [vp]
     lib.fmbem_solve_batch.argtypes = [ct.c_int32, ct.POINTER(vp), ct.POINTER(SolveOpts), ct.POINTER(ct.c_int32),
                                       ct.POINTER(vp), ct.POINTER(vp), ct.POINTER(SolveInfo), vp]
@@ -299,6 +306,11 @@ class Engine:
         a, q, u = ct.c_int32(), ct.c_int32(), ct.c_size_t()
         check(self._lib.fmbem_engine_stats(self._h, ct.byref(a), ct.byref(q), ct.byref(u)), "fmbem_engine_stats")
         return dict(active=a.value, queued=q.value, bytes_in_use=u.value)
+
+    def timing(self):
+        t = EngineTiming()
+        check(self._lib.fmbem_engine_timing_read(self._h, ct.byref(t)), "fmbem_engine_timing_read")
+        return {name: getattr(t, name) for name, _ in EngineTiming._fields_}
 
 
 def _precision(p) -> int:

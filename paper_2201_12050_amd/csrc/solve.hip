@@ -13,6 +13,7 @@
 // already queued when it waits for step j, so the device never idles on the
 // host; a step queued after convergence is discarded by the per-RHS freeze.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <deque>
 #include <map>
@@ -230,7 +231,7 @@ __device__ inline double partial_norm(const double* __restrict__ npart, int nb, 
 // Givens update of Hessenberg column j (rotations [[conj(c), conj(s)], [-s, c]]) and of g on
 // LDS copies, the residual estimate |g_{j+1}| and the freeze flag (also written to mapped
 // host memory for the host's convergence check).  Grid (blocks, R), 256 threads.
-constexpr int kMaxRestart = 200;
+constexpr int kMaxRestart = 1000;
 __global__ __launch_bounds__(256) void scale_givens_kernel(const double* __restrict__ npart, int nb, int m, int j,
                                                            const double2* __restrict__ hc, int hstride,
                                                            double2* __restrict__ hn, double2* __restrict__ H,
@@ -249,7 +250,11 @@ __global__ __launch_bounds__(256) void scale_givens_kernel(const double* __restr
     if (w32) w32[(size_t)r * N + n] = make_float2((float)o.x, (float)o.y);
   }
   if (blockIdx.x != 0) return;
-  __shared__ double2 col[kMaxRestart + 2], lc[kMaxRestart], ls[kMaxRestart];
+  // LDS (dynamic, 3m + 2 entries): Hessenberg column, cosines and sines of the earlier rotations
+  extern __shared__ double2 gv_lds[];
+  double2* col = gv_lds;
+  double2* lc = col + m + 2;
+  double2* ls = lc + m;
   const int frozen = jdone[r];
   if (threadIdx.x == 0) hn[(size_t)r * hstride] = make_double2(nrm, 0.0);
   if (frozen >= 0) {
@@ -303,7 +308,7 @@ __global__ __launch_bounds__(256) void backsolve_kernel(int m, int jcur, const d
                                                         const double2* __restrict__ g,
                                                         const int* __restrict__ jdone, double2* __restrict__ y,
                                                         int ystride) {
-  __shared__ double2 gl[kMaxRestart + 1];
+  extern __shared__ double2 gl[];  // [m + 1]
   __shared__ double2 yi;
   const int r = blockIdx.x;
   const int J = jdone[r] >= 0 ? jdone[r] : jcur;
@@ -556,7 +561,8 @@ struct Member {
   }
   // end of a GMRES cycle: sol += V y with y = H^-1 g over each RHS's own step count
   void close_cycle() {
-    hipLaunchKernelGGL(backsolve_kernel, dim3(R), dim3(256), 0, s, m, j, H, g, jdone, y, hstride);
+    hipLaunchKernelGGL(backsolve_kernel, dim3(R), dim3(256), (m + 1) * sizeof(double2), s, m, j, H, g, jdone, y,
+                       hstride);
     maxpy(V, y, gm_sol, j, 1.0);
     ++epoch;
   }
@@ -649,7 +655,8 @@ struct Member {
             mdot(V, j + 1, wv, hc, 3, y, reorth);
             maxpy(V, y, wv, j + 1, -1.0, true, reorth);
           }
-          hipLaunchKernelGGL(scale_givens_kernel, vgrid(), dim3(256), 0, s, npart, nb, m, j, hc, hstride, hn, H, cs,
+          hipLaunchKernelGGL(scale_givens_kernel, vgrid(), dim3(256), (3 * m + 2) * sizeof(double2), s, npart, nb, m,
+                             j, hc, hstride, hn, H, cs,
                              sn, g, res, jdone, djd[slot], tolv, wv, gm_prec == FMBEM_FP32 ? x32 : nullptr, N);
         }
         ++its;
@@ -860,6 +867,7 @@ struct Engine {
   std::unordered_map<long long, Result> results;
   hipEvent_t ev[2] = {nullptr, nullptr};
   std::mutex mu;
+  fmbem_engine_timing timing{};
 
   ~Engine() {
     if (s) hipStreamSynchronize(s);
@@ -881,12 +889,22 @@ struct Engine {
     sl.mb.reset();
   }
 
+  static double now() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+  }
   hipError_t step() {
     std::vector<Member*> ms;
     for (Slot& sl : active) ms.push_back(sl.mb.get());
     const int slot = (int)(t & 1);
+    double t0 = now();
     hipError_t e = round_enqueue(ms, slot, s, false);
     if (e) return e;
+    double t1 = now();
+    timing.enqueue_s += t1 - t0;
+    if (!ms.empty()) {
+      ++timing.rounds;
+      timing.member_rounds += (int64_t)ms.size();
+    }
     // admission in arrival order: the queue head waits until it fits
     while (!queue.empty() && (int)active.size() < max_slots && used + queue.front().bytes <= budget) {
       Req q = queue.front();
@@ -906,15 +924,23 @@ struct Engine {
       used += q.bytes;
       ms.push_back(sl.mb.get());
       active.push_back(std::move(sl));
+      ++timing.admitted;
     }
+    double t2 = now();
+    timing.admit_s += t2 - t1;
     if ((e = round_finish(ms, t, s, ev))) return e;
     ++t;
+    double t3 = now();
+    timing.wait_s += t3 - t2;
     // retire: a finished problem has no work in flight (its last step was the true residual
     // read above, and it queued nothing since)
     for (Slot& sl : active)
-      if (sl.mb->phase == Member::DONE)
+      if (sl.mb->phase == Member::DONE) {
         finish(sl, sl.mb->bad_input ? FMBEM_ERR_INVALID_ARG : (sl.mb->ok ? FMBEM_OK : FMBEM_ERR_NOT_CONVERGED));
+        ++timing.retired;
+      }
     active.erase(std::remove_if(active.begin(), active.end(), [](const Slot& sl) { return !sl.mb; }), active.end());
+    timing.retire_s += now() - t3;
     return hipSuccess;
   }
 };
@@ -1147,6 +1173,14 @@ extern "C" fmbem_status fmbem_engine_stats(fmbem_engine engine, int32_t* active,
   if (active) *active = (int32_t)E.active.size();
   if (queued) *queued = (int32_t)E.queue.size();
   if (bytes_in_use) *bytes_in_use = E.used;
+  return FMBEM_OK;
+}
+
+extern "C" fmbem_status fmbem_engine_timing_read(fmbem_engine engine, fmbem_engine_timing* out) {
+  if (!engine || !out) return FMBEM_ERR_INVALID_ARG;
+  Engine& E = *reinterpret_cast<Engine*>(engine);
+  std::lock_guard<std::mutex> lk(E.mu);
+  *out = E.timing;
   return FMBEM_OK;
 }
 

@@ -119,6 +119,7 @@ def test_other_entry_points_reject_null_plan():
     assert lib.fmbem_engine_step(None) == 1
     assert lib.fmbem_engine_poll(None, 1, None, None) == 1
     assert lib.fmbem_engine_stats(None, None, None, None) == 1
+    assert lib.fmbem_engine_timing_read(None, None) == 1
     assert lib.fmbem_engine_destroy(None) == 1
     assert lib.fmbem_solver_create(None, None, 1, 0, None) == 1
     assert lib.fmbem_solver_run(None, None, None, None, None) == 1
@@ -158,7 +159,8 @@ def test_struct_layouts_match_header(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     mirrors = {"fmbem_cell_mesh": _lib.CellMesh, "fmbem_plan_desc": _lib.PlanDesc, "fmbem_plan_info": _lib.PlanInfo,
-               "fmbem_solve_opts": _lib.SolveOpts, "fmbem_solve_info": _lib.SolveInfo}
+               "fmbem_solve_opts": _lib.SolveOpts, "fmbem_solve_info": _lib.SolveInfo,
+               "fmbem_engine_timing": _lib.EngineTiming}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "fmbem.h"', "int main(void) {"]
     for cname, py in mirrors.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
