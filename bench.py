@@ -338,6 +338,8 @@ def serving(fm, torch, args, mode, rate):
     ready = queue.Queue()
     build_stream = torch.cuda.Stream()
     build_s = []
+    # at most this many requests built and not yet finished (their plans stay resident meanwhile)
+    outstanding = threading.Semaphore(args.serving_outstanding)
     torch.cuda.synchronize()
     start = time.perf_counter()
 
@@ -350,6 +352,7 @@ def serving(fm, torch, args, mode, rate):
                     wait = arr - (time.perf_counter() - start)
                     if wait > 0:
                         time.sleep(wait)
+                    outstanding.acquire()
                     t0 = time.perf_counter()
                     k = 2 * np.pi * f / 343.0
                     P = fm.Plan(v, t, grid, (0.3, 0.3, 0.3), k, 10 if f <= 1200.0 else 12, stream=build_stream)
@@ -389,6 +392,7 @@ def serving(fm, torch, args, mode, rate):
             x, infos, st = r
             t_done = time.perf_counter() - start
             finished += 1
+            outstanding.release()
             if idx >= n_warm:
                 if st != 0:
                     # not converged, out of memory or invalid input: reported, never counted as served
@@ -460,6 +464,8 @@ def main():
     ap.add_argument("--barrier-max-iters", type=int, default=4000)
     ap.add_argument("--serving-budget-gib", type=float, default=96.0)
     ap.add_argument("--serving-slots", type=int, default=32)
+    ap.add_argument("--serving-outstanding", type=int, default=64,
+                    help="requests built (plan resident) and not yet finished, at most")
     ap.add_argument("--serving-modes", nargs="*", default=["fp32", "fp64"], choices=["fp32", "fp64"])
     args = ap.parse_args()
     if args.gpus != 1:

@@ -263,7 +263,11 @@ fmbem_status fmbem_solve_batch(int32_t n, const fmbem_plan* plans, const fmbem_s
  * and its device footprint fits hbm_budget_bytes minus what the active problems
  * hold.  The footprint of a request is its Krylov basis ((restart + 1) vectors),
  * four work vectors and the FP32 copy ([n_rhs][N] each) plus the operator
- * workspace; plans are the caller's and stay resident.  A step advances every
+ * workspace, and the resident bytes of its plan unless an active problem of the
+ * same plan already counts them; plans are the caller's and stay resident.  The
+ * problems' device buffers are stream-ordered allocations from a memory pool of
+ * the engine that keeps freed memory for later problems, so admitting and
+ * retiring problems never synchronises the device.  A step advances every
  * active problem by one round: one operator application each, with the
  * near-field + S2M and the L2T GEMMs of all of them in shared grouped launches,
  * then their Gram-Schmidt, Givens and residual kernels; finished problems free
@@ -275,7 +279,8 @@ fmbem_status fmbem_solve_batch(int32_t n, const fmbem_plan* plans, const fmbem_s
  * submit: plan, b and x (device complex128 [n_rhs][n_cells][n_dof_cell], x the
  *   initial guess, overwritten with the solution) must stay valid until the
  *   ticket is polled done.  Validates opts like fmbem_solve; returns
- *   FMBEM_ERR_ADMISSION (nothing queued) when the footprint exceeds the budget.
+ *   FMBEM_ERR_ADMISSION (nothing queued) when the footprint (plan included)
+ *   exceeds the budget.
  * step: returns FMBEM_OK when idle.
  * poll: *done = 0 while pending (FMBEM_OK); when finished *done = 1, info (host
  *   [n_rhs], may be NULL) is filled and the solve's status is returned

@@ -17,6 +17,7 @@
 #include <cmath>
 #include <deque>
 #include <map>
+#include <cstdint>
 #include <memory>
 #include <mutex>
 #include <unordered_map>
@@ -361,6 +362,30 @@ __global__ void gmres_init_kernel(int R, int m, const double2* __restrict__ beta
 // runs.  Arnoldi steps continue speculatively on the one-round-late convergence flags (a
 // step queued after convergence is frozen on the device and discarded); true residuals
 // make the member wait one round for the host's decision.
+// Pinned host buffers of finished problems, kept for reuse: freeing pinned memory
+// synchronises the device, which would stall the rounds of every other problem in flight.
+static std::mutex g_pin_mu;
+static std::multimap<std::pair<size_t, unsigned>, void*> g_pin_free;
+static size_t pin_bytes(size_t b) { return (b + 255) / 256 * 256; }
+static hipError_t pinned_get(void** p, size_t bytes, unsigned flags) {
+  bytes = pin_bytes(bytes);
+  {
+    std::lock_guard<std::mutex> lk(g_pin_mu);
+    auto it = g_pin_free.find({bytes, flags});
+    if (it != g_pin_free.end()) {
+      *p = it->second;
+      g_pin_free.erase(it);
+      return hipSuccess;
+    }
+  }
+  return hipHostMalloc(p, bytes, flags);
+}
+static void pinned_put(void* p, size_t bytes, unsigned flags) {
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  g_pin_free.insert({{pin_bytes(bytes), flags}, p});
+}
+constexpr unsigned kMapped = hipHostMallocMapped | hipHostMallocCoherent;
+
 struct Member {
   const Plan& P;
   hipStream_t s;
@@ -377,6 +402,7 @@ struct Member {
   int hstride;
   int nb;          // workgroups of the multi-axpy kernel (and of its norm partials)
   std::vector<void*> mem;
+  hipMemPool_t pool = nullptr;  // set: device buffers are stream-ordered allocations from this pool
   double2 *V = nullptr, *r = nullptr, *d = nullptr, *t = nullptr, *rin = nullptr;
   float2* x32 = nullptr;
   void* ws = nullptr;
@@ -430,12 +456,17 @@ struct Member {
     rel.assign(R, 0.0);
   }
   ~Member() {
-    for (void* q : mem) hipFree(q);
-    for (int i = 0; i < 2; ++i) {
-      if (hjd[i]) hipHostFree(hjd[i]);
-      if (hres[i]) hipHostFree(hres[i]);
+    for (void* q : mem) {
+      if (pool)
+        hipFreeAsync(q, s);  // after the member's last work on its stream
+      else
+        hipFree(q);
     }
-    if (htol) hipHostFree(htol);
+    for (int i = 0; i < 2; ++i) {
+      if (hjd[i]) pinned_put(hjd[i], R * sizeof(int), kMapped);
+      if (hres[i]) pinned_put(hres[i], 2 * R * sizeof(double), kMapped);
+    }
+    if (htol) pinned_put(htol, R * sizeof(double), hipHostMallocDefault);
   }
   // device buffers of a member, in allocation order (footprint() sums exactly these)
   struct Buf {
@@ -474,20 +505,20 @@ struct Member {
     for (const Buf& q : buffers(need32)) sum += q.bytes;
     return sum;
   }
-  hipError_t setup(bool need32) {
+  hipError_t setup(bool need32, hipMemPool_t from = nullptr) {
     hipError_t e;
+    pool = from;
     for (const Buf& q : buffers(need32)) {
-      if ((e = hipMalloc(q.ptr, q.bytes))) return e;
+      if ((e = pool ? hipMallocFromPoolAsync(q.ptr, q.bytes, pool, s) : hipMalloc(q.ptr, q.bytes))) return e;
       mem.push_back(*q.ptr);
     }
     for (int i = 0; i < 2; ++i) {
-      if ((e = hipHostMalloc((void**)&hjd[i], R * sizeof(int), hipHostMallocMapped | hipHostMallocCoherent))) return e;
+      if ((e = pinned_get((void**)&hjd[i], R * sizeof(int), kMapped))) return e;
       if ((e = hipHostGetDevicePointer((void**)&djd[i], hjd[i], 0))) return e;
-      if ((e = hipHostMalloc((void**)&hres[i], 2 * R * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent)))
-        return e;
+      if ((e = pinned_get((void**)&hres[i], 2 * R * sizeof(double), kMapped))) return e;
       if ((e = hipHostGetDevicePointer((void**)&dres[i], hres[i], 0))) return e;
     }
-    if ((e = hipHostMalloc((void**)&htol, R * sizeof(double), hipHostMallocDefault))) return e;
+    if ((e = pinned_get((void**)&htol, R * sizeof(double), hipHostMallocDefault))) return e;
     return hipSuccess;
   }
   dim3 vgrid() const { return dim3((unsigned)nb, R); }
@@ -868,12 +899,44 @@ struct Engine {
   hipEvent_t ev[2] = {nullptr, nullptr};
   std::mutex mu;
   fmbem_engine_timing timing{};
+  // device memory of the problems: stream-ordered allocations from the engine's own pool, which
+  // keeps freed memory for the next problem (no device-wide synchronisation at admission or
+  // retirement); nullptr where pools are unavailable (plain allocations then)
+  hipMemPool_t pool = nullptr;
+  // plans of the active problems (a plan's resident bytes count once against the budget while
+  // any of its problems is active)
+  std::unordered_map<const Plan*, int> plan_refs;
 
   ~Engine() {
-    if (s) hipStreamSynchronize(s);
+    hipStreamSynchronize(s);
     active.clear();
+    hipStreamSynchronize(s);
     for (int i = 0; i < 2; ++i)
       if (ev[i]) hipEventDestroy(ev[i]);
+    if (pool) hipMemPoolDestroy(pool);
+  }
+
+  hipError_t make_pool() {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e) return e;
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    if (hipMemPoolCreate(&pool, &props) != hipSuccess) {
+      (void)hipGetLastError();
+      pool = nullptr;  // plain allocations
+      return hipSuccess;
+    }
+    uint64_t keep = UINT64_MAX;
+    return hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  }
+
+  // bytes a request adds to the budget when admitted: its buffers, and its plan unless counted
+  size_t admit_bytes(const Req& q) const {
+    auto it = plan_refs.find(q.P);
+    return q.bytes + ((it == plan_refs.end() || it->second == 0) ? q.P->resident : 0);
   }
 
   static size_t footprint(const Plan& P, const SolveCfg& c, int R) {
@@ -886,6 +949,11 @@ struct Engine {
     fill_info(*sl.mb, r.info.data());
     results[sl.ticket] = std::move(r);
     used -= sl.bytes;
+    const Plan* P = &sl.mb->P;
+    if (--plan_refs[P] == 0) {
+      used -= P->resident;
+      plan_refs.erase(P);
+    }
     sl.mb.reset();
   }
 
@@ -906,12 +974,12 @@ struct Engine {
       timing.member_rounds += (int64_t)ms.size();
     }
     // admission in arrival order: the queue head waits until it fits
-    while (!queue.empty() && (int)active.size() < max_slots && used + queue.front().bytes <= budget) {
+    while (!queue.empty() && (int)active.size() < max_slots && used + admit_bytes(queue.front()) <= budget) {
       Req q = queue.front();
       queue.pop_front();
       Slot sl{std::unique_ptr<Member>(new Member(*q.P, s, q.R, q.c.m)), q.ticket, q.bytes};
       configure(*sl.mb, q.c, q.b, q.x);
-      e = sl.mb->setup(q.c.ip == FMBEM_FP32);
+      e = sl.mb->setup(q.c.ip == FMBEM_FP32, pool);
       if (e) {
         results[q.ticket] = Result{st_of(e), std::vector<fmbem_solve_info>(q.R)};
         if (e == hipErrorOutOfMemory) {
@@ -922,6 +990,7 @@ struct Engine {
       }
       sl.mb->start(slot);
       used += q.bytes;
+      if (plan_refs[q.P]++ == 0) used += q.P->resident;
       ms.push_back(sl.mb.get());
       active.push_back(std::move(sl));
       ++timing.admitted;
@@ -1113,6 +1182,7 @@ extern "C" fmbem_status fmbem_engine_create(size_t hbm_budget_bytes, int32_t max
   e->max_slots = max_slots;
   for (int i = 0; i < 2; ++i)
     if (hipEventCreateWithFlags(&e->ev[i], hipEventDisableTiming) != hipSuccess) return FMBEM_ERR_DEVICE;
+  if (e->make_pool() != hipSuccess) return FMBEM_ERR_DEVICE;
   *out = reinterpret_cast<fmbem_engine>(e.release());
   return FMBEM_OK;
 }
@@ -1127,7 +1197,7 @@ extern "C" fmbem_status fmbem_engine_submit(fmbem_engine engine, fmbem_plan plan
   if (st != FMBEM_OK) return st;
   const size_t bytes = Engine::footprint(P, c, n_rhs);
   std::lock_guard<std::mutex> lk(E.mu);
-  if (bytes > E.budget) return FMBEM_ERR_ADMISSION;
+  if (bytes + P.resident > E.budget) return FMBEM_ERR_ADMISSION;
   *ticket = E.next_ticket++;
   E.queue.push_back(Engine::Req{*ticket, &P, c, n_rhs, b, x, bytes});
   return FMBEM_OK;

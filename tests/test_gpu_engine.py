@@ -110,13 +110,16 @@ def test_engine_admission_by_bytes(requests):
     assert e.value.status == 7
     assert E.stats()["queued"] == 0
     E.close()
-    # a budget of one request at a time: the second waits in the queue until the first leaves
+    # a budget of one request at a time: the second waits in the queue until the first leaves; the
+    # plan's resident bytes count once, with the first active problem of that plan
     E = fm.Engine(hbm_budget_bytes=8 << 30, max_slots=4)
     t0 = E.submit(p["P"], p["b"], **p["opts"])
     E.step()
     one = E.stats()["bytes_in_use"]
+    member = one - p["P"].info["resident_bytes"]
+    assert member > 0
     E.close()
-    E = fm.Engine(hbm_budget_bytes=one + one // 2, max_slots=4)
+    E = fm.Engine(hbm_budget_bytes=one + member // 2, max_slots=4)
     ta = E.submit(p["P"], p["b"], **p["opts"])
     tb = E.submit(p["P"], p["b"].clone(), **p["opts"])
     E.step()
