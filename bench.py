@@ -285,6 +285,49 @@ def barrier_ground_sweep(fm, torch, args):
             "per_frequency": rows}
 
 
+def pbem_comparison(fm, torch, args):
+    """The paper's speed comparison of the exact periodic BEM (every block integrated, n x n blocks
+    per bin of the circulant embedding) with the FMPBEM on the same GPU: plan build time, resident
+    bytes and operator applications per second at one and 64 right-hand sides, on the tiny
+    workload and the three batched-grid lattices (320-triangle spheres)."""
+    from workloads import config_tiny, config_batched_grids
+
+    def apply_rate(P, R, prec):
+        dt = torch.complex64 if prec == "fp32" else torch.complex128
+        x = torch.ones((R, P.n_cells, P.n), dtype=dt, device="cuda")
+        y = torch.empty_like(x)
+        ws = P.workspace(R, prec)
+        for _ in range(3):
+            P.matvec(x, y, prec, ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record()
+        for _ in range(reps):
+            P.matvec(x, y, prec, ws)
+        e1.record()
+        torch.cuda.synchronize()
+        return R * reps / (e0.elapsed_time(e1) / 1e3)
+
+    rows = []
+    for w in [config_tiny()] + config_batched_grids(1):
+        row = {"lattice": "x".join(str(g) for g in w.lattice.grid[:2]), "n": w.n_dof_cell, "f_hz": w.frequency,
+               "n_dof": int(w.n_dof)}
+        for name, kw in (("pbem", {"exact": True}), ("fmpbem", {})):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P = fm.Plan.from_workload(w, **kw)
+            torch.cuda.synchronize()
+            build = time.perf_counter() - t0
+            rate = {f"{prec}_R{R}": apply_rate(P, R, prec) for prec in ("fp64", "fp32") for R in (1, 64)}
+            row[name] = {"plan_build_ms": build * 1e3, "resident_mib": P.info["resident_bytes"] / 2**20,
+                         "matvecs_per_s": rate}
+            P.close()
+        rows.append(row)
+    return {"workloads": "tiny 4x1 line (500 Hz) and the batched lattices 8x8, 12x20, 32x4 (800 Hz), "
+                         "320-triangle spheres; FMPBEM n_t = 10", "rows": rows}
+
+
 def ground_solves(fm, torch, args):
     """The 16x16 lattice of the headline above a sound-hard plane 0.05 m below the spheres (image
     blocks near, R_p = 1), a plane wave travelling down toward it: FP32-refined solves with the
@@ -448,6 +491,7 @@ def main():
     ap.add_argument("--batch-rhs", type=int, default=64, help="plane waves per lattice of the batched-grids run")
     ap.add_argument("--no-batched-grids", action="store_true")
     ap.add_argument("--no-ground", action="store_true", help="skip the half-space 16x16 solves")
+    ap.add_argument("--no-pbem", action="store_true", help="skip the exact PBEM comparison")
     ap.add_argument("--ground-freqs", type=int, default=4,
                     help="frequencies of the barrier-on-ground sweep (0: skip)")
     ap.add_argument("--serving-requests", type=int, default=100, help="measured requests of the serving run")
@@ -641,6 +685,9 @@ def main():
     if not args.no_batched_grids:
         out["batched_grids"] = batched_grids(fm, torch, args)
         print(f"[bench] batched grids {out['batched_grids']}", file=sys.stderr, flush=True)
+    if not args.no_pbem:
+        out["pbem_vs_fmpbem"] = pbem_comparison(fm, torch, args)
+        print(f"[bench] PBEM vs FMPBEM {out['pbem_vs_fmpbem']}", file=sys.stderr, flush=True)
     if not args.no_ground:
         out["halfspace_grid16"] = ground_solves(fm, torch, args)
         print(f"[bench] half-space 16x16 {out['halfspace_grid16']}", file=sys.stderr, flush=True)

@@ -104,6 +104,16 @@ typedef struct {
    * batched solves and the engine tune the launches they share between plans.  Outside
    * 0..FMBEM_TILE_SHAPES => FMBEM_ERR_INVALID_ARG. */
   int32_t tile_shape[3];
+  /* exact = 1: the exact periodic BEM operator (PBEM, Sec. 2.2 eq. (toeplitzBEM), Sec. 2.4
+   * eqs. (blockDiagonal), (diagonalized)) instead of the fast multipole one: every block S_d of
+   * the lattice (|d_a| <= M_a - 1) is integrated with the element quadrature, the first block
+   * column of its circulant embedding is transformed over the grid, and each bin holds an n x n
+   * block (no truncation: the matrix is the dense collocation matrix, applied in
+   * O(B n^2) per right-hand side).  The same operator application and solvers run on it (the
+   * expansion space is the element space: P2M and L2P are identities).  order and near_radius
+   * are ignored; the half-space is not supported (FMBEM_ERR_UNSUPPORTED).  The paper's
+   * comparison method; the plan stores B n^2 complex values per precision.  0 => FMPBEM. */
+  int32_t exact;
 } fmbem_plan_desc;
 
 #define FMBEM_TILE_SHAPES 10

@@ -102,6 +102,9 @@ struct Plan {
   // the canonical-bin pairing Lambda(-w) = D Lambda(w) D holds (off in the half-space, whose
   // image part pairs differently): when off every bin is stored and the DFT applies no D
   bool paired = true;
+  // exact periodic BEM (comparison method): Lambda holds the n x n exact blocks per bin, V0 = U0 = I,
+  // no near blocks, p = n
+  bool exact = false;
   int flip_p() const { return paired ? p : 0; }
   // Lambda of bin -w is D Lambda(w) D, D = diag((-1)^n) (reciprocity of the translations), so only
   // canonical bins (linear index <= that of the partner bin -w) are stored.

@@ -520,6 +520,44 @@ __global__ void incident_kernel(const double* __restrict__ geom, int n, int C, i
   out[idx] = cadd<double>(pv, cmul<double>(alpha, dp));
 }
 
+// Exact periodic BEM (Sec. 2.2 eq. (toeplitzBEM), Sec. 2.4 eq. (blockDiagonal)): the first block
+// column of the circulant embedding holds the exact block S_d at bin (d mod N) for every offset of
+// the lattice; S [nd][n n] -> G [bin][n n] (G zeroed first)
+__global__ void place_blocks_kernel(const double2* __restrict__ S, const int* __restrict__ bins, int nd, size_t nn,
+                                    double2* __restrict__ G) {
+  const size_t total = (size_t)nd * nn;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t d = e / nn, r = e - d * nn;
+    G[(size_t)bins[d] * nn + r] = S[e];
+  }
+}
+
+// Lambda_b = G_b / B transposed to the column-major per-bin layout (column stride ldp) of the
+// M2L products, FP64 and (optionally) FP32
+__global__ void exact_lambda_kernel(const double2* __restrict__ G, int B, int n, int ldp, double inv,
+                                    double2* __restrict__ L64, float2* __restrict__ L32) {
+  const size_t nn = (size_t)n * n, total = (size_t)B * nn;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const size_t b = e / nn, r = e - b * nn;
+    const int i = (int)(r / n), j = (int)(r - (size_t)i * n);
+    const double2 v = G[e];
+    const double2 o = make_double2(v.x * inv, v.y * inv);
+    const size_t dst = (b * n + j) * ldp + i;
+    L64[dst] = o;
+    if (L32) L32[dst] = make_float2((float)o.x, (float)o.y);
+  }
+}
+
+// n x n identity (the P2M and L2P maps of the exact operator), FP64 and (optionally) FP32
+__global__ void identity_kernel(double2* __restrict__ I64, float2* __restrict__ I32, int n) {
+  const size_t total = (size_t)n * n;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const double v = (e / n == e % n) ? 1.0 : 0.0;
+    I64[e] = make_double2(v, 0.0);
+    if (I32) I32[e] = make_float2((float)v, 0.0f);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // host: plan creation
 // ---------------------------------------------------------------------------
@@ -629,6 +667,88 @@ void plan_release(Plan* P) {
   delete P;
 }
 
+// Exact periodic BEM plan: every block S_d (|d_a| <= M_a - 1) integrated like the near blocks,
+// placed at bin (d mod N) of the zeroed grid, the grid transformed (forward DFT over every bin,
+// n^2 channels), Lambda_b = that transform / B per bin; V0 = U0 = I (p = n); no near blocks.
+static hipError_t exact_build(Plan& P, const QuadTab& Q, double2 alpha, int hyper, bool want32, hipStream_t s) {
+  const int n = P.n;
+  const size_t nn = (size_t)n * n;
+  // offsets of the lattice and their bins
+  std::vector<int> offs, bins;
+  for (int d2 = -(P.grid[2] - 1); d2 <= P.grid[2] - 1; ++d2)
+    for (int d1 = -(P.grid[1] - 1); d1 <= P.grid[1] - 1; ++d1)
+      for (int d0 = -(P.grid[0] - 1); d0 <= P.grid[0] - 1; ++d0) {
+        offs.push_back(d0);
+        offs.push_back(d1);
+        offs.push_back(d2);
+        const int b0 = (d0 + P.fft[0]) % P.fft[0], b1 = (d1 + P.fft[1]) % P.fft[1], b2 = (d2 + P.fft[2]) % P.fft[2];
+        bins.push_back(b0 + P.fft[0] * (b1 + P.fft[1] * b2));
+      }
+  const int nd = (int)bins.size();
+  FM_CHECK(plan_alloc(P, &P.S[0], sizeof(double2)));  // no near blocks
+  if (want32) FM_CHECK(plan_alloc(P, &P.S[1], sizeof(float2)));
+  std::vector<void*> scratch;
+  auto salloc = [&](void** ptr, size_t bytes) -> hipError_t {
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e == hipSuccess) scratch.push_back(*ptr);
+    return e;
+  };
+  hipError_t err = hipSuccess;
+  do {
+    int *d_offs = nullptr, *d_bins = nullptr;
+    double2 *Sall = nullptr, *G = nullptr;
+    if ((err = salloc((void**)&d_offs, offs.size() * sizeof(int))) != hipSuccess) break;
+    if ((err = salloc((void**)&d_bins, bins.size() * sizeof(int))) != hipSuccess) break;
+    if ((err = salloc((void**)&Sall, (size_t)nd * nn * sizeof(double2))) != hipSuccess) break;
+    if ((err = salloc((void**)&G, (size_t)P.B * nn * sizeof(double2))) != hipSuccess) break;
+    hipMemcpyAsync(d_offs, offs.data(), offs.size() * sizeof(int), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(d_bins, bins.data(), bins.size() * sizeof(int), hipMemcpyHostToDevice, s);
+    hipMemsetAsync(G, 0, (size_t)P.B * nn * sizeof(double2), s);
+    const size_t total = (size_t)nd * nn;
+    hipLaunchKernelGGL(assemble_near_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, P.geom, n, d_offs,
+                       nd, P.pitch[0], P.pitch[1], P.pitch[2], P.k, alpha, hyper, Q, 0, 0, 0.0, make_double2(0, 0),
+                       Sall, (float2*)nullptr);
+    hipLaunchKernelGGL(place_blocks_kernel, dim3(4096), dim3(256), 0, s, Sall, d_bins, nd, nn, G);
+    if ((err = hipGetLastError()) != hipSuccess) break;
+    if ((err = grid_dft_launch<double>(G, (int)nn, P.fft, P.fft, false, false, s)) != hipSuccess) break;
+    // every bin is its own canonical bin (the exact blocks have no D-symmetry pairing)
+    std::vector<int> canon(P.B), pairs(2 * (size_t)P.B);
+    for (int b = 0; b < P.B; ++b) {
+      canon[b] = b;
+      pairs[2 * b] = b;
+      pairs[2 * b + 1] = -1;
+    }
+    P.Bc = P.B;
+    if ((err = plan_alloc(P, (void**)&P.d_canon, P.B * sizeof(int))) != hipSuccess) break;
+    if ((err = plan_alloc(P, (void**)&P.d_pairs, pairs.size() * sizeof(int))) != hipSuccess) break;
+    hipMemcpyAsync(P.d_canon, canon.data(), P.B * sizeof(int), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(P.d_pairs, pairs.data(), pairs.size() * sizeof(int), hipMemcpyHostToDevice, s);
+    const int ldp = lambda_ld(n);
+    const size_t nl = (size_t)P.B * n * ldp;
+    if ((err = plan_alloc(P, &P.Lam[0], nl * sizeof(double2))) != hipSuccess) break;
+    if (want32 && (err = plan_alloc(P, &P.Lam[1], nl * sizeof(float2))) != hipSuccess) break;
+    if (ldp != n) {
+      hipMemsetAsync(P.Lam[0], 0, nl * sizeof(double2), s);
+      if (want32) hipMemsetAsync(P.Lam[1], 0, nl * sizeof(float2), s);
+    }
+    hipLaunchKernelGGL(exact_lambda_kernel, dim3(4096), dim3(256), 0, s, G, P.B, n, ldp, 1.0 / P.B,
+                       (double2*)P.Lam[0], (float2*)P.Lam[1]);
+    // V0 = U0 = I (n x n)
+    if ((err = plan_alloc(P, &P.V0[0], nn * sizeof(double2))) != hipSuccess) break;
+    if ((err = plan_alloc(P, &P.U0[0], nn * sizeof(double2))) != hipSuccess) break;
+    if (want32 && (err = plan_alloc(P, &P.V0[1], nn * sizeof(float2))) != hipSuccess) break;
+    if (want32 && (err = plan_alloc(P, &P.U0[1], nn * sizeof(float2))) != hipSuccess) break;
+    hipLaunchKernelGGL(identity_kernel, dim3(256), dim3(256), 0, s, (double2*)P.V0[0], (float2*)P.V0[1], n);
+    hipLaunchKernelGGL(identity_kernel, dim3(256), dim3(256), 0, s, (double2*)P.U0[0], (float2*)P.U0[1], n);
+    err = hipGetLastError();
+  } while (0);
+  // host tables must outlive the async copies; the scratch buffers are freed after the stream drains
+  hipError_t e2 = hipStreamSynchronize(s);
+  free_list(scratch);
+  if (err == hipSuccess) err = e2;
+  return err;
+}
+
 static hipError_t plan_build(Plan& P, const std::vector<double>& geo, hipStream_t s) {
   const int n = P.n;
   // geometry (an image sub-plan shares its parent's)
@@ -703,6 +823,7 @@ static hipError_t plan_build(Plan& P, const std::vector<double>& geo, hipStream_
   }
   const double2 alpha = make_double2(P.alpha_re, P.alpha_im);
   const int hyper = (P.alpha_re != 0.0 || P.alpha_im != 0.0) ? 1 : 0;
+  if (P.exact) return exact_build(P, Q, alpha, hyper, want32, s);
   // near blocks
   const size_t ns = (size_t)P.n_near * n * n;
   FM_CHECK(plan_alloc(P, &P.S[0], std::max<size_t>(1, ns) * sizeof(double2)));
@@ -931,7 +1052,9 @@ extern "C" fmbem_status fmbem_plan_create(const fmbem_cell_mesh* mesh, const fmb
     if (desc->grid[a] > kMaxGridDim || desc->fft_shape[a] > 2 * kMaxGridDim) return FMBEM_ERR_UNSUPPORTED;
   }
   if (!(desc->k > 0.0) || !std::isfinite(desc->k)) return FMBEM_ERR_INVALID_ARG;
-  if (desc->order < 0 || desc->order > 20) return FMBEM_ERR_INVALID_ARG;
+  if (desc->exact != 0 && desc->exact != 1) return FMBEM_ERR_INVALID_ARG;
+  if (desc->exact == 1 && desc->halfspace != 0) return FMBEM_ERR_UNSUPPORTED;
+  if (desc->exact == 0 && (desc->order < 0 || desc->order > 20)) return FMBEM_ERR_INVALID_ARG;
   if (desc->formulation != FMBEM_BURTON_MILLER && desc->formulation != FMBEM_CBIE) return FMBEM_ERR_INVALID_ARG;
   if (desc->precisions & ~3u) return FMBEM_ERR_INVALID_ARG;
   if (desc->dft_schedule < FMBEM_DFT_AUTO || desc->dft_schedule > FMBEM_DFT_FFT) return FMBEM_ERR_INVALID_ARG;
@@ -1008,9 +1131,11 @@ extern "C" fmbem_status fmbem_plan_create(const fmbem_cell_mesh* mesh, const fmb
   }
   P->B = P->fft[0] * P->fft[1] * P->fft[2];
   P->k = desc->k;
-  P->order = desc->order;
-  P->p = (desc->order + 1) * (desc->order + 1);
-  P->p2 = (2 * desc->order + 1) * (2 * desc->order + 1);
+  P->exact = desc->exact == 1;
+  P->order = P->exact ? 0 : desc->order;
+  // exact PBEM: the per-bin blocks act on the element values themselves (p = n)
+  P->p = P->exact ? n : (desc->order + 1) * (desc->order + 1);
+  P->p2 = (2 * P->order + 1) * (2 * P->order + 1);
   P->formulation = desc->formulation;
   if (desc->formulation == FMBEM_CBIE) {
     P->alpha_re = 0.0;
@@ -1035,6 +1160,10 @@ extern "C" fmbem_status fmbem_plan_create(const fmbem_cell_mesh* mesh, const fmb
         P->near_off.push_back(d1);
         P->near_off.push_back(d2);
       }
+  if (P->exact) {
+    P->near_off.clear();  // every block goes through the transformed column
+    P->paired = false;
+  }
   P->n_near = (int)P->near_off.size() / 3;
   if (P->n_near > kMaxSeg) {
     delete P;
@@ -1063,7 +1192,7 @@ extern "C" fmbem_status fmbem_plan_create(const fmbem_cell_mesh* mesh, const fmb
     const double* x = mesh->vertices + 3 * v;
     rmax = std::max(rmax, std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]));
   }
-  P->scale = std::min(1.0, std::max(1e-3, P->k * rmax));
+  P->scale = P->exact ? 1.0 : std::min(1.0, std::max(1e-3, P->k * rmax));
   hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
   hipError_t e = plan_build(*P, geo, s);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking);
