@@ -836,14 +836,15 @@ bool dft_fft_applies(int channels, const int M[3], const int N[3], bool pruned) 
 }
 
 // channels per workgroup: 128 bytes of channels per grid entry (16 FP32 or 8 FP64), halved while
-// the launch would leave CUs without a workgroup or the slab would exceed 64 KB; CP channels per
+// the launch would have fewer than 64 workgroups (measured: more, narrower slices cost more in
+// scattered writes than they gain in parallelism) or the slab would exceed 64 KB; CP channels per
 // task (two FP32 channels in one 16-byte access when the channel count is even)
 template <typename T>
 static hipError_t fft2_launch(cplx<T>* buf, int channels, const int M[3], const int N[3], bool inverse, int flip_p,
                               hipStream_t s) {
   const int CP = (sizeof(T) == 4 && channels % 2 == 0) ? 2 : 1;
   int CT = 128 / (int)sizeof(cplx<T>);
-  while (CT > CP && ((channels + CT - 1) / CT < 256 || fft2_lds<T>(M, N, CT) > 64 * 1024)) CT /= 2;
+  while (CT > CP && ((channels + CT - 1) / CT < 64 || fft2_lds<T>(M, N, CT) > 64 * 1024)) CT /= 2;
   const size_t lds = fft2_lds<T>(M, N, CT);
   if (lds > kLdsMax) return hipErrorInvalidValue;
   if (lds > 64 * 1024) {

@@ -277,12 +277,12 @@ def test_matvec_batched_equals_alone(cases):
     # below the M2L GEMM threshold every stage computes each column in the same order
     # whatever the batch, so a batched apply equals the single ones bit for bit
     F, P, lat = cases["sphere80_5x3_ragged"]
-    x = torch.from_numpy(random_complex((5, lat.n_cells, F.n), 7)).cuda().to(torch.complex64)
+    x = torch.from_numpy(random_complex((4, lat.n_cells, F.n), 7)).cuda().to(torch.complex64)
     yb = P.matvec(x, precision="fp32")
-    for r in range(5):
+    for r in range(4):
         ya = P.matvec(x[r:r + 1].contiguous(), precision="fp32")
         assert torch.equal(yb[r:r + 1], ya)
-    # from 8 right-hand sides on the M2L product is a GEMM: equal to FP32 rounding
+    # from 5 right-hand sides on the M2L product is a GEMM: equal to FP32 rounding
     x = torch.from_numpy(random_complex((12, lat.n_cells, F.n), 8)).cuda().to(torch.complex64)
     yb = P.matvec(x, precision="fp32")
     for r in (0, 7, 11):
