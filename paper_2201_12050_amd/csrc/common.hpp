@@ -323,6 +323,17 @@ bool dft_fused_applies(int channels, const int M[3], const int N[3], bool pruned
 // whether the fused two-axis FFT applies (N3 = 1, pruned, the slab of one channel fits the LDS)
 template <typename T>
 bool dft_fft_applies(int channels, const int M[3], const int N[3], bool pruned);
+// one grid transform of the FFT schedule (pruned forward / cropped inverse, as grid_dft_launch)
+struct FftTransform {
+  void* buf;
+  int channels;
+  int M[3], N[3];
+  int flip_p;
+};
+// the FFT schedule of several grids, grouped into as few launches as possible (each grid must
+// satisfy dft_fft_applies); the result of each equals that of its own launch bit for bit
+template <typename T>
+hipError_t fft2_group_launch(const std::vector<FftTransform>& tr, bool inverse, hipStream_t s);
 
 // column stride (complex elements) of the per-bin column-major Lambda blocks
 int lambda_ld(int p);
@@ -330,6 +341,18 @@ int lambda_ld(int p);
 // to the R vectors of the bin and of its partner
 template <typename T>
 hipError_t m2l_launch(const void* Lam, const int* pairs, int Bc, void* buf, int R, int p, hipStream_t s);
+// one plan's GEMV product (in place in buf) within a grouped launch
+struct M2lProduct {
+  const void* Lam;
+  const int* pairs;
+  int Bc;
+  void* buf;
+  int R, p;
+};
+// the GEMV products of several plans in as few launches as their orders allow (one per kernel form);
+// each result equals that of its own launch bit for bit
+template <typename T>
+hipError_t m2l_group_launch(const std::vector<M2lProduct>& v, hipStream_t s);
 // right-hand-side count from which the M2L runs as a batched MFMA GEMM into a second buffer (the GEMV
 // streams Lambda once per 4 vectors of a bin pair: at 5 or more right-hand sides the GEMM, which
 // reads it once per bin, is faster; measured on 16 x 16 and 40 x 8 lattices at n_t = 10)

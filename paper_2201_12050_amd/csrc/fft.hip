@@ -724,9 +724,9 @@ __host__ __device__ inline int fft_first_axis(const int M[3], const int N[3], bo
 // grid entry (k0, k1) at (k1 N0 + k0) channels; T entry (line, pos) at (line LT + pos) CT
 template <typename T, int CP, int S>
 __device__ inline void fft2_body(cplx<T>* __restrict__ buf, int channels, int CT, const int M[2], const int N[2],
-                                 int a, int flip_p, const cplx<T>* twa, const cplx<T>* twb, cplx<T>* Tm) {
+                                 int a, int flip_p, const cplx<T>* twa, const cplx<T>* twb, cplx<T>* Tm, int blk) {
   const int b = 1 - a;
-  const int c0 = blockIdx.x * CT;
+  const int c0 = blk * CT;
   const int NCP = CT / CP;
   const int npk = (min(CT, channels - c0) + CP - 1) / CP;  // packs of the slice in range
   // the block size is a multiple of NCP, so a thread keeps its channel pack in every task
@@ -793,27 +793,46 @@ __device__ inline void fft2_body(cplx<T>* __restrict__ buf, int channels, int CT
 
 constexpr int kFftThreads = 512;
 
+// one plan's transform in a grouped launch: its grid, channel slices of CT channels, first axis,
+// spectrum-symmetry flag and first workgroup
+struct FftJob {
+  void* buf;
+  int channels, CT, N0, N1, M0, M1, a, flip_p, block0;
+};
+constexpr int kMaxFftJobs = 32;
+struct FftJobs {
+  int count;
+  FftJob job[kMaxFftJobs];
+};
+
+// the transforms of several plans (same precision and channels per task) in one launch:
+// workgroup blockIdx.x belongs to the last job whose block0 it reaches
 template <typename T, int CP>
-__global__ __launch_bounds__(kFftThreads) void fft2_kernel(cplx<T>* __restrict__ buf, int channels, int CT, int N0,
-                                                           int N1, int M0, int M1, int inverse, int a, int flip_p) {
+__global__ __launch_bounds__(kFftThreads) void fft2_kernel(FftJobs J, int inverse) {
   extern __shared__ unsigned char smem_raw[];
-  const int N[2] = {N0, N1}, M[2] = {M0, M1};
+  int q = 0;
+  while (q + 1 < J.count && (int)blockIdx.x >= J.job[q + 1].block0) ++q;
+  const FftJob jb = J.job[q];
+  const int N[2] = {jb.N0, jb.N1}, M[2] = {jb.M0, jb.M1};
+  const int a = jb.a;
   cplx<T>* twa = reinterpret_cast<cplx<T>*>(smem_raw);  // [N_a]
   cplx<T>* twb = twa + N[a];                            // [N_b]
   constexpr int kAl = 16 / sizeof(cplx<T>);
-  cplx<T>* Tm = twa + (N0 + N1 + kAl - 1) / kAl * kAl;  // the slab, 16-byte aligned
+  cplx<T>* Tm = twa + (N[0] + N[1] + kAl - 1) / kAl * kAl;  // the slab, 16-byte aligned
   const double sg = inverse ? 1.0 : -1.0;
-  for (int e = threadIdx.x; e < N0 + N1; e += blockDim.x) {
+  for (int e = threadIdx.x; e < N[0] + N[1]; e += blockDim.x) {
     const int n = e < N[a] ? N[a] : N[1 - a], k = e < N[a] ? e : e - N[a];
     double sn, cs;
     sincospi(2.0 * k / n, &sn, &cs);
     twa[e] = mk<T>((T)cs, (T)(sg * sn));
   }
   __syncthreads();
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(jb.buf);
+  const int blk = (int)blockIdx.x - jb.block0;
   if (inverse)
-    fft2_body<T, CP, 1>(buf, channels, CT, M, N, a, flip_p, twa, twb, Tm);
+    fft2_body<T, CP, 1>(buf, jb.channels, jb.CT, M, N, a, jb.flip_p, twa, twb, Tm, blk);
   else
-    fft2_body<T, CP, -1>(buf, channels, CT, M, N, a, flip_p, twa, twb, Tm);
+    fft2_body<T, CP, -1>(buf, jb.channels, jb.CT, M, N, a, jb.flip_p, twa, twb, Tm, blk);
 }
 
 // LDS bytes of the FFT schedule for a slice of CT channels (the larger direction's slab)
@@ -840,45 +859,71 @@ bool dft_fft_applies(int channels, const int M[3], const int N[3], bool pruned) 
 // scattered writes than they gain in parallelism) or the slab would exceed 64 KB; CP channels per
 // task (two FP32 channels in one 16-byte access when the channel count is even)
 template <typename T>
-static hipError_t fft2_launch(cplx<T>* buf, int channels, const int M[3], const int N[3], bool inverse, int flip_p,
-                              hipStream_t s) {
-  const int CP = (sizeof(T) == 4 && channels % 2 == 0) ? 2 : 1;
-  int CT = 128 / (int)sizeof(cplx<T>);
-  while (CT > CP && ((channels + CT - 1) / CT < 64 || fft2_lds<T>(M, N, CT) > 64 * 1024)) CT /= 2;
-  const size_t lds = fft2_lds<T>(M, N, CT);
-  if (lds > kLdsMax) return hipErrorInvalidValue;
-  if (lds > 64 * 1024) {
-    static std::once_flag once;
-    static hipError_t attr = hipSuccess;
-    std::call_once(once, [] {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fft2_kernel<T, 1>),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
-      if constexpr (sizeof(T) == 4)
-        if (e == hipSuccess)
-          e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fft2_kernel<T, 2>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
-      attr = e;
-    });
-    if (attr != hipSuccess) return attr;
-  }
-  const int a = fft_first_axis(M, N, inverse), b = 1 - a;
-  // threads: the larger pass's task count, whole waves, at most kFftThreads (a multiple of the
-  // channel packs per slice, so that every thread keeps one pack)
-  const int NCP = CT / CP;
-  const int Pa = N[a] / fft_radix(N[a]), Pb = N[b] / fft_radix(N[b]);
-  const long long ta = (long long)(inverse ? N[b] : M[b]) * Pa, tb = (long long)(inverse ? M[a] : N[a]) * Pb;
-  const int threads = (int)std::min<long long>(kFftThreads, (std::max(ta, tb) * NCP + 63) / 64 * 64);
-  const int blocks = (channels + CT - 1) / CT;
-  if constexpr (sizeof(T) == 4) {
-    if (CP == 2) {
-      hipLaunchKernelGGL((fft2_kernel<T, 2>), dim3(blocks), dim3(threads), lds, s, buf, channels, CT, N[0], N[1],
-                         M[0], M[1], inverse ? 1 : 0, a, flip_p);
-      return hipGetLastError();
+static int fft2_cp(int channels) {
+  return (sizeof(T) == 4 && channels % 2 == 0) ? 2 : 1;
+}
+
+template <typename T, int CP>
+static hipError_t fft2_launch_jobs(const std::vector<FftTransform>& tr, bool inverse, hipStream_t s) {
+  for (size_t i0 = 0; i0 < tr.size(); i0 += kMaxFftJobs) {
+    FftJobs J{};
+    size_t lds = 0;
+    int threads = 64, blocks = 0;
+    for (size_t i = i0; i < std::min(tr.size(), i0 + kMaxFftJobs); ++i) {
+      const FftTransform& t = tr[i];
+      int CT = 128 / (int)sizeof(cplx<T>);
+      while (CT > CP && ((t.channels + CT - 1) / CT < 64 || fft2_lds<T>(t.M, t.N, CT) > 64 * 1024)) CT /= 2;
+      const size_t l = fft2_lds<T>(t.M, t.N, CT);
+      if (l > kLdsMax) return hipErrorInvalidValue;
+      const int a = fft_first_axis(t.M, t.N, inverse), b = 1 - a;
+      // threads: the larger pass's task count, whole waves, at most kFftThreads (any multiple of 64
+      // is a multiple of the channel packs per slice, so that every thread keeps one pack)
+      const int NCP = CT / CP;
+      const int Pa = t.N[a] / fft_radix(t.N[a]), Pb = t.N[b] / fft_radix(t.N[b]);
+      const long long ta = (long long)(inverse ? t.N[b] : t.M[b]) * Pa;
+      const long long tb = (long long)(inverse ? t.M[a] : t.N[a]) * Pb;
+      threads = (int)std::max<long long>(threads, std::min<long long>(kFftThreads, (std::max(ta, tb) * NCP + 63) / 64 * 64));
+      lds = std::max(lds, l);
+      FftJob& j = J.job[J.count++];
+      j.buf = t.buf;
+      j.channels = t.channels;
+      j.CT = CT;
+      j.N0 = t.N[0];
+      j.N1 = t.N[1];
+      j.M0 = t.M[0];
+      j.M1 = t.M[1];
+      j.a = a;
+      j.flip_p = t.flip_p;
+      j.block0 = blocks;
+      blocks += (t.channels + CT - 1) / CT;
     }
+    if (lds > 64 * 1024) {
+      static std::once_flag once;
+      static hipError_t attr = hipSuccess;
+      std::call_once(once, [] {
+        attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&fft2_kernel<T, CP>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
+      });
+      if (attr != hipSuccess) return attr;
+    }
+    hipLaunchKernelGGL((fft2_kernel<T, CP>), dim3(blocks), dim3(threads), lds, s, J, inverse ? 1 : 0);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((fft2_kernel<T, 1>), dim3(blocks), dim3(threads), lds, s, buf, channels, CT, N[0], N[1], M[0],
-                     M[1], inverse ? 1 : 0, a, flip_p);
-  return hipGetLastError();
+  return hipSuccess;
+}
+
+// the FFT schedule of several grids (every one an N3 = 1 grid where dft_fft_applies), in as few
+// launches as their channels-per-task allow (one per precision and pairing of FP32 channels)
+template <typename T>
+hipError_t fft2_group_launch(const std::vector<FftTransform>& tr, bool inverse, hipStream_t s) {
+  std::vector<FftTransform> one, two;
+  for (const FftTransform& t : tr) (fft2_cp<T>(t.channels) == 2 ? two : one).push_back(t);
+  hipError_t e = hipSuccess;
+  if (!one.empty()) e = fft2_launch_jobs<T, 1>(one, inverse, s);
+  if constexpr (sizeof(T) == 4)
+    if (e == hipSuccess && !two.empty()) e = fft2_launch_jobs<T, 2>(two, inverse, s);
+  return e;
 }
 
 template <typename T>
@@ -892,7 +937,9 @@ hipError_t grid_dft_launch(void* bufv, int channels, const int M[3], const int N
       schedule = channels <= kDft2MaxChannels ? 1 : (channels >= kDftmMinChannels ? 3 : 2);
   }
   if (schedule == 4) {
-    if (dft_fft_applies<T>(channels, M, N, pruned)) return fft2_launch<T>(buf, channels, M, N, inverse, flip_p, s);
+    if (dft_fft_applies<T>(channels, M, N, pruned))
+      return fft2_group_launch<T>({FftTransform{buf, channels, {M[0], M[1], M[2]}, {N[0], N[1], N[2]}, flip_p}},
+                                  inverse, s);
     schedule = 0;
   }
   if (schedule == 3 && !dft_mfma_applies<T>(channels, M, N, pruned, fmat)) schedule = 2;
@@ -987,5 +1034,7 @@ template bool dft_mfma_applies<float>(int, const int*, const int*, bool, const v
 template bool dft_fused_applies<float>(int, const int*, const int*, bool);
 template bool dft_fft_applies<double>(int, const int*, const int*, bool);
 template bool dft_fft_applies<float>(int, const int*, const int*, bool);
+template hipError_t fft2_group_launch<double>(const std::vector<FftTransform>&, bool, hipStream_t);
+template hipError_t fft2_group_launch<float>(const std::vector<FftTransform>&, bool, hipStream_t);
 
 }  // namespace fmbem

@@ -11,6 +11,9 @@
 // the groups are summed in LDS.  The product is in place in the [bin][R][p] spectrum
 // buffer.  FP32 takes 8 groups (twice the loads in flight of 4: a bin's matrix is only
 // 118 KB at n_t = 10, measured 17.7 -> 13.7 us on 514 bins), FP64 4.
+#include <algorithm>
+#include <vector>
+
 #include "common.hpp"
 
 namespace fmbem {
@@ -28,16 +31,34 @@ __device__ inline cplx<T>* pair_vec(cplx<T>* buf, int a, int b, int R, int p, in
   return buf + ((size_t)(t < R ? a : b) * R + (t < R ? t : t - R)) * p;
 }
 
+// several plans' products in one launch: workgroup blockIdx.x belongs to the last job whose block0
+// it reaches and handles canonical bin blockIdx.x - block0 of that plan
+struct M2lJob {
+  const void* Lam;
+  const int* pairs;
+  void* buf;
+  int R, p, ldp, block0;
+};
+constexpr int kMaxM2lJobs = 32;
+struct M2lJobs {
+  int count;
+  M2lJob job[kMaxM2lJobs];
+};
+
 // RP row-pair threads per column group (p <= 2 RP) and G groups: RP * G threads
 template <typename T, int RP, int G>
-__global__ __launch_bounds__(RP * G) void m2l_gemv_kernel(const cplx<T>* __restrict__ Lam,
-                                                                 const int* __restrict__ pairs,
-                                                                 cplx<T>* __restrict__ buf, int R, int p, int ldp) {
+__global__ __launch_bounds__(RP * G) void m2l_gemv_kernel(M2lJobs J) {
   extern __shared__ unsigned char smem_raw[];
+  int jq = 0;
+  while (jq + 1 < J.count && (int)blockIdx.x >= J.job[jq + 1].block0) ++jq;
+  const cplx<T>* __restrict__ Lam = reinterpret_cast<const cplx<T>*>(J.job[jq].Lam);
+  const int* __restrict__ pairs = J.job[jq].pairs;
+  cplx<T>* __restrict__ buf = reinterpret_cast<cplx<T>*>(J.job[jq].buf);
+  const int R = J.job[jq].R, p = J.job[jq].p, ldp = J.job[jq].ldp;
   cplx<T>* xs = reinterpret_cast<cplx<T>*>(smem_raw);        // [kRhs][p]
   cplx<T>* red = xs + kRhs * p;                               // [G][RP][kRhs][2]
   using P2 = typename Pair<T>::type;
-  const int c = blockIdx.x;
+  const int c = (int)blockIdx.x - J.job[jq].block0;
   const int ba = pairs[2 * c], bb = pairs[2 * c + 1];
   const int nv = bb >= 0 ? 2 * R : R;
   const cplx<T>* Lb = Lam + (size_t)c * p * ldp;
@@ -99,13 +120,18 @@ __global__ __launch_bounds__(RP * G) void m2l_gemv_kernel(const cplx<T>* __restr
   }
 }
 
-// generic fallback for p > 256 (n_t >= 16): one thread per row
+// generic fallback for p > 256 (n_t >= 16, exact PBEM blocks): one thread per row
 template <typename T>
-__global__ void m2l_rows_kernel(const cplx<T>* __restrict__ Lam, const int* __restrict__ pairs,
-                                cplx<T>* __restrict__ buf, int R, int p, int ldp) {
+__global__ void m2l_rows_kernel(M2lJobs J) {
   extern __shared__ unsigned char smem_raw[];
+  int jq = 0;
+  while (jq + 1 < J.count && (int)blockIdx.x >= J.job[jq + 1].block0) ++jq;
+  const cplx<T>* __restrict__ Lam = reinterpret_cast<const cplx<T>*>(J.job[jq].Lam);
+  const int* __restrict__ pairs = J.job[jq].pairs;
+  cplx<T>* __restrict__ buf = reinterpret_cast<cplx<T>*>(J.job[jq].buf);
+  const int R = J.job[jq].R, p = J.job[jq].p, ldp = J.job[jq].ldp;
   cplx<T>* xs = reinterpret_cast<cplx<T>*>(smem_raw);  // [kRhs][p]
-  const int c = blockIdx.x;
+  const int c = (int)blockIdx.x - J.job[jq].block0;
   const int ba = pairs[2 * c], bb = pairs[2 * c + 1];
   const int nv = bb >= 0 ? 2 * R : R;
   const cplx<T>* Lb = Lam + (size_t)c * p * ldp;
@@ -134,27 +160,66 @@ __global__ void m2l_rows_kernel(const cplx<T>* __restrict__ Lam, const int* __re
 
 int lambda_ld(int p) { return p + (p & 1); }
 
+// kernel form of a plan's product: 0 the GEMV with 64 row pairs (p <= 128), 1 with 128 row pairs
+// (p <= 256), 2 one thread per row
+static int m2l_form(int p) { return p <= 128 ? 0 : (p <= 256 ? 1 : 2); }
+
+template <typename T>
+static hipError_t m2l_launch_form(int form, const std::vector<M2lProduct>& v, hipStream_t s) {
+  for (size_t i0 = 0; i0 < v.size(); i0 += kMaxM2lJobs) {
+    M2lJobs J{};
+    int blocks = 0, pmax = 1;
+    for (size_t i = i0; i < std::min(v.size(), i0 + kMaxM2lJobs); ++i) {
+      M2lJob& j = J.job[J.count++];
+      j.Lam = v[i].Lam;
+      j.pairs = v[i].pairs;
+      j.buf = v[i].buf;
+      j.R = v[i].R;
+      j.p = v[i].p;
+      j.ldp = lambda_ld(v[i].p);
+      j.block0 = blocks;
+      blocks += v[i].Bc;
+      pmax = std::max(pmax, v[i].p);
+    }
+    if (form == 0) {
+      constexpr int G = gemv_groups<T>();
+      const size_t lds = (size_t)(kRhs * pmax + G * 64 * kRhs * 2) * sizeof(cplx<T>);
+      hipLaunchKernelGGL((m2l_gemv_kernel<T, 64, G>), dim3(blocks), dim3(64 * G), lds, s, J);
+    } else if (form == 1) {
+      const size_t lds = (size_t)(kRhs * pmax + 4 * 128 * kRhs * 2) * sizeof(cplx<T>);
+      hipLaunchKernelGGL((m2l_gemv_kernel<T, 128, 4>), dim3(blocks), dim3(128 * 4), lds, s, J);
+    } else {
+      const int threads = std::min(512, ((pmax + 63) / 64) * 64);
+      hipLaunchKernelGGL(m2l_rows_kernel<T>, dim3(blocks), dim3(threads), kRhs * pmax * sizeof(cplx<T>), s, J);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// the GEMV products of several plans, one launch per kernel form
+template <typename T>
+hipError_t m2l_group_launch(const std::vector<M2lProduct>& v, hipStream_t s) {
+  for (int form = 0; form < 3; ++form) {
+    std::vector<M2lProduct> sel;
+    for (const M2lProduct& q : v)
+      if (m2l_form(q.p) == form) sel.push_back(q);
+    if (sel.empty()) continue;
+    const hipError_t e = m2l_launch_form<T>(form, sel, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 template <typename T>
 hipError_t m2l_launch(const void* Lam, const int* pairs, int Bc, void* buf, int R, int p, hipStream_t s) {
-  const int ldp = lambda_ld(p);
-  if (p <= 128) {
-    constexpr int G = gemv_groups<T>();
-    const size_t lds = (size_t)(kRhs * p + G * 64 * kRhs * 2) * sizeof(cplx<T>);
-    hipLaunchKernelGGL((m2l_gemv_kernel<T, 64, G>), dim3(Bc), dim3(64 * G), lds, s,
-                       reinterpret_cast<const cplx<T>*>(Lam), pairs, reinterpret_cast<cplx<T>*>(buf), R, p, ldp);
-  } else if (p <= 256) {
-    const size_t lds = (size_t)(kRhs * p + 4 * 128 * kRhs * 2) * sizeof(cplx<T>);
-    hipLaunchKernelGGL((m2l_gemv_kernel<T, 128, 4>), dim3(Bc), dim3(128 * 4), lds, s,
-                       reinterpret_cast<const cplx<T>*>(Lam), pairs, reinterpret_cast<cplx<T>*>(buf), R, p, ldp);
-  } else {
-    const int threads = min(512, ((p + 63) / 64) * 64);
-    hipLaunchKernelGGL(m2l_rows_kernel<T>, dim3(Bc), dim3(threads), kRhs * p * sizeof(cplx<T>), s,
-                       reinterpret_cast<const cplx<T>*>(Lam), pairs, reinterpret_cast<cplx<T>*>(buf), R, p, ldp);
-  }
-  return hipGetLastError();
+  return m2l_group_launch<T>({M2lProduct{Lam, pairs, Bc, buf, R, p}}, s);
 }
 
 template hipError_t m2l_launch<double>(const void*, const int*, int, void*, int, int, hipStream_t);
 template hipError_t m2l_launch<float>(const void*, const int*, int, void*, int, int, hipStream_t);
+template hipError_t m2l_group_launch<double>(const std::vector<M2lProduct>&, hipStream_t);
+template hipError_t m2l_group_launch<float>(const std::vector<M2lProduct>&, hipStream_t);
 
 }  // namespace fmbem

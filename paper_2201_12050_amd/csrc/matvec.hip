@@ -388,10 +388,14 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
   return e;
 }
 
-// Operator applications of several plans in one sequence: the near field + S2M jobs of all
-// of them share one grouped launch and so do the L2T jobs; the DFT / M2L / inverse DFT
-// stages run per plan.  tune: autotune the tile shape of the combined job list (blocks the
-// host once per composition); otherwise a cached shape of that composition or the default.
+// Operator applications of several plans in one sequence, every stage in shared launches: the near
+// field + S2M jobs of all of them in one grouped launch, then the forward grid FFTs of all of them,
+// their GEMV M2L products and their M2L GEMMs, the inverse FFTs, and one grouped L2T launch (a plan
+// whose DFT schedule is not the FFT, or whose M2L GEMM tile shape is forced, runs that stage in a
+// launch of its own).  The grouped FFT and GEMV kernels sum every output of a plan in the same order
+// as its own launch; the GEMM tile shapes are those tuned for the combined job list.  tune: autotune
+// the tile shapes of the combined job lists (blocks the host once per composition); otherwise cached
+// shapes or defaults.
 template <typename T>
 static hipError_t matvec_group_t(const std::vector<GroupApply>& g, hipStream_t s, bool tune) {
   const int prec = sizeof(T) == 8 ? 0 : 1;
@@ -402,24 +406,81 @@ static hipError_t matvec_group_t(const std::vector<GroupApply>& g, hipStream_t s
   int shape = tune ? tuned_shape<T>(0, jobs, s) : cached_shape<T>(0, jobs);
   hipError_t e = near_launch<T>(jobs, s, shape, 0);
   if (e != hipSuccess) return e;
-  std::vector<NearJob> l2t;
+  std::vector<size_t> far;
   for (size_t q = 0; q < g.size(); ++q) {
     const GroupApply& a = g[q];
     const Plan& P = *a.P;
     if (P.n_far == 0) {
       e = near_reduce_launch<T>(near_partials<T>(P, a.R, a.ws), P.n_near, (size_t)a.R * P.C * P.n, a.y, a.y64, s);
       if (e != hipSuccess) return e;
-      continue;
+    } else {
+      far.push_back(q);
     }
-    void* lhat = nullptr;
-    e = grid_dft_launch<T>(a.ws, a.R * P.p, P.grid, P.fft, false, true, s, P.flip_p(), sched_fwd(dsched[q]), P.dftF[prec]);
-    if (e != hipSuccess) return e;
-    if ((e = m2l_apply<T>(P, a.R, a.ws, s, &lhat, tune)) != hipSuccess) return e;
-    e = grid_dft_launch<T>(lhat, a.R * P.p, P.grid, P.fft, true, true, s, P.flip_p(), sched_inv(dsched[q]), P.dftF[prec]);
-    if (e != hipSuccess) return e;
-    l2t.push_back(l2t_job<T>(P, a.R, a.ws, lhat, a.y, a.y64));
   }
-  if (l2t.empty()) return hipSuccess;
+  if (far.empty()) return hipSuccess;
+  auto fft_ok = [&](size_t q, bool inv) {
+    const GroupApply& a = g[q];
+    const int sc = inv ? sched_inv(dsched[q]) : sched_fwd(dsched[q]);
+    return sc == 4 && dft_fft_applies<T>(a.R * a.P->p, a.P->grid, a.P->fft, true);
+  };
+  // forward transforms
+  std::vector<FftTransform> tr;
+  for (size_t q : far) {
+    const GroupApply& a = g[q];
+    const Plan& P = *a.P;
+    if (fft_ok(q, false)) {
+      tr.push_back(FftTransform{a.ws, a.R * P.p, {P.grid[0], P.grid[1], P.grid[2]}, {P.fft[0], P.fft[1], P.fft[2]},
+                                P.flip_p()});
+    } else if ((e = grid_dft_launch<T>(a.ws, a.R * P.p, P.grid, P.fft, false, true, s, P.flip_p(), sched_fwd(dsched[q]),
+                                       P.dftF[prec])) != hipSuccess) {
+      return e;
+    }
+  }
+  if (!tr.empty() && (e = fft2_group_launch<T>(tr, false, s)) != hipSuccess) return e;
+  // per-bin M2L: GEMV products together, GEMMs together (into the second grid)
+  std::vector<void*> lhat(g.size(), nullptr);
+  std::vector<M2lProduct> gemv;
+  std::vector<NearJob> gemm;
+  for (size_t q : far) {
+    const GroupApply& a = g[q];
+    const Plan& P = *a.P;
+    if (a.R < kM2lGemmRhs) {
+      gemv.push_back(M2lProduct{P.Lam[prec], P.d_pairs, P.Bc, a.ws, a.R, P.p});
+      lhat[q] = a.ws;
+    } else if (P.tile_forced[2] >= 0) {
+      if ((e = m2l_apply<T>(P, a.R, a.ws, s, &lhat[q], tune)) != hipSuccess) return e;
+    } else {
+      void* out = second_grid<T>(P, a.R, a.ws);
+      NearJob j = near_job(P, a.R, P.Lam[prec], out, P.p, P.p, a.ws, SRC_BATCH, DEST_SLICE);
+      j.N = a.R;
+      j.lda = lambda_ld(P.p);
+      j.batch = P.B;
+      j.amap = P.d_canon;
+      gemm.push_back(j);
+      lhat[q] = out;
+    }
+  }
+  if (!gemv.empty() && (e = m2l_group_launch<T>(gemv, s)) != hipSuccess) return e;
+  if (!gemm.empty()) {
+    shape = tune ? tuned_shape<T>(2, gemm, s) : cached_shape<T>(2, gemm);
+    if ((e = near_launch<T>(gemm, s, shape, 2)) != hipSuccess) return e;
+  }
+  // inverse transforms
+  tr.clear();
+  for (size_t q : far) {
+    const GroupApply& a = g[q];
+    const Plan& P = *a.P;
+    if (fft_ok(q, true)) {
+      tr.push_back(FftTransform{lhat[q], a.R * P.p, {P.grid[0], P.grid[1], P.grid[2]},
+                                {P.fft[0], P.fft[1], P.fft[2]}, P.flip_p()});
+    } else if ((e = grid_dft_launch<T>(lhat[q], a.R * P.p, P.grid, P.fft, true, true, s, P.flip_p(),
+                                       sched_inv(dsched[q]), P.dftF[prec])) != hipSuccess) {
+      return e;
+    }
+  }
+  if (!tr.empty() && (e = fft2_group_launch<T>(tr, true, s)) != hipSuccess) return e;
+  std::vector<NearJob> l2t;
+  for (size_t q : far) l2t.push_back(l2t_job<T>(*g[q].P, g[q].R, g[q].ws, lhat[q], g[q].y, g[q].y64));
   shape = tune ? tuned_shape<T>(1, l2t, s) : cached_shape<T>(1, l2t);
   return near_launch<T>(l2t, s, shape, 1);
 }
