@@ -36,16 +36,15 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
-// part[r][i][blk] = sum_{n in block} conj(V_i[r][n]) w[r][n]; grid (blocks, vector groups of 8, R)
-__global__ __launch_bounds__(kDotThreads) void mdot_kernel(const double2* __restrict__ V, size_t vstride,
-                                                           const double2* __restrict__ w, size_t N, int J,
-                                                           double2* __restrict__ part, const int* __restrict__ flag) {
+// part[r][i][blk] = sum_{n in block} conj(V_i[r][n]) w[r][n]; workgroup (bx, by, r) of a grid
+// (nblk blocks, vector groups of 8, R)
+__device__ inline void mdot_body(const double2* __restrict__ V, size_t vstride, const double2* __restrict__ w,
+                                 size_t N, int J, double2* __restrict__ part, const int* __restrict__ flag, int bx,
+                                 int by, int r, int nblk) {
   __shared__ double2 red[kDotThreads / 64][kDotVec];
-  const int r = blockIdx.z;
   if (flag && !flag[r]) return;  // conditional pass not needed for this RHS
-  const int i0 = blockIdx.y * kDotVec;
-  const int nblk = gridDim.x;
-  const size_t base = (size_t)blockIdx.x * kDotThreads * kDotEl + threadIdx.x;
+  const int i0 = by * kDotVec;
+  const size_t base = (size_t)bx * kDotThreads * kDotEl + threadIdx.x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   // every load first, from clamped indices (an element past N has w = 0, a vector past J is
   // never written out), so that all kDotVec x kDotEl loads are in flight together
@@ -87,15 +86,22 @@ __global__ __launch_bounds__(kDotThreads) void mdot_kernel(const double2* __rest
       s.x += red[t][threadIdx.x].x;
       s.y += red[t][threadIdx.x].y;
     }
-    part[((size_t)r * J + i0 + threadIdx.x) * nblk + blockIdx.x] = s;
+    part[((size_t)r * J + i0 + threadIdx.x) * nblk + bx] = s;
   }
+}
+
+__global__ __launch_bounds__(kDotThreads) void mdot_kernel(const double2* __restrict__ V, size_t vstride,
+                                                           const double2* __restrict__ w, size_t N, int J,
+                                                           double2* __restrict__ part, const int* __restrict__ flag) {
+  mdot_body(V, vstride, w, N, J, part, flag, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x);
 }
 
 // one wave per (r, i) sums the block partials s; mode 0: h = s; mode 2: h = sqrt(Re s);
 // mode 3: h2 = s and h += s (second Gram-Schmidt pass)
-__global__ void mdot_finish(const double2* __restrict__ part, int nblk, int R, int J, double2* __restrict__ h,
-                            int hstride, int mode, double2* __restrict__ h2, const int* __restrict__ flag) {
-  const int t = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+__device__ inline void finish_body(const double2* __restrict__ part, int nblk, int R, int J, double2* __restrict__ h,
+                                   int hstride, int mode, double2* __restrict__ h2, const int* __restrict__ flag,
+                                   int bx) {
+  const int t = bx * (blockDim.x / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (t >= R * J) return;
   const int r = t / J, i = t - r * J;
@@ -119,19 +125,22 @@ __global__ void mdot_finish(const double2* __restrict__ part, int nblk, int R, i
   }
 }
 
+__global__ void mdot_finish(const double2* __restrict__ part, int nblk, int R, int J, double2* __restrict__ h,
+                            int hstride, int mode, double2* __restrict__ h2, const int* __restrict__ flag) {
+  finish_body(part, nblk, R, J, h, hstride, mode, h2, flag, blockIdx.x);
+}
+
 // w[r][n] += sgn * sum_{i<J} c[r][i] V_i[r][n]; with npart, also per-block sums of |w|^2
-__global__ __launch_bounds__(256) void maxpy_kernel(const double2* __restrict__ V, size_t vstride,
-                                                    const double2* __restrict__ c, int cstride,
-                                                    double2* __restrict__ w, size_t N, int J, double sgn,
-                                                    double* __restrict__ npart, const int* __restrict__ flag) {
+__device__ inline void maxpy_body(const double2* __restrict__ V, size_t vstride, const double2* __restrict__ c,
+                                  int cstride, double2* __restrict__ w, size_t N, int J, double sgn,
+                                  double* __restrict__ npart, const int* __restrict__ flag, int bx, int r, int gx) {
   extern __shared__ double2 cs[];
   __shared__ double red[4];
-  const int r = blockIdx.y;
   if (flag && !flag[r]) return;
   for (int i = threadIdx.x; i < J; i += blockDim.x) cs[i] = c[(size_t)r * cstride + i];
   __syncthreads();
   double nn = 0.0;
-  for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (size_t)gridDim.x * blockDim.x) {
+  for (size_t n = (size_t)bx * blockDim.x + threadIdx.x; n < N; n += (size_t)gx * blockDim.x) {
     double2 acc = w[(size_t)r * N + n];
     for (int i = 0; i < J; ++i) {
       const double2 v = V[i * vstride + (size_t)r * N + n];
@@ -145,8 +154,15 @@ __global__ __launch_bounds__(256) void maxpy_kernel(const double2* __restrict__ 
     nn = wave_sum(nn);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nn;
     __syncthreads();
-    if (threadIdx.x == 0) npart[(size_t)r * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    if (threadIdx.x == 0) npart[(size_t)r * gx + bx] = red[0] + red[1] + red[2] + red[3];
   }
+}
+
+__global__ __launch_bounds__(256) void maxpy_kernel(const double2* __restrict__ V, size_t vstride,
+                                                    const double2* __restrict__ c, int cstride,
+                                                    double2* __restrict__ w, size_t N, int J, double sgn,
+                                                    double* __restrict__ npart, const int* __restrict__ flag) {
+  maxpy_body(V, vstride, c, cstride, w, N, J, sgn, npart, flag, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 // DGKS criterion (Daniel, Gragg, Kaufman & Stewart, 1976): a second Gram-Schmidt pass is
@@ -233,24 +249,22 @@ __device__ inline double partial_norm(const double* __restrict__ npart, int nb, 
 // LDS copies, the residual estimate |g_{j+1}| and the freeze flag (also written to mapped
 // host memory for the host's convergence check).  Grid (blocks, R), 256 threads.
 constexpr int kMaxRestart = 1000;
-__global__ __launch_bounds__(256) void scale_givens_kernel(const double* __restrict__ npart, int nb, int m, int j,
-                                                           const double2* __restrict__ hc, int hstride,
-                                                           double2* __restrict__ hn, double2* __restrict__ H,
-                                                           double2* __restrict__ cs, double2* __restrict__ sn,
-                                                           double2* __restrict__ g, double* __restrict__ res,
-                                                           int* __restrict__ jdone, int* __restrict__ jdone_host,
-                                                           const double* __restrict__ tol, double2* __restrict__ w,
-                                                           float2* __restrict__ w32, size_t N) {
-  const int r = blockIdx.y;
+__device__ inline void scale_givens_body(const double* __restrict__ npart, int nb, int m, int j,
+                                         const double2* __restrict__ hc, int hstride, double2* __restrict__ hn,
+                                         double2* __restrict__ H, double2* __restrict__ cs, double2* __restrict__ sn,
+                                         double2* __restrict__ g, double* __restrict__ res, int* __restrict__ jdone,
+                                         int* __restrict__ jdone_host, const double* __restrict__ tol,
+                                         double2* __restrict__ w, float2* __restrict__ w32, size_t N, int bx, int r,
+                                         int gx) {
   const double nrm = partial_norm(npart, nb, r);
   const double f = nrm > 0 ? 1.0 / nrm : 0.0;
-  for (size_t n = (size_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (size_t)gridDim.x * blockDim.x) {
+  for (size_t n = (size_t)bx * blockDim.x + threadIdx.x; n < N; n += (size_t)gx * blockDim.x) {
     const double2 v = w[(size_t)r * N + n];
     const double2 o = make_double2(v.x * f, v.y * f);
     w[(size_t)r * N + n] = o;
     if (w32) w32[(size_t)r * N + n] = make_float2((float)o.x, (float)o.y);
   }
-  if (blockIdx.x != 0) return;
+  if (bx != 0) return;
   // LDS (dynamic, 3m + 2 entries): Hessenberg column, cosines and sines of the earlier rotations
   extern __shared__ double2 gv_lds[];
   double2* col = gv_lds;
@@ -304,6 +318,18 @@ __global__ __launch_bounds__(256) void scale_givens_kernel(const double* __restr
   for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) Hr[(size_t)i * m + j] = col[i];
 }
 
+__global__ __launch_bounds__(256) void scale_givens_kernel(const double* __restrict__ npart, int nb, int m, int j,
+                                                           const double2* __restrict__ hc, int hstride,
+                                                           double2* __restrict__ hn, double2* __restrict__ H,
+                                                           double2* __restrict__ cs, double2* __restrict__ sn,
+                                                           double2* __restrict__ g, double* __restrict__ res,
+                                                           int* __restrict__ jdone, int* __restrict__ jdone_host,
+                                                           const double* __restrict__ tol, double2* __restrict__ w,
+                                                           float2* __restrict__ w32, size_t N) {
+  scale_givens_body(npart, nb, m, j, hc, hstride, hn, H, cs, sn, g, res, jdone, jdone_host, tol, w, w32, N,
+                    blockIdx.x, blockIdx.y, gridDim.x);
+}
+
 // y = H^{-1} g (upper triangular, size jdone[r] or jcur) by column sweeps; one workgroup per RHS
 __global__ __launch_bounds__(256) void backsolve_kernel(int m, int jcur, const double2* __restrict__ H,
                                                         const double2* __restrict__ g,
@@ -352,6 +378,70 @@ __global__ void gmres_init_kernel(int R, int m, const double2* __restrict__ beta
   jdone[r] = b > tol[r] ? -1 : 0;
   jdone_host[r] = jdone[r];
   res[r] = b;
+}
+
+// Classical Gram-Schmidt of several members' Arnoldi steps in shared launches: each of the four
+// kernels of a single-pass step (dots, their reduction, the multi-axpy with |w|^2 partials, the
+// normalisation with the Givens update) runs once for all members of a round.  Member q owns the
+// workgroups [block0[q], block0[q+1]) of a launch and sees the same local workgroup indices and
+// grid sizes as its own launch would give it, so its results are bitwise those of the
+// per-member sequence.
+struct GsDev {  // a member's buffers and sizes, copied to the device when the member is set up
+  double2 *V, *part, *hc, *hn, *H, *cs, *sn, *g;
+  double *res, *tolv, *npart;
+  int* jdone;
+  int* djd[2];
+  float2* x32;
+  size_t N, vlen;
+  int R, nblk, nb, hstride, m;
+};
+constexpr int kMaxGsJobs = 32;
+struct GsJobs {
+  int count;
+  const GsDev* d[kMaxGsJobs];
+  int j[kMaxGsJobs];     // Arnoldi step: w = A v_j sits in the slot of v_{j+1}
+  int mode[kMaxGsJobs];  // bit 0: round slot of the freeze flags, bit 1: FP32 copy of v_{j+1}
+  int block0[kMaxGsJobs + 1];
+};
+__device__ inline int gs_job(const GsJobs& J) {
+  int q = 0;
+  while (q + 1 < J.count && (int)blockIdx.x >= J.block0[q + 1]) ++q;
+  return q;
+}
+// workgroups of member q in each kernel
+static inline int gs_blocks(int kernel, const GsDev& h, int j) {
+  if (kernel == 0) return h.nblk * ((j + 2 + kDotVec - 1) / kDotVec) * h.R;
+  if (kernel == 1) return (h.R * (j + 2) + 3) / 4;
+  return h.nb * h.R;
+}
+
+__global__ __launch_bounds__(kDotThreads) void gs_mdot_kernel(GsJobs J) {
+  const int q = gs_job(J);
+  const GsDev& D = *J.d[q];
+  const int jn = J.j[q] + 2, ny = (jn + kDotVec - 1) / kDotVec;
+  const int l = (int)blockIdx.x - J.block0[q];
+  const int bx = l % D.nblk, by = (l / D.nblk) % ny, r = l / (D.nblk * ny);
+  mdot_body(D.V, D.vlen, D.V + (size_t)(J.j[q] + 1) * D.vlen, D.N, jn, D.part, nullptr, bx, by, r, D.nblk);
+}
+__global__ void gs_finish_kernel(GsJobs J) {
+  const int q = gs_job(J);
+  const GsDev& D = *J.d[q];
+  finish_body(D.part, D.nblk, D.R, J.j[q] + 2, D.hc, D.hstride, 0, nullptr, nullptr, (int)blockIdx.x - J.block0[q]);
+}
+__global__ __launch_bounds__(256) void gs_maxpy_kernel(GsJobs J) {
+  const int q = gs_job(J);
+  const GsDev& D = *J.d[q];
+  const int l = (int)blockIdx.x - J.block0[q];
+  maxpy_body(D.V, D.vlen, D.hc, D.hstride, D.V + (size_t)(J.j[q] + 1) * D.vlen, D.N, J.j[q] + 1, -1.0, D.npart,
+             nullptr, l % D.nb, l / D.nb, D.nb);
+}
+__global__ __launch_bounds__(256) void gs_scale_givens_kernel(GsJobs J) {
+  const int q = gs_job(J);
+  const GsDev& D = *J.d[q];
+  const int l = (int)blockIdx.x - J.block0[q], md = J.mode[q];
+  scale_givens_body(D.npart, D.nb, D.m, J.j[q], D.hc, D.hstride, D.hn, D.H, D.cs, D.sn, D.g, D.res, D.jdone,
+                    D.djd[md & 1], D.tolv, D.V + (size_t)(J.j[q] + 1) * D.vlen, (md & 2) ? D.x32 : nullptr, D.N,
+                    l % D.nb, l / D.nb, D.nb);
 }
 
 // One linear system set (a plan and R right-hand sides) advanced one operator application
@@ -417,6 +507,8 @@ struct Member {
   double* hres[2] = {nullptr, nullptr};
   double* dres[2] = {nullptr, nullptr};
   double* htol = nullptr;  // pinned staging of per-RHS tolerances
+  GsDev gsh{};             // host image of gsd (kept: the copy to the device is asynchronous)
+  GsDev* gsd = nullptr;    // this member's buffers for the grouped Gram-Schmidt kernels
 
   // state
   enum Phase { RUN_TRUE, START_INNER, RUN_RESTART, RUN_ARN, CLOSE, WAIT, DONE };
@@ -494,7 +586,8 @@ struct Member {
                        {(void**)&tolv, R * sizeof(double)},
                        {(void**)&jdone, R * sizeof(int)},
                        {(void**)&npart, (size_t)R * nb * sizeof(double)},
-                       {(void**)&reorth, R * sizeof(int)}};
+                       {(void**)&reorth, R * sizeof(int)},
+                       {(void**)&gsd, sizeof(GsDev)}};
     if (need32) v.push_back({(void**)&x32, vlen * sizeof(float2)});
     for (Buf& q : v) q.bytes = std::max<size_t>((q.bytes + 255) / 256 * 256, 256);
     return v;
@@ -519,7 +612,9 @@ struct Member {
       if ((e = hipHostGetDevicePointer((void**)&dres[i], hres[i], 0))) return e;
     }
     if ((e = pinned_get((void**)&htol, R * sizeof(double), hipHostMallocDefault))) return e;
-    return hipSuccess;
+    gsh = GsDev{V, part, hc, hn, H, cs, sn, g, res, tolv, npart, jdone, {djd[0], djd[1]}, x32, N, vlen, R, nblk, nb,
+                hstride, m};
+    return hipMemcpyAsync(gsd, &gsh, sizeof(GsDev), hipMemcpyHostToDevice, s);
   }
   dim3 vgrid() const { return dim3((unsigned)nb, R); }
   unsigned lgrid(size_t len) const { return (unsigned)std::min<size_t>((len + 255) / 256, 4096); }
@@ -658,7 +753,10 @@ struct Member {
     }
   }
 
-  void post(int slot) {
+  // grouped: this step's single-pass Gram-Schmidt is launched by the caller together with other
+  // members' (gs_group_launch)
+  bool gs_groupable(int slot) const { return rec[slot].kind == K_ARN && emit && ortho == FMBEM_ORTHO_ONCE; }
+  void post(int slot, bool grouped = false) {
     switch (rec[slot].kind) {
       case K_TRUE:
         hipLaunchKernelGGL(sub_kernel, dim3(lgrid(vlen)), dim3(256), 0, s, b, t, r, vlen);
@@ -674,7 +772,7 @@ struct Member {
         phase = RUN_ARN;
         break;
       case K_ARN: {
-        if (emit) {
+        if (emit && !grouped) {
           double2* wv = V + (size_t)(j + 1) * vlen;
           // Gram-Schmidt: h = V^H w (and ||w||^2 as the last dot), w -= V h (with |w|^2 partials);
           // second pass h2 = V^H w, w -= V h2, h += h2 where the DGKS criterion (or the mode) asks for it
@@ -792,6 +890,40 @@ static void configure(Member& mb, const SolveCfg& c, const void* b, void* x) {
   mb.x = reinterpret_cast<double2*>(x);
 }
 
+// single-pass Gram-Schmidt steps of several members, each kernel once per kMaxGsJobs steps
+struct GsStep {
+  const GsDev* d;
+  const GsDev* h;
+  int j, mode;
+};
+static hipError_t gs_group_launch(const std::vector<GsStep>& v, hipStream_t s) {
+  for (size_t i0 = 0; i0 < v.size(); i0 += kMaxGsJobs) {
+    const size_t i1 = std::min(v.size(), i0 + kMaxGsJobs);
+    for (int kernel = 0; kernel < 4; ++kernel) {
+      GsJobs J{};
+      int blocks = 0;
+      size_t lds = 0;
+      for (size_t i = i0; i < i1; ++i) {
+        J.d[J.count] = v[i].d;
+        J.j[J.count] = v[i].j;
+        J.mode[J.count] = v[i].mode;
+        J.block0[J.count++] = blocks;
+        blocks += gs_blocks(kernel, *v[i].h, v[i].j);
+        if (kernel == 2) lds = std::max(lds, (size_t)(v[i].j + 1) * sizeof(double2));
+        if (kernel == 3) lds = std::max(lds, (size_t)(3 * v[i].h->m + 2) * sizeof(double2));
+      }
+      J.block0[J.count] = blocks;
+      if (kernel == 0) hipLaunchKernelGGL(gs_mdot_kernel, dim3(blocks), dim3(kDotThreads), 0, s, J);
+      else if (kernel == 1) hipLaunchKernelGGL(gs_finish_kernel, dim3(blocks), dim3(256), 0, s, J);
+      else if (kernel == 2) hipLaunchKernelGGL(gs_maxpy_kernel, dim3(blocks), dim3(256), lds, s, J);
+      else hipLaunchKernelGGL(gs_scale_givens_kernel, dim3(blocks), dim3(256), lds, s, J);
+      const hipError_t e = hipGetLastError();
+      if (e) return e;
+    }
+  }
+  return hipSuccess;
+}
+
 // The work of one round: pre() of every member, the members' operator applications in
 // grouped launches (one sequence per precision), post() of every member.
 static hipError_t round_enqueue(const std::vector<Member*>& ms, int slot, hipStream_t s, bool tune) {
@@ -807,7 +939,13 @@ static hipError_t round_enqueue(const std::vector<Member*>& ms, int slot, hipStr
   hipError_t e = matvec_group(FMBEM_FP64, g64, s, tune);
   if (!e) e = matvec_group(FMBEM_FP32, g32, s, tune);
   if (e) return e;
-  for (Member* mb : ms) mb->post(slot);
+  std::vector<GsStep> gs;
+  for (Member* mb : ms)
+    if (mb->gs_groupable(slot))
+      gs.push_back(GsStep{mb->gsd, &mb->gsh, mb->j, slot | (mb->gm_prec == FMBEM_FP32 ? 2 : 0)});
+  const bool grouped = gs.size() >= 2;
+  for (Member* mb : ms) mb->post(slot, grouped && mb->gs_groupable(slot));
+  if (grouped && (e = gs_group_launch(gs, s))) return e;
   return hipGetLastError();
 }
 

@@ -60,16 +60,31 @@ def problems():
     return out
 
 
-def test_batch_matches_oracle_and_alone(problems):
+@pytest.mark.parametrize("ortho", ["dgks", "once"])
+def test_batch_matches_oracle_and_alone(problems, ortho):
+    # single-pass Gram-Schmidt of the members runs in shared launches, DGKS per member
     import paper_2201_12050_amd as fm
-    res = fm.solve_batch([(p["P"], p["b"], None, p["opts"]) for p in problems])
-    for p, (x, infos) in zip(problems, res):
+    opts = [dict(p["opts"], ortho=ortho) for p in problems]
+    res = fm.solve_batch([(p["P"], p["b"], None, o) for p, o in zip(problems, opts)])
+    for p, o, (x, infos) in zip(problems, opts, res):
         for q, inf in enumerate(infos):
             assert inf["rel_residual"] <= 1e-9, (p["name"], q, inf)
         xb = x.cpu().numpy().reshape(p["x_lu"].shape)
         assert rel(xb, p["x_lu"]) < 1e-6, p["name"]
-        xa, ia = p["P"].solve(p["b"], **p["opts"])
+        xa, ia = p["P"].solve(p["b"], **o)
         assert rel(xb, xa.cpu().numpy().reshape(xb.shape)) < 1e-9, p["name"]
+
+
+def test_batch_copies_agree_bitwise(problems):
+    # the same problem three times in one batch: each member's share of the shared launches
+    # (grouped operator and Gram-Schmidt kernels) gives it the same bits
+    import paper_2201_12050_amd as fm
+    p = problems[2]
+    o = dict(p["opts"], ortho="once")
+    res = fm.solve_batch([(p["P"], p["b"].clone(), None, o) for _ in range(3)])
+    for x, infos in res[1:]:
+        assert torch.equal(x, res[0][0])
+        assert infos == res[0][1]
 
 
 def test_batch_of_one_equals_solve(problems):
