@@ -18,11 +18,26 @@ Operators (Appendix A), every cell using the same matrices (Sec. 3.2):
     with W = (2l+1) i^{n-n'+l} (n n' l; 0 0 0)(n n' l; m m' -m-m')  (eq. (wigner))
     and l over max(|m+m'|, |n-n'|) <= l <= n+n', n+n'-l even.
 
+Multilevel translations (Appendix A, eqs. (m2m), (l2l); used by the FMPBEM2
+near field of Sec. 3.3):
+  T(b) (M2M, eq. (m2m)): moments about y_c' from moments about y_c, b = y_c - y_c'
+      T[(n,m),(n',m')] = (2n'+1)(-1)^{m'} sum_l W_{n,n',m,-m',l} I_l^{m'-m}(b)
+      (eq. (m2m) with its summation index m' renamed to -m'); it is the
+      regular addition theorem conj(I_n^m(a + b)) = sum T[(n,m),(n',m')] conj(I_n'^m'(a)).
+  L2L: local coefficients about x_c' from those about x_c, b = x_c' - x_c
+      L'(n,m) = (-1)^m sum_{n',m'} (2n'+1) sum_l W_{n',n,m',-m,l} I_l^{m-m'}(b) L(n',m'),
+      i.e. (2n+1) L'(n,m) = sum (2n'+1) T[(n',m'),(n,m)](b) L(n',m'): the expansion of
+      eq. (l2p) re-centred with the same addition theorem.
+  Both truncate the source order at n_t (exact as the source order grows).
+
 Readings of the printed formulas (each checked against the exact kernel by
 the addition-theorem tests): the bounds on l are inclusive (the printed strict
 bounds leave the monopole term n = n' = 0 empty), the power of i in W is
 n - n' + l (the printed n' - n + l does not reproduce G), and the harmonics
-carry the (-1)^m phase stated in ``specfun``.
+carry the (-1)^m phase stated in ``specfun``.  The same power reading holds in
+eq. (m2m) (W_{n,n',...} takes i^{n'-n+l}); in eq. (l2l) the second row of the
+second 3j symbol reads (-m, m', m-m'), matching the order m - m' of I_l (the
+printed (m, m', -m-m') pairs it with I_l^{-m-m'}).
 """
 from __future__ import annotations
 
@@ -90,9 +105,12 @@ def grad_conj_regular(v, k, order):
     return g
 
 
-def p2m(vertices, triangles, k, order, q: int = 8):
-    """V0 [p, n]: P2M moments of each element for unit density (eq. (p2m))."""
+def p2m(vertices, triangles, k, order, q: int = 8, center=None):
+    """V0 [p, n]: P2M moments of each element for unit density (eq. (p2m)), about
+    ``center`` (the cell centre, the origin, by default)."""
     v = np.asarray(vertices, dtype=np.float64)
+    if center is not None:
+        v = v - np.asarray(center, dtype=np.float64)[None, :]
     t = np.asarray(triangles)
     a, b, c = v[t[:, 0]], v[t[:, 1]], v[t[:, 2]]
     nrm = np.cross(b - a, c - a)
@@ -107,9 +125,12 @@ def p2m(vertices, triangles, k, order, q: int = 8):
     return out                                               # [p, n]
 
 
-def l2p(vertices, triangles, k, order, alpha):
-    """U0 [n, p]: local-to-collocation-point operator incl. the Burton-Miller term (eq. (l2p))."""
+def l2p(vertices, triangles, k, order, alpha, center=None):
+    """U0 [n, p]: local-to-collocation-point operator incl. the Burton-Miller term (eq. (l2p)),
+    local expansion about ``center`` (the origin by default)."""
     v = np.asarray(vertices, dtype=np.float64)
+    if center is not None:
+        v = v - np.asarray(center, dtype=np.float64)[None, :]
     t = np.asarray(triangles)
     a, b, c = v[t[:, 0]], v[t[:, 1]], v[t[:, 2]]
     nrm = np.cross(b - a, c - a)
@@ -156,3 +177,74 @@ def m2l(offsets_xyz, k, order):
     T = m2l_table(order)
     p = n_coeffs(order)
     return np.asarray((T @ O.T).T).reshape(D.shape[0], p, p)
+
+
+@lru_cache(maxsize=None)
+def m2m_table(order: int, order_src: int | None = None):
+    """Sparse map T [(p_t*p_s), (n_t+n_s+1)^2] with M2M(b).ravel() = T @ I(b), eq. (m2m).
+    Rows (n, m) up to ``order``, columns (n', m') up to ``order_src`` (default: ``order``)."""
+    ns = order if order_src is None else order_src
+    rows, cols, vals = [], [], []
+    ps = n_coeffs(ns)
+    for n in range(order + 1):
+        for m in range(-n, n + 1):
+            for n2 in range(ns + 1):
+                for m2 in range(-n2, n2 + 1):
+                    mu = m2 - m  # order of I_l
+                    for l in range(max(abs(mu), abs(n - n2)), n + n2 + 1):
+                        if (n + n2 - l) % 2:
+                            continue
+                        # W_{n,n',m,-m',l}: (2l+1) i^{n'-n+l} (n' n l; 0 0 0)(n' n l; -m' m m'-m)
+                        w = (2 * l + 1) * specfun.wigner3j(n2, n, l, 0, 0, 0) * specfun.wigner3j(n2, n, l, -m2, m, mu)
+                        if w == 0.0:
+                            continue
+                        coef = (2 * n2 + 1) * (-1.0) ** m2 * w * (1j ** ((n2 - n + l) % 4))
+                        rows.append(specfun.idx(n, m) * ps + specfun.idx(n2, m2))
+                        cols.append(specfun.idx(l, mu))
+                        vals.append(coef)
+    return sp.csr_matrix((np.array(vals, dtype=np.complex128), (rows, cols)),
+                         shape=(n_coeffs(order) * ps, (order + ns + 1) ** 2))
+
+
+def m2m(shifts, k, order, order_src=None):
+    """M2M [len, p_t, p_s] for b = y_c - y_c' (old centre minus new centre), eq. (m2m)."""
+    ns = order if order_src is None else order_src
+    b = np.atleast_2d(np.asarray(shifts, dtype=np.float64))
+    Ib = regular(b, k, order + ns)
+    T = m2m_table(order, order_src)
+    return np.asarray((T @ Ib.T).T).reshape(b.shape[0], n_coeffs(order), n_coeffs(ns))
+
+
+@lru_cache(maxsize=None)
+def l2l_table(order: int, order_src: int | None = None):
+    """Sparse map T [(p_t*p_s), (n_t+n_s+1)^2] with L2L(b).ravel() = T @ I(b), eq. (l2l)."""
+    ns = order if order_src is None else order_src
+    rows, cols, vals = [], [], []
+    ps = n_coeffs(ns)
+    for n in range(order + 1):
+        for m in range(-n, n + 1):
+            for n2 in range(ns + 1):
+                for m2 in range(-n2, n2 + 1):
+                    mu = m - m2  # order of I_l
+                    for l in range(max(abs(mu), abs(n - n2)), n + n2 + 1):
+                        if (n + n2 - l) % 2:
+                            continue
+                        # W_{n',n,m',-m,l}: (2l+1) i^{n-n'+l} (n n' l; 0 0 0)(n n' l; -m m' m-m')
+                        w = (2 * l + 1) * specfun.wigner3j(n, n2, l, 0, 0, 0) * specfun.wigner3j(n, n2, l, -m, m2, mu)
+                        if w == 0.0:
+                            continue
+                        coef = (2 * n2 + 1) * (-1.0) ** m * w * (1j ** ((n - n2 + l) % 4))
+                        rows.append(specfun.idx(n, m) * ps + specfun.idx(n2, m2))
+                        cols.append(specfun.idx(l, mu))
+                        vals.append(coef)
+    return sp.csr_matrix((np.array(vals, dtype=np.complex128), (rows, cols)),
+                         shape=(n_coeffs(order) * ps, (order + ns + 1) ** 2))
+
+
+def l2l(shifts, k, order, order_src=None):
+    """L2L [len, p_t, p_s] for b = x_c' - x_c (new centre minus old centre), eq. (l2l)."""
+    ns = order if order_src is None else order_src
+    b = np.atleast_2d(np.asarray(shifts, dtype=np.float64))
+    Ib = regular(b, k, order + ns)
+    T = l2l_table(order, order_src)
+    return np.asarray((T @ Ib.T).T).reshape(b.shape[0], n_coeffs(order), n_coeffs(ns))
