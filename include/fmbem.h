@@ -114,6 +114,21 @@ typedef struct {
    * are ignored; the half-space is not supported (FMBEM_ERR_UNSUPPORTED).  The paper's
    * comparison method; the plan stores B n^2 complex values per precision.  0 => FMPBEM. */
   int32_t exact;
+  /* near_levels = L >= 1: the multilevel near field of FMPBEM2 (Sec. 3.3).  The lattice box of
+   * the unit cell (edge = pitch per axis, centred on the cell centre) is halved L times along
+   * every axis (uniform depth; an element belongs to the box of its centroid), and the near
+   * blocks S_d are applied as a multilevel FMM over the lattice's boxes: boxes whose grid
+   * offset has Chebyshev norm >= 2 interact through M2L on the coarsest such level (moments
+   * gathered by P2M about the leaf centres and M2M, locals spread by L2L and L2P, Appendix A
+   * eqs. (p2m), (m2m), (m2l), (l2l), (l2p)), leaves that stay near through exact P2P blocks.
+   * Storage O(n log n) instead of 9 (or 27) n x n blocks.  Requires near_radius 1 on every
+   * axis, every centroid inside the cell's lattice box (else FMBEM_ERR_UNSUPPORTED), no
+   * half-space and no exact mode (FMBEM_ERR_UNSUPPORTED); at most 8 levels.  0 => the dense
+   * near blocks (FMPBEM). */
+  int32_t near_levels;
+  /* truncation number n_t,near of the multilevel near field, 1..7 ((n_t,near + 1)^2 <= 64
+   * expansion coefficients per box); 0 => min(order, 7).  Ignored when near_levels = 0. */
+  int32_t near_order;
 } fmbem_plan_desc;
 
 #define FMBEM_TILE_SHAPES 10

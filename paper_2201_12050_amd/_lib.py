@@ -38,7 +38,8 @@ class PlanDesc(ct.Structure):
                 ("alpha_im", ct.c_double), ("near_radius", ct.c_int32 * 3), ("fft_shape", ct.c_int32 * 3),
                 ("precisions", ct.c_uint32), ("dft_schedule", ct.c_int32), ("halfspace", ct.c_int32),
                 ("plane_z", ct.c_double), ("reflection_re", ct.c_double), ("reflection_im", ct.c_double),
-                ("tile_shape", ct.c_int32 * 3), ("exact", ct.c_int32)]
+                ("tile_shape", ct.c_int32 * 3), ("exact", ct.c_int32),
+                ("near_levels", ct.c_int32), ("near_order", ct.c_int32)]
 
 
 DFT_SCHEDULE = {"auto": 0, "axes": 1, "fused": 2, "gemm": 3, "mfma": 4, "fft": 5}
@@ -326,12 +327,15 @@ class Plan:
 
     def __init__(self, vertices, triangles, grid, pitch, k, order, formulation="bm", alpha=None,
                  near_radius=(1, 1, 1), fft_shape=(0, 0, 0), precisions=("fp64", "fp32"), stream=None,
-                 dft_schedule="auto", halfspace=None, tile_shape=(0, 0, 0), exact=False):
+                 dft_schedule="auto", halfspace=None, tile_shape=(0, 0, 0), exact=False, near_levels=0,
+                 near_order=0):
         """halfspace: None (full space) or (plane_z, R_p): the half-space Green's function with the
         plane z = plane_z and reflection coefficient R_p.  tile_shape: forced tile shapes of the
         near-field, L2T and M2L GEMM launches (0 = autotuned, v = shape v - 1).  exact: the exact
         periodic BEM operator (every block integrated, n x n blocks per bin) instead of the fast
-        multipole one; order is then ignored."""
+        multipole one; order is then ignored.  near_levels >= 1: the multilevel near field of
+        FMPBEM2 with that many subdivisions of the cell box and truncation near_order (0:
+        min(order, 7))."""
         lib = load()
         self._lib = lib
         v = np.ascontiguousarray(vertices, dtype=np.float64)
@@ -356,6 +360,8 @@ class Plan:
         for a in range(3):
             d.tile_shape[a] = int(tile_shape[a])
         d.exact = 1 if exact else 0
+        d.near_levels = int(near_levels)
+        d.near_order = int(near_order)
         if halfspace is not None:
             zg, rp = halfspace
             d.halfspace = 1

@@ -56,6 +56,44 @@ struct QuadTab {
   double w[28];
 };
 
+// Multilevel near field (FMPBEM2, Sec. 3.3): launch tables of the block-sparse products.
+// Output rows [out_row, out_row + rows) of a stage's output buffer (rows <= 64) receive the sum
+// of the target's tasks; a task multiplies the operator A (rows x ks, row-major with row stride
+// lda, at ops + a_off) into source rows [src_row, src_row + ks) of buffer sel & 3, taken at the
+// column of cell c - d for output cell c (d = the cell shift sel >> 2, encoded as
+// (d0 + 1) + 3 (d1 + 1) + 9 (d2 + 1); zero outside the lattice).  Buffers ([rows][R C]): 0 the
+// input in tree order, 1 moments, 2 locals, 3 the output in tree order.
+struct MlTarget {
+  int out_row, rows, t0, t1;
+};
+struct MlTask {
+  long long a_off;
+  int lda, ks, src_row, sel;
+};
+struct MlStage {
+  const MlTarget* tg;  // device, n_tg targets
+  const MlTask* tk;    // device (all tasks of the plan)
+  int n_tg;
+  int out, accum;      // output buffer; 1: add to it
+};
+struct MlData {
+  int levels = 0, order = 0, p = 0;
+  int rows = 0;                      // expansion rows of levels 1..L (p per box)
+  int* pos = nullptr;                // device [n]: tree position of every element
+  int* perm = nullptr;               // device [n]: element at every tree position
+  void* ops[2] = {nullptr, nullptr}; // operator pool FP64 / FP32 (P2M, L2P, M2M, L2L, M2L, P2P)
+  size_t ops_elems = 0;
+  std::vector<MlStage> stages;       // P2M, M2M per level, M2L, L2L per level, L2P + P2P
+  int boxes = 0, leaves = 0;
+  long long m2l_pairs = 0, p2p_pairs = 0, p2p_entries = 0;
+};
+// exact entries of one P2P block: rows = tree positions [te0, te0 + nt), columns [se0, se0 + ns)
+// of S_d (shift index sd as in MlTask), row-major at ops + off
+struct P2pBlock {
+  long long off;
+  int te0, nt, se0, ns, sd;
+};
+
 struct Plan {
   int device = 0;
   int n = 0;                 // triangles (DOFs) per cell
@@ -105,6 +143,9 @@ struct Plan {
   // exact periodic BEM (comparison method): Lambda holds the n x n exact blocks per bin, V0 = U0 = I,
   // no near blocks, p = n
   bool exact = false;
+  // multilevel near field (FMPBEM2): set => no dense near blocks (n_near = 0), the near offsets
+  // of radius 1 are applied by the multilevel FMM after the far field
+  std::shared_ptr<MlData> ml;
   int flip_p() const { return paired ? p : 0; }
   // Lambda of bin -w is D Lambda(w) D, D = diag((-1)^n) (reciprocity of the translations), so only
   // canonical bins (linear index <= that of the partner bin -w) are stored.
@@ -144,6 +185,25 @@ hipEvent_t prof_begin(const Plan& P, int stage, hipStream_t s);
 void prof_end(const Plan& P, int stage, hipEvent_t start, hipStream_t s);
 
 size_t matvec_workspace_bytes_per_rhs(const Plan& P, int precision);
+
+// multilevel near field (multilevel.hip): tree and operators (plan build), workspace, application
+// (y (+)= the near field of x; y64: complex128 output of an FP32 application)
+bool ml_cell_fits(const std::vector<double>& geo, int n, const double pitch[3], int L);
+hipError_t ml_build(Plan& P, const std::vector<double>& geo, hipStream_t s);
+size_t ml_workspace_bytes_per_rhs(const Plan& P, int precision);
+template <typename T>
+hipError_t ml_apply(const Plan& P, int R, const void* x, void* y, void* y64, void* ws, bool accum, hipStream_t s);
+// plan.hip helpers used by the multilevel build
+hipError_t plan_alloc(Plan& P, void** ptr, size_t bytes);
+void gauss_legendre_host(int q, std::vector<double>& x, std::vector<double>& w);
+void theta_table(int L, const std::vector<double>& x, std::vector<double>& tab);
+hipError_t cast_launch(const double2* a, float2* b, size_t n, hipStream_t s);
+// leaf P2M (columns of ops + oV, row stride n) and L2P (rows of ops + oU, row stride p) about the
+// leaf centre of every element (cen, host [n][3]) with the column / row scaling isig (host),
+// and the exact entries of the P2P blocks
+hipError_t ml_assemble_launch(const Plan& P, int nt, const std::vector<double>& cen, const std::vector<double>& isig,
+                              const std::vector<P2pBlock>& blocks, long long entries, double2* ops, long long oV,
+                              long long oU, hipStream_t s);
 
 // stream-ordered operator application (all arguments validated by the caller);
 // y64 (FP32 only, optional): write the result as complex128 there instead of y

@@ -8,7 +8,9 @@
 //   [4] inverse DFT  cropped to the first M_a outputs per axis
 //   [5] L2T          y = sum_d part_d + U0 l_c              (GEMM reading the padded grid, fixed-order sum)
 //   [1] only without far-field offsets: y = sum_d part_d
-// Workspace: [padded grid B x R x p][near partials n_near x R x C x n], 256-byte aligned.
+//   [1] multilevel near field (FMPBEM2 plans, no dense near blocks): y += S~ x after [5]
+// Workspace: [padded grid B x R x p][second grid][near partials n_near x R x C x n][multilevel
+// buffers], 256-byte aligned.
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -22,7 +24,8 @@ static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 static size_t direct_ws_per_rhs(const Plan& P, int precision) {
   const size_t el = precision == FMBEM_FP64 ? 16 : 8;
-  return 2 * align256((size_t)P.B * P.p * el) + align256((size_t)P.n_near * P.C * P.n * el);
+  return 2 * align256((size_t)P.B * P.p * el) + align256((size_t)P.n_near * P.C * P.n * el) +
+         ml_workspace_bytes_per_rhs(P, precision);
 }
 
 // workspace per RHS: the plan's own; with an image sub-plan (half-space periodic along z) also
@@ -234,6 +237,21 @@ template <typename T>
 static char* near_partials(const Plan& P, int R, void* ws) {
   return reinterpret_cast<char*>(ws) + 2 * align256((size_t)P.B * R * P.p * sizeof(cplx<T>));
 }
+// buffers of the multilevel near field, after the near partials
+template <typename T>
+static char* ml_buffers(const Plan& P, int R, void* ws) {
+  return near_partials<T>(P, R, ws) + align256((size_t)P.n_near * R * P.C * P.n * sizeof(cplx<T>));
+}
+// [1] the multilevel near field of an FMPBEM2 plan: y (+)= S~ x
+template <typename T>
+static hipError_t ml_stage(const Plan& P, int R, const void* x, void* y, void* y64, void* ws, bool accum,
+                           hipStream_t s) {
+  const int prec = sizeof(T) == 8 ? 0 : 1;
+  hipEvent_t ev = prof_begin(P, 1 + 6 * prec, s);
+  const hipError_t e = ml_apply<T>(P, R, x, y, y64, ml_buffers<T>(P, R, ws), accum, s);
+  prof_end(P, 1 + 6 * prec, ev, s);
+  return e;
+}
 
 // lhat_b = Lambda_b mhat_b for every bin: a GEMV in place for few right-hand sides, a
 // batched MFMA GEMM into the second grid from kM2lGemmRhs on; returns the buffer of lhat
@@ -319,10 +337,12 @@ static hipError_t matvec_overlap(const Plan& P, int R, const void* x, void* y, v
     std::vector<NearJob> jobs;
     near_s2m_jobs<T>(P, R, x, ws, jobs);
     jobs.pop_back();  // the S2M job ran on the second stream
-    const int shape = plan_shape<T>(P, 0, jobs, s, tune);
-    ev = prof_begin(P, 0 + 6 * prec, s);
-    if ((e = near_launch<T>(jobs, s, shape, 0))) return e;
-    prof_end(P, 0 + 6 * prec, ev, s);
+    if (!jobs.empty()) {
+      const int shape = plan_shape<T>(P, 0, jobs, s, tune);
+      ev = prof_begin(P, 0 + 6 * prec, s);
+      if ((e = near_launch<T>(jobs, s, shape, 0))) return e;
+      prof_end(P, 0 + 6 * prec, ev, s);
+    }
   }
   if ((e = hipStreamWaitEvent(s, P.ev_join, 0))) return e;
   // [5] L2T with the fixed-order sum of the near partials
@@ -331,6 +351,7 @@ static hipError_t matvec_overlap(const Plan& P, int R, const void* x, void* y, v
   ev = prof_begin(P, 5 + 6 * prec, s);
   e = near_launch<T>(jobs, s, shape, 1);
   prof_end(P, 5 + 6 * prec, ev, s);
+  if (e == hipSuccess && P.ml) e = ml_stage<T>(P, R, x, y, y64, ws, true, s);
   return e;
 }
 
@@ -349,12 +370,15 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
   {
     std::vector<NearJob> jobs;
     near_s2m_jobs<T>(P, R, x, ws, jobs);
-    const int shape = plan_shape<T>(P, 0, jobs, s, tune);
-    ev = prof_begin(P, 0 + 6 * prec, s);
-    hipError_t e = near_launch<T>(jobs, s, shape, 0);
-    if (e != hipSuccess) return e;
+    if (!jobs.empty()) {
+      const int shape = plan_shape<T>(P, 0, jobs, s, tune);
+      ev = prof_begin(P, 0 + 6 * prec, s);
+      hipError_t e = near_launch<T>(jobs, s, shape, 0);
+      if (e != hipSuccess) return e;
+    }
   }
   prof_end(P, 0 + 6 * prec, ev, s);
+  if (P.n_far == 0 && P.ml) return ml_stage<T>(P, R, x, y, y64, ws, false, s);
   if (P.n_far == 0) {
     // [1] sum of the near partials
     ev = prof_begin(P, 1 + 6 * prec, s);
@@ -385,6 +409,7 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
     e = near_launch<T>(jobs, s, shape, 1);
   }
   prof_end(P, 5 + 6 * prec, ev, s);
+  if (e == hipSuccess && P.ml) e = ml_stage<T>(P, R, x, y, y64, ws, true, s);
   return e;
 }
 
@@ -403,14 +428,19 @@ static hipError_t matvec_group_t(const std::vector<GroupApply>& g, hipStream_t s
   std::vector<int> dsched;
   for (const GroupApply& a : g) dsched.push_back(dft_schedule<T>(*a.P, a.R, a.ws, s, tune));
   for (const GroupApply& a : g) near_s2m_jobs<T>(*a.P, a.R, a.x, a.ws, jobs);
-  int shape = tune ? tuned_shape<T>(0, jobs, s) : cached_shape<T>(0, jobs);
-  hipError_t e = near_launch<T>(jobs, s, shape, 0);
-  if (e != hipSuccess) return e;
+  int shape = -1;
+  hipError_t e = hipSuccess;
+  if (!jobs.empty()) {
+    shape = tune ? tuned_shape<T>(0, jobs, s) : cached_shape<T>(0, jobs);
+    if ((e = near_launch<T>(jobs, s, shape, 0)) != hipSuccess) return e;
+  }
   std::vector<size_t> far;
   for (size_t q = 0; q < g.size(); ++q) {
     const GroupApply& a = g[q];
     const Plan& P = *a.P;
-    if (P.n_far == 0) {
+    if (P.n_far == 0 && P.ml) {
+      if ((e = ml_stage<T>(P, a.R, a.x, a.y, a.y64, a.ws, false, s)) != hipSuccess) return e;
+    } else if (P.n_far == 0) {
       e = near_reduce_launch<T>(near_partials<T>(P, a.R, a.ws), P.n_near, (size_t)a.R * P.C * P.n, a.y, a.y64, s);
       if (e != hipSuccess) return e;
     } else {
@@ -482,7 +512,12 @@ static hipError_t matvec_group_t(const std::vector<GroupApply>& g, hipStream_t s
   std::vector<NearJob> l2t;
   for (size_t q : far) l2t.push_back(l2t_job<T>(*g[q].P, g[q].R, g[q].ws, lhat[q], g[q].y, g[q].y64));
   shape = tune ? tuned_shape<T>(1, l2t, s) : cached_shape<T>(1, l2t);
-  return near_launch<T>(l2t, s, shape, 1);
+  if ((e = near_launch<T>(l2t, s, shape, 1)) != hipSuccess) return e;
+  for (size_t q : far) {
+    const GroupApply& a = g[q];
+    if (a.P->ml && (e = ml_stage<T>(*a.P, a.R, a.x, a.y, a.y64, a.ws, true, s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // xr[r][i0, i1, M2 - 1 - i2][:] = x[r][i0, i1, i2][:] (cells reversed along z)

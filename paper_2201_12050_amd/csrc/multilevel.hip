@@ -1,0 +1,608 @@
+// Multilevel near field of FMPBEM2 (Sec. 3.3): every near block S_d applied as a
+// multilevel FMM over the boxes of the lattice instead of as a dense n x n block.
+//
+// Subdivision: the lattice box of the unit cell (edge = pitch per axis, centred on the cell
+// centre) is halved L times along every axis; an element belongs to the box holding its
+// centroid.  The boxes of one level of the whole lattice lie on one regular grid (edge
+// h_l = pitch / 2^l), and two boxes are well separated when their grid offset has Chebyshev
+// norm >= 2 (eq. (admissibility) with r the box edge; on level 0, the cells, that is the far
+// set of the single-level FMPBEM).  Descending from the pairs (cell i, cell i - d) of the
+// near offsets d, a pair of boxes is translated by M2L on the first level on which it is well
+// separated; pairs of leaves that are near on every level take the exact entries of S_d
+// (P2P).  Moments: P2M about the leaf centres (eq. (p2m)), M2M up to level 1 (eq. (m2m));
+// locals: M2L (eq. (m2l)), L2L down to the leaves (eq. (l2l)), L2P (eq. (l2p)); truncation
+// n_t,near.  Every cell has the same tree, so each interaction list is one list of (target
+// box, source box, cell offset) entries applied to every cell of the lattice at once.
+//
+// Translation matrices (host, FP64): with G(a,alpha; b,beta; c,gamma) = (a b c;0 0 0)
+// (a b c;alpha beta gamma), evaluated as the Gaunt integral 1/2 int Yt_a^alpha Yt_b^beta
+// Yt_c^gamma dx,
+//   M2M (b = y_c - y_c'):  T[(n,m),(n',m')] = (2n'+1)(-1)^{m'} sum_l (2l+1) i^{n'-n+l}
+//                                             G(n',-m'; n,m; l,m'-m) I_l^{m'-m}(b)
+//   L2L (b = x_c' - x_c):  T[(n,m),(n',m')] = (2n'+1)(-1)^m sum_l (2l+1) i^{n-n'+l}
+//                                             G(n,-m; n',m'; l,m-m') I_l^{m-m'}(b)
+//   M2L: the cell-level table of plan.hip with O_l^mu at the box-centre offset.
+// Each level carries the diagonal scaling s_l^n (s_l = k times the box half-diagonal,
+// clamped to [1e-3, 1]): moments / s_l^n, locals * s_l^n, so that FP32 stays in range.
+//
+// Application (all cells and right-hand sides at once): the input is gathered into tree
+// order with the columns (RHS r, cell c) innermost, then every stage is one launch of the
+// block-sparse product kernel -- P2M, M2M per level, M2L of all levels, L2L per level, L2P
+// together with the P2P blocks -- and the result is scattered back and added to y.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <functional>
+#include <map>
+#include <numeric>
+#include <tuple>
+#include <vector>
+
+#include "common.hpp"
+#include "specfun.hpp"
+
+namespace fmbem {
+
+constexpr int kMlRows = 64;  // rows of one output block
+constexpr int kMlKc = 16;    // contraction chunk staged in LDS
+constexpr int kMlZeroShift = 13;
+
+// ---------------------------------------------------------------------------
+// device: block-sparse products
+// ---------------------------------------------------------------------------
+struct MlBufs {
+  void* b[4];  // 0: input in tree order, 1: moments, 2: locals, 3: output in tree order ([row][cols])
+};
+
+// out[out_row + i][col] (+)= sum over the target's tasks of A[i][k] src[src_row + k][col'] with
+// col' the column of cell c - d (zero outside the lattice); TC columns per workgroup
+template <typename T, int TC>
+__global__ __launch_bounds__(256) void ml_kernel(const MlTarget* __restrict__ tg, const MlTask* __restrict__ tk,
+                                                 const cplx<T>* __restrict__ ops, MlBufs B, int out_id, int accum,
+                                                 int cols, int C, int M0, int M1, int M2) {
+  constexpr int RG = 256 / TC, RPT = kMlRows / RG;
+  __shared__ cplx<T> As[kMlKc][kMlRows + 1];
+  const MlTarget t = tg[blockIdx.x];
+  const int cl = threadIdx.x % TC, rg = threadIdx.x / TC;
+  const int col = blockIdx.y * TC + cl;
+  const bool cok = col < cols;
+  const int c = cok ? col % C : 0;
+  const int c0 = c % M0, c1 = (c / M0) % M1, c2 = c / (M0 * M1);
+  const cplx<T> zero = mk<T>(0, 0);
+  cplx<T> acc[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) acc[i] = zero;
+  for (int q = t.t0; q < t.t1; ++q) {
+    const MlTask w = tk[q];
+    const cplx<T>* __restrict__ src = reinterpret_cast<const cplx<T>*>(B.b[w.sel & 3]);
+    const int sh = w.sel >> 2;
+    const int d0 = sh % 3 - 1, d1 = (sh / 3) % 3 - 1, d2 = sh / 9 - 1;
+    const bool ok = cok && (unsigned)(c0 - d0) < (unsigned)M0 && (unsigned)(c1 - d1) < (unsigned)M1 &&
+                    (unsigned)(c2 - d2) < (unsigned)M2;
+    const int scol = col - (d0 + M0 * (d1 + M1 * d2));
+    const cplx<T>* __restrict__ A = ops + w.a_off;
+    for (int k0 = 0; k0 < w.ks; k0 += kMlKc) {
+      cplx<T> xv[kMlKc];
+#pragma unroll
+      for (int kk = 0; kk < kMlKc; ++kk)
+        xv[kk] = (ok && k0 + kk < w.ks) ? src[(size_t)(w.src_row + k0 + kk) * cols + scol] : zero;
+      __syncthreads();
+      for (int e = threadIdx.x; e < kMlRows * kMlKc; e += 256) {
+        const int row = e / kMlKc, kk = e - row * kMlKc;
+        As[kk][row] = (row < t.rows && k0 + kk < w.ks) ? A[(size_t)row * w.lda + k0 + kk] : zero;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < kMlKc; ++kk)
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) cfma<T>(acc[i], As[kk][rg + i * RG], xv[kk]);
+    }
+  }
+  if (!cok) return;
+  cplx<T>* __restrict__ out = reinterpret_cast<cplx<T>*>(B.b[out_id]);
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int row = rg + i * RG;
+    if (row < t.rows) {
+      cplx<T>* o = out + (size_t)(t.out_row + row) * cols + col;
+      *o = accum ? cadd<T>(*o, acc[i]) : acc[i];
+    }
+  }
+}
+
+// xt[pos[e]][col] = x[col][e]  (x: [R][C][n], col = r C + c)
+template <typename T>
+__global__ void ml_in_kernel(const cplx<T>* __restrict__ x, const int* __restrict__ pos, int n, size_t total,
+                             int cols, cplx<T>* __restrict__ xt) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const int col = (int)(i / n);
+    const int e = (int)(i - (size_t)col * n);
+    xt[(size_t)pos[e] * cols + col] = x[i];
+  }
+}
+
+// y[col][e] (+)= yt[pos[e]][col] in the output type U (the application's precision or FP64)
+template <typename T, typename U>
+__global__ void ml_out_kernel(const cplx<T>* __restrict__ yt, const int* __restrict__ pos, int n, size_t total,
+                              int cols, int accum, cplx<U>* __restrict__ y) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const int col = (int)(i / n);
+    const int e = (int)(i - (size_t)col * n);
+    const cplx<T> v = yt[(size_t)pos[e] * cols + col];
+    const cplx<U> w = mk<U>((U)v.x, (U)v.y);
+    y[i] = accum ? cadd<U>(y[i], w) : w;
+  }
+}
+
+static size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+
+size_t ml_workspace_bytes_per_rhs(const Plan& P, int precision) {
+  if (!P.ml) return 0;
+  const size_t el = precision == FMBEM_FP32 ? sizeof(float2) : sizeof(double2);
+  return 2 * al256((size_t)P.n * P.C * el) + 2 * al256((size_t)P.ml->rows * P.C * el);
+}
+
+template <typename T, int TC>
+static void ml_stage_launch(const MlStage& st, const cplx<T>* ops, const MlBufs& B, int cols, const Plan& P,
+                            hipStream_t s) {
+  hipLaunchKernelGGL((ml_kernel<T, TC>), dim3(st.n_tg, (cols + TC - 1) / TC), dim3(256), 0, s, st.tg, st.tk, ops, B,
+                     st.out, st.accum, cols, P.C, P.grid[0], P.grid[1], P.grid[2]);
+}
+
+template <typename T>
+hipError_t ml_apply(const Plan& P, int R, const void* x, void* y, void* y64, void* ws, bool accum, hipStream_t s) {
+  const MlData& M = *P.ml;
+  const int prec = sizeof(T) == 8 ? 0 : 1;
+  const int cols = R * P.C;
+  const size_t el = sizeof(cplx<T>);
+  char* w = reinterpret_cast<char*>(ws);
+  MlBufs B;
+  B.b[0] = w;
+  w += al256((size_t)P.n * cols * el);
+  B.b[1] = w;
+  w += al256((size_t)M.rows * cols * el);
+  B.b[2] = w;
+  w += al256((size_t)M.rows * cols * el);
+  B.b[3] = w;
+  const size_t total = (size_t)P.n * cols;
+  const unsigned g = (unsigned)std::min<size_t>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL(ml_in_kernel<T>, dim3(g), dim3(256), 0, s, reinterpret_cast<const cplx<T>*>(x), M.pos, P.n,
+                     total, cols, reinterpret_cast<cplx<T>*>(B.b[0]));
+  const cplx<T>* ops = reinterpret_cast<const cplx<T>*>(M.ops[prec]);
+  for (const MlStage& st : M.stages) {
+    if (st.n_tg == 0) continue;
+    if (cols >= 64) ml_stage_launch<T, 64>(st, ops, B, cols, P, s);
+    else if (cols >= 32) ml_stage_launch<T, 32>(st, ops, B, cols, P, s);
+    else ml_stage_launch<T, 16>(st, ops, B, cols, P, s);
+  }
+  if (y64)
+    hipLaunchKernelGGL((ml_out_kernel<T, double>), dim3(g), dim3(256), 0, s,
+                       reinterpret_cast<const cplx<T>*>(B.b[3]), M.pos, P.n, total, cols, accum ? 1 : 0,
+                       reinterpret_cast<double2*>(y64));
+  else
+    hipLaunchKernelGGL((ml_out_kernel<T, T>), dim3(g), dim3(256), 0, s, reinterpret_cast<const cplx<T>*>(B.b[3]),
+                       M.pos, P.n, total, cols, accum ? 1 : 0, reinterpret_cast<cplx<T>*>(y));
+  return hipGetLastError();
+}
+
+template hipError_t ml_apply<double>(const Plan&, int, const void*, void*, void*, void*, bool, hipStream_t);
+template hipError_t ml_apply<float>(const Plan&, int, const void*, void*, void*, void*, bool, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// host: translation matrices
+// ---------------------------------------------------------------------------
+// I_l^mu (regular) or O_l^mu (singular) at v for l <= L: out[l l + l + mu]
+static void harmonics_at(const double* v, double k, int L, bool singular, std::vector<double2>& out) {
+  out.assign((size_t)(L + 1) * (L + 1), make_double2(0, 0));
+  const double rho2 = v[0] * v[0] + v[1] * v[1];
+  const double r = std::sqrt(rho2 + v[2] * v[2]);
+  const double rho = std::sqrt(rho2);
+  const double ct = v[2] / r, st = rho / r;
+  const double cp = rho > 0 ? v[0] / rho : 1.0, sp = rho > 0 ? v[1] / rho : 0.0;
+  std::vector<double> jl(L + 2), yl(L + 2), Nl(L + 2);
+  sph_j_all(L, k * r, jl.data());
+  if (singular) sph_y_all(L, k * r, yl.data());
+  for (int mu = 0; mu <= L; ++mu) {
+    legendre_N_col(mu, L, ct, st, Nl.data());
+    const double er = std::cos(mu * std::atan2(sp, cp)), ei = std::sin(mu * std::atan2(sp, cp));
+    const double sg = (mu & 1) ? -1.0 : 1.0;
+    for (int l = mu; l <= L; ++l) {
+      const double2 h = make_double2(jl[l], singular ? yl[l] : 0.0);
+      // Y_l^mu = (-1)^mu N e^{i mu phi}; Y_l^{-mu} = N e^{-i mu phi}
+      out[l * l + l + mu] = cmul<double>(h, make_double2(sg * Nl[l] * er, sg * Nl[l] * ei));
+      if (mu > 0) out[l * l + l - mu] = cmul<double>(h, make_double2(Nl[l] * er, -Nl[l] * ei));
+    }
+  }
+}
+
+// sparse table of one translation kind: entry (row, col) = sum coef * H[hidx]
+struct TransTable {
+  std::vector<int> ptr, hidx;
+  std::vector<double2> coef;
+};
+
+// kind 0: M2M, 1: L2L (regular harmonics); 2: M2L (singular)
+static void trans_table(int nt, int kind, TransTable& T) {
+  const int p = (nt + 1) * (nt + 1);
+  const int L = 2 * nt;
+  std::vector<double> gx, gw, tab;
+  gauss_legendre_host(2 * nt + 2, gx, gw);
+  theta_table(L, gx, tab);
+  const int q = (int)gx.size(), W = 2 * L + 1;
+  auto yt = [&](int l, int mu) { return &tab[((size_t)l * W + (L + mu)) * q]; };
+  auto gaunt = [&](int a, int al, int b, int be, int c, int ga) {
+    const double *x = yt(a, al), *y = yt(b, be), *z = yt(c, ga);
+    double g = 0.0;
+    for (int i = 0; i < q; ++i) g += gw[i] * x[i] * y[i] * z[i];
+    return 0.5 * g;
+  };
+  static const double ire[4] = {1, 0, -1, 0}, iim[4] = {0, 1, 0, -1};
+  T.ptr.assign((size_t)p * p + 1, 0);
+  T.hidx.clear();
+  T.coef.clear();
+  for (int n = 0; n <= nt; ++n)
+    for (int m = -n; m <= n; ++m)
+      for (int n2 = 0; n2 <= nt; ++n2)
+        for (int m2 = -n2; m2 <= n2; ++m2) {
+          const int e = (n * n + n + m) * p + (n2 * n2 + n2 + m2);
+          // order of the harmonic and the sign / power conventions of each kind
+          const int mu = kind == 0 ? m2 - m : (kind == 1 ? m - m2 : m + m2);
+          int lo = std::max(std::abs(mu), std::abs(n - n2));
+          if ((n + n2 - lo) & 1) ++lo;
+          for (int l = lo; l <= n + n2; l += 2) {
+            double g, sgn;
+            int pw;
+            if (kind == 0) {
+              g = gaunt(n2, -m2, n, m, l, mu);
+              sgn = (m2 & 1) ? -1.0 : 1.0;
+              pw = n2 - n + l;
+            } else if (kind == 1) {
+              g = gaunt(n, -m, n2, m2, l, mu);
+              sgn = (m & 1) ? -1.0 : 1.0;
+              pw = n - n2 + l;
+            } else {
+              g = gaunt(n, m, n2, m2, l, -mu);
+              sgn = ((m + m2) & 1) ? -1.0 : 1.0;
+              pw = n - n2 + l;
+            }
+            if (g == 0.0) continue;
+            const double f = (2.0 * n2 + 1.0) * sgn * (2.0 * l + 1.0) * g;
+            const int ip = ((pw % 4) + 4) % 4;
+            T.coef.push_back(make_double2(f * ire[ip], f * iim[ip]));
+            T.hidx.push_back(l * l + l + mu);
+          }
+          T.ptr[e + 1] = (int)T.coef.size();
+        }
+}
+
+// matrix (row-major p x p) of a table at vector v, scaled: out[i][j] = rs[n(i)] T[i][j] cs[n(j)]
+static void trans_matrix(const TransTable& T, int nt, const double* v, double k, bool singular,
+                         const std::vector<double>& rs, const std::vector<double>& cs, double2* out) {
+  const int p = (nt + 1) * (nt + 1);
+  std::vector<double2> H;
+  harmonics_at(v, k, 2 * nt, singular, H);
+  std::vector<int> nof(p);
+  for (int n = 0; n <= nt; ++n)
+    for (int m = -n; m <= n; ++m) nof[n * n + n + m] = n;
+  for (int i = 0; i < p; ++i)
+    for (int j = 0; j < p; ++j) {
+      const int e = i * p + j;
+      double2 a = make_double2(0, 0);
+      for (int t = T.ptr[e]; t < T.ptr[e + 1]; ++t) a = cadd<double>(a, cmul<double>(T.coef[t], H[T.hidx[t]]));
+      const double f = rs[nof[i]] * cs[nof[j]];
+      out[e] = make_double2(a.x * f, a.y * f);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host: tree, interaction lists, launch tables
+// ---------------------------------------------------------------------------
+static uint32_t morton(const int* c, int L) {
+  uint32_t key = 0;
+  for (int b = L - 1; b >= 0; --b)
+    for (int a = 2; a >= 0; --a) key = (key << 1) | ((c[a] >> b) & 1);
+  return key;
+}
+
+// every centroid inside the cell's lattice box and off the centre of its leaf (where the L2P
+// gradient has no spherical-coordinate form)
+bool ml_cell_fits(const std::vector<double>& geo, int n, const double pitch[3], int L) {
+  for (int e = 0; e < n; ++e) {
+    double dist2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const double x = geo[(size_t)e * 18 + 9 + a];
+      if (!(std::fabs(x) <= 0.5 * pitch[a])) return false;
+      const double h = pitch[a] / (1 << L);
+      const int c = std::min(std::max((int)std::floor((x + 0.5 * pitch[a]) / h), 0), (1 << L) - 1);
+      const double dc = x - (-0.5 * pitch[a] + (c + 0.5) * h);
+      dist2 += dc * dc;
+    }
+    if (!(dist2 > 1e-24 * (pitch[0] * pitch[0] + pitch[1] * pitch[1] + pitch[2] * pitch[2]))) return false;
+  }
+  return true;
+}
+
+hipError_t ml_build(Plan& P, const std::vector<double>& geo, hipStream_t s) {
+  MlData& M = *P.ml;
+  const int n = P.n, L = M.levels, nt = M.order, p = M.p;
+  const bool want32 = (P.precisions & (1u << FMBEM_FP32)) != 0;
+  // leaf coordinates and the tree order of the elements (Morton order of the leaves)
+  std::vector<std::array<int, 3>> leafc(n);
+  std::vector<uint32_t> key(n);
+  const int nl = 1 << L;
+  for (int e = 0; e < n; ++e) {
+    for (int a = 0; a < 3; ++a) {
+      const double h = P.pitch[a] / nl;
+      int c = (int)std::floor((geo[(size_t)e * 18 + 9 + a] + 0.5 * P.pitch[a]) / h);
+      leafc[e][a] = std::min(std::max(c, 0), nl - 1);
+    }
+    key[e] = morton(leafc[e].data(), L);
+  }
+  std::vector<int> perm(n), pos(n);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return key[a] < key[b]; });
+  for (int t = 0; t < n; ++t) pos[perm[t]] = t;
+  // boxes per level (1..L) in Morton order: coordinates, parent, children, leaf element ranges
+  struct Box {
+    int c[3];
+    int parent = -1;
+    std::vector<int> child;
+    int e0 = 0, e1 = 0;  // leaves: tree positions
+  };
+  std::vector<std::vector<Box>> lv(L + 1);
+  lv[0].resize(1);
+  for (int l = 1; l <= L; ++l) {
+    uint32_t last = 0xffffffffu;
+    for (int t = 0; t < n; ++t) {
+      const uint32_t kk = key[perm[t]] >> (3 * (L - l));
+      if (kk != last) {
+        Box b;
+        for (int a = 0; a < 3; ++a) b.c[a] = leafc[perm[t]][a] >> (L - l);
+        b.e0 = t;
+        lv[l].push_back(b);
+        last = kk;
+      }
+      lv[l].back().e1 = t + 1;
+    }
+  }
+  for (int l = 1; l <= L; ++l) {
+    // parents: boxes of level l - 1 in the same Morton order, matched by coordinates
+    std::map<std::tuple<int, int, int>, int> idx;
+    for (int b = 0; b < (int)lv[l - 1].size(); ++b)
+      idx[{lv[l - 1][b].c[0], lv[l - 1][b].c[1], lv[l - 1][b].c[2]}] = b;
+    for (int b = 0; b < (int)lv[l].size(); ++b) {
+      Box& x = lv[l][b];
+      const int pa = l == 1 ? 0 : idx.at({x.c[0] >> 1, x.c[1] >> 1, x.c[2] >> 1});
+      x.parent = pa;
+      lv[l - 1][pa].child.push_back(b);
+    }
+  }
+  std::vector<int> base(L + 2, 0);  // first expansion row of every level (levels 1..L)
+  for (int l = 1; l <= L; ++l) base[l + 1] = base[l] + (int)lv[l].size() * p;
+  M.rows = base[L + 1];
+  auto row0 = [&](int l, int b) { return base[l] + b * p; };
+  M.boxes = base[L + 1] / p;
+  M.leaves = (int)lv[L].size();
+  // interaction lists: descend from the cell pairs of the near offsets
+  struct Pair {
+    int l, a, b, sd, tr;
+  };
+  std::vector<Pair> m2l, p2p;
+  std::map<std::tuple<int, int, int, int>, int> tr_index;  // (level, grid offset) -> M2L matrix
+  std::vector<std::tuple<int, int, int, int>> tr_list;
+  std::vector<int> near;
+  int rr[3];
+  for (int a = 0; a < 3; ++a) rr[a] = P.grid[a] > 1 ? 1 : 0;
+  std::function<void(int, int, int, const int*, int)> visit = [&](int l, int a, int b, const int* d, int sd) {
+    const Box& A = lv[l][a];
+    const Box& Bx = lv[l][b];
+    int del[3], cheb = 0;
+    for (int x = 0; x < 3; ++x) {
+      del[x] = (l == 0 ? 0 : A.c[x] - Bx.c[x]) + d[x] * (1 << l);
+      cheb = std::max(cheb, std::abs(del[x]));
+    }
+    if (cheb >= 2) {
+      const auto kk = std::make_tuple(l, del[0], del[1], del[2]);
+      auto it = tr_index.find(kk);
+      int ti;
+      if (it == tr_index.end()) {
+        ti = (int)tr_list.size();
+        tr_index[kk] = ti;
+        tr_list.push_back(kk);
+      } else {
+        ti = it->second;
+      }
+      m2l.push_back(Pair{l, a, b, sd, ti});
+      return;
+    }
+    if (l == L) {
+      p2p.push_back(Pair{l, a, b, sd, -1});
+      return;
+    }
+    for (int ca : A.child)
+      for (int cb : Bx.child) visit(l + 1, ca, cb, d, sd);
+  };
+  for (int d2 = -rr[2]; d2 <= rr[2]; ++d2)
+    for (int d1 = -rr[1]; d1 <= rr[1]; ++d1)
+      for (int d0 = -rr[0]; d0 <= rr[0]; ++d0) {
+        const int d[3] = {d0, d1, d2};
+        visit(0, 0, 0, d, (d0 + 1) + 3 * (d1 + 1) + 9 * (d2 + 1));
+      }
+  M.m2l_pairs = (long long)m2l.size();
+  M.p2p_pairs = (long long)p2p.size();
+  // operator pool: [V p x n][U n x p][M2M (L-1) x 8][L2L (L-1) x 8][M2L][P2P blocks]
+  const long long pp = (long long)p * p;
+  const long long oV = 0, oU = (long long)p * n, oM = oU + (long long)n * p;
+  const long long oL = oM + (long long)std::max(L - 1, 0) * 8 * pp;
+  const long long oK = oL + (long long)std::max(L - 1, 0) * 8 * pp;
+  const long long oP = oK + (long long)tr_list.size() * pp;
+  std::vector<long long> poff(p2p.size());
+  long long pe = 0;
+  for (size_t i = 0; i < p2p.size(); ++i) {
+    const Box& A = lv[L][p2p[i].a];
+    const Box& Bx = lv[L][p2p[i].b];
+    poff[i] = pe;
+    pe += (long long)(A.e1 - A.e0) * (Bx.e1 - Bx.e0);
+  }
+  M.p2p_entries = pe;
+  M.ops_elems = (size_t)(oP + pe);
+  // level scalings s_l^n
+  std::vector<std::vector<double>> sig(L + 1, std::vector<double>(nt + 1)), isig = sig;
+  for (int l = 0; l <= L; ++l) {
+    double hd = 0.0;
+    for (int a = 0; a < 3; ++a) hd += std::pow(P.pitch[a] / (1 << l), 2);
+    const double sl = std::min(1.0, std::max(1e-3, P.k * 0.5 * std::sqrt(hd)));
+    for (int i = 0; i <= nt; ++i) {
+      sig[l][i] = std::pow(sl, i);
+      isig[l][i] = 1.0 / sig[l][i];
+    }
+  }
+  // translation matrices on the host
+  std::vector<double2> hT((size_t)(oP - oM));
+  {
+    TransTable t0, t1, t2;
+    trans_table(nt, 0, t0);
+    trans_table(nt, 1, t1);
+    trans_table(nt, 2, t2);
+    for (int l = 2; l <= L; ++l)
+      for (int oct = 0; oct < 8; ++oct) {
+        double b[3];
+        for (int a = 0; a < 3; ++a) {
+          const double h = P.pitch[a] / (1 << l);
+          b[a] = (((oct >> a) & 1) ? 0.5 : -0.5) * h;  // child centre minus parent centre
+        }
+        // M2M child (level l) -> parent (level l - 1): b = child - parent; moments / s^n
+        trans_matrix(t0, nt, b, P.k, false, isig[l - 1], sig[l], &hT[(size_t)(((l - 2) * 8 + oct) * pp)]);
+        // L2L parent -> child: b = child - parent
+        trans_matrix(t1, nt, b, P.k, false, sig[l], isig[l - 1],
+                     &hT[(size_t)(oL - oM + ((l - 2) * 8 + oct) * pp)]);
+      }
+    for (size_t i = 0; i < tr_list.size(); ++i) {
+      const int l = std::get<0>(tr_list[i]);
+      const int del[3] = {std::get<1>(tr_list[i]), std::get<2>(tr_list[i]), std::get<3>(tr_list[i])};
+      double D[3];
+      for (int a = 0; a < 3; ++a) D[a] = del[a] * (P.pitch[a] / (1 << l));
+      trans_matrix(t2, nt, D, P.k, true, sig[l], sig[l], &hT[(size_t)(oK - oM + (long long)i * pp)]);
+    }
+  }
+  // launch tables
+  std::vector<MlTarget> tg;
+  std::vector<MlTask> tk;
+  std::vector<std::pair<int, int>> stage_range;  // first target, count
+  std::vector<std::pair<int, int>> stage_mode;   // out buffer, accumulate
+  auto begin_stage = [&](int out, int accum) {
+    stage_range.push_back({(int)tg.size(), 0});
+    stage_mode.push_back({out, accum});
+  };
+  auto add_target = [&](int out_row, int rows) {
+    tg.push_back(MlTarget{out_row, rows, (int)tk.size(), (int)tk.size()});
+    ++stage_range.back().second;
+  };
+  auto add_task = [&](long long a_off, int lda, int ks, int src_row, int buf, int sd) {
+    tk.push_back(MlTask{a_off, lda, ks, src_row, buf | (sd << 2)});
+    tg.back().t1 = (int)tk.size();
+  };
+  // P2M
+  begin_stage(1, 0);
+  for (int b = 0; b < (int)lv[L].size(); ++b) {
+    const Box& x = lv[L][b];
+    add_target(row0(L, b), p);
+    add_task(oV + x.e0, n, x.e1 - x.e0, x.e0, 0, kMlZeroShift);
+  }
+  // M2M, finest parents first
+  for (int l = L - 1; l >= 1; --l) {
+    begin_stage(1, 0);
+    for (int b = 0; b < (int)lv[l].size(); ++b) {
+      add_target(row0(l, b), p);
+      for (int c : lv[l][b].child) {
+        const Box& x = lv[l + 1][c];
+        const int oct = (x.c[0] & 1) + 2 * (x.c[1] & 1) + 4 * (x.c[2] & 1);
+        add_task(oM + ((long long)(l + 1 - 2) * 8 + oct) * pp, p, p, row0(l + 1, c), 1, kMlZeroShift);
+      }
+    }
+  }
+  // M2L of every level, grouped by target box (every box gets a target, so the locals start at 0)
+  {
+    begin_stage(2, 0);
+    std::vector<std::vector<std::vector<int>>> by(L + 1);
+    for (int l = 1; l <= L; ++l) by[l].resize(lv[l].size());
+    for (size_t i = 0; i < m2l.size(); ++i) by[m2l[i].l][m2l[i].a].push_back((int)i);
+    for (int l = 1; l <= L; ++l)
+      for (int b = 0; b < (int)lv[l].size(); ++b) {
+        add_target(row0(l, b), p);
+        for (int i : by[l][b]) {
+          const Pair& q = m2l[i];
+          add_task(oK + (long long)q.tr * pp, p, p, row0(l, q.b), 1, q.sd);
+        }
+      }
+  }
+  // L2L, coarsest children first, added to the M2L locals
+  for (int l = 2; l <= L; ++l) {
+    begin_stage(2, 1);
+    for (int b = 0; b < (int)lv[l].size(); ++b) {
+      const Box& x = lv[l][b];
+      const int oct = (x.c[0] & 1) + 2 * (x.c[1] & 1) + 4 * (x.c[2] & 1);
+      add_target(row0(l, b), p);
+      add_task(oL + ((long long)(l - 2) * 8 + oct) * pp, p, p, row0(l - 1, x.parent), 2, kMlZeroShift);
+    }
+  }
+  // L2P and P2P per leaf, in chunks of at most kMlRows element rows
+  {
+    begin_stage(3, 0);
+    std::vector<std::vector<int>> by(lv[L].size());
+    for (size_t i = 0; i < p2p.size(); ++i) by[p2p[i].a].push_back((int)i);
+    for (int b = 0; b < (int)lv[L].size(); ++b) {
+      const Box& x = lv[L][b];
+      for (int r0 = x.e0; r0 < x.e1; r0 += kMlRows) {
+        const int rows = std::min(kMlRows, x.e1 - r0);
+        add_target(r0, rows);
+        add_task(oU + (long long)r0 * p, p, p, row0(L, b), 2, kMlZeroShift);
+        for (int i : by[b]) {
+          const Box& y = lv[L][p2p[i].b];
+          const int ns = y.e1 - y.e0;
+          add_task(oP + poff[i] + (long long)(r0 - x.e0) * ns, ns, ns, y.e0, 0, p2p[i].sd);
+        }
+      }
+    }
+  }
+  // device arrays
+  hipError_t e;
+  MlTarget* d_tg = nullptr;
+  MlTask* d_tk = nullptr;
+  if ((e = plan_alloc(P, (void**)&d_tg, std::max<size_t>(1, tg.size()) * sizeof(MlTarget)))) return e;
+  if ((e = plan_alloc(P, (void**)&d_tk, std::max<size_t>(1, tk.size()) * sizeof(MlTask)))) return e;
+  if ((e = plan_alloc(P, (void**)&M.pos, n * sizeof(int)))) return e;
+  if ((e = plan_alloc(P, (void**)&M.perm, n * sizeof(int)))) return e;
+  if ((e = plan_alloc(P, &M.ops[0], M.ops_elems * sizeof(double2)))) return e;
+  if (want32 && (e = plan_alloc(P, &M.ops[1], M.ops_elems * sizeof(float2)))) return e;
+  hipMemcpyAsync(d_tg, tg.data(), tg.size() * sizeof(MlTarget), hipMemcpyHostToDevice, s);
+  hipMemcpyAsync(d_tk, tk.data(), tk.size() * sizeof(MlTask), hipMemcpyHostToDevice, s);
+  hipMemcpyAsync(M.pos, pos.data(), n * sizeof(int), hipMemcpyHostToDevice, s);
+  hipMemcpyAsync(M.perm, perm.data(), n * sizeof(int), hipMemcpyHostToDevice, s);
+  double2* ops = reinterpret_cast<double2*>(M.ops[0]);
+  hipMemcpyAsync(ops + oM, hT.data(), hT.size() * sizeof(double2), hipMemcpyHostToDevice, s);
+  M.stages.clear();
+  for (size_t i = 0; i < stage_range.size(); ++i)
+    M.stages.push_back(MlStage{d_tg + stage_range[i].first, d_tk, stage_range[i].second, stage_mode[i].first,
+                               stage_mode[i].second});
+  // leaf P2M / L2P about the leaf centres (device), and the exact P2P entries
+  std::vector<double> cen((size_t)n * 3);
+  for (int e2 = 0; e2 < n; ++e2)
+    for (int a = 0; a < 3; ++a) {
+      const double h = P.pitch[a] / nl;
+      cen[(size_t)e2 * 3 + a] = -0.5 * P.pitch[a] + (leafc[e2][a] + 0.5) * h;
+    }
+  std::vector<P2pBlock> blocks(p2p.size());
+  for (size_t i = 0; i < p2p.size(); ++i) {
+    const Box& A = lv[L][p2p[i].a];
+    const Box& Bx = lv[L][p2p[i].b];
+    blocks[i] = P2pBlock{oP + poff[i], A.e0, A.e1 - A.e0, Bx.e0, Bx.e1 - Bx.e0, p2p[i].sd};
+  }
+  e = ml_assemble_launch(P, nt, cen, isig[L], blocks, pe, ops, oV, oU, s);
+  if (!e && want32) e = cast_launch(ops, reinterpret_cast<float2*>(M.ops[1]), M.ops_elems, s);
+  // the host tables must outlive their copies, also when a step failed
+  const hipError_t e2 = hipStreamSynchronize(s);
+  return e ? e : e2;
+}
+
+}  // namespace fmbem

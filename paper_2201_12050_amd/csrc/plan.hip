@@ -45,7 +45,7 @@ namespace fmbem {
 // ---------------------------------------------------------------------------
 // host helpers
 // ---------------------------------------------------------------------------
-static void gauss_legendre_host(int q, std::vector<double>& x, std::vector<double>& w) {
+void gauss_legendre_host(int q, std::vector<double>& x, std::vector<double>& w) {
   x.assign(q, 0.0);
   w.assign(q, 0.0);
   for (int i = 0; i < q; ++i) {
@@ -157,6 +157,50 @@ __device__ inline double2 elem_integral(const double* x, const double* nx, const
   return make_double2(re, im);
 }
 
+// S_d[i][j] for collocation element ex (index i) and source element ey (index j) of the cell
+// shifted by sh = -d * pitch
+__device__ inline double2 near_entry(const Geo& ex, const Geo& ey, bool same, int o0, int o1, int o2,
+                                     const double* sh, double k, double2 alpha, int hyper, const QuadTab& Q) {
+  if (o0 == 0 && o1 == 0 && o2 == 0 && same) {
+    double2 val = make_double2(0.5, 0.0);
+    if (hyper) val = cadd<double>(val, cmul<double>(alpha, hyper_self(ex, k, Q)));
+    return val;
+  }
+  double a[3], ba[3], cb[3], ca[3], cen[3];
+  for (int t = 0; t < 3; ++t) {
+    a[t] = ey.a[t] + sh[t];
+    ba[t] = ey.b[t] - ey.a[t];
+    cb[t] = ey.c[t] - ey.b[t];
+    ca[t] = ey.c[t] - ey.a[t];
+    cen[t] = ey.cen[t] + sh[t];
+  }
+  return elem_integral(ex.cen, ex.nrm, a, ba, cb, ca, cen, ey.longest, ey.nrm, k, alpha, hyper, Q);
+}
+
+// entries of the P2P blocks of the multilevel near field, one per thread in block order (the
+// block of entry idx found by bisection over the block offsets)
+__global__ void ml_p2p_kernel(const double* __restrict__ geom, const P2pBlock* __restrict__ blk, int nblk,
+                              long long base, long long total, const int* __restrict__ perm, double p0, double p1,
+                              double p2, double k, double2 alpha, int hyper, QuadTab Q, double2* __restrict__ out) {
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (long long)gridDim.x * blockDim.x) {
+    int lo = 0, hi = nblk - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (blk[mid].off - base <= idx) lo = mid;
+      else hi = mid - 1;
+    }
+    const P2pBlock b = blk[lo];
+    const long long r = idx - (b.off - base);
+    const int i = (int)(r / b.ns), j = (int)(r - (long long)i * b.ns);
+    const int o0 = b.sd % 3 - 1, o1 = (b.sd / 3) % 3 - 1, o2 = b.sd / 9 - 1;
+    const double sh[3] = {-o0 * p0, -o1 * p1, -o2 * p2};
+    const int ei = perm[b.te0 + i], ej = perm[b.se0 + j];
+    out[b.off + r - base] = near_entry(load_geo(geom, ei), load_geo(geom, ej), ei == ej, o0, o1, o2, sh, k, alpha,
+                                       hyper, Q);
+  }
+}
+
 // one entry S_d[i][j] per thread; entries ordered (d, i, j) with j fastest.  Half-space:
 // img = 1 (plane parallel to the periodic axes) adds R_p times the image block to every near
 // block: the source element of the shifted cell mirrored in z = zg, vertices (a, c, b) so that
@@ -179,22 +223,7 @@ __global__ void assemble_near_kernel(const double* __restrict__ geom, int n, con
   const Geo ex = load_geo(geom, i);
   const Geo ey = load_geo(geom, j);
   double2 val = make_double2(0.0, 0.0);
-  if (img == 2) {
-    // image block only
-  } else if (o0 == 0 && o1 == 0 && o2 == 0 && i == j) {
-    val = make_double2(0.5, 0.0);
-    if (hyper) val = cadd<double>(val, cmul<double>(alpha, hyper_self(ex, k, Q)));
-  } else {
-    double a[3], ba[3], cb[3], ca[3], cen[3];
-    for (int t = 0; t < 3; ++t) {
-      a[t] = ey.a[t] + sh[t];
-      ba[t] = ey.b[t] - ey.a[t];
-      cb[t] = ey.c[t] - ey.b[t];
-      ca[t] = ey.c[t] - ey.a[t];
-      cen[t] = ey.cen[t] + sh[t];
-    }
-    val = elem_integral(ex.cen, ex.nrm, a, ba, cb, ca, cen, ey.longest, ey.nrm, k, alpha, hyper, Q);
-  }
+  if (img != 2) val = near_entry(ex, ey, i == j, o0, o1, o2, sh, k, alpha, hyper, Q);
   if (img) {
     // mirrored element (a, c, b): z -> 2 zg - z after the lattice shift
     const double shz = img == 2 ? (o2 + zbase) * p2 : sh[2];
@@ -285,9 +314,12 @@ __device__ inline double wave_sum64(double v) {
   return v;
 }
 
+// cen (optional): expansion centre of every element ([n][3], default the origin); pos (optional):
+// column of every element (default its index)
 __global__ __launch_bounds__(64) void p2m_kernel(const double* __restrict__ geom, int n, int nt, double k,
                                                  QuadTab Qt, const double* __restrict__ isig,
-                                                 double2* __restrict__ V0) {
+                                                 double2* __restrict__ V0, const double* __restrict__ cen,
+                                                 const int* __restrict__ pos) {
   const int b = blockIdx.x / (nt + 1);
   const int m = blockIdx.x - b * (nt + 1);
   const int lane = threadIdx.x;
@@ -301,7 +333,8 @@ __global__ __launch_bounds__(64) void p2m_kernel(const double* __restrict__ geom
   const double u = Qt.t[o + ia], v = Qt.t[o + ib];
   const double wt = Qt.w[o + ia] * u * jac * Qt.w[o + ib];
   double y[3];
-  for (int t = 0; t < 3; ++t) y[t] = e.a[t] + u * (ba[t] + v * cb[t]);
+  for (int t = 0; t < 3; ++t) y[t] = e.a[t] + u * (ba[t] + v * cb[t]) - (cen ? cen[3 * b + t] : 0.0);
+  const int col = pos ? pos[b] : b;
   RegularWork W;
   double2 cI[21], dn[21];
   regular_m(y, e.nrm, k, nt, m, W, cI, dn);
@@ -309,36 +342,40 @@ __global__ __launch_bounds__(64) void p2m_kernel(const double* __restrict__ geom
   for (int nn = m; nn <= nt; ++nn) {
     const double re = wave_sum64(wt * dn[nn].x), im = wave_sum64(wt * dn[nn].y);
     if (lane == 0) {
-      V0[(size_t)(nn * nn + nn + m) * n + b] = cscale<double>(make_double2(re, im), isig[nn]);
+      V0[(size_t)(nn * nn + nn + m) * n + col] = cscale<double>(make_double2(re, im), isig[nn]);
       // conj(I_n^{-m}) = (-1)^m I_n^m => its gradient is (-1)^m conj(grad conj(I_n^m))
-      if (m > 0) V0[(size_t)(nn * nn + nn - m) * n + b] = cscale<double>(make_double2(sg * re, -sg * im), isig[nn]);
+      if (m > 0) V0[(size_t)(nn * nn + nn - m) * n + col] = cscale<double>(make_double2(sg * re, -sg * im), isig[nn]);
     }
   }
 }
 
-// U0: one thread per (element a, m >= 0), at the centroid
+// U0: one thread per (element a, m >= 0), at the centroid (cen, pos: as for p2m_kernel, pos the row)
 __global__ void l2p_kernel(const double* __restrict__ geom, int n, int nt, double k, double2 alpha,
-                           const double* __restrict__ isig, double2* __restrict__ U0) {
+                           const double* __restrict__ isig, double2* __restrict__ U0, const double* __restrict__ cen,
+                           const int* __restrict__ pos) {
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= n * (nt + 1)) return;
   const int a = tid / (nt + 1);
   const int m = tid - a * (nt + 1);
   const Geo e = load_geo(geom, a);
+  double x[3];
+  for (int t = 0; t < 3; ++t) x[t] = e.cen[t] - (cen ? cen[3 * a + t] : 0.0);
+  const size_t row = pos ? pos[a] : a;
   RegularWork W;
   double2 cI[21], dn[21];
-  regular_m(e.cen, e.nrm, k, nt, m, W, cI, dn);
+  regular_m(x, e.nrm, k, nt, m, W, cI, dn);
   const int p = (nt + 1) * (nt + 1);
   const double sg = (m & 1) ? -1.0 : 1.0;
   for (int nn = m; nn <= nt; ++nn) {
     const double f = k / kFourPi * (2.0 * nn + 1.0) * isig[nn];
     const double2 ik = make_double2(0.0, f);  // (ik/4pi)(2n+1)/sigma_n
     double2 vp = cadd<double>(cI[nn], cmul<double>(alpha, dn[nn]));
-    U0[(size_t)a * p + nn * nn + nn + m] = cmul<double>(ik, vp);
+    U0[row * p + nn * nn + nn + m] = cmul<double>(ik, vp);
     if (m > 0) {
       // conj(I_n^{-m}) = (-1)^m conj(conj(I_n^m)); gradient likewise
       double2 vm = cadd<double>(cconj<double>(cI[nn]), cmul<double>(alpha, cconj<double>(dn[nn])));
       vm = cscale<double>(vm, sg);
-      U0[(size_t)a * p + nn * nn + nn - m] = cmul<double>(ik, vm);
+      U0[row * p + nn * nn + nn - m] = cmul<double>(ik, vm);
     }
   }
 }
@@ -464,6 +501,11 @@ __global__ void cast_kernel(const double2* __restrict__ a, float2* __restrict__ 
     b[i] = make_float2((float)a[i].x, (float)a[i].y);
 }
 
+hipError_t cast_launch(const double2* a, float2* b, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(cast_kernel, dim3(4096), dim3(256), 0, s, a, b, n);
+  return hipGetLastError();
+}
+
 // incident fields: b = p_inc + alpha dp_inc/dn at every collocation point
 // p_inc and dp_inc/dn of a plane wave (complex amplitude a, unit direction s) or a monopole at s
 __device__ inline void incident_at(const double* x, const double* nx, const double* s, int point, double k,
@@ -567,7 +609,7 @@ __global__ void identity_kernel(double2* __restrict__ I64, float2* __restrict__ 
     if (e_ != hipSuccess) return e_;           \
   } while (0)
 
-static hipError_t plan_alloc(Plan& P, void** ptr, size_t bytes) {
+hipError_t plan_alloc(Plan& P, void** ptr, size_t bytes) {
   FM_CHECK(hipMalloc(ptr, bytes));
   P.allocations.push_back(*ptr);
   P.resident += bytes;
@@ -580,7 +622,7 @@ static void free_list(std::vector<void*>& v) {
 }
 
 // theta part of the harmonics at Gauss nodes: table [l][mu + l][node], l <= L
-static void theta_table(int L, const std::vector<double>& x, std::vector<double>& tab) {
+void theta_table(int L, const std::vector<double>& x, std::vector<double>& tab) {
   const int q = (int)x.size();
   const int W = 2 * L + 1;
   tab.assign((size_t)(L + 1) * W * q, 0.0);
@@ -665,6 +707,47 @@ void plan_release(Plan* P) {
   free_list(P->allocations);
   hipSetDevice(cur);
   delete P;
+}
+
+hipError_t ml_assemble_launch(const Plan& P, int nt, const std::vector<double>& cen, const std::vector<double>& isig,
+                              const std::vector<P2pBlock>& blocks, long long entries, double2* ops, long long oV,
+                              long long oU, hipStream_t s) {
+  const int n = P.n;
+  std::vector<void*> scratch;
+  auto salloc = [&](void** ptr, size_t bytes) -> hipError_t {
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e == hipSuccess) scratch.push_back(*ptr);
+    return e;
+  };
+  double *d_cen = nullptr, *d_isig = nullptr;
+  P2pBlock* d_blk = nullptr;
+  hipError_t err = hipSuccess;
+  do {
+    if ((err = salloc((void**)&d_cen, cen.size() * sizeof(double)))) break;
+    if ((err = salloc((void**)&d_isig, isig.size() * sizeof(double)))) break;
+    if ((err = salloc((void**)&d_blk, std::max<size_t>(1, blocks.size()) * sizeof(P2pBlock)))) break;
+    hipMemcpyAsync(d_cen, cen.data(), cen.size() * sizeof(double), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(d_isig, isig.data(), isig.size() * sizeof(double), hipMemcpyHostToDevice, s);
+    hipMemcpyAsync(d_blk, blocks.data(), blocks.size() * sizeof(P2pBlock), hipMemcpyHostToDevice, s);
+    const double2 alpha = make_double2(P.alpha_re, P.alpha_im);
+    const int hyper = (P.alpha_re != 0.0 || P.alpha_im != 0.0) ? 1 : 0;
+    const int th = n * (nt + 1);
+    hipLaunchKernelGGL(p2m_kernel, dim3(th), dim3(64), 0, s, P.geom, n, nt, P.k, P.quad, d_isig, ops + oV, d_cen,
+                       P.ml->pos);
+    hipLaunchKernelGGL(l2p_kernel, dim3((th + 63) / 64), dim3(64), 0, s, P.geom, n, nt, P.k, alpha, d_isig, ops + oU,
+                       d_cen, P.ml->pos);
+    if (entries > 0) {
+      const long long base = blocks[0].off;
+      const unsigned g = (unsigned)std::min<long long>((entries + 255) / 256, 1 << 16);
+      hipLaunchKernelGGL(ml_p2p_kernel, dim3(g), dim3(256), 0, s, P.geom, d_blk, (int)blocks.size(), base, entries,
+                         P.ml->perm, P.pitch[0], P.pitch[1], P.pitch[2], P.k, alpha, hyper, P.quad, ops + base);
+    }
+    if ((err = hipGetLastError())) break;
+    err = hipStreamSynchronize(s);  // the host tables must outlive their copies
+  } while (0);
+  const hipError_t e2 = hipStreamSynchronize(s);
+  free_list(scratch);
+  return err ? err : e2;
 }
 
 // Exact periodic BEM plan: every block S_d (|d_a| <= M_a - 1) integrated like the near blocks,
@@ -868,9 +951,10 @@ static hipError_t plan_build(Plan& P, const std::vector<double>& geo, hipStream_
     if (!P.parent && (err = plan_alloc(P, &P.U0[0], (size_t)p * n * sizeof(double2))) != hipSuccess) break;
     if (!P.parent) {
       const int th = n * (nt + 1);
-      hipLaunchKernelGGL(p2m_kernel, dim3(th), dim3(64), 0, s, P.geom, n, nt, P.k, Q, d_isig, (double2*)P.V0[0]);
+      hipLaunchKernelGGL(p2m_kernel, dim3(th), dim3(64), 0, s, P.geom, n, nt, P.k, Q, d_isig, (double2*)P.V0[0],
+                         (const double*)nullptr, (const int*)nullptr);
       hipLaunchKernelGGL(l2p_kernel, dim3((th + 63) / 64), dim3(64), 0, s, P.geom, n, nt, P.k, alpha, d_isig,
-                         (double2*)P.U0[0]);
+                         (double2*)P.U0[0], (const double*)nullptr, (const int*)nullptr);
       if ((err = hipGetLastError()) != hipSuccess) break;
     }
     if (want32 && !P.parent) {
@@ -881,6 +965,7 @@ static hipError_t plan_build(Plan& P, const std::vector<double>& geo, hipStream_
       hipLaunchKernelGGL(cast_kernel, dim3(256), dim3(256), 0, s, (const double2*)P.U0[0], (float2*)P.U0[1],
                          (size_t)p * n);
     }
+    if (P.ml && (err = ml_build(P, geo, s)) != hipSuccess) break;
     if (P.n_far == 0) break;
     // O grid -> FFT -> Lambda
     const int L = 2 * nt, P2 = (L + 1) * (L + 1);
@@ -1055,6 +1140,13 @@ extern "C" fmbem_status fmbem_plan_create(const fmbem_cell_mesh* mesh, const fmb
   if (desc->exact != 0 && desc->exact != 1) return FMBEM_ERR_INVALID_ARG;
   if (desc->exact == 1 && desc->halfspace != 0) return FMBEM_ERR_UNSUPPORTED;
   if (desc->exact == 0 && (desc->order < 0 || desc->order > 20)) return FMBEM_ERR_INVALID_ARG;
+  if (desc->near_levels < 0 || desc->near_levels > 8 || desc->near_order < 0 || desc->near_order > 7)
+    return FMBEM_ERR_INVALID_ARG;
+  if (desc->near_levels > 0) {
+    if (desc->exact != 0 || desc->halfspace != 0) return FMBEM_ERR_UNSUPPORTED;
+    for (int a = 0; a < 3; ++a)
+      if (desc->near_radius[a] > 1) return FMBEM_ERR_UNSUPPORTED;
+  }
   if (desc->formulation != FMBEM_BURTON_MILLER && desc->formulation != FMBEM_CBIE) return FMBEM_ERR_INVALID_ARG;
   if (desc->precisions & ~3u) return FMBEM_ERR_INVALID_ARG;
   if (desc->dft_schedule < FMBEM_DFT_AUTO || desc->dft_schedule > FMBEM_DFT_FFT) return FMBEM_ERR_INVALID_ARG;
@@ -1108,6 +1200,7 @@ extern "C" fmbem_status fmbem_plan_create(const fmbem_cell_mesh* mesh, const fmb
     g[15] = longest;
     g[16] = 0.5 * two_a;
   }
+  if (desc->near_levels > 0 && !ml_cell_fits(geo, n, desc->pitch, desc->near_levels)) return FMBEM_ERR_UNSUPPORTED;
   Plan* P = new (std::nothrow) Plan();
   if (!P) return FMBEM_ERR_OUT_OF_MEMORY;
   if (hipGetDevice(&P->device) != hipSuccess) {
@@ -1170,6 +1263,15 @@ extern "C" fmbem_status fmbem_plan_create(const fmbem_cell_mesh* mesh, const fmb
     return FMBEM_ERR_UNSUPPORTED;
   }
   P->n_far = (2 * P->grid[0] - 1) * (2 * P->grid[1] - 1) * (2 * P->grid[2] - 1) - P->n_near;
+  if (desc->near_levels > 0) {
+    // the near offsets stay out of the far field but have no dense blocks
+    P->ml = std::make_shared<MlData>();
+    P->ml->levels = desc->near_levels;
+    P->ml->order = desc->near_order > 0 ? desc->near_order : std::max(1, std::min(desc->order, 7));
+    P->ml->p = (P->ml->order + 1) * (P->ml->order + 1);
+    P->near_off.clear();
+    P->n_near = 0;
+  }
   if (desc->halfspace == 1) {
     P->half = true;
     P->zg = desc->plane_z;

@@ -105,6 +105,44 @@ def test_plan_create_rejects_invalid_arguments(case):
     assert out.value is None
 
 
+@pytest.mark.parametrize("case", ["levels_negative", "levels_high", "order_high", "order_negative"])
+def test_multilevel_descriptor_rejects_invalid_values(case):
+    lib = fm.load()
+    v, t = icosphere(1, 0.1)
+    kw = {"levels_negative": dict(near_levels=-1), "levels_high": dict(near_levels=9),
+          "order_high": dict(near_levels=2, near_order=8), "order_negative": dict(near_levels=2, near_order=-1)}[case]
+    mesh, keep = _mesh(v, t)
+    out = ct.c_void_p()
+    assert lib.fmbem_plan_create(ct.byref(mesh), ct.byref(_desc(**kw)), None, ct.byref(out)) == 1
+    assert out.value is None
+
+
+@pytest.mark.parametrize("case", ["exact", "halfspace", "radius", "outside_box", "at_leaf_centre"])
+def test_multilevel_descriptor_rejects_unsupported_combinations(case):
+    # FMPBEM2 needs near radius 1, the full space, the multipole far field and every collocation
+    # point inside the cell's lattice box, off its leaf centre (checked before any device work)
+    lib = fm.load()
+    v, t = icosphere(1, 0.1)
+    kw = dict(near_levels=2)
+    if case == "exact":
+        kw["exact"] = 1
+    elif case == "halfspace":
+        kw.update(halfspace=1, plane_z=-0.2)
+    elif case == "radius":
+        kw["near_radius"] = (2, 1, 1)
+    elif case == "outside_box":
+        kw["pitch"] = (0.15, 0.15, 0.15)   # the sphere of radius 0.1 leaves the box
+    elif case == "at_leaf_centre":
+        # one triangle whose centroid is the centre of its level-2 leaf
+        c = np.array([0.0375, 0.0375, 0.0375])
+        v = np.array([c + [0.01, 0, 0], c + [-0.005, 0.008, 0], c + [-0.005, -0.008, 0]])
+        t = np.array([[0, 1, 2]])
+    mesh, keep = _mesh(v, t)
+    out = ct.c_void_p()
+    assert lib.fmbem_plan_create(ct.byref(mesh), ct.byref(_desc(**kw)), None, ct.byref(out)) == 2
+    assert out.value is None
+
+
 def test_other_entry_points_reject_null_plan():
     lib = fm.load()
     assert lib.fmbem_matvec(None, 0, 1, None, None, None, 0, None) == 1

@@ -1,0 +1,128 @@
+"""FMPBEM2 (Sec. 3.3: the near blocks as a multilevel FMM over the boxes of the lattice) on
+the GPU against the oracle's FMPBEM2 (oracle.multilevel: every near block composed leaf pair
+by leaf pair from the exact entries and the P2M / M2M / M2L / L2L / L2P chain), through the C
+ABI.  Tolerances: FP64 operator 1e-12, FP32 1e-5 (relative l2 and max-norm), solutions 1e-8
+against the oracle's LU of the same operator."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import bem, solve, multilevel as ml
+from workloads import icosphere, tube_segment, Lattice
+from workloads.rng import random_complex, unit_directions
+from tolerance import rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+CASES = {
+    # name: (geometry, grid, frequency, n_t, levels, n_t,near)
+    "sphere80_3x3_L2": ("sphere1", (3, 3, 1), 900.0, 6, 2, 4),
+    "sphere320_4x3_L2": ("sphere2", (4, 3, 1), 700.0, 6, 2, 5),
+    "sphere320_5x1_L3": ("sphere2", (5, 1, 1), 1300.0, 8, 3, 6),
+    "sphere80_1x1_L2": ("sphere1", (1, 1, 1), 600.0, 4, 2, 4),      # no far field
+    "tube192_2x2x2_L1": ("tube", (2, 2, 2), 600.0, 6, 1, 7),        # 27 near offsets
+}
+
+
+def _geometry(kind):
+    if kind == "tube":
+        v, t = tube_segment(0.08, 0.25, 32, 3)
+        return v, t, (0.2, 0.2, 0.25)
+    v, t = icosphere(int(kind[-1]), 0.1)
+    return v, t, (0.3, 0.3, 0.3)
+
+
+_ORACLE = {}
+
+
+def _case(name):
+    if name not in _ORACLE:
+        kind, grid, f, nt, levels, ntn = CASES[name]
+        v, t, pitch = _geometry(kind)
+        lat = Lattice(grid, pitch)
+        k = 2 * np.pi * f / 343.0
+        F = ml.FMPBEM2(v, t, lat, k, nt, -1j / k, levels, ntn)
+        _ORACLE[name] = (v, t, lat, k, F, F.dense())
+    return _ORACLE[name]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_multilevel_matvec_matches_oracle(name):
+    import paper_2201_12050_amd as fm
+    v, t, lat, k, F, A = _case(name)
+    _, grid, _, nt, levels, ntn = CASES[name]
+    P = fm.Plan(v, t, grid, lat.pitch, k, nt, near_levels=levels, near_order=ntn)
+    assert P.info["n_near"] == 0
+    n = t.shape[0]
+    for R in (1, 3, 9):   # column tiles of 16, 32 and 64 (R C columns), GEMV and GEMM M2L
+        x = random_complex((R, lat.n_cells, n), 2200 + R)
+        ref = (x.reshape(R, -1) @ A.T).reshape(x.shape)
+        xd = torch.from_numpy(x).cuda()
+        assert rel(P.matvec(xd, precision="fp64").cpu().numpy(), ref) < 1e-12, R
+        assert rel(P.matvec(xd.to(torch.complex64), precision="fp32").cpu().numpy(), ref) < 1e-5, R
+    P.close()
+
+
+def test_multilevel_differs_from_dense_near_field_by_the_truncation():
+    # the same plan with dense near blocks: the two operators differ by the multilevel
+    # approximation of the near blocks alone (oracle: S~_d - S_d)
+    import paper_2201_12050_amd as fm
+    v, t, lat, k, F, A = _case("sphere320_4x3_L2")
+    _, grid, _, nt, levels, ntn = CASES["sphere320_4x3_L2"]
+    P2 = fm.Plan(v, t, grid, lat.pitch, k, nt, near_levels=levels, near_order=ntn)
+    P1 = fm.Plan(v, t, grid, lat.pitch, k, nt)
+    x = random_complex((2, lat.n_cells, t.shape[0]), 77)
+    xd = torch.from_numpy(x).cuda()
+    diff = (P2.matvec(xd, precision="fp64") - P1.matvec(xd, precision="fp64")).cpu().numpy()
+    ref = np.zeros_like(x)
+    for d in F.near:
+        tg, src = F._pairs[d]
+        ref[:, tg, :] += x[:, src, :] @ (F.S[d] - F.S_exact[d]).T
+    assert rel(diff, ref) < 1e-9
+    # storage: the multilevel plan keeps no n x n blocks
+    assert P2.info["resident_bytes"] < P1.info["resident_bytes"]
+    P1.close()
+    P2.close()
+
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32"])
+def test_multilevel_solve_matches_lu(inner):
+    import paper_2201_12050_amd as fm
+    v, t, lat, k, F, A = _case("sphere80_3x3_L2")
+    _, grid, _, nt, levels, ntn = CASES["sphere80_3x3_L2"]
+    P = fm.Plan(v, t, grid, lat.pitch, k, nt, near_levels=levels, near_order=ntn)
+    dirs = unit_directions(2, 31)
+    b = bem.rhs_plane_wave(v, t, lat, k, -1j / k, dirs)
+    xl = np.stack([solve.lu_solve(A, b[q]) for q in range(2)])
+    xs, info = P.solve(P.incident_plane_wave(dirs), tol=1e-11, inner=inner)
+    assert max(i["rel_residual"] for i in info) <= 1e-11
+    assert rel(xs.cpu().numpy().reshape(xl.shape), xl) < 1e-8
+    P.close()
+
+
+def test_multilevel_in_a_batch_with_a_dense_plan():
+    # grouped launches: an FMPBEM2 plan and an FMPBEM plan solved together equal each alone
+    import paper_2201_12050_amd as fm
+    v, t, lat, k, F, A = _case("sphere80_3x3_L2")
+    _, grid, _, nt, levels, ntn = CASES["sphere80_3x3_L2"]
+    P2 = fm.Plan(v, t, grid, lat.pitch, k, nt, near_levels=levels, near_order=ntn)
+    P1 = fm.Plan(v, t, (4, 2, 1), lat.pitch, k, nt)
+    b2 = P2.incident_plane_wave(unit_directions(3, 5))
+    b1 = P1.incident_plane_wave(unit_directions(2, 6))
+    for ortho in ("once", "dgks"):
+        o = dict(tol=1e-10, inner="fp32", ortho=ortho)
+        res = fm.solve_batch([(P2, b2, None, o), (P1, b1, None, o)])
+        for P, b, (x, infos) in zip((P2, P1), (b2, b1), res):
+            assert max(i["rel_residual"] for i in infos) <= 1e-10
+            xa, _ = P.solve(b, **o)
+            assert rel(x.cpu().numpy(), xa.cpu().numpy()) < 1e-8
+    P1.close()
+    P2.close()

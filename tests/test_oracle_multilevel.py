@@ -25,7 +25,7 @@ def test_m2m_is_the_regular_addition_theorem():
     lhs = np.conj(fmm.regular(a + b, K, 5))
     rhs = np.conj(fmm.regular(a, K, 24)) @ T.T
     assert np.abs(lhs - rhs).max() <= 1e-13 * np.abs(lhs).max()
-    # a plausible slip (the printed power of i) breaks it
+    # the translation depends on the direction of b (a swapped shift fails)
     assert np.abs(T - fmm.m2m(-b, K, 5, 24)[0]).max() > 1e-3
 
 
