@@ -328,6 +328,94 @@ def pbem_comparison(fm, torch, args):
                          "320-triangle spheres; FMPBEM n_t = 10", "rows": rows}
 
 
+PEAK_VALU = 78.6e12  # non-packed FP32 / FP64 vector FMA: 256 CUs x 64 lanes x 2 flop x 2.4 GHz
+
+
+def large_cell_comparison(fm, torch, args):
+    """FMPBEM2 (Sec. 3.3: the near blocks as a multilevel FMM inside the cells) against the FMPBEM
+    with dense near blocks on the 4 x 4 lattice of 20480-triangle spheres (1 kHz, n_t = 10,
+    N = 327,680): plan build time and bytes, operator applications per second, device time of the
+    multilevel near field with its algorithmic rate (8 flop per complex multiply-add over the
+    cells inside the lattice) against the vector-unit peak, the operator difference between the
+    two methods, sampled rows against the oracle's FMPBEM2 (stored fixture), and FP32-refined
+    solves."""
+    from workloads import config_large_cell
+    from workloads.rng import random_complex
+    w = config_large_cell()
+    x = torch.from_numpy(random_complex((1, w.lattice.n_cells, w.n_dof_cell), 7)).cuda()
+    plans = [("fmpbem2_L4_nt4", dict(near_levels=4, near_order=4)),
+             ("fmpbem2_L4_nt6", dict(near_levels=4, near_order=6))]
+    if not args.no_large_dense:
+        plans.append(("fmpbem_dense_near", {}))
+    out = {"workload": "4x4 lattice of 20480-triangle spheres (r = 0.1 m, pitch 0.3 m), 1 kHz, n_t = 10, "
+                       "N = 327,680; FMPBEM2 with 4 levels, n_t,near = 4 and 6",
+           "peak_valu_tflops": PEAK_VALU / 1e12}
+    ref = {}
+    for name, kw in plans:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P = fm.Plan.from_workload(w, **kw)
+        torch.cuda.synchronize()
+        rec = {"plan_build_s": time.perf_counter() - t0, "resident_gib": P.info["resident_bytes"] / 2**30}
+        if kw:
+            rec.update({"boxes": P.info["near_boxes"], "m2l_pairs": P.info["near_m2l_pairs"],
+                        "p2p_entries": P.info["near_p2p_entries"], "near_macs_per_rhs": P.info["near_macs_per_rhs"]})
+        for prec, xx in (("fp64", x), ("fp32", x.to(torch.complex64))):
+            ws = P.workspace(1, prec)
+            y = torch.empty_like(xx)
+            for _ in range(3):
+                P.matvec(xx, y, prec, ws)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 20
+            e0.record()
+            for _ in range(reps):
+                P.matvec(xx, y, prec, ws)
+            e1.record()
+            torch.cuda.synchronize()
+            rec[f"matvec_ms_{prec}"] = e0.elapsed_time(e1) / reps
+            if kw:
+                P.profile([f"reduce_{prec}"])
+                for _ in range(5):
+                    P.matvec(xx, y, prec, ws)
+                torch.cuda.synchronize()
+                ms, cnt = P.profile_read()[f"reduce_{prec}"]
+                P.profile([])
+                us = ms / max(cnt, 1) * 1e3
+                rate = 8 * rec["near_macs_per_rhs"] / (us * 1e-6)
+                rec[f"multilevel_near_us_{prec}"] = us
+                rec[f"multilevel_near_tflops_{prec}"] = rate / 1e12
+                rec[f"multilevel_near_frac_valu_{prec}"] = rate / PEAK_VALU
+            if prec == "fp64":
+                ref[name] = y.clone()
+        if kw.get("near_levels") == 4 and kw.get("near_order") == 4:
+            rec["operator_rows_vs_oracle"] = operator_rows_vs_oracle(P, w, "large_cell_rows.npz")
+        b = P.incident_plane_wave(w.plane_waves)
+        xs, info = P.solve(b, tol=args.tol, inner="fp32", ortho=args.ortho)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            xs, info = P.solve(b, tol=args.tol, inner="fp32", ortho=args.ortho)
+        torch.cuda.synchronize()
+        rec["solve_ms_fp32_refined"] = (time.perf_counter() - t0) / reps * 1e3
+        rec["solve_iterations"] = info[0]["iterations"]
+        rec["solve_rel_residual"] = info[0]["rel_residual"]
+        ref[name + "_solution"] = xs.clone()
+        out[name] = rec
+        P.close()
+        torch.cuda.empty_cache()
+    if "fmpbem_dense_near" in ref:
+        r = ref["fmpbem_dense_near"]
+        xr = ref["fmpbem_dense_near_solution"]
+        for name, _ in plans[:2]:
+            out[name]["operator_diff_vs_dense_near"] = (torch.linalg.vector_norm(ref[name] - r) /
+                                                        torch.linalg.vector_norm(r)).item()
+            out[name]["solution_diff_vs_dense_near"] = (torch.linalg.vector_norm(ref[name + "_solution"] - xr) /
+                                                        torch.linalg.vector_norm(xr)).item()
+    return out
+
+
 def ground_solves(fm, torch, args):
     """The 16x16 lattice of the headline above a sound-hard plane 0.05 m below the spheres (image
     blocks near, R_p = 1), a plane wave travelling down toward it: FP32-refined solves with the
@@ -492,6 +580,9 @@ def main():
     ap.add_argument("--no-batched-grids", action="store_true")
     ap.add_argument("--no-ground", action="store_true", help="skip the half-space 16x16 solves")
     ap.add_argument("--no-pbem", action="store_true", help="skip the exact PBEM comparison")
+    ap.add_argument("--no-large-cell", action="store_true", help="skip the FMPBEM2 large-cell comparison")
+    ap.add_argument("--no-large-dense", action="store_true",
+                    help="large-cell comparison without the dense-near plan (90 GiB of near blocks)")
     ap.add_argument("--ground-freqs", type=int, default=4,
                     help="frequencies of the barrier-on-ground sweep (0: skip)")
     ap.add_argument("--serving-requests", type=int, default=100, help="measured requests of the serving run")
@@ -688,6 +779,9 @@ def main():
     if not args.no_pbem:
         out["pbem_vs_fmpbem"] = pbem_comparison(fm, torch, args)
         print(f"[bench] PBEM vs FMPBEM {out['pbem_vs_fmpbem']}", file=sys.stderr, flush=True)
+    if not args.no_large_cell:
+        out["large_cell_fmpbem2"] = large_cell_comparison(fm, torch, args)
+        print(f"[bench] large cells {out['large_cell_fmpbem2']}", file=sys.stderr, flush=True)
     if not args.no_ground:
         out["halfspace_grid16"] = ground_solves(fm, torch, args)
         print(f"[bench] half-space 16x16 {out['halfspace_grid16']}", file=sys.stderr, flush=True)

@@ -156,6 +156,13 @@ typedef struct {
   size_t resident_bytes;      /* device memory owned by the plan */
   size_t workspace_bytes_per_rhs[2]; /* matvec workspace per right-hand side, [FP64, FP32] */
   double scale;               /* s of the diagonal scaling s^n applied to V0, U0, Lambda */
+  int32_t near_levels;        /* multilevel near field (FMPBEM2): levels L (0: dense near blocks) */
+  int32_t near_order;         /* its truncation number n_t,near */
+  int64_t near_boxes;         /* boxes of levels 1..L of one cell */
+  int64_t near_m2l_pairs;     /* (target box, source box, near offset) triples translated by M2L */
+  int64_t near_p2p_entries;   /* exact entries kept in the P2P blocks */
+  double near_macs_per_rhs;   /* complex multiply-adds of one multilevel near-field application per
+                                 right-hand side, counting only source cells inside the lattice */
 } fmbem_plan_info;
 
 /* Build the plan: near blocks S_d (Sec. 3.2), P2M V0 and L2P U0 (Appendix A,

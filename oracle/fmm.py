@@ -107,17 +107,20 @@ def grad_conj_regular(v, k, order):
 
 def p2m(vertices, triangles, k, order, q: int = 8, center=None):
     """V0 [p, n]: P2M moments of each element for unit density (eq. (p2m)), about
-    ``center`` (the cell centre, the origin, by default)."""
+    ``center``: one point [3] for every element (the cell centre, the origin, by default)
+    or one per element [n, 3]."""
     v = np.asarray(vertices, dtype=np.float64)
-    if center is not None:
-        v = v - np.asarray(center, dtype=np.float64)[None, :]
     t = np.asarray(triangles)
     a, b, c = v[t[:, 0]], v[t[:, 1]], v[t[:, 2]]
+    if center is not None:
+        cen = np.asarray(center, dtype=np.float64)
+        a, b, c = a - cen, b - cen, c - cen
     nrm = np.cross(b - a, c - a)
     nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
     out = np.zeros((n_coeffs(order), a.shape[0]), dtype=np.complex128)
-    for s in range(0, a.shape[0], 64):
-        e = slice(s, s + 64)
+    step = 256  # elements per vectorised batch
+    for s in range(0, a.shape[0], step):
+        e = slice(s, s + step)
         pts, w = duffy_points(a[e], b[e], c[e], q)           # [ne, q*q, 3], [ne, q*q]
         g = grad_conj_regular(pts, k, order)                 # [ne, q*q, p, 3]
         dn = (g * nrm[e][:, None, None, :]).sum(-1)          # [ne, q*q, p]

@@ -29,7 +29,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import bem, fmm
-from .operator import FMPBEM
+from .operator import FMPBEM, sampled_apply, grid_coords
 
 
 class CellTree:
@@ -147,3 +147,88 @@ class FMPBEM2(FMPBEM):
         self.S_exact = self.S
         self.S = approx_blocks(vertices, triangles, lattice, k, alpha, levels, near_order, near_radius,
                                exact=self.S_exact)
+
+
+def sampled_apply2(vertices, triangles, lattice, k, order, alpha, levels, near_order, x, dofs):
+    """(A2 x)[:, dof] of the FMPBEM2 operator for the listed DOFs only, for lattices whose
+    near blocks are too large to form: the far field as in operator.sampled_apply, the near
+    field leaf pair by leaf pair as in approx_blocks (exact row entries for P2P pairs,
+    U_a L2L K M2M V_b otherwise), restricted to the listed rows.  x: [R, C, n]."""
+    x = np.asarray(x, dtype=np.complex128)
+    grid = tuple(lattice.grid)
+    n = int(np.asarray(triangles).shape[0])
+    R = x.shape[0]
+    tree = CellTree(vertices, triangles, lattice.pitch, levels)
+    pitch = tree.pitch
+    L = tree.levels
+    t = np.asarray(triangles)
+    geom = bem.element_geometry(vertices, triangles)
+    leaves = tree.leaves()
+    leaf_of = {int(e): c for c, es in leaves.items() for e in es}
+    # P2M of every element about its leaf centre (one batched evaluation)
+    Vall = fmm.p2m(vertices, t, k, near_order, center=tree.centre(L, tree.leaf))
+    V = {c: Vall[:, e] for c, e in leaves.items()}
+    g = grid_coords(grid)
+    gsz = np.asarray(grid)
+    dofs = [int(v) for v in dofs]
+    out = sampled_apply(vertices, triangles, lattice, k, order, alpha, x, dofs, with_near=False)
+    cache = {}
+
+    def translation(kind, vec):
+        key = (kind,) + tuple(np.round(np.asarray(vec) / pitch * (1 << (L + 2))).astype(int))
+        if key not in cache:
+            fn = {"m2m": fmm.m2m, "l2l": fmm.l2l, "m2l": fmm.m2l}[kind]
+            cache[key] = fn(vec, k, near_order)[0]
+        return cache[key]
+
+    def up(c, lev):
+        key = ("up", c, lev)
+        if key not in cache:
+            T = np.eye(fmm.n_coeffs(near_order), dtype=np.complex128)
+            cc = np.asarray(c)
+            for l in range(L, lev, -1):
+                T = translation("m2m", tree.centre(l, cc) - tree.centre(l - 1, cc >> 1)) @ T
+                cc = cc >> 1
+            cache[key] = T @ V[c]
+        return cache[key]
+
+    def down_row(a, c, lev):
+        """Row of U_a L2L(level lev -> leaf c) for element a of leaf c."""
+        if ("u", a) not in cache:
+            cache[("u", a)] = fmm.l2p(vertices, t[[a]], k, near_order, alpha, center=tree.centre(L, c))[0]
+        u = cache[("u", a)]
+        path = [np.asarray(c) >> (L - l) for l in range(lev, L + 1)]
+        T = np.eye(fmm.n_coeffs(near_order), dtype=np.complex128)
+        for l in range(lev, L):
+            T = translation("l2l", tree.centre(l + 1, path[l - lev + 1]) - tree.centre(l, path[l - lev])) @ T
+        return u @ T
+
+    near = bem.near_offsets(grid)
+    for s, dof in enumerate(dofs):
+        i, a = divmod(dof, n)
+        ca = leaf_of[a]
+        acc = np.zeros(R, dtype=np.complex128)
+        for d in near:
+            src = g[i] - np.asarray(d)
+            if not np.all((src >= 0) & (src < gsz)):
+                continue
+            j = int(src[0] + grid[0] * (src[1] + grid[1] * src[2]))
+            xs = x[:, j, :]
+            exact = None
+            rows = {}
+            for cb, eb in leaves.items():
+                lev = interaction_level(tree, ca, cb, d)
+                if lev is None:
+                    if exact is None:
+                        exact = bem.block(geom, k, alpha, np.zeros(3), -np.asarray(d) * pitch, d == (0, 0, 0),
+                                          rows=[a])[0]
+                    acc += xs[:, eb] @ exact[eb]
+                    continue
+                sh = L - lev
+                D = tree.centre(lev, np.asarray(ca) >> sh) - tree.centre(lev, np.asarray(cb) >> sh) + np.asarray(d) * pitch
+                key = (lev,) + tuple(np.round(D / pitch * (1 << (L + 2))).astype(int))
+                if key not in rows:
+                    rows[key] = down_row(a, ca, lev) @ translation("m2l", D)
+                acc += (xs[:, eb] @ up(cb, lev).T) @ rows[key]
+        out[:, s] += acc
+    return out

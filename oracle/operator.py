@@ -127,12 +127,14 @@ class FMPBEM:
         return out
 
 
-def sampled_apply(vertices, triangles, lattice, k, order, alpha, x, dofs, near_radius=(1, 1, 1), chunk=256):
+def sampled_apply(vertices, triangles, lattice, k, order, alpha, x, dofs, near_radius=(1, 1, 1), chunk=256,
+                  with_near=True):
     """(A x)[:, dof] of the O2 operator for the listed DOFs only, for lattices too large
     to materialise S_d.  Near field: for every cell holding a listed DOF, the rows of its
     near blocks S_d at the listed elements, each integrated for its collocation point
     alone.  Far field: U0[a] sum_j K_{i-j} V0 x_j, the translations K_d formed ``chunk``
-    offsets at a time so that memory stays bounded on large lattices.
+    offsets at a time so that memory stays bounded on large lattices.  ``with_near=False``:
+    the far field alone.
     x: [R, C, n]; returns [R, len(dofs)]."""
     x = np.asarray(x, dtype=np.complex128)
     grid = tuple(lattice.grid)
@@ -160,7 +162,7 @@ def sampled_apply(vertices, triangles, lattice, k, order, alpha, x, dofs, near_r
     for i in cells:
         rows = sorted(set(d % n for d in dofs if d // n == i))
         acc = np.zeros((R, len(rows)), dtype=np.complex128)
-        for d in near:
+        for d in (near if with_near else []):
             j = source(i, d)
             if j is None:
                 continue

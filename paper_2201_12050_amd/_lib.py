@@ -49,7 +49,9 @@ class PlanInfo(ct.Structure):
     _fields_ = [("n_dof_cell", ct.c_int32), ("n_cells", ct.c_int32), ("n_dof", ct.c_int64), ("p", ct.c_int32),
                 ("fft_shape", ct.c_int32 * 3), ("n_near", ct.c_int32), ("n_far", ct.c_int32),
                 ("precisions", ct.c_uint32), ("resident_bytes", ct.c_size_t),
-                ("workspace_bytes_per_rhs", ct.c_size_t * 2), ("scale", ct.c_double)]
+                ("workspace_bytes_per_rhs", ct.c_size_t * 2), ("scale", ct.c_double),
+                ("near_levels", ct.c_int32), ("near_order", ct.c_int32), ("near_boxes", ct.c_int64),
+                ("near_m2l_pairs", ct.c_int64), ("near_p2p_entries", ct.c_int64), ("near_macs_per_rhs", ct.c_double)]
 
 
 class SolveOpts(ct.Structure):

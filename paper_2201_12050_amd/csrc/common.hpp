@@ -75,6 +75,7 @@ struct MlStage {
   const MlTask* tk;    // device (all tasks of the plan)
   int n_tg;
   int out, accum;      // output buffer; 1: add to it
+  int max_rows;        // largest target
 };
 struct MlData {
   int levels = 0, order = 0, p = 0;
@@ -84,8 +85,15 @@ struct MlData {
   void* ops[2] = {nullptr, nullptr}; // operator pool FP64 / FP32 (P2M, L2P, M2M, L2L, M2L, P2P)
   size_t ops_elems = 0;
   std::vector<MlStage> stages;       // P2M, M2M per level, M2L, L2L per level, L2P + P2P
+  // S2M of the cell-level far field from the input in tree order: V0 with its columns in tree
+  // order at ops + oS, products over chunks of the elements into partial sums (buffer 4), summed
+  // in chunk order into the padded grid
+  MlStage s2m{};
+  long long oS = 0;
+  int s2m_chunks = 0;
   int boxes = 0, leaves = 0;
   long long m2l_pairs = 0, p2p_pairs = 0, p2p_entries = 0;
+  double macs_per_rhs = 0.0;         // complex multiply-adds of one application per RHS (cells inside)
 };
 // exact entries of one P2P block: rows = tree positions [te0, te0 + nt), columns [se0, se0 + ns)
 // of S_d (shift index sd as in MlTask), row-major at ops + off
@@ -192,7 +200,9 @@ bool ml_cell_fits(const std::vector<double>& geo, int n, const double pitch[3], 
 hipError_t ml_build(Plan& P, const std::vector<double>& geo, hipStream_t s);
 size_t ml_workspace_bytes_per_rhs(const Plan& P, int precision);
 template <typename T>
-hipError_t ml_apply(const Plan& P, int R, const void* x, void* y, void* y64, void* ws, bool accum, hipStream_t s);
+hipError_t ml_prepare(const Plan& P, int R, const void* x, void* ws, void* grid, hipStream_t s);
+template <typename T>
+hipError_t ml_apply(const Plan& P, int R, void* y, void* y64, void* ws, bool accum, hipStream_t s);
 // plan.hip helpers used by the multilevel build
 hipError_t plan_alloc(Plan& P, void** ptr, size_t bytes);
 void gauss_legendre_host(int q, std::vector<double>& x, std::vector<double>& w);

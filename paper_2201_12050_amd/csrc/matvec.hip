@@ -242,14 +242,22 @@ template <typename T>
 static char* ml_buffers(const Plan& P, int R, void* ws) {
   return near_partials<T>(P, R, ws) + align256((size_t)P.n_near * R * P.C * P.n * sizeof(cplx<T>));
 }
-// [1] the multilevel near field of an FMPBEM2 plan: y (+)= S~ x
+// [1] the multilevel near field of an FMPBEM2 plan: y (+)= S~ x (after ml_s2m)
 template <typename T>
-static hipError_t ml_stage(const Plan& P, int R, const void* x, void* y, void* y64, void* ws, bool accum,
-                           hipStream_t s) {
+static hipError_t ml_stage(const Plan& P, int R, void* y, void* y64, void* ws, bool accum, hipStream_t s) {
   const int prec = sizeof(T) == 8 ? 0 : 1;
   hipEvent_t ev = prof_begin(P, 1 + 6 * prec, s);
-  const hipError_t e = ml_apply<T>(P, R, x, y, y64, ml_buffers<T>(P, R, ws), accum, s);
+  const hipError_t e = ml_apply<T>(P, R, y, y64, ml_buffers<T>(P, R, ws), accum, s);
   prof_end(P, 1 + 6 * prec, ev, s);
+  return e;
+}
+// [0] of an FMPBEM2 plan: the input in tree order and the S2M into the padded grid
+template <typename T>
+static hipError_t ml_s2m(const Plan& P, int R, const void* x, void* ws, hipStream_t s) {
+  const int prec = sizeof(T) == 8 ? 0 : 1;
+  hipEvent_t ev = prof_begin(P, 0 + 6 * prec, s);
+  const hipError_t e = ml_prepare<T>(P, R, x, ml_buffers<T>(P, R, ws), ws, s);
+  prof_end(P, 0 + 6 * prec, ev, s);
   return e;
 }
 
@@ -289,7 +297,8 @@ void near_s2m_jobs(const Plan& P, int R, const void* x, void* ws, std::vector<Ne
     j.d2 = (short)P.near_off[3 * d + 2];
     out.push_back(j);
   }
-  if (P.n_far > 0) out.push_back(near_job(P, R, P.V0[prec], ws, P.p, n, x, SRC_X, DEST_GRID));
+  // (FMPBEM2 plans: the S2M runs in ml_s2m)
+  if (P.n_far > 0 && !P.ml) out.push_back(near_job(P, R, P.V0[prec], ws, P.p, n, x, SRC_X, DEST_GRID));
 }
 
 template <typename T>
@@ -317,7 +326,9 @@ static hipError_t matvec_overlap(const Plan& P, int R, const void* x, void* y, v
   if ((e = hipStreamWaitEvent(P.aux, P.ev_fork, 0))) return e;
   // far chain [2]-[4] (S2M counted with the DFT stage)
   hipEvent_t ev = prof_begin(P, 2 + 6 * prec, P.aux);
-  {
+  if (P.ml) {
+    if ((e = ml_prepare<T>(P, R, x, ml_buffers<T>(P, R, ws), ws, P.aux))) return e;
+  } else {
     std::vector<NearJob> s2m{near_job(P, R, P.V0[prec], ws, p, n, x, SRC_X, DEST_GRID)};
     const int shape = plan_shape<T>(P, 0, s2m, P.aux, tune);
     if ((e = near_launch<T>(s2m, P.aux, shape, 0))) return e;
@@ -336,7 +347,7 @@ static hipError_t matvec_overlap(const Plan& P, int R, const void* x, void* y, v
   {
     std::vector<NearJob> jobs;
     near_s2m_jobs<T>(P, R, x, ws, jobs);
-    jobs.pop_back();  // the S2M job ran on the second stream
+    if (!P.ml) jobs.pop_back();  // the S2M job ran on the second stream
     if (!jobs.empty()) {
       const int shape = plan_shape<T>(P, 0, jobs, s, tune);
       ev = prof_begin(P, 0 + 6 * prec, s);
@@ -351,7 +362,7 @@ static hipError_t matvec_overlap(const Plan& P, int R, const void* x, void* y, v
   ev = prof_begin(P, 5 + 6 * prec, s);
   e = near_launch<T>(jobs, s, shape, 1);
   prof_end(P, 5 + 6 * prec, ev, s);
-  if (e == hipSuccess && P.ml) e = ml_stage<T>(P, R, x, y, y64, ws, true, s);
+  if (e == hipSuccess && P.ml) e = ml_stage<T>(P, R, y, y64, ws, true, s);
   return e;
 }
 
@@ -378,7 +389,11 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
     }
   }
   prof_end(P, 0 + 6 * prec, ev, s);
-  if (P.n_far == 0 && P.ml) return ml_stage<T>(P, R, x, y, y64, ws, false, s);
+  if (P.ml) {
+    hipError_t e = ml_s2m<T>(P, R, x, ws, s);
+    if (e == hipSuccess && P.n_far == 0) e = ml_stage<T>(P, R, y, y64, ws, false, s);
+    if (e != hipSuccess || P.n_far == 0) return e;
+  }
   if (P.n_far == 0) {
     // [1] sum of the near partials
     ev = prof_begin(P, 1 + 6 * prec, s);
@@ -409,7 +424,7 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
     e = near_launch<T>(jobs, s, shape, 1);
   }
   prof_end(P, 5 + 6 * prec, ev, s);
-  if (e == hipSuccess && P.ml) e = ml_stage<T>(P, R, x, y, y64, ws, true, s);
+  if (e == hipSuccess && P.ml) e = ml_stage<T>(P, R, y, y64, ws, true, s);
   return e;
 }
 
@@ -438,8 +453,9 @@ static hipError_t matvec_group_t(const std::vector<GroupApply>& g, hipStream_t s
   for (size_t q = 0; q < g.size(); ++q) {
     const GroupApply& a = g[q];
     const Plan& P = *a.P;
+    if (P.ml && (e = ml_s2m<T>(P, a.R, a.x, a.ws, s)) != hipSuccess) return e;
     if (P.n_far == 0 && P.ml) {
-      if ((e = ml_stage<T>(P, a.R, a.x, a.y, a.y64, a.ws, false, s)) != hipSuccess) return e;
+      if ((e = ml_stage<T>(P, a.R, a.y, a.y64, a.ws, false, s)) != hipSuccess) return e;
     } else if (P.n_far == 0) {
       e = near_reduce_launch<T>(near_partials<T>(P, a.R, a.ws), P.n_near, (size_t)a.R * P.C * P.n, a.y, a.y64, s);
       if (e != hipSuccess) return e;
@@ -515,7 +531,7 @@ static hipError_t matvec_group_t(const std::vector<GroupApply>& g, hipStream_t s
   if ((e = near_launch<T>(l2t, s, shape, 1)) != hipSuccess) return e;
   for (size_t q : far) {
     const GroupApply& a = g[q];
-    if (a.P->ml && (e = ml_stage<T>(*a.P, a.R, a.x, a.y, a.y64, a.ws, true, s)) != hipSuccess) return e;
+    if (a.P->ml && (e = ml_stage<T>(*a.P, a.R, a.y, a.y64, a.ws, true, s)) != hipSuccess) return e;
   }
   return hipSuccess;
 }

@@ -44,65 +44,161 @@
 namespace fmbem {
 
 constexpr int kMlRows = 64;  // rows of one output block
-constexpr int kMlKc = 16;    // contraction chunk staged in LDS
 constexpr int kMlZeroShift = 13;
+constexpr int kMlS2mChunk = 256;  // elements per partial sum of the S2M
 
 // ---------------------------------------------------------------------------
 // device: block-sparse products
 // ---------------------------------------------------------------------------
 struct MlBufs {
-  void* b[4];  // 0: input in tree order, 1: moments, 2: locals, 3: output in tree order ([row][cols])
+  void* b[5];  // 0: input in tree order, 1: moments, 2: locals, 3: output in tree order ([row][cols]),
+               // 4: S2M partial sums
 };
 
+// *p when c, else 0 (component-wise, so that the value stays in registers)
+template <typename T>
+__device__ inline cplx<T> load_if(const cplx<T>* p, bool c) {
+  const T re = c ? p->x : T(0);
+  const T im = c ? p->y : T(0);
+  return mk<T>(re, im);
+}
+
 // out[out_row + i][col] (+)= sum over the target's tasks of A[i][k] src[src_row + k][col'] with
-// col' the column of cell c - d (zero outside the lattice); TC columns per workgroup
-template <typename T, int TC>
+// col' the column of cell c - d (zero outside the lattice).  The target's work is a list of items
+// (task, KW-wide contraction chunk; KW = 16 in FP32, 8 in FP64).  A wave covers 16 columns x 4
+// row groups (RPT rows each); the workgroup's 4 waves form WS streams of 4 / WS column slices,
+// stream j taking items j, j + WS, ...  Every round each stream stages its item (A chunk
+// ROWS x KW and source chunk KW x its columns) in its own LDS region, one barrier pair per round
+// for all streams, while the next item is loaded into registers.  The streams' partial sums are
+// added in stream order.
+template <typename T, int WS, int RPT>
 __global__ __launch_bounds__(256) void ml_kernel(const MlTarget* __restrict__ tg, const MlTask* __restrict__ tk,
                                                  const cplx<T>* __restrict__ ops, MlBufs B, int out_id, int accum,
                                                  int cols, int C, int M0, int M1, int M2) {
-  constexpr int RG = 256 / TC, RPT = kMlRows / RG;
-  __shared__ cplx<T> As[kMlKc][kMlRows + 1];
+  constexpr int SLICES = 4 / WS, ROWS = 4 * RPT, KW = sizeof(T) == 8 ? 8 : 16;
+  constexpr int SC = SLICES * 16;               // columns of a stream
+  constexpr int STG = (ROWS * KW + SLICES * 64 - 1) / (SLICES * 64);  // A entries staged per thread and item
+  constexpr int XSTG = KW * SC / (SLICES * 64);   // source entries staged per thread and item
+  __shared__ cplx<T> As[WS][KW][ROWS + 1];
+  __shared__ cplx<T> Xs[WS][KW][SC];
+  __shared__ cplx<T> red[WS > 1 ? ROWS * SC : 1];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int stream = wave / SLICES, slice = wave - stream * SLICES;
+  const int ts = slice * 64 + lane;  // thread index within the stream
+  const int cl = lane & 15, rg = lane >> 4;
   const MlTarget t = tg[blockIdx.x];
-  const int cl = threadIdx.x % TC, rg = threadIdx.x / TC;
-  const int col = blockIdx.y * TC + cl;
-  const bool cok = col < cols;
-  const int c = cok ? col % C : 0;
-  const int c0 = c % M0, c1 = (c / M0) % M1, c2 = c / (M0 * M1);
+  const int col0 = blockIdx.y * SC;
   const cplx<T> zero = mk<T>(0, 0);
+  // the columns this thread loads (fixed for every item): cc = (ts + s SLICES 64) mod SC
+  int lcol[XSTG], lc0[XSTG], lc1[XSTG], lc2[XSTG];
+#pragma unroll
+  for (int s = 0; s < XSTG; ++s) {
+    const int cc = (ts + s * SLICES * 64) % SC;
+    lcol[s] = col0 + cc;
+    const int c = lcol[s] < cols ? lcol[s] % C : 0;
+    lc0[s] = c % M0;
+    lc1[s] = (c / M0) % M1;
+    lc2[s] = c / (M0 * M1);
+  }
   cplx<T> acc[RPT];
 #pragma unroll
   for (int i = 0; i < RPT; ++i) acc[i] = zero;
-  for (int q = t.t0; q < t.t1; ++q) {
-    const MlTask w = tk[q];
-    const cplx<T>* __restrict__ src = reinterpret_cast<const cplx<T>*>(B.b[w.sel & 3]);
-    const int sh = w.sel >> 2;
-    const int d0 = sh % 3 - 1, d1 = (sh / 3) % 3 - 1, d2 = sh / 9 - 1;
-    const bool ok = cok && (unsigned)(c0 - d0) < (unsigned)M0 && (unsigned)(c1 - d1) < (unsigned)M1 &&
-                    (unsigned)(c2 - d2) < (unsigned)M2;
-    const int scol = col - (d0 + M0 * (d1 + M1 * d2));
-    const cplx<T>* __restrict__ A = ops + w.a_off;
-    for (int k0 = 0; k0 < w.ks; k0 += kMlKc) {
-      cplx<T> xv[kMlKc];
+  int q = t.t0, ch = stream, nch = 0;
+  if (q < t.t1) nch = (tk[q].ks + KW - 1) / KW;
+  // the cursor (task q, chunk ch) of this stream moves by `by` items
+#define ML_ADVANCE(by)                                     \
+  do {                                                     \
+    ch += (by);                                            \
+    while (q < t.t1 && ch >= nch) {                        \
+      ch -= nch;                                           \
+      ++q;                                                 \
+      nch = q < t.t1 ? (tk[q].ks + KW - 1) / KW : 0;       \
+    }                                                      \
+  } while (0)
+  // the cursor's item into registers (kn = 0: no item left)
+#define ML_LOAD()                                                                                        \
+  do {                                                                                                   \
+    kn = 0;                                                                                              \
+    if (q < t.t1) {                                                                                      \
+      const MlTask w = tk[q];                                                                            \
+      const int k0 = ch * KW;                                                                            \
+      kn = min(KW, w.ks - k0);                                                                           \
+      const cplx<T>* __restrict__ A = ops + w.a_off + k0;                                                \
+      _Pragma("unroll") for (int s = 0; s < STG; ++s) {                                                  \
+        const int e = ts + s * SLICES * 64;                                                              \
+        const int row = e / KW, kk = e % KW;                                                             \
+        an[s] = load_if<T>(A + (size_t)row * w.lda + kk, e < ROWS * KW && row < t.rows && kk < kn);    \
+      }                                                                                                  \
+      const int sh = w.sel >> 2;                                                                         \
+      const int d0 = sh % 3 - 1, d1 = (sh / 3) % 3 - 1, d2 = sh / 9 - 1;                                 \
+      const int dl = d0 + M0 * (d1 + M1 * d2);                                                           \
+      const cplx<T>* __restrict__ src =                                                                  \
+          reinterpret_cast<const cplx<T>*>(B.b[w.sel & 3]) + (size_t)(w.src_row + k0) * cols;            \
+      _Pragma("unroll") for (int s = 0; s < XSTG; ++s) {                                                 \
+        const int kk = (ts + s * SLICES * 64) / SC;                                                      \
+        const bool ok = lcol[s] < cols && kk < kn && (unsigned)(lc0[s] - d0) < (unsigned)M0 &&           \
+                        (unsigned)(lc1[s] - d1) < (unsigned)M1 && (unsigned)(lc2[s] - d2) < (unsigned)M2; \
+        xn[s] = load_if<T>(src + ((size_t)kk * cols + lcol[s] - dl), ok);                                \
+      }                                                                                                  \
+    }                                                                                                    \
+  } while (0)
+  ML_ADVANCE(0);
+  cplx<T> an[STG], xn[XSTG];
+  int kn = 0;  // contraction length of the loaded item (0: none)
+  int items = 0;
+  for (int qq = t.t0; qq < t.t1; ++qq) items += (tk[qq].ks + KW - 1) / KW;
+  const int rounds = (items + WS - 1) / WS;
+  ML_LOAD();
+  for (int r = 0; r < rounds; ++r) {
+    __syncthreads();
 #pragma unroll
-      for (int kk = 0; kk < kMlKc; ++kk)
-        xv[kk] = (ok && k0 + kk < w.ks) ? src[(size_t)(w.src_row + k0 + kk) * cols + scol] : zero;
-      __syncthreads();
-      for (int e = threadIdx.x; e < kMlRows * kMlKc; e += 256) {
-        const int row = e / kMlKc, kk = e - row * kMlKc;
-        As[kk][row] = (row < t.rows && k0 + kk < w.ks) ? A[(size_t)row * w.lda + k0 + kk] : zero;
+    for (int s = 0; s < STG; ++s) {
+      const int e = ts + s * SLICES * 64;
+      if (e < ROWS * KW) As[stream][e % KW][e / KW] = an[s];
+    }
+#pragma unroll
+    for (int s = 0; s < XSTG; ++s) {
+      const int e = ts + s * SLICES * 64;
+      Xs[stream][e / SC][e % SC] = xn[s];
+    }
+    const int kc = kn;
+    ML_ADVANCE(WS);
+    ML_LOAD();
+    __syncthreads();
+    if (kc > 0) {
+#pragma unroll
+      for (int kk = 0; kk < KW; ++kk) {
+        if (kk >= kc) break;  // uniform: the tail of the item's contraction
+        const cplx<T> xv = Xs[stream][kk][slice * 16 + cl];
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) cfma<T>(acc[i], As[stream][kk][rg + 4 * i], xv);
       }
-      __syncthreads();
-#pragma unroll
-      for (int kk = 0; kk < kMlKc; ++kk)
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) cfma<T>(acc[i], As[kk][rg + i * RG], xv[kk]);
     }
   }
-  if (!cok) return;
+#undef ML_LOAD
+#undef ML_ADVANCE
+  if constexpr (WS > 1) {
+    // stream j > 0 hands its partial sums to stream 0, one stream at a time (stream order)
+    for (int j = 1; j < WS; ++j) {
+      __syncthreads();
+      if (stream == j) {
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) red[(rg + 4 * i) * SC + slice * 16 + cl] = acc[i];
+      }
+      __syncthreads();
+      if (stream == 0) {
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) acc[i] = cadd<T>(acc[i], red[(rg + 4 * i) * SC + slice * 16 + cl]);
+      }
+    }
+    if (stream > 0) return;
+  }
+  const int col = col0 + slice * 16 + cl;
+  if (col >= cols) return;
   cplx<T>* __restrict__ out = reinterpret_cast<cplx<T>*>(B.b[out_id]);
 #pragma unroll
   for (int i = 0; i < RPT; ++i) {
-    const int row = rg + i * RG;
+    const int row = rg + 4 * i;
     if (row < t.rows) {
       cplx<T>* o = out + (size_t)(t.out_row + row) * cols + col;
       *o = accum ? cadd<T>(*o, acc[i]) : acc[i];
@@ -134,47 +230,117 @@ __global__ void ml_out_kernel(const cplx<T>* __restrict__ yt, const int* __restr
   }
 }
 
+// grid[bin(c)][r][i] = sum over chunks q (in order) of part[q p + i][r C + c]
+template <typename T>
+__global__ void ml_s2m_reduce_kernel(const cplx<T>* __restrict__ part, int chunks, int p, int cols, int C, int R,
+                                     int M0, int M1, int N0, int N1, cplx<T>* __restrict__ grid) {
+  const size_t total = (size_t)p * cols;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int col = (int)(idx / p), i = (int)(idx - (size_t)col * p);
+    cplx<T> s = mk<T>(0, 0);
+    for (int q = 0; q < chunks; ++q) s = cadd<T>(s, part[((size_t)q * p + i) * cols + col]);
+    const int r = col / C, c = col - r * C;
+    const int c0 = c % M0, c1 = (c / M0) % M1, c2 = c / (M0 * M1);
+    const size_t bin = (size_t)c0 + (size_t)N0 * (c1 + (size_t)N1 * c2);
+    grid[(bin * R + r) * p + i] = s;
+  }
+}
+
+// out[i][t] = in[i][perm[t]] (V0 with its columns in tree order)
+__global__ void ml_permute_kernel(const double2* __restrict__ in, const int* __restrict__ perm, int rows, int n,
+                                  double2* __restrict__ out) {
+  const size_t total = (size_t)rows * n;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx / n), t = (int)(idx - (size_t)i * n);
+    out[idx] = in[(size_t)i * n + perm[t]];
+  }
+}
+
 static size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 
 size_t ml_workspace_bytes_per_rhs(const Plan& P, int precision) {
   if (!P.ml) return 0;
   const size_t el = precision == FMBEM_FP32 ? sizeof(float2) : sizeof(double2);
-  return 2 * al256((size_t)P.n * P.C * el) + 2 * al256((size_t)P.ml->rows * P.C * el);
-}
-
-template <typename T, int TC>
-static void ml_stage_launch(const MlStage& st, const cplx<T>* ops, const MlBufs& B, int cols, const Plan& P,
-                            hipStream_t s) {
-  hipLaunchKernelGGL((ml_kernel<T, TC>), dim3(st.n_tg, (cols + TC - 1) / TC), dim3(256), 0, s, st.tg, st.tk, ops, B,
-                     st.out, st.accum, cols, P.C, P.grid[0], P.grid[1], P.grid[2]);
+  return 2 * al256((size_t)P.n * P.C * el) + 2 * al256((size_t)P.ml->rows * P.C * el) +
+         al256((size_t)P.ml->s2m_chunks * P.p * P.C * el);
 }
 
 template <typename T>
-hipError_t ml_apply(const Plan& P, int R, const void* x, void* y, void* y64, void* ws, bool accum, hipStream_t s) {
+static MlBufs ml_bufs(const Plan& P, int R, void* ws) {
   const MlData& M = *P.ml;
-  const int prec = sizeof(T) == 8 ? 0 : 1;
   const int cols = R * P.C;
   const size_t el = sizeof(cplx<T>);
   char* w = reinterpret_cast<char*>(ws);
   MlBufs B;
-  B.b[0] = w;
-  w += al256((size_t)P.n * cols * el);
-  B.b[1] = w;
-  w += al256((size_t)M.rows * cols * el);
-  B.b[2] = w;
-  w += al256((size_t)M.rows * cols * el);
-  B.b[3] = w;
+  const size_t sz[5] = {(size_t)P.n * cols, (size_t)M.rows * cols, (size_t)M.rows * cols, (size_t)P.n * cols,
+                        (size_t)M.s2m_chunks * P.p * cols};
+  for (int i = 0; i < 5; ++i) {
+    B.b[i] = w;
+    w += al256(sz[i] * el);
+  }
+  return B;
+}
+
+template <typename T, int WS, int RPT>
+static void ml_stage_launch(const MlStage& st, const cplx<T>* ops, const MlBufs& B, int cols, const Plan& P,
+                            hipStream_t s) {
+  const int tile = 16 * (4 / WS);
+  hipLaunchKernelGGL((ml_kernel<T, WS, RPT>), dim3(st.n_tg, (cols + tile - 1) / tile), dim3(256), 0, s, st.tg, st.tk,
+                     ops, B, st.out, st.accum, cols, P.C, P.grid[0], P.grid[1], P.grid[2]);
+}
+
+// waves per column slice by the column count, rows per lane by the stage's largest target
+template <typename T, int WS>
+static void ml_stage_rows(const MlStage& st, const cplx<T>* ops, const MlBufs& B, int cols, const Plan& P,
+                          hipStream_t s) {
+  if (st.max_rows <= 16) ml_stage_launch<T, WS, 4>(st, ops, B, cols, P, s);
+  else if (st.max_rows <= 32) ml_stage_launch<T, WS, 8>(st, ops, B, cols, P, s);
+  else ml_stage_launch<T, WS, 16>(st, ops, B, cols, P, s);
+}
+
+template <typename T>
+static void ml_stage_any(const MlStage& st, const cplx<T>* ops, const MlBufs& B, int cols, const Plan& P,
+                         hipStream_t s) {
+  if (st.n_tg == 0) return;
+  if (cols > 32) ml_stage_rows<T, 1>(st, ops, B, cols, P, s);
+  else if (cols > 16) ml_stage_rows<T, 2>(st, ops, B, cols, P, s);
+  else ml_stage_rows<T, 4>(st, ops, B, cols, P, s);
+}
+
+// the input in tree order and, with a far field, the S2M into the padded grid
+template <typename T>
+hipError_t ml_prepare(const Plan& P, int R, const void* x, void* ws, void* grid, hipStream_t s) {
+  const MlData& M = *P.ml;
+  const int prec = sizeof(T) == 8 ? 0 : 1;
+  const int cols = R * P.C;
+  const MlBufs B = ml_bufs<T>(P, R, ws);
   const size_t total = (size_t)P.n * cols;
   const unsigned g = (unsigned)std::min<size_t>((total + 255) / 256, 8192);
   hipLaunchKernelGGL(ml_in_kernel<T>, dim3(g), dim3(256), 0, s, reinterpret_cast<const cplx<T>*>(x), M.pos, P.n,
                      total, cols, reinterpret_cast<cplx<T>*>(B.b[0]));
-  const cplx<T>* ops = reinterpret_cast<const cplx<T>*>(M.ops[prec]);
-  for (const MlStage& st : M.stages) {
-    if (st.n_tg == 0) continue;
-    if (cols >= 64) ml_stage_launch<T, 64>(st, ops, B, cols, P, s);
-    else if (cols >= 32) ml_stage_launch<T, 32>(st, ops, B, cols, P, s);
-    else ml_stage_launch<T, 16>(st, ops, B, cols, P, s);
+  if (P.n_far > 0) {
+    ml_stage_any<T>(M.s2m, reinterpret_cast<const cplx<T>*>(M.ops[prec]), B, cols, P, s);
+    const size_t pt = (size_t)P.p * cols;
+    hipLaunchKernelGGL(ml_s2m_reduce_kernel<T>, dim3((unsigned)std::min<size_t>((pt + 255) / 256, 4096)), dim3(256),
+                       0, s, reinterpret_cast<const cplx<T>*>(B.b[4]), M.s2m_chunks, P.p, cols, P.C, R, P.grid[0],
+                       P.grid[1], P.fft[0], P.fft[1], reinterpret_cast<cplx<T>*>(grid));
   }
+  return hipGetLastError();
+}
+
+// the near field from the input in tree order (ml_prepare earlier on the stream): y (+)= S~ x
+template <typename T>
+hipError_t ml_apply(const Plan& P, int R, void* y, void* y64, void* ws, bool accum, hipStream_t s) {
+  const MlData& M = *P.ml;
+  const int prec = sizeof(T) == 8 ? 0 : 1;
+  const int cols = R * P.C;
+  const MlBufs B = ml_bufs<T>(P, R, ws);
+  const size_t total = (size_t)P.n * cols;
+  const unsigned g = (unsigned)std::min<size_t>((total + 255) / 256, 8192);
+  const cplx<T>* ops = reinterpret_cast<const cplx<T>*>(M.ops[prec]);
+  for (const MlStage& st : M.stages) ml_stage_any<T>(st, ops, B, cols, P, s);
   if (y64)
     hipLaunchKernelGGL((ml_out_kernel<T, double>), dim3(g), dim3(256), 0, s,
                        reinterpret_cast<const cplx<T>*>(B.b[3]), M.pos, P.n, total, cols, accum ? 1 : 0,
@@ -185,8 +351,10 @@ hipError_t ml_apply(const Plan& P, int R, const void* x, void* y, void* y64, voi
   return hipGetLastError();
 }
 
-template hipError_t ml_apply<double>(const Plan&, int, const void*, void*, void*, void*, bool, hipStream_t);
-template hipError_t ml_apply<float>(const Plan&, int, const void*, void*, void*, void*, bool, hipStream_t);
+template hipError_t ml_prepare<double>(const Plan&, int, const void*, void*, void*, hipStream_t);
+template hipError_t ml_prepare<float>(const Plan&, int, const void*, void*, void*, hipStream_t);
+template hipError_t ml_apply<double>(const Plan&, int, void*, void*, void*, bool, hipStream_t);
+template hipError_t ml_apply<float>(const Plan&, int, void*, void*, void*, bool, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // host: translation matrices
@@ -445,7 +613,27 @@ hipError_t ml_build(Plan& P, const std::vector<double>& geo, hipStream_t s) {
     pe += (long long)(A.e1 - A.e0) * (Bx.e1 - Bx.e0);
   }
   M.p2p_entries = pe;
-  M.ops_elems = (size_t)(oP + pe);
+  M.oS = oP + pe;
+  M.ops_elems = (size_t)(M.oS + (long long)P.p * n);
+  M.s2m_chunks = (n + kMlS2mChunk - 1) / kMlS2mChunk;
+  // algorithmic work per RHS: every stage over the cells whose source cell lies in the lattice
+  {
+    auto inside = [&](int sd) {
+      const int d[3] = {sd % 3 - 1, (sd / 3) % 3 - 1, sd / 9 - 1};
+      double c = 1.0;
+      for (int a = 0; a < 3; ++a) c *= P.grid[a] - std::abs(d[a]);
+      return c;
+    };
+    double macs = 2.0 * (double)p * n * P.C;  // P2M and L2P
+    for (int l = 2; l <= L; ++l) macs += 2.0 * (double)lv[l].size() * pp * P.C;  // M2M and L2L
+    for (const Pair& q : m2l) macs += (double)pp * inside(q.sd);
+    for (size_t i = 0; i < p2p.size(); ++i) {
+      const Box& A = lv[L][p2p[i].a];
+      const Box& Bx = lv[L][p2p[i].b];
+      macs += (double)(A.e1 - A.e0) * (Bx.e1 - Bx.e0) * inside(p2p[i].sd);
+    }
+    M.macs_per_rhs = macs;
+  }
   // level scalings s_l^n
   std::vector<std::vector<double>> sig(L + 1, std::vector<double>(nt + 1)), isig = sig;
   for (int l = 0; l <= L; ++l) {
@@ -490,13 +678,16 @@ hipError_t ml_build(Plan& P, const std::vector<double>& geo, hipStream_t s) {
   std::vector<MlTask> tk;
   std::vector<std::pair<int, int>> stage_range;  // first target, count
   std::vector<std::pair<int, int>> stage_mode;   // out buffer, accumulate
+  std::vector<int> stage_rows;
   auto begin_stage = [&](int out, int accum) {
     stage_range.push_back({(int)tg.size(), 0});
     stage_mode.push_back({out, accum});
+    stage_rows.push_back(0);
   };
   auto add_target = [&](int out_row, int rows) {
     tg.push_back(MlTarget{out_row, rows, (int)tk.size(), (int)tk.size()});
     ++stage_range.back().second;
+    stage_rows.back() = std::max(stage_rows.back(), rows);
   };
   auto add_task = [&](long long a_off, int lda, int ks, int src_row, int buf, int sd) {
     tk.push_back(MlTask{a_off, lda, ks, src_row, buf | (sd << 2)});
@@ -565,6 +756,15 @@ hipError_t ml_build(Plan& P, const std::vector<double>& geo, hipStream_t s) {
       }
     }
   }
+  // S2M of the cell-level far field (kept last; launched by ml_prepare): partial sums over element
+  // chunks into buffer 4, rows q p + i
+  begin_stage(4, 0);
+  for (int r0 = 0; r0 < P.p; r0 += kMlRows)
+    for (int q = 0; q < M.s2m_chunks; ++q) {
+      const int k0 = q * kMlS2mChunk;
+      add_target(q * P.p + r0, std::min(kMlRows, P.p - r0));
+      add_task(M.oS + (long long)r0 * n + k0, n, std::min(kMlS2mChunk, n - k0), k0, 0, kMlZeroShift);
+    }
   // device arrays
   hipError_t e;
   MlTarget* d_tg = nullptr;
@@ -582,9 +782,11 @@ hipError_t ml_build(Plan& P, const std::vector<double>& geo, hipStream_t s) {
   double2* ops = reinterpret_cast<double2*>(M.ops[0]);
   hipMemcpyAsync(ops + oM, hT.data(), hT.size() * sizeof(double2), hipMemcpyHostToDevice, s);
   M.stages.clear();
-  for (size_t i = 0; i < stage_range.size(); ++i)
+  for (size_t i = 0; i + 1 < stage_range.size(); ++i)
     M.stages.push_back(MlStage{d_tg + stage_range[i].first, d_tk, stage_range[i].second, stage_mode[i].first,
-                               stage_mode[i].second});
+                               stage_mode[i].second, stage_rows[i]});
+  M.s2m = MlStage{d_tg + stage_range.back().first, d_tk, stage_range.back().second, stage_mode.back().first,
+                  stage_mode.back().second, stage_rows.back()};
   // leaf P2M / L2P about the leaf centres (device), and the exact P2P entries
   std::vector<double> cen((size_t)n * 3);
   for (int e2 = 0; e2 < n; ++e2)
@@ -599,6 +801,11 @@ hipError_t ml_build(Plan& P, const std::vector<double>& geo, hipStream_t s) {
     blocks[i] = P2pBlock{oP + poff[i], A.e0, A.e1 - A.e0, Bx.e0, Bx.e1 - Bx.e0, p2p[i].sd};
   }
   e = ml_assemble_launch(P, nt, cen, isig[L], blocks, pe, ops, oV, oU, s);
+  if (!e) {
+    hipLaunchKernelGGL(ml_permute_kernel, dim3(4096), dim3(256), 0, s, reinterpret_cast<const double2*>(P.V0[0]),
+                       M.perm, P.p, n, ops + M.oS);
+    e = hipGetLastError();
+  }
   if (!e && want32) e = cast_launch(ops, reinterpret_cast<float2*>(M.ops[1]), M.ops_elems, s);
   // the host tables must outlive their copies, also when a step failed
   const hipError_t e2 = hipStreamSynchronize(s);

@@ -1330,6 +1330,12 @@ extern "C" fmbem_status fmbem_plan_query(fmbem_plan plan, fmbem_plan_info* out) 
   out->workspace_bytes_per_rhs[0] = matvec_workspace_bytes_per_rhs(P, FMBEM_FP64);
   out->workspace_bytes_per_rhs[1] = matvec_workspace_bytes_per_rhs(P, FMBEM_FP32);
   out->scale = P.scale;
+  out->near_levels = P.ml ? P.ml->levels : 0;
+  out->near_order = P.ml ? P.ml->order : 0;
+  out->near_boxes = P.ml ? P.ml->boxes : 0;
+  out->near_m2l_pairs = P.ml ? P.ml->m2l_pairs : 0;
+  out->near_p2p_entries = P.ml ? P.ml->p2p_entries : 0;
+  out->near_macs_per_rhs = P.ml ? P.ml->macs_per_rhs : 0.0;
   return FMBEM_OK;
 }
 

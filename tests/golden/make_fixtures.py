@@ -3,7 +3,7 @@
 Every value here comes from the FP64 CPU oracle (``oracle/``) applied to the seeded
 synthetic inputs of ``workloads/``; nothing is read from the HIP library.
 
-    python tests/golden/make_fixtures.py [grid16_rows] [barrier_rows] [grid16_solution]
+    python tests/golden/make_fixtures.py [grid16_rows] [barrier_rows] [large_cell_rows] [grid16_solution]
 
 Fixtures (NumPy ``.npz``, no pickles):
   grid16_rows.npz        O2 operator (Sec. 3.2 eq. (2dPeriodicFMM), App. A) applied to a
@@ -12,6 +12,11 @@ Fixtures (NumPy ``.npz``, no pickles):
                          interior cells, each computed alone (``operator.sampled_apply``).
   barrier_rows_<f>.npz   the same on the 40 x 2 x 8 lattice of open tube cells at 100 Hz
                          (n_t = 10) and 2 kHz (n_t = 14), 128 rows.
+  large_cell_rows.npz    the FMPBEM2 operator (Sec. 3.3: near blocks by the multilevel FMM
+                         of ``multilevel.sampled_apply2``, 4 levels, n_t,near = 4) applied
+                         to a seeded random vector on the 4 x 4 lattice of 20480-triangle
+                         spheres at 1 kHz, n_t = 10: 24 rows in corner, edge and interior
+                         cells.
   grid16_solution.npz    solution of the O2 system for the plane-wave right-hand side
                          (Sec. 2.1 eq. (bm), Sec. 4.1 eq. (planewave)) of the same
                          lattice, by the oracle's GMRES(100) to a relative residual of
@@ -31,8 +36,8 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-from oracle import bem, operator as op, solve  # noqa: E402
-from workloads import config_grid16, config_barrier_r4b  # noqa: E402
+from oracle import bem, operator as op, solve, multilevel as ml  # noqa: E402
+from workloads import config_grid16, config_barrier_r4b, config_large_cell  # noqa: E402
 from workloads.rng import generator, random_complex  # noqa: E402
 
 # seeds of the random input vectors and of the sampled rows
@@ -87,6 +92,22 @@ def barrier_rows(freq_index):
              order=w.order, dofs=dofs, y=y[0])
 
 
+LARGE_X_SEED = 2203
+LARGE_ROW_SEED = 22031
+LARGE_CELLS = [(0, 0), (3, 3), (0, 3), (1, 0), (3, 2), (1, 1), (2, 2), (2, 1)]
+
+
+def large_cell_rows():
+    w = config_large_cell()
+    n = w.n_dof_cell
+    x = random_complex((1, w.lattice.n_cells, n), LARGE_X_SEED)
+    dofs = sampled_dofs(w.lattice.grid, n, LARGE_CELLS, 3, LARGE_ROW_SEED)
+    lv, no = w.extra["near_levels"], w.extra["near_order"]
+    y = ml.sampled_apply2(w.vertices, w.triangles, w.lattice, w.k, w.order, -1j / w.k, lv, no, x, dofs)
+    np.savez(os.path.join(HERE, "large_cell_rows.npz"), x_seed=LARGE_X_SEED, dofs=dofs, near_levels=lv,
+             near_order=no, y=y[0])
+
+
 def grid16_solution(tol=1e-12):
     w = config_grid16()
     n = w.n_dof_cell
@@ -104,7 +125,7 @@ def grid16_solution(tol=1e-12):
 
 
 if __name__ == "__main__":
-    want = sys.argv[1:] or ["grid16_rows", "barrier_rows", "grid16_solution"]
+    want = sys.argv[1:] or ["grid16_rows", "barrier_rows", "large_cell_rows", "grid16_solution"]
     for name in want:
         t0 = time.time()
         if name == "grid16_rows":
@@ -112,6 +133,8 @@ if __name__ == "__main__":
         elif name == "barrier_rows":
             barrier_rows(0)    # 100 Hz, n_t = 10
             barrier_rows(95)   # 2 kHz, n_t = 14
+        elif name == "large_cell_rows":
+            large_cell_rows()
         elif name == "grid16_solution":
             grid16_solution()
         else:

@@ -9,9 +9,9 @@ own from these raw inputs.
 """
 from .meshes import icosphere, tube_segment, mesh_is_closed
 from .configs import (Lattice, Workload, config_tiny, config_grid16, config_grid16_ground, config_batched_grids,
-                      config_barrier_r4b, config_barrier_ground, barrier_receivers, serving_stream, SOUND_SPEED, DENSITY)
+                      config_large_cell, config_barrier_r4b, config_barrier_ground, barrier_receivers, serving_stream, SOUND_SPEED, DENSITY)
 from .rng import unit_directions, random_complex
 
 __all__ = ["icosphere", "tube_segment", "mesh_is_closed", "Lattice", "Workload",
-           "config_tiny", "config_grid16", "config_grid16_ground", "config_batched_grids", "config_barrier_r4b", "config_barrier_ground", "barrier_receivers",
+           "config_tiny", "config_grid16", "config_grid16_ground", "config_batched_grids", "config_large_cell", "config_barrier_r4b", "config_barrier_ground", "barrier_receivers",
            "serving_stream", "unit_directions", "random_complex", "SOUND_SPEED", "DENSITY"]

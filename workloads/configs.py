@@ -97,6 +97,18 @@ def config_grid16(grid=(16, 16, 1), level: int = 3, order: int = 10) -> Workload
                     plane_waves=np.array([[math.cos(a), math.sin(a), 0.0]]))
 
 
+def config_large_cell(levels: int = 4, near_order: int = 4) -> Workload:
+    """Large unit cells for the multilevel near field (Sec. 3.3): 4x4 lattice of icosphere-level-5
+    spheres (20480 triangles, r = 0.1 m), pitch 0.3 m, 1 kHz, n_t = 10, one plane wave at 30
+    degrees azimuth (N = 327,680, the size of the 16x16 lattice with 16 times larger cells);
+    the subdivision of the cell box (levels) and n_t,near in ``extra``."""
+    v, t = icosphere(5, 0.1)
+    a = math.radians(30.0)
+    return Workload("cells4x4_l5_1kHz", v, t, Lattice((4, 4, 1), (0.3, 0.3, 0.3)), 1000.0, 10, "bm",
+                    plane_waves=np.array([[math.cos(a), math.sin(a), 0.0]]),
+                    extra={"near_levels": levels, "near_order": near_order})
+
+
 def config_grid16_ground(plane_z: float = -0.15, reflection: complex = 1.0) -> Workload:
     """The 16x16 sphere lattice above a plane z = plane_z (sound-hard for reflection 1), one
     plane wave at 30 degrees azimuth travelling 30 degrees downwards, toward the plane."""
