@@ -76,6 +76,10 @@ struct MlStage {
   int n_tg;
   int out, accum;      // output buffer; 1: add to it
   int max_rows;        // largest target
+  // split > 1: each target's tasks are divided over `split` workgroups that write the partial
+  // buffer 5 (slot s at rows s nrows + out_row - row0); the slots are then added in slot order into
+  // rows [row0, row0 + nrows) of buffer `dest` (added to it when dest_accum)
+  int split = 1, dest = 0, dest_accum = 0, row0 = 0, nrows = 0;
 };
 struct MlData {
   int levels = 0, order = 0, p = 0;
@@ -91,6 +95,7 @@ struct MlData {
   MlStage s2m{};
   long long oS = 0;
   int s2m_chunks = 0;
+  size_t part_rows = 0;              // rows of the partial buffer of split stages (split x nrows, largest)
   int boxes = 0, leaves = 0;
   long long m2l_pairs = 0, p2p_pairs = 0, p2p_entries = 0;
   double macs_per_rhs = 0.0;         // complex multiply-adds of one application per RHS (cells inside)

@@ -51,8 +51,8 @@ constexpr int kMlS2mChunk = 256;  // elements per partial sum of the S2M
 // device: block-sparse products
 // ---------------------------------------------------------------------------
 struct MlBufs {
-  void* b[5];  // 0: input in tree order, 1: moments, 2: locals, 3: output in tree order ([row][cols]),
-               // 4: S2M partial sums
+  void* b[6];  // 0: input in tree order, 1: moments, 2: locals, 3: output in tree order ([row][cols]),
+               // 4: S2M partial sums, 5: partial sums of split stages
 };
 
 // *p when c, else 0 (component-wise, so that the value stays in registers)
@@ -65,7 +65,7 @@ __device__ inline cplx<T> load_if(const cplx<T>* p, bool c) {
 
 // out[out_row + i][col] (+)= sum over the target's tasks of A[i][k] src[src_row + k][col'] with
 // col' the column of cell c - d (zero outside the lattice).  The target's work is a list of items
-// (task, KW-wide contraction chunk; KW = 16 in FP32, 8 in FP64).  A wave covers 16 columns x 4
+// (task, KW = 8-wide contraction chunk).  A wave covers 16 columns x 4
 // row groups (RPT rows each); the workgroup's 4 waves form WS streams of 4 / WS column slices,
 // stream j taking items j, j + WS, ...  Every round each stream stages its item (A chunk
 // ROWS x KW and source chunk KW x its columns) in its own LDS region, one barrier pair per round
@@ -75,13 +75,16 @@ template <typename T, int WS, int RPT>
 __global__ __launch_bounds__(256) void ml_kernel(const MlTarget* __restrict__ tg, const MlTask* __restrict__ tk,
                                                  const cplx<T>* __restrict__ ops, MlBufs B, int out_id, int accum,
                                                  int cols, int C, int M0, int M1, int M2) {
-  constexpr int SLICES = 4 / WS, ROWS = 4 * RPT, KW = sizeof(T) == 8 ? 8 : 16;
+  constexpr int SLICES = 4 / WS, ROWS = 4 * RPT, KW = 8;
   constexpr int SC = SLICES * 16;               // columns of a stream
   constexpr int STG = (ROWS * KW + SLICES * 64 - 1) / (SLICES * 64);  // A entries staged per thread and item
   constexpr int XSTG = KW * SC / (SLICES * 64);   // source entries staged per thread and item
   __shared__ cplx<T> As[WS][KW][ROWS + 1];
   __shared__ cplx<T> Xs[WS][KW][SC];
-  __shared__ cplx<T> red[WS > 1 ? ROWS * SC : 1];
+  // the streams' reduction area: the staging area when it is large enough
+  constexpr bool kAlias = ROWS * SC <= WS * KW * (ROWS + 1);
+  __shared__ cplx<T> red_own[(WS > 1 && !kAlias) ? ROWS * SC : 1];
+  cplx<T>* red = kAlias ? &As[0][0][0] : red_own;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int stream = wave / SLICES, slice = wave - stream * SLICES;
   const int ts = slice * 64 + lane;  // thread index within the stream
@@ -230,6 +233,17 @@ __global__ void ml_out_kernel(const cplx<T>* __restrict__ yt, const int* __restr
   }
 }
 
+// out[i] (+)= sum over slots s (in order) of part[s slot + i], i < slot
+template <typename T>
+__global__ void ml_reduce_kernel(const cplx<T>* __restrict__ part, int S, size_t slot, int accum,
+                                 cplx<T>* __restrict__ out) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < slot; i += (size_t)gridDim.x * blockDim.x) {
+    cplx<T> s = accum ? out[i] : mk<T>(0, 0);
+    for (int q = 0; q < S; ++q) s = cadd<T>(s, part[(size_t)q * slot + i]);
+    out[i] = s;
+  }
+}
+
 // grid[bin(c)][r][i] = sum over chunks q (in order) of part[q p + i][r C + c]
 template <typename T>
 __global__ void ml_s2m_reduce_kernel(const cplx<T>* __restrict__ part, int chunks, int p, int cols, int C, int R,
@@ -264,7 +278,7 @@ size_t ml_workspace_bytes_per_rhs(const Plan& P, int precision) {
   if (!P.ml) return 0;
   const size_t el = precision == FMBEM_FP32 ? sizeof(float2) : sizeof(double2);
   return 2 * al256((size_t)P.n * P.C * el) + 2 * al256((size_t)P.ml->rows * P.C * el) +
-         al256((size_t)P.ml->s2m_chunks * P.p * P.C * el);
+         al256((size_t)P.ml->s2m_chunks * P.p * P.C * el) + al256(P.ml->part_rows * P.C * el);
 }
 
 template <typename T>
@@ -274,9 +288,9 @@ static MlBufs ml_bufs(const Plan& P, int R, void* ws) {
   const size_t el = sizeof(cplx<T>);
   char* w = reinterpret_cast<char*>(ws);
   MlBufs B;
-  const size_t sz[5] = {(size_t)P.n * cols, (size_t)M.rows * cols, (size_t)M.rows * cols, (size_t)P.n * cols,
-                        (size_t)M.s2m_chunks * P.p * cols};
-  for (int i = 0; i < 5; ++i) {
+  const size_t sz[6] = {(size_t)P.n * cols, (size_t)M.rows * cols, (size_t)M.rows * cols, (size_t)P.n * cols,
+                        (size_t)M.s2m_chunks * P.p * cols, M.part_rows * cols};
+  for (int i = 0; i < 6; ++i) {
     B.b[i] = w;
     w += al256(sz[i] * el);
   }
@@ -307,6 +321,12 @@ static void ml_stage_any(const MlStage& st, const cplx<T>* ops, const MlBufs& B,
   if (cols > 32) ml_stage_rows<T, 1>(st, ops, B, cols, P, s);
   else if (cols > 16) ml_stage_rows<T, 2>(st, ops, B, cols, P, s);
   else ml_stage_rows<T, 4>(st, ops, B, cols, P, s);
+  if (st.split > 1) {
+    const size_t slot = (size_t)st.nrows * cols;
+    hipLaunchKernelGGL(ml_reduce_kernel<T>, dim3((unsigned)std::min<size_t>((slot + 255) / 256, 4096)), dim3(256), 0,
+                       s, reinterpret_cast<const cplx<T>*>(B.b[5]), st.split, slot, st.dest_accum,
+                       reinterpret_cast<cplx<T>*>(B.b[st.dest]) + (size_t)st.row0 * cols);
+  }
 }
 
 // the input in tree order and, with a far field, the S2M into the padded grid
@@ -765,6 +785,49 @@ hipError_t ml_build(Plan& P, const std::vector<double>& geo, hipStream_t s) {
       add_target(q * P.p + r0, std::min(kMlRows, P.p - r0));
       add_task(M.oS + (long long)r0 * n + k0, n, std::min(kMlS2mChunk, n - k0), k0, 0, kMlZeroShift);
     }
+  // stages whose targets carry many tasks (M2L, L2P + P2P) are divided over more workgroups when
+  // the targets alone would leave the CUs short of work (columns of a one-RHS application)
+  std::vector<std::array<int, 5>> split_of(stage_range.size(), {1, 0, 0, 0, 0});  // split, dest, accum, row0, nrows
+  auto split_stage = [&](size_t si, int row0s, int nrows) {
+    const int first = stage_range[si].first, count = stage_range[si].second;
+    if (count == 0) return;
+    const int tile = P.C > 32 ? 64 : (P.C > 16 ? 32 : 16);
+    const long long wgs = (long long)count * ((P.C + tile - 1) / tile);
+    long long tasks = 0;
+    for (int i = first; i < first + count; ++i) tasks += tg[i].t1 - tg[i].t0;
+    int S = (int)std::min<long long>(8, (2048 + wgs - 1) / wgs);
+    S = (int)std::min<long long>(S, std::max<long long>(1, tasks / (4LL * count)));
+    if (S <= 1) return;
+    const int nfirst = (int)tg.size();
+    for (int s2 = 0; s2 < S; ++s2)
+      for (int i = first; i < first + count; ++i) {
+        const MlTarget x = tg[i];
+        // tasks of slot s2: a contiguous share of the target's contraction length
+        long long total = 0;
+        for (int q = x.t0; q < x.t1; ++q) total += tk[q].ks;
+        long long acc = 0;
+        int a = x.t0, b = x.t0;
+        for (int q = x.t0; q < x.t1; ++q) {
+          const long long mid = acc + tk[q].ks / 2;  // a task goes to the slot holding its middle
+          const int owner = total > 0 ? (int)std::min<long long>(S - 1, mid * S / total) : 0;
+          if (owner < s2) a = q + 1;
+          if (owner <= s2) b = q + 1;
+          acc += tk[q].ks;
+        }
+        if (b < a) b = a;
+        tg.push_back(MlTarget{s2 * nrows + (x.out_row - row0s), x.rows, a, b});
+      }
+    stage_range[si] = {nfirst, S * count};
+    split_of[si] = {S, stage_mode[si].first, stage_mode[si].second, row0s, nrows};
+    stage_mode[si] = {5, 0};
+    M.part_rows = std::max(M.part_rows, (size_t)S * nrows);
+  };
+  {
+    // stage order: P2M, M2M x (L - 1), M2L, L2L x (L - 1), L2P + P2P, S2M
+    const size_t m2l_stage = 1 + (size_t)(L - 1), l2p_stage = m2l_stage + 1 + (size_t)(L - 1);
+    split_stage(m2l_stage, 0, M.rows);
+    split_stage(l2p_stage, 0, n);
+  }
   // device arrays
   hipError_t e;
   MlTarget* d_tg = nullptr;
@@ -784,7 +847,8 @@ hipError_t ml_build(Plan& P, const std::vector<double>& geo, hipStream_t s) {
   M.stages.clear();
   for (size_t i = 0; i + 1 < stage_range.size(); ++i)
     M.stages.push_back(MlStage{d_tg + stage_range[i].first, d_tk, stage_range[i].second, stage_mode[i].first,
-                               stage_mode[i].second, stage_rows[i]});
+                               stage_mode[i].second, stage_rows[i], split_of[i][0], split_of[i][1], split_of[i][2],
+                               split_of[i][3], split_of[i][4]});
   M.s2m = MlStage{d_tg + stage_range.back().first, d_tk, stage_range.back().second, stage_mode.back().first,
                   stage_mode.back().second, stage_rows.back()};
   // leaf P2M / L2P about the leaf centres (device), and the exact P2P entries
