@@ -39,8 +39,30 @@ size_t matvec_workspace_bytes_per_rhs(const Plan& P, int precision) {
   return b;
 }
 
+// completed marks: their times added to the stage totals, their events back in the pool
+static void prof_harvest(const Plan& P) {
+  size_t keep = 0;
+  for (size_t i = 0; i < P.prof.marks.size(); ++i) {
+    auto& m = P.prof.marks[i];
+    float t = 0.f;
+    if (hipEventQuery(m.second.second) == hipSuccess &&
+        hipEventElapsedTime(&t, m.second.first, m.second.second) == hipSuccess) {
+      P.prof.ms[m.first] += t;
+      P.prof.count[m.first] += 1;
+      P.prof.pool.push_back(m.second.first);
+      P.prof.pool.push_back(m.second.second);
+    } else {
+      P.prof.marks[keep++] = m;
+    }
+  }
+  P.prof.marks.resize(keep);
+}
+
+// events come from the pool (filled when profiling starts and by completed marks), so that
+// recording creates none while an application is timed
 static hipEvent_t prof_record(const Plan& P, hipStream_t s) {
   hipEvent_t e = nullptr;
+  if (P.prof.pool.empty()) prof_harvest(P);
   if (!P.prof.pool.empty()) {
     e = P.prof.pool.back();
     P.prof.pool.pop_back();
@@ -703,6 +725,11 @@ extern "C" fmbem_status fmbem_plan_profile(fmbem_plan plan, uint32_t stage_mask,
     for (int i = 0; i < FMBEM_N_STAGES; ++i) {
       P.prof.ms[i] = 0;
       P.prof.count[i] = 0;
+    }
+    while (P.prof.pool.size() < 256) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) break;
+      P.prof.pool.push_back(e);
     }
   }
   P.prof.mask = stage_mask;

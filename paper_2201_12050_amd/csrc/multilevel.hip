@@ -253,6 +253,7 @@ __global__ void ml_s2m_reduce_kernel(const cplx<T>* __restrict__ part, int chunk
        idx += (size_t)gridDim.x * blockDim.x) {
     const int col = (int)(idx / p), i = (int)(idx - (size_t)col * p);
     cplx<T> s = mk<T>(0, 0);
+#pragma unroll 16
     for (int q = 0; q < chunks; ++q) s = cadd<T>(s, part[((size_t)q * p + i) * cols + col]);
     const int r = col / C, c = col - r * C;
     const int c0 = c % M0, c1 = (c / M0) % M1, c2 = c / (M0 * M1);
@@ -343,7 +344,7 @@ hipError_t ml_prepare(const Plan& P, int R, const void* x, void* ws, void* grid,
   if (P.n_far > 0) {
     ml_stage_any<T>(M.s2m, reinterpret_cast<const cplx<T>*>(M.ops[prec]), B, cols, P, s);
     const size_t pt = (size_t)P.p * cols;
-    hipLaunchKernelGGL(ml_s2m_reduce_kernel<T>, dim3((unsigned)std::min<size_t>((pt + 255) / 256, 4096)), dim3(256),
+    hipLaunchKernelGGL(ml_s2m_reduce_kernel<T>, dim3((unsigned)std::min<size_t>((pt + 63) / 64, 16384)), dim3(64),
                        0, s, reinterpret_cast<const cplx<T>*>(B.b[4]), M.s2m_chunks, P.p, cols, P.C, R, P.grid[0],
                        P.grid[1], P.fft[0], P.fft[1], reinterpret_cast<cplx<T>*>(grid));
   }

@@ -38,7 +38,7 @@ __device__ inline double wave_sum(double v) {
 
 // part[r][i][blk] = sum_{n in block} conj(V_i[r][n]) w[r][n]; workgroup (bx, by, r) of a grid
 // (nblk blocks, vector groups of 8, R)
-__device__ inline void mdot_body(const double2* __restrict__ V, size_t vstride, const double2* __restrict__ w,
+__device__ __attribute__((always_inline)) inline void mdot_body(const double2* __restrict__ V, size_t vstride, const double2* __restrict__ w,
                                  size_t N, int J, double2* __restrict__ part, const int* __restrict__ flag, int bx,
                                  int by, int r, int nblk) {
   __shared__ double2 red[kDotThreads / 64][kDotVec];
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kDotThreads) void mdot_kernel(const double2* __rest
 
 // one wave per (r, i) sums the block partials s; mode 0: h = s; mode 2: h = sqrt(Re s);
 // mode 3: h2 = s and h += s (second Gram-Schmidt pass)
-__device__ inline void finish_body(const double2* __restrict__ part, int nblk, int R, int J, double2* __restrict__ h,
+__device__ __attribute__((always_inline)) inline void finish_body(const double2* __restrict__ part, int nblk, int R, int J, double2* __restrict__ h,
                                    int hstride, int mode, double2* __restrict__ h2, const int* __restrict__ flag,
                                    int bx) {
   const int t = bx * (blockDim.x / 64) + (threadIdx.x >> 6);
@@ -131,7 +131,7 @@ __global__ void mdot_finish(const double2* __restrict__ part, int nblk, int R, i
 }
 
 // w[r][n] += sgn * sum_{i<J} c[r][i] V_i[r][n]; with npart, also per-block sums of |w|^2
-__device__ inline void maxpy_body(const double2* __restrict__ V, size_t vstride, const double2* __restrict__ c,
+__device__ __attribute__((always_inline)) inline void maxpy_body(const double2* __restrict__ V, size_t vstride, const double2* __restrict__ c,
                                   int cstride, double2* __restrict__ w, size_t N, int J, double sgn,
                                   double* __restrict__ npart, const int* __restrict__ flag, int bx, int r, int gx) {
   extern __shared__ double2 cs[];
@@ -249,7 +249,7 @@ __device__ inline double partial_norm(const double* __restrict__ npart, int nb, 
 // LDS copies, the residual estimate |g_{j+1}| and the freeze flag (also written to mapped
 // host memory for the host's convergence check).  Grid (blocks, R), 256 threads.
 constexpr int kMaxRestart = 1000;
-__device__ inline void scale_givens_body(const double* __restrict__ npart, int nb, int m, int j,
+__device__ __attribute__((always_inline)) inline void scale_givens_body(const double* __restrict__ npart, int nb, int m, int j,
                                          const double2* __restrict__ hc, int hstride, double2* __restrict__ hn,
                                          double2* __restrict__ H, double2* __restrict__ cs, double2* __restrict__ sn,
                                          double2* __restrict__ g, double* __restrict__ res, int* __restrict__ jdone,
