@@ -45,7 +45,8 @@ namespace fmbem {
 
 constexpr int kMlRows = 64;  // rows of one output block
 constexpr int kMlZeroShift = 13;
-constexpr int kMlS2mChunk = 256;  // elements per partial sum of the S2M
+constexpr int kMlS2mChunk = 128;  // elements per partial sum of the S2M
+constexpr int kMlLeafRows = 32;   // element rows of one L2P + P2P output block
 
 // ---------------------------------------------------------------------------
 // device: block-sparse products
@@ -244,22 +245,32 @@ __global__ void ml_reduce_kernel(const cplx<T>* __restrict__ part, int S, size_t
   }
 }
 
-// grid[bin(c)][r][i] = sum over chunks q (in order) of part[q p + i][r C + c]
+// grid[bin(c)][r][i] = sum over chunks q (in order) of part[q p + i][r C + c]: a workgroup takes 64
+// consecutive outputs (i, col) of the [p][cols] layout, each of its 4 waves a contiguous quarter of
+// the chunks; the quarters are added in order through LDS
 template <typename T>
-__global__ void ml_s2m_reduce_kernel(const cplx<T>* __restrict__ part, int chunks, int p, int cols, int C, int R,
-                                     int M0, int M1, int N0, int N1, cplx<T>* __restrict__ grid) {
+__global__ __launch_bounds__(256) void ml_s2m_reduce_kernel(const cplx<T>* __restrict__ part, int chunks, int p,
+                                                            int cols, int C, int R, int M0, int M1, int N0, int N1,
+                                                            cplx<T>* __restrict__ grid) {
+  __shared__ cplx<T> qs[3][64];
   const size_t total = (size_t)p * cols;
-  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (size_t)gridDim.x * blockDim.x) {
-    const int col = (int)(idx / p), i = (int)(idx - (size_t)col * p);
-    cplx<T> s = mk<T>(0, 0);
-#pragma unroll 16
-    for (int q = 0; q < chunks; ++q) s = cadd<T>(s, part[((size_t)q * p + i) * cols + col]);
-    const int r = col / C, c = col - r * C;
-    const int c0 = c % M0, c1 = (c / M0) % M1, c2 = c / (M0 * M1);
-    const size_t bin = (size_t)c0 + (size_t)N0 * (c1 + (size_t)N1 * c2);
-    grid[(bin * R + r) * p + i] = s;
+  const size_t idx = (size_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int wv = threadIdx.x >> 6;
+  const int q0 = (int)((long long)chunks * wv / 4), q1 = (int)((long long)chunks * (wv + 1) / 4);
+  cplx<T> s = mk<T>(0, 0);
+  if (idx < total) {
+#pragma unroll 8
+    for (int q = q0; q < q1; ++q) s = cadd<T>(s, part[(size_t)q * total + idx]);
   }
+  if (wv > 0) qs[wv - 1][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (wv > 0 || idx >= total) return;
+  for (int w = 0; w < 3; ++w) s = cadd<T>(s, qs[w][threadIdx.x]);
+  const int i = (int)(idx / cols), col = (int)(idx - (size_t)i * cols);
+  const int r = col / C, c = col - r * C;
+  const int c0 = c % M0, c1 = (c / M0) % M1, c2 = c / (M0 * M1);
+  const size_t bin = (size_t)c0 + (size_t)N0 * (c1 + (size_t)N1 * c2);
+  grid[(bin * R + r) * p + i] = s;
 }
 
 // out[i][t] = in[i][perm[t]] (V0 with its columns in tree order)
@@ -344,8 +355,8 @@ hipError_t ml_prepare(const Plan& P, int R, const void* x, void* ws, void* grid,
   if (P.n_far > 0) {
     ml_stage_any<T>(M.s2m, reinterpret_cast<const cplx<T>*>(M.ops[prec]), B, cols, P, s);
     const size_t pt = (size_t)P.p * cols;
-    hipLaunchKernelGGL(ml_s2m_reduce_kernel<T>, dim3((unsigned)std::min<size_t>((pt + 63) / 64, 16384)), dim3(64),
-                       0, s, reinterpret_cast<const cplx<T>*>(B.b[4]), M.s2m_chunks, P.p, cols, P.C, R, P.grid[0],
+    hipLaunchKernelGGL(ml_s2m_reduce_kernel<T>, dim3((unsigned)((pt + 63) / 64)), dim3(256), 0, s,
+                       reinterpret_cast<const cplx<T>*>(B.b[4]), M.s2m_chunks, P.p, cols, P.C, R, P.grid[0],
                        P.grid[1], P.fft[0], P.fft[1], reinterpret_cast<cplx<T>*>(grid));
   }
   return hipGetLastError();
@@ -765,8 +776,8 @@ hipError_t ml_build(Plan& P, const std::vector<double>& geo, hipStream_t s) {
     for (size_t i = 0; i < p2p.size(); ++i) by[p2p[i].a].push_back((int)i);
     for (int b = 0; b < (int)lv[L].size(); ++b) {
       const Box& x = lv[L][b];
-      for (int r0 = x.e0; r0 < x.e1; r0 += kMlRows) {
-        const int rows = std::min(kMlRows, x.e1 - r0);
+      for (int r0 = x.e0; r0 < x.e1; r0 += kMlLeafRows) {
+        const int rows = std::min(kMlLeafRows, x.e1 - r0);
         add_target(r0, rows);
         add_task(oU + (long long)r0 * p, p, p, row0(L, b), 2, kMlZeroShift);
         for (int i : by[b]) {
