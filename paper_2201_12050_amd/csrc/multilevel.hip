@@ -834,9 +834,37 @@ hipError_t ml_build(Plan& P, const std::vector<double>& geo, hipStream_t s) {
     stage_mode[si] = {5, 0};
     M.part_rows = std::max(M.part_rows, (size_t)S * nrows);
   };
+  // expansion targets of more than 32 rows (p > 32) become balanced row blocks of at most 32, each
+  // with the tasks' operators offset to its rows (fewer idle rows in the 32- and 64-row tiles)
+  auto row_split_stage = [&](size_t si) {
+    const int first = stage_range[si].first, count = stage_range[si].second;
+    bool any = false;
+    for (int i = first; i < first + count; ++i) any = any || tg[i].rows > 32;
+    if (!any) return;
+    const int nfirst = (int)tg.size();
+    int maxr = 0;
+    for (int i = first; i < first + count; ++i) {
+      const MlTarget x = tg[i];
+      const int nch = (x.rows + 31) / 32, rc = (x.rows + nch - 1) / nch;
+      for (int c = 0; c < nch; ++c) {
+        const int r0 = c * rc, rows = std::min(rc, x.rows - r0);
+        const int t0 = (int)tk.size();
+        for (int q = x.t0; q < x.t1; ++q) {
+          MlTask w = tk[q];
+          w.a_off += (long long)r0 * w.lda;
+          tk.push_back(w);
+        }
+        tg.push_back(MlTarget{x.out_row + r0, rows, t0, (int)tk.size()});
+        maxr = std::max(maxr, rows);
+      }
+    }
+    stage_range[si] = {nfirst, (int)tg.size() - nfirst};
+    stage_rows[si] = maxr;
+  };
   {
     // stage order: P2M, M2M x (L - 1), M2L, L2L x (L - 1), L2P + P2P, S2M
     const size_t m2l_stage = 1 + (size_t)(L - 1), l2p_stage = m2l_stage + 1 + (size_t)(L - 1);
+    for (size_t si = 0; si < l2p_stage; ++si) row_split_stage(si);
     split_stage(m2l_stage, 0, M.rows);
     split_stage(l2p_stage, 0, n);
   }
