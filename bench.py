@@ -82,8 +82,23 @@ def cpu_baseline(w, its_per_solve, seconds_budget=30.0):
     sample.far_cells(x)
     t_far = time.perf_counter() - t0
     t_apply = t_near + t_far
+    # the same sample on one host thread (BLAS pools limited to 1)
+    single = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            sample.near_rows(x)
+            t1_near = (time.perf_counter() - t0) * (n / rows.size)
+            t0 = time.perf_counter()
+            sample.far_cells(x)
+            t1_far = time.perf_counter() - t0
+        single = {"value": 1.0 / ((t1_near + t1_far) * its_per_solve), "matvec_s": t1_near + t1_far,
+                  "near_s": t1_near, "far_s": t1_far, "cores": 1}
+    except ImportError:  # pragma: no cover
+        pass
     return {"value": 1.0 / (t_apply * its_per_solve), "unit": "solves/s", "cores": int(threads), "kind": "oracle",
-            "matvec_s": t_apply, "near_s": t_near, "far_s": t_far,
+            "matvec_s": t_apply, "near_s": t_near, "far_s": t_far, "single_thread": single,
             "sample": (f"oracle O2 apply on the same 16x16 workload: near field for 64 of {n} rows per cell "
                        f"(scaled x{n // rows.size}), far field (S2M, all 952 M2L offsets, L2T) in full; "
                        f"solves/s = 1 / (apply time x {its_per_solve} operator applications of the GPU FP64 solve)")}

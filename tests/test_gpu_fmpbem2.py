@@ -126,3 +126,52 @@ def test_multilevel_in_a_batch_with_a_dense_plan():
             assert rel(x.cpu().numpy(), xa.cpu().numpy()) < 1e-8
     P1.close()
     P2.close()
+
+
+def test_multilevel_in_the_engine():
+    # serving form: an FMPBEM2 request and a dense-near request in one engine, each equal to its
+    # own solve
+    import paper_2201_12050_amd as fm
+    v, t, lat, k, F, A = _case("sphere80_3x3_L2")
+    _, grid, _, nt, levels, ntn = CASES["sphere80_3x3_L2"]
+    P2 = fm.Plan(v, t, grid, lat.pitch, k, nt, near_levels=levels, near_order=ntn)
+    P1 = fm.Plan(v, t, (4, 2, 1), lat.pitch, k, nt)
+    b2 = P2.incident_plane_wave(unit_directions(2, 15))
+    b1 = P1.incident_plane_wave(unit_directions(3, 16))
+    o = dict(tol=1e-10, inner="fp32", ortho="once")
+    E = fm.Engine(hbm_budget_bytes=8 << 30, max_slots=4)
+    t2, t1 = E.submit(P2, b2, **o), E.submit(P1, b1, **o)
+    done = {}
+    for _ in range(100000):
+        for tk in (t2, t1):
+            if tk not in done:
+                r = E.poll(tk)
+                if r is not None:
+                    done[tk] = r
+        if len(done) == 2:
+            break
+        E.step()
+    assert len(done) == 2
+    for tk, P, b in ((t2, P2, b2), (t1, P1, b1)):
+        x, infos, st = done[tk]
+        assert st == 0 and max(i["rel_residual"] for i in infos) <= 1e-10
+        xa, _ = P.solve(b, **o)
+        assert rel(x.cpu().numpy(), xa.cpu().numpy()) < 1e-8
+    E.close()
+    P1.close()
+    P2.close()
+
+
+def test_multilevel_noalloc_equals_workspace_entry_point():
+    import paper_2201_12050_amd as fm
+    v, t, lat, k, F, A = _case("sphere80_3x3_L2")
+    _, grid, _, nt, levels, ntn = CASES["sphere80_3x3_L2"]
+    P = fm.Plan(v, t, grid, lat.pitch, k, nt, near_levels=levels, near_order=ntn)
+    x = torch.from_numpy(random_complex((2, lat.n_cells, t.shape[0]), 91)).cuda()
+    for prec, xx in (("fp64", x), ("fp32", x.to(torch.complex64))):
+        y_ws = P.matvec(xx, precision=prec)
+        y_na = torch.full_like(xx, float("nan"))
+        P.matvec_noalloc(xx, y_na, precision=prec)
+        assert torch.isfinite(torch.view_as_real(y_na)).all()
+        assert rel(y_na.cpu().numpy(), y_ws.cpu().numpy()) < (1e-13 if prec == "fp64" else 1e-6)
+    P.close()
