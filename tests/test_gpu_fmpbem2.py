@@ -29,6 +29,8 @@ CASES = {
     "sphere320_5x1_L3": ("sphere2", (5, 1, 1), 1300.0, 8, 3, 6),
     "sphere80_1x1_L2": ("sphere1", (1, 1, 1), 600.0, 4, 2, 4),      # no far field
     "tube192_2x2x2_L1": ("tube", (2, 2, 2), 600.0, 6, 1, 7),        # 27 near offsets
+    "sphere80_3x1_L4_nt1": ("sphere1", (3, 1, 1), 800.0, 5, 4, 1),  # deep tree, lowest order
+    "sphere80_4x2_100Hz": ("sphere1", (4, 2, 1), 100.0, 6, 2, 7),   # FP32 range, highest order
 }
 
 
