@@ -28,7 +28,12 @@
 // Application (all cells and right-hand sides at once): the input is gathered into tree
 // order with the columns (RHS r, cell c) innermost, then every stage is one launch of the
 // block-sparse product kernel -- P2M, M2M per level, M2L of all levels, L2L per level, L2P
-// together with the P2P blocks -- and the result is scattered back and added to y.
+// together with the P2P blocks -- and the result is scattered back and added to y.  Targets
+// of more than 32 expansion rows are split into row blocks, and the two heavy stages (M2L,
+// L2P + P2P) divide each target's tasks over several workgroups whose partial sums are added
+// in slot order afterwards.  The S2M of the cell-level far field reads the same tree-ordered
+// input as a split-K product (partial sums over element chunks, added in chunk order).
+// Every sum runs in a fixed order, so an application's result does not depend on timing.
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -43,7 +48,7 @@
 
 namespace fmbem {
 
-constexpr int kMlRows = 64;  // rows of one output block
+constexpr int kMlRows = 64;  // rows of one S2M output block (the largest target of any stage)
 constexpr int kMlZeroShift = 13;
 constexpr int kMlS2mChunk = 128;  // elements per partial sum of the S2M
 constexpr int kMlLeafRows = 32;   // element rows of one L2P + P2P output block
@@ -66,12 +71,13 @@ __device__ inline cplx<T> load_if(const cplx<T>* p, bool c) {
 
 // out[out_row + i][col] (+)= sum over the target's tasks of A[i][k] src[src_row + k][col'] with
 // col' the column of cell c - d (zero outside the lattice).  The target's work is a list of items
-// (task, KW = 8-wide contraction chunk).  A wave covers 16 columns x 4
-// row groups (RPT rows each); the workgroup's 4 waves form WS streams of 4 / WS column slices,
-// stream j taking items j, j + WS, ...  Every round each stream stages its item (A chunk
-// ROWS x KW and source chunk KW x its columns) in its own LDS region, one barrier pair per round
-// for all streams, while the next item is loaded into registers.  The streams' partial sums are
-// added in stream order.
+// (task, KW = 8-wide contraction chunk).  A wave covers 16 columns x 4 row groups (RPT rows
+// each); the workgroup's 4 waves form WS streams of 4 / WS column slices, stream j taking items
+// j, j + WS, ...  Every round each stream stages its item (A chunk ROWS x KW and source chunk
+// KW x its columns) in its own LDS region, one barrier pair per round for all streams, while the
+// next item is loaded into registers.  The streams' partial sums are added in stream order.
+// (Measured: operands read per lane without LDS staging were 2-4 times slower; a second item of
+// prefetch in registers 10-30 % slower; 16-wide FP32 chunks slower than 8.)
 template <typename T, int WS, int RPT>
 __global__ __launch_bounds__(256) void ml_kernel(const MlTarget* __restrict__ tg, const MlTask* __restrict__ tk,
                                                  const cplx<T>* __restrict__ ops, MlBufs B, int out_id, int accum,
