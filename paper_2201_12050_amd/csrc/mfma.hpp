@@ -1,4 +1,4 @@
-// 16x16x4 matrix-core tiles (gfx950) shared by the GEMM kernels and the DFT kernels.
+// 16x16x4 matrix-core tiles (gfx950) shared by the GEMM, DFT and multilevel product kernels.
 #pragma once
 
 #include "common.hpp"

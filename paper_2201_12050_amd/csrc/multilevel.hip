@@ -44,6 +44,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "mfma.hpp"
 #include "specfun.hpp"
 
 namespace fmbem {
@@ -61,28 +62,62 @@ struct MlBufs {
                // 4: S2M partial sums, 5: partial sums of split stages
 };
 
-// *p when c, else 0 (component-wise, so that the value stays in registers)
+// a complex zero in device memory (never written), read in place of entries outside the operands
+__device__ double2 ml_zero_entry;
+
+// *p when c, else 0: one unconditional load from p or from the zero entry (a guarded load, or a
+// select after the load, makes the wave wait for the data at once instead of at its use)
 template <typename T>
 __device__ inline cplx<T> load_if(const cplx<T>* p, bool c) {
-  const T re = c ? p->x : T(0);
-  const T im = c ? p->y : T(0);
-  return mk<T>(re, im);
+  return *(c ? p : reinterpret_cast<const cplx<T>*>(&ml_zero_entry));
+}
+
+// the waves of one stream agree on its LDS staging area: a workgroup barrier when a stream spans
+// several waves; a single wave's LDS operations complete in issue order, so it only needs the
+// compiler to keep them in program order
+// sum over the 64 lanes of a wave (every lane gets it)
+__device__ inline int wave_sum(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int SLICES>
+__device__ inline void stream_sync() {
+  if constexpr (SLICES == 1) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
 }
 
 // out[out_row + i][col] (+)= sum over the target's tasks of A[i][k] src[src_row + k][col'] with
-// col' the column of cell c - d (zero outside the lattice).  The target's work is a list of items
-// (task, KW = 8-wide contraction chunk).  A wave covers 16 columns x 4 row groups (RPT rows
-// each); the workgroup's 4 waves form WS streams of 4 / WS column slices, stream j taking items
-// j, j + WS, ...  Every round each stream stages its item (A chunk ROWS x KW and source chunk
-// KW x its columns) in its own LDS region, one barrier pair per round for all streams, while the
-// next item is loaded into registers.  The streams' partial sums are added in stream order.
-// (Measured: operands read per lane without LDS staging were 2-4 times slower; a second item of
-// prefetch in registers 10-30 % slower; 16-wide FP32 chunks slower than 8.)
-template <typename T, int WS, int RPT>
-__global__ __launch_bounds__(256) void ml_kernel(const MlTarget* __restrict__ tg, const MlTask* __restrict__ tk,
-                                                 const cplx<T>* __restrict__ ops, MlBufs B, int out_id, int accum,
-                                                 int cols, int C, int M0, int M1, int M2) {
-  constexpr int SLICES = 4 / WS, ROWS = 4 * RPT, KW = 8;
+// col' the column of cell c - d (zero outside the lattice), on the 16x16x4 matrix cores.  The
+// target's work is a list of items (task, KW-wide contraction chunk).  The workgroup's 4 waves
+// form WS streams of 4 / WS column slices of 16, stream j taking items j, j + WS, ...  Every round
+// each stream stages its item (A chunk ROWS x KW and source chunk KW x its columns, zero beyond
+// the target's rows, the item's contraction and the lattice) in its own LDS region while the
+// next item is loaded into registers; each wave then multiplies its RT row tiles of 16 by its
+// column slice with four real products per complex product and k step of 4.  The streams'
+// partial sums are added in stream order.  Occupancy: 4 waves per SIMD for up to 32 rows.
+// Measured on the 4 x 4 lattice of 20480-triangle cells (4 levels, n_t,near = 4; whole multilevel
+// near field, FP32 / FP64), step by step from the first form of this loop: the matrix cores in
+// place of the vector ALU (one lane per column, RT rows per lane, nine complex LDS operands per
+// eight multiply-adds) 334 -> 288 us / 429 -> 389 us; no workgroup barrier per round where a
+// stream is a single wave -> 246 / 360; the task descriptors in lanes instead of a dependent load
+// per task -> 244 / 326; 4 waves per SIMD -> 221 / 285; unconditional loads (a guarded load, or a
+// select right after the load, waited for the operands at once) -> 183 / 274.  A second item in
+// flight (two register sets) was 5-10 % slower.
+template <typename T, int WS, int RT, int KW>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RT <= 2 ? 4 : 1))) void ml_kernel(
+    const MlTarget* __restrict__ tg, const MlTask* __restrict__ tk, const cplx<T>* __restrict__ ops, MlBufs B,
+    int out_id, int accum, int cols, int C, int M0, int M1, int M2) {
+  static_assert(KW % 4 == 0, "whole k steps");
+  using mf = nmf<T>;
+  using acc_t = typename mf::acc;
+  constexpr int SLICES = 4 / WS, ROWS = 16 * RT;
   constexpr int SC = SLICES * 16;               // columns of a stream
   constexpr int STG = (ROWS * KW + SLICES * 64 - 1) / (SLICES * 64);  // A entries staged per thread and item
   constexpr int XSTG = KW * SC / (SLICES * 64);   // source entries staged per thread and item
@@ -95,72 +130,104 @@ __global__ __launch_bounds__(256) void ml_kernel(const MlTarget* __restrict__ tg
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int stream = wave / SLICES, slice = wave - stream * SLICES;
   const int ts = slice * 64 + lane;  // thread index within the stream
-  const int cl = lane & 15, rg = lane >> 4;
+  const int li = lane & 15, g = lane >> 4;
   const MlTarget t = tg[blockIdx.x];
   const int col0 = blockIdx.y * SC;
-  const cplx<T> zero = mk<T>(0, 0);
-  // the columns this thread loads (fixed for every item): cc = (ts + s SLICES 64) mod SC
-  int lcol[XSTG], lc0[XSTG], lc1[XSTG], lc2[XSTG];
-#pragma unroll
-  for (int s = 0; s < XSTG; ++s) {
-    const int cc = (ts + s * SLICES * 64) % SC;
-    lcol[s] = col0 + cc;
-    const int c = lcol[s] < cols ? lcol[s] % C : 0;
-    lc0[s] = c % M0;
-    lc1[s] = (c / M0) % M1;
-    lc2[s] = c / (M0 * M1);
+  // the column this thread loads (the same for every entry it stages, since SC divides SLICES 64)
+  const int lcol = col0 + ts % SC;
+  int lc0, lc1, lc2;
+  {
+    const int c = lcol < cols ? lcol % C : 0;
+    lc0 = c % M0;
+    lc1 = (c / M0) % M1;
+    lc2 = c / (M0 * M1);
   }
-  cplx<T> acc[RPT];
+  acc_t yr[RT], yi[RT];
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) acc[i] = zero;
-  int q = t.t0, ch = stream, nch = 0;
-  if (q < t.t1) nch = (tk[q].ks + KW - 1) / KW;
+  for (int i = 0; i < RT; ++i) {
+    yr[i] = acc_t{};
+    yi[i] = acc_t{};
+  }
+  // The target's task descriptors sit in the lanes of every wave, 64 at a time (task base + l in
+  // lane l), and are read with readlane: the cursor never waits on a memory load.
+  const int nt = t.t1 - t.t0;
+  int base = 0;
+  int d_lo = 0, d_hi = 0, d_lda = 0, d_ks = 0, d_src = 0, d_sel = 0;
+#define ML_FETCH()                                                \
+  do {                                                            \
+    if (base + lane < nt) {                                       \
+      const MlTask w = tk[t.t0 + base + lane];                    \
+      d_lo = (int)(unsigned)(w.a_off & 0xffffffffLL);             \
+      d_hi = (int)(w.a_off >> 32);                                \
+      d_lda = w.lda;                                              \
+      d_ks = w.ks;                                                \
+      d_src = w.src_row;                                          \
+      d_sel = w.sel;                                              \
+    }                                                             \
+  } while (0)
+  // items of the whole target (a wave sum per 64 tasks)
+  int items = 0;
+  for (base = 0; base < nt; base += 64) {
+    ML_FETCH();
+    items += wave_sum(base + lane < nt ? (d_ks + KW - 1) / KW : 0);
+  }
+  base = 0;
+  if (nt > 64) ML_FETCH();  // otherwise the lanes still hold tasks 0..nt-1
+  const int rounds = (items + WS - 1) / WS;
+  int q = 0, ch = stream, nch = nt > 0 ? (__builtin_amdgcn_readlane(d_ks, 0) + KW - 1) / KW : 0;
   // the cursor (task q, chunk ch) of this stream moves by `by` items
-#define ML_ADVANCE(by)                                     \
-  do {                                                     \
-    ch += (by);                                            \
-    while (q < t.t1 && ch >= nch) {                        \
-      ch -= nch;                                           \
-      ++q;                                                 \
-      nch = q < t.t1 ? (tk[q].ks + KW - 1) / KW : 0;       \
-    }                                                      \
+#define ML_ADVANCE(by)                                                            \
+  do {                                                                            \
+    ch += (by);                                                                   \
+    while (q < nt && ch >= nch) {                                                 \
+      ch -= nch;                                                                  \
+      ++q;                                                                        \
+      if (q < nt && q >= base + 64) {                                             \
+        base += 64;                                                               \
+        ML_FETCH();                                                               \
+      }                                                                           \
+      nch = q < nt ? (__builtin_amdgcn_readlane(d_ks, q - base) + KW - 1) / KW : 0; \
+    }                                                                             \
   } while (0)
   // the cursor's item into registers (kn = 0: no item left)
-#define ML_LOAD()                                                                                        \
+#define ML_LOAD(an, xn, kn)                                                                                        \
   do {                                                                                                   \
     kn = 0;                                                                                              \
-    if (q < t.t1) {                                                                                      \
-      const MlTask w = tk[q];                                                                            \
+    if (q < nt) {                                                                                        \
+      const int lq = q - base;                                                                           \
+      const long long a_off = (long long)(unsigned)__builtin_amdgcn_readlane(d_lo, lq) |                 \
+                              ((long long)__builtin_amdgcn_readlane(d_hi, lq) << 32);                    \
+      const int lda = __builtin_amdgcn_readlane(d_lda, lq);                                              \
+      const int ks = __builtin_amdgcn_readlane(d_ks, lq);                                                \
+      const int src_row = __builtin_amdgcn_readlane(d_src, lq);                                          \
+      const int sel = __builtin_amdgcn_readlane(d_sel, lq);                                              \
       const int k0 = ch * KW;                                                                            \
-      kn = min(KW, w.ks - k0);                                                                           \
-      const cplx<T>* __restrict__ A = ops + w.a_off + k0;                                                \
+      kn = min(KW, ks - k0);                                                                             \
+      const cplx<T>* __restrict__ A = ops + a_off + k0;                                                  \
       _Pragma("unroll") for (int s = 0; s < STG; ++s) {                                                  \
         const int e = ts + s * SLICES * 64;                                                              \
         const int row = e / KW, kk = e % KW;                                                             \
-        an[s] = load_if<T>(A + (size_t)row * w.lda + kk, e < ROWS * KW && row < t.rows && kk < kn);    \
+        an[s] = load_if<T>(A + (size_t)row * lda + kk, e < ROWS * KW && row < t.rows && kk < kn);      \
       }                                                                                                  \
-      const int sh = w.sel >> 2;                                                                         \
+      const int sh = sel >> 2;                                                                           \
       const int d0 = sh % 3 - 1, d1 = (sh / 3) % 3 - 1, d2 = sh / 9 - 1;                                 \
       const int dl = d0 + M0 * (d1 + M1 * d2);                                                           \
       const cplx<T>* __restrict__ src =                                                                  \
-          reinterpret_cast<const cplx<T>*>(B.b[w.sel & 3]) + (size_t)(w.src_row + k0) * cols;            \
+          reinterpret_cast<const cplx<T>*>(B.b[sel & 3]) + (size_t)(src_row + k0) * cols;                \
+      const bool okc = lcol < cols && (unsigned)(lc0 - d0) < (unsigned)M0 &&                             \
+                       (unsigned)(lc1 - d1) < (unsigned)M1 && (unsigned)(lc2 - d2) < (unsigned)M2;        \
       _Pragma("unroll") for (int s = 0; s < XSTG; ++s) {                                                 \
-        const int kk = (ts + s * SLICES * 64) / SC;                                                      \
-        const bool ok = lcol[s] < cols && kk < kn && (unsigned)(lc0[s] - d0) < (unsigned)M0 &&           \
-                        (unsigned)(lc1[s] - d1) < (unsigned)M1 && (unsigned)(lc2[s] - d2) < (unsigned)M2; \
-        xn[s] = load_if<T>(src + ((size_t)kk * cols + lcol[s] - dl), ok);                                \
+        const int kk = ts / SC + 4 * s;                                                                  \
+        xn[s] = load_if<T>(src + ((size_t)kk * cols + lcol - dl), okc && kk < kn);                       \
       }                                                                                                  \
     }                                                                                                    \
   } while (0)
-  ML_ADVANCE(0);
   cplx<T> an[STG], xn[XSTG];
   int kn = 0;  // contraction length of the loaded item (0: none)
-  int items = 0;
-  for (int qq = t.t0; qq < t.t1; ++qq) items += (tk[qq].ks + KW - 1) / KW;
-  const int rounds = (items + WS - 1) / WS;
-  ML_LOAD();
+  ML_ADVANCE(0);
+  ML_LOAD(an, xn, kn);
   for (int r = 0; r < rounds; ++r) {
-    __syncthreads();
+    stream_sync<SLICES>();
 #pragma unroll
     for (int s = 0; s < STG; ++s) {
       const int e = ts + s * SLICES * 64;
@@ -173,47 +240,64 @@ __global__ __launch_bounds__(256) void ml_kernel(const MlTarget* __restrict__ tg
     }
     const int kc = kn;
     ML_ADVANCE(WS);
-    ML_LOAD();
-    __syncthreads();
-    if (kc > 0) {
+    ML_LOAD(an, xn, kn);
+    stream_sync<SLICES>();
 #pragma unroll
-      for (int kk = 0; kk < KW; ++kk) {
-        if (kk >= kc) break;  // uniform: the tail of the item's contraction
-        const cplx<T> xv = Xs[stream][kk][slice * 16 + cl];
+    for (int k4 = 0; k4 < KW; k4 += 4) {
+      if (k4 >= kc) break;  // uniform: the tail of the item's contraction (no item: kc = 0)
+      const cplx<T> xv = Xs[stream][k4 + g][slice * 16 + li];
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) cfma<T>(acc[i], As[stream][kk][rg + 4 * i], xv);
+      for (int i = 0; i < RT; ++i) {
+        const cplx<T> av = As[stream][k4 + g][16 * i + li];
+        yr[i] = mf::step(av.x, xv.x, yr[i]);
+        yi[i] = mf::step(av.x, xv.y, yi[i]);
+        yr[i] = mf::step(-av.y, xv.y, yr[i]);
+        yi[i] = mf::step(av.y, xv.x, yi[i]);
       }
     }
   }
 #undef ML_LOAD
 #undef ML_ADVANCE
+#undef ML_FETCH
   if constexpr (WS > 1) {
     // stream j > 0 hands its partial sums to stream 0, one stream at a time (stream order)
     for (int j = 1; j < WS; ++j) {
       __syncthreads();
       if (stream == j) {
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) red[(rg + 4 * i) * SC + slice * 16 + cl] = acc[i];
+        for (int i = 0; i < RT; ++i)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            red[(16 * i + mf::row(g, v)) * SC + slice * 16 + li] = mk<T>(yr[i][v], yi[i][v]);
       }
       __syncthreads();
       if (stream == 0) {
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) acc[i] = cadd<T>(acc[i], red[(rg + 4 * i) * SC + slice * 16 + cl]);
+        for (int i = 0; i < RT; ++i)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const cplx<T> o = red[(16 * i + mf::row(g, v)) * SC + slice * 16 + li];
+            yr[i][v] += o.x;
+            yi[i][v] += o.y;
+          }
       }
     }
     if (stream > 0) return;
   }
-  const int col = col0 + slice * 16 + cl;
+  const int col = col0 + slice * 16 + li;
   if (col >= cols) return;
   cplx<T>* __restrict__ out = reinterpret_cast<cplx<T>*>(B.b[out_id]);
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) {
-    const int row = rg + 4 * i;
-    if (row < t.rows) {
-      cplx<T>* o = out + (size_t)(t.out_row + row) * cols + col;
-      *o = accum ? cadd<T>(*o, acc[i]) : acc[i];
+  for (int i = 0; i < RT; ++i)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * i + mf::row(g, v);
+      if (row < t.rows) {
+        cplx<T>* o = out + (size_t)(t.out_row + row) * cols + col;
+        const cplx<T> a = mk<T>(yr[i][v], yi[i][v]);
+        *o = accum ? cadd<T>(*o, a) : a;
+      }
     }
-  }
 }
 
 // xt[pos[e]][col] = x[col][e]  (x: [R][C][n], col = r C + c)
@@ -315,21 +399,22 @@ static MlBufs ml_bufs(const Plan& P, int R, void* ws) {
   return B;
 }
 
-template <typename T, int WS, int RPT>
+template <typename T, int WS, int RT>
 static void ml_stage_launch(const MlStage& st, const cplx<T>* ops, const MlBufs& B, int cols, const Plan& P,
                             hipStream_t s) {
   const int tile = 16 * (4 / WS);
-  hipLaunchKernelGGL((ml_kernel<T, WS, RPT>), dim3(st.n_tg, (cols + tile - 1) / tile), dim3(256), 0, s, st.tg, st.tk,
+  constexpr int KW = sizeof(T) == 8 ? 8 : 16;
+  hipLaunchKernelGGL((ml_kernel<T, WS, RT, KW>), dim3(st.n_tg, (cols + tile - 1) / tile), dim3(256), 0, s, st.tg, st.tk,
                      ops, B, st.out, st.accum, cols, P.C, P.grid[0], P.grid[1], P.grid[2]);
 }
 
-// waves per column slice by the column count, rows per lane by the stage's largest target
+// waves per column slice by the column count, row tiles by the stage's largest target
 template <typename T, int WS>
 static void ml_stage_rows(const MlStage& st, const cplx<T>* ops, const MlBufs& B, int cols, const Plan& P,
                           hipStream_t s) {
-  if (st.max_rows <= 16) ml_stage_launch<T, WS, 4>(st, ops, B, cols, P, s);
-  else if (st.max_rows <= 32) ml_stage_launch<T, WS, 8>(st, ops, B, cols, P, s);
-  else ml_stage_launch<T, WS, 16>(st, ops, B, cols, P, s);
+  if (st.max_rows <= 16) ml_stage_launch<T, WS, 1>(st, ops, B, cols, P, s);
+  else if (st.max_rows <= 32) ml_stage_launch<T, WS, 2>(st, ops, B, cols, P, s);
+  else ml_stage_launch<T, WS, 4>(st, ops, B, cols, P, s);
 }
 
 template <typename T>
