@@ -200,14 +200,16 @@ void prof_end(const Plan& P, int stage, hipEvent_t start, hipStream_t s);
 size_t matvec_workspace_bytes_per_rhs(const Plan& P, int precision);
 
 // multilevel near field (multilevel.hip): tree and operators (plan build), workspace, application
-// (y (+)= the near field of x; y64: complex128 output of an FP32 application)
+// (y (+)= the near field of x; y64: complex128 output of an FP32 application).  Parts (bit mask):
+// ml_prepare 1 = the input into tree order, 2 = the S2M from it; ml_apply 1 = the products into
+// the tree-ordered output, 2 = that output added to (or written into) y
 bool ml_cell_fits(const std::vector<double>& geo, int n, const double pitch[3], int L);
 hipError_t ml_build(Plan& P, const std::vector<double>& geo, hipStream_t s);
 size_t ml_workspace_bytes_per_rhs(const Plan& P, int precision);
 template <typename T>
-hipError_t ml_prepare(const Plan& P, int R, const void* x, void* ws, void* grid, hipStream_t s);
+hipError_t ml_prepare(const Plan& P, int R, const void* x, void* ws, void* grid, hipStream_t s, int parts = 3);
 template <typename T>
-hipError_t ml_apply(const Plan& P, int R, void* y, void* y64, void* ws, bool accum, hipStream_t s);
+hipError_t ml_apply(const Plan& P, int R, void* y, void* y64, void* ws, bool accum, hipStream_t s, int parts = 3);
 // plan.hip helpers used by the multilevel build
 hipError_t plan_alloc(Plan& P, void** ptr, size_t bytes);
 void gauss_legendre_host(int q, std::vector<double>& x, std::vector<double>& w);

@@ -264,12 +264,13 @@ template <typename T>
 static char* ml_buffers(const Plan& P, int R, void* ws) {
   return near_partials<T>(P, R, ws) + align256((size_t)P.n_near * R * P.C * P.n * sizeof(cplx<T>));
 }
-// [1] the multilevel near field of an FMPBEM2 plan: y (+)= S~ x (after ml_s2m)
+// [1] the multilevel near field of an FMPBEM2 plan: y (+)= S~ x (after ml_s2m); parts as ml_apply
 template <typename T>
-static hipError_t ml_stage(const Plan& P, int R, void* y, void* y64, void* ws, bool accum, hipStream_t s) {
+static hipError_t ml_stage(const Plan& P, int R, void* y, void* y64, void* ws, bool accum, hipStream_t s,
+                           int parts = 3) {
   const int prec = sizeof(T) == 8 ? 0 : 1;
   hipEvent_t ev = prof_begin(P, 1 + 6 * prec, s);
-  const hipError_t e = ml_apply<T>(P, R, y, y64, ml_buffers<T>(P, R, ws), accum, s);
+  const hipError_t e = ml_apply<T>(P, R, y, y64, ml_buffers<T>(P, R, ws), accum, s, parts);
   prof_end(P, 1 + 6 * prec, ev, s);
   return e;
 }
@@ -335,7 +336,10 @@ NearJob l2t_job(const Plan& P, int R, void* ws, const void* lhat, void* y, void*
 
 // Far-field chain of one plan on the plan's second stream, overlapping the near field on the
 // caller's stream: fork after x is ready, S2M -> DFT -> M2L -> inverse DFT on the second
-// stream, join before the L2T GEMM.  Not used while the caller's stream is being captured.
+// stream, join before the L2T GEMM.  An FMPBEM2 plan gathers x into tree order before the fork,
+// runs its S2M from it on the second stream and its multilevel products on the caller's stream,
+// and adds their tree-ordered output to y after the L2T.  Not used while the caller's stream is
+// being captured.
 template <typename T>
 static hipError_t matvec_overlap(const Plan& P, int R, const void* x, void* y, void* ws, hipStream_t s, void* y64,
                                  bool tune) {
@@ -344,12 +348,13 @@ static hipError_t matvec_overlap(const Plan& P, int R, const void* x, void* y, v
   const int dsched = dft_schedule<T>(P, R, ws, s, tune);
   std::lock_guard<std::mutex> lk(*P.aux_mu);
   hipError_t e;
+  if (P.ml && (e = ml_prepare<T>(P, R, x, ml_buffers<T>(P, R, ws), ws, s, 1))) return e;
   if ((e = hipEventRecord(P.ev_fork, s))) return e;
   if ((e = hipStreamWaitEvent(P.aux, P.ev_fork, 0))) return e;
   // far chain [2]-[4] (S2M counted with the DFT stage)
   hipEvent_t ev = prof_begin(P, 2 + 6 * prec, P.aux);
   if (P.ml) {
-    if ((e = ml_prepare<T>(P, R, x, ml_buffers<T>(P, R, ws), ws, P.aux))) return e;
+    if ((e = ml_prepare<T>(P, R, x, ml_buffers<T>(P, R, ws), ws, P.aux, 2))) return e;
   } else {
     std::vector<NearJob> s2m{near_job(P, R, P.V0[prec], ws, p, n, x, SRC_X, DEST_GRID)};
     const int shape = plan_shape<T>(P, 0, s2m, P.aux, tune);
@@ -365,11 +370,13 @@ static hipError_t matvec_overlap(const Plan& P, int R, const void* x, void* y, v
   if ((e = grid_dft_launch<T>(lhat, R * p, P.grid, P.fft, true, true, P.aux, P.flip_p(), sched_inv(dsched), P.dftF[prec]))) return e;
   prof_end(P, 4 + 6 * prec, ev, P.aux);
   if ((e = hipEventRecord(P.ev_join, P.aux))) return e;
-  // [0] near field on the caller's stream
-  {
+  // [0] near field on the caller's stream (the multilevel products of an FMPBEM2 plan)
+  if (P.ml) {
+    if ((e = ml_stage<T>(P, R, y, y64, ws, true, s, 1))) return e;
+  } else {
     std::vector<NearJob> jobs;
     near_s2m_jobs<T>(P, R, x, ws, jobs);
-    if (!P.ml) jobs.pop_back();  // the S2M job ran on the second stream
+    jobs.pop_back();  // the S2M job ran on the second stream
     if (!jobs.empty()) {
       const int shape = plan_shape<T>(P, 0, jobs, s, tune);
       ev = prof_begin(P, 0 + 6 * prec, s);
@@ -384,7 +391,7 @@ static hipError_t matvec_overlap(const Plan& P, int R, const void* x, void* y, v
   ev = prof_begin(P, 5 + 6 * prec, s);
   e = near_launch<T>(jobs, s, shape, 1);
   prof_end(P, 5 + 6 * prec, ev, s);
-  if (e == hipSuccess && P.ml) e = ml_stage<T>(P, R, y, y64, ws, true, s);
+  if (e == hipSuccess && P.ml) e = ml_apply<T>(P, R, y, y64, ml_buffers<T>(P, R, ws), true, s, 2);
   return e;
 }
 
@@ -394,9 +401,11 @@ static hipError_t matvec_t(const Plan& P, int R, const void* x, void* y, void* w
   const int prec = sizeof(T) == 8 ? 0 : 1;
   const int p = P.p;
   P.prof.active = P.prof.mask != 0 && (P.prof.calls++ % P.prof.period) == 0;
-  // FP64 only: the FP32 near-field GEMM keeps every CU occupied until it drains, so a
-  // concurrent far chain only delays it (measured on gfx950); the FP64 one leaves room
-  if (sizeof(T) == 8 && P.aux && P.n_far > 0 && !capturing(s)) return matvec_overlap<T>(P, R, x, y, ws, s, y64, tune);
+  // FP64, and FMPBEM2 plans: the FP32 near-field GEMM keeps every CU occupied until it drains, so a
+  // concurrent far chain only delays it (measured on gfx950); the FP64 one leaves room, and so do
+  // the short launches of the multilevel products
+  if ((sizeof(T) == 8 || P.ml) && P.aux && P.n_far > 0 && !capturing(s))
+    return matvec_overlap<T>(P, R, x, y, ws, s, y64, tune);
   const int dsched = dft_schedule<T>(P, R, ws, s, tune);
   // [0] near field and S2M
   hipEvent_t ev = nullptr;

@@ -432,18 +432,19 @@ static void ml_stage_any(const MlStage& st, const cplx<T>* ops, const MlBufs& B,
   }
 }
 
-// the input in tree order and, with a far field, the S2M into the padded grid
+// the input in tree order (parts & 1) and, with a far field, the S2M into the padded grid (parts & 2)
 template <typename T>
-hipError_t ml_prepare(const Plan& P, int R, const void* x, void* ws, void* grid, hipStream_t s) {
+hipError_t ml_prepare(const Plan& P, int R, const void* x, void* ws, void* grid, hipStream_t s, int parts) {
   const MlData& M = *P.ml;
   const int prec = sizeof(T) == 8 ? 0 : 1;
   const int cols = R * P.C;
   const MlBufs B = ml_bufs<T>(P, R, ws);
   const size_t total = (size_t)P.n * cols;
   const unsigned g = (unsigned)std::min<size_t>((total + 255) / 256, 8192);
-  hipLaunchKernelGGL(ml_in_kernel<T>, dim3(g), dim3(256), 0, s, reinterpret_cast<const cplx<T>*>(x), M.pos, P.n,
-                     total, cols, reinterpret_cast<cplx<T>*>(B.b[0]));
-  if (P.n_far > 0) {
+  if (parts & 1)
+    hipLaunchKernelGGL(ml_in_kernel<T>, dim3(g), dim3(256), 0, s, reinterpret_cast<const cplx<T>*>(x), M.pos, P.n,
+                       total, cols, reinterpret_cast<cplx<T>*>(B.b[0]));
+  if ((parts & 2) && P.n_far > 0) {
     ml_stage_any<T>(M.s2m, reinterpret_cast<const cplx<T>*>(M.ops[prec]), B, cols, P, s);
     const size_t pt = (size_t)P.p * cols;
     hipLaunchKernelGGL(ml_s2m_reduce_kernel<T>, dim3((unsigned)((pt + 63) / 64)), dim3(256), 0, s,
@@ -453,9 +454,10 @@ hipError_t ml_prepare(const Plan& P, int R, const void* x, void* ws, void* grid,
   return hipGetLastError();
 }
 
-// the near field from the input in tree order (ml_prepare earlier on the stream): y (+)= S~ x
+// the near field from the input in tree order (ml_prepare earlier on the stream): the products into
+// the tree-ordered output (parts & 1), then y (+)= that output (parts & 2)
 template <typename T>
-hipError_t ml_apply(const Plan& P, int R, void* y, void* y64, void* ws, bool accum, hipStream_t s) {
+hipError_t ml_apply(const Plan& P, int R, void* y, void* y64, void* ws, bool accum, hipStream_t s, int parts) {
   const MlData& M = *P.ml;
   const int prec = sizeof(T) == 8 ? 0 : 1;
   const int cols = R * P.C;
@@ -463,7 +465,9 @@ hipError_t ml_apply(const Plan& P, int R, void* y, void* y64, void* ws, bool acc
   const size_t total = (size_t)P.n * cols;
   const unsigned g = (unsigned)std::min<size_t>((total + 255) / 256, 8192);
   const cplx<T>* ops = reinterpret_cast<const cplx<T>*>(M.ops[prec]);
-  for (const MlStage& st : M.stages) ml_stage_any<T>(st, ops, B, cols, P, s);
+  if (parts & 1)
+    for (const MlStage& st : M.stages) ml_stage_any<T>(st, ops, B, cols, P, s);
+  if (!(parts & 2)) return hipGetLastError();
   if (y64)
     hipLaunchKernelGGL((ml_out_kernel<T, double>), dim3(g), dim3(256), 0, s,
                        reinterpret_cast<const cplx<T>*>(B.b[3]), M.pos, P.n, total, cols, accum ? 1 : 0,
@@ -474,10 +478,10 @@ hipError_t ml_apply(const Plan& P, int R, void* y, void* y64, void* ws, bool acc
   return hipGetLastError();
 }
 
-template hipError_t ml_prepare<double>(const Plan&, int, const void*, void*, void*, hipStream_t);
-template hipError_t ml_prepare<float>(const Plan&, int, const void*, void*, void*, hipStream_t);
-template hipError_t ml_apply<double>(const Plan&, int, void*, void*, void*, bool, hipStream_t);
-template hipError_t ml_apply<float>(const Plan&, int, void*, void*, void*, bool, hipStream_t);
+template hipError_t ml_prepare<double>(const Plan&, int, const void*, void*, void*, hipStream_t, int);
+template hipError_t ml_prepare<float>(const Plan&, int, const void*, void*, void*, hipStream_t, int);
+template hipError_t ml_apply<double>(const Plan&, int, void*, void*, void*, bool, hipStream_t, int);
+template hipError_t ml_apply<float>(const Plan&, int, void*, void*, void*, bool, hipStream_t, int);
 
 // ---------------------------------------------------------------------------
 // host: translation matrices
