@@ -77,9 +77,9 @@ struct MlStage {
   int out, accum;      // output buffer; 1: add to it
   int max_rows;        // largest target
   // split > 1: each target's tasks are divided over `split` workgroups that write the partial
-  // buffer 5 (slot s at rows s nrows + out_row - row0); the slots are then added in slot order into
-  // rows [row0, row0 + nrows) of buffer `dest` (added to it when dest_accum)
-  int split = 1, dest = 0, dest_accum = 0, row0 = 0, nrows = 0;
+  // buffer `part` (slot s at rows s nrows + out_row - row0); the slots are then added in slot order
+  // into rows [row0, row0 + nrows) of buffer `dest` (added to it when dest_accum)
+  int split = 1, dest = 0, dest_accum = 0, row0 = 0, nrows = 0, part = 5;
 };
 struct MlData {
   int levels = 0, order = 0, p = 0;
@@ -88,14 +88,16 @@ struct MlData {
   int* perm = nullptr;               // device [n]: element at every tree position
   void* ops[2] = {nullptr, nullptr}; // operator pool FP64 / FP32 (P2M, L2P, M2M, L2L, M2L, P2P)
   size_t ops_elems = 0;
-  std::vector<MlStage> stages;       // P2M, M2M per level, M2L, L2L per level, L2P + P2P
+  std::vector<MlStage> stages;       // P2M, M2M per level, M2L, L2L per level, L2P (added to the P2P)
+  MlStage p2p{};                     // the exact leaf blocks, from the input alone (written first)
   // S2M of the cell-level far field from the input in tree order: V0 with its columns in tree
   // order at ops + oS, products over chunks of the elements into partial sums (buffer 4), summed
   // in chunk order into the padded grid
   MlStage s2m{};
   long long oS = 0;
   int s2m_chunks = 0;
-  size_t part_rows = 0;              // rows of the partial buffer of split stages (split x nrows, largest)
+  size_t part_rows = 0;              // rows of the partial buffer of the split M2L (split x nrows)
+  size_t p2p_part_rows = 0;          // rows of the partial buffer of the split P2P stage
   int boxes = 0, leaves = 0;
   long long m2l_pairs = 0, p2p_pairs = 0, p2p_entries = 0;
   double macs_per_rhs = 0.0;         // complex multiply-adds of one application per RHS (cells inside)
@@ -193,9 +195,11 @@ inline fmbem_status to_status(hipError_t e) {
   return FMBEM_ERR_DEVICE;
 }
 
-// record the start / end of a stage when that stage is being profiled (returns the start event)
+// record the start / end of a stage when that stage is being profiled (returns the start event);
+// counted = false: the interval adds its time to the stage but not to its count of applications
+constexpr int kProfUncounted = 0x100;
 hipEvent_t prof_begin(const Plan& P, int stage, hipStream_t s);
-void prof_end(const Plan& P, int stage, hipEvent_t start, hipStream_t s);
+void prof_end(const Plan& P, int stage, hipEvent_t start, hipStream_t s, bool counted = true);
 
 size_t matvec_workspace_bytes_per_rhs(const Plan& P, int precision);
 

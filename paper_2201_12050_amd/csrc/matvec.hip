@@ -47,8 +47,8 @@ static void prof_harvest(const Plan& P) {
     float t = 0.f;
     if (hipEventQuery(m.second.second) == hipSuccess &&
         hipEventElapsedTime(&t, m.second.first, m.second.second) == hipSuccess) {
-      P.prof.ms[m.first] += t;
-      P.prof.count[m.first] += 1;
+      P.prof.ms[m.first & ~kProfUncounted] += t;
+      if (!(m.first & kProfUncounted)) P.prof.count[m.first] += 1;
       P.prof.pool.push_back(m.second.first);
       P.prof.pool.push_back(m.second.second);
     } else {
@@ -78,11 +78,11 @@ hipEvent_t prof_begin(const Plan& P, int stage, hipStream_t s) {
   return prof_record(P, s);
 }
 
-void prof_end(const Plan& P, int stage, hipEvent_t start, hipStream_t s) {
+void prof_end(const Plan& P, int stage, hipEvent_t start, hipStream_t s, bool counted) {
   if (!start) return;
   hipEvent_t e = prof_record(P, s);
   if (!e) return;
-  P.prof.marks.push_back({stage, {start, e}});
+  P.prof.marks.push_back({stage | (counted ? 0 : kProfUncounted), {start, e}});
 }
 
 // Autotuner of the tile shape of a grouped launch: on the first launch of a given
@@ -264,14 +264,16 @@ template <typename T>
 static char* ml_buffers(const Plan& P, int R, void* ws) {
   return near_partials<T>(P, R, ws) + align256((size_t)P.n_near * R * P.C * P.n * sizeof(cplx<T>));
 }
-// [1] the multilevel near field of an FMPBEM2 plan: y (+)= S~ x (after ml_s2m); parts as ml_apply
+// [1] the multilevel near field of an FMPBEM2 plan: y (+)= S~ x (after ml_s2m); parts as ml_apply.
+// counted: the interval counts as one application of the stage (the other parts of a split
+// application add their device time only)
 template <typename T>
 static hipError_t ml_stage(const Plan& P, int R, void* y, void* y64, void* ws, bool accum, hipStream_t s,
-                           int parts = 3) {
+                           int parts = 15, bool counted = true) {
   const int prec = sizeof(T) == 8 ? 0 : 1;
   hipEvent_t ev = prof_begin(P, 1 + 6 * prec, s);
   const hipError_t e = ml_apply<T>(P, R, y, y64, ml_buffers<T>(P, R, ws), accum, s, parts);
-  prof_end(P, 1 + 6 * prec, ev, s);
+  prof_end(P, 1 + 6 * prec, ev, s, counted);
   return e;
 }
 // [0] of an FMPBEM2 plan: the input in tree order and the S2M into the padded grid
@@ -337,9 +339,10 @@ NearJob l2t_job(const Plan& P, int R, void* ws, const void* lhat, void* y, void*
 // Far-field chain of one plan on the plan's second stream, overlapping the near field on the
 // caller's stream: fork after x is ready, S2M -> DFT -> M2L -> inverse DFT on the second
 // stream, join before the L2T GEMM.  An FMPBEM2 plan gathers x into tree order before the fork,
-// runs its S2M from it on the second stream and its multilevel products on the caller's stream,
-// and adds their tree-ordered output to y after the L2T.  Not used while the caller's stream is
-// being captured.
+// runs its S2M from it and, after the far chain, its exact leaf blocks on the second stream, and
+// its tree stages (P2M up to the locals of the leaves) on the caller's stream; after the L2T it
+// adds the L2P to the leaf-block output and that output to y.  Not used while the caller's stream
+// is being captured.
 template <typename T>
 static hipError_t matvec_overlap(const Plan& P, int R, const void* x, void* y, void* ws, hipStream_t s, void* y64,
                                  bool tune) {
@@ -369,8 +372,10 @@ static hipError_t matvec_overlap(const Plan& P, int R, const void* x, void* y, v
   ev = prof_begin(P, 4 + 6 * prec, P.aux);
   if ((e = grid_dft_launch<T>(lhat, R * p, P.grid, P.fft, true, true, P.aux, P.flip_p(), sched_inv(dsched), P.dftF[prec]))) return e;
   prof_end(P, 4 + 6 * prec, ev, P.aux);
+  // the exact leaf blocks of an FMPBEM2 plan follow the far chain on the second stream
+  if (P.ml && (e = ml_stage<T>(P, R, y, y64, ws, true, P.aux, 4, false))) return e;
   if ((e = hipEventRecord(P.ev_join, P.aux))) return e;
-  // [0] near field on the caller's stream (the multilevel products of an FMPBEM2 plan)
+  // [0] near field on the caller's stream (the tree stages of an FMPBEM2 plan)
   if (P.ml) {
     if ((e = ml_stage<T>(P, R, y, y64, ws, true, s, 1))) return e;
   } else {
@@ -391,7 +396,7 @@ static hipError_t matvec_overlap(const Plan& P, int R, const void* x, void* y, v
   ev = prof_begin(P, 5 + 6 * prec, s);
   e = near_launch<T>(jobs, s, shape, 1);
   prof_end(P, 5 + 6 * prec, ev, s);
-  if (e == hipSuccess && P.ml) e = ml_apply<T>(P, R, y, y64, ml_buffers<T>(P, R, ws), true, s, 2);
+  if (e == hipSuccess && P.ml) e = ml_stage<T>(P, R, y, y64, ws, true, s, 8 | 2, false);
   return e;
 }
 

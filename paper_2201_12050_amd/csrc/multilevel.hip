@@ -58,8 +58,8 @@ constexpr int kMlLeafRows = 32;   // element rows of one L2P + P2P output block
 // device: block-sparse products
 // ---------------------------------------------------------------------------
 struct MlBufs {
-  void* b[6];  // 0: input in tree order, 1: moments, 2: locals, 3: output in tree order ([row][cols]),
-               // 4: S2M partial sums, 5: partial sums of split stages
+  void* b[7];  // 0: input in tree order, 1: moments, 2: locals, 3: output in tree order ([row][cols]),
+               // 4: S2M partial sums, 5: partial sums of the split M2L, 6: of the split P2P stage
 };
 
 // a complex zero in device memory (never written), read in place of entries outside the operands
@@ -380,7 +380,8 @@ size_t ml_workspace_bytes_per_rhs(const Plan& P, int precision) {
   if (!P.ml) return 0;
   const size_t el = precision == FMBEM_FP32 ? sizeof(float2) : sizeof(double2);
   return 2 * al256((size_t)P.n * P.C * el) + 2 * al256((size_t)P.ml->rows * P.C * el) +
-         al256((size_t)P.ml->s2m_chunks * P.p * P.C * el) + al256(P.ml->part_rows * P.C * el);
+         al256((size_t)P.ml->s2m_chunks * P.p * P.C * el) + al256(P.ml->part_rows * P.C * el) +
+         al256(P.ml->p2p_part_rows * P.C * el);
 }
 
 template <typename T>
@@ -390,9 +391,9 @@ static MlBufs ml_bufs(const Plan& P, int R, void* ws) {
   const size_t el = sizeof(cplx<T>);
   char* w = reinterpret_cast<char*>(ws);
   MlBufs B;
-  const size_t sz[6] = {(size_t)P.n * cols, (size_t)M.rows * cols, (size_t)M.rows * cols, (size_t)P.n * cols,
-                        (size_t)M.s2m_chunks * P.p * cols, M.part_rows * cols};
-  for (int i = 0; i < 6; ++i) {
+  const size_t sz[7] = {(size_t)P.n * cols,       (size_t)M.rows * cols, (size_t)M.rows * cols, (size_t)P.n * cols,
+                        (size_t)M.s2m_chunks * P.p * cols, M.part_rows * cols,  M.p2p_part_rows * cols};
+  for (int i = 0; i < 7; ++i) {
     B.b[i] = w;
     w += al256(sz[i] * el);
   }
@@ -427,7 +428,7 @@ static void ml_stage_any(const MlStage& st, const cplx<T>* ops, const MlBufs& B,
   if (st.split > 1) {
     const size_t slot = (size_t)st.nrows * cols;
     hipLaunchKernelGGL(ml_reduce_kernel<T>, dim3((unsigned)std::min<size_t>((slot + 255) / 256, 4096)), dim3(256), 0,
-                       s, reinterpret_cast<const cplx<T>*>(B.b[5]), st.split, slot, st.dest_accum,
+                       s, reinterpret_cast<const cplx<T>*>(B.b[st.part]), st.split, slot, st.dest_accum,
                        reinterpret_cast<cplx<T>*>(B.b[st.dest]) + (size_t)st.row0 * cols);
   }
 }
@@ -454,8 +455,10 @@ hipError_t ml_prepare(const Plan& P, int R, const void* x, void* ws, void* grid,
   return hipGetLastError();
 }
 
-// the near field from the input in tree order (ml_prepare earlier on the stream): the products into
-// the tree-ordered output (parts & 1), then y (+)= that output (parts & 2)
+// the near field from the input in tree order (ml_prepare earlier on the stream), in parts: the exact
+// leaf blocks into the tree-ordered output (parts & 4); the tree stages up to the locals of the
+// leaves (parts & 1); the L2P added to the output (parts & 8, after parts 4 and 1); y (+)= that
+// output (parts & 2)
 template <typename T>
 hipError_t ml_apply(const Plan& P, int R, void* y, void* y64, void* ws, bool accum, hipStream_t s, int parts) {
   const MlData& M = *P.ml;
@@ -465,8 +468,10 @@ hipError_t ml_apply(const Plan& P, int R, void* y, void* y64, void* ws, bool acc
   const size_t total = (size_t)P.n * cols;
   const unsigned g = (unsigned)std::min<size_t>((total + 255) / 256, 8192);
   const cplx<T>* ops = reinterpret_cast<const cplx<T>*>(M.ops[prec]);
+  if (parts & 4) ml_stage_any<T>(M.p2p, ops, B, cols, P, s);
   if (parts & 1)
-    for (const MlStage& st : M.stages) ml_stage_any<T>(st, ops, B, cols, P, s);
+    for (size_t i = 0; i + 1 < M.stages.size(); ++i) ml_stage_any<T>(M.stages[i], ops, B, cols, P, s);
+  if (parts & 8) ml_stage_any<T>(M.stages.back(), ops, B, cols, P, s);
   if (!(parts & 2)) return hipGetLastError();
   if (y64)
     hipLaunchKernelGGL((ml_out_kernel<T, double>), dim3(g), dim3(256), 0, s,
@@ -864,7 +869,16 @@ hipError_t ml_build(Plan& P, const std::vector<double>& geo, hipStream_t s) {
       add_task(oL + ((long long)(l - 2) * 8 + oct) * pp, p, p, row0(l - 1, x.parent), 2, kMlZeroShift);
     }
   }
-  // L2P and P2P per leaf, in chunks of at most kMlRows element rows
+  // L2P per leaf, in chunks of at most kMlLeafRows element rows, added to the P2P output
+  begin_stage(3, 1);
+  for (int b = 0; b < (int)lv[L].size(); ++b) {
+    const Box& x = lv[L][b];
+    for (int r0 = x.e0; r0 < x.e1; r0 += kMlLeafRows) {
+      add_target(r0, std::min(kMlLeafRows, x.e1 - r0));
+      add_task(oU + (long long)r0 * p, p, p, row0(L, b), 2, kMlZeroShift);
+    }
+  }
+  // P2P per leaf, the same row chunks (every leaf is near itself, so every chunk has a task)
   {
     begin_stage(3, 0);
     std::vector<std::vector<int>> by(lv[L].size());
@@ -872,9 +886,7 @@ hipError_t ml_build(Plan& P, const std::vector<double>& geo, hipStream_t s) {
     for (int b = 0; b < (int)lv[L].size(); ++b) {
       const Box& x = lv[L][b];
       for (int r0 = x.e0; r0 < x.e1; r0 += kMlLeafRows) {
-        const int rows = std::min(kMlLeafRows, x.e1 - r0);
-        add_target(r0, rows);
-        add_task(oU + (long long)r0 * p, p, p, row0(L, b), 2, kMlZeroShift);
+        add_target(r0, std::min(kMlLeafRows, x.e1 - r0));
         for (int i : by[b]) {
           const Box& y = lv[L][p2p[i].b];
           const int ns = y.e1 - y.e0;
@@ -895,7 +907,7 @@ hipError_t ml_build(Plan& P, const std::vector<double>& geo, hipStream_t s) {
   // stages whose targets carry many tasks (M2L, L2P + P2P) are divided over more workgroups when
   // the targets alone would leave the CUs short of work (columns of a one-RHS application)
   std::vector<std::array<int, 5>> split_of(stage_range.size(), {1, 0, 0, 0, 0});  // split, dest, accum, row0, nrows
-  auto split_stage = [&](size_t si, int row0s, int nrows) {
+  auto split_stage = [&](size_t si, int row0s, int nrows, int part) {
     const int first = stage_range[si].first, count = stage_range[si].second;
     if (count == 0) return;
     const int tile = P.C > 32 ? 64 : (P.C > 16 ? 32 : 16);
@@ -926,8 +938,9 @@ hipError_t ml_build(Plan& P, const std::vector<double>& geo, hipStream_t s) {
       }
     stage_range[si] = {nfirst, S * count};
     split_of[si] = {S, stage_mode[si].first, stage_mode[si].second, row0s, nrows};
-    stage_mode[si] = {5, 0};
-    M.part_rows = std::max(M.part_rows, (size_t)S * nrows);
+    stage_mode[si] = {part, 0};
+    size_t& rows_of_part = part == 5 ? M.part_rows : M.p2p_part_rows;
+    rows_of_part = std::max(rows_of_part, (size_t)S * nrows);
   };
   // expansion targets of more than 32 rows (p > 32) become balanced row blocks of at most 32, each
   // with the tasks' operators offset to its rows (fewer idle rows in the 32- and 64-row tiles)
@@ -957,11 +970,11 @@ hipError_t ml_build(Plan& P, const std::vector<double>& geo, hipStream_t s) {
     stage_rows[si] = maxr;
   };
   {
-    // stage order: P2M, M2M x (L - 1), M2L, L2L x (L - 1), L2P + P2P, S2M
+    // stage order: P2M, M2M x (L - 1), M2L, L2L x (L - 1), L2P, P2P, S2M
     const size_t m2l_stage = 1 + (size_t)(L - 1), l2p_stage = m2l_stage + 1 + (size_t)(L - 1);
     for (size_t si = 0; si < l2p_stage; ++si) row_split_stage(si);
-    split_stage(m2l_stage, 0, M.rows);
-    split_stage(l2p_stage, 0, n);
+    split_stage(m2l_stage, 0, M.rows, 5);
+    split_stage(l2p_stage + 1, 0, n, 6);
   }
   // device arrays
   hipError_t e;
@@ -979,13 +992,15 @@ hipError_t ml_build(Plan& P, const std::vector<double>& geo, hipStream_t s) {
   hipMemcpyAsync(M.perm, perm.data(), n * sizeof(int), hipMemcpyHostToDevice, s);
   double2* ops = reinterpret_cast<double2*>(M.ops[0]);
   hipMemcpyAsync(ops + oM, hT.data(), hT.size() * sizeof(double2), hipMemcpyHostToDevice, s);
+  auto make_stage = [&](size_t i) {
+    return MlStage{d_tg + stage_range[i].first, d_tk,          stage_range[i].second, stage_mode[i].first,
+                   stage_mode[i].second,         stage_rows[i], split_of[i][0],        split_of[i][1],
+                   split_of[i][2],               split_of[i][3], split_of[i][4],       stage_mode[i].first};
+  };
   M.stages.clear();
-  for (size_t i = 0; i + 1 < stage_range.size(); ++i)
-    M.stages.push_back(MlStage{d_tg + stage_range[i].first, d_tk, stage_range[i].second, stage_mode[i].first,
-                               stage_mode[i].second, stage_rows[i], split_of[i][0], split_of[i][1], split_of[i][2],
-                               split_of[i][3], split_of[i][4]});
-  M.s2m = MlStage{d_tg + stage_range.back().first, d_tk, stage_range.back().second, stage_mode.back().first,
-                  stage_mode.back().second, stage_rows.back()};
+  for (size_t i = 0; i + 2 < stage_range.size(); ++i) M.stages.push_back(make_stage(i));
+  M.p2p = make_stage(stage_range.size() - 2);
+  M.s2m = make_stage(stage_range.size() - 1);
   // leaf P2M / L2P about the leaf centres (device), and the exact P2P entries
   std::vector<double> cen((size_t)n * 3);
   for (int e2 = 0; e2 < n; ++e2)
