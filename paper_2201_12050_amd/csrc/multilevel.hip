@@ -27,13 +27,14 @@
 //
 // Application (all cells and right-hand sides at once): the input is gathered into tree
 // order with the columns (RHS r, cell c) innermost, then every stage is one launch of the
-// block-sparse product kernel -- P2M, M2M per level, M2L of all levels, L2L per level, L2P
-// together with the P2P blocks -- and the result is scattered back and added to y.  Targets
-// of more than 32 expansion rows are split into row blocks, and the two heavy stages (M2L,
-// L2P + P2P) divide each target's tasks over several workgroups whose partial sums are added
-// in slot order afterwards.  The S2M of the cell-level far field reads the same tree-ordered
-// input as a split-K product (partial sums over element chunks, added in chunk order).
-// Every sum runs in a fixed order, so an application's result does not depend on timing.
+// block-sparse product kernel -- the P2P blocks (from the input alone, so they may run beside
+// the tree stages), P2M, M2M per level, M2L of all levels, L2L per level, and the L2P added to
+// the P2P output -- and the result is scattered back and added to y.  Targets of more than 32
+// expansion rows are split into row blocks, and the two heavy stages (M2L, P2P) divide each
+// target's tasks over several workgroups whose partial sums are added in slot order afterwards.
+// The S2M of the cell-level far field reads the same tree-ordered input as a split-K product
+// (partial sums over element chunks, added in chunk order).  Every sum runs in a fixed order,
+// so an application's result does not depend on timing.
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -52,7 +53,7 @@ namespace fmbem {
 constexpr int kMlRows = 64;  // rows of one S2M output block (the largest target of any stage)
 constexpr int kMlZeroShift = 13;
 constexpr int kMlS2mChunk = 128;  // elements per partial sum of the S2M
-constexpr int kMlLeafRows = 32;   // element rows of one L2P + P2P output block
+constexpr int kMlLeafRows = 32;   // element rows of one L2P / P2P output block
 
 // ---------------------------------------------------------------------------
 // device: block-sparse products
@@ -904,7 +905,7 @@ hipError_t ml_build(Plan& P, const std::vector<double>& geo, hipStream_t s) {
       add_target(q * P.p + r0, std::min(kMlRows, P.p - r0));
       add_task(M.oS + (long long)r0 * n + k0, n, std::min(kMlS2mChunk, n - k0), k0, 0, kMlZeroShift);
     }
-  // stages whose targets carry many tasks (M2L, L2P + P2P) are divided over more workgroups when
+  // stages whose targets carry many tasks (M2L, P2P) are divided over more workgroups when
   // the targets alone would leave the CUs short of work (columns of a one-RHS application)
   std::vector<std::array<int, 5>> split_of(stage_range.size(), {1, 0, 0, 0, 0});  // split, dest, accum, row0, nrows
   auto split_stage = [&](size_t si, int row0s, int nrows, int part) {
