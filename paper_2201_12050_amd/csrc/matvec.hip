@@ -39,6 +39,15 @@ size_t matvec_workspace_bytes_per_rhs(const Plan& P, int precision) {
   return b;
 }
 
+// a mark's time added to its stage (a mark carries the stage, with kProfUncounted for an interval
+// that is not an application of its own)
+static void prof_add(const Plan& P, int mark, float t) {
+  const int stage = mark & ~kProfUncounted;
+  if (stage < 0 || stage >= FMBEM_N_STAGES) return;
+  P.prof.ms[stage] += t;
+  if (!(mark & kProfUncounted)) P.prof.count[stage] += 1;
+}
+
 // completed marks: their times added to the stage totals, their events back in the pool
 static void prof_harvest(const Plan& P) {
   size_t keep = 0;
@@ -47,8 +56,7 @@ static void prof_harvest(const Plan& P) {
     float t = 0.f;
     if (hipEventQuery(m.second.second) == hipSuccess &&
         hipEventElapsedTime(&t, m.second.first, m.second.second) == hipSuccess) {
-      P.prof.ms[m.first & ~kProfUncounted] += t;
-      if (!(m.first & kProfUncounted)) P.prof.count[m.first] += 1;
+      prof_add(P, m.first, t);
       P.prof.pool.push_back(m.second.first);
       P.prof.pool.push_back(m.second.second);
     } else {
@@ -757,8 +765,7 @@ extern "C" fmbem_status fmbem_plan_profile_read(fmbem_plan plan, double* ms, int
     float t = 0.f;
     if (hipEventSynchronize(m.second.second) != hipSuccess) return FMBEM_ERR_DEVICE;
     if (hipEventElapsedTime(&t, m.second.first, m.second.second) != hipSuccess) return FMBEM_ERR_DEVICE;
-    P.prof.ms[m.first] += t;
-    P.prof.count[m.first] += 1;
+    prof_add(P, m.first, t);
     P.prof.pool.push_back(m.second.first);
     P.prof.pool.push_back(m.second.second);
   }

@@ -177,3 +177,31 @@ def test_multilevel_noalloc_equals_workspace_entry_point():
         assert torch.isfinite(torch.view_as_real(y_na)).all()
         assert rel(y_na.cpu().numpy(), y_ws.cpu().numpy()) < (1e-13 if prec == "fp64" else 1e-6)
     P.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_multilevel_profile_counts_each_application_once(prec):
+    # an FMPBEM2 application records its multilevel products as several intervals on two streams
+    # (tree stages, P2P blocks, L2P); the stage's count is the number of applications and its time
+    # covers every interval, whether the marks are read at once or after later applications
+    import paper_2201_12050_amd as fm
+    v, t, lat, k, F, A = _case("sphere80_3x3_L2")
+    _, grid, _, nt, levels, ntn = CASES["sphere80_3x3_L2"]
+    P = fm.Plan(v, t, grid, lat.pitch, k, nt, near_levels=levels, near_order=ntn)
+    x = torch.from_numpy(random_complex((1, lat.n_cells, t.shape[0]), 5)).cuda()
+    x = x.to(torch.complex64) if prec == "fp32" else x
+    ref = P.matvec(x, precision=prec)
+    P.profile([f"reduce_{prec}", f"fft_{prec}"])
+    for _ in range(3):
+        y = P.matvec(x, precision=prec)
+    torch.cuda.synchronize()
+    first = P.profile_read()
+    for _ in range(2):
+        y = P.matvec(x, precision=prec)
+    second = P.profile_read()
+    P.profile([])
+    assert first[f"reduce_{prec}"][1] == 3 and second[f"reduce_{prec}"][1] == 5
+    assert first[f"fft_{prec}"][1] == 3 and second[f"fft_{prec}"][1] == 5
+    assert 0 < first[f"reduce_{prec}"][0] < second[f"reduce_{prec}"][0]
+    assert rel(y.cpu().numpy(), ref.cpu().numpy()) < 1e-12
+    P.close()
