@@ -347,11 +347,11 @@ def large_cell_comparison(fm, torch, args):
     """FMPBEM2 (Sec. 3.3: the near blocks as a multilevel FMM inside the cells) against the FMPBEM
     with dense near blocks on the 4 x 4 lattice of 20480-triangle spheres (1 kHz, n_t = 10,
     N = 327,680): plan build time and bytes, operator applications per second, device time of the
-    multilevel near field with its algorithmic rate (8 flop per complex multiply-add over the
-    cells inside the lattice) against the matrix-core peak of its precision (its products run on
-    the 16x16x4 FP32 / FP64 MFMA), the operator difference between the
-    two methods, sampled rows against the oracle's FMPBEM2 (stored fixture), and FP32-refined
-    solves."""
+    multilevel near field (summed over its intervals on both streams of an application, which
+    overlap the cell-level far field) with its algorithmic rate (8 flop per complex multiply-add
+    over the cells inside the lattice) against the matrix-core peak of its precision (its products
+    run on the 16x16x4 FP32 / FP64 MFMA), the operator difference between the two methods, sampled
+    rows against the oracle's FMPBEM2 (stored fixture), and FP32-refined solves."""
     from workloads import config_large_cell
     from workloads.rng import random_complex
     w = config_large_cell()
