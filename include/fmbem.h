@@ -163,6 +163,8 @@ typedef struct {
   int64_t near_p2p_entries;   /* exact entries kept in the P2P blocks */
   double near_macs_per_rhs;   /* complex multiply-adds of one multilevel near-field application per
                                  right-hand side, counting only source cells inside the lattice */
+  int32_t near_max_tasks;     /* longest list of operator blocks that one workgroup adds up for one
+                                 target in any multilevel stage (after the stages are split) */
 } fmbem_plan_info;
 
 /* Build the plan: near blocks S_d (Sec. 3.2), P2M V0 and L2P U0 (Appendix A,

@@ -51,7 +51,8 @@ class PlanInfo(ct.Structure):
                 ("precisions", ct.c_uint32), ("resident_bytes", ct.c_size_t),
                 ("workspace_bytes_per_rhs", ct.c_size_t * 2), ("scale", ct.c_double),
                 ("near_levels", ct.c_int32), ("near_order", ct.c_int32), ("near_boxes", ct.c_int64),
-                ("near_m2l_pairs", ct.c_int64), ("near_p2p_entries", ct.c_int64), ("near_macs_per_rhs", ct.c_double)]
+                ("near_m2l_pairs", ct.c_int64), ("near_p2p_entries", ct.c_int64), ("near_macs_per_rhs", ct.c_double),
+                ("near_max_tasks", ct.c_int32)]
 
 
 class SolveOpts(ct.Structure):

@@ -98,6 +98,7 @@ struct MlData {
   int s2m_chunks = 0;
   size_t part_rows = 0;              // rows of the partial buffer of the split M2L (split x nrows)
   size_t p2p_part_rows = 0;          // rows of the partial buffer of the split P2P stage
+  int max_tasks = 0;                 // longest task list of one launched target (any stage)
   int boxes = 0, leaves = 0;
   long long m2l_pairs = 0, p2p_pairs = 0, p2p_entries = 0;
   double macs_per_rhs = 0.0;         // complex multiply-adds of one application per RHS (cells inside)

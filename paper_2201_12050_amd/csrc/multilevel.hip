@@ -993,6 +993,10 @@ hipError_t ml_build(Plan& P, const std::vector<double>& geo, hipStream_t s) {
   hipMemcpyAsync(M.perm, perm.data(), n * sizeof(int), hipMemcpyHostToDevice, s);
   double2* ops = reinterpret_cast<double2*>(M.ops[0]);
   hipMemcpyAsync(ops + oM, hT.data(), hT.size() * sizeof(double2), hipMemcpyHostToDevice, s);
+  M.max_tasks = 0;
+  for (size_t i = 0; i < stage_range.size(); ++i)
+    for (int x = stage_range[i].first; x < stage_range[i].first + stage_range[i].second; ++x)
+      M.max_tasks = std::max(M.max_tasks, tg[x].t1 - tg[x].t0);
   auto make_stage = [&](size_t i) {
     return MlStage{d_tg + stage_range[i].first, d_tk,          stage_range[i].second, stage_mode[i].first,
                    stage_mode[i].second,         stage_rows[i], split_of[i][0],        split_of[i][1],

@@ -1336,6 +1336,7 @@ extern "C" fmbem_status fmbem_plan_query(fmbem_plan plan, fmbem_plan_info* out) 
   out->near_m2l_pairs = P.ml ? P.ml->m2l_pairs : 0;
   out->near_p2p_entries = P.ml ? P.ml->p2p_entries : 0;
   out->near_macs_per_rhs = P.ml ? P.ml->macs_per_rhs : 0.0;
+  out->near_max_tasks = P.ml ? P.ml->max_tasks : 0;
   return FMBEM_OK;
 }
 

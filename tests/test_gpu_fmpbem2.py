@@ -205,3 +205,28 @@ def test_multilevel_profile_counts_each_application_once(prec):
     assert 0 < first[f"reduce_{prec}"][0] < second[f"reduce_{prec}"][0]
     assert rel(y.cpu().numpy(), ref.cpu().numpy()) < 1e-12
     P.close()
+
+
+def test_multilevel_task_lists_longer_than_a_wave():
+    # a 16x16x8 lattice (27 near offsets) with 3 levels: the M2L stage is not split, and a box
+    # interacts with up to 189 source boxes, so the product kernel walks task lists in several
+    # batches of 64 descriptors.  Sampled rows against the oracle's FMPBEM2 (computed here).
+    import paper_2201_12050_amd as fm
+    v, t = icosphere(1, 0.1)
+    lat = Lattice((16, 16, 8), (0.3, 0.3, 0.3))
+    k = 2 * np.pi * 700 / 343.0
+    P = fm.Plan(v, t, lat.grid, lat.pitch, k, 4, near_levels=3, near_order=2)
+    assert P.info["near_max_tasks"] > 128
+    n = t.shape[0]
+    x = random_complex((1, lat.n_cells, n), 2301)
+    rng = np.random.default_rng(23011)
+    cells = [0, 17, 255, 1000, 1535, 2047]      # corners, an edge and the interior
+    dofs = [c * n + int(e) for c in cells for e in rng.integers(0, n, size=3)]
+    ref = ml.sampled_apply2(v, t, lat, k, 4, -1j / k, 3, 2, x, dofs)[0]
+    xd = torch.from_numpy(x).cuda()
+    y64 = P.matvec(xd, precision="fp64").cpu().numpy().reshape(-1)[dofs]
+    y32 = P.matvec(xd.to(torch.complex64), precision="fp32").cpu().numpy().reshape(-1)[dofs]
+    for y, tol in ((y64, 1e-12), (y32, 1e-5)):
+        assert rel(y, ref) < tol
+        assert np.abs(y - ref).max() <= tol * np.abs(ref).max()
+    P.close()
