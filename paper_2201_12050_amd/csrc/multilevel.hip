@@ -110,7 +110,8 @@ __device__ inline void stream_sync() {
 // stream is a single wave -> 246 / 360; the task descriptors in lanes instead of a dependent load
 // per task -> 244 / 326; 4 waves per SIMD -> 221 / 285; unconditional loads (a guarded load, or a
 // select right after the load, waited for the operands at once) -> 183 / 274.  A second item in
-// flight (two register sets) was 5-10 % slower.
+// flight (two register sets) was 5-10 % slower; FP32 chunks of 8 were 3 % slower and of 32 (fewer
+// waves per SIMD) 23 % slower than 16.
 template <typename T, int WS, int RT, int KW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(RT <= 2 ? 4 : 1))) void ml_kernel(
     const MlTarget* __restrict__ tg, const MlTask* __restrict__ tk, const cplx<T>* __restrict__ ops, MlBufs B,
