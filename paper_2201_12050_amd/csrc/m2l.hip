@@ -10,7 +10,10 @@
 // columns j, each thread of a group accumulates two rows for up to kRhs vectors, and
 // the groups are summed in LDS.  The product is in place in the [bin][R][p] spectrum
 // buffer.  FP32 takes 8 groups (twice the loads in flight of 4: a bin's matrix is only
-// 118 KB at n_t = 10, measured 17.7 -> 13.7 us on 514 bins), FP64 4.
+// 118 KB at n_t = 10, measured 17.7 -> 13.7 us on 514 bins), FP64 4.  Measured and not kept
+// (16x16 lattice, n_t = 10, inside the FP32-refined solve, 20.2 us): a bin's rows split over 2
+// or 4 workgroups (20.4 / 21.4 us), and every matrix load of a thread issued before the vectors
+// are staged (20.7 us).
 #include <algorithm>
 #include <vector>
 
