@@ -104,6 +104,46 @@ def cpu_baseline(w, its_per_solve, seconds_budget=30.0):
                        f"solves/s = 1 / (apply time x {its_per_solve} operator applications of the GPU FP64 solve)")}
 
 
+def cpu_baseline_configs():
+    """The oracle on the other workloads of the baseline plan, each timed once on the host cores
+    (not part of the default run: about a minute of CPU work): the tiny 4x1 line as a dense exact
+    system (assembly, then LU solve of the plane-wave right-hand side), and one block-by-block
+    FMPBEM apply on each batched lattice (8x8, 12x20, 32x4 of 320-triangle spheres, 800 Hz,
+    n_t = 10; the plan construction is timed apart).  The barrier sweep is not timed (its far
+    field alone needs about 4e5 cell pairs of 225 x 225 translations per apply)."""
+    from oracle import bem, solve, operator as op
+    from workloads import config_tiny, config_batched_grids
+    from workloads.rng import random_complex
+    out = {"kind": "oracle", "cores": os.cpu_count()}
+    try:
+        from threadpoolctl import threadpool_info
+        out["cores"] = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        pass
+    w = config_tiny()
+    alpha = bem.default_alpha(w.k, w.formulation)
+    t0 = time.perf_counter()
+    A = bem.dense_exact(w.vertices, w.triangles, w.lattice, w.k, alpha)
+    t1 = time.perf_counter()
+    b = bem.rhs_plane_wave(w.vertices, w.triangles, w.lattice, w.k, alpha, w.plane_waves)[0]
+    t2 = time.perf_counter()
+    solve.lu_solve(A, b)
+    t3 = time.perf_counter()
+    out["tiny_4x1_dense"] = {"n_dof": int(A.shape[0]), "assembly_s": t1 - t0, "lu_solve_s": t3 - t2}
+    grids = {}
+    for wb in config_batched_grids(1):
+        t0 = time.perf_counter()
+        F = op.FMPBEM.from_workload(wb)
+        t1 = time.perf_counter()
+        x = random_complex((1, wb.lattice.n_cells, wb.n_dof_cell), 3).reshape(1, -1)
+        F.matvec(x)
+        t2 = time.perf_counter()
+        grids["x".join(map(str, wb.lattice.grid[:2]))] = {"n_dof": int(x.size), "build_s": t1 - t0,
+                                                          "matvec_s": t2 - t1}
+    out["batched_grids_fmpbem_apply"] = grids
+    return out
+
+
 def batched_grids(fm, torch, args):
     """Three uneven lattices (8x8, 12x20, 32x4 of 320-triangle spheres, 800 Hz, n_t = 10), 64
     seeded plane waves each, solved together by one batched solve (grouped launches over the
@@ -588,6 +628,8 @@ def main():
     ap.add_argument("--ortho", choices=("dgks", "twice", "once"), default="once")
     ap.add_argument("--matvec-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-baseline-configs", action="store_true",
+                    help="also time the oracle on the tiny line (dense LU) and the batched lattices (about a minute)")
     ap.add_argument("--grid", type=int, nargs=2, default=(16, 16))
     ap.add_argument("--batch-rhs", type=int, default=64, help="plane waves per lattice of the batched-grids run")
     ap.add_argument("--no-batched-grids", action="store_true")
@@ -824,6 +866,8 @@ def main():
     if not args.no_cpu_baseline:
         its64 = inf64[-1]["iterations"] + 2
         out["cpu_baseline"] = cpu_baseline(w, its64)
+    if args.cpu_baseline_configs:
+        out["cpu_baseline_configs"] = cpu_baseline_configs()
     print(json.dumps(out), flush=True)
     return 0
 
